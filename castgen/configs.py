@@ -1,0 +1,221 @@
+"""Seeded problem builders for the casting workloads.
+
+A problem is a dict of host arrays in the layout the C interface takes:
+
+  elem_type      4 (tet4) or 8 (hex8)
+  xyz            (N, 3) float64, metres
+  conn           (E, nen) int32, 0-based node ids
+  elem_mat       (E,) int32 material index
+  materials      (M, 6) float64 rows [k, rho, c, T_sol, T_liq, L] (SI, deg C)
+  dirichlet_nodes, dirichlet_T        fixed-temperature nodes
+  flux_faces (nf, npf) int32, flux_q, flux_h, flux_Tinf     Robin faces
+  if_a, if_b (np, 3) int32, if_h       matched cast/mold interface triangles
+  T0             (N,) float64 initial temperature
+  meta           dict describing the recipe (sizes, seeds)
+
+The workloads follow the casting setting of the paper (aluminium-like alloy
+poured into a sand mould, heat crossing the cast/mould contact through an
+interface heat-transfer coefficient) on synthetic meshes, since the paper's
+meshes are not published.  No finite-element arithmetic lives here.
+"""
+import numpy as np
+
+from . import meshes, rng
+
+# [k, rho, c, T_sol, T_liq, L]
+ALLOY = (150.0, 2700.0, 900.0, 600.0, 660.0, 3.9e5)
+SAND = (0.6, 1500.0, 1000.0, 0.0, 0.0, 0.0)
+
+
+def box_hex_grid(nx, ny, nz, lx, ly, lz):
+    """Hex8 grid of nx*ny*nz boxes on [0,lx]x[0,ly]x[0,lz]; node (i,j,k) id = i + (nx+1)(j + (ny+1)k)."""
+    mx, my, mz = nx + 1, ny + 1, nz + 1
+    ids = np.arange(mx * my * mz, dtype=np.int64)
+    i, j, k = ids % mx, (ids // mx) % my, ids // (mx * my)
+    xyz = np.stack([i * (lx / nx), j * (ly / ny), k * (lz / nz)], axis=1)
+    c = np.arange(nx * ny * nz, dtype=np.int64)
+    ci, cj, ck = c % nx, (c // nx) % ny, c // (nx * ny)
+    base = ci + mx * (cj + my * ck)
+    offs = np.array([a + mx * (b + my * cc) for (a, b, cc) in meshes.HEX_CORNERS], dtype=np.int64)
+    conn = base[:, None] + offs[None, :]
+    return xyz, conn, (i, j, k)
+
+
+def x0_quads(nx, ny, nz):
+    """Quad faces of a box hex grid on the plane x = 0, nodes ordered around the face."""
+    mx, my = nx + 1, ny + 1
+    q = []
+    for k in range(nz):
+        for j in range(ny):
+            a = 0 + mx * (j + my * k)
+            b = 0 + mx * (j + 1 + my * k)
+            c = 0 + mx * (j + 1 + my * (k + 1))
+            d = 0 + mx * (j + my * (k + 1))
+            q.append((a, b, c, d))
+    return np.array(q, dtype=np.int64)
+
+
+def smooth_noise(xyz, length, seed, modes=8):
+    """sum_m a_m sin(2 pi k_m.x / length + phi_m), k_m in {0..3}^3 without 0, scaled to max |.| = 1."""
+    ks = []
+    off = 0
+    while len(ks) < modes:
+        v = (rng.u64(seed, 7, 3, off) % np.uint64(4)).astype(np.int64)
+        off += 3
+        if np.any(v):
+            ks.append(v)
+    a = rng.uniform(seed, 8, modes, 0.5, 1.0)
+    phi = rng.uniform(seed, 9, modes, 0.0, 2.0 * np.pi)
+    s = np.zeros(xyz.shape[0])
+    for m in range(modes):
+        s += a[m] * np.sin(2.0 * np.pi * (xyz @ ks[m].astype(np.float64)) / length + phi[m])
+    return s / np.max(np.abs(s))
+
+
+def _empty_faces(problem):
+    problem.setdefault("dirichlet_nodes", np.zeros(0, np.int32))
+    problem.setdefault("dirichlet_T", np.zeros(0))
+    problem.setdefault("flux_faces", np.zeros((0, 3), np.int32))
+    problem.setdefault("flux_q", np.zeros(0))
+    problem.setdefault("flux_h", np.zeros(0))
+    problem.setdefault("flux_Tinf", np.zeros(0))
+    problem.setdefault("if_a", np.zeros((0, 3), np.int32))
+    problem.setdefault("if_b", np.zeros((0, 3), np.int32))
+    problem.setdefault("if_h", np.zeros(0))
+    return problem
+
+
+def hex_cube(n=16, length=0.1, T_pour=700.0, noise_amp=2.0, noise_seed=1,
+             dirichlet_x0=25.0, robin_x0=None, material=ALLOY):
+    """The 0.1 m alloy cube as n^3 hex8 elements.
+
+    dirichlet_x0: temperature held on the x = 0 face (None for none).
+    robin_x0: (h, T_inf) of a convective chill on the x = 0 face, or None.
+    The initial field is T_pour plus seeded smooth noise of amplitude noise_amp.
+    """
+    xyz, conn, (i, j, k) = box_hex_grid(n, n, n, length, length, length)
+    N = xyz.shape[0]
+    T0 = np.full(N, float(T_pour))
+    if noise_amp:
+        T0 = T0 + noise_amp * smooth_noise(xyz, length, noise_seed)
+    prob = dict(elem_type=8, xyz=xyz, conn=conn.astype(np.int32),
+                elem_mat=np.zeros(conn.shape[0], np.int32),
+                materials=np.array([material], dtype=np.float64), T0=T0,
+                meta=dict(kind="hex_cube", n=n, length=length, T_pour=T_pour,
+                          noise_amp=noise_amp, noise_seed=noise_seed))
+    if dirichlet_x0 is not None:
+        d = np.nonzero(i == 0)[0]
+        prob["dirichlet_nodes"] = d.astype(np.int32)
+        prob["dirichlet_T"] = np.full(d.size, float(dirichlet_x0))
+    if robin_x0 is not None:
+        q = x0_quads(n, n, n)
+        prob["flux_faces"] = q.astype(np.int32)
+        prob["flux_q"] = np.zeros(q.shape[0])
+        prob["flux_h"] = np.full(q.shape[0], float(robin_x0[0]))
+        prob["flux_Tinf"] = np.full(q.shape[0], float(robin_x0[1]))
+    return _empty_faces(prob)
+
+
+def hex_bar(nx=64, ny=4, nz=4, lx=0.4, ly=0.025, lz=0.025, T_init=700.0, T_wall=25.0, material=ALLOY):
+    """A bar of hexes along x with a fixed temperature on x = 0 (semi-infinite conduction setting)."""
+    xyz, conn, (i, j, k) = box_hex_grid(nx, ny, nz, lx, ly, lz)
+    d = np.nonzero(i == 0)[0]
+    prob = dict(elem_type=8, xyz=xyz, conn=conn.astype(np.int32),
+                elem_mat=np.zeros(conn.shape[0], np.int32),
+                materials=np.array([material], dtype=np.float64),
+                T0=np.full(xyz.shape[0], float(T_init)),
+                dirichlet_nodes=d.astype(np.int32), dirichlet_T=np.full(d.size, float(T_wall)),
+                meta=dict(kind="hex_bar", nx=nx, ny=ny, nz=nz, lx=lx))
+    return _empty_faces(prob)
+
+
+def tet_casting(n=128, length=0.1, region="cube", cube=(0.2, 0.8), boxes_seed=6, n_boxes=8,
+                jitter=0.2, jitter_seed=2, perm_seed=3, T_pour=700.0, T_mold=25.0,
+                h_interface=1000.0, alloy=ALLOY, mold=SAND, permute=True):
+    """Jittered Kuhn-tet cast+mold mesh of the cube [0, length]^3 with an adiabatic outer boundary.
+
+    region: "cube" (cubes whose centre lies in [cube[0], cube[1]]^3 are casting),
+            "boxes" (union of `n_boxes` seeded boxes), or "none" (all casting).
+    Nodes on the cast/mold interface are duplicated; each interface triangle is
+    listed once as a (casting copy, mold copy) pair with coefficient h_interface.
+    With permute, node ids and element order are seeded random permutations.
+    """
+    conn_grid = meshes.kuhn_conn(n)
+    if jitter:
+        xyz01, redrawn = meshes.jitter_grid(n, conn_grid, jitter, jitter_seed)
+    else:
+        xyz01, redrawn = meshes.grid_xyz(n, 1.0), 0
+    ncell = n ** 3
+    if region == "cube":
+        cell_cast = meshes.cube_region_cells(n, cube[0], cube[1])
+        boxes = None
+    elif region == "boxes":
+        boxes = meshes.random_boxes(boxes_seed, n_boxes)
+        cell_cast = meshes.boxes_region_cells(n, boxes)
+    elif region == "none":
+        cell_cast = np.ones(ncell, dtype=bool)
+        boxes = None
+    else:
+        raise ValueError(region)
+    elem_is_cast = np.repeat(cell_cast, 6)
+    Ng = (n + 1) ** 3
+    if np.all(elem_is_cast):
+        conn, dup, copy_id = conn_grid, np.zeros(0, np.int64), np.full(Ng, -1, np.int64)
+        fa, fb = np.zeros((0, 3), np.int64), np.zeros((0, 3), np.int64)
+    else:
+        conn, dup, copy_id = meshes.split_materials(conn_grid, elem_is_cast, Ng)
+        fa, fb = meshes.interface_faces(conn_grid, elem_is_cast, dup, copy_id)
+    xyz = np.concatenate([xyz01, xyz01[dup]], axis=0) * length
+    N = xyz.shape[0]
+    node_is_cast = np.zeros(N, dtype=bool)
+    node_is_cast[conn[elem_is_cast].ravel()] = True
+    T0 = np.where(node_is_cast, float(T_pour), float(T_mold))
+    materials = np.array([alloy, mold], dtype=np.float64)
+    prob = dict(elem_type=4, xyz=xyz, conn=conn.astype(np.int32),
+                elem_mat=np.where(elem_is_cast, 0, 1).astype(np.int32),
+                materials=materials, T0=T0,
+                if_a=fa.astype(np.int32), if_b=fb.astype(np.int32),
+                if_h=np.full(fa.shape[0], float(h_interface)),
+                meta=dict(kind="tet_casting", n=n, length=length, region=region, cube=cube,
+                          boxes=boxes, jitter=jitter, jitter_seed=jitter_seed, perm_seed=perm_seed,
+                          redrawn_nodes=int(redrawn), n_dup=int(dup.size)))
+    prob = _empty_faces(prob)
+    if permute:
+        node_perm = rng.permutation(perm_seed, 0, N)
+        elem_perm = rng.permutation(perm_seed, 1, conn.shape[0])
+        prob = meshes.apply_permutations(prob, node_perm, elem_perm)
+    return prob
+
+
+def config1(**kw):
+    """16^3 hex8 alloy cube, noise seed 1, 25 C on x = 0, adiabatic elsewhere."""
+    return hex_cube(**kw)
+
+
+def config2(n=128, **kw):
+    """128^3 jittered Kuhn tets, inner casting cube [0.2, 0.8]^3 in sand, h_i = 1000, jitter 2, perm 3."""
+    kw.setdefault("jitter_seed", 2)
+    kw.setdefault("perm_seed", 3)
+    return tet_casting(n=n, region="cube", **kw)
+
+
+def config5(n=256, **kw):
+    """256^3 jittered Kuhn tets, casting = union of 8 seeded boxes (seed 6), jitter 7, perm 8."""
+    kw.setdefault("boxes_seed", 6)
+    kw.setdefault("jitter_seed", 7)
+    kw.setdefault("perm_seed", 8)
+    return tet_casting(n=n, region="boxes", **kw)
+
+
+def chill_params(seed):
+    """Pour temperature U(680, 760) C and chill coefficient log-uniform on [300, 3000] W/m^2K."""
+    u = rng.uniform(seed, 11, 2)
+    T_pour = 680.0 + 80.0 * u[0]
+    h = float(np.exp(np.log(300.0) + (np.log(3000.0) - np.log(300.0)) * u[1]))
+    return T_pour, h
+
+
+def config4_trajectory(seed, n=16):
+    """Alloy cube with a convective chill (h, 25 C) on x = 0 and a uniform pour temperature."""
+    T_pour, h = chill_params(seed)
+    return hex_cube(n=n, T_pour=T_pour, noise_amp=0.0, dirichlet_x0=None, robin_x0=(h, 25.0))

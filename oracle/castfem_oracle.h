@@ -1,0 +1,109 @@
+/*
+ * Plain FP64 CPU oracle of the explicit finite-element casting step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the package smoke check and
+ * the CPU-baseline leg of the benchmark may load this library.  The product
+ * path never calls it and shares no code, header or table with it.
+ *
+ * What it computes (R. Tavakoli, "Improvement cache efficiency of explicit
+ * finite element procedure and its application to parallel casting
+ * solidification simulation", 2006):
+ *   - conduction with phase change in enthalpy form, dH/dt = div(k grad T)
+ *     (Sec. 2, Eq. 1 and Eq. 5), with the enthalpy-temperature relation of
+ *     Eq. 11 for a linear latent release between solidus and liquidus;
+ *   - Galerkin linear tetrahedra (Sec. 3, Eq. 9) and trilinear hexahedra,
+ *     with the row-sum lumped capacitance (Sec. 3);
+ *   - convective/flux boundaries (Eq. 4) and the cast/mould contact
+ *     conductance (Eq. 8) with the sister-face average as ambient
+ *     temperature (end of Sec. 3);
+ *   - the fully explicit update (Eq. 10 with theta = 0, i.e. Eq. 14),
+ *     assembled element by element (Eq. 15-18), written here for the nodal
+ *     enthalpy state: H_i += dt * r_i / m_i with r = F - K T;
+ *   - the partition-local sums with shared-node exchange of Eq. 19-22.
+ * Every routine is a direct loop over elements, faces or nodes in double
+ * precision with no blocking, fusion or reordering.
+ *
+ * Conventions: SI units, temperatures in deg C, specific enthalpy in J/kg with
+ * H = 0 at 0 C.  A material row is {k, rho, c, T_sol, T_liq, L}.  Indices are
+ * 0-based.  Every function returns 0 on success and a negative value on bad
+ * input (inverted element, index out of range, node shared by two materials).
+ */
+#ifndef CASTFEM_ORACLE_H
+#define CASTFEM_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    int32_t elem_type;          /* 4 = linear tetrahedron, 8 = trilinear hexahedron */
+    int64_t n_nodes;
+    const double *xyz;          /* n_nodes x 3 */
+    int64_t n_elems;
+    const int32_t *conn;        /* n_elems x elem_type */
+    const int32_t *elem_mat;    /* n_elems */
+    int32_t n_mat;
+    const double *materials;    /* n_mat x 6 */
+    int64_t n_dir;
+    const int32_t *dir_nodes;
+    const double *dir_T;
+    int64_t n_flux;
+    int32_t flux_npf;           /* 3 or 4 nodes per flux face */
+    const int32_t *flux_faces;  /* n_flux x flux_npf */
+    const double *flux_q, *flux_h, *flux_Tinf;
+    int64_t n_if;
+    const int32_t *if_a, *if_b; /* n_if x 3 each: matched faces on the two sides */
+    const double *if_h;
+} orc_problem;
+
+/* per-state diagnostics written by orc_run, ORC_NDIAG doubles per state */
+enum {
+    ORC_D_E = 0,        /* sum_i m_i H_i */
+    ORC_D_LATENT = 1,   /* sum_i m_i L_i (1 - fs_i): latent heat still to release */
+    ORC_D_Q = 2,        /* boundary heat inflow rate of the step leaving this state (W) */
+    ORC_D_QCUM = 3,     /* sum over earlier steps of dt * Q */
+    ORC_D_TMIN = 4,
+    ORC_D_TMAX = 5,
+    ORC_D_NLIQ = 6,     /* number of phase-change nodes with fs < 1 */
+    ORC_D_NONFINITE = 7,
+    ORC_D_RESID = 8,    /* |E - E0 - QCUM| / |E0 - E_ref|, E_ref = sum m_i H_i(25 C) */
+    ORC_NDIAG = 9
+};
+
+/* Element conductance matrix of a linear tetrahedron, row-major 4x4; *vol = volume. */
+int orc_tet_ke(const double x[12], double k, double Ke[16], double *vol);
+/* Element conductance matrix of a trilinear hexahedron by 2x2x2 Gauss-Legendre. */
+int orc_hex_ke(const double x[24], double k, double Ke[64], double *vol);
+/* Row-sum lumped capacitance weights rho * int N_a dV of one element. */
+int orc_elem_mass(int32_t elem_type, const double *x, double rho, double *m);
+
+/* Enthalpy relation of one material (Eq. 11 with linear latent release). */
+double orc_H_of_T(const double mat[6], double T);
+double orc_T_of_H(const double mat[6], double H);
+double orc_fs_of_H(const double mat[6], double H);
+
+/* m_i for every node; also validates the mesh. */
+int orc_lumped_mass(const orc_problem *p, double *m);
+/* Material of every node (-1 for nodes in no element); error if a node has two. */
+int orc_node_material(const orc_problem *p, int32_t *node_mat);
+/* r = F(T) - K T: element conduction, flux faces, interface pairs. */
+int orc_residual(const orc_problem *p, const double *T, double *r);
+/* Explicit stability bound 2 / lambda_hat with the Gershgorin estimate of M^-1 K. */
+int orc_stable_dt(const orc_problem *p, double *dt_bound);
+/* H_i = H(T0_i), Dirichlet temperatures overriding T0. */
+int orc_initial_H(const orc_problem *p, const double *T0, double *H);
+/* T and fs of every node from the enthalpy state. */
+int orc_state_T(const orc_problem *p, const double *H, double *T, double *fs);
+/* n explicit steps of the enthalpy update in place on H; diag (n_steps+1) x ORC_NDIAG or NULL. */
+int orc_run(const orc_problem *p, double dt, int64_t n_steps, double *H, double *diag);
+/* The same steps with the mesh split into n_parts element partitions (Eq. 19-22):
+   local capacitances and residuals per partition, then a sum over partitions at
+   shared nodes.  Face terms are given to partition (face index mod n_parts). */
+int orc_run_partitioned(const orc_problem *p, int32_t n_parts, const int32_t *elem_part,
+                        double dt, int64_t n_steps, double *H);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

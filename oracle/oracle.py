@@ -1,0 +1,210 @@
+"""ctypes front end of the FP64 CPU oracle (castfem_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: the test-suite, the package smoke check and the
+CPU-baseline leg of the benchmark are the only callers.  The product path
+never imports this module.
+"""
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "castfem_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+ORC_NDIAG = 9
+D_E, D_LATENT, D_Q, D_QCUM, D_TMIN, D_TMAX, D_NLIQ, D_NONFINITE, D_RESID = range(9)
+
+
+def build(force=False):
+    """Compile the oracle with gcc (plain -O2, no fast-math)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        _lib = C.CDLL(LIB)
+        d = C.c_double
+        _lib.orc_H_of_T.restype = d
+        _lib.orc_T_of_H.restype = d
+        _lib.orc_fs_of_H.restype = d
+        for f in (_lib.orc_H_of_T, _lib.orc_T_of_H, _lib.orc_fs_of_H):
+            f.argtypes = [C.c_void_p, d]
+    return _lib
+
+
+class _Problem(C.Structure):
+    _fields_ = [
+        ("elem_type", C.c_int32), ("n_nodes", C.c_int64), ("xyz", C.c_void_p),
+        ("n_elems", C.c_int64), ("conn", C.c_void_p), ("elem_mat", C.c_void_p),
+        ("n_mat", C.c_int32), ("materials", C.c_void_p),
+        ("n_dir", C.c_int64), ("dir_nodes", C.c_void_p), ("dir_T", C.c_void_p),
+        ("n_flux", C.c_int64), ("flux_npf", C.c_int32), ("flux_faces", C.c_void_p),
+        ("flux_q", C.c_void_p), ("flux_h", C.c_void_p), ("flux_Tinf", C.c_void_p),
+        ("n_if", C.c_int64), ("if_a", C.c_void_p), ("if_b", C.c_void_p), ("if_h", C.c_void_p),
+    ]
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p) if a.size else None
+
+
+class Problem:
+    """Holds contiguous copies of a problem dict and the C struct pointing at them."""
+
+    def __init__(self, prob):
+        f8 = lambda k: np.ascontiguousarray(prob[k], dtype=np.float64)
+        i4 = lambda k: np.ascontiguousarray(prob[k], dtype=np.int32)
+        self.keep = dict(
+            xyz=f8("xyz"), conn=i4("conn"), elem_mat=i4("elem_mat"), materials=f8("materials"),
+            dir_nodes=i4("dirichlet_nodes"), dir_T=f8("dirichlet_T"),
+            flux_faces=i4("flux_faces"), flux_q=f8("flux_q"), flux_h=f8("flux_h"),
+            flux_Tinf=f8("flux_Tinf"), if_a=i4("if_a"), if_b=i4("if_b"), if_h=f8("if_h"))
+        k = self.keep
+        self.T0 = np.ascontiguousarray(prob["T0"], dtype=np.float64)
+        self.n_nodes = k["xyz"].shape[0]
+        ff = k["flux_faces"]
+        self.s = _Problem(
+            int(prob["elem_type"]), self.n_nodes, _ptr(k["xyz"]),
+            k["conn"].shape[0], _ptr(k["conn"]), _ptr(k["elem_mat"]),
+            k["materials"].shape[0], _ptr(k["materials"]),
+            k["dir_nodes"].size, _ptr(k["dir_nodes"]), _ptr(k["dir_T"]),
+            ff.shape[0] if ff.size else 0, ff.shape[1] if ff.ndim == 2 else 3, _ptr(ff),
+            _ptr(k["flux_q"]), _ptr(k["flux_h"]), _ptr(k["flux_Tinf"]),
+            k["if_a"].shape[0] if k["if_a"].size else 0, _ptr(k["if_a"]), _ptr(k["if_b"]),
+            _ptr(k["if_h"]))
+
+    @property
+    def ref(self):
+        return C.byref(self.s)
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise ValueError("oracle %s failed with code %d" % (what, rc))
+
+
+def _as_problem(p):
+    return p if isinstance(p, Problem) else Problem(p)
+
+
+def tet_ke(x, k):
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(12)
+    Ke = np.zeros(16)
+    V = C.c_double()
+    _check(lib().orc_tet_ke(_ptr(x), C.c_double(k), _ptr(Ke), C.byref(V)), "tet_ke")
+    return Ke.reshape(4, 4), V.value
+
+
+def hex_ke(x, k):
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(24)
+    Ke = np.zeros(64)
+    V = C.c_double()
+    _check(lib().orc_hex_ke(_ptr(x), C.c_double(k), _ptr(Ke), C.byref(V)), "hex_ke")
+    return Ke.reshape(8, 8), V.value
+
+
+def elem_mass(elem_type, x, rho):
+    x = np.ascontiguousarray(x, dtype=np.float64).ravel()
+    m = np.zeros(elem_type)
+    _check(lib().orc_elem_mass(C.c_int32(elem_type), _ptr(x), C.c_double(rho), _ptr(m)), "elem_mass")
+    return m
+
+
+def _mat(mat):
+    a = np.ascontiguousarray(mat, dtype=np.float64).reshape(6)
+    return a, _ptr(a)
+
+
+def H_of_T(mat, T):
+    a, p = _mat(mat)
+    return np.array([lib().orc_H_of_T(p, float(t)) for t in np.ravel(T)])
+
+
+def T_of_H(mat, H):
+    a, p = _mat(mat)
+    return np.array([lib().orc_T_of_H(p, float(h)) for h in np.ravel(H)])
+
+
+def fs_of_H(mat, H):
+    a, p = _mat(mat)
+    return np.array([lib().orc_fs_of_H(p, float(h)) for h in np.ravel(H)])
+
+
+def lumped_mass(prob):
+    P = _as_problem(prob)
+    m = np.zeros(P.n_nodes)
+    _check(lib().orc_lumped_mass(P.ref, _ptr(m)), "lumped_mass")
+    return m
+
+
+def node_material(prob):
+    P = _as_problem(prob)
+    nm = np.zeros(P.n_nodes, np.int32)
+    _check(lib().orc_node_material(P.ref, _ptr(nm)), "node_material")
+    return nm
+
+
+def residual(prob, T):
+    P = _as_problem(prob)
+    T = np.ascontiguousarray(T, dtype=np.float64)
+    r = np.zeros(P.n_nodes)
+    _check(lib().orc_residual(P.ref, _ptr(T), _ptr(r)), "residual")
+    return r
+
+
+def stable_dt(prob):
+    P = _as_problem(prob)
+    dt = C.c_double()
+    _check(lib().orc_stable_dt(P.ref, C.byref(dt)), "stable_dt")
+    return dt.value
+
+
+def initial_H(prob, T0=None):
+    P = _as_problem(prob)
+    if T0 is None:
+        T0 = P.T0
+    T0 = np.ascontiguousarray(T0, dtype=np.float64)
+    H = np.zeros(P.n_nodes)
+    _check(lib().orc_initial_H(P.ref, _ptr(T0), _ptr(H)), "initial_H")
+    return H
+
+
+def state_T(prob, H):
+    P = _as_problem(prob)
+    H = np.ascontiguousarray(H, dtype=np.float64)
+    T = np.zeros(P.n_nodes)
+    fs = np.zeros(P.n_nodes)
+    _check(lib().orc_state_T(P.ref, _ptr(H), _ptr(T), _ptr(fs)), "state_T")
+    return T, fs
+
+
+def run(prob, dt, n_steps, H=None, diag=False):
+    """n explicit steps from H (default: the initial state of prob).  Returns (H, T, fs[, diag])."""
+    P = _as_problem(prob)
+    H = initial_H(P) if H is None else np.array(H, dtype=np.float64)
+    D = np.zeros((n_steps + 1, ORC_NDIAG)) if diag else None
+    _check(lib().orc_run(P.ref, C.c_double(dt), C.c_int64(n_steps), _ptr(H),
+                         _ptr(D) if diag else None), "run")
+    T, fs = state_T(P, H)
+    return (H, T, fs, D) if diag else (H, T, fs)
+
+
+def run_partitioned(prob, elem_part, n_parts, dt, n_steps, H=None):
+    P = _as_problem(prob)
+    H = initial_H(P) if H is None else np.array(H, dtype=np.float64)
+    ep = np.ascontiguousarray(elem_part, dtype=np.int32)
+    _check(lib().orc_run_partitioned(P.ref, C.c_int32(n_parts), _ptr(ep), C.c_double(dt),
+                                     C.c_int64(n_steps), _ptr(H)), "run_partitioned")
+    return H
