@@ -1,0 +1,199 @@
+#!/usr/bin/env python3
+"""Benchmark of the explicit casting step on one MI355X.
+
+Workload: 128^3 jittered Kuhn tetrahedra (12,582,912 tets, 2,181,347 nodes with
+the duplicated cast/mould interface), an alloy cube [0.2, 0.8]^3 poured at
+700 C in a sand mould at 25 C, contact coefficient 1000 W/m^2K, adiabatic outer
+boundary, random input numbering, FP32 state with compensated enthalpy and FP64
+T(H) and reductions, dt = 0.9 x the Gershgorin stability bound.
+
+A step is one explicit time step over the whole mesh (element residuals,
+scatter, interface fluxes, enthalpy update, FP64 energy partials).  Setup
+(reordering, blocking, autotuning) is outside the timed region and reported
+separately.  Prints one JSON line.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "element-steps/s + HBM GB/s %peak; surrogate vs plain time-to-solidify at ≤0.5 K"
+HBM_PEAK_GBS = 8000.0
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "kernels.hpp", "elem.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_1005_3158_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kind):
+    """HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs, if they
+    were taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % kind)
+    if not os.path.exists(path):
+        return None
+    t = json.load(open(path))
+    if t.get("kernel_hash") != kernel_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=32)
+    ap.add_argument("--n", type=int, default=128, help="grid cubes per axis (128 = the benchmark mesh)")
+    ap.add_argument("--cpu-steps", type=int, default=3, help="oracle steps timed for the CPU baseline (0 = skip)")
+    ap.add_argument("--profile-steps", type=int, default=64)
+    ap.add_argument("--scatter", default="lds", choices=["lds", "atomic", "colored"])
+    ap.add_argument("--ordering", default="hilbert", choices=["none", "rcm", "morton", "hilbert"])
+    ap.add_argument("--block-nodes", type=int, default=0, help="LDS block node cap (0 = autotune)")
+    ap.add_argument("--quiet", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: the explicit step is built and measured on a single MI355X; "
+              "a multi-GPU run is not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    def log(*a):
+        if not args.quiet:
+            print(*a, file=sys.stderr, flush=True)
+
+    import torch
+    from castgen import configs
+    from paper_1005_3158_amd import castfem as cf
+
+    t0 = time.time()
+    prob = configs.config2(n=args.n)
+    t_gen = time.time() - t0
+    E, N = prob["conn"].shape[0], prob["xyz"].shape[0]
+    log("inputs: %d tets, %d nodes (%.1f s)" % (E, N, t_gen))
+    golden = json.load(open(os.path.join(ROOT, "tests", "golden", "oracle_constants.json")))
+
+    scatter = {"lds": cf.FEM_SCATTER_LDS_BLOCKED, "atomic": cf.FEM_SCATTER_GLOBAL_ATOMIC,
+               "colored": cf.FEM_SCATTER_COLORED}[args.scatter]
+    ordering = {"none": cf.FEM_ORDER_NONE, "rcm": cf.FEM_ORDER_RCM, "morton": cf.FEM_ORDER_MORTON,
+                "hilbert": cf.FEM_ORDER_HILBERT}[args.ordering]
+    opts = dict(precision=cf.FEM_PREC_FP32_KAHAN, scatter=scatter, ordering=ordering)
+    if args.block_nodes:
+        opts["lds_bytes"] = 24 * args.block_nodes
+    t0 = time.time()
+    s = cf.Solver(prob, **opts)
+    t_setup = time.time() - t0
+    rep = s.report
+    log("setup %.1f s (host prep %.1f s): blocks %d, shared %.3f, max local nodes %d"
+        % (t_setup, rep["setup_seconds"], rep["n_blocks"], rep["shared_fraction"], rep["max_local_nodes"]))
+    dt_bound = s.stable_dt()
+    if args.n == 128:
+        ref = golden["config2"]["dt_bound"]
+        if abs(dt_bound - ref) > 1e-9 * ref:
+            raise SystemExit("stability bound %.17g differs from the oracle's %.17g" % (dt_bound, ref))
+        dt_bound = ref
+    dt = 0.9 * dt_bound
+
+    # warm-up, then the timed steps (inputs resident in HBM)
+    s.step(dt, args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(dt, args.steps)
+    torch.cuda.synchronize()
+    t_run = time.perf_counter() - t0
+    en = s.energy()
+    ms_step = 1e3 * t_run / args.steps
+    value = E * args.steps / t_run
+    b_alg = 16.0 * E + 48.0 * N
+    eff_gbs = b_alg * args.steps / t_run / 1e9
+    log("steps %d in %.4f s: %.3f ms/step, %.4g element-steps/s, effective %.1f GB/s; energy residual %.2e"
+        % (args.steps, t_run, ms_step, value, eff_gbs, en["residual"]))
+
+    # per-kernel durations with HIP events on the solver stream
+    kt = cf.fem_time_kernels(s.ctx, dt, args.profile_steps)
+    ach_e = kt["bytes_element"] / (kt["ms_element"] * 1e-3) / 1e9
+    ach_c = kt["bytes_combine"] / (kt["ms_combine"] * 1e-3) / 1e9 if kt["ms_combine"] > 0 else None
+    log("element kernel %.4f ms (%.1f GB/s alg), node kernel %.4f ms" % (kt["ms_element"], ach_e, kt["ms_combine"]))
+    traffic = load_traffic("block_element_config2")
+
+    # plain copy ceiling on this device
+    nbytes = 1 << 30
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    ms_copy = cf.fem_copy_kernel(s.ctx, dst.data_ptr(), src.data_ptr(), nbytes, 20)
+    copy_gbs = 2 * nbytes / (ms_copy * 1e-3) / 1e9
+    del src, dst
+    log("copy kernel: %.1f GB/s" % copy_gbs)
+
+    # parity spot check and CPU baseline: the FP64 oracle over the first steps
+    cpu = None
+    parity = None
+    if args.cpu_steps > 0:
+        from oracle import oracle
+        k = args.cpu_steps
+        s2 = cf.Solver(prob, **dict(opts, lds_bytes=24 * rep["max_local_nodes"]) if scatter == cf.FEM_SCATTER_LDS_BLOCKED else opts)
+        s2.step(dt, k)
+        T_gpu = s2.T()
+        s2.close()
+        P = oracle.Problem(prob)
+        t0 = time.perf_counter()
+        H, T_ref, fs_ref = oracle.run(P, dt, k)
+        t_cpu = time.perf_counter() - t0
+        cpu = {"value": E * k / t_cpu, "unit": "element-steps/s", "cores": 1, "kind": "oracle",
+               "sample": "%d explicit steps of the full 128^3 mesh from the initial state (FP64, one thread, "
+                         "including its lumping and initial enthalpy), %.1f s" % (k, t_cpu)}
+        parity = {"steps": k, "max_abs_dT_K": float(np.max(np.abs(T_gpu - T_ref)))}
+        log("oracle: %d steps in %.1f s; max|T_gpu - T_oracle| = %.3e K" % (k, t_cpu, parity["max_abs_dT_K"]))
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "element-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (compensated enthalpy, f64 T(H) and reductions)",
+        "data": "synthetic",
+        "config": {
+            "workload": "128^3 jittered Kuhn tets (%d tets, %d nodes), alloy cube in sand mould, h_i=1000, "
+                        "random input numbering, %s ordering, %s scatter, dt=0.9 x bound" % (E, N, args.ordering, args.scatter),
+            "n_elems": E, "n_nodes": N, "dt": dt, "block_nodes": rep["max_local_nodes"], "n_blocks": rep["n_blocks"],
+            "shared_fraction": rep["shared_fraction"], "setup_s": t_setup,
+        },
+        "effective_GBps": eff_gbs,
+        "effective_frac_hbm": eff_gbs / HBM_PEAK_GBS,
+        "copy_kernel_GBps": copy_gbs,
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_block<float,4> (blocked element residual + private-node update)",
+            "achieved": ach_e,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": ach_e / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "ms_per_launch": kt["ms_element"],
+            "alg_bytes_per_launch": kt["bytes_element"],
+            "node_kernel": {"ms_per_launch": kt["ms_combine"], "alg_bytes_per_launch": kt["bytes_combine"],
+                            "achieved": ach_c},
+        },
+        "cpu_baseline": cpu,
+        "parity": parity,
+        "energy_residual": en["residual"],
+    }
+    s.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,219 @@
+/*
+ * castfem: explicit finite-element casting-solidification step on MI355X (gfx950).
+ *
+ * Method (R. Tavakoli, "Improvement cache efficiency of explicit finite element
+ * procedure and its application to parallel casting solidification
+ * simulation", 2006):
+ *   - heat conduction with phase change, written for the nodal specific
+ *     enthalpy H (Sec. 2, Eq. 1 and Eq. 5) with T = T(H) from the enthalpy
+ *     relation of Eq. 11 (linear latent release between solidus and liquidus);
+ *   - Galerkin linear tetrahedra (Sec. 3, Eq. 9) or trilinear hexahedra,
+ *     row-sum lumped capacitance (Sec. 3);
+ *   - fully explicit update (Eq. 10 with theta = 0, i.e. Eq. 14) assembled
+ *     element by element (Eq. 15-18): H_i += dt * r_i / m_i, r = F - K T;
+ *   - flux/convective boundaries (Eq. 4) and cast/mould contact conductance
+ *     (Eq. 8) whose ambient temperature is the mean of the sister face on the
+ *     other side (end of Sec. 3);
+ *   - element blocks with private/shared nodes and a sum of partial residuals
+ *     at shared nodes (Eq. 19-22, Sec. 4.1.2 and the cache blocking of
+ *     Sec. 4.2), here held in LDS per workgroup.
+ *
+ * Conventions
+ *   - SI units, temperatures in deg C, specific enthalpy J/kg with H = 0 at 0 C.
+ *   - Indices are 0-based int32; counts are int64.
+ *   - Every function returns FEM_OK (0) or a negative FEM_E_* code and, on
+ *     error, sets a thread-local message read by fem_last_error().  No C++
+ *     exception crosses this interface.  A setup call that fails leaves the
+ *     context as it was.
+ *   - Host arrays passed in are owned by the caller and copied during the call.
+ *   - Device buffers are owned by the caller (allocated after
+ *     fem_query_buffers) and borrowed by the context until fem_destroy.  The
+ *     library allocates no device memory of its own.
+ *   - Work is enqueued on the stream given to fem_set_stream.  Stepping is
+ *     asynchronous; read-back calls synchronise that stream.  A failure of
+ *     asynchronous work is reported by the next synchronising call.
+ */
+#ifndef CASTFEM_H
+#define CASTFEM_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ codes */
+enum {
+    FEM_OK = 0,
+    FEM_E_INVALID_ARG = -1,   /* null pointer, bad size or enum value */
+    FEM_E_MESH = -2,          /* inverted element, node in two materials, index out of range */
+    FEM_E_STATE = -3,         /* call out of order (e.g. step before bind) */
+    FEM_E_UNSTABLE = -4,      /* dt above the explicit stability bound */
+    FEM_E_NONFINITE = -5,     /* the state holds NaN or Inf */
+    FEM_E_HIP = -6,           /* a HIP runtime call failed */
+    FEM_E_UNSUPPORTED = -7    /* option combination not built */
+};
+
+enum { FEM_TET4 = 4, FEM_HEX8 = 8 };
+enum { FEM_PREC_FP64 = 0, FEM_PREC_FP32_KAHAN = 1 };
+enum { FEM_ORDER_NONE = 0, FEM_ORDER_RCM = 1, FEM_ORDER_MORTON = 2, FEM_ORDER_HILBERT = 3 };
+enum { FEM_SCATTER_GLOBAL_ATOMIC = 0, FEM_SCATTER_LDS_BLOCKED = 1, FEM_SCATTER_COLORED = 2 };
+
+typedef struct fem_ctx fem_ctx;
+
+typedef struct {
+    int32_t device;          /* HIP device ordinal */
+    int32_t precision;       /* FEM_PREC_* */
+    int32_t ordering;        /* FEM_ORDER_*: node/element locality reordering */
+    int32_t scatter;         /* FEM_SCATTER_* */
+    int32_t block_elems;     /* LDS-blocked: elements per block; 0 = autotune */
+    int32_t allow_unstable;  /* nonzero: fem_step accepts dt above the bound */
+    int32_t lds_bytes;       /* LDS-blocked: LDS budget per workgroup; 0 = default */
+    int32_t threads;         /* LDS-blocked: threads per workgroup; 0 = default (256) */
+    int32_t reserved[8];     /* must be zero */
+} fem_options;
+
+/* One material: conductivity k (W/mK), density rho (kg/m^3), specific heat c
+ * (J/kgK), solidus and liquidus (C) and latent heat L (J/kg).  L = 0: no phase
+ * change (fraction solid reported as 1).  T_sol == T_liq: isothermal change. */
+typedef struct {
+    double k, rho, c, T_sol, T_liq, L;
+} fem_material;
+
+typedef struct {
+    int64_t n_nodes, n_elems;
+    int64_t n_blocks;            /* LDS-blocked: element blocks */
+    int64_t n_shared;            /* LDS-blocked: nodes touched by more than one block */
+    int64_t n_partials;          /* LDS-blocked: (block, shared node) partial slots */
+    int64_t max_local_nodes;     /* LDS-blocked: largest block node set */
+    int64_t n_colors;            /* colored: element colours */
+    int64_t bandwidth_before;    /* max |i - j| over coupled nodes, input numbering */
+    int64_t bandwidth_after;     /* the same after reordering */
+    int64_t block_elems;         /* elements per block in use */
+    double shared_fraction;      /* n_shared / n_nodes */
+    double dt_bound;             /* explicit stability bound (s) */
+    double setup_seconds;        /* host time of fem_finalize */
+    int64_t reserved[4];
+} fem_prep_report;
+
+typedef struct {
+    char name[32];
+    int64_t bytes;               /* size the caller must allocate (may be 0) */
+    int64_t alignment;           /* required alignment of the device pointer */
+} fem_buffer_desc;
+
+typedef struct {
+    double E;                /* sum_i m_i H_i (J), FP64 */
+    double E0;               /* E of the initial state */
+    double latent;           /* sum_i m_i L_i (1 - fs_i): latent heat still to release */
+    double Q_cum;            /* sum over steps of dt * boundary inflow (J) */
+    double residual;         /* |E - E0 - Q_cum| / |E0 - E_ref|, E_ref = sum m_i H_i(25 C) */
+    double T_min, T_max;
+    int64_t n_liquid;        /* phase-change nodes with fraction solid < 1 */
+    int64_t nonfinite;       /* nodes whose enthalpy is NaN or Inf */
+    int64_t steps;           /* steps taken since the initial state */
+    double time;             /* simulated time (s) */
+} fem_energy_report;
+
+typedef struct {
+    double ms_element;       /* mean duration of one element (block) kernel launch */
+    double ms_combine;       /* mean duration of one node update / shared combine launch */
+    int64_t launches_element, launches_combine;
+    double bytes_element;    /* algorithmic bytes per element-kernel launch */
+    double bytes_combine;    /* algorithmic bytes per combine-kernel launch */
+} fem_kernel_times;
+
+/* ------------------------------------------------------------ lifecycle */
+/* Create a context.  opt may be NULL for the defaults (device 0, FP32 with
+ * Kahan-compensated enthalpy, Hilbert ordering, LDS-blocked scatter,
+ * autotuned block size).  *out receives the handle. */
+int fem_create(fem_ctx **out, const fem_options *opt);
+/* Release host memory of the context.  Device buffers stay with the caller. */
+int fem_destroy(fem_ctx *ctx);
+/* Message of the last failing call on this thread ("" if none). */
+const char *fem_last_error(void);
+/* Stream (a hipStream_t) for all device work; NULL = the null stream, which
+ * disables graph capture of fem_step. */
+int fem_set_stream(fem_ctx *ctx, void *hip_stream);
+
+/* ------------------------------------------------------------ problem */
+/* Mesh (Sec. 3): xyz is n_nodes x 3 (m), conn is n_elems x elem_type node ids
+ * with positive orientation (tet: (x1-x0).((x2-x0)x(x3-x0)) > 0; hex: the
+ * usual bottom-then-top ordering), elem_mat the material of every element.
+ * Nodes on a cast/mould interface must be duplicated, one copy per side, so
+ * that every node belongs to one material (checked by fem_finalize). */
+int fem_upload_mesh(fem_ctx *ctx, int32_t elem_type, int64_t n_nodes, const double *xyz,
+                    int64_t n_elems, const int32_t *conn, const int32_t *elem_mat);
+/* Material table (Eq. 1, Eq. 11); n_mat entries indexed by elem_mat. */
+int fem_set_materials(fem_ctx *ctx, int32_t n_mat, const fem_material *m);
+/* Fixed temperatures (Eq. 3, constant in time): n node ids and their values.
+ * A fixed node keeps H(T_value) and its residual counts as boundary inflow. */
+int fem_set_dirichlet(fem_ctx *ctx, int64_t n, const int32_t *node, const double *T_value);
+/* Flux/convective faces (Eq. 4): -k dT/dn = q + h (T - T_inf).  face_nodes is
+ * nf x nodes_per_face (3 or 4); each node of face f receives
+ * (A_f / nodes_per_face) (-q_f - h_f (T_i - T_inf_f)).  A quad's area is half
+ * the norm of the cross product of its diagonals.  Faces not listed are
+ * adiabatic. */
+int fem_set_flux_faces(fem_ctx *ctx, int64_t nf, int32_t nodes_per_face, const int32_t *face_nodes,
+                       const double *q, const double *h, const double *T_inf);
+/* Cast/mould contact (Eq. 8, sister faces at the end of Sec. 3): npairs
+ * triangles face_a[3] / face_b[3] on the two sides of the interface with
+ * coefficient h_i.  Node i of one side receives h_i (A/3) (mean T of the
+ * other face - T_i), A the area of face_a. */
+int fem_set_interface(fem_ctx *ctx, int64_t npairs, const int32_t *face_a, const int32_t *face_b,
+                      const double *h_i);
+/* Initial temperature of every node (Eq. 2); fixed nodes take their value. */
+int fem_set_initial_T(fem_ctx *ctx, const double *T0);
+
+/* Validate, lump, reorder, block, colour and bound dt (host work only, no
+ * device call).  rep may be NULL. */
+int fem_finalize(fem_ctx *ctx, fem_prep_report *rep);
+/* Device buffers the context needs.  Call with d == NULL to get the count in
+ * *n; then with an array of *n descriptors. */
+int fem_query_buffers(const fem_ctx *ctx, fem_buffer_desc *d, int32_t *n);
+/* Hand over device pointers in the order of fem_query_buffers, upload the
+ * static data and the initial state (and autotune the block size when
+ * requested).  Synchronises the stream. */
+int fem_bind_buffers(fem_ctx *ctx, void *const *dev_ptrs, int32_t n);
+/* Report of the finalized layout (valid after fem_finalize; block fields are
+ * final after fem_bind_buffers). */
+int fem_get_report(const fem_ctx *ctx, fem_prep_report *rep);
+
+/* ------------------------------------------------------------ stepping */
+/* Explicit stability bound: 2 / max_i [sum_j |K_ij| + boundary terms] / (m_i c_i)
+ * (Gershgorin on the lumped system with the sensible heat c; Eq. 13 states
+ * only the scaling rho c l^2 / k). */
+int fem_stable_dt(const fem_ctx *ctx, double *dt);
+/* n_steps explicit steps of size dt (Eq. 14 in enthalpy form), enqueued on the
+ * stream; repeated calls reuse a captured hipGraph. */
+int fem_step(fem_ctx *ctx, double dt, int64_t n_steps);
+
+/* ------------------------------------------------------------ read-back */
+/* Temperature / fraction solid / enthalpy of every node in the caller's
+ * numbering (n_nodes doubles).  Synchronous. */
+int fem_read_T(fem_ctx *ctx, double *T_host);
+int fem_read_fs(fem_ctx *ctx, double *fs_host);
+int fem_read_H(fem_ctx *ctx, double *H_host);
+/* FP64 energy balance of the current state (wavefront partials summed in a
+ * fixed order).  Synchronous. */
+int fem_energy(fem_ctx *ctx, fem_energy_report *rep);
+/* Checkpoint of the evolving state (enthalpy, its compensation, both
+ * temperature buffers, step count, time, energy budget).  With buf == NULL
+ * *bytes receives the size. */
+int fem_read_state(fem_ctx *ctx, void *buf, int64_t *bytes);
+int fem_write_state(fem_ctx *ctx, const void *buf, int64_t bytes);
+/* New (device) id of every input node (n_nodes int32). */
+int fem_get_node_perm(const fem_ctx *ctx, int32_t *perm);
+
+/* ------------------------------------------------------------ measurement */
+/* Run n_steps without a graph, bracketing every kernel with HIP events on the
+ * context stream, and return the mean launch durations and the algorithmic
+ * bytes per launch (16 B per element, 48 B per node split between kernels). */
+int fem_time_kernels(fem_ctx *ctx, double dt, int64_t n_steps, fem_kernel_times *out);
+/* Device-to-device copy of `bytes` (multiple of 16) by a plain vector kernel on
+ * the context stream; the reference for measured bandwidth and counters. */
+int fem_copy_kernel(fem_ctx *ctx, void *dst, const void *src, int64_t bytes, int32_t repeats, double *ms_per_copy);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

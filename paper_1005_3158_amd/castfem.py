@@ -1,0 +1,355 @@
+"""ctypes binding of libcastfem.so: the C functions under their own names, plus
+`Solver`, which owns the device buffers through torch.
+
+Every step of the casting path runs in the HIP library; this module only
+marshals arguments.  If the library is missing the import fails loudly.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcastfem.so")
+
+FEM_OK = 0
+ERRORS = {-1: "FEM_E_INVALID_ARG", -2: "FEM_E_MESH", -3: "FEM_E_STATE", -4: "FEM_E_UNSTABLE",
+          -5: "FEM_E_NONFINITE", -6: "FEM_E_HIP", -7: "FEM_E_UNSUPPORTED"}
+FEM_TET4, FEM_HEX8 = 4, 8
+FEM_PREC_FP64, FEM_PREC_FP32_KAHAN = 0, 1
+FEM_ORDER_NONE, FEM_ORDER_RCM, FEM_ORDER_MORTON, FEM_ORDER_HILBERT = 0, 1, 2, 3
+FEM_SCATTER_GLOBAL_ATOMIC, FEM_SCATTER_LDS_BLOCKED, FEM_SCATTER_COLORED = 0, 1, 2
+
+EXPORTS = [
+    "fem_create", "fem_destroy", "fem_last_error", "fem_set_stream", "fem_upload_mesh", "fem_set_materials",
+    "fem_set_dirichlet", "fem_set_flux_faces", "fem_set_interface", "fem_set_initial_T", "fem_finalize",
+    "fem_query_buffers", "fem_bind_buffers", "fem_get_report", "fem_stable_dt", "fem_step", "fem_read_T",
+    "fem_read_fs", "fem_read_H", "fem_energy", "fem_read_state", "fem_write_state", "fem_get_node_perm",
+    "fem_time_kernels", "fem_copy_kernel",
+]
+
+
+class FemError(RuntimeError):
+    def __init__(self, code, fn, msg):
+        super().__init__("%s failed: %s (%s)" % (fn, msg, ERRORS.get(code, code)))
+        self.code = code
+
+
+class fem_options(C.Structure):
+    _fields_ = [("device", C.c_int32), ("precision", C.c_int32), ("ordering", C.c_int32),
+                ("scatter", C.c_int32), ("block_elems", C.c_int32), ("allow_unstable", C.c_int32),
+                ("lds_bytes", C.c_int32), ("threads", C.c_int32), ("reserved", C.c_int32 * 8)]
+
+
+class fem_material(C.Structure):
+    _fields_ = [("k", C.c_double), ("rho", C.c_double), ("c", C.c_double), ("T_sol", C.c_double),
+                ("T_liq", C.c_double), ("L", C.c_double)]
+
+
+class fem_prep_report(C.Structure):
+    _fields_ = [("n_nodes", C.c_int64), ("n_elems", C.c_int64), ("n_blocks", C.c_int64),
+                ("n_shared", C.c_int64), ("n_partials", C.c_int64), ("max_local_nodes", C.c_int64),
+                ("n_colors", C.c_int64), ("bandwidth_before", C.c_int64), ("bandwidth_after", C.c_int64),
+                ("block_elems", C.c_int64), ("shared_fraction", C.c_double), ("dt_bound", C.c_double),
+                ("setup_seconds", C.c_double), ("reserved", C.c_int64 * 4)]
+
+
+class fem_buffer_desc(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("bytes", C.c_int64), ("alignment", C.c_int64)]
+
+
+class fem_energy_report(C.Structure):
+    _fields_ = [("E", C.c_double), ("E0", C.c_double), ("latent", C.c_double), ("Q_cum", C.c_double),
+                ("residual", C.c_double), ("T_min", C.c_double), ("T_max", C.c_double),
+                ("n_liquid", C.c_int64), ("nonfinite", C.c_int64), ("steps", C.c_int64), ("time", C.c_double)]
+
+
+class fem_kernel_times(C.Structure):
+    _fields_ = [("ms_element", C.c_double), ("ms_combine", C.c_double), ("launches_element", C.c_int64),
+                ("launches_combine", C.c_int64), ("bytes_element", C.c_double), ("bytes_combine", C.c_double)]
+
+
+def _as_dict(s):
+    return {k: (list(getattr(s, k)) if k == "reserved" else getattr(s, k)) for k, _ in s._fields_ if k != "reserved"}
+
+
+_lib = None
+
+
+def lib():
+    """Load libcastfem.so; raise if it has not been built (there is no fallback path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libcastfem.so is not built: run __graft_entry__.build() "
+                              "(or python paper_1005_3158_amd/build.py)")
+        L = C.CDLL(LIB_PATH)
+        L.fem_last_error.restype = C.c_char_p
+        vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        sig = {
+            "fem_create": [vp, vp], "fem_destroy": [vp], "fem_set_stream": [vp, vp],
+            "fem_upload_mesh": [vp, i32, i64, vp, i64, vp, vp], "fem_set_materials": [vp, i32, vp],
+            "fem_set_dirichlet": [vp, i64, vp, vp], "fem_set_flux_faces": [vp, i64, i32, vp, vp, vp, vp],
+            "fem_set_interface": [vp, i64, vp, vp, vp], "fem_set_initial_T": [vp, vp],
+            "fem_finalize": [vp, vp], "fem_query_buffers": [vp, vp, vp], "fem_bind_buffers": [vp, vp, i32],
+            "fem_get_report": [vp, vp], "fem_stable_dt": [vp, vp], "fem_step": [vp, dp, i64],
+            "fem_read_T": [vp, vp], "fem_read_fs": [vp, vp], "fem_read_H": [vp, vp], "fem_energy": [vp, vp],
+            "fem_read_state": [vp, vp, vp], "fem_write_state": [vp, vp, i64], "fem_get_node_perm": [vp, vp],
+            "fem_time_kernels": [vp, dp, i64, vp], "fem_copy_kernel": [vp, vp, vp, i64, i32, vp],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _call(name, *args):
+    rc = getattr(lib(), name)(*args)
+    if rc != FEM_OK:
+        raise FemError(rc, name, lib().fem_last_error().decode())
+    return rc
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None and a.size else None
+
+
+# ------------------------------------------------------------ same-name wrappers
+def fem_create(opt=None):
+    ctx = C.c_void_p()
+    _call("fem_create", C.byref(ctx), C.byref(opt) if opt is not None else None)
+    return ctx
+
+
+def fem_destroy(ctx):
+    _call("fem_destroy", ctx)
+
+
+def fem_last_error():
+    return lib().fem_last_error().decode()
+
+
+def fem_set_stream(ctx, stream_ptr):
+    _call("fem_set_stream", ctx, C.c_void_p(stream_ptr))
+
+
+def fem_upload_mesh(ctx, elem_type, xyz, conn, elem_mat):
+    xyz = np.ascontiguousarray(xyz, np.float64)
+    conn = np.ascontiguousarray(conn, np.int32)
+    em = np.ascontiguousarray(elem_mat, np.int32)
+    _call("fem_upload_mesh", ctx, int(elem_type), xyz.shape[0], _p(xyz), conn.shape[0], _p(conn), _p(em))
+
+
+def fem_set_materials(ctx, materials):
+    m = np.ascontiguousarray(materials, np.float64).reshape(-1, 6)
+    arr = (fem_material * m.shape[0])(*[fem_material(*row) for row in m])
+    _call("fem_set_materials", ctx, m.shape[0], arr)
+
+
+def fem_set_dirichlet(ctx, nodes, values):
+    n = np.ascontiguousarray(nodes, np.int32)
+    v = np.ascontiguousarray(values, np.float64)
+    _call("fem_set_dirichlet", ctx, n.size, _p(n), _p(v))
+
+
+def fem_set_flux_faces(ctx, faces, q, h, T_inf):
+    f = np.ascontiguousarray(faces, np.int32)
+    npf = f.shape[1] if f.ndim == 2 and f.size else 3
+    nf = f.shape[0] if f.size else 0
+    _call("fem_set_flux_faces", ctx, nf, npf, _p(f), _p(np.ascontiguousarray(q, np.float64)),
+          _p(np.ascontiguousarray(h, np.float64)), _p(np.ascontiguousarray(T_inf, np.float64)))
+
+
+def fem_set_interface(ctx, face_a, face_b, h):
+    a = np.ascontiguousarray(face_a, np.int32)
+    b = np.ascontiguousarray(face_b, np.int32)
+    hh = np.ascontiguousarray(h, np.float64)
+    _call("fem_set_interface", ctx, hh.size, _p(a), _p(b), _p(hh))
+
+
+def fem_set_initial_T(ctx, T0):
+    t = np.ascontiguousarray(T0, np.float64)
+    _call("fem_set_initial_T", ctx, _p(t))
+
+
+def fem_finalize(ctx):
+    rep = fem_prep_report()
+    _call("fem_finalize", ctx, C.byref(rep))
+    return _as_dict(rep)
+
+
+def fem_get_report(ctx):
+    rep = fem_prep_report()
+    _call("fem_get_report", ctx, C.byref(rep))
+    return _as_dict(rep)
+
+
+def fem_query_buffers(ctx):
+    n = C.c_int32(0)
+    _call("fem_query_buffers", ctx, None, C.byref(n))
+    arr = (fem_buffer_desc * n.value)()
+    _call("fem_query_buffers", ctx, arr, C.byref(n))
+    return [(d.name.decode(), d.bytes, d.alignment) for d in arr]
+
+
+def fem_bind_buffers(ctx, ptrs):
+    arr = (C.c_void_p * len(ptrs))(*[C.c_void_p(p) if p else None for p in ptrs])
+    _call("fem_bind_buffers", ctx, arr, len(ptrs))
+
+
+def fem_stable_dt(ctx):
+    dt = C.c_double()
+    _call("fem_stable_dt", ctx, C.byref(dt))
+    return dt.value
+
+
+def fem_step(ctx, dt, n_steps):
+    _call("fem_step", ctx, float(dt), int(n_steps))
+
+
+def _read(name, ctx, n):
+    out = np.empty(n, np.float64)
+    _call(name, ctx, _p(out))
+    return out
+
+
+def fem_read_T(ctx, n):
+    return _read("fem_read_T", ctx, n)
+
+
+def fem_read_fs(ctx, n):
+    return _read("fem_read_fs", ctx, n)
+
+
+def fem_read_H(ctx, n):
+    return _read("fem_read_H", ctx, n)
+
+
+def fem_energy(ctx):
+    rep = fem_energy_report()
+    _call("fem_energy", ctx, C.byref(rep))
+    return _as_dict(rep)
+
+
+def fem_read_state(ctx):
+    nb = C.c_int64(0)
+    _call("fem_read_state", ctx, None, C.byref(nb))
+    buf = np.empty(nb.value, np.uint8)
+    _call("fem_read_state", ctx, _p(buf), C.byref(nb))
+    return buf
+
+
+def fem_write_state(ctx, buf):
+    b = np.ascontiguousarray(buf, np.uint8)
+    _call("fem_write_state", ctx, _p(b), b.size)
+
+
+def fem_get_node_perm(ctx, n):
+    out = np.empty(n, np.int32)
+    _call("fem_get_node_perm", ctx, _p(out))
+    return out
+
+
+def fem_time_kernels(ctx, dt, n_steps):
+    t = fem_kernel_times()
+    _call("fem_time_kernels", ctx, float(dt), int(n_steps), C.byref(t))
+    return _as_dict(t)
+
+
+def fem_copy_kernel(ctx, dst_ptr, src_ptr, nbytes, repeats):
+    ms = C.c_double()
+    _call("fem_copy_kernel", ctx, C.c_void_p(dst_ptr), C.c_void_p(src_ptr), int(nbytes), int(repeats), C.byref(ms))
+    return ms.value
+
+
+# ------------------------------------------------------------ convenience
+def make_options(precision=FEM_PREC_FP32_KAHAN, ordering=FEM_ORDER_HILBERT, scatter=FEM_SCATTER_LDS_BLOCKED,
+                 block_elems=0, device=0, allow_unstable=False, lds_bytes=0, threads=0):
+    o = fem_options()
+    o.device, o.precision, o.ordering, o.scatter = device, precision, ordering, scatter
+    o.block_elems, o.allow_unstable, o.lds_bytes, o.threads = block_elems, int(allow_unstable), lds_bytes, threads
+    return o
+
+
+def setup_problem(ctx, prob):
+    """Upload a problem dict (castgen layout) and finalize; returns the prep report."""
+    fem_upload_mesh(ctx, prob["elem_type"], prob["xyz"], prob["conn"], prob["elem_mat"])
+    fem_set_materials(ctx, prob["materials"])
+    if np.size(prob.get("dirichlet_nodes", [])):
+        fem_set_dirichlet(ctx, prob["dirichlet_nodes"], prob["dirichlet_T"])
+    if np.size(prob.get("flux_faces", [])):
+        fem_set_flux_faces(ctx, prob["flux_faces"], prob["flux_q"], prob["flux_h"], prob["flux_Tinf"])
+    if np.size(prob.get("if_h", [])):
+        fem_set_interface(ctx, prob["if_a"], prob["if_b"], prob["if_h"])
+    fem_set_initial_T(ctx, prob["T0"])
+    return fem_finalize(ctx)
+
+
+class Solver:
+    """One casting problem on one GPU: torch allocates the device buffers and
+    the stream, the library borrows them."""
+
+    def __init__(self, prob, device=0, stream=None, **opts):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("castfem.Solver needs a ROCm GPU")
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        self.n_nodes = prob["xyz"].shape[0]
+        self.n_elems = prob["conn"].shape[0]
+        self.ctx = fem_create(make_options(device=device, **opts))
+        self.report = setup_problem(self.ctx, prob)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        fem_set_stream(self.ctx, self.stream.cuda_stream)
+        self.buffers = []
+        ptrs = []
+        for name, nbytes, align in fem_query_buffers(self.ctx):
+            if nbytes:
+                t = torch.empty(nbytes + align, dtype=torch.uint8, device=self.device)
+                p = t.data_ptr()
+                off = (-p) % align
+                self.buffers.append(t)
+                ptrs.append(p + off)
+            else:
+                ptrs.append(0)
+        fem_bind_buffers(self.ctx, ptrs)
+        self.report = fem_get_report(self.ctx)
+
+    def stable_dt(self):
+        return fem_stable_dt(self.ctx)
+
+    def step(self, dt, n):
+        fem_step(self.ctx, dt, n)
+
+    def T(self):
+        return fem_read_T(self.ctx, self.n_nodes)
+
+    def fs(self):
+        return fem_read_fs(self.ctx, self.n_nodes)
+
+    def H(self):
+        return fem_read_H(self.ctx, self.n_nodes)
+
+    def energy(self):
+        return fem_energy(self.ctx)
+
+    def node_perm(self):
+        return fem_get_node_perm(self.ctx, self.n_nodes)
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def close(self):
+        if self.ctx is not None:
+            self.synchronize()
+            fem_destroy(self.ctx)
+            self.ctx = None
+            self.buffers = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,939 @@
+// C interface of the casting step (include/castfem.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/castfem.h"
+#include "kernels.hpp"
+#include "prep.hpp"
+
+using namespace castfem;
+
+namespace {
+
+thread_local std::string g_err;
+
+int set_err(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHECK(x)                                                                                   \
+    do {                                                                                              \
+        hipError_t e_ = (x);                                                                          \
+        if (e_ != hipSuccess) throw PrepError{FEM_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+
+enum Stage { ST_NEW = 0, ST_FINAL = 1, ST_BOUND = 2 };
+
+enum Buf {
+    B_NODE_X, B_T, B_H, B_INV_M, B_FS, B_MATS, B_CONN, B_R, B_LCONN, B_BLOCKS, B_SH_LIST, B_PARTIALS,
+    B_COMB_PTR, B_COMB_IDX, B_ROBIN, B_LINK_PTR, B_LINK_NODE, B_LINK_W, B_DIAG, B_CUMQ, B_COUNT
+};
+const char *BUF_NAMES[B_COUNT] = {"node_x", "T", "H", "inv_m", "fs", "mats", "conn", "r", "lconn", "blocks",
+                                  "sh_list", "partials", "comb_ptr", "comb_idx", "robin", "link_ptr",
+                                  "link_node", "link_w", "diag", "cumQ"};
+constexpr int64_t ALIGN = 256;
+constexpr int GRAPH_STEPS = 16;  // steps per captured graph (even: both parities)
+constexpr size_t MAX_BLOCK_LDS = 160 * 1024 - 2048;  // gfx950 LDS per workgroup, less static use
+
+struct Candidate {
+    PrepOptions o;
+    int threads = 256;
+    Layout L;
+    double ms = -1;
+};
+
+MatDev make_mat(const fem_material &m, double dt) {
+    MatDev d{};
+    d.c = m.c;
+    d.inv_c = 1.0 / m.c;
+    d.Ts = m.T_sol;
+    d.Tl = m.T_liq;
+    d.L = m.L;
+    d.Hs = m.c * m.T_sol;
+    d.Hl = m.c * m.T_liq + m.L;
+    d.latent = m.L > 0 ? 1 : 0;
+    d.slope = (m.L > 0 && m.T_liq > m.T_sol) ? (m.T_liq - m.T_sol) / (m.c * (m.T_liq - m.T_sol) + m.L) : 0.0;
+    d.inv_dH = m.L > 0 ? 1.0 / (d.Hl - d.Hs) : 0.0;
+    d.dt = dt;
+    d.k = m.k;
+    d.kf = (float)m.k;
+    d.dtf = (float)dt;
+    return d;
+}
+
+// enthalpy relation on the host (initial state and read-back of fraction solid)
+double h_of_t(const fem_material &m, double T) {
+    double g = 0.0;
+    if (m.L > 0 && T > m.T_sol) g = T >= m.T_liq ? 1.0 : (T - m.T_sol) / (m.T_liq - m.T_sol);
+    return m.c * T + m.L * g;
+}
+
+void t_of_h(const MatDev &M, double H, double &T, double &fs) {
+    if (!M.latent || H <= M.Hs) {
+        T = H * M.inv_c;
+        fs = 1.0;
+    } else if (H >= M.Hl) {
+        T = (H - M.L) * M.inv_c;
+        fs = 0.0;
+    } else {
+        T = M.Ts + (H - M.Hs) * M.slope;
+        fs = 1.0 - (H - M.Hs) * M.inv_dH;
+    }
+}
+
+}  // namespace
+
+struct fem_ctx {
+    fem_options opt{};
+    Problem prob;
+    bool have_mesh = false;
+    Stage stage = ST_NEW;
+    Base base;
+    std::vector<Candidate> cands;
+    int chosen = 0;
+    hipStream_t stream = nullptr;
+    int64_t sizes[B_COUNT] = {};
+    void *ptr[B_COUNT] = {};
+    Dev dev;
+    std::vector<MatDev> mats_host;
+    double dt_cur = -1.0;
+    int parity = 0;
+    int64_t steps = 0;
+    double time = 0.0;
+    double E0 = 0, Eref = 0, lat0 = 0, tmin0 = 0, tmax0 = 0;
+    int64_t nliq0 = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    double setup_seconds = 0;
+    int64_t diag_slots = 0;
+
+    Layout &L() { return cands[chosen].L; }
+    const Layout &L() const { return cands[chosen].L; }
+    size_t rsize() const { return opt.precision == FEM_PREC_FP64 ? 8 : 4; }
+};
+
+namespace {
+
+int64_t rup(int64_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+// byte sizes of every buffer for one layout
+void layout_sizes(const fem_ctx *c, const Layout &L, int64_t *sz) {
+    const int64_t R = (int64_t)c->rsize();
+    const int64_t N = L.N, E = L.E;
+    const bool blocked = c->opt.scatter == FEM_SCATTER_LDS_BLOCKED;
+    for (int b = 0; b < B_COUNT; ++b) sz[b] = 0;
+    sz[B_NODE_X] = N * 4 * R;
+    sz[B_T] = 2 * N * R;
+    sz[B_H] = N * 8;
+    sz[B_INV_M] = N * R;
+    sz[B_FS] = N * R;
+    sz[B_MATS] = (int64_t)c->prob.mats.size() * (int64_t)sizeof(MatDev);
+    if (!blocked) {
+        sz[B_CONN] = E * L.nen * 4;
+        sz[B_R] = N * R;
+    } else {
+        const int64_t np = (int64_t)L.sh_list.size();
+        sz[B_LCONN] = E * L.nen * 2;
+        sz[B_BLOCKS] = (int64_t)L.blocks.size() * (int64_t)sizeof(BlockInfo);
+        sz[B_SH_LIST] = np * 4;
+        sz[B_PARTIALS] = np * R;
+        sz[B_COMB_PTR] = (N - L.n_private + 1) * 4;
+        sz[B_COMB_IDX] = np * 4;
+    }
+    sz[B_ROBIN] = (int64_t)L.robin_a.size() * 2 * R;
+    sz[B_LINK_PTR] = (L.n_bc_slots + 1) * 4;
+    sz[B_LINK_NODE] = (int64_t)L.link_node.size() * 4;
+    sz[B_LINK_W] = (int64_t)L.link_w.size() * R;
+    const int64_t slots = (blocked ? (int64_t)L.blocks.size() : 0) + node_grid(blocked ? N - L.n_private : N);
+    sz[B_DIAG] = slots * NDIAG * 8;
+    sz[B_CUMQ] = slots * 8;
+}
+
+template <class T>
+void h2d(fem_ctx *c, int b, const T *src, int64_t bytes) {
+    if (bytes == 0) return;
+    if (bytes > c->sizes[b]) throw PrepError{FEM_E_INVALID_ARG, std::string("internal: buffer too small: ") + BUF_NAMES[b]};
+    HIPCHECK(hipMemcpyAsync(c->ptr[b], src, bytes, hipMemcpyHostToDevice, c->stream));
+}
+
+template <class R>
+void upload_layout_t(fem_ctx *c, const Layout &L) {
+    using V4 = typename std::conditional<sizeof(R) == 4, float4, double4>::type;
+    const int64_t N = L.N;
+    std::vector<V4> nx(N);
+    std::vector<R> im(N), T2(2 * N), fs(N);
+    std::vector<uint8_t> H(N * 8);
+    c->E0 = c->Eref = c->lat0 = 0;
+    c->tmin0 = INFINITY;
+    c->tmax0 = -INFINITY;
+    c->nliq0 = 0;
+    for (int64_t n = 0; n < N; ++n) {
+        const uint32_t f = L.nflag[n];
+        V4 v;
+        v.x = (R)L.xyz[3 * n];
+        v.y = (R)L.xyz[3 * n + 1];
+        v.z = (R)L.xyz[3 * n + 2];
+        if (sizeof(R) == 4) {
+            uint32_t u = f;
+            std::memcpy(&v.w, &u, 4);
+        } else {
+            uint64_t u = f;
+            std::memcpy(&v.w, &u, 8);
+        }
+        nx[n] = v;
+        im[n] = (R)(1.0 / L.m[n]);
+        const fem_material &mat = c->prob.mats[f & NODE_MAT_MASK];
+        const MatDev &M = c->mats_host[f & NODE_MAT_MASK];
+        const double h0 = h_of_t(mat, L.T_init[n]);
+        double hd;
+        if (sizeof(R) == 4) {
+            float hi = (float)h0;
+            float lo = (float)(h0 - (double)hi);
+            std::memcpy(&H[8 * n], &hi, 4);
+            std::memcpy(&H[8 * n + 4], &lo, 4);
+            hd = (double)hi + (double)lo;
+        } else {
+            std::memcpy(&H[8 * n], &h0, 8);
+            hd = h0;
+        }
+        double T, f_s;
+        t_of_h(M, hd, T, f_s);
+        if (f & NODE_FIXED) T = L.T_init[n];
+        T2[n] = T2[N + n] = (R)T;
+        fs[n] = (R)f_s;
+        const double m = 1.0 / (double)im[n];
+        c->E0 += m * hd;
+        c->Eref += m * h_of_t(mat, 25.0);
+        c->lat0 += m * mat.L * (1.0 - f_s);
+        c->tmin0 = std::min(c->tmin0, (double)T2[n]);
+        c->tmax0 = std::max(c->tmax0, (double)T2[n]);
+        if (mat.L > 0 && f_s < 1.0) c->nliq0++;
+    }
+    h2d(c, B_NODE_X, nx.data(), N * (int64_t)sizeof(V4));
+    h2d(c, B_INV_M, im.data(), N * (int64_t)sizeof(R));
+    h2d(c, B_H, H.data(), N * 8);
+    h2d(c, B_T, T2.data(), 2 * N * (int64_t)sizeof(R));
+    h2d(c, B_FS, fs.data(), N * (int64_t)sizeof(R));
+    std::vector<R> rob(L.robin_a.size() * 2), lw(L.link_w.size());
+    for (size_t s = 0; s < L.robin_a.size(); ++s) {
+        rob[2 * s] = (R)L.robin_a[s];
+        rob[2 * s + 1] = (R)L.robin_b[s];
+    }
+    for (size_t s = 0; s < L.link_w.size(); ++s) lw[s] = (R)L.link_w[s];
+    h2d(c, B_ROBIN, rob.data(), (int64_t)rob.size() * (int64_t)sizeof(R));
+    h2d(c, B_LINK_PTR, L.link_ptr.data(), (int64_t)L.link_ptr.size() * 4);
+    h2d(c, B_LINK_NODE, L.link_node.data(), (int64_t)L.link_node.size() * 4);
+    h2d(c, B_LINK_W, lw.data(), (int64_t)lw.size() * (int64_t)sizeof(R));
+    if (c->opt.scatter == FEM_SCATTER_LDS_BLOCKED) {
+        h2d(c, B_LCONN, L.lconn.data(), (int64_t)L.lconn.size() * 2);
+        h2d(c, B_BLOCKS, L.blocks.data(), (int64_t)L.blocks.size() * (int64_t)sizeof(BlockInfo));
+        h2d(c, B_SH_LIST, L.sh_list.data(), (int64_t)L.sh_list.size() * 4);
+        h2d(c, B_COMB_PTR, L.comb_ptr.data(), (int64_t)L.comb_ptr.size() * 4);
+        h2d(c, B_COMB_IDX, L.comb_idx.data(), (int64_t)L.comb_idx.size() * 4);
+    } else {
+        h2d(c, B_CONN, L.conn.data(), (int64_t)L.conn.size() * 4);
+        HIPCHECK(hipMemsetAsync(c->ptr[B_R], 0, N * sizeof(R), c->stream));
+    }
+    int64_t sz[B_COUNT];
+    layout_sizes(c, L, sz);
+    HIPCHECK(hipMemsetAsync(c->ptr[B_DIAG], 0, sz[B_DIAG], c->stream));
+    HIPCHECK(hipMemsetAsync(c->ptr[B_CUMQ], 0, sz[B_CUMQ], c->stream));
+    // the host vectors above must outlive the copies
+    HIPCHECK(hipStreamSynchronize(c->stream));
+}
+
+void fill_dev(fem_ctx *c, const Candidate &cd) {
+    const Layout &L = cd.L;
+    Dev d;
+    d.prec = c->opt.precision;
+    d.nen = L.nen;
+    d.scatter = c->opt.scatter;
+    d.N = L.N;
+    d.E = L.E;
+    d.node_x = c->ptr[B_NODE_X];
+    d.T = c->ptr[B_T];
+    d.H = c->ptr[B_H];
+    d.inv_m = c->ptr[B_INV_M];
+    d.fs = c->ptr[B_FS];
+    d.mats = (const MatDev *)c->ptr[B_MATS];
+    d.conn = (const int32_t *)c->ptr[B_CONN];
+    d.r = c->ptr[B_R];
+    d.lconn = (const uint16_t *)c->ptr[B_LCONN];
+    d.blocks = (const BlockInfo *)c->ptr[B_BLOCKS];
+    d.sh_list = (const int32_t *)c->ptr[B_SH_LIST];
+    d.partials = c->ptr[B_PARTIALS];
+    d.comb_ptr = (const int32_t *)c->ptr[B_COMB_PTR];
+    d.comb_idx = (const int32_t *)c->ptr[B_COMB_IDX];
+    d.robin = L.robin_a.empty() ? nullptr : c->ptr[B_ROBIN];
+    d.link_ptr = (const int32_t *)c->ptr[B_LINK_PTR];
+    d.link_node = (const int32_t *)c->ptr[B_LINK_NODE];
+    d.link_w = c->ptr[B_LINK_W];
+    d.diag = (double *)c->ptr[B_DIAG];
+    d.cumQ = (double *)c->ptr[B_CUMQ];
+    d.n_private = L.n_private;
+    d.n_blocks = (int64_t)L.blocks.size();
+    d.n_bc_slots = L.n_bc_slots;
+    d.bc_first = L.bc_first;
+    d.threads = cd.threads;
+    d.lds_bytes = (size_t)L.max_local * lds_per_node(d.prec);
+    d.n_colors = L.color_ptr.empty() ? 0 : (int)L.color_ptr.size() - 1;
+    d.color_ptr_host = L.color_ptr.empty() ? nullptr : L.color_ptr.data();
+    const bool blocked = d.scatter == FEM_SCATTER_LDS_BLOCKED;
+    d.diag_k1 = blocked ? d.n_blocks : 0;
+    d.diag_k2 = node_grid(blocked ? d.N - d.n_private : d.N);
+    c->diag_slots = d.diag_k1 + d.diag_k2;
+    c->dev = d;
+}
+
+void reset_graph(fem_ctx *c) {
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->gexec = nullptr;
+    c->graph = nullptr;
+}
+
+void set_dt(fem_ctx *c, double dt) {
+    if (dt == c->dt_cur) return;
+    for (size_t q = 0; q < c->prob.mats.size(); ++q) c->mats_host[q] = make_mat(c->prob.mats[q], dt);
+    h2d(c, B_MATS, c->mats_host.data(), (int64_t)(c->mats_host.size() * sizeof(MatDev)));
+    HIPCHECK(hipStreamSynchronize(c->stream));
+    c->dt_cur = dt;
+}
+
+void eager_steps(fem_ctx *c, int64_t n) {
+    for (int64_t s = 0; s < n; ++s) {
+        HIPCHECK(enqueue_step(c->dev, c->parity, c->stream, nullptr));
+        c->parity ^= 1;
+    }
+}
+
+void run_steps(fem_ctx *c, int64_t n) {
+    if (c->stream == nullptr || n < GRAPH_STEPS) {
+        eager_steps(c, n);
+        return;
+    }
+    if (c->parity == 1) {
+        eager_steps(c, 1);
+        --n;
+    }
+    if (!c->gexec) {
+        HIPCHECK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        hipError_t err = hipSuccess;
+        for (int s = 0; s < GRAPH_STEPS && err == hipSuccess; ++s) err = enqueue_step(c->dev, s & 1, c->stream, nullptr);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+        HIPCHECK(err);
+        HIPCHECK(e2);
+        c->graph = g;
+        HIPCHECK(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+    }
+    for (int64_t r = 0; r < n / GRAPH_STEPS; ++r) HIPCHECK(hipGraphLaunch(c->gexec, c->stream));
+    eager_steps(c, n % GRAPH_STEPS);
+}
+
+void check_bound(fem_ctx *c, int fn_stage) {
+    if (c->stage < fn_stage) throw PrepError{FEM_E_STATE, "call out of order: the context is not bound yet"};
+}
+
+template <class F>
+int guarded(F &&f) {
+    try {
+        f();
+        g_err.clear();
+        return FEM_OK;
+    } catch (const PrepError &e) {
+        return set_err(e.code, e.msg);
+    } catch (const std::bad_alloc &) {
+        return set_err(FEM_E_INVALID_ARG, "host allocation failed");
+    } catch (const std::exception &e) {
+        return set_err(FEM_E_INVALID_ARG, e.what());
+    } catch (...) {
+        return set_err(FEM_E_INVALID_ARG, "unknown error");
+    }
+}
+
+void fill_report(const fem_ctx *c, fem_prep_report *rep) {
+    std::memset(rep, 0, sizeof(*rep));
+    const Layout &L = c->L();
+    rep->n_nodes = L.N;
+    rep->n_elems = L.E;
+    rep->n_blocks = (int64_t)L.blocks.size();
+    rep->n_shared = c->opt.scatter == FEM_SCATTER_LDS_BLOCKED ? L.N - L.n_private : 0;
+    rep->n_partials = (int64_t)L.sh_list.size();
+    rep->max_local_nodes = L.max_local;
+    rep->n_colors = L.color_ptr.empty() ? 0 : (int64_t)L.color_ptr.size() - 1;
+    rep->bandwidth_before = L.bw_before;
+    rep->bandwidth_after = L.bw_after;
+    rep->block_elems = L.block_elems;
+    rep->shared_fraction = L.N ? (double)rep->n_shared / (double)L.N : 0.0;
+    rep->dt_bound = c->base.dt_bound;
+    rep->setup_seconds = c->setup_seconds;
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" {
+
+const char *fem_last_error(void) { return g_err.c_str(); }
+
+int fem_create(fem_ctx **out, const fem_options *opt) {
+    if (!out) return set_err(FEM_E_INVALID_ARG, "out is null");
+    return guarded([&] {
+        fem_options o{};
+        o.device = 0;
+        o.precision = FEM_PREC_FP32_KAHAN;
+        o.ordering = FEM_ORDER_HILBERT;
+        o.scatter = FEM_SCATTER_LDS_BLOCKED;
+        if (opt) o = *opt;
+        if (o.precision != FEM_PREC_FP64 && o.precision != FEM_PREC_FP32_KAHAN)
+            throw PrepError{FEM_E_INVALID_ARG, "unknown precision"};
+        if (o.ordering < FEM_ORDER_NONE || o.ordering > FEM_ORDER_HILBERT) throw PrepError{FEM_E_INVALID_ARG, "unknown ordering"};
+        if (o.scatter < FEM_SCATTER_GLOBAL_ATOMIC || o.scatter > FEM_SCATTER_COLORED)
+            throw PrepError{FEM_E_INVALID_ARG, "unknown scatter"};
+        if (o.block_elems < 0 || o.lds_bytes < 0 || o.threads < 0) throw PrepError{FEM_E_INVALID_ARG, "negative size option"};
+        if (o.threads && (o.threads % 64 || o.threads > 1024)) throw PrepError{FEM_E_INVALID_ARG, "threads must be a multiple of 64 up to 1024"};
+        for (int r : o.reserved)
+            if (r) throw PrepError{FEM_E_INVALID_ARG, "reserved option fields must be zero"};
+        fem_ctx *c = new fem_ctx();
+        c->opt = o;
+        *out = c;
+    });
+}
+
+int fem_destroy(fem_ctx *ctx) {
+    if (!ctx) return set_err(FEM_E_INVALID_ARG, "ctx is null");
+    reset_graph(ctx);
+    delete ctx;
+    return FEM_OK;
+}
+
+int fem_set_stream(fem_ctx *ctx, void *hip_stream) {
+    if (!ctx) return set_err(FEM_E_INVALID_ARG, "ctx is null");
+    if (ctx->stream != (hipStream_t)hip_stream) reset_graph(ctx);
+    ctx->stream = (hipStream_t)hip_stream;
+    return FEM_OK;
+}
+
+int fem_upload_mesh(fem_ctx *ctx, int32_t elem_type, int64_t n_nodes, const double *xyz, int64_t n_elems,
+                    const int32_t *conn, const int32_t *elem_mat) {
+    if (!ctx) return set_err(FEM_E_INVALID_ARG, "ctx is null");
+    return guarded([&] {
+        if (ctx->stage != ST_NEW) throw PrepError{FEM_E_STATE, "mesh must be uploaded before fem_finalize"};
+        if (elem_type != FEM_TET4 && elem_type != FEM_HEX8) throw PrepError{FEM_E_INVALID_ARG, "elem_type must be 4 or 8"};
+        if (n_nodes <= 0 || n_elems <= 0 || !xyz || !conn || !elem_mat) throw PrepError{FEM_E_INVALID_ARG, "empty mesh or null array"};
+        if (n_nodes >= INT32_MAX || n_elems * elem_type >= INT32_MAX)
+            throw PrepError{FEM_E_UNSUPPORTED, "mesh too large for 32-bit indices"};
+        Problem p = ctx->prob;
+        p.nen = elem_type;
+        p.N = n_nodes;
+        p.E = n_elems;
+        p.xyz.assign(xyz, xyz + 3 * n_nodes);
+        p.conn.assign(conn, conn + n_elems * elem_type);
+        p.emat.assign(elem_mat, elem_mat + n_elems);
+        for (int64_t i = 0; i < 3 * n_nodes; ++i)
+            if (!std::isfinite(p.xyz[i])) throw PrepError{FEM_E_INVALID_ARG, "node coordinates must be finite"};
+        if ((int64_t)p.T0.size() != n_nodes) p.T0.clear();
+        ctx->prob = std::move(p);
+        ctx->have_mesh = true;
+    });
+}
+
+int fem_set_materials(fem_ctx *ctx, int32_t n_mat, const fem_material *m) {
+    if (!ctx) return set_err(FEM_E_INVALID_ARG, "ctx is null");
+    return guarded([&] {
+        if (ctx->stage != ST_NEW) throw PrepError{FEM_E_STATE, "materials must be set before fem_finalize"};
+        if (n_mat <= 0 || n_mat > (int32_t)NODE_MAT_MASK || !m) throw PrepError{FEM_E_INVALID_ARG, "bad material table"};
+        ctx->prob.mats.assign(m, m + n_mat);
+    });
+}
+
+int fem_set_dirichlet(fem_ctx *ctx, int64_t n, const int32_t *node, const double *T_value) {
+    if (!ctx) return set_err(FEM_E_INVALID_ARG, "ctx is null");
+    return guarded([&] {
+        if (ctx->stage != ST_NEW) throw PrepError{FEM_E_STATE, "boundary sets must be given before fem_finalize"};
+        if (n < 0 || (n > 0 && (!node || !T_value))) throw PrepError{FEM_E_INVALID_ARG, "bad fixed-temperature set"};
+        for (int64_t i = 0; i < n; ++i)
+            if (!std::isfinite(T_value[i])) throw PrepError{FEM_E_INVALID_ARG, "fixed temperature not finite"};
+        ctx->prob.dir_nodes.assign(node, node + n);
+        ctx->prob.dir_T.assign(T_value, T_value + n);
+    });
+}
+
+int fem_set_flux_faces(fem_ctx *ctx, int64_t nf, int32_t nodes_per_face, const int32_t *face_nodes, const double *q,
+                       const double *h, const double *T_inf) {
+    if (!ctx) return set_err(FEM_E_INVALID_ARG, "ctx is null");
+    return guarded([&] {
+        if (ctx->stage != ST_NEW) throw PrepError{FEM_E_STATE, "boundary sets must be given before fem_finalize"};
+        if (nf < 0 || (nodes_per_face != 3 && nodes_per_face != 4)) throw PrepError{FEM_E_INVALID_ARG, "bad flux faces"};
+        if (nf > 0 && (!face_nodes || !q || !h || !T_inf)) throw PrepError{FEM_E_INVALID_ARG, "null flux face array"};
+        for (int64_t f = 0; f < nf; ++f)
+            if (!std::isfinite(q[f]) || !std::isfinite(h[f]) || !std::isfinite(T_inf[f]) || h[f] < 0)
+                throw PrepError{FEM_E_INVALID_ARG, "flux face values must be finite, h >= 0"};
+        Problem &p = ctx->prob;
+        p.npf = nodes_per_face;
+        p.flux_faces.assign(face_nodes, face_nodes + nf * nodes_per_face);
+        p.flux_q.assign(q, q + nf);
+        p.flux_h.assign(h, h + nf);
+        p.flux_Tinf.assign(T_inf, T_inf + nf);
+    });
+}
+
+int fem_set_interface(fem_ctx *ctx, int64_t npairs, const int32_t *face_a, const int32_t *face_b, const double *h_i) {
+    if (!ctx) return set_err(FEM_E_INVALID_ARG, "ctx is null");
+    return guarded([&] {
+        if (ctx->stage != ST_NEW) throw PrepError{FEM_E_STATE, "interface must be given before fem_finalize"};
+        if (npairs < 0 || (npairs > 0 && (!face_a || !face_b || !h_i))) throw PrepError{FEM_E_INVALID_ARG, "bad interface"};
+        for (int64_t f = 0; f < npairs; ++f)
+            if (!std::isfinite(h_i[f]) || h_i[f] < 0) throw PrepError{FEM_E_INVALID_ARG, "interface h must be finite, >= 0"};
+        Problem &p = ctx->prob;
+        p.if_a.assign(face_a, face_a + 3 * npairs);
+        p.if_b.assign(face_b, face_b + 3 * npairs);
+        p.if_h.assign(h_i, h_i + npairs);
+    });
+}
+
+int fem_set_initial_T(fem_ctx *ctx, const double *T0) {
+    if (!ctx) return set_err(FEM_E_INVALID_ARG, "ctx is null");
+    return guarded([&] {
+        if (ctx->stage != ST_NEW) throw PrepError{FEM_E_STATE, "initial field must be given before fem_finalize"};
+        if (!ctx->have_mesh) throw PrepError{FEM_E_STATE, "upload the mesh first"};
+        if (!T0) throw PrepError{FEM_E_INVALID_ARG, "T0 is null"};
+        ctx->prob.T0.assign(T0, T0 + ctx->prob.N);
+    });
+}
+
+int fem_finalize(fem_ctx *ctx, fem_prep_report *rep) {
+    if (!ctx) return set_err(FEM_E_INVALID_ARG, "ctx is null");
+    return guarded([&] {
+        if (ctx->stage != ST_NEW) throw PrepError{FEM_E_STATE, "already finalized"};
+        if (!ctx->have_mesh) throw PrepError{FEM_E_STATE, "no mesh uploaded"};
+        auto t0 = std::chrono::steady_clock::now();
+        Base base;
+        prep_base(ctx->prob, base);
+        Ordering ord;
+        prep_order(ctx->prob, base, ctx->opt.ordering, ord);
+        std::vector<Candidate> cands;
+        const size_t per = lds_per_node(ctx->opt.precision);
+        const int thr = ctx->opt.threads ? ctx->opt.threads : 256;
+        if (ctx->opt.scatter == FEM_SCATTER_LDS_BLOCKED && ctx->opt.block_elems == 0 && ctx->opt.lds_bytes == 0) {
+            // autotune over block node sets (the paper's timed search over the block count)
+            for (int64_t nodes : {1024, 1536, 2048, 3072, 4096}) {
+                if ((size_t)nodes * per > MAX_BLOCK_LDS) continue;
+                Candidate c;
+                c.o.ordering = ctx->opt.ordering;
+                c.o.scatter = ctx->opt.scatter;
+                c.o.max_local_nodes = nodes;
+                c.o.block_elems = 1 << 20;
+                c.threads = thr;
+                cands.push_back(std::move(c));
+            }
+        } else {
+            Candidate c;
+            c.o.ordering = ctx->opt.ordering;
+            c.o.scatter = ctx->opt.scatter;
+            const size_t lds = ctx->opt.lds_bytes ? (size_t)ctx->opt.lds_bytes : (size_t)65536;
+            if (lds > MAX_BLOCK_LDS) throw PrepError{FEM_E_INVALID_ARG, "lds_bytes above the gfx950 limit"};
+            c.o.max_local_nodes = std::min<int64_t>(65535, (int64_t)(lds / per));
+            c.o.block_elems = ctx->opt.block_elems ? ctx->opt.block_elems : (1 << 20);
+            c.threads = thr;
+            cands.push_back(std::move(c));
+        }
+        // candidate layouts are independent: build them concurrently
+        std::vector<PrepError> errs(cands.size(), PrepError{FEM_OK, ""});
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int q = 0; q < (int)cands.size(); ++q) {
+            try {
+                prep_layout(ctx->prob, base, cands[q].o, ord, cands[q].L);
+            } catch (const PrepError &e) {
+                errs[q] = e;
+            } catch (const std::bad_alloc &) {
+                errs[q] = PrepError{FEM_E_INVALID_ARG, "host allocation failed"};
+            }
+        }
+        for (const PrepError &e : errs)
+            if (e.code != FEM_OK) throw e;
+        ctx->base = std::move(base);
+        ctx->cands = std::move(cands);
+        ctx->chosen = 0;
+        for (int b = 0; b < B_COUNT; ++b) ctx->sizes[b] = 0;
+        for (const Candidate &c : ctx->cands) {
+            int64_t sz[B_COUNT];
+            layout_sizes(ctx, c.L, sz);
+            for (int b = 0; b < B_COUNT; ++b) ctx->sizes[b] = std::max(ctx->sizes[b], sz[b]);
+        }
+        ctx->mats_host.resize(ctx->prob.mats.size());
+        for (size_t q = 0; q < ctx->prob.mats.size(); ++q) ctx->mats_host[q] = make_mat(ctx->prob.mats[q], 0.0);
+        ctx->setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        ctx->stage = ST_FINAL;
+        if (rep) fill_report(ctx, rep);
+    });
+}
+
+int fem_get_report(const fem_ctx *ctx, fem_prep_report *rep) {
+    if (!ctx || !rep) return set_err(FEM_E_INVALID_ARG, "null argument");
+    if (ctx->stage < ST_FINAL) return set_err(FEM_E_STATE, "not finalized");
+    fill_report(ctx, rep);
+    return FEM_OK;
+}
+
+int fem_query_buffers(const fem_ctx *ctx, fem_buffer_desc *d, int32_t *n) {
+    if (!ctx || !n) return set_err(FEM_E_INVALID_ARG, "null argument");
+    if (ctx->stage < ST_FINAL) return set_err(FEM_E_STATE, "call fem_finalize first");
+    if (!d) {
+        *n = B_COUNT;
+        return FEM_OK;
+    }
+    if (*n < B_COUNT) return set_err(FEM_E_INVALID_ARG, "descriptor array too short");
+    for (int b = 0; b < B_COUNT; ++b) {
+        std::memset(&d[b], 0, sizeof(fem_buffer_desc));
+        std::strncpy(d[b].name, BUF_NAMES[b], sizeof(d[b].name) - 1);
+        d[b].bytes = ctx->sizes[b] ? rup(ctx->sizes[b]) : 0;
+        d[b].alignment = ALIGN;
+    }
+    *n = B_COUNT;
+    return FEM_OK;
+}
+
+int fem_bind_buffers(fem_ctx *ctx, void *const *dev_ptrs, int32_t n) {
+    if (!ctx) return set_err(FEM_E_INVALID_ARG, "ctx is null");
+    return guarded([&] {
+        if (ctx->stage != ST_FINAL) throw PrepError{FEM_E_STATE, "call fem_finalize (once) before binding"};
+        if (n != B_COUNT || !dev_ptrs) throw PrepError{FEM_E_INVALID_ARG, "wrong number of device buffers"};
+        for (int b = 0; b < B_COUNT; ++b) {
+            if (ctx->sizes[b] > 0 && !dev_ptrs[b]) throw PrepError{FEM_E_INVALID_ARG, std::string("null buffer ") + BUF_NAMES[b]};
+            if ((uintptr_t)dev_ptrs[b] % ALIGN) throw PrepError{FEM_E_INVALID_ARG, std::string("misaligned buffer ") + BUF_NAMES[b]};
+        }
+        HIPCHECK(hipSetDevice(ctx->opt.device));
+        for (int b = 0; b < B_COUNT; ++b) ctx->ptr[b] = ctx->sizes[b] ? dev_ptrs[b] : nullptr;
+        reset_graph(ctx);
+        if (ctx->opt.scatter == FEM_SCATTER_LDS_BLOCKED) {
+            hipDeviceProp_t prop;
+            HIPCHECK(hipGetDeviceProperties(&prop, ctx->opt.device));
+            size_t mx = 0;
+            for (const Candidate &c : ctx->cands) mx = std::max(mx, (size_t)c.L.max_local * lds_per_node(ctx->opt.precision));
+            const size_t cap = prop.maxSharedMemoryPerMultiProcessor ? prop.maxSharedMemoryPerMultiProcessor : prop.sharedMemPerBlock;
+            if (mx + 1024 > cap) throw PrepError{FEM_E_UNSUPPORTED, "block LDS footprint above the device limit"};
+            HIPCHECK(set_block_lds_limit(ctx->opt.precision, ctx->prob.nen, mx));
+        }
+        ctx->dt_cur = -1.0;
+        if (ctx->cands.size() > 1) {
+            // timed trial steps per candidate layout; keep the fastest
+            const double dt = 0.5 * ctx->base.dt_bound;
+            hipEvent_t e0, e1;
+            HIPCHECK(hipEventCreate(&e0));
+            HIPCHECK(hipEventCreate(&e1));
+            for (size_t q = 0; q < ctx->cands.size(); ++q) {
+                ctx->chosen = (int)q;
+                if (ctx->opt.precision == FEM_PREC_FP64) upload_layout_t<double>(ctx, ctx->cands[q].L);
+                else upload_layout_t<float>(ctx, ctx->cands[q].L);
+                fill_dev(ctx, ctx->cands[q]);
+                set_dt(ctx, dt);
+                ctx->parity = 0;
+                eager_steps(ctx, 4);
+                HIPCHECK(hipEventRecord(e0, ctx->stream));
+                eager_steps(ctx, 20);
+                HIPCHECK(hipEventRecord(e1, ctx->stream));
+                HIPCHECK(hipEventSynchronize(e1));
+                float ms = 0;
+                HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+                ctx->cands[q].ms = ms / 20.0;
+            }
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            int best = 0;
+            for (size_t q = 1; q < ctx->cands.size(); ++q)
+                if (ctx->cands[q].ms < ctx->cands[best].ms) best = (int)q;
+            ctx->chosen = best;
+        }
+        if (ctx->opt.precision == FEM_PREC_FP64) upload_layout_t<double>(ctx, ctx->L());
+        else upload_layout_t<float>(ctx, ctx->L());
+        fill_dev(ctx, ctx->cands[ctx->chosen]);
+        ctx->dt_cur = -1.0;
+        ctx->parity = 0;
+        ctx->steps = 0;
+        ctx->time = 0.0;
+        // drop the layouts that lost the trial
+        Candidate keep = std::move(ctx->cands[ctx->chosen]);
+        ctx->cands.clear();
+        ctx->cands.push_back(std::move(keep));
+        ctx->chosen = 0;
+        fill_dev(ctx, ctx->cands[0]);
+        ctx->stage = ST_BOUND;
+    });
+}
+
+int fem_stable_dt(const fem_ctx *ctx, double *dt) {
+    if (!ctx || !dt) return set_err(FEM_E_INVALID_ARG, "null argument");
+    if (ctx->stage < ST_FINAL) return set_err(FEM_E_STATE, "call fem_finalize first");
+    *dt = ctx->base.dt_bound;
+    return FEM_OK;
+}
+
+int fem_step(fem_ctx *ctx, double dt, int64_t n_steps) {
+    if (!ctx) return set_err(FEM_E_INVALID_ARG, "ctx is null");
+    return guarded([&] {
+        check_bound(ctx, ST_BOUND);
+        if (!(dt > 0) || !std::isfinite(dt) || n_steps < 0) throw PrepError{FEM_E_INVALID_ARG, "dt must be > 0 and n_steps >= 0"};
+        if (dt > ctx->base.dt_bound && !ctx->opt.allow_unstable)
+            throw PrepError{FEM_E_UNSTABLE, "dt " + std::to_string(dt) + " above the stability bound " + std::to_string(ctx->base.dt_bound)};
+        set_dt(ctx, dt);
+        run_steps(ctx, n_steps);
+        ctx->steps += n_steps;
+        ctx->time += dt * (double)n_steps;
+    });
+}
+
+}  // extern "C"
+
+namespace {
+
+template <class R>
+void read_node_array(fem_ctx *c, const void *dev, double *out) {
+    const Layout &L = c->L();
+    std::vector<R> h(L.N);
+    HIPCHECK(hipMemcpyAsync(h.data(), dev, L.N * sizeof(R), hipMemcpyDeviceToHost, c->stream));
+    HIPCHECK(hipStreamSynchronize(c->stream));
+    for (int64_t i = 0; i < L.N; ++i) out[i] = (double)h[L.perm[i]];
+}
+
+const void *T_dev(fem_ctx *c) { return (const char *)c->ptr[B_T] + (size_t)c->parity * c->L().N * c->rsize(); }
+
+}  // namespace
+
+extern "C" {
+
+int fem_read_T(fem_ctx *ctx, double *T_host) {
+    if (!ctx || !T_host) return set_err(FEM_E_INVALID_ARG, "null argument");
+    return guarded([&] {
+        check_bound(ctx, ST_BOUND);
+        if (ctx->opt.precision == FEM_PREC_FP64) read_node_array<double>(ctx, T_dev(ctx), T_host);
+        else read_node_array<float>(ctx, T_dev(ctx), T_host);
+    });
+}
+
+int fem_read_fs(fem_ctx *ctx, double *fs_host) {
+    if (!ctx || !fs_host) return set_err(FEM_E_INVALID_ARG, "null argument");
+    return guarded([&] {
+        check_bound(ctx, ST_BOUND);
+        if (ctx->opt.precision == FEM_PREC_FP64) read_node_array<double>(ctx, ctx->ptr[B_FS], fs_host);
+        else read_node_array<float>(ctx, ctx->ptr[B_FS], fs_host);
+    });
+}
+
+int fem_read_H(fem_ctx *ctx, double *H_host) {
+    if (!ctx || !H_host) return set_err(FEM_E_INVALID_ARG, "null argument");
+    return guarded([&] {
+        check_bound(ctx, ST_BOUND);
+        const Layout &L = ctx->L();
+        std::vector<uint8_t> h(L.N * 8);
+        HIPCHECK(hipMemcpyAsync(h.data(), ctx->ptr[B_H], L.N * 8, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHECK(hipStreamSynchronize(ctx->stream));
+        for (int64_t i = 0; i < L.N; ++i) {
+            const int64_t n = L.perm[i];
+            if (ctx->opt.precision == FEM_PREC_FP64) {
+                std::memcpy(&H_host[i], &h[8 * n], 8);
+            } else {
+                float hi, lo;
+                std::memcpy(&hi, &h[8 * n], 4);
+                std::memcpy(&lo, &h[8 * n + 4], 4);
+                H_host[i] = (double)hi + (double)lo;
+            }
+        }
+    });
+}
+
+int fem_energy(fem_ctx *ctx, fem_energy_report *rep) {
+    if (!ctx || !rep) return set_err(FEM_E_INVALID_ARG, "null argument");
+    return guarded([&] {
+        check_bound(ctx, ST_BOUND);
+        std::memset(rep, 0, sizeof(*rep));
+        rep->E0 = ctx->E0;
+        rep->steps = ctx->steps;
+        rep->time = ctx->time;
+        const int64_t S = ctx->diag_slots;
+        std::vector<double> dg(S * NDIAG), cq(S);
+        HIPCHECK(hipMemcpyAsync(cq.data(), ctx->ptr[B_CUMQ], S * 8, hipMemcpyDeviceToHost, ctx->stream));
+        if (ctx->steps > 0) HIPCHECK(hipMemcpyAsync(dg.data(), ctx->ptr[B_DIAG], S * NDIAG * 8, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHECK(hipStreamSynchronize(ctx->stream));
+        HIPCHECK(hipGetLastError());
+        double qc = 0;
+        for (int64_t s = 0; s < S; ++s) qc += cq[s];
+        rep->Q_cum = qc;
+        if (ctx->steps == 0) {
+            rep->E = ctx->E0;
+            rep->latent = ctx->lat0;
+            rep->T_min = ctx->tmin0;
+            rep->T_max = ctx->tmax0;
+            rep->n_liquid = ctx->nliq0;
+        } else {
+            double E = 0, lat = 0, nl = 0, nf = 0, tmin = INFINITY, tmax = -INFINITY;
+            for (int64_t s = 0; s < S; ++s) {
+                const double *v = &dg[s * NDIAG];
+                E += v[DG_E];
+                lat += v[DG_LAT];
+                nl += v[DG_NLIQ];
+                nf += v[DG_NONFIN];
+                tmin = std::min(tmin, v[DG_TMIN]);
+                tmax = std::max(tmax, v[DG_TMAX]);
+            }
+            rep->E = E;
+            rep->latent = lat;
+            rep->T_min = tmin;
+            rep->T_max = tmax;
+            rep->n_liquid = (int64_t)nl;
+            rep->nonfinite = (int64_t)nf;
+        }
+        rep->residual = std::fabs(rep->E - ctx->E0 - rep->Q_cum) / std::fabs(ctx->E0 - ctx->Eref);
+        if (rep->nonfinite > 0 || !std::isfinite(rep->E))
+            throw PrepError{FEM_E_NONFINITE, "the state holds non-finite enthalpy at " + std::to_string(rep->nonfinite) + " nodes"};
+    });
+}
+
+// checkpoint layout: header, H, T (both buffers), fs, cumQ, diag
+struct CkptHeader {
+    uint64_t magic, N, prec, slots;
+    int64_t parity, steps;
+    double time, E0, Eref, lat0;
+};
+constexpr uint64_t CKPT_MAGIC = 0x31504B434D454643ull;
+
+int fem_read_state(fem_ctx *ctx, void *buf, int64_t *bytes) {
+    if (!ctx || !bytes) return set_err(FEM_E_INVALID_ARG, "null argument");
+    return guarded([&] {
+        check_bound(ctx, ST_BOUND);
+        const int64_t N = ctx->L().N, R = (int64_t)ctx->rsize(), S = ctx->diag_slots;
+        const int64_t need = (int64_t)sizeof(CkptHeader) + N * 8 + 2 * N * R + N * R + S * 8 + S * NDIAG * 8;
+        if (!buf) {
+            *bytes = need;
+            return;
+        }
+        if (*bytes < need) throw PrepError{FEM_E_INVALID_ARG, "checkpoint buffer too small"};
+        CkptHeader h{CKPT_MAGIC, (uint64_t)N, (uint64_t)ctx->opt.precision, (uint64_t)S, ctx->parity, ctx->steps,
+                     ctx->time, ctx->E0, ctx->Eref, ctx->lat0};
+        char *p = (char *)buf;
+        std::memcpy(p, &h, sizeof h);
+        p += sizeof h;
+        HIPCHECK(hipMemcpyAsync(p, ctx->ptr[B_H], N * 8, hipMemcpyDeviceToHost, ctx->stream));
+        p += N * 8;
+        HIPCHECK(hipMemcpyAsync(p, ctx->ptr[B_T], 2 * N * R, hipMemcpyDeviceToHost, ctx->stream));
+        p += 2 * N * R;
+        HIPCHECK(hipMemcpyAsync(p, ctx->ptr[B_FS], N * R, hipMemcpyDeviceToHost, ctx->stream));
+        p += N * R;
+        HIPCHECK(hipMemcpyAsync(p, ctx->ptr[B_CUMQ], S * 8, hipMemcpyDeviceToHost, ctx->stream));
+        p += S * 8;
+        HIPCHECK(hipMemcpyAsync(p, ctx->ptr[B_DIAG], S * NDIAG * 8, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHECK(hipStreamSynchronize(ctx->stream));
+        *bytes = need;
+    });
+}
+
+int fem_write_state(fem_ctx *ctx, const void *buf, int64_t bytes) {
+    if (!ctx || !buf) return set_err(FEM_E_INVALID_ARG, "null argument");
+    return guarded([&] {
+        check_bound(ctx, ST_BOUND);
+        const int64_t N = ctx->L().N, R = (int64_t)ctx->rsize(), S = ctx->diag_slots;
+        const int64_t need = (int64_t)sizeof(CkptHeader) + N * 8 + 2 * N * R + N * R + S * 8 + S * NDIAG * 8;
+        if (bytes < need) throw PrepError{FEM_E_INVALID_ARG, "checkpoint too small"};
+        CkptHeader h;
+        std::memcpy(&h, buf, sizeof h);
+        if (h.magic != CKPT_MAGIC || h.N != (uint64_t)N || h.prec != (uint64_t)ctx->opt.precision || h.slots != (uint64_t)S)
+            throw PrepError{FEM_E_INVALID_ARG, "checkpoint does not match this context"};
+        const char *p = (const char *)buf + sizeof h;
+        HIPCHECK(hipMemcpyAsync(ctx->ptr[B_H], p, N * 8, hipMemcpyHostToDevice, ctx->stream));
+        p += N * 8;
+        HIPCHECK(hipMemcpyAsync(ctx->ptr[B_T], p, 2 * N * R, hipMemcpyHostToDevice, ctx->stream));
+        p += 2 * N * R;
+        HIPCHECK(hipMemcpyAsync(ctx->ptr[B_FS], p, N * R, hipMemcpyHostToDevice, ctx->stream));
+        p += N * R;
+        HIPCHECK(hipMemcpyAsync(ctx->ptr[B_CUMQ], p, S * 8, hipMemcpyHostToDevice, ctx->stream));
+        p += S * 8;
+        HIPCHECK(hipMemcpyAsync(ctx->ptr[B_DIAG], p, S * NDIAG * 8, hipMemcpyHostToDevice, ctx->stream));
+        HIPCHECK(hipStreamSynchronize(ctx->stream));
+        ctx->parity = (int)h.parity;
+        ctx->steps = h.steps;
+        ctx->time = h.time;
+        ctx->E0 = h.E0;
+        ctx->Eref = h.Eref;
+        ctx->lat0 = h.lat0;
+    });
+}
+
+int fem_get_node_perm(const fem_ctx *ctx, int32_t *perm) {
+    if (!ctx || !perm) return set_err(FEM_E_INVALID_ARG, "null argument");
+    if (ctx->stage < ST_FINAL) return set_err(FEM_E_STATE, "call fem_finalize first");
+    const Layout &L = ctx->L();
+    std::memcpy(perm, L.perm.data(), L.N * sizeof(int32_t));
+    return FEM_OK;
+}
+
+int fem_time_kernels(fem_ctx *ctx, double dt, int64_t n_steps, fem_kernel_times *out) {
+    if (!ctx || !out) return set_err(FEM_E_INVALID_ARG, "null argument");
+    return guarded([&] {
+        check_bound(ctx, ST_BOUND);
+        if (n_steps <= 0 || n_steps > 100000) throw PrepError{FEM_E_INVALID_ARG, "n_steps must be in 1..100000"};
+        if (!(dt > 0) || (dt > ctx->base.dt_bound && !ctx->opt.allow_unstable)) throw PrepError{FEM_E_UNSTABLE, "bad dt"};
+        set_dt(ctx, dt);
+        std::vector<hipEvent_t> ev(4 * n_steps);
+        for (auto &e : ev) HIPCHECK(hipEventCreate(&e));
+        for (int64_t s = 0; s < n_steps; ++s) {
+            HIPCHECK(enqueue_step(ctx->dev, ctx->parity, ctx->stream, &ev[4 * s]));
+            ctx->parity ^= 1;
+        }
+        HIPCHECK(hipEventSynchronize(ev.back()));
+        double a = 0, b = 0;
+        for (int64_t s = 0; s < n_steps; ++s) {
+            float m1 = 0, m2 = 0;
+            HIPCHECK(hipEventElapsedTime(&m1, ev[4 * s], ev[4 * s + 1]));
+            HIPCHECK(hipEventElapsedTime(&m2, ev[4 * s + 2], ev[4 * s + 3]));
+            a += m1;
+            b += m2;
+        }
+        for (auto &e : ev) (void)hipEventDestroy(e);
+        ctx->steps += n_steps;
+        ctx->time += dt * (double)n_steps;
+        const Layout &L = ctx->L();
+        const double R = (double)ctx->rsize();
+        const double gather = 4.0 * R + 4.0;             // xyz + T read + flags
+        const double update = R + 16.0 + 2.0 * R;        // 1/m, H read+write, T and fs write
+        const double elem = 4.0 * L.nen;                 // connectivity
+        const bool blocked = ctx->opt.scatter == FEM_SCATTER_LDS_BLOCKED;
+        const double upd_k1 = blocked ? (double)L.n_private : 0.0;
+        std::memset(out, 0, sizeof(*out));
+        out->launches_element = n_steps * (ctx->opt.scatter == FEM_SCATTER_COLORED ? (int64_t)ctx->dev.n_colors : 1);
+        out->launches_combine = n_steps;
+        out->ms_element = a / (double)n_steps;
+        out->ms_combine = b / (double)n_steps;
+        out->bytes_element = elem * (double)L.E + gather * (double)L.N + update * upd_k1;
+        out->bytes_combine = update * ((double)L.N - upd_k1);
+    });
+}
+
+int fem_copy_kernel(fem_ctx *ctx, void *dst, const void *src, int64_t bytes, int32_t repeats, double *ms_per_copy) {
+    if (!ctx || !dst || !src || !ms_per_copy) return set_err(FEM_E_INVALID_ARG, "null argument");
+    return guarded([&] {
+        if (bytes <= 0 || bytes % 16 || repeats <= 0) throw PrepError{FEM_E_INVALID_ARG, "bytes must be a positive multiple of 16"};
+        hipEvent_t e0, e1;
+        HIPCHECK(hipEventCreate(&e0));
+        HIPCHECK(hipEventCreate(&e1));
+        HIPCHECK(enqueue_copy(dst, src, bytes / 16, ctx->stream));
+        HIPCHECK(hipEventRecord(e0, ctx->stream));
+        for (int r = 0; r < repeats; ++r) HIPCHECK(enqueue_copy(dst, src, bytes / 16, ctx->stream));
+        HIPCHECK(hipEventRecord(e1, ctx->stream));
+        HIPCHECK(hipEventSynchronize(e1));
+        float ms = 0;
+        HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        *ms_per_copy = ms / repeats;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,414 @@
+// gfx950 kernels of the explicit casting step.
+//
+// One step is two launches:
+//   element phase: the conduction residual r = -K T assembled element by
+//     element (Eq. 15-18 of the paper).  Three ways to scatter it:
+//       - LDS-blocked: a workgroup takes one element block (the cache block of
+//         Sec. 4.2 with the private/shared node classes of Sec. 4.1), gathers
+//         the block's node coordinates and temperatures into LDS, accumulates
+//         the residual with LDS atomics, updates its private nodes in place and
+//         writes one partial per shared node (the Eq. 19-22 exchange, on chip);
+//       - global atomics into r[N];
+//       - colour by colour with plain read-modify-write (no two elements of a
+//         colour share a node).
+//   node phase: per node (or per shared node in the blocked layout) the sum of
+//     partials, the flux and interface terms (Eq. 4, Eq. 8, sister-face mean),
+//     and the enthalpy update H += dt r / m (Eq. 14 in enthalpy form) with
+//     T = T(H), fs = fs(H) (Eq. 11) in FP64; FP64 wavefront reductions of the
+//     energy balance.
+// FP32 state keeps the enthalpy as an FP32 (hi, lo) pair updated by an
+// error-free two-sum; T(H) is evaluated in FP64 from hi + lo.
+#include "kernels.hpp"
+
+#include <cfloat>
+
+#include "elem.hpp"
+
+namespace castfem {
+namespace {
+
+template <class R> struct VT;
+template <> struct VT<float> { using V4 = float4; using V2 = float2; };
+template <> struct VT<double> { using V4 = double4; using V2 = double2; };
+
+__device__ __forceinline__ uint32_t flag_bits(float w) { return __float_as_uint(w); }
+__device__ __forceinline__ uint32_t flag_bits(double w) { return (uint32_t)__double_as_longlong(w); }
+
+__device__ __forceinline__ float mat_k(const MatDev &m, float) { return m.kf; }
+__device__ __forceinline__ double mat_k(const MatDev &m, double) { return m.k; }
+
+// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+// contiguous range of logical blocks so neighbouring blocks share its L2.
+__device__ __forceinline__ int xcd_remap(int w, int n) {
+    const int x = w & 7, i = w >> 3;
+    const int q = n >> 3, rem = n & 7;
+    return x * q + min(x, rem) + i;
+}
+
+struct DiagAcc {
+    double v[NDIAG];
+    __device__ void init() {
+        for (int k = 0; k < NDIAG; ++k) v[k] = 0.0;
+        v[DG_TMIN] = DBL_MAX;
+        v[DG_TMAX] = -DBL_MAX;
+    }
+};
+
+// enthalpy relation (Eq. 11, linear latent release); isothermal: slope = 0
+__device__ __forceinline__ void t_of_h(const MatDev &M, double H, double &T, double &fs) {
+    if (!M.latent || H <= M.Hs) {
+        T = H * M.inv_c;
+        fs = 1.0;
+    } else if (H >= M.Hl) {
+        T = (H - M.L) * M.inv_c;
+        fs = 0.0;
+    } else {
+        T = M.Ts + (H - M.Hs) * M.slope;
+        fs = 1.0 - (H - M.Hs) * M.inv_dH;
+    }
+}
+
+__device__ __forceinline__ void accumulate(DiagAcc &a, const MatDev &M, double m, double H, double T,
+                                           double fs, double q) {
+    a.v[DG_E] += m * H;
+    a.v[DG_LAT] += m * M.L * (1.0 - fs);
+    a.v[DG_Q] += q;
+    a.v[DG_QDT] += q * M.dt;
+    a.v[DG_TMIN] = fmin(a.v[DG_TMIN], T);
+    a.v[DG_TMAX] = fmax(a.v[DG_TMAX], T);
+    if (M.latent && fs < 1.0) a.v[DG_NLIQ] += 1.0;
+    if (!isfinite(H)) a.v[DG_NONFIN] += 1.0;
+}
+
+// ------------------------------------------------------------ node update
+// FP32: error-free two-sum of (hi, inc) carried into lo, then renormalised.
+__device__ __forceinline__ float2 kahan_add(float2 h, float inc) {
+#pragma clang fp contract(off)
+    float s = h.x + inc;
+    float bp = s - h.x;
+    float e = (h.x - (s - bp)) + (inc - bp);
+    float lo = h.y + e;
+    float hi = s + lo;
+    lo = lo - (hi - s);
+    return make_float2(hi, lo);
+}
+
+template <class R> struct Node;
+
+template <> struct Node<float> {
+    // update node g with residual r; q = boundary inflow already attributed to it
+    static __device__ __forceinline__ void update(const Dev &d, int64_t g, float r, uint32_t flag, float Tcur,
+                                                  float *Tn, double q, DiagAcc &acc) {
+        const MatDev &M = d.mats[flag & NODE_MAT_MASK];
+        float2 *H = (float2 *)d.H;
+        const float im = ((const float *)d.inv_m)[g];
+        float2 h = H[g];
+        float Tnew;
+        if (flag & NODE_FIXED) {
+            q -= (double)r;
+        } else {
+            float inc;
+            {
+#pragma clang fp contract(off)
+                inc = r * (M.dtf * im);
+            }
+            h = kahan_add(h, inc);
+            H[g] = h;
+        }
+        const double Hd = (double)h.x + (double)h.y;
+        double T, fs;
+        t_of_h(M, Hd, T, fs);
+        Tnew = (flag & NODE_FIXED) ? Tcur : (float)T;
+        Tn[g] = Tnew;
+        ((float *)d.fs)[g] = (float)fs;
+        accumulate(acc, M, 1.0 / (double)im, Hd, (double)Tnew, fs, q);
+    }
+};
+
+template <> struct Node<double> {
+    static __device__ __forceinline__ void update(const Dev &d, int64_t g, double r, uint32_t flag, double Tcur,
+                                                  double *Tn, double q, DiagAcc &acc) {
+        const MatDev &M = d.mats[flag & NODE_MAT_MASK];
+        double *H = (double *)d.H;
+        const double im = ((const double *)d.inv_m)[g];
+        double h = H[g];
+        if (flag & NODE_FIXED) {
+            q -= r;
+        } else {
+            h = h + r * (M.dt * im);
+            H[g] = h;
+        }
+        double T, fs;
+        t_of_h(M, h, T, fs);
+        const double Tnew = (flag & NODE_FIXED) ? Tcur : T;
+        Tn[g] = Tnew;
+        ((double *)d.fs)[g] = fs;
+        accumulate(acc, M, 1.0 / im, h, Tnew, fs, q);
+    }
+};
+
+// Robin and interface terms of boundary slot s for a node at temperature Ti:
+// adds them to r and returns the Robin inflow
+template <class R>
+__device__ __forceinline__ double boundary_terms(const Dev &d, int64_t s, R Ti, const R *Tc, R &r) {
+    using V2 = typename VT<R>::V2;
+    double q = 0.0;
+    if (d.robin) {
+        const V2 ab = ((const V2 *)d.robin)[s];
+        const R f = ab.x - ab.y * Ti;
+        r += f;
+        q = (double)f;
+    }
+    const int32_t l0 = d.link_ptr[s], l1 = d.link_ptr[s + 1];
+    const R *w = (const R *)d.link_w;
+    for (int32_t k = l0; k < l1; ++k) r += w[k] * (Tc[d.link_node[k]] - Ti);
+    return q;
+}
+
+// wavefront then workgroup reduction of the diagnostics into slot `slot`
+__device__ void reduce_diag(const Dev &d, DiagAcc &acc, int64_t slot) {
+    __shared__ double part[16][NDIAG];
+    for (int k = 0; k < NDIAG; ++k) {
+        double v = acc.v[k];
+        for (int off = 32; off > 0; off >>= 1) {
+            double o = __shfl_down(v, off, 64);
+            if (k == DG_TMIN) v = fmin(v, o);
+            else if (k == DG_TMAX) v = fmax(v, o);
+            else v += o;
+        }
+        acc.v[k] = v;
+    }
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0)
+        for (int k = 0; k < NDIAG; ++k) part[wave][k] = acc.v[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        double out[NDIAG];
+        for (int k = 0; k < NDIAG; ++k) out[k] = part[0][k];
+        for (int w = 1; w < nw; ++w)
+            for (int k = 0; k < NDIAG; ++k) {
+                if (k == DG_TMIN) out[k] = fmin(out[k], part[w][k]);
+                else if (k == DG_TMAX) out[k] = fmax(out[k], part[w][k]);
+                else out[k] += part[w][k];
+            }
+        for (int k = 0; k < NDIAG; ++k) d.diag[slot * NDIAG + k] = out[k];
+        d.cumQ[slot] += out[DG_QDT];
+    }
+}
+
+// ------------------------------------------------------------ element math
+template <class R, int NEN> struct Elem;
+
+template <class R> struct Elem<R, 4> {
+    using V4 = typename VT<R>::V4;
+    static __device__ __forceinline__ void residual(const V4 *p, R k, R *r) {
+        tet_residual<R>({p[0].x, p[0].y, p[0].z}, {p[1].x, p[1].y, p[1].z}, {p[2].x, p[2].y, p[2].z},
+                        {p[3].x, p[3].y, p[3].z}, p[0].w, p[1].w, p[2].w, p[3].w, k, r[0], r[1], r[2], r[3]);
+    }
+};
+
+template <class R> struct Elem<R, 8> {
+    using V4 = typename VT<R>::V4;
+    static __device__ __forceinline__ void residual(const V4 *p, R k, R *r) {
+        V3<R> x[8];
+        R t[8];
+        for (int a = 0; a < 8; ++a) {
+            x[a] = {p[a].x, p[a].y, p[a].z};
+            t[a] = p[a].w;
+        }
+        hex_residual<R>(x, t, k, r);
+    }
+};
+
+// ------------------------------------------------------------ kernels
+// element phase, one thread per element, scatter into r[N] by global atomics
+// (ATOMIC) or by plain read-modify-write within one colour
+template <class R, int NEN, bool ATOMIC>
+__global__ __launch_bounds__(256) void k_elems(Dev d, int parity, int64_t e0, int64_t e1) {
+    using V4 = typename VT<R>::V4;
+    const int64_t e = e0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= e1) return;
+    const V4 *X = (const V4 *)d.node_x;
+    const R *Tc = (const R *)d.T + parity * d.N;
+    R *r = (R *)d.r;
+    int32_t c[NEN];
+    V4 p[NEN];
+    for (int a = 0; a < NEN; ++a) c[a] = d.conn[e * NEN + a];
+    for (int a = 0; a < NEN; ++a) {
+        p[a] = X[c[a]];
+        p[a].w = Tc[c[a]];
+    }
+    const uint32_t f0 = flag_bits(X[c[0]].w);
+    const R k = mat_k(d.mats[f0 & NODE_MAT_MASK], R(0));
+    R re[NEN];
+    Elem<R, NEN>::residual(p, k, re);
+    for (int a = 0; a < NEN; ++a) {
+        if (ATOMIC) atomicAdd(&r[c[a]], re[a]);
+        else r[c[a]] += re[a];
+    }
+}
+
+// element phase of the blocked layout, one workgroup per element block
+template <class R, int NEN>
+__global__ __launch_bounds__(1024) void k_block(Dev d, int parity) {
+    using V4 = typename VT<R>::V4;
+    extern __shared__ __attribute__((aligned(32))) unsigned char smem[];
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const BlockInfo bi = d.blocks[b];
+    const int nloc = bi.n_int + bi.n_sh;
+    V4 *s_x = (V4 *)smem;
+    R *s_r = (R *)(s_x + nloc);
+    uint32_t *s_f = (uint32_t *)(s_r + nloc);
+    const V4 *X = (const V4 *)d.node_x;
+    const R *Tc = (const R *)d.T + parity * d.N;
+    R *Tn = (R *)d.T + (1 - parity) * d.N;
+
+    // gather: private nodes are a contiguous range, shared nodes a list
+    for (int l = threadIdx.x; l < bi.n_int; l += blockDim.x) {
+        const int64_t g = (int64_t)bi.int_base + l;
+        V4 x = X[g];
+        s_f[l] = flag_bits(x.w);
+        x.w = Tc[g];
+        s_x[l] = x;
+        s_r[l] = R(0);
+    }
+    for (int l = threadIdx.x; l < bi.n_sh; l += blockDim.x) {
+        const int64_t g = d.sh_list[bi.sh_begin + l];
+        V4 x = X[g];
+        s_f[bi.n_int + l] = flag_bits(x.w);
+        x.w = Tc[g];
+        s_x[bi.n_int + l] = x;
+        s_r[bi.n_int + l] = R(0);
+    }
+    __syncthreads();
+
+    // element residuals accumulated in LDS
+    const uint16_t *lc = d.lconn + (int64_t)bi.e_begin * NEN;
+    for (int e = threadIdx.x; e < bi.n_e; e += blockDim.x) {
+        int l[NEN];
+        if (NEN == 4) {
+            const uint2 c = ((const uint2 *)lc)[e];
+            l[0] = c.x & 0xFFFF;
+            l[1] = c.x >> 16;
+            l[2] = c.y & 0xFFFF;
+            l[3] = c.y >> 16;
+        } else {
+            const uint4 c = ((const uint4 *)lc)[e];
+            const uint32_t w[4] = {c.x, c.y, c.z, c.w};
+            for (int a = 0; a < 4; ++a) {
+                l[2 * a] = w[a] & 0xFFFF;
+                l[2 * a + 1] = w[a] >> 16;
+            }
+        }
+        V4 p[NEN];
+        for (int a = 0; a < NEN; ++a) p[a] = s_x[l[a]];
+        const R k = mat_k(d.mats[s_f[l[0]] & NODE_MAT_MASK], R(0));
+        R re[NEN];
+        Elem<R, NEN>::residual(p, k, re);
+        for (int a = 0; a < NEN; ++a) atomicAdd(&s_r[l[a]], re[a]);
+    }
+    __syncthreads();
+
+    // private nodes are complete: update them in place
+    DiagAcc acc;
+    acc.init();
+    for (int l = threadIdx.x; l < bi.n_int; l += blockDim.x) {
+        const uint32_t f = s_f[l];
+        Node<R>::update(d, (int64_t)bi.int_base + l, s_r[l], f, s_x[l].w, Tn, 0.0, acc);
+    }
+    // one partial per shared node
+    R *P = (R *)d.partials;
+    for (int l = threadIdx.x; l < bi.n_sh; l += blockDim.x) P[bi.sh_begin + l] = s_r[bi.n_int + l];
+    reduce_diag(d, acc, b);
+}
+
+// node phase: all nodes (COMBINE = false: residual from r[N], which is reset)
+// or the shared nodes of the blocked layout (COMBINE = true: sum of partials)
+template <class R, bool COMBINE>
+__global__ __launch_bounds__(NODE_THREADS) void k_nodes(Dev d, int parity) {
+    using V4 = typename VT<R>::V4;
+    const int64_t count = COMBINE ? d.N - d.n_private : d.N;
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    DiagAcc acc;
+    acc.init();
+    if (s < count) {
+        const int64_t g = d.bc_first + s;
+        const R *Tc = (const R *)d.T + parity * d.N;
+        R *Tn = (R *)d.T + (1 - parity) * d.N;
+        R r;
+        if (COMBINE) {
+            const R *P = (const R *)d.partials;
+            r = R(0);
+            for (int32_t k = d.comb_ptr[s]; k < d.comb_ptr[s + 1]; ++k) r += P[d.comb_idx[k]];
+        } else {
+            R *rr = (R *)d.r;
+            r = rr[g];
+            rr[g] = R(0);
+        }
+        const uint32_t f = flag_bits(((const V4 *)d.node_x)[g].w);
+        const R Ti = Tc[g];
+        const double q = boundary_terms<R>(d, s, Ti, Tc, r);
+        Node<R>::update(d, g, r, f, Ti, Tn, q, acc);
+    }
+    reduce_diag(d, acc, d.diag_k1 + blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_copy(float4 *__restrict__ dst, const float4 *__restrict__ src, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+template <class R, int NEN>
+hipError_t step_t(const Dev &d, int parity, hipStream_t s, hipEvent_t *ev) {
+    if (ev) (void)hipEventRecord(ev[0], s);
+    if (d.scatter == FEM_SCATTER_LDS_BLOCKED) {
+        hipLaunchKernelGGL((k_block<R, NEN>), dim3((unsigned)d.n_blocks), dim3(d.threads), d.lds_bytes, s, d, parity);
+    } else if (d.scatter == FEM_SCATTER_GLOBAL_ATOMIC) {
+        if (d.E > 0)
+            hipLaunchKernelGGL((k_elems<R, NEN, true>), dim3((unsigned)((d.E + 255) / 256)), dim3(256), 0, s, d,
+                               parity, (int64_t)0, d.E);
+    } else {
+        for (int c = 0; c < d.n_colors; ++c) {
+            const int64_t e0 = d.color_ptr_host[c], e1 = d.color_ptr_host[c + 1];
+            if (e1 > e0)
+                hipLaunchKernelGGL((k_elems<R, NEN, false>), dim3((unsigned)((e1 - e0 + 255) / 256)), dim3(256), 0, s,
+                                   d, parity, e0, e1);
+        }
+    }
+    if (ev) {
+        (void)hipEventRecord(ev[1], s);
+        (void)hipEventRecord(ev[2], s);
+    }
+    const bool comb = d.scatter == FEM_SCATTER_LDS_BLOCKED;
+    const int64_t count = comb ? d.N - d.n_private : d.N;
+    if (count > 0) {
+        if (comb)
+            hipLaunchKernelGGL((k_nodes<R, true>), dim3((unsigned)node_grid(count)), dim3(NODE_THREADS), 0, s, d, parity);
+        else
+            hipLaunchKernelGGL((k_nodes<R, false>), dim3((unsigned)node_grid(count)), dim3(NODE_THREADS), 0, s, d, parity);
+    }
+    if (ev) (void)hipEventRecord(ev[3], s);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t enqueue_step(const Dev &d, int parity, hipStream_t s, hipEvent_t *ev) {
+    if (d.prec == FEM_PREC_FP64) return d.nen == 4 ? step_t<double, 4>(d, parity, s, ev) : step_t<double, 8>(d, parity, s, ev);
+    return d.nen == 4 ? step_t<float, 4>(d, parity, s, ev) : step_t<float, 8>(d, parity, s, ev);
+}
+
+hipError_t set_block_lds_limit(int prec, int nen, size_t bytes) {
+    const void *f;
+    if (prec == FEM_PREC_FP64) f = nen == 4 ? (const void *)k_block<double, 4> : (const void *)k_block<double, 8>;
+    else f = nen == 4 ? (const void *)k_block<float, 4> : (const void *)k_block<float, 8>;
+    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+hipError_t enqueue_copy(void *dst, const void *src, int64_t n16, hipStream_t s) {
+    hipLaunchKernelGGL(k_copy, dim3(2048), dim3(256), 0, s, (float4 *)dst, (const float4 *)src, n16);
+    return hipGetLastError();
+}
+
+}  // namespace castfem

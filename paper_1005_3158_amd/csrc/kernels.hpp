@@ -1,0 +1,76 @@
+// Device-side data layout of one context and the step launchers (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "prep.hpp"
+
+namespace castfem {
+
+// material constants of the enthalpy relation, precomputed in FP64 on the host
+struct MatDev {
+    double c, inv_c, Ts, Tl, L, Hs, Hl, slope, inv_dH, dt;
+    double k;
+    float kf, dtf;
+    int32_t latent, pad;
+};
+
+// number of FP64 values in one per-workgroup diagnostics record
+constexpr int NDIAG = 8;
+enum { DG_E = 0, DG_LAT = 1, DG_Q = 2, DG_TMIN = 3, DG_TMAX = 4, DG_NLIQ = 5, DG_NONFIN = 6, DG_QDT = 7 };
+
+struct Dev {
+    int prec = FEM_PREC_FP32_KAHAN;
+    int nen = 4;
+    int scatter = FEM_SCATTER_LDS_BLOCKED;
+    int64_t N = 0, E = 0;
+    // nodes
+    void *node_x = nullptr;   // R4 per node: x, y, z, flag bits
+    void *T = nullptr;        // R[2N] ping-pong temperatures
+    void *H = nullptr;        // float2 (hi, lo) or double per node
+    void *inv_m = nullptr;    // R per node
+    void *fs = nullptr;       // R per node
+    const MatDev *mats = nullptr;
+    // elements
+    const int32_t *conn = nullptr;      // global-atomic / coloured
+    void *r = nullptr;                  // R[N] residual (global-atomic / coloured)
+    const uint16_t *lconn = nullptr;    // LDS-blocked local connectivity
+    const BlockInfo *blocks = nullptr;
+    const int32_t *sh_list = nullptr;
+    void *partials = nullptr;           // R per (block, shared node)
+    const int32_t *comb_ptr = nullptr, *comb_idx = nullptr;
+    // boundary slots
+    const void *robin = nullptr;        // R2 (a, b) per slot or null
+    const int32_t *link_ptr = nullptr, *link_node = nullptr;
+    const void *link_w = nullptr;       // R per link
+    // diagnostics
+    double *diag = nullptr;             // NDIAG per workgroup slot
+    double *cumQ = nullptr;             // per workgroup slot: sum of dt * inflow
+    // sizes and launch shape
+    int64_t n_private = 0, n_blocks = 0, n_bc_slots = 0, bc_first = 0;
+    int threads = 256;
+    size_t lds_bytes = 0;
+    int n_colors = 0;
+    const int32_t *color_ptr_host = nullptr;
+    int64_t diag_k1 = 0;                // diagnostics slots of the element kernel
+    int64_t diag_k2 = 0;                // diagnostics slots of the node kernel
+};
+
+constexpr int NODE_THREADS = 256;
+
+inline int64_t node_grid(int64_t n) { return (n + NODE_THREADS - 1) / NODE_THREADS; }
+
+// LDS bytes per local node of the blocked kernel
+inline size_t lds_per_node(int prec) { return prec == FEM_PREC_FP64 ? 44 : 24; }
+
+// Enqueue one explicit step reading T buffer `parity` and writing 1 - parity.
+// If ev is not null, ev[0..1] bracket the element kernel(s) and ev[2..3] the
+// node kernel.
+hipError_t enqueue_step(const Dev &d, int parity, hipStream_t s, hipEvent_t *ev);
+// Allow the blocked element kernel `bytes` of dynamic LDS.
+hipError_t set_block_lds_limit(int prec, int nen, size_t bytes);
+// Plain vector copy of n16 16-byte words.
+hipError_t enqueue_copy(void *dst, const void *src, int64_t n16, hipStream_t s);
+
+}  // namespace castfem

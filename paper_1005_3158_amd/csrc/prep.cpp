@@ -1,0 +1,757 @@
+// Host preprocessing of the casting step (see prep.hpp).
+#include "prep.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <numeric>
+
+#include "elem.hpp"
+
+namespace castfem {
+
+namespace {
+
+[[noreturn]] void fail(int code, const std::string &msg) { throw PrepError{code, msg}; }
+
+// phase timing on stderr when CASTFEM_PREP_TIMING is set
+struct PhaseTimer {
+    bool on = std::getenv("CASTFEM_PREP_TIMING") != nullptr;
+    std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
+    void mark(const char *what) {
+        if (!on) return;
+        auto n = std::chrono::steady_clock::now();
+        std::fprintf(stderr, "[castfem prep] %-28s %8.3f s\n", what, std::chrono::duration<double>(n - t).count());
+        t = n;
+    }
+};
+
+V3<double> node_x(const std::vector<double> &xyz, int64_t i) {
+    return {xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]};
+}
+
+// indices 0..n-1 stably sorted by 64-bit key (LSD radix sort over 11-bit
+// digits; digits above the largest key and digits equal for every key are skipped)
+template <class I>
+std::vector<I> sort_by_key(const std::vector<uint64_t> &key) {
+    const size_t n = key.size();
+    std::vector<I> idx(n), tmp(n);
+    for (size_t i = 0; i < n; ++i) idx[i] = (I)i;
+    uint64_t kmax = 0;
+    for (size_t i = 0; i < n; ++i) kmax = std::max(kmax, key[i]);
+    std::vector<uint64_t> k(key), ktmp(n);
+    constexpr int DIG = 11, RAD = 1 << DIG;
+    std::vector<size_t> cnt(RAD + 1);
+    for (int shift = 0; shift < 64 && (kmax >> shift) != 0; shift += DIG) {
+        std::fill(cnt.begin(), cnt.end(), 0);
+        for (size_t i = 0; i < n; ++i) cnt[((k[i] >> shift) & (RAD - 1)) + 1]++;
+        bool trivial = false;
+        for (int d = 1; d <= RAD; ++d)
+            if (cnt[d] == n) trivial = true;
+        if (trivial) continue;
+        for (int d = 0; d < RAD; ++d) cnt[d + 1] += cnt[d];
+        for (size_t i = 0; i < n; ++i) {
+            size_t pos = cnt[(k[i] >> shift) & (RAD - 1)]++;
+            tmp[pos] = idx[i];
+            ktmp[pos] = k[i];
+        }
+        idx.swap(tmp);
+        k.swap(ktmp);
+    }
+    return idx;
+}
+
+// area of a triangle, or of a quad as half the norm of the cross product of its diagonals
+double face_area(const std::vector<double> &xyz, const int32_t *f, int npf) {
+    V3<double> u, v;
+    if (npf == 3) {
+        u = sub3(node_x(xyz, f[1]), node_x(xyz, f[0]));
+        v = sub3(node_x(xyz, f[2]), node_x(xyz, f[0]));
+    } else {
+        u = sub3(node_x(xyz, f[2]), node_x(xyz, f[0]));
+        v = sub3(node_x(xyz, f[3]), node_x(xyz, f[1]));
+    }
+    V3<double> w = cross3(u, v);
+    return 0.5 * std::sqrt(dot3(w, w));
+}
+
+// node -> incident element slots (e * nen + a), CSR
+void node_elem_csr(const Problem &p, std::vector<int64_t> &ptr, std::vector<int64_t> &inc) {
+    ptr.assign(p.N + 1, 0);
+    const int64_t tot = p.E * p.nen;
+    for (int64_t s = 0; s < tot; ++s) ptr[p.conn[s] + 1]++;
+    for (int64_t i = 0; i < p.N; ++i) ptr[i + 1] += ptr[i];
+    inc.resize(tot);
+    std::vector<int64_t> fill(ptr.begin(), ptr.end() - 1);
+    for (int64_t s = 0; s < tot; ++s) inc[fill[p.conn[s]]++] = s;
+}
+
+void elem_ke(const Problem &p, int64_t e, double Ke[8][8]) {
+    const int32_t *c = &p.conn[e * p.nen];
+    double k = p.mats[p.emat[e]].k;
+    if (p.nen == 4) {
+        double K4[4][4];
+        tet_ke<double>(node_x(p.xyz, c[0]), node_x(p.xyz, c[1]), node_x(p.xyz, c[2]), node_x(p.xyz, c[3]), k, K4);
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b) Ke[a][b] = K4[a][b];
+    } else {
+        V3<double> x[8];
+        for (int a = 0; a < 8; ++a) x[a] = node_x(p.xyz, c[a]);
+        double m[8];
+        hex_ke_mass<double>(x, k, 1.0, Ke, m);
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- base data
+void prep_base(const Problem &p, Base &b) {
+    if (p.nen != 4 && p.nen != 8) fail(FEM_E_STATE, "no mesh uploaded");
+    if (p.mats.empty()) fail(FEM_E_STATE, "no materials set");
+    if ((int64_t)p.T0.size() != p.N) fail(FEM_E_STATE, "no initial temperature set");
+    for (size_t q = 0; q < p.mats.size(); ++q) {
+        const fem_material &m = p.mats[q];
+        if (!(m.k > 0) || !(m.rho > 0) || !(m.c > 0) || !(m.L >= 0) || !(m.T_liq >= m.T_sol))
+            fail(FEM_E_INVALID_ARG, "material " + std::to_string(q) + " has invalid properties");
+    }
+    const int nen = p.nen;
+    const int64_t N = p.N, E = p.E;
+    PhaseTimer tm;
+    // node materials
+    b.nmat.assign(N, -1);
+    for (int64_t e = 0; e < E; ++e) {
+        int32_t mt = p.emat[e];
+        if (mt < 0 || mt >= (int32_t)p.mats.size()) fail(FEM_E_MESH, "element " + std::to_string(e) + " has no valid material");
+        for (int a = 0; a < nen; ++a) {
+            int32_t n = p.conn[e * nen + a];
+            if (n < 0 || n >= N) fail(FEM_E_MESH, "element " + std::to_string(e) + " refers to node out of range");
+            if (b.nmat[n] >= 0 && b.nmat[n] != mt)
+                fail(FEM_E_MESH, "node " + std::to_string(n) + " belongs to two materials (duplicate interface nodes)");
+            b.nmat[n] = mt;
+        }
+    }
+    for (int64_t i = 0; i < N; ++i)
+        if (b.nmat[i] < 0) fail(FEM_E_MESH, "node " + std::to_string(i) + " is in no element");
+    tm.mark("node materials");
+    // lumped capacitance, element orientation
+    b.m.assign(N, 0.0);
+    for (int64_t e = 0; e < E; ++e) {
+        const int32_t *c = &p.conn[e * nen];
+        double rho = p.mats[p.emat[e]].rho;
+        if (nen == 4) {
+            double D = tet_six_vol<double>(node_x(p.xyz, c[0]), node_x(p.xyz, c[1]), node_x(p.xyz, c[2]), node_x(p.xyz, c[3]));
+            if (!(D > 0)) fail(FEM_E_MESH, "tetrahedron " + std::to_string(e) + " is inverted or degenerate");
+            double w = rho * D / 24.0;  // rho V / 4
+            for (int a = 0; a < 4; ++a) b.m[c[a]] += w;
+        } else {
+            V3<double> x[8];
+            for (int a = 0; a < 8; ++a) x[a] = node_x(p.xyz, c[a]);
+            double Ke[8][8], me[8];
+            double mindet = hex_ke_mass<double>(x, 1.0, rho, Ke, me);
+            if (!(mindet > 0)) fail(FEM_E_MESH, "hexahedron " + std::to_string(e) + " is inverted or degenerate");
+            for (int a = 0; a < 8; ++a) b.m[c[a]] += me[a];
+        }
+    }
+    tm.mark("lumping");
+    // fixed temperatures and the initial field
+    b.fixed.assign(N, 0);
+    b.T_init = p.T0;
+    for (size_t d = 0; d < p.dir_nodes.size(); ++d) {
+        int32_t n = p.dir_nodes[d];
+        if (n < 0 || n >= N) fail(FEM_E_MESH, "fixed-temperature node out of range");
+        b.fixed[n] = 1;
+        b.T_init[n] = p.dir_T[d];
+    }
+    for (int64_t i = 0; i < N; ++i)
+        if (!std::isfinite(b.T_init[i])) fail(FEM_E_INVALID_ARG, "initial temperature not finite");
+    // convective / flux faces: r_i += a_i - b_i T_i
+    b.robin_a.assign(N, 0.0);
+    b.robin_b.assign(N, 0.0);
+    const int64_t nf = p.npf ? (int64_t)p.flux_faces.size() / p.npf : 0;
+    b.any_robin = nf > 0;
+    for (int64_t f = 0; f < nf; ++f) {
+        const int32_t *fn = &p.flux_faces[f * p.npf];
+        for (int a = 0; a < p.npf; ++a)
+            if (fn[a] < 0 || fn[a] >= N) fail(FEM_E_MESH, "flux face node out of range");
+        double A = face_area(p.xyz, fn, p.npf) / p.npf;
+        for (int a = 0; a < p.npf; ++a) {
+            b.robin_a[fn[a]] += A * (-p.flux_q[f] + p.flux_h[f] * p.flux_Tinf[f]);
+            b.robin_b[fn[a]] += A * p.flux_h[f];
+        }
+    }
+    // interface pairs as symmetric node links: node i of one face and node j of
+    // its sister face share w = h A / 9, so r_i += sum_j w_ij (T_j - T_i)
+    struct Trip {
+        int32_t i, j;
+        double w;
+    };
+    std::vector<Trip> t;
+    const int64_t npair = (int64_t)p.if_h.size();
+    t.reserve(npair * 18);
+    for (int64_t f = 0; f < npair; ++f) {
+        const int32_t *fa = &p.if_a[3 * f], *fb = &p.if_b[3 * f];
+        for (int a = 0; a < 3; ++a)
+            if (fa[a] < 0 || fa[a] >= N || fb[a] < 0 || fb[a] >= N) fail(FEM_E_MESH, "interface face node out of range");
+        double A = face_area(p.xyz, fa, 3);
+        double w = p.if_h[f] * A / 9.0;
+        for (int a = 0; a < 3; ++a)
+            for (int c = 0; c < 3; ++c) {
+                t.push_back({fa[a], fb[c], w});
+                t.push_back({fb[c], fa[a], w});
+            }
+    }
+    std::sort(t.begin(), t.end(), [](const Trip &x, const Trip &y) { return x.i != y.i ? x.i < y.i : x.j < y.j; });
+    b.lptr.assign(N + 1, 0);
+    b.lnode.clear();
+    b.lw.clear();
+    for (size_t s = 0; s < t.size();) {
+        size_t u = s;
+        double w = 0;
+        while (u < t.size() && t[u].i == t[s].i && t[u].j == t[s].j) w += t[u++].w;
+        b.lnode.push_back(t[s].j);
+        b.lw.push_back(w);
+        b.lptr[t[s].i + 1]++;
+        s = u;
+    }
+    for (int64_t i = 0; i < N; ++i) b.lptr[i + 1] += b.lptr[i];
+    tm.mark("boundary terms");
+    // stability bound: Gershgorin rows of the assembled operator over m_i c_i
+    std::vector<int64_t> ptr, inc;
+    node_elem_csr(p, ptr, inc);
+    tm.mark("node-element lists");
+    double lam = 0.0;
+#pragma omp parallel
+    {
+        std::vector<int32_t> cols;
+        std::vector<double> vals;
+        double lam_t = 0.0;
+#pragma omp for schedule(dynamic, 4096)
+        for (int64_t i = 0; i < N; ++i) {
+            cols.clear();
+            vals.clear();
+            double Ke[8][8];
+            for (int64_t s = ptr[i]; s < ptr[i + 1]; ++s) {
+                int64_t e = inc[s] / nen;
+                int a = (int)(inc[s] % nen);
+                elem_ke(p, e, Ke);
+                for (int c = 0; c < nen; ++c) {
+                    int32_t j = p.conn[e * nen + c];
+                    size_t q = 0;
+                    while (q < cols.size() && cols[q] != j) ++q;
+                    if (q == cols.size()) {
+                        cols.push_back(j);
+                        vals.push_back(0.0);
+                    }
+                    vals[q] += Ke[a][c];
+                }
+            }
+            double row = b.robin_b[i];
+            for (double v : vals) row += std::fabs(v);
+            for (int32_t s = b.lptr[i]; s < b.lptr[i + 1]; ++s) row += 2.0 * b.lw[s];
+            double li = row / (b.m[i] * p.mats[b.nmat[i]].c);
+            if (li > lam_t) lam_t = li;
+        }
+#pragma omp critical
+        if (lam_t > lam) lam = lam_t;
+    }
+    b.dt_bound = lam > 0 ? 2.0 / lam : INFINITY;
+    tm.mark("stability bound");
+}
+
+int64_t bandwidth(const Problem &p, const Base &b, const std::vector<int32_t> *perm) {
+    auto id = [&](int32_t n) -> int64_t { return perm ? (*perm)[n] : n; };
+    int64_t bw = 0;
+    for (int64_t e = 0; e < p.E; ++e) {
+        int64_t lo = INT64_MAX, hi = INT64_MIN;
+        for (int a = 0; a < p.nen; ++a) {
+            int64_t v = id(p.conn[e * p.nen + a]);
+            lo = std::min(lo, v);
+            hi = std::max(hi, v);
+        }
+        bw = std::max(bw, hi - lo);
+    }
+    for (int64_t i = 0; i < p.N; ++i)
+        for (int32_t s = b.lptr[i]; s < b.lptr[i + 1]; ++s) bw = std::max(bw, std::abs(id((int32_t)i) - id(b.lnode[s])));
+    return bw;
+}
+
+// ---------------------------------------------------------------- orderings
+namespace {
+
+// Node graph (element edges and interface links), CSR with sorted unique neighbours.
+void node_graph(const Problem &p, const Base &b, std::vector<int64_t> &gptr, std::vector<int32_t> &adj) {
+    std::vector<int64_t> ptr, inc;
+    node_elem_csr(p, ptr, inc);
+    const int64_t N = p.N;
+    std::vector<int32_t> deg(N);
+#pragma omp parallel
+    {
+        std::vector<int32_t> nb;
+#pragma omp for schedule(dynamic, 4096)
+        for (int64_t i = 0; i < N; ++i) {
+            nb.clear();
+            for (int64_t s = ptr[i]; s < ptr[i + 1]; ++s) {
+                int64_t e = inc[s] / p.nen;
+                for (int c = 0; c < p.nen; ++c) {
+                    int32_t j = p.conn[e * p.nen + c];
+                    if (j != i) nb.push_back(j);
+                }
+            }
+            for (int32_t s = b.lptr[i]; s < b.lptr[i + 1]; ++s) nb.push_back(b.lnode[s]);
+            std::sort(nb.begin(), nb.end());
+            deg[i] = (int32_t)(std::unique(nb.begin(), nb.end()) - nb.begin());
+        }
+    }
+    gptr.assign(N + 1, 0);
+    for (int64_t i = 0; i < N; ++i) gptr[i + 1] = gptr[i] + deg[i];
+    adj.resize(gptr[N]);
+#pragma omp parallel
+    {
+        std::vector<int32_t> nb;
+#pragma omp for schedule(dynamic, 4096)
+        for (int64_t i = 0; i < N; ++i) {
+            nb.clear();
+            for (int64_t s = ptr[i]; s < ptr[i + 1]; ++s) {
+                int64_t e = inc[s] / p.nen;
+                for (int c = 0; c < p.nen; ++c) {
+                    int32_t j = p.conn[e * p.nen + c];
+                    if (j != i) nb.push_back(j);
+                }
+            }
+            for (int32_t s = b.lptr[i]; s < b.lptr[i + 1]; ++s) nb.push_back(b.lnode[s]);
+            std::sort(nb.begin(), nb.end());
+            nb.erase(std::unique(nb.begin(), nb.end()), nb.end());
+            std::copy(nb.begin(), nb.end(), adj.begin() + gptr[i]);
+        }
+    }
+}
+
+// breadth-first level structure from `root` over unvisited-in-component nodes;
+// returns the last level and the depth
+int bfs_levels(const std::vector<int64_t> &gptr, const std::vector<int32_t> &adj, int32_t root,
+               std::vector<int32_t> &mark, int32_t stamp, std::vector<int32_t> &last) {
+    std::vector<int32_t> cur{root}, nxt;
+    mark[root] = stamp;
+    int depth = 0;
+    for (;;) {
+        nxt.clear();
+        for (int32_t u : cur)
+            for (int64_t s = gptr[u]; s < gptr[u + 1]; ++s) {
+                int32_t v = adj[s];
+                if (mark[v] != stamp) {
+                    mark[v] = stamp;
+                    nxt.push_back(v);
+                }
+            }
+        if (nxt.empty()) break;
+        cur.swap(nxt);
+        ++depth;
+    }
+    last = cur;
+    return depth;
+}
+
+}  // namespace
+
+// Reverse Cuthill-McKee: per connected component, a pseudo-peripheral start
+// node (repeated breadth-first searches from a minimum-degree node of the last
+// level while the depth grows), then a breadth-first numbering that visits
+// neighbours in increasing degree, reversed at the end.
+std::vector<int32_t> order_rcm(const Problem &p, const Base &b) {
+    std::vector<int64_t> gptr;
+    std::vector<int32_t> adj;
+    node_graph(p, b, gptr, adj);
+    const int64_t N = p.N;
+    auto deg = [&](int32_t u) { return gptr[u + 1] - gptr[u]; };
+    std::vector<int32_t> order;
+    order.reserve(N);
+    std::vector<uint8_t> done(N, 0);
+    std::vector<int32_t> mark(N, -1);
+    int32_t stamp = 0;
+    // nodes by degree, to seed each component at a low-degree node
+    std::vector<uint64_t> dkey(N);
+    for (int64_t i = 0; i < N; ++i) dkey[i] = (uint64_t)deg((int32_t)i);
+    std::vector<int32_t> bydeg = sort_by_key<int32_t>(dkey);
+    std::vector<int32_t> last, nb;
+    for (int32_t seed : bydeg) {
+        if (done[seed]) continue;
+        int32_t root = seed;
+        int depth = bfs_levels(gptr, adj, root, mark, stamp++, last);
+        for (int it = 0; it < 16; ++it) {
+            int32_t best = last[0];
+            for (int32_t v : last)
+                if (deg(v) < deg(best)) best = v;
+            int d2 = bfs_levels(gptr, adj, best, mark, stamp++, last);
+            if (d2 <= depth) break;
+            depth = d2;
+            root = best;
+        }
+        size_t head = order.size();
+        order.push_back(root);
+        done[root] = 1;
+        while (head < order.size()) {
+            int32_t u = order[head++];
+            nb.clear();
+            for (int64_t s = gptr[u]; s < gptr[u + 1]; ++s)
+                if (!done[adj[s]]) {
+                    nb.push_back(adj[s]);
+                    done[adj[s]] = 1;
+                }
+            std::stable_sort(nb.begin(), nb.end(), [&](int32_t x, int32_t y) { return deg(x) < deg(y); });
+            order.insert(order.end(), nb.begin(), nb.end());
+        }
+    }
+    std::vector<int32_t> perm(N);
+    for (int64_t r = 0; r < N; ++r) perm[order[N - 1 - r]] = (int32_t)r;
+    return perm;
+}
+
+namespace {
+
+// Hilbert index of a point with `bits`-bit coordinates: the axes are turned
+// into the transposed Hilbert form by Skilling's inverse-undo and Gray-code
+// passes ("Programming the Hilbert curve", AIP Conf. Proc. 707, 2004), then
+// the bits are interleaved, most significant level first.
+uint64_t hilbert3(uint32_t X[3], int bits) {
+    const uint32_t M = 1u << (bits - 1);
+    for (uint32_t Q = M; Q > 1; Q >>= 1) {
+        uint32_t P = Q - 1;
+        for (int i = 0; i < 3; ++i) {
+            if (X[i] & Q) {
+                X[0] ^= P;
+            } else {
+                uint32_t t = (X[0] ^ X[i]) & P;
+                X[0] ^= t;
+                X[i] ^= t;
+            }
+        }
+    }
+    for (int i = 1; i < 3; ++i) X[i] ^= X[i - 1];
+    uint32_t t = 0;
+    for (uint32_t Q = M; Q > 1; Q >>= 1)
+        if (X[2] & Q) t ^= Q - 1;
+    for (int i = 0; i < 3; ++i) X[i] ^= t;
+    uint64_t h = 0;
+    for (int bit = bits - 1; bit >= 0; --bit)
+        for (int i = 0; i < 3; ++i) h = (h << 1) | ((X[i] >> bit) & 1u);
+    return h;
+}
+
+uint64_t morton3(const uint32_t X[3], int bits) {
+    uint64_t h = 0;
+    for (int bit = bits - 1; bit >= 0; --bit)
+        for (int i = 2; i >= 0; --i) h = (h << 1) | ((X[i] >> bit) & 1u);
+    return h;
+}
+
+struct Quant {
+    double lo[3], scale[3];
+    int bits = 21;
+    // `count` points will be keyed: about 2^4 cells per point and axis resolve them
+    Quant(const std::vector<double> &xyz, int64_t N, int64_t count) {
+        bits = 4;
+        while (bits < 21 && ((int64_t)1 << (3 * (bits - 4))) < count) ++bits;
+        double hi[3];
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = INFINITY;
+            hi[d] = -INFINITY;
+        }
+        for (int64_t i = 0; i < N; ++i)
+            for (int d = 0; d < 3; ++d) {
+                lo[d] = std::min(lo[d], xyz[3 * i + d]);
+                hi[d] = std::max(hi[d], xyz[3 * i + d]);
+            }
+        double ext = 0;
+        for (int d = 0; d < 3; ++d) ext = std::max(ext, hi[d] - lo[d]);
+        for (int d = 0; d < 3; ++d) scale[d] = ext > 0 ? ((1u << bits) - 1) / ext : 0.0;
+    }
+    uint64_t key(double x, double y, double z, bool hilbert) const {
+        double v[3] = {x, y, z};
+        uint32_t X[3];
+        for (int d = 0; d < 3; ++d) {
+            double q = (v[d] - lo[d]) * scale[d];
+            X[d] = (uint32_t)std::min(std::max(q, 0.0), (double)((1u << bits) - 1));
+        }
+        return hilbert ? hilbert3(X, bits) : morton3(X, bits);
+    }
+};
+
+}  // namespace
+
+std::vector<int32_t> order_sfc(const Problem &p, bool hilbert) {
+    const int64_t N = p.N;
+    Quant qz(p.xyz, N, N);
+    std::vector<uint64_t> key(N);
+#pragma omp parallel for
+    for (int64_t i = 0; i < N; ++i) key[i] = qz.key(p.xyz[3 * i], p.xyz[3 * i + 1], p.xyz[3 * i + 2], hilbert);
+    std::vector<int32_t> idx = sort_by_key<int32_t>(key);
+    std::vector<int32_t> perm(N);
+    for (int64_t r = 0; r < N; ++r) perm[idx[r]] = (int32_t)r;
+    return perm;
+}
+
+// ---------------------------------------------------------------- layout
+namespace {
+
+// element order for a node ordering: SFC key of the centroid for curve
+// orderings, the smallest renumbered node otherwise
+std::vector<int64_t> element_order(const Problem &p, const std::vector<int32_t> &perm, int ordering) {
+    const int64_t E = p.E;
+    const int nen = p.nen;
+    if (ordering == FEM_ORDER_NONE) {
+        std::vector<int64_t> idx(E);
+        std::iota(idx.begin(), idx.end(), 0);
+        return idx;
+    }
+    std::vector<uint64_t> key(E);
+    if (ordering == FEM_ORDER_MORTON || ordering == FEM_ORDER_HILBERT) {
+        Quant qz(p.xyz, p.N, E);
+#pragma omp parallel for
+        for (int64_t e = 0; e < E; ++e) {
+            double c[3] = {0, 0, 0};
+            for (int a = 0; a < nen; ++a)
+                for (int d = 0; d < 3; ++d) c[d] += p.xyz[3 * (int64_t)p.conn[e * nen + a] + d];
+            key[e] = qz.key(c[0] / nen, c[1] / nen, c[2] / nen, ordering == FEM_ORDER_HILBERT);
+        }
+    } else {
+#pragma omp parallel for
+        for (int64_t e = 0; e < E; ++e) {
+            uint64_t lo = UINT64_MAX, hi = 0;
+            for (int a = 0; a < nen; ++a) {
+                uint64_t v = (uint64_t)perm[p.conn[e * nen + a]];
+                lo = std::min(lo, v);
+                hi = std::max(hi, v);
+            }
+            key[e] = (lo << 32) | hi;
+        }
+    }
+    return sort_by_key<int64_t>(key);
+}
+
+}  // namespace
+
+void prep_order(const Problem &p, const Base &b, int ordering, Ordering &ord) {
+    PhaseTimer tm;
+    if (ordering == FEM_ORDER_RCM) ord.perm = order_rcm(p, b);
+    else if (ordering == FEM_ORDER_MORTON) ord.perm = order_sfc(p, false);
+    else if (ordering == FEM_ORDER_HILBERT) ord.perm = order_sfc(p, true);
+    else if (ordering == FEM_ORDER_NONE) {
+        ord.perm.resize(p.N);
+        std::iota(ord.perm.begin(), ord.perm.end(), 0);
+    } else fail(FEM_E_INVALID_ARG, "unknown ordering");
+    tm.mark("node ordering");
+    ord.eorder = element_order(p, ord.perm, ordering);
+    tm.mark("element ordering");
+}
+
+void prep_layout(const Problem &p, const Base &b, const PrepOptions &o, const Ordering &ord, Layout &L) {
+    const int64_t N = p.N, E = p.E;
+    const int nen = p.nen;
+    L.nen = nen;
+    L.N = N;
+    L.E = E;
+    L.dt_bound = b.dt_bound;
+    // 1. locality ordering of nodes and elements
+    std::vector<int32_t> perm = ord.perm;
+    std::vector<int64_t> eorder = ord.eorder;
+
+    auto has_bc = [&](int64_t i) {
+        return b.robin_b[i] != 0.0 || b.robin_a[i] != 0.0 || b.lptr[i + 1] > b.lptr[i];
+    };
+
+    // 2. element blocks (LDS-blocked scatter) and the final node numbering
+    if (o.scatter == FEM_SCATTER_LDS_BLOCKED) {
+        if (o.max_local_nodes > 65535) fail(FEM_E_INVALID_ARG, "block node cap above 65535");
+        std::vector<int64_t> stamp(N, -1);
+        std::vector<std::pair<int64_t, int64_t>> blk;  // (first slot in eorder, count)
+        int64_t cur = 0, nloc = 0, start = 0;
+        for (int64_t s = 0; s < E; ++s) {
+            const int32_t *c = &p.conn[eorder[s] * nen];
+            int nnew = 0;
+            for (int a = 0; a < nen; ++a) nnew += stamp[c[a]] != cur;
+            int64_t cnt = s - start;
+            if (cnt > 0 && (cnt + 1 > o.block_elems || nloc + nnew > o.max_local_nodes)) {
+                blk.push_back({start, cnt});
+                ++cur;
+                start = s;
+                nloc = 0;
+                nnew = nen;
+                for (int a = 0; a < nen; ++a)
+                    for (int q = 0; q < a; ++q)
+                        if (c[q] == c[a]) --nnew;
+            }
+            for (int a = 0; a < nen; ++a) stamp[c[a]] = cur;
+            nloc += nnew;
+        }
+        if (E - start > 0) blk.push_back({start, E - start});
+        const int64_t nb = (int64_t)blk.size();
+        // blocks touching each node; owner block of private nodes
+        std::vector<int32_t> nblk(N, 0), owner(N, -1);
+        std::fill(stamp.begin(), stamp.end(), -1);
+        for (int64_t q = 0; q < nb; ++q)
+            for (int64_t s = blk[q].first; s < blk[q].first + blk[q].second; ++s)
+                for (int a = 0; a < nen; ++a) {
+                    int32_t n = p.conn[eorder[s] * nen + a];
+                    if (stamp[n] != q) {
+                        stamp[n] = q;
+                        nblk[n]++;
+                        if (owner[n] < 0) owner[n] = (int32_t)q;
+                    }
+                }
+        // private nodes grouped by owner block, in ordering rank within a block;
+        // shared nodes after them ordered by first block then rank
+        std::vector<int32_t> priv, shar;
+        for (int64_t i = 0; i < N; ++i) (nblk[i] == 1 && !has_bc(i) ? priv : shar).push_back((int32_t)i);
+        auto by_owner_rank = [&](std::vector<int32_t> &v) {
+            std::vector<uint64_t> key(v.size());
+            for (size_t r = 0; r < v.size(); ++r) key[r] = ((uint64_t)owner[v[r]] << 32) | (uint32_t)perm[v[r]];
+            std::vector<int64_t> o2 = sort_by_key<int64_t>(key);
+            std::vector<int32_t> out(v.size());
+            for (size_t r = 0; r < v.size(); ++r) out[r] = v[o2[r]];
+            v.swap(out);
+        };
+        by_owner_rank(priv);
+        by_owner_rank(shar);
+        L.n_private = (int64_t)priv.size();
+        std::vector<int32_t> fin(N);
+        for (size_t r = 0; r < priv.size(); ++r) fin[priv[r]] = (int32_t)r;
+        for (size_t r = 0; r < shar.size(); ++r) fin[shar[r]] = (int32_t)(priv.size() + r);
+        perm.swap(fin);
+        // per block: private range, shared list, local connectivity
+        std::vector<int64_t> priv_begin(nb + 1, 0);
+        for (int32_t n : priv) priv_begin[owner[n] + 1]++;
+        for (int64_t q = 0; q < nb; ++q) priv_begin[q + 1] += priv_begin[q];
+        L.blocks.resize(nb);
+        L.sh_list.clear();
+        L.lconn.resize(E * nen);
+        L.max_local = 0;
+        std::vector<int32_t> local(N, -1);
+        std::vector<int32_t> shl;
+        for (int64_t q = 0; q < nb; ++q) {
+            BlockInfo &bi = L.blocks[q];
+            bi.e_begin = (int32_t)blk[q].first;
+            bi.n_e = (int32_t)blk[q].second;
+            bi.int_base = (int32_t)priv_begin[q];
+            bi.n_int = (int32_t)(priv_begin[q + 1] - priv_begin[q]);
+            shl.clear();
+            for (int64_t s = blk[q].first; s < blk[q].first + blk[q].second; ++s)
+                for (int a = 0; a < nen; ++a) {
+                    int32_t n = p.conn[eorder[s] * nen + a];
+                    if (perm[n] >= L.n_private) shl.push_back(perm[n]);
+                }
+            std::sort(shl.begin(), shl.end());
+            shl.erase(std::unique(shl.begin(), shl.end()), shl.end());
+            bi.sh_begin = (int32_t)L.sh_list.size();
+            bi.n_sh = (int32_t)shl.size();
+            bi.pad0 = bi.pad1 = 0;
+            L.sh_list.insert(L.sh_list.end(), shl.begin(), shl.end());
+            for (size_t r = 0; r < shl.size(); ++r) local[shl[r]] = bi.n_int + (int32_t)r;
+            L.max_local = std::max<int64_t>(L.max_local, bi.n_int + bi.n_sh);
+            for (int64_t s = blk[q].first; s < blk[q].first + blk[q].second; ++s)
+                for (int a = 0; a < nen; ++a) {
+                    int32_t g = perm[p.conn[eorder[s] * nen + a]];
+                    int32_t l = g < L.n_private ? g - bi.int_base : local[g];
+                    if (l < 0 || l >= bi.n_int + bi.n_sh) fail(FEM_E_MESH, "internal: block numbering");
+                    L.lconn[s * nen + a] = (uint16_t)l;
+                }
+        }
+        if (L.max_local > o.max_local_nodes) fail(FEM_E_INVALID_ARG, "internal: block above node cap");
+        // combine lists: the partial slots of every shared node in block order
+        const int64_t nsh = N - L.n_private;
+        L.comb_ptr.assign(nsh + 1, 0);
+        for (int32_t g : L.sh_list) L.comb_ptr[g - L.n_private + 1]++;
+        for (int64_t s = 0; s < nsh; ++s) L.comb_ptr[s + 1] += L.comb_ptr[s];
+        L.comb_idx.resize(L.sh_list.size());
+        std::vector<int32_t> fill(L.comb_ptr.begin(), L.comb_ptr.end() - 1);
+        for (size_t slot = 0; slot < L.sh_list.size(); ++slot)
+            L.comb_idx[fill[L.sh_list[slot] - L.n_private]++] = (int32_t)slot;
+        L.bc_first = L.n_private;
+        L.n_bc_slots = nsh;
+        L.block_elems = o.block_elems;
+    } else {
+        L.bc_first = 0;
+        L.n_bc_slots = N;
+        L.n_private = 0;
+    }
+
+    // 3. colouring (colour by colour scatter): greedy first-fit in element order
+    if (o.scatter == FEM_SCATTER_COLORED) {
+        std::vector<uint64_t> used(2 * N, 0);
+        std::vector<int32_t> col(E);
+        int ncol = 0;
+        for (int64_t s = 0; s < E; ++s) {
+            const int32_t *c = &p.conn[eorder[s] * nen];
+            uint64_t f0 = 0, f1 = 0;
+            for (int a = 0; a < nen; ++a) {
+                f0 |= used[2 * c[a]];
+                f1 |= used[2 * c[a] + 1];
+            }
+            int k;
+            if (~f0) k = __builtin_ctzll(~f0);
+            else if (~f1) k = 64 + __builtin_ctzll(~f1);
+            else fail(FEM_E_UNSUPPORTED, "element colouring needs more than 128 colours");
+            col[s] = k;
+            ncol = std::max(ncol, k + 1);
+            for (int a = 0; a < nen; ++a) used[2 * c[a] + (k >> 6)] |= 1ull << (k & 63);
+        }
+        std::vector<uint64_t> ckey(col.begin(), col.end());
+        std::vector<int64_t> idx = sort_by_key<int64_t>(ckey);
+        std::vector<int64_t> e2(E);
+        for (int64_t s = 0; s < E; ++s) e2[s] = eorder[idx[s]];
+        eorder.swap(e2);
+        L.color_ptr.assign(ncol + 1, 0);
+        for (int64_t s = 0; s < E; ++s) L.color_ptr[col[s] + 1]++;
+        for (int c = 0; c < ncol; ++c) L.color_ptr[c + 1] += L.color_ptr[c];
+    }
+
+    // 4. arrays in the final numbering
+    L.perm = perm;
+    L.iperm.assign(N, 0);
+    for (int64_t i = 0; i < N; ++i) L.iperm[perm[i]] = (int32_t)i;
+    L.xyz.resize(3 * N);
+    L.nflag.resize(N);
+    L.m.resize(N);
+    L.T_init.resize(N);
+    for (int64_t n = 0; n < N; ++n) {
+        int64_t i = L.iperm[n];
+        for (int d = 0; d < 3; ++d) L.xyz[3 * n + d] = p.xyz[3 * i + d];
+        L.nflag[n] = (uint32_t)b.nmat[i] | (b.fixed[i] ? NODE_FIXED : 0u);
+        L.m[n] = b.m[i];
+        L.T_init[n] = b.T_init[i];
+    }
+    L.conn.resize(E * nen);
+    for (int64_t s = 0; s < E; ++s)
+        for (int a = 0; a < nen; ++a) L.conn[s * nen + a] = perm[p.conn[eorder[s] * nen + a]];
+    // boundary slots
+    L.robin_a.clear();
+    L.robin_b.clear();
+    if (b.any_robin) {
+        L.robin_a.resize(L.n_bc_slots);
+        L.robin_b.resize(L.n_bc_slots);
+    }
+    L.link_ptr.assign(L.n_bc_slots + 1, 0);
+    L.link_node.clear();
+    L.link_w.clear();
+    for (int64_t s = 0; s < L.n_bc_slots; ++s) {
+        int64_t i = L.iperm[L.bc_first + s];
+        if (b.any_robin) {
+            L.robin_a[s] = b.robin_a[i];
+            L.robin_b[s] = b.robin_b[i];
+        }
+        for (int32_t q = b.lptr[i]; q < b.lptr[i + 1]; ++q) {
+            L.link_node.push_back(perm[b.lnode[q]]);
+            L.link_w.push_back(b.lw[q]);
+        }
+        L.link_ptr[s + 1] = (int32_t)L.link_node.size();
+    }
+    // a private node never carries boundary terms
+    for (int64_t n = 0; n < L.n_private; ++n)
+        if (has_bc(L.iperm[n])) fail(FEM_E_MESH, "internal: boundary node classed private");
+    L.bw_before = bandwidth(p, b, nullptr);
+    L.bw_after = bandwidth(p, b, &L.perm);
+}
+
+}  // namespace castfem

@@ -1,0 +1,124 @@
+// Host preprocessing of the casting step: validation, lumping, boundary
+// aggregation, stability bound, locality reordering, colouring and the
+// LDS element blocks with private/shared node classes.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/castfem.h"
+
+namespace castfem {
+
+struct Problem {
+    int nen = 0;
+    int64_t N = 0, E = 0;
+    std::vector<double> xyz;
+    std::vector<int32_t> conn, emat;
+    std::vector<fem_material> mats;
+    std::vector<int32_t> dir_nodes;
+    std::vector<double> dir_T;
+    int npf = 3;
+    std::vector<int32_t> flux_faces;
+    std::vector<double> flux_q, flux_h, flux_Tinf;
+    std::vector<int32_t> if_a, if_b;
+    std::vector<double> if_h;
+    std::vector<double> T0;
+};
+
+// node flag bits stored next to the material id
+enum : uint32_t { NODE_FIXED = 1u << 31, NODE_MAT_MASK = 0xFFFFu };
+
+struct BlockInfo {        // one LDS element block (8 ints, 32 bytes)
+    int32_t e_begin;      // first element of the block (blocked element order)
+    int32_t n_e;          // elements in the block
+    int32_t int_base;     // first global id of its private nodes (contiguous)
+    int32_t n_int;        // private nodes: local ids 0..n_int-1
+    int32_t sh_begin;     // offset of its shared-node list (and partial slots)
+    int32_t n_sh;         // shared nodes: local ids n_int..n_int+n_sh-1
+    int32_t pad0, pad1;
+};
+
+struct Layout {
+    int nen = 0;
+    int64_t N = 0, E = 0;
+    // numbering: perm[original] = new id, iperm[new] = original
+    std::vector<int32_t> perm, iperm;
+    // nodes in new numbering
+    std::vector<double> xyz;          // N x 3
+    std::vector<uint32_t> nflag;      // material | NODE_FIXED
+    std::vector<double> m;            // lumped capacitance weights (kg)
+    std::vector<double> T_init;       // initial temperature after fixed values
+    // elements in new order, node ids in new numbering
+    std::vector<int32_t> conn;
+    // boundary terms per "bc slot" (all nodes, or shared nodes when blocked):
+    // r_i += robin_a - robin_b T_i + sum_k w_k (T_{j_k} - T_i)
+    int64_t bc_first = 0;             // node id of slot 0 (0, or the first shared node)
+    int64_t n_bc_slots = 0;
+    std::vector<double> robin_a, robin_b;  // per slot (empty if no flux faces)
+    std::vector<int32_t> link_ptr;    // per slot + 1
+    std::vector<int32_t> link_node;
+    std::vector<double> link_w;
+    // colouring
+    std::vector<int32_t> color_ptr;   // elements of colour c: [color_ptr[c], color_ptr[c+1])
+    // LDS blocks
+    std::vector<BlockInfo> blocks;
+    int64_t n_private = 0;            // nodes 0..n_private-1 are private to one block
+    std::vector<int32_t> sh_list;     // per block: global ids of its shared nodes
+    std::vector<uint16_t> lconn;      // per element: local ids in its block
+    std::vector<int32_t> comb_ptr;    // per shared node: partial slots
+    std::vector<int32_t> comb_idx;
+    int64_t max_local = 0;
+    // report
+    double dt_bound = 0;
+    int64_t bw_before = 0, bw_after = 0;
+    double setup_seconds = 0;
+    int64_t block_elems = 0;
+};
+
+struct PrepOptions {
+    int ordering = FEM_ORDER_HILBERT;
+    int scatter = FEM_SCATTER_LDS_BLOCKED;
+    int64_t block_elems = 8192;
+    int64_t max_local_nodes = 2600;
+};
+
+// Throws std::runtime_error with a message; the C interface maps it to a code.
+struct PrepError {
+    int code;
+    std::string msg;
+};
+
+// Validation, lumping, boundary aggregation and the stability bound; the parts
+// that do not depend on the ordering.  Fills per-node data in input numbering.
+struct Base {
+    std::vector<int32_t> nmat;        // material of every node
+    std::vector<double> m;            // lumped weights
+    std::vector<double> robin_a, robin_b;
+    std::vector<uint8_t> fixed;
+    std::vector<double> T_init;
+    // aggregated interface links in input numbering, CSR by node
+    std::vector<int32_t> lptr, lnode;
+    std::vector<double> lw;
+    double dt_bound = 0;
+    bool any_robin = false;
+};
+
+// node permutation (perm[original] = rank) and element order of a locality ordering
+struct Ordering {
+    std::vector<int32_t> perm;
+    std::vector<int64_t> eorder;
+};
+
+void prep_base(const Problem &p, Base &b);                                     // throws PrepError
+void prep_order(const Problem &p, const Base &b, int ordering, Ordering &ord);  // throws PrepError
+void prep_layout(const Problem &p, const Base &b, const PrepOptions &o, const Ordering &ord,
+                 Layout &L);                                                    // throws PrepError
+int64_t bandwidth(const Problem &p, const Base &b, const std::vector<int32_t> *perm);
+
+// orderings (exposed for testing through the C interface report)
+std::vector<int32_t> order_rcm(const Problem &p, const Base &b);
+std::vector<int32_t> order_sfc(const Problem &p, bool hilbert);
+
+}  // namespace castfem

@@ -1,0 +1,143 @@
+"""CPU-only checks of the C interface: exported symbols, argument and call-order
+errors, and the host preprocessing (lumping, stability bound, orderings,
+blocks, colours) that runs before any device call."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from castgen import configs
+from paper_1005_3158_amd import castfem as cf
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "castfem.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fem_[A-Za-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = header_functions()
+    assert len(names) >= 20
+    out = subprocess.check_output(["nm", "-D", "--defined-only", cf.LIB_PATH]).decode()
+    exported = set(re.findall(r"\bT (fem_\w+)", out))
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    assert sorted(cf.EXPORTS) == names
+    lib = cf.lib()
+    for n in names:
+        assert getattr(lib, n) is not None
+
+
+def test_library_carries_gfx950_code_only():
+    blob = open(cf.LIB_PATH, "rb").read()
+    assert b"amdgcn-amd-amdhsa--gfx950" in blob
+    assert b"amdgcn-amd-amdhsa--gfx906" not in blob
+
+
+def test_errors_and_call_order():
+    with pytest.raises(cf.FemError) as e:
+        cf.fem_create(cf.make_options(precision=7))
+    assert e.value.code == -1
+    ctx = cf.fem_create(None)
+    with pytest.raises(cf.FemError) as e:
+        cf.fem_finalize(ctx)
+    assert e.value.code == -3
+    with pytest.raises(cf.FemError) as e:
+        cf.fem_step(ctx, 0.1, 1)
+    assert e.value.code == -3
+    assert "not bound" in cf.fem_last_error()
+    p = configs.config2(n=4)
+    # node in two materials: glue a casting tet onto a mould node
+    bad = dict(p)
+    conn = p["conn"].copy()
+    cast = np.nonzero(p["elem_mat"] == 0)[0][0]
+    mould_node = p["conn"][np.nonzero(p["elem_mat"] == 1)[0][0], 0]
+    conn[cast, 0] = mould_node
+    bad["conn"] = conn
+    ctx2 = cf.fem_create(None)
+    with pytest.raises(cf.FemError) as e:
+        cf.setup_problem(ctx2, bad)
+    assert e.value.code == -2
+    # inverted element
+    inv = dict(p)
+    conn = p["conn"].copy()
+    conn[0, [1, 2]] = conn[0, [2, 1]]
+    inv["conn"] = conn
+    ctx3 = cf.fem_create(None)
+    with pytest.raises(cf.FemError) as e:
+        cf.setup_problem(ctx3, inv)
+    assert e.value.code == -2 and "inverted" in cf.fem_last_error()
+    # out-of-range node
+    oor = dict(p)
+    conn = p["conn"].copy()
+    conn[3, 2] = p["xyz"].shape[0]
+    oor["conn"] = conn
+    ctx4 = cf.fem_create(None)
+    with pytest.raises(cf.FemError) as e:
+        cf.setup_problem(ctx4, oor)
+    assert e.value.code == -2
+    # a failed finalize leaves the context usable
+    cf.setup_problem(ctx4, p)
+    for c in (ctx, ctx2, ctx3, ctx4):
+        cf.fem_destroy(c)
+
+
+def test_dt_bound_matches_oracle(orc):
+    for p in (configs.config1(), configs.config2(n=10), configs.config4_trajectory(5001, n=6)):
+        ctx = cf.fem_create(cf.make_options(scatter=cf.FEM_SCATTER_GLOBAL_ATOMIC))
+        rep = cf.setup_problem(ctx, p)
+        assert rep["dt_bound"] == pytest.approx(orc.stable_dt(p), rel=1e-12)
+        cf.fem_destroy(ctx)
+
+
+@pytest.mark.parametrize("ordering", [cf.FEM_ORDER_NONE, cf.FEM_ORDER_RCM, cf.FEM_ORDER_MORTON, cf.FEM_ORDER_HILBERT])
+def test_orderings_are_permutations_and_shrink_bandwidth(ordering):
+    p = configs.config2(n=16)
+    ctx = cf.fem_create(cf.make_options(ordering=ordering, scatter=cf.FEM_SCATTER_GLOBAL_ATOMIC))
+    rep = cf.setup_problem(ctx, p)
+    perm = cf.fem_get_node_perm(ctx, p["xyz"].shape[0])
+    assert np.array_equal(np.sort(perm), np.arange(perm.size))
+    if ordering == cf.FEM_ORDER_NONE:
+        assert np.array_equal(perm, np.arange(perm.size))
+        assert rep["bandwidth_after"] == rep["bandwidth_before"]
+    elif ordering == cf.FEM_ORDER_RCM:
+        # the random input numbering has bandwidth ~N; RCM brings it near a grid plane
+        assert rep["bandwidth_after"] < 0.1 * rep["bandwidth_before"]
+    else:
+        assert rep["bandwidth_after"] < rep["bandwidth_before"]
+    cf.fem_destroy(ctx)
+
+
+def test_blocks_and_colours_report():
+    p = configs.config2(n=16)
+    ctx = cf.fem_create(cf.make_options(scatter=cf.FEM_SCATTER_LDS_BLOCKED, lds_bytes=24 * 700, block_elems=4000))
+    rep = cf.setup_problem(ctx, p)
+    assert rep["max_local_nodes"] <= 700
+    assert rep["n_blocks"] >= p["conn"].shape[0] // 4000
+    assert 0 < rep["n_shared"] < p["xyz"].shape[0]
+    assert rep["n_partials"] >= rep["n_shared"]    # interface nodes may sit in one block
+    cf.fem_destroy(ctx)
+    ctx = cf.fem_create(cf.make_options(scatter=cf.FEM_SCATTER_COLORED))
+    rep = cf.setup_problem(ctx, p)
+    assert 24 <= rep["n_colors"] <= 64      # 24 Kuhn tets share an interior node
+    cf.fem_destroy(ctx)
+
+
+def test_buffer_query_shapes():
+    p = configs.config1()
+    ctx = cf.fem_create(cf.make_options(precision=cf.FEM_PREC_FP64, scatter=cf.FEM_SCATTER_GLOBAL_ATOMIC))
+    cf.setup_problem(ctx, p)
+    bufs = {n: (b, a) for n, b, a in cf.fem_query_buffers(ctx)}
+    N, E = p["xyz"].shape[0], p["conn"].shape[0]
+    assert bufs["node_x"][0] >= 32 * N and bufs["T"][0] >= 16 * N and bufs["conn"][0] >= 32 * E
+    assert all(a == 256 for b, a in bufs.values())
+    with pytest.raises(cf.FemError) as e:
+        cf.fem_bind_buffers(ctx, [0] * 3)
+    assert e.value.code == -1
+    cf.fem_destroy(ctx)

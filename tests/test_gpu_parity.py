@@ -1,0 +1,227 @@
+"""GPU parity: the HIP path through the C interface against the FP64 CPU oracle,
+element by element on the same seeded inputs.
+
+Tolerances (max over nodes):
+  FP64 GPU path: 1e-8 K (only the summation order differs from the oracle).
+  FP32 state with compensated enthalpy: 1e-3 K away from the solidification
+  front, 0.05 K in the front band (oracle T within 5 K of [T_sol, T_liq]);
+  fraction solid 1e-4 (1e-3 in the band).
+"""
+import numpy as np
+import pytest
+
+from castgen import configs
+
+pytestmark = pytest.mark.gpu
+
+CONFIG1_DT = 0.284765625          # 0.9 x h^2 / (2 alpha), the exact bound of the 16^3 hex cube
+SCATTERS = ["atomic", "lds", "colored"]
+TOL64 = 1e-8
+
+
+def _cf():
+    from paper_1005_3158_amd import castfem as cf
+    return cf
+
+
+def scatter_id(name):
+    cf = _cf()
+    return {"atomic": cf.FEM_SCATTER_GLOBAL_ATOMIC, "lds": cf.FEM_SCATTER_LDS_BLOCKED,
+            "colored": cf.FEM_SCATTER_COLORED}[name]
+
+
+def gpu_run(prob, dt, steps, **opts):
+    cf = _cf()
+    s = cf.Solver(prob, **opts)
+    try:
+        s.step(dt, steps)
+        return s.T(), s.fs(), s.H(), s.energy(), s.report
+    finally:
+        s.close()
+
+
+def band_mask(T_ref, mats=configs.ALLOY):
+    return (T_ref >= mats[3] - 5.0) & (T_ref <= mats[4] + 5.0)
+
+
+def check_fp32(T, fs, T_ref, fs_ref, what):
+    band = band_mask(T_ref)
+    err = np.abs(T - T_ref)
+    e_out = float(np.max(err[~band])) if np.any(~band) else 0.0
+    e_band = float(np.max(err[band])) if np.any(band) else 0.0
+    print("%s: max|dT| off-front %.3e K, front band %.3e K (%d nodes), rms %.3e" %
+          (what, e_out, e_band, int(band.sum()), float(np.sqrt(np.mean(err ** 2)))), flush=True)
+    assert e_out <= 1e-3, what
+    assert e_band <= 0.05, what
+    ef = np.abs(fs - fs_ref)
+    assert float(np.max(ef[~band])) <= 1e-4 if np.any(~band) else True
+    assert float(np.max(ef)) <= 1e-3
+
+
+@pytest.fixture(scope="module")
+def c1_ref(orc):
+    p = configs.config1()
+    H, T, fs, D = orc.run(p, CONFIG1_DT, 200, diag=True)
+    return p, T, fs, H, D
+
+
+@pytest.mark.parametrize("scatter", SCATTERS)
+def test_config1_fp64(c1_ref, scatter, orc):
+    cf = _cf()
+    p, T_ref, fs_ref, H_ref, D = c1_ref
+    # the exact bound of this mesh (0.3164 s) lies above the Gershgorin bound (0.2373 s) the library enforces
+    T, fs, H, en, rep = gpu_run(p, CONFIG1_DT, 200, precision=cf.FEM_PREC_FP64, scatter=scatter_id(scatter),
+                                block_elems=512, allow_unstable=True)
+    err = float(np.max(np.abs(T - T_ref)))
+    print("config1 fp64 %s: max|dT| = %.3e K" % (scatter, err), flush=True)
+    assert err <= TOL64
+    assert float(np.max(np.abs(fs - fs_ref))) <= 1e-10
+    assert float(np.max(np.abs(H - H_ref))) <= 1e-8 * 1e6
+    assert en["E"] == pytest.approx(D[-1, orc.D_E], rel=1e-12)
+    assert en["Q_cum"] == pytest.approx(D[-1, orc.D_QCUM], rel=1e-9)
+    assert en["residual"] <= 1e-11
+    assert en["n_liquid"] == int(D[-1, orc.D_NLIQ])
+
+
+@pytest.fixture(scope="module")
+def tet12_ref(orc):
+    p = configs.config2(n=12)
+    dt = 0.9 * orc.stable_dt(p)
+    H, T, fs, D = orc.run(p, dt, 300, diag=True)
+    return p, dt, T, fs, H, D
+
+
+@pytest.mark.parametrize("scatter", SCATTERS)
+@pytest.mark.parametrize("ordering", ["none", "rcm", "hilbert"])
+def test_tet_fp64(tet12_ref, scatter, ordering, orc):
+    cf = _cf()
+    p, dt, T_ref, fs_ref, H_ref, D = tet12_ref
+    order = {"none": cf.FEM_ORDER_NONE, "rcm": cf.FEM_ORDER_RCM, "hilbert": cf.FEM_ORDER_HILBERT}[ordering]
+    T, fs, H, en, rep = gpu_run(p, dt, 300, precision=cf.FEM_PREC_FP64, scatter=scatter_id(scatter), ordering=order,
+                                lds_bytes=44 * 600)
+    err = float(np.max(np.abs(T - T_ref)))
+    print("tet12 fp64 %s/%s: max|dT| = %.3e K blocks=%d" % (scatter, ordering, err, rep["n_blocks"]), flush=True)
+    assert err <= TOL64
+    assert float(np.max(np.abs(fs - fs_ref))) <= 1e-10
+    assert en["E"] == pytest.approx(D[-1, orc.D_E], rel=1e-12)
+    assert en["residual"] <= 1e-11
+
+
+@pytest.fixture(scope="module")
+def tet16_ref(orc):
+    p = configs.config2(n=16)
+    dt = 0.9 * orc.stable_dt(p)
+    H, T, fs, D = orc.run(p, dt, 2000, diag=True)
+    return p, dt, T, fs, H, D
+
+
+@pytest.mark.parametrize("scatter,ordering", [("lds", "hilbert"), ("lds", "morton"), ("lds", "rcm"),
+                                              ("atomic", "none"), ("atomic", "hilbert"), ("colored", "rcm")])
+def test_tet_fp32_kahan_2000_steps(tet16_ref, scatter, ordering, orc):
+    cf = _cf()
+    p, dt, T_ref, fs_ref, H_ref, D = tet16_ref
+    order = {"none": cf.FEM_ORDER_NONE, "rcm": cf.FEM_ORDER_RCM, "morton": cf.FEM_ORDER_MORTON,
+             "hilbert": cf.FEM_ORDER_HILBERT}[ordering]
+    T, fs, H, en, rep = gpu_run(p, dt, 2000, precision=cf.FEM_PREC_FP32_KAHAN, scatter=scatter_id(scatter),
+                                ordering=order)
+    check_fp32(T, fs, T_ref, fs_ref, "tet16 fp32 %s/%s" % (scatter, ordering))
+    assert en["E"] == pytest.approx(D[-1, orc.D_E], rel=1e-6)
+    assert en["residual"] <= 1e-5
+    assert en["n_liquid"] == pytest.approx(D[-1, orc.D_NLIQ], abs=3)
+
+
+def test_many_small_blocks_with_ragged_tail(tet12_ref):
+    """A tiny LDS budget gives many blocks, most nodes shared, and a short last block."""
+    cf = _cf()
+    p, dt, T_ref, fs_ref, H_ref, D = tet12_ref
+    T, fs, H, en, rep = gpu_run(p, dt, 300, precision=cf.FEM_PREC_FP64, scatter=cf.FEM_SCATTER_LDS_BLOCKED,
+                                lds_bytes=44 * 90, block_elems=333)
+    assert rep["n_blocks"] > 30 and rep["shared_fraction"] > 0.5
+    assert p["conn"].shape[0] % 333 != 0
+    assert float(np.max(np.abs(T - T_ref))) <= TOL64
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_convective_chill_hex(prec, orc):
+    cf = _cf()
+    p = configs.config4_trajectory(5003, n=10)
+    dt = 0.9 * orc.stable_dt(p)
+    H_ref, T_ref, fs_ref = orc.run(p, dt, 400)
+    pr = cf.FEM_PREC_FP64 if prec == "fp64" else cf.FEM_PREC_FP32_KAHAN
+    T, fs, H, en, rep = gpu_run(p, dt, 400, precision=pr, scatter=cf.FEM_SCATTER_LDS_BLOCKED, lds_bytes=44 * 300)
+    if prec == "fp64":
+        assert float(np.max(np.abs(T - T_ref))) <= TOL64
+    else:
+        check_fp32(T, fs, T_ref, fs_ref, "chill hex fp32")
+    assert en["Q_cum"] < 0 and en["residual"] <= (1e-11 if prec == "fp64" else 1e-5)
+
+
+def test_single_element_and_isothermal(orc):
+    """One hexahedron with an isothermal change, cooled through one face, stopped on the plateau."""
+    cf = _cf()
+    iso = (150.0, 2700.0, 900.0, 660.0, 660.0, 3.9e5)
+    p = configs.hex_cube(n=1, T_pour=661.0, noise_amp=0.0, dirichlet_x0=None, robin_x0=(2000.0, 25.0), material=iso)
+    dt = 0.05 * orc.stable_dt(p)
+    steps = 0
+    H = None
+    while True:                          # advance the oracle until the chilled face is partly solid
+        H, T_ref, fs_ref = orc.run(p, dt, 1, H=H)
+        steps += 1
+        if np.max(fs_ref) > 0.3:
+            break
+        assert steps < 100000
+    assert np.any((fs_ref > 0.0) & (fs_ref < 1.0) & (T_ref == 660.0))
+    for scatter in SCATTERS:
+        T, fs, H_gpu, en, rep = gpu_run(p, dt, steps, precision=cf.FEM_PREC_FP64, scatter=scatter_id(scatter))
+        assert float(np.max(np.abs(T - T_ref))) <= TOL64
+        assert float(np.max(np.abs(fs - fs_ref))) <= 1e-10
+
+
+def test_checkpoint_roundtrip_is_bitwise():
+    cf = _cf()
+    p = configs.config2(n=10)
+    opts = dict(precision=cf.FEM_PREC_FP64, scatter=cf.FEM_SCATTER_COLORED)
+    a = cf.Solver(p, **opts)
+    dt = 0.9 * a.stable_dt()
+    a.step(dt, 37)
+    ck = cf.fem_read_state(a.ctx)
+    a.step(dt, 63)
+    Ta, Ha = a.T(), a.H()
+    a.close()
+    b = cf.Solver(p, **opts)
+    cf.fem_write_state(b.ctx, ck)
+    b.step(dt, 63)
+    assert np.array_equal(b.T(), Ta) and np.array_equal(b.H(), Ha)
+    assert b.energy()["steps"] == 100
+    b.close()
+
+
+def test_graph_and_eager_steps_agree():
+    cf = _cf()
+    p = configs.config2(n=10)
+    opts = dict(precision=cf.FEM_PREC_FP64, scatter=cf.FEM_SCATTER_COLORED)
+    a = cf.Solver(p, **opts)
+    dt = 0.9 * a.stable_dt()
+    a.step(dt, 48)                       # 3 captured 16-step graphs
+    b = cf.Solver(p, **opts)
+    cf.fem_time_kernels(b.ctx, dt, 48)   # 48 eager launches with timing events
+    assert np.array_equal(a.T(), b.T())
+    a.close()
+    b.close()
+
+
+def test_unstable_dt_is_refused_and_blowup_is_detected():
+    cf = _cf()
+    p = configs.config2(n=6)
+    s = cf.Solver(p, scatter=cf.FEM_SCATTER_GLOBAL_ATOMIC)
+    bound = s.stable_dt()
+    with pytest.raises(cf.FemError) as e:
+        s.step(1.01 * bound, 1)
+    assert e.value.code == -4
+    s.close()
+    u = cf.Solver(p, scatter=cf.FEM_SCATTER_GLOBAL_ATOMIC, allow_unstable=True)
+    u.step(50.0 * bound, 400)
+    with pytest.raises(cf.FemError) as e:
+        u.energy()
+    assert e.value.code == -5
+    u.close()
