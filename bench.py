@@ -86,7 +86,7 @@ def main():
                 "hilbert": cf.FEM_ORDER_HILBERT}[args.ordering]
     opts = dict(precision=cf.FEM_PREC_FP32_KAHAN, scatter=scatter, ordering=ordering)
     if args.block_nodes:
-        opts["lds_bytes"] = 24 * args.block_nodes
+        opts["lds_bytes"] = cf.lds_for_nodes(args.block_nodes)
     t0 = time.time()
     s = cf.Solver(prob, **opts)
     t_setup = time.time() - t0
@@ -138,7 +138,7 @@ def main():
     if args.cpu_steps > 0:
         from oracle import oracle
         k = args.cpu_steps
-        s2 = cf.Solver(prob, **dict(opts, lds_bytes=24 * rep["max_local_nodes"]) if scatter == cf.FEM_SCATTER_LDS_BLOCKED else opts)
+        s2 = cf.Solver(prob, **dict(opts, lds_bytes=cf.lds_for_nodes(rep["max_local_nodes"])) if scatter == cf.FEM_SCATTER_LDS_BLOCKED else opts)
         s2.step(dt, k)
         T_gpu = s2.T()
         s2.close()

@@ -19,6 +19,13 @@ FEM_TET4, FEM_HEX8 = 4, 8
 FEM_PREC_FP64, FEM_PREC_FP32_KAHAN = 0, 1
 FEM_ORDER_NONE, FEM_ORDER_RCM, FEM_ORDER_MORTON, FEM_ORDER_HILBERT = 0, 1, 2, 3
 FEM_SCATTER_GLOBAL_ATOMIC, FEM_SCATTER_LDS_BLOCKED, FEM_SCATTER_COLORED = 0, 1, 2
+# LDS bytes per block-local node of the blocked element kernel, by precision
+LDS_PER_NODE = {FEM_PREC_FP64: 52, FEM_PREC_FP32_KAHAN: 32}
+
+
+def lds_for_nodes(nodes, precision=FEM_PREC_FP32_KAHAN):
+    """lds_bytes option that caps an LDS block at `nodes` local nodes."""
+    return LDS_PER_NODE[precision] * int(nodes)
 
 EXPORTS = [
     "fem_create", "fem_destroy", "fem_last_error", "fem_set_stream", "fem_upload_mesh", "fem_set_materials",

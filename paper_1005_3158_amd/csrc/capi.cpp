@@ -33,11 +33,11 @@ enum Stage { ST_NEW = 0, ST_FINAL = 1, ST_BOUND = 2 };
 
 enum Buf {
     B_NODE_X, B_T, B_H, B_INV_M, B_FS, B_MATS, B_CONN, B_R, B_LCONN, B_BLOCKS, B_SH_LIST, B_PARTIALS,
-    B_COMB_PTR, B_COMB_IDX, B_ROBIN, B_LINK_PTR, B_LINK_NODE, B_LINK_W, B_DIAG, B_CUMQ, B_COUNT
+    B_COMB_PTR, B_SH_POS, B_ROBIN, B_LINK_PTR, B_LINK_NODE, B_LINK_W, B_DIAG, B_CUMQ, B_FLAGS, B_COUNT
 };
 const char *BUF_NAMES[B_COUNT] = {"node_x", "T", "H", "inv_m", "fs", "mats", "conn", "r", "lconn", "blocks",
-                                  "sh_list", "partials", "comb_ptr", "comb_idx", "robin", "link_ptr",
-                                  "link_node", "link_w", "diag", "cumQ"};
+                                  "sh_list", "partials", "comb_ptr", "sh_pos", "robin", "link_ptr",
+                                  "link_node", "link_w", "diag", "cumQ", "flags"};
 constexpr int64_t ALIGN = 256;
 constexpr int GRAPH_STEPS = 16;  // steps per captured graph (even: both parities)
 constexpr size_t MAX_BLOCK_LDS = 160 * 1024 - 2048;  // gfx950 LDS per workgroup, less static use
@@ -145,7 +145,7 @@ void layout_sizes(const fem_ctx *c, const Layout &L, int64_t *sz) {
         sz[B_SH_LIST] = np * 4;
         sz[B_PARTIALS] = np * R;
         sz[B_COMB_PTR] = (N - L.n_private + 1) * 4;
-        sz[B_COMB_IDX] = np * 4;
+        sz[B_SH_POS] = np * 4;
     }
     sz[B_ROBIN] = (int64_t)L.robin_a.size() * 2 * R;
     sz[B_LINK_PTR] = (L.n_bc_slots + 1) * 4;
@@ -154,6 +154,7 @@ void layout_sizes(const fem_ctx *c, const Layout &L, int64_t *sz) {
     const int64_t slots = (blocked ? (int64_t)L.blocks.size() : 0) + node_grid(blocked ? N - L.n_private : N);
     sz[B_DIAG] = slots * NDIAG * 8;
     sz[B_CUMQ] = slots * 8;
+    sz[B_FLAGS] = N * 4;
 }
 
 template <class T>
@@ -221,6 +222,7 @@ void upload_layout_t(fem_ctx *c, const Layout &L) {
     h2d(c, B_H, H.data(), N * 8);
     h2d(c, B_T, T2.data(), 2 * N * (int64_t)sizeof(R));
     h2d(c, B_FS, fs.data(), N * (int64_t)sizeof(R));
+    h2d(c, B_FLAGS, L.nflag.data(), N * 4);
     std::vector<R> rob(L.robin_a.size() * 2), lw(L.link_w.size());
     for (size_t s = 0; s < L.robin_a.size(); ++s) {
         rob[2 * s] = (R)L.robin_a[s];
@@ -236,7 +238,7 @@ void upload_layout_t(fem_ctx *c, const Layout &L) {
         h2d(c, B_BLOCKS, L.blocks.data(), (int64_t)L.blocks.size() * (int64_t)sizeof(BlockInfo));
         h2d(c, B_SH_LIST, L.sh_list.data(), (int64_t)L.sh_list.size() * 4);
         h2d(c, B_COMB_PTR, L.comb_ptr.data(), (int64_t)L.comb_ptr.size() * 4);
-        h2d(c, B_COMB_IDX, L.comb_idx.data(), (int64_t)L.comb_idx.size() * 4);
+        h2d(c, B_SH_POS, L.sh_pos.data(), (int64_t)L.sh_pos.size() * 4);
     } else {
         h2d(c, B_CONN, L.conn.data(), (int64_t)L.conn.size() * 4);
         HIPCHECK(hipMemsetAsync(c->ptr[B_R], 0, N * sizeof(R), c->stream));
@@ -270,7 +272,8 @@ void fill_dev(fem_ctx *c, const Candidate &cd) {
     d.sh_list = (const int32_t *)c->ptr[B_SH_LIST];
     d.partials = c->ptr[B_PARTIALS];
     d.comb_ptr = (const int32_t *)c->ptr[B_COMB_PTR];
-    d.comb_idx = (const int32_t *)c->ptr[B_COMB_IDX];
+    d.sh_pos = (const int32_t *)c->ptr[B_SH_POS];
+    d.flags = (const uint32_t *)c->ptr[B_FLAGS];
     d.robin = L.robin_a.empty() ? nullptr : c->ptr[B_ROBIN];
     d.link_ptr = (const int32_t *)c->ptr[B_LINK_PTR];
     d.link_node = (const int32_t *)c->ptr[B_LINK_NODE];
@@ -285,6 +288,16 @@ void fill_dev(fem_ctx *c, const Candidate &cd) {
     d.lds_bytes = (size_t)L.max_local * lds_per_node(d.prec);
     d.n_colors = L.color_ptr.empty() ? 0 : (int)L.color_ptr.size() - 1;
     d.color_ptr_host = L.color_ptr.empty() ? nullptr : L.color_ptr.data();
+    // fixed-point scale: a node's element sum is bounded by
+    // sum_e sum_j |K^e_ij| times the temperature span; with a margin of 16 on
+    // the span every partial sum stays below 2^50
+    {
+        const double bound = 16.0 * std::max(c->base.elem_abs_max, 1e-300) * c->base.T_span;
+        const int S = std::min(80, (int)std::floor(std::log2(std::ldexp(1.0, 50) / bound)));
+        d.fx_scale = std::ldexp(1.0, S);
+        d.fx_inv = std::ldexp(1.0, -S);
+        d.fx_limit = (float)std::ldexp(1.0, 50 - S);
+    }
     const bool blocked = d.scatter == FEM_SCATTER_LDS_BLOCKED;
     d.diag_k1 = blocked ? d.n_blocks : 0;
     d.diag_k2 = node_grid(blocked ? d.N - d.n_private : d.N);

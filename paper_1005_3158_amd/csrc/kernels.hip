@@ -21,6 +21,7 @@
 #include "kernels.hpp"
 
 #include <cfloat>
+#include <type_traits>
 
 #include "elem.hpp"
 
@@ -249,53 +250,77 @@ __global__ __launch_bounds__(256) void k_elems(Dev d, int parity, int64_t e0, in
     }
 }
 
+// Fixed-point residual accumulation (FP32 state).  LDS floating-point atomic
+// adds are slow on gfx950 while 64-bit integer adds run at close to full LDS
+// rate, so each element contribution r is rounded to the integer q = r * 2^S
+// (|q| < 2^51, scale chosen on the host from a bound on every node's element
+// sums) and added with an integer atomic.  Integer sums do not depend on the
+// order of the additions, so the blocked path is bitwise reproducible, and
+// the four contributions of an element sum to exactly zero.
+struct Fixed {
+    // round(r * scale) as a two's-complement integer: adding 1.5 * 2^52 puts
+    // the rounded value in the low mantissa bits of the double
+    static __device__ __forceinline__ long long from(float r, double scale) {
+        const double magic = 6755399441055744.0;  // 1.5 * 2^52
+        const double x = __builtin_fma((double)r, scale, magic);
+        return __double_as_longlong(x) - __double_as_longlong(magic);
+    }
+    static __device__ __forceinline__ float to(long long q, double inv_scale) {
+        return (float)((double)q * inv_scale);
+    }
+};
+
 // element phase of the blocked layout, one workgroup per element block
 template <class R, int NEN>
 __global__ __launch_bounds__(1024) void k_block(Dev d, int parity) {
     using V4 = typename VT<R>::V4;
+    using LC = typename std::conditional<NEN == 4, uint2, uint4>::type;
+    // FP32: 64-bit fixed-point accumulators; FP64: double accumulators
+    using ACC = typename std::conditional<std::is_same<R, float>::value, long long, double>::type;
     extern __shared__ __attribute__((aligned(32))) unsigned char smem[];
+    __shared__ int s_bad;
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const BlockInfo bi = d.blocks[b];
     const int nloc = bi.n_int + bi.n_sh;
-    V4 *s_x = (V4 *)smem;
-    R *s_r = (R *)(s_x + nloc);
-    uint32_t *s_f = (uint32_t *)(s_r + nloc);
+    V4 *s_x = (V4 *)smem;                       // x, y, z, T per local node
+    ACC *s_acc = (ACC *)(s_x + nloc);           // residual accumulator
+    R *s_k = (R *)(s_acc + nloc);               // conductivity of the node's material
+    uint32_t *s_f = (uint32_t *)(s_k + nloc);   // material | flags
     const V4 *X = (const V4 *)d.node_x;
     const R *Tc = (const R *)d.T + parity * d.N;
     R *Tn = (R *)d.T + (1 - parity) * d.N;
+    if (threadIdx.x == 0) s_bad = 0;
 
     // gather: private nodes are a contiguous range, shared nodes a list
-    for (int l = threadIdx.x; l < bi.n_int; l += blockDim.x) {
-        const int64_t g = (int64_t)bi.int_base + l;
+    for (int l = threadIdx.x; l < nloc; l += blockDim.x) {
+        const int64_t g = l < bi.n_int ? (int64_t)bi.int_base + l : (int64_t)d.sh_list[bi.sh_begin + (l - bi.n_int)];
         V4 x = X[g];
-        s_f[l] = flag_bits(x.w);
+        const uint32_t f = flag_bits(x.w);
+        s_f[l] = f;
+        s_k[l] = mat_k(d.mats[f & NODE_MAT_MASK], R(0));
         x.w = Tc[g];
         s_x[l] = x;
-        s_r[l] = R(0);
-    }
-    for (int l = threadIdx.x; l < bi.n_sh; l += blockDim.x) {
-        const int64_t g = d.sh_list[bi.sh_begin + l];
-        V4 x = X[g];
-        s_f[bi.n_int + l] = flag_bits(x.w);
-        x.w = Tc[g];
-        s_x[bi.n_int + l] = x;
-        s_r[bi.n_int + l] = R(0);
+        s_acc[l] = ACC(0);
     }
     __syncthreads();
 
-    // element residuals accumulated in LDS
-    const uint16_t *lc = d.lconn + (int64_t)bi.e_begin * NEN;
+    // element residuals accumulated in LDS; the next element's connectivity
+    // is loaded one iteration ahead
+    const LC *lc = (const LC *)(d.lconn + (int64_t)bi.e_begin * NEN);
+    LC cur{};
+    if ((int)threadIdx.x < bi.n_e) cur = lc[threadIdx.x];
+    bool bad = false;
     for (int e = threadIdx.x; e < bi.n_e; e += blockDim.x) {
+        LC nxt{};
+        if (e + (int)blockDim.x < bi.n_e) nxt = lc[e + blockDim.x];
         int l[NEN];
-        if (NEN == 4) {
-            const uint2 c = ((const uint2 *)lc)[e];
-            l[0] = c.x & 0xFFFF;
-            l[1] = c.x >> 16;
-            l[2] = c.y & 0xFFFF;
-            l[3] = c.y >> 16;
+        if constexpr (NEN == 4) {
+            l[0] = cur.x & 0xFFFF;
+            l[1] = cur.x >> 16;
+            l[2] = cur.y & 0xFFFF;
+            l[3] = cur.y >> 16;
         } else {
-            const uint4 c = ((const uint4 *)lc)[e];
-            const uint32_t w[4] = {c.x, c.y, c.z, c.w};
+            const uint32_t w[4] = {cur.x, cur.y, cur.z, cur.w};
             for (int a = 0; a < 4; ++a) {
                 l[2 * a] = w[a] & 0xFFFF;
                 l[2 * a + 1] = w[a] >> 16;
@@ -303,31 +328,52 @@ __global__ __launch_bounds__(1024) void k_block(Dev d, int parity) {
         }
         V4 p[NEN];
         for (int a = 0; a < NEN; ++a) p[a] = s_x[l[a]];
-        const R k = mat_k(d.mats[s_f[l[0]] & NODE_MAT_MASK], R(0));
+        const R k = s_k[l[0]];
         R re[NEN];
         Elem<R, NEN>::residual(p, k, re);
-        for (int a = 0; a < NEN; ++a) atomicAdd(&s_r[l[a]], re[a]);
+        if constexpr (std::is_same<R, float>::value) {
+            long long q[NEN];
+            long long sum = 0;
+            for (int a = 1; a < NEN; ++a) {
+                bad |= !(fabsf(re[a]) < d.fx_limit);   // also catches NaN
+                q[a] = Fixed::from(re[a], d.fx_scale);
+                sum += q[a];
+            }
+            q[0] = -sum;
+            for (int a = 0; a < NEN; ++a)
+                atomicAdd((unsigned long long *)&s_acc[l[a]], (unsigned long long)q[a]);
+        } else {
+            for (int a = 0; a < NEN; ++a) atomicAdd(&s_acc[l[a]], re[a]);
+        }
+        cur = nxt;
     }
+    if (bad) s_bad = 1;
     __syncthreads();
 
-    // private nodes are complete: update them in place
+    // private nodes are complete: update them in place; a contribution outside
+    // the fixed-point range poisons the block so the run reports non-finite
+    const bool poison = s_bad != 0;
+    auto resid = [&](int l) -> R {
+        R r;
+        if constexpr (std::is_same<R, float>::value) r = Fixed::to(s_acc[l], d.fx_inv);
+        else r = s_acc[l];
+        return poison ? R(NAN) : r;
+    };
     DiagAcc acc;
     acc.init();
-    for (int l = threadIdx.x; l < bi.n_int; l += blockDim.x) {
-        const uint32_t f = s_f[l];
-        Node<R>::update(d, (int64_t)bi.int_base + l, s_r[l], f, s_x[l].w, Tn, 0.0, acc);
-    }
+    for (int l = threadIdx.x; l < bi.n_int; l += blockDim.x)
+        Node<R>::update(d, (int64_t)bi.int_base + l, resid(l), s_f[l], s_x[l].w, Tn, 0.0, acc);
     // one partial per shared node
     R *P = (R *)d.partials;
-    for (int l = threadIdx.x; l < bi.n_sh; l += blockDim.x) P[bi.sh_begin + l] = s_r[bi.n_int + l];
+    for (int l = threadIdx.x; l < bi.n_sh; l += blockDim.x) P[d.sh_pos[bi.sh_begin + l]] = resid(bi.n_int + l);
     reduce_diag(d, acc, b);
 }
 
 // node phase: all nodes (COMBINE = false: residual from r[N], which is reset)
-// or the shared nodes of the blocked layout (COMBINE = true: sum of partials)
+// or the shared nodes of the blocked layout (COMBINE = true: sum of the
+// node's contiguous partials, in block order)
 template <class R, bool COMBINE>
 __global__ __launch_bounds__(NODE_THREADS) void k_nodes(Dev d, int parity) {
-    using V4 = typename VT<R>::V4;
     const int64_t count = COMBINE ? d.N - d.n_private : d.N;
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     DiagAcc acc;
@@ -336,19 +382,23 @@ __global__ __launch_bounds__(NODE_THREADS) void k_nodes(Dev d, int parity) {
         const int64_t g = d.bc_first + s;
         const R *Tc = (const R *)d.T + parity * d.N;
         R *Tn = (R *)d.T + (1 - parity) * d.N;
+        const uint32_t f = d.flags[g];
         R r;
         if (COMBINE) {
             const R *P = (const R *)d.partials;
             r = R(0);
-            for (int32_t k = d.comb_ptr[s]; k < d.comb_ptr[s + 1]; ++k) r += P[d.comb_idx[k]];
+            for (int32_t k = d.comb_ptr[s]; k < d.comb_ptr[s + 1]; ++k) r += P[k];
         } else {
             R *rr = (R *)d.r;
             r = rr[g];
             rr[g] = R(0);
         }
-        const uint32_t f = flag_bits(((const V4 *)d.node_x)[g].w);
-        const R Ti = Tc[g];
-        const double q = boundary_terms<R>(d, s, Ti, Tc, r);
+        double q = 0.0;
+        R Ti = R(0);
+        if (f & (NODE_FIXED | NODE_BC)) {
+            Ti = Tc[g];
+            if (f & NODE_BC) q = boundary_terms<R>(d, s, Ti, Tc, r);
+        }
         Node<R>::update(d, g, r, f, Ti, Tn, q, acc);
     }
     reduce_diag(d, acc, d.diag_k1 + blockIdx.x);

@@ -39,7 +39,8 @@ struct Dev {
     const BlockInfo *blocks = nullptr;
     const int32_t *sh_list = nullptr;
     void *partials = nullptr;           // R per (block, shared node)
-    const int32_t *comb_ptr = nullptr, *comb_idx = nullptr;
+    const int32_t *comb_ptr = nullptr, *sh_pos = nullptr;
+    const uint32_t *flags = nullptr;    // material | flag bits per node
     // boundary slots
     const void *robin = nullptr;        // R2 (a, b) per slot or null
     const int32_t *link_ptr = nullptr, *link_node = nullptr;
@@ -53,6 +54,8 @@ struct Dev {
     size_t lds_bytes = 0;
     int n_colors = 0;
     const int32_t *color_ptr_host = nullptr;
+    double fx_scale = 1.0, fx_inv = 1.0; // FP32 blocked path: fixed-point scale 2^S and 2^-S
+    float fx_limit = 0.0f;              // largest element contribution that fits (|r| * 2^S < 2^50)
     int64_t diag_k1 = 0;                // diagnostics slots of the element kernel
     int64_t diag_k2 = 0;                // diagnostics slots of the node kernel
 };
@@ -62,7 +65,7 @@ constexpr int NODE_THREADS = 256;
 inline int64_t node_grid(int64_t n) { return (n + NODE_THREADS - 1) / NODE_THREADS; }
 
 // LDS bytes per local node of the blocked kernel
-inline size_t lds_per_node(int prec) { return prec == FEM_PREC_FP64 ? 44 : 24; }
+inline size_t lds_per_node(int prec) { return prec == FEM_PREC_FP64 ? 52 : 32; }
 
 // Enqueue one explicit step reading T buffer `parity` and writing 1 - parity.
 // If ev is not null, ev[0..1] bracket the element kernel(s) and ev[2..3] the

@@ -120,6 +120,7 @@ void prep_base(const Problem &p, Base &b) {
     const int nen = p.nen;
     const int64_t N = p.N, E = p.E;
     PhaseTimer tm;
+    b.elem_abs_max = 0.0;
     // node materials
     b.nmat.assign(N, -1);
     for (int64_t e = 0; e < E; ++e) {
@@ -227,12 +228,13 @@ void prep_base(const Problem &p, Base &b) {
     {
         std::vector<int32_t> cols;
         std::vector<double> vals;
-        double lam_t = 0.0;
+        double lam_t = 0.0, eabs_t = 0.0;
 #pragma omp for schedule(dynamic, 4096)
         for (int64_t i = 0; i < N; ++i) {
             cols.clear();
             vals.clear();
             double Ke[8][8];
+            double eabs = 0.0;  // sum over elements of sum_j |K^e_ij|
             for (int64_t s = ptr[i]; s < ptr[i + 1]; ++s) {
                 int64_t e = inc[s] / nen;
                 int a = (int)(inc[s] % nen);
@@ -246,8 +248,10 @@ void prep_base(const Problem &p, Base &b) {
                         vals.push_back(0.0);
                     }
                     vals[q] += Ke[a][c];
+                    eabs += std::fabs(Ke[a][c]);
                 }
             }
+            if (eabs > eabs_t) eabs_t = eabs;
             double row = b.robin_b[i];
             for (double v : vals) row += std::fabs(v);
             for (int32_t s = b.lptr[i]; s < b.lptr[i + 1]; ++s) row += 2.0 * b.lw[s];
@@ -255,9 +259,23 @@ void prep_base(const Problem &p, Base &b) {
             if (li > lam_t) lam_t = li;
         }
 #pragma omp critical
-        if (lam_t > lam) lam = lam_t;
+        {
+            if (lam_t > lam) lam = lam_t;
+            if (eabs_t > b.elem_abs_max) b.elem_abs_max = eabs_t;
+        }
     }
     b.dt_bound = lam > 0 ? 2.0 / lam : INFINITY;
+    // temperature span of the data: initial field, fixed values, ambient temperatures
+    double tlo = INFINITY, thi = -INFINITY;
+    for (int64_t i = 0; i < N; ++i) {
+        tlo = std::min(tlo, b.T_init[i]);
+        thi = std::max(thi, b.T_init[i]);
+    }
+    for (double t : p.flux_Tinf) {
+        tlo = std::min(tlo, t);
+        thi = std::max(thi, t);
+    }
+    b.T_span = std::max(thi - tlo, 1.0);
     tm.mark("stability bound");
 }
 
@@ -630,6 +648,9 @@ void prep_layout(const Problem &p, const Base &b, const PrepOptions &o, const Or
         L.max_local = 0;
         std::vector<int32_t> local(N, -1);
         std::vector<int32_t> shl;
+        std::vector<uint64_t> cmask;
+        std::vector<int32_t> bcol;
+        std::vector<int64_t> bord;
         for (int64_t q = 0; q < nb; ++q) {
             BlockInfo &bi = L.blocks[q];
             bi.e_begin = (int32_t)blk[q].first;
@@ -649,14 +670,46 @@ void prep_layout(const Problem &p, const Base &b, const PrepOptions &o, const Or
             bi.pad0 = bi.pad1 = 0;
             L.sh_list.insert(L.sh_list.end(), shl.begin(), shl.end());
             for (size_t r = 0; r < shl.size(); ++r) local[shl[r]] = bi.n_int + (int32_t)r;
-            L.max_local = std::max<int64_t>(L.max_local, bi.n_int + bi.n_sh);
-            for (int64_t s = blk[q].first; s < blk[q].first + blk[q].second; ++s)
-                for (int a = 0; a < nen; ++a) {
-                    int32_t g = perm[p.conn[eorder[s] * nen + a]];
-                    int32_t l = g < L.n_private ? g - bi.int_base : local[g];
-                    if (l < 0 || l >= bi.n_int + bi.n_sh) fail(FEM_E_MESH, "internal: block numbering");
-                    L.lconn[s * nen + a] = (uint16_t)l;
+            const int64_t nl = bi.n_int + bi.n_sh;
+            L.max_local = std::max<int64_t>(L.max_local, nl);
+            const int64_t b0 = blk[q].first, b1 = blk[q].first + blk[q].second;
+            auto local_id = [&](int64_t s, int a) {
+                int32_t g = perm[p.conn[eorder[s] * nen + a]];
+                int32_t l = g < L.n_private ? g - bi.int_base : local[g];
+                if (l < 0 || l >= nl) fail(FEM_E_MESH, "internal: block numbering");
+                return l;
+            };
+            if (o.color_in_block) {
+                // greedy colouring inside the block, then elements ordered by
+                // colour: the elements of one wavefront then touch distinct
+                // nodes and their LDS additions do not collide on one address
+                cmask.assign(2 * nl, 0);
+                bcol.resize(b1 - b0);
+                int ncol = 0;
+                for (int64_t s = b0; s < b1; ++s) {
+                    uint64_t f0 = 0, f1 = 0;
+                    for (int a = 0; a < nen; ++a) {
+                        int32_t l = local_id(s, a);
+                        f0 |= cmask[2 * l];
+                        f1 |= cmask[2 * l + 1];
+                    }
+                    int k;
+                    if (~f0) k = __builtin_ctzll(~f0);
+                    else if (~f1) k = 64 + __builtin_ctzll(~f1);
+                    else fail(FEM_E_UNSUPPORTED, "block colouring needs more than 128 colours");
+                    bcol[s - b0] = k;
+                    ncol = std::max(ncol, k + 1);
+                    for (int a = 0; a < nen; ++a) cmask[2 * local_id(s, a) + (k >> 6)] |= 1ull << (k & 63);
                 }
+                std::vector<int64_t> cstart(ncol + 1, 0);
+                for (int64_t s = b0; s < b1; ++s) cstart[bcol[s - b0] + 1]++;
+                for (int c = 0; c < ncol; ++c) cstart[c + 1] += cstart[c];
+                bord.resize(b1 - b0);
+                for (int64_t s = b0; s < b1; ++s) bord[cstart[bcol[s - b0]]++] = eorder[s];
+                std::copy(bord.begin(), bord.end(), eorder.begin() + b0);
+            }
+            for (int64_t s = b0; s < b1; ++s)
+                for (int a = 0; a < nen; ++a) L.lconn[s * nen + a] = (uint16_t)local_id(s, a);
         }
         if (L.max_local > o.max_local_nodes) fail(FEM_E_INVALID_ARG, "internal: block above node cap");
         // combine lists: the partial slots of every shared node in block order
@@ -664,10 +717,12 @@ void prep_layout(const Problem &p, const Base &b, const PrepOptions &o, const Or
         L.comb_ptr.assign(nsh + 1, 0);
         for (int32_t g : L.sh_list) L.comb_ptr[g - L.n_private + 1]++;
         for (int64_t s = 0; s < nsh; ++s) L.comb_ptr[s + 1] += L.comb_ptr[s];
-        L.comb_idx.resize(L.sh_list.size());
+        // partials of one node are contiguous, in block order, so the combine
+        // reads them in one run; each block writes its partial to sh_pos
+        L.sh_pos.resize(L.sh_list.size());
         std::vector<int32_t> fill(L.comb_ptr.begin(), L.comb_ptr.end() - 1);
         for (size_t slot = 0; slot < L.sh_list.size(); ++slot)
-            L.comb_idx[fill[L.sh_list[slot] - L.n_private]++] = (int32_t)slot;
+            L.sh_pos[slot] = fill[L.sh_list[slot] - L.n_private]++;
         L.bc_first = L.n_private;
         L.n_bc_slots = nsh;
         L.block_elems = o.block_elems;
@@ -718,7 +773,7 @@ void prep_layout(const Problem &p, const Base &b, const PrepOptions &o, const Or
     for (int64_t n = 0; n < N; ++n) {
         int64_t i = L.iperm[n];
         for (int d = 0; d < 3; ++d) L.xyz[3 * n + d] = p.xyz[3 * i + d];
-        L.nflag[n] = (uint32_t)b.nmat[i] | (b.fixed[i] ? NODE_FIXED : 0u);
+        L.nflag[n] = (uint32_t)b.nmat[i] | (b.fixed[i] ? NODE_FIXED : 0u) | (has_bc(i) ? NODE_BC : 0u);
         L.m[n] = b.m[i];
         L.T_init[n] = b.T_init[i];
     }

@@ -28,7 +28,7 @@ struct Problem {
 };
 
 // node flag bits stored next to the material id
-enum : uint32_t { NODE_FIXED = 1u << 31, NODE_MAT_MASK = 0xFFFFu };
+enum : uint32_t { NODE_FIXED = 1u << 31, NODE_BC = 1u << 30, NODE_MAT_MASK = 0xFFFFu };
 
 struct BlockInfo {        // one LDS element block (8 ints, 32 bytes)
     int32_t e_begin;      // first element of the block (blocked element order)
@@ -47,7 +47,7 @@ struct Layout {
     std::vector<int32_t> perm, iperm;
     // nodes in new numbering
     std::vector<double> xyz;          // N x 3
-    std::vector<uint32_t> nflag;      // material | NODE_FIXED
+    std::vector<uint32_t> nflag;      // material | NODE_FIXED | NODE_BC (Robin or interface terms)
     std::vector<double> m;            // lumped capacitance weights (kg)
     std::vector<double> T_init;       // initial temperature after fixed values
     // elements in new order, node ids in new numbering
@@ -67,8 +67,8 @@ struct Layout {
     int64_t n_private = 0;            // nodes 0..n_private-1 are private to one block
     std::vector<int32_t> sh_list;     // per block: global ids of its shared nodes
     std::vector<uint16_t> lconn;      // per element: local ids in its block
-    std::vector<int32_t> comb_ptr;    // per shared node: partial slots
-    std::vector<int32_t> comb_idx;
+    std::vector<int32_t> comb_ptr;    // per shared node: its partials are [comb_ptr[s], comb_ptr[s+1])
+    std::vector<int32_t> sh_pos;      // per sh_list entry: where that block writes its partial
     int64_t max_local = 0;
     // report
     double dt_bound = 0;
@@ -82,6 +82,7 @@ struct PrepOptions {
     int scatter = FEM_SCATTER_LDS_BLOCKED;
     int64_t block_elems = 8192;
     int64_t max_local_nodes = 2600;
+    bool color_in_block = true;       // order each block's elements by a local colouring
 };
 
 // Throws std::runtime_error with a message; the C interface maps it to a code.
@@ -103,6 +104,8 @@ struct Base {
     std::vector<double> lw;
     double dt_bound = 0;
     bool any_robin = false;
+    double elem_abs_max = 0;          // max_i sum_{e at i} sum_j |K^e_ij|  (W/K)
+    double T_span = 1;                // span of initial, fixed and ambient temperatures (K)
 };
 
 // node permutation (perm[original] = rank) and element order of a locality ordering

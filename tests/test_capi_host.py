@@ -116,7 +116,7 @@ def test_orderings_are_permutations_and_shrink_bandwidth(ordering):
 
 def test_blocks_and_colours_report():
     p = configs.config2(n=16)
-    ctx = cf.fem_create(cf.make_options(scatter=cf.FEM_SCATTER_LDS_BLOCKED, lds_bytes=24 * 700, block_elems=4000))
+    ctx = cf.fem_create(cf.make_options(scatter=cf.FEM_SCATTER_LDS_BLOCKED, lds_bytes=cf.lds_for_nodes(700), block_elems=4000))
     rep = cf.setup_problem(ctx, p)
     assert rep["max_local_nodes"] <= 700
     assert rep["n_blocks"] >= p["conn"].shape[0] // 4000

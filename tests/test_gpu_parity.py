@@ -98,7 +98,7 @@ def test_tet_fp64(tet12_ref, scatter, ordering, orc):
     p, dt, T_ref, fs_ref, H_ref, D = tet12_ref
     order = {"none": cf.FEM_ORDER_NONE, "rcm": cf.FEM_ORDER_RCM, "hilbert": cf.FEM_ORDER_HILBERT}[ordering]
     T, fs, H, en, rep = gpu_run(p, dt, 300, precision=cf.FEM_PREC_FP64, scatter=scatter_id(scatter), ordering=order,
-                                lds_bytes=44 * 600)
+                                lds_bytes=cf.lds_for_nodes(600, cf.FEM_PREC_FP64))
     err = float(np.max(np.abs(T - T_ref)))
     print("tet12 fp64 %s/%s: max|dT| = %.3e K blocks=%d" % (scatter, ordering, err, rep["n_blocks"]), flush=True)
     assert err <= TOL64
@@ -135,7 +135,7 @@ def test_many_small_blocks_with_ragged_tail(tet12_ref):
     cf = _cf()
     p, dt, T_ref, fs_ref, H_ref, D = tet12_ref
     T, fs, H, en, rep = gpu_run(p, dt, 300, precision=cf.FEM_PREC_FP64, scatter=cf.FEM_SCATTER_LDS_BLOCKED,
-                                lds_bytes=44 * 90, block_elems=333)
+                                lds_bytes=cf.lds_for_nodes(90, cf.FEM_PREC_FP64), block_elems=333)
     assert rep["n_blocks"] > 30 and rep["shared_fraction"] > 0.5
     assert p["conn"].shape[0] % 333 != 0
     assert float(np.max(np.abs(T - T_ref))) <= TOL64
@@ -148,7 +148,7 @@ def test_convective_chill_hex(prec, orc):
     dt = 0.9 * orc.stable_dt(p)
     H_ref, T_ref, fs_ref = orc.run(p, dt, 400)
     pr = cf.FEM_PREC_FP64 if prec == "fp64" else cf.FEM_PREC_FP32_KAHAN
-    T, fs, H, en, rep = gpu_run(p, dt, 400, precision=pr, scatter=cf.FEM_SCATTER_LDS_BLOCKED, lds_bytes=44 * 300)
+    T, fs, H, en, rep = gpu_run(p, dt, 400, precision=pr, scatter=cf.FEM_SCATTER_LDS_BLOCKED, lds_bytes=cf.lds_for_nodes(300, pr))
     if prec == "fp64":
         assert float(np.max(np.abs(T - T_ref))) <= TOL64
     else:
@@ -225,3 +225,26 @@ def test_unstable_dt_is_refused_and_blowup_is_detected():
         u.energy()
     assert e.value.code == -5
     u.close()
+
+
+def test_blocked_fp32_path_is_bitwise_reproducible():
+    """Fixed-point LDS accumulation: two runs (and a checkpointed run) agree bit for bit."""
+    cf = _cf()
+    p = configs.config2(n=14)
+    opts = dict(precision=cf.FEM_PREC_FP32_KAHAN, scatter=cf.FEM_SCATTER_LDS_BLOCKED, lds_bytes=cf.lds_for_nodes(400))
+    a = cf.Solver(p, **opts)
+    dt = 0.9 * a.stable_dt()
+    a.step(dt, 150)
+    ck = cf.fem_read_state(a.ctx)
+    a.step(dt, 150)
+    Ta, Ha = a.T(), a.H()
+    a.close()
+    b = cf.Solver(p, **opts)
+    b.step(dt, 300)
+    assert np.array_equal(b.T(), Ta) and np.array_equal(b.H(), Ha)
+    b.close()
+    c = cf.Solver(p, **opts)
+    cf.fem_write_state(c.ctx, ck)
+    c.step(dt, 150)
+    assert np.array_equal(c.T(), Ta)
+    c.close()
