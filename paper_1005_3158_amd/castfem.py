@@ -20,7 +20,7 @@ FEM_PREC_FP64, FEM_PREC_FP32_KAHAN = 0, 1
 FEM_ORDER_NONE, FEM_ORDER_RCM, FEM_ORDER_MORTON, FEM_ORDER_HILBERT = 0, 1, 2, 3
 FEM_SCATTER_GLOBAL_ATOMIC, FEM_SCATTER_LDS_BLOCKED, FEM_SCATTER_COLORED = 0, 1, 2
 # LDS bytes per block-local node of the blocked element kernel, by precision
-LDS_PER_NODE = {FEM_PREC_FP64: 52, FEM_PREC_FP32_KAHAN: 32}
+LDS_PER_NODE = {FEM_PREC_FP64: 48, FEM_PREC_FP32_KAHAN: 28}
 
 
 def lds_for_nodes(nodes, precision=FEM_PREC_FP32_KAHAN):

@@ -33,11 +33,11 @@ enum Stage { ST_NEW = 0, ST_FINAL = 1, ST_BOUND = 2 };
 
 enum Buf {
     B_NODE_X, B_T, B_H, B_INV_M, B_FS, B_MATS, B_CONN, B_R, B_LCONN, B_BLOCKS, B_SH_LIST, B_PARTIALS,
-    B_COMB_PTR, B_SH_POS, B_ROBIN, B_LINK_PTR, B_LINK_NODE, B_LINK_W, B_DIAG, B_CUMQ, B_FLAGS, B_COUNT
+    B_COMB_PTR, B_SH_POS, B_ROBIN, B_LINK_PTR, B_LINK_NODE, B_LINK_W, B_DIAG, B_QACC, B_FLAGS, B_COUNT
 };
 const char *BUF_NAMES[B_COUNT] = {"node_x", "T", "H", "inv_m", "fs", "mats", "conn", "r", "lconn", "blocks",
                                   "sh_list", "partials", "comb_ptr", "sh_pos", "robin", "link_ptr",
-                                  "link_node", "link_w", "diag", "cumQ", "flags"};
+                                  "link_node", "link_w", "diag", "qacc", "flags"};
 constexpr int64_t ALIGN = 256;
 constexpr int GRAPH_STEPS = 16;  // steps per captured graph (even: both parities)
 constexpr size_t MAX_BLOCK_LDS = 160 * 1024 - 2048;  // gfx950 LDS per workgroup, less static use
@@ -112,7 +112,6 @@ struct fem_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     double setup_seconds = 0;
-    int64_t diag_slots = 0;
 
     Layout &L() { return cands[chosen].L; }
     const Layout &L() const { return cands[chosen].L; }
@@ -151,9 +150,8 @@ void layout_sizes(const fem_ctx *c, const Layout &L, int64_t *sz) {
     sz[B_LINK_PTR] = (L.n_bc_slots + 1) * 4;
     sz[B_LINK_NODE] = (int64_t)L.link_node.size() * 4;
     sz[B_LINK_W] = (int64_t)L.link_w.size() * R;
-    const int64_t slots = (blocked ? (int64_t)L.blocks.size() : 0) + node_grid(blocked ? N - L.n_private : N);
-    sz[B_DIAG] = slots * NDIAG * 8;
-    sz[B_CUMQ] = slots * 8;
+    sz[B_DIAG] = node_grid(N) * NDIAG * 8;
+    sz[B_QACC] = node_grid(blocked ? N - L.n_private : N) * 2 * 8;
     sz[B_FLAGS] = N * 4;
 }
 
@@ -181,13 +179,7 @@ void upload_layout_t(fem_ctx *c, const Layout &L) {
         v.x = (R)L.xyz[3 * n];
         v.y = (R)L.xyz[3 * n + 1];
         v.z = (R)L.xyz[3 * n + 2];
-        if (sizeof(R) == 4) {
-            uint32_t u = f;
-            std::memcpy(&v.w, &u, 4);
-        } else {
-            uint64_t u = f;
-            std::memcpy(&v.w, &u, 8);
-        }
+        v.w = (R)c->prob.mats[f & NODE_MAT_MASK].k;   // conductivity of the node's material
         nx[n] = v;
         im[n] = (R)(1.0 / L.m[n]);
         const fem_material &mat = c->prob.mats[f & NODE_MAT_MASK];
@@ -246,7 +238,7 @@ void upload_layout_t(fem_ctx *c, const Layout &L) {
     int64_t sz[B_COUNT];
     layout_sizes(c, L, sz);
     HIPCHECK(hipMemsetAsync(c->ptr[B_DIAG], 0, sz[B_DIAG], c->stream));
-    HIPCHECK(hipMemsetAsync(c->ptr[B_CUMQ], 0, sz[B_CUMQ], c->stream));
+    HIPCHECK(hipMemsetAsync(c->ptr[B_QACC], 0, sz[B_QACC], c->stream));
     // the host vectors above must outlive the copies
     HIPCHECK(hipStreamSynchronize(c->stream));
 }
@@ -279,7 +271,9 @@ void fill_dev(fem_ctx *c, const Candidate &cd) {
     d.link_node = (const int32_t *)c->ptr[B_LINK_NODE];
     d.link_w = c->ptr[B_LINK_W];
     d.diag = (double *)c->ptr[B_DIAG];
-    d.cumQ = (double *)c->ptr[B_CUMQ];
+    d.qacc = (double *)c->ptr[B_QACC];
+    d.n_inflow = L.n_inflow;
+    d.n_mat = (int32_t)c->prob.mats.size();
     d.n_private = L.n_private;
     d.n_blocks = (int64_t)L.blocks.size();
     d.n_bc_slots = L.n_bc_slots;
@@ -299,9 +293,7 @@ void fill_dev(fem_ctx *c, const Candidate &cd) {
         d.fx_limit = (float)std::ldexp(1.0, 50 - S);
     }
     const bool blocked = d.scatter == FEM_SCATTER_LDS_BLOCKED;
-    d.diag_k1 = blocked ? d.n_blocks : 0;
-    d.diag_k2 = node_grid(blocked ? d.N - d.n_private : d.N);
-    c->diag_slots = d.diag_k1 + d.diag_k2;
+    d.node_blocks = node_grid(blocked ? d.N - d.n_private : d.N);
     c->dev = d;
 }
 
@@ -538,7 +530,7 @@ int fem_finalize(fem_ctx *ctx, fem_prep_report *rep) {
         const int thr = ctx->opt.threads ? ctx->opt.threads : 256;
         if (ctx->opt.scatter == FEM_SCATTER_LDS_BLOCKED && ctx->opt.block_elems == 0 && ctx->opt.lds_bytes == 0) {
             // autotune over block node sets (the paper's timed search over the block count)
-            for (int64_t nodes : {1024, 1536, 2048, 3072, 4096}) {
+            for (int64_t nodes : {512, 640, 768, 1024, 1536}) {
                 if ((size_t)nodes * per > MAX_BLOCK_LDS) continue;
                 Candidate c;
                 c.o.ordering = ctx->opt.ordering;
@@ -771,46 +763,38 @@ int fem_energy(fem_ctx *ctx, fem_energy_report *rep) {
         rep->E0 = ctx->E0;
         rep->steps = ctx->steps;
         rep->time = ctx->time;
-        const int64_t S = ctx->diag_slots;
-        std::vector<double> dg(S * NDIAG), cq(S);
-        HIPCHECK(hipMemcpyAsync(cq.data(), ctx->ptr[B_CUMQ], S * 8, hipMemcpyDeviceToHost, ctx->stream));
-        if (ctx->steps > 0) HIPCHECK(hipMemcpyAsync(dg.data(), ctx->ptr[B_DIAG], S * NDIAG * 8, hipMemcpyDeviceToHost, ctx->stream));
+        const int64_t S = node_grid(ctx->dev.N), Q = ctx->dev.node_blocks;
+        std::vector<double> dg(S * NDIAG), qa(2 * Q);
+        HIPCHECK(enqueue_state_diag(ctx->dev, ctx->parity, ctx->stream));
+        HIPCHECK(hipMemcpyAsync(dg.data(), ctx->ptr[B_DIAG], S * NDIAG * 8, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHECK(hipMemcpyAsync(qa.data(), ctx->ptr[B_QACC], 2 * Q * 8, hipMemcpyDeviceToHost, ctx->stream));
         HIPCHECK(hipStreamSynchronize(ctx->stream));
         HIPCHECK(hipGetLastError());
-        double qc = 0;
-        for (int64_t s = 0; s < S; ++s) qc += cq[s];
-        rep->Q_cum = qc;
-        if (ctx->steps == 0) {
-            rep->E = ctx->E0;
-            rep->latent = ctx->lat0;
-            rep->T_min = ctx->tmin0;
-            rep->T_max = ctx->tmax0;
-            rep->n_liquid = ctx->nliq0;
-        } else {
-            double E = 0, lat = 0, nl = 0, nf = 0, tmin = INFINITY, tmax = -INFINITY;
-            for (int64_t s = 0; s < S; ++s) {
-                const double *v = &dg[s * NDIAG];
-                E += v[DG_E];
-                lat += v[DG_LAT];
-                nl += v[DG_NLIQ];
-                nf += v[DG_NONFIN];
-                tmin = std::min(tmin, v[DG_TMIN]);
-                tmax = std::max(tmax, v[DG_TMAX]);
-            }
-            rep->E = E;
-            rep->latent = lat;
-            rep->T_min = tmin;
-            rep->T_max = tmax;
-            rep->n_liquid = (int64_t)nl;
-            rep->nonfinite = (int64_t)nf;
+        double qc = 0, E = 0, lat = 0, nl = 0, nf = 0, tmin = INFINITY, tmax = -INFINITY;
+        for (int64_t b = 0; b < Q; ++b) qc += qa[2 * b + 1];
+        for (int64_t b = 0; b < S; ++b) {
+            const double *v = &dg[b * NDIAG];
+            E += v[DG_E];
+            lat += v[DG_LAT];
+            nl += v[DG_NLIQ];
+            nf += v[DG_NONFIN];
+            tmin = std::min(tmin, v[DG_TMIN]);
+            tmax = std::max(tmax, v[DG_TMAX]);
         }
+        rep->Q_cum = qc;
+        rep->E = E;
+        rep->latent = lat;
+        rep->T_min = tmin;
+        rep->T_max = tmax;
+        rep->n_liquid = (int64_t)nl;
+        rep->nonfinite = (int64_t)nf;
         rep->residual = std::fabs(rep->E - ctx->E0 - rep->Q_cum) / std::fabs(ctx->E0 - ctx->Eref);
         if (rep->nonfinite > 0 || !std::isfinite(rep->E))
             throw PrepError{FEM_E_NONFINITE, "the state holds non-finite enthalpy at " + std::to_string(rep->nonfinite) + " nodes"};
     });
 }
 
-// checkpoint layout: header, H, T (both buffers), fs, cumQ, diag
+// checkpoint layout: header, H, T (both buffers), fs, inflow accumulators
 struct CkptHeader {
     uint64_t magic, N, prec, slots;
     int64_t parity, steps;
@@ -822,8 +806,8 @@ int fem_read_state(fem_ctx *ctx, void *buf, int64_t *bytes) {
     if (!ctx || !bytes) return set_err(FEM_E_INVALID_ARG, "null argument");
     return guarded([&] {
         check_bound(ctx, ST_BOUND);
-        const int64_t N = ctx->L().N, R = (int64_t)ctx->rsize(), S = ctx->diag_slots;
-        const int64_t need = (int64_t)sizeof(CkptHeader) + N * 8 + 2 * N * R + N * R + S * 8 + S * NDIAG * 8;
+        const int64_t N = ctx->L().N, R = (int64_t)ctx->rsize(), S = 2 * ctx->dev.node_blocks;
+        const int64_t need = (int64_t)sizeof(CkptHeader) + N * 8 + 2 * N * R + N * R + S * 8;
         if (!buf) {
             *bytes = need;
             return;
@@ -840,9 +824,7 @@ int fem_read_state(fem_ctx *ctx, void *buf, int64_t *bytes) {
         p += 2 * N * R;
         HIPCHECK(hipMemcpyAsync(p, ctx->ptr[B_FS], N * R, hipMemcpyDeviceToHost, ctx->stream));
         p += N * R;
-        HIPCHECK(hipMemcpyAsync(p, ctx->ptr[B_CUMQ], S * 8, hipMemcpyDeviceToHost, ctx->stream));
-        p += S * 8;
-        HIPCHECK(hipMemcpyAsync(p, ctx->ptr[B_DIAG], S * NDIAG * 8, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHECK(hipMemcpyAsync(p, ctx->ptr[B_QACC], S * 8, hipMemcpyDeviceToHost, ctx->stream));
         HIPCHECK(hipStreamSynchronize(ctx->stream));
         *bytes = need;
     });
@@ -852,8 +834,8 @@ int fem_write_state(fem_ctx *ctx, const void *buf, int64_t bytes) {
     if (!ctx || !buf) return set_err(FEM_E_INVALID_ARG, "null argument");
     return guarded([&] {
         check_bound(ctx, ST_BOUND);
-        const int64_t N = ctx->L().N, R = (int64_t)ctx->rsize(), S = ctx->diag_slots;
-        const int64_t need = (int64_t)sizeof(CkptHeader) + N * 8 + 2 * N * R + N * R + S * 8 + S * NDIAG * 8;
+        const int64_t N = ctx->L().N, R = (int64_t)ctx->rsize(), S = 2 * ctx->dev.node_blocks;
+        const int64_t need = (int64_t)sizeof(CkptHeader) + N * 8 + 2 * N * R + N * R + S * 8;
         if (bytes < need) throw PrepError{FEM_E_INVALID_ARG, "checkpoint too small"};
         CkptHeader h;
         std::memcpy(&h, buf, sizeof h);
@@ -866,9 +848,7 @@ int fem_write_state(fem_ctx *ctx, const void *buf, int64_t bytes) {
         p += 2 * N * R;
         HIPCHECK(hipMemcpyAsync(ctx->ptr[B_FS], p, N * R, hipMemcpyHostToDevice, ctx->stream));
         p += N * R;
-        HIPCHECK(hipMemcpyAsync(ctx->ptr[B_CUMQ], p, S * 8, hipMemcpyHostToDevice, ctx->stream));
-        p += S * 8;
-        HIPCHECK(hipMemcpyAsync(ctx->ptr[B_DIAG], p, S * NDIAG * 8, hipMemcpyHostToDevice, ctx->stream));
+        HIPCHECK(hipMemcpyAsync(ctx->ptr[B_QACC], p, S * 8, hipMemcpyHostToDevice, ctx->stream));
         HIPCHECK(hipStreamSynchronize(ctx->stream));
         ctx->parity = (int)h.parity;
         ctx->steps = h.steps;

@@ -69,18 +69,6 @@ __device__ __forceinline__ void t_of_h(const MatDev &M, double H, double &T, dou
     }
 }
 
-__device__ __forceinline__ void accumulate(DiagAcc &a, const MatDev &M, double m, double H, double T,
-                                           double fs, double q) {
-    a.v[DG_E] += m * H;
-    a.v[DG_LAT] += m * M.L * (1.0 - fs);
-    a.v[DG_Q] += q;
-    a.v[DG_QDT] += q * M.dt;
-    a.v[DG_TMIN] = fmin(a.v[DG_TMIN], T);
-    a.v[DG_TMAX] = fmax(a.v[DG_TMAX], T);
-    if (M.latent && fs < 1.0) a.v[DG_NLIQ] += 1.0;
-    if (!isfinite(H)) a.v[DG_NONFIN] += 1.0;
-}
-
 // ------------------------------------------------------------ node update
 // FP32: error-free two-sum of (hi, inc) carried into lo, then renormalised.
 __device__ __forceinline__ float2 kahan_add(float2 h, float inc) {
@@ -96,55 +84,40 @@ __device__ __forceinline__ float2 kahan_add(float2 h, float inc) {
 
 template <class R> struct Node;
 
+// Enthalpy update of a free node g with residual r (fixed nodes are never
+// passed: their H, T and fs keep the values set at bind time).
 template <> struct Node<float> {
-    // update node g with residual r; q = boundary inflow already attributed to it
-    static __device__ __forceinline__ void update(const Dev &d, int64_t g, float r, uint32_t flag, float Tcur,
-                                                  float *Tn, double q, DiagAcc &acc) {
-        const MatDev &M = d.mats[flag & NODE_MAT_MASK];
+    static __device__ __forceinline__ void update(const Dev &d, const MatDev *mats, int64_t g, float r,
+                                                  uint32_t flag, float *Tn) {
+        const MatDev &M = mats[flag & NODE_MAT_MASK];
         float2 *H = (float2 *)d.H;
         const float im = ((const float *)d.inv_m)[g];
-        float2 h = H[g];
-        float Tnew;
-        if (flag & NODE_FIXED) {
-            q -= (double)r;
-        } else {
-            float inc;
-            {
+        float inc;
+        {
 #pragma clang fp contract(off)
-                inc = r * (M.dtf * im);
-            }
-            h = kahan_add(h, inc);
-            H[g] = h;
+            inc = r * (M.dtf * im);
         }
-        const double Hd = (double)h.x + (double)h.y;
+        const float2 h = kahan_add(H[g], inc);
+        H[g] = h;
         double T, fs;
-        t_of_h(M, Hd, T, fs);
-        Tnew = (flag & NODE_FIXED) ? Tcur : (float)T;
-        Tn[g] = Tnew;
+        t_of_h(M, (double)h.x + (double)h.y, T, fs);
+        Tn[g] = (float)T;
         ((float *)d.fs)[g] = (float)fs;
-        accumulate(acc, M, 1.0 / (double)im, Hd, (double)Tnew, fs, q);
     }
 };
 
 template <> struct Node<double> {
-    static __device__ __forceinline__ void update(const Dev &d, int64_t g, double r, uint32_t flag, double Tcur,
-                                                  double *Tn, double q, DiagAcc &acc) {
-        const MatDev &M = d.mats[flag & NODE_MAT_MASK];
+    static __device__ __forceinline__ void update(const Dev &d, const MatDev *mats, int64_t g, double r,
+                                                  uint32_t flag, double *Tn) {
+        const MatDev &M = mats[flag & NODE_MAT_MASK];
         double *H = (double *)d.H;
         const double im = ((const double *)d.inv_m)[g];
-        double h = H[g];
-        if (flag & NODE_FIXED) {
-            q -= r;
-        } else {
-            h = h + r * (M.dt * im);
-            H[g] = h;
-        }
+        const double h = H[g] + r * (M.dt * im);
+        H[g] = h;
         double T, fs;
         t_of_h(M, h, T, fs);
-        const double Tnew = (flag & NODE_FIXED) ? Tcur : T;
-        Tn[g] = Tnew;
+        Tn[g] = T;
         ((double *)d.fs)[g] = fs;
-        accumulate(acc, M, 1.0 / im, h, Tnew, fs, q);
     }
 };
 
@@ -166,19 +139,25 @@ __device__ __forceinline__ double boundary_terms(const Dev &d, int64_t s, R Ti, 
     return q;
 }
 
-// wavefront then workgroup reduction of the diagnostics into slot `slot`
+// sum / min / max over the 64 lanes of a wavefront
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+    for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_down(v, off, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+    return v;
+}
+
+// workgroup reduction of the state diagnostics into d.diag[slot]
 __device__ void reduce_diag(const Dev &d, DiagAcc &acc, int64_t slot) {
     __shared__ double part[16][NDIAG];
-    for (int k = 0; k < NDIAG; ++k) {
-        double v = acc.v[k];
-        for (int off = 32; off > 0; off >>= 1) {
-            double o = __shfl_down(v, off, 64);
-            if (k == DG_TMIN) v = fmin(v, o);
-            else if (k == DG_TMAX) v = fmax(v, o);
-            else v += o;
-        }
-        acc.v[k] = v;
-    }
+    for (int k = 0; k < NDIAG; ++k)
+        acc.v[k] = k == DG_TMIN ? wave_min(acc.v[k]) : (k == DG_TMAX ? wave_max(acc.v[k]) : wave_sum(acc.v[k]));
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (lane == 0)
         for (int k = 0; k < NDIAG; ++k) part[wave][k] = acc.v[k];
@@ -194,7 +173,6 @@ __device__ void reduce_diag(const Dev &d, DiagAcc &acc, int64_t slot) {
                 else out[k] += part[w][k];
             }
         for (int k = 0; k < NDIAG; ++k) d.diag[slot * NDIAG + k] = out[k];
-        d.cumQ[slot] += out[DG_QDT];
     }
 }
 
@@ -236,12 +214,9 @@ __global__ __launch_bounds__(256) void k_elems(Dev d, int parity, int64_t e0, in
     int32_t c[NEN];
     V4 p[NEN];
     for (int a = 0; a < NEN; ++a) c[a] = d.conn[e * NEN + a];
-    for (int a = 0; a < NEN; ++a) {
-        p[a] = X[c[a]];
-        p[a].w = Tc[c[a]];
-    }
-    const uint32_t f0 = flag_bits(X[c[0]].w);
-    const R k = mat_k(d.mats[f0 & NODE_MAT_MASK], R(0));
+    for (int a = 0; a < NEN; ++a) p[a] = X[c[a]];
+    const R k = p[0].w;       // conductivity of the element's material
+    for (int a = 0; a < NEN; ++a) p[a].w = Tc[c[a]];
     R re[NEN];
     Elem<R, NEN>::residual(p, k, re);
     for (int a = 0; a < NEN; ++a) {
@@ -270,6 +245,17 @@ struct Fixed {
     }
 };
 
+// materials staged in LDS when the table is small
+constexpr int LDS_MATS = 8;
+
+__device__ __forceinline__ const MatDev *stage_mats(const Dev &d, MatDev *s_mats) {
+    if (d.n_mat > LDS_MATS) return d.mats;
+    const int words = d.n_mat * (int)(sizeof(MatDev) / 8);
+    for (int w = threadIdx.x; w < words; w += blockDim.x)
+        ((double *)s_mats)[w] = ((const double *)d.mats)[w];
+    return s_mats;   // visible after the caller's next barrier
+}
+
 // element phase of the blocked layout, one workgroup per element block
 template <class R, int NEN>
 __global__ __launch_bounds__(1024) void k_block(Dev d, int parity) {
@@ -278,6 +264,7 @@ __global__ __launch_bounds__(1024) void k_block(Dev d, int parity) {
     // FP32: 64-bit fixed-point accumulators; FP64: double accumulators
     using ACC = typename std::conditional<std::is_same<R, float>::value, long long, double>::type;
     extern __shared__ __attribute__((aligned(32))) unsigned char smem[];
+    __shared__ MatDev s_mats[LDS_MATS];
     __shared__ int s_bad;
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const BlockInfo bi = d.blocks[b];
@@ -285,19 +272,18 @@ __global__ __launch_bounds__(1024) void k_block(Dev d, int parity) {
     V4 *s_x = (V4 *)smem;                       // x, y, z, T per local node
     ACC *s_acc = (ACC *)(s_x + nloc);           // residual accumulator
     R *s_k = (R *)(s_acc + nloc);               // conductivity of the node's material
-    uint32_t *s_f = (uint32_t *)(s_k + nloc);   // material | flags
     const V4 *X = (const V4 *)d.node_x;
     const R *Tc = (const R *)d.T + parity * d.N;
     R *Tn = (R *)d.T + (1 - parity) * d.N;
     if (threadIdx.x == 0) s_bad = 0;
+    const MatDev *mats = stage_mats(d, s_mats);
 
-    // gather: private nodes are a contiguous range, shared nodes a list
+    // gather: private nodes are a contiguous range, shared nodes a list;
+    // node_x holds x, y, z and the conductivity of the node's material
     for (int l = threadIdx.x; l < nloc; l += blockDim.x) {
         const int64_t g = l < bi.n_int ? (int64_t)bi.int_base + l : (int64_t)d.sh_list[bi.sh_begin + (l - bi.n_int)];
         V4 x = X[g];
-        const uint32_t f = flag_bits(x.w);
-        s_f[l] = f;
-        s_k[l] = mat_k(d.mats[f & NODE_MAT_MASK], R(0));
+        s_k[l] = x.w;
         x.w = Tc[g];
         s_x[l] = x;
         s_acc[l] = ACC(0);
@@ -350,8 +336,9 @@ __global__ __launch_bounds__(1024) void k_block(Dev d, int parity) {
     if (bad) s_bad = 1;
     __syncthreads();
 
-    // private nodes are complete: update them in place; a contribution outside
-    // the fixed-point range poisons the block so the run reports non-finite
+    // private nodes are complete and free (fixed nodes are always shared):
+    // update them in place; a contribution outside the fixed-point range
+    // poisons the block so the run reports non-finite values
     const bool poison = s_bad != 0;
     auto resid = [&](int l) -> R {
         R r;
@@ -359,25 +346,31 @@ __global__ __launch_bounds__(1024) void k_block(Dev d, int parity) {
         else r = s_acc[l];
         return poison ? R(NAN) : r;
     };
-    DiagAcc acc;
-    acc.init();
-    for (int l = threadIdx.x; l < bi.n_int; l += blockDim.x)
-        Node<R>::update(d, (int64_t)bi.int_base + l, resid(l), s_f[l], s_x[l].w, Tn, 0.0, acc);
-    // one partial per shared node
+    for (int l = threadIdx.x; l < bi.n_int; l += blockDim.x) {
+        const int64_t g = (int64_t)bi.int_base + l;
+        Node<R>::update(d, mats, g, resid(l), d.flags[g], Tn);
+    }
+    // one partial per shared node, stored where the combine reads it
     R *P = (R *)d.partials;
     for (int l = threadIdx.x; l < bi.n_sh; l += blockDim.x) P[d.sh_pos[bi.sh_begin + l]] = resid(bi.n_int + l);
-    reduce_diag(d, acc, b);
 }
 
 // node phase: all nodes (COMBINE = false: residual from r[N], which is reset)
 // or the shared nodes of the blocked layout (COMBINE = true: sum of the
-// node's contiguous partials, in block order)
+// node's contiguous partials, in block order).  Workgroups covering nodes
+// with boundary inflow (the first n_inflow slots) reduce it in FP64.
 template <class R, bool COMBINE>
 __global__ __launch_bounds__(NODE_THREADS) void k_nodes(Dev d, int parity) {
+    __shared__ MatDev s_mats[LDS_MATS];
+    __shared__ double s_q[NODE_THREADS / 64][2];
     const int64_t count = COMBINE ? d.N - d.n_private : d.N;
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    DiagAcc acc;
-    acc.init();
+    const bool inflow_block = (int64_t)blockIdx.x * blockDim.x < d.n_inflow;
+    double cum_old = 0.0;
+    if (inflow_block && threadIdx.x == 0) cum_old = d.qacc[2 * blockIdx.x + 1];   // issued early
+    const MatDev *mats = stage_mats(d, s_mats);
+    __syncthreads();
+    double q = 0.0, qdt = 0.0;
     if (s < count) {
         const int64_t g = d.bc_first + s;
         const R *Tc = (const R *)d.T + parity * d.N;
@@ -393,15 +386,59 @@ __global__ __launch_bounds__(NODE_THREADS) void k_nodes(Dev d, int parity) {
             r = rr[g];
             rr[g] = R(0);
         }
-        double q = 0.0;
-        R Ti = R(0);
-        if (f & (NODE_FIXED | NODE_BC)) {
-            Ti = Tc[g];
-            if (f & NODE_BC) q = boundary_terms<R>(d, s, Ti, Tc, r);
-        }
-        Node<R>::update(d, g, r, f, Ti, Tn, q, acc);
+        if (f & NODE_BC) q = boundary_terms<R>(d, s, Tc[g], Tc, r);
+        if (f & NODE_FIXED) q -= (double)r;     // reaction of a fixed temperature
+        else Node<R>::update(d, mats, g, r, f, Tn);
+        qdt = q * mats[f & NODE_MAT_MASK].dt;
     }
-    reduce_diag(d, acc, d.diag_k1 + blockIdx.x);
+    if (inflow_block) {
+        q = wave_sum(q);
+        qdt = wave_sum(qdt);
+        if ((threadIdx.x & 63) == 0) {
+            s_q[threadIdx.x >> 6][0] = q;
+            s_q[threadIdx.x >> 6][1] = qdt;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double Q = 0.0, QD = 0.0;
+            for (int w = 0; w < NODE_THREADS / 64; ++w) {
+                Q += s_q[w][0];
+                QD += s_q[w][1];
+            }
+            d.qacc[2 * blockIdx.x] = Q;
+            d.qacc[2 * blockIdx.x + 1] = cum_old + QD;
+        }
+    }
+}
+
+// state diagnostics on demand: E, latent heat, T range, liquid and non-finite counts
+template <class R>
+__global__ __launch_bounds__(NODE_THREADS) void k_state(Dev d, int parity) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    DiagAcc acc;
+    acc.init();
+    if (i < d.N) {
+        const uint32_t f = d.flags[i];
+        const MatDev &M = d.mats[f & NODE_MAT_MASK];
+        double H;
+        if constexpr (std::is_same<R, float>::value) {
+            const float2 h = ((const float2 *)d.H)[i];
+            H = (double)h.x + (double)h.y;
+        } else {
+            H = ((const double *)d.H)[i];
+        }
+        const double m = 1.0 / (double)((const R *)d.inv_m)[i];
+        const double T = (double)((const R *)d.T)[parity * d.N + i];
+        double Th, fs;
+        t_of_h(M, H, Th, fs);
+        acc.v[DG_E] = m * H;
+        acc.v[DG_LAT] = m * M.L * (1.0 - fs);
+        acc.v[DG_TMIN] = T;
+        acc.v[DG_TMAX] = T;
+        acc.v[DG_NLIQ] = (M.latent && fs < 1.0) ? 1.0 : 0.0;
+        acc.v[DG_NONFIN] = isfinite(H) ? 0.0 : 1.0;
+    }
+    reduce_diag(d, acc, blockIdx.x);
 }
 
 __global__ __launch_bounds__(256) void k_copy(float4 *__restrict__ dst, const float4 *__restrict__ src, int64_t n) {
@@ -447,6 +484,13 @@ hipError_t step_t(const Dev &d, int parity, hipStream_t s, hipEvent_t *ev) {
 hipError_t enqueue_step(const Dev &d, int parity, hipStream_t s, hipEvent_t *ev) {
     if (d.prec == FEM_PREC_FP64) return d.nen == 4 ? step_t<double, 4>(d, parity, s, ev) : step_t<double, 8>(d, parity, s, ev);
     return d.nen == 4 ? step_t<float, 4>(d, parity, s, ev) : step_t<float, 8>(d, parity, s, ev);
+}
+
+hipError_t enqueue_state_diag(const Dev &d, int parity, hipStream_t s) {
+    const unsigned grid = (unsigned)node_grid(d.N);
+    if (d.prec == FEM_PREC_FP64) hipLaunchKernelGGL((k_state<double>), dim3(grid), dim3(NODE_THREADS), 0, s, d, parity);
+    else hipLaunchKernelGGL((k_state<float>), dim3(grid), dim3(NODE_THREADS), 0, s, d, parity);
+    return hipGetLastError();
 }
 
 hipError_t set_block_lds_limit(int prec, int nen, size_t bytes) {

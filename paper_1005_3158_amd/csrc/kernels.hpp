@@ -17,8 +17,8 @@ struct MatDev {
 };
 
 // number of FP64 values in one per-workgroup diagnostics record
-constexpr int NDIAG = 8;
-enum { DG_E = 0, DG_LAT = 1, DG_Q = 2, DG_TMIN = 3, DG_TMAX = 4, DG_NLIQ = 5, DG_NONFIN = 6, DG_QDT = 7 };
+constexpr int NDIAG = 6;
+enum { DG_E = 0, DG_LAT = 1, DG_TMIN = 2, DG_TMAX = 3, DG_NLIQ = 4, DG_NONFIN = 5 };
 
 struct Dev {
     int prec = FEM_PREC_FP32_KAHAN;
@@ -46,8 +46,10 @@ struct Dev {
     const int32_t *link_ptr = nullptr, *link_node = nullptr;
     const void *link_w = nullptr;       // R per link
     // diagnostics
-    double *diag = nullptr;             // NDIAG per workgroup slot
-    double *cumQ = nullptr;             // per workgroup slot: sum of dt * inflow
+    double *diag = nullptr;             // state diagnostics: NDIAG per node-grid workgroup
+    double *qacc = nullptr;             // per node-kernel workgroup: inflow of the last step, sum of dt * inflow
+    int64_t n_inflow = 0;               // node-kernel slots 0..n_inflow-1 may carry boundary inflow
+    int32_t n_mat = 0;
     // sizes and launch shape
     int64_t n_private = 0, n_blocks = 0, n_bc_slots = 0, bc_first = 0;
     int threads = 256;
@@ -56,8 +58,7 @@ struct Dev {
     const int32_t *color_ptr_host = nullptr;
     double fx_scale = 1.0, fx_inv = 1.0; // FP32 blocked path: fixed-point scale 2^S and 2^-S
     float fx_limit = 0.0f;              // largest element contribution that fits (|r| * 2^S < 2^50)
-    int64_t diag_k1 = 0;                // diagnostics slots of the element kernel
-    int64_t diag_k2 = 0;                // diagnostics slots of the node kernel
+    int64_t node_blocks = 0;            // workgroups of the node kernel
 };
 
 constexpr int NODE_THREADS = 256;
@@ -65,12 +66,14 @@ constexpr int NODE_THREADS = 256;
 inline int64_t node_grid(int64_t n) { return (n + NODE_THREADS - 1) / NODE_THREADS; }
 
 // LDS bytes per local node of the blocked kernel
-inline size_t lds_per_node(int prec) { return prec == FEM_PREC_FP64 ? 52 : 32; }
+inline size_t lds_per_node(int prec) { return prec == FEM_PREC_FP64 ? 48 : 28; }
 
 // Enqueue one explicit step reading T buffer `parity` and writing 1 - parity.
 // If ev is not null, ev[0..1] bracket the element kernel(s) and ev[2..3] the
 // node kernel.
 hipError_t enqueue_step(const Dev &d, int parity, hipStream_t s, hipEvent_t *ev);
+// Reduce the state diagnostics of T buffer `parity` into d.diag.
+hipError_t enqueue_state_diag(const Dev &d, int parity, hipStream_t s);
 // Allow the blocked element kernel `bytes` of dynamic LDS.
 hipError_t set_block_lds_limit(int prec, int nen, size_t bytes);
 // Plain vector copy of n16 16-byte words.

@@ -622,7 +622,10 @@ void prep_layout(const Problem &p, const Base &b, const PrepOptions &o, const Or
         // private nodes grouped by owner block, in ordering rank within a block;
         // shared nodes after them ordered by first block then rank
         std::vector<int32_t> priv, shar;
-        for (int64_t i = 0; i < N; ++i) (nblk[i] == 1 && !has_bc(i) ? priv : shar).push_back((int32_t)i);
+        // nodes with boundary terms or a fixed temperature are always shared,
+        // so all boundary inflow is computed by the node kernel
+        auto special = [&](int64_t i) { return has_bc(i) || b.fixed[i]; };
+        for (int64_t i = 0; i < N; ++i) (nblk[i] == 1 && !special(i) ? priv : shar).push_back((int32_t)i);
         auto by_owner_rank = [&](std::vector<int32_t> &v) {
             std::vector<uint64_t> key(v.size());
             for (size_t r = 0; r < v.size(); ++r) key[r] = ((uint64_t)owner[v[r]] << 32) | (uint32_t)perm[v[r]];
@@ -633,6 +636,13 @@ void prep_layout(const Problem &p, const Base &b, const PrepOptions &o, const Or
         };
         by_owner_rank(priv);
         by_owner_rank(shar);
+        // shared nodes carrying boundary inflow (Robin faces, fixed temperature)
+        // come first: only the node-kernel workgroups covering them reduce it
+        std::stable_partition(shar.begin(), shar.end(), [&](int32_t i) {
+            return b.fixed[i] || b.robin_b[i] != 0.0 || b.robin_a[i] != 0.0;
+        });
+        L.n_inflow = 0;
+        for (int32_t i : shar) L.n_inflow += (b.fixed[i] || b.robin_b[i] != 0.0 || b.robin_a[i] != 0.0) ? 1 : 0;
         L.n_private = (int64_t)priv.size();
         std::vector<int32_t> fin(N);
         for (size_t r = 0; r < priv.size(); ++r) fin[priv[r]] = (int32_t)r;
@@ -730,6 +740,7 @@ void prep_layout(const Problem &p, const Base &b, const PrepOptions &o, const Or
         L.bc_first = 0;
         L.n_bc_slots = N;
         L.n_private = 0;
+        L.n_inflow = N;
     }
 
     // 3. colouring (colour by colour scatter): greedy first-fit in element order
@@ -804,7 +815,7 @@ void prep_layout(const Problem &p, const Base &b, const PrepOptions &o, const Or
     }
     // a private node never carries boundary terms
     for (int64_t n = 0; n < L.n_private; ++n)
-        if (has_bc(L.iperm[n])) fail(FEM_E_MESH, "internal: boundary node classed private");
+        if (has_bc(L.iperm[n]) || b.fixed[L.iperm[n]]) fail(FEM_E_MESH, "internal: boundary node classed private");
     L.bw_before = bandwidth(p, b, nullptr);
     L.bw_after = bandwidth(p, b, &L.perm);
 }

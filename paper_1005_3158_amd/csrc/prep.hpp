@@ -65,6 +65,7 @@ struct Layout {
     // LDS blocks
     std::vector<BlockInfo> blocks;
     int64_t n_private = 0;            // nodes 0..n_private-1 are private to one block
+    int64_t n_inflow = 0;             // node-kernel slots 0..n_inflow-1 may carry boundary inflow
     std::vector<int32_t> sh_list;     // per block: global ids of its shared nodes
     std::vector<uint16_t> lconn;      // per element: local ids in its block
     std::vector<int32_t> comb_ptr;    // per shared node: its partials are [comb_ptr[s], comb_ptr[s+1])
