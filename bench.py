@@ -47,7 +47,43 @@ def load_traffic(kind):
     return t.get("bytes_per_launch")
 
 
+def traffic_from_counters(fetch_dir, write_dir, kernel_key="k_block<float, 4>", out_name="block_element_config2"):
+    """Summarise two rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE,
+    KiB per dispatch) into HBM bytes per launch of the blocked element kernel.
+    Each counter is scaled by what it reads for the plain 1 GiB copy kernel the
+    benchmark launches in the same run (1 GiB read and 1 GiB written)."""
+    import csv
+    import glob
+
+    def per_kernel(d):
+        rows = []
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            rows += list(csv.DictReader(open(f)))
+        kern = [float(r["Counter_Value"]) for r in rows if kernel_key in r["Kernel_Name"]]
+        copy = [float(r["Counter_Value"]) for r in rows if "k_copy" in r["Kernel_Name"]]
+        return sum(kern) / len(kern), sum(copy) / len(copy), len(kern)
+
+    kf, cf_, nk = per_kernel(fetch_dir)
+    kw, cw, _ = per_kernel(write_dir)
+    gib_kib = float(1 << 20)
+    fetch_scale, write_scale = gib_kib / cf_, gib_kib / cw
+    out = {
+        "kernel": kernel_key, "kernel_hash": kernel_hash(), "dispatches": nk,
+        "fetch_kib_raw": kf, "write_kib_raw": kw, "copy_fetch_kib": cf_, "copy_write_kib": cw,
+        "fetch_scale": fetch_scale, "write_scale": write_scale,
+        "bytes_per_launch": 1024.0 * (kf * fetch_scale + kw * write_scale),
+        "fetch_bytes": 1024.0 * kf * fetch_scale, "write_bytes": 1024.0 * kw * write_scale,
+    }
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % out_name)
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--traffic-from":
+        traffic_from_counters(sys.argv[2], sys.argv[3])
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)

@@ -21,6 +21,7 @@
 #include "kernels.hpp"
 
 #include <cfloat>
+#include <algorithm>
 #include <type_traits>
 
 #include "elem.hpp"
@@ -378,9 +379,16 @@ __global__ __launch_bounds__(NODE_THREADS) void k_nodes(Dev d, int parity) {
         const uint32_t f = d.flags[g];
         R r;
         if (COMBINE) {
+            // most shared nodes sit in two to four blocks: issue the first
+            // four loads together, then sum in block order
             const R *P = (const R *)d.partials;
-            r = R(0);
-            for (int32_t k = d.comb_ptr[s]; k < d.comb_ptr[s + 1]; ++k) r += P[k];
+            const int32_t k0 = d.comb_ptr[s], k1 = d.comb_ptr[s + 1];
+            const R p0 = P[k0];                        // every shared node has a partial
+            const R p1 = k0 + 1 < k1 ? P[k0 + 1] : R(0);
+            const R p2 = k0 + 2 < k1 ? P[k0 + 2] : R(0);
+            const R p3 = k0 + 3 < k1 ? P[k0 + 3] : R(0);
+            r = ((p0 + p1) + p2) + p3;
+            for (int32_t k = k0 + 4; k < k1; ++k) r += P[k];
         } else {
             R *rr = (R *)d.r;
             r = rr[g];
@@ -441,9 +449,18 @@ __global__ __launch_bounds__(NODE_THREADS) void k_state(Dev d, int parity) {
     reduce_diag(d, acc, blockIdx.x);
 }
 
+// plain copy, four 16-byte words in flight per thread
 __global__ __launch_bounds__(256) void k_copy(float4 *__restrict__ dst, const float4 *__restrict__ src, int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        dst[i] = src[i];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n; i += 4 * stride) {
+        const float4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], e = src[i + 3 * stride];
+        dst[i] = a;
+        dst[i + stride] = b;
+        dst[i + 2 * stride] = c;
+        dst[i + 3 * stride] = e;
+    }
+    for (; i < n; i += stride) dst[i] = src[i];
 }
 
 template <class R, int NEN>
@@ -501,7 +518,9 @@ hipError_t set_block_lds_limit(int prec, int nen, size_t bytes) {
 }
 
 hipError_t enqueue_copy(void *dst, const void *src, int64_t n16, hipStream_t s) {
-    hipLaunchKernelGGL(k_copy, dim3(2048), dim3(256), 0, s, (float4 *)dst, (const float4 *)src, n16);
+    const int64_t want = (n16 + 4 * 256 - 1) / (4 * 256);
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, 256 * 32));
+    hipLaunchKernelGGL(k_copy, dim3(grid), dim3(256), 0, s, (float4 *)dst, (const float4 *)src, n16);
     return hipGetLastError();
 }
 
