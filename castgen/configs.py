@@ -219,3 +219,65 @@ def config4_trajectory(seed, n=16):
     """Alloy cube with a convective chill (h, 25 C) on x = 0 and a uniform pour temperature."""
     T_pour, h = chill_params(seed)
     return hex_cube(n=n, T_pour=T_pour, noise_amp=0.0, dirichlet_x0=None, robin_x0=(h, 25.0))
+
+
+def batch_scenarios(n_scen=256, seed=4, elems_range=(20000, 400000), n_range=None):
+    """Parameters of a batch of casting scenarios (one dict per scenario).
+
+    Scenario s uses seed 4000 + s for its jitter and numbering; its size is drawn as
+    E_s ~ U(elems_range) and n_s = round((E_s / 6)^(1/3)) cubes per axis (or n_s
+    ~ U{n_range} when given); pour temperature U(680, 760) C, contact coefficient
+    log-uniform on [300, 3000] W/m^2K, mould conductivity U(0.4, 1.5) W/mK.
+    """
+    u = rng.uniform(seed, 21, 4 * n_scen).reshape(n_scen, 4)
+    out = []
+    for s in range(n_scen):
+        if n_range is None:
+            E_s = elems_range[0] + (elems_range[1] - elems_range[0]) * u[s, 0]
+            n_s = int(round((E_s / 6.0) ** (1.0 / 3.0)))
+        else:
+            n_s = int(n_range[0] + min(int(u[s, 0] * (n_range[1] - n_range[0] + 1)), n_range[1] - n_range[0]))
+        out.append(dict(
+            n=n_s, seed=4000 + s,
+            T_pour=680.0 + 80.0 * u[s, 1],
+            h_interface=float(np.exp(np.log(300.0) + (np.log(3000.0) - np.log(300.0)) * u[s, 2])),
+            k_mold=0.4 + 1.1 * u[s, 3]))
+    return out
+
+
+def batch(n_scen=256, seed=4, elems_range=(20000, 400000), n_range=None, permute=True):
+    """A batch of cast+mould scenarios as one disjoint problem.
+
+    Scenario s owns materials 2s (alloy) and 2s+1 (its sand mould); node and
+    element ranges of every scenario are listed in meta['scenarios'] (input
+    numbering: nodes [node0, node1), elements [elem0, elem1)).
+    """
+    params = batch_scenarios(n_scen, seed, elems_range, n_range)
+    parts = []
+    mats = []
+    n0 = e0 = 0
+    for s, sp in enumerate(params):
+        mold = (sp["k_mold"], SAND[1], SAND[2], SAND[3], SAND[4], SAND[5])
+        p = tet_casting(n=sp["n"], region="cube", jitter_seed=sp["seed"], perm_seed=sp["seed"],
+                        T_pour=sp["T_pour"], h_interface=sp["h_interface"], alloy=ALLOY, mold=mold,
+                        permute=permute)
+        N, E = p["xyz"].shape[0], p["conn"].shape[0]
+        sp.update(node0=n0, node1=n0 + N, elem0=e0, elem1=e0 + E, mat_cast=2 * s, mat_mold=2 * s + 1)
+        parts.append((p, n0))
+        mats += [ALLOY, mold]
+        n0 += N
+        e0 += E
+    cat = lambda key, shift: np.concatenate([q[key] + (off if shift else 0) for q, off in parts], axis=0)
+    prob = dict(
+        elem_type=4,
+        xyz=np.concatenate([q["xyz"] for q, _ in parts], axis=0),
+        conn=np.concatenate([q["conn"] + off for q, off in parts], axis=0).astype(np.int32),
+        elem_mat=np.concatenate([q["elem_mat"] + 2 * s for s, (q, _) in enumerate(parts)]).astype(np.int32),
+        materials=np.array(mats, dtype=np.float64),
+        T0=np.concatenate([q["T0"] for q, _ in parts]),
+        if_a=np.concatenate([q["if_a"] + off for q, off in parts], axis=0).astype(np.int32),
+        if_b=np.concatenate([q["if_b"] + off for q, off in parts], axis=0).astype(np.int32),
+        if_h=np.concatenate([q["if_h"] for q, _ in parts]),
+        mat_scenario=np.repeat(np.arange(n_scen, dtype=np.int32), 2),
+        meta=dict(kind="batch", n_scen=n_scen, seed=seed, scenarios=params))
+    return _empty_faces(prob)

@@ -111,7 +111,7 @@ typedef struct {
     int64_t n_liquid;        /* phase-change nodes with fraction solid < 1 */
     int64_t nonfinite;       /* nodes whose enthalpy is NaN or Inf */
     int64_t steps;           /* steps taken since the initial state */
-    double time;             /* simulated time (s) */
+    double time;             /* simulated time (s); the largest over scenarios for a batch */
 } fem_energy_report;
 
 typedef struct {
@@ -163,6 +163,14 @@ int fem_set_interface(fem_ctx *ctx, int64_t npairs, const int32_t *face_a, const
                       const double *h_i);
 /* Initial temperature of every node (Eq. 2); fixed nodes take their value. */
 int fem_set_initial_T(fem_ctx *ctx, const double *T0);
+/* Batch of independent casting scenarios in one mesh: material_scenario[m]
+ * (one entry per material, set after fem_set_materials) names the scenario of
+ * material m, 0 <= id < n_scen, every scenario owning at least one material.
+ * Elements of different scenarios may not share nodes and no interface pair
+ * may join two scenarios (checked by fem_finalize, FEM_E_MESH).  Each
+ * scenario has its own time step (fem_step_batch), stability bound and energy
+ * balance.  Without this call the whole problem is scenario 0. */
+int fem_set_scenarios(fem_ctx *ctx, int32_t n_scen, const int32_t *material_scenario);
 
 /* Validate, lump, reorder, block, colour and bound dt (host work only, no
  * device call).  rep may be NULL. */
@@ -186,6 +194,11 @@ int fem_stable_dt(const fem_ctx *ctx, double *dt);
 /* n_steps explicit steps of size dt (Eq. 14 in enthalpy form), enqueued on the
  * stream; repeated calls reuse a captured hipGraph. */
 int fem_step(fem_ctx *ctx, double dt, int64_t n_steps);
+/* Stability bound of every scenario (n_scen doubles). */
+int fem_stable_dt_scenarios(const fem_ctx *ctx, double *dt_bounds);
+/* n_steps steps of every scenario at once, scenario s with its own dt
+ * (dt_per_scenario[n_scen]); each checked against that scenario's bound. */
+int fem_step_batch(fem_ctx *ctx, const double *dt_per_scenario, int64_t n_steps);
 
 /* ------------------------------------------------------------ read-back */
 /* Temperature / fraction solid / enthalpy of every node in the caller's
@@ -194,8 +207,11 @@ int fem_read_T(fem_ctx *ctx, double *T_host);
 int fem_read_fs(fem_ctx *ctx, double *fs_host);
 int fem_read_H(fem_ctx *ctx, double *H_host);
 /* FP64 energy balance of the current state (wavefront partials summed in a
- * fixed order).  Synchronous. */
+ * fixed order), over all scenarios.  Synchronous; FEM_E_NONFINITE if any
+ * enthalpy is NaN or Inf. */
 int fem_energy(fem_ctx *ctx, fem_energy_report *rep);
+/* The same per scenario: reps[n_scen]. */
+int fem_energy_scenarios(fem_ctx *ctx, fem_energy_report *reps);
 /* Checkpoint of the evolving state (enthalpy, its compensation, both
  * temperature buffers, step count, time, energy budget).  With buf == NULL
  * *bytes receives the size. */

@@ -32,7 +32,8 @@ EXPORTS = [
     "fem_set_dirichlet", "fem_set_flux_faces", "fem_set_interface", "fem_set_initial_T", "fem_finalize",
     "fem_query_buffers", "fem_bind_buffers", "fem_get_report", "fem_stable_dt", "fem_step", "fem_read_T",
     "fem_read_fs", "fem_read_H", "fem_energy", "fem_read_state", "fem_write_state", "fem_get_node_perm",
-    "fem_time_kernels", "fem_copy_kernel",
+    "fem_time_kernels", "fem_copy_kernel", "fem_set_scenarios", "fem_stable_dt_scenarios", "fem_step_batch",
+    "fem_energy_scenarios",
 ]
 
 
@@ -103,6 +104,8 @@ def lib():
             "fem_read_T": [vp, vp], "fem_read_fs": [vp, vp], "fem_read_H": [vp, vp], "fem_energy": [vp, vp],
             "fem_read_state": [vp, vp, vp], "fem_write_state": [vp, vp, i64], "fem_get_node_perm": [vp, vp],
             "fem_time_kernels": [vp, dp, i64, vp], "fem_copy_kernel": [vp, vp, vp, i64, i32, vp],
+            "fem_set_scenarios": [vp, i32, vp], "fem_stable_dt_scenarios": [vp, vp],
+            "fem_step_batch": [vp, vp, i64], "fem_energy_scenarios": [vp, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -179,6 +182,28 @@ def fem_set_interface(ctx, face_a, face_b, h):
 def fem_set_initial_T(ctx, T0):
     t = np.ascontiguousarray(T0, np.float64)
     _call("fem_set_initial_T", ctx, _p(t))
+
+
+def fem_set_scenarios(ctx, material_scenario):
+    ms = np.ascontiguousarray(material_scenario, np.int32)
+    _call("fem_set_scenarios", ctx, int(ms.max()) + 1, _p(ms))
+
+
+def fem_stable_dt_scenarios(ctx, n_scen):
+    out = np.empty(n_scen, np.float64)
+    _call("fem_stable_dt_scenarios", ctx, _p(out))
+    return out
+
+
+def fem_step_batch(ctx, dt_per_scenario, n_steps):
+    dt = np.ascontiguousarray(dt_per_scenario, np.float64)
+    _call("fem_step_batch", ctx, _p(dt), int(n_steps))
+
+
+def fem_energy_scenarios(ctx, n_scen):
+    arr = (fem_energy_report * n_scen)()
+    _call("fem_energy_scenarios", ctx, arr)
+    return [_as_dict(r) for r in arr]
 
 
 def fem_finalize(ctx):
@@ -291,6 +316,8 @@ def setup_problem(ctx, prob):
     if np.size(prob.get("if_h", [])):
         fem_set_interface(ctx, prob["if_a"], prob["if_b"], prob["if_h"])
     fem_set_initial_T(ctx, prob["T0"])
+    if "mat_scenario" in prob:
+        fem_set_scenarios(ctx, prob["mat_scenario"])
     return fem_finalize(ctx)
 
 
@@ -306,6 +333,7 @@ class Solver:
         self.device = torch.device("cuda", device)
         self.n_nodes = prob["xyz"].shape[0]
         self.n_elems = prob["conn"].shape[0]
+        self.n_scen = int(np.max(prob["mat_scenario"])) + 1 if "mat_scenario" in prob else 1
         self.ctx = fem_create(make_options(device=device, **opts))
         self.report = setup_problem(self.ctx, prob)
         self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
@@ -341,6 +369,15 @@ class Solver:
 
     def energy(self):
         return fem_energy(self.ctx)
+
+    def stable_dt_scenarios(self):
+        return fem_stable_dt_scenarios(self.ctx, self.n_scen)
+
+    def step_batch(self, dt_per_scenario, n):
+        fem_step_batch(self.ctx, dt_per_scenario, n)
+
+    def energy_scenarios(self):
+        return fem_energy_scenarios(self.ctx, self.n_scen)
 
     def node_perm(self):
         return fem_get_node_perm(self.ctx, self.n_nodes)

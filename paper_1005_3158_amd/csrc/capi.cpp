@@ -33,11 +33,11 @@ enum Stage { ST_NEW = 0, ST_FINAL = 1, ST_BOUND = 2 };
 
 enum Buf {
     B_NODE_X, B_T, B_H, B_INV_M, B_FS, B_MATS, B_CONN, B_R, B_LCONN, B_BLOCKS, B_SH_LIST, B_PARTIALS,
-    B_COMB_PTR, B_SH_POS, B_ROBIN, B_LINK_PTR, B_LINK_NODE, B_LINK_W, B_DIAG, B_QACC, B_FLAGS, B_COUNT
+    B_COMB_PTR, B_SH_POS, B_ROBIN, B_LINK_PTR, B_LINK_NODE, B_LINK_W, B_DIAG, B_QNODE, B_FLAGS, B_SEG, B_COUNT
 };
 const char *BUF_NAMES[B_COUNT] = {"node_x", "T", "H", "inv_m", "fs", "mats", "conn", "r", "lconn", "blocks",
                                   "sh_list", "partials", "comb_ptr", "sh_pos", "robin", "link_ptr",
-                                  "link_node", "link_w", "diag", "qacc", "flags"};
+                                  "link_node", "link_w", "diag", "qnode", "flags", "segments"};
 constexpr int64_t ALIGN = 256;
 constexpr int GRAPH_STEPS = 16;  // steps per captured graph (even: both parities)
 constexpr size_t MAX_BLOCK_LDS = 160 * 1024 - 2048;  // gfx950 LDS per workgroup, less static use
@@ -103,12 +103,12 @@ struct fem_ctx {
     void *ptr[B_COUNT] = {};
     Dev dev;
     std::vector<MatDev> mats_host;
-    double dt_cur = -1.0;
     int parity = 0;
     int64_t steps = 0;
-    double time = 0.0;
     double E0 = 0, Eref = 0, lat0 = 0, tmin0 = 0, tmax0 = 0;
     int64_t nliq0 = 0;
+    // per scenario (a single problem is scenario 0)
+    std::vector<double> E0_s, Eref_s, time_s, dt_s;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     double setup_seconds = 0;
@@ -150,8 +150,10 @@ void layout_sizes(const fem_ctx *c, const Layout &L, int64_t *sz) {
     sz[B_LINK_PTR] = (L.n_bc_slots + 1) * 4;
     sz[B_LINK_NODE] = (int64_t)L.link_node.size() * 4;
     sz[B_LINK_W] = (int64_t)L.link_w.size() * R;
-    sz[B_DIAG] = node_grid(N) * NDIAG * 8;
-    sz[B_QACC] = node_grid(blocked ? N - L.n_private : N) * 2 * 8;
+    const int64_t nseg = (int64_t)L.seg_scen.size();
+    sz[B_DIAG] = nseg * NDIAG * 8;
+    sz[B_QNODE] = L.n_inflow * 8;
+    sz[B_SEG] = (nseg + 1) * 4;
     sz[B_FLAGS] = N * 4;
 }
 
@@ -170,6 +172,8 @@ void upload_layout_t(fem_ctx *c, const Layout &L) {
     std::vector<R> im(N), T2(2 * N), fs(N);
     std::vector<uint8_t> H(N * 8);
     c->E0 = c->Eref = c->lat0 = 0;
+    c->E0_s.assign(c->prob.n_scen, 0.0);
+    c->Eref_s.assign(c->prob.n_scen, 0.0);
     c->tmin0 = INFINITY;
     c->tmax0 = -INFINITY;
     c->nliq0 = 0;
@@ -202,6 +206,9 @@ void upload_layout_t(fem_ctx *c, const Layout &L) {
         T2[n] = T2[N + n] = (R)T;
         fs[n] = (R)f_s;
         const double m = 1.0 / (double)im[n];
+        const int32_t sc = c->prob.scen_of_mat((int32_t)(f & NODE_MAT_MASK));
+        c->E0_s[sc] += m * hd;
+        c->Eref_s[sc] += m * h_of_t(mat, 25.0);
         c->E0 += m * hd;
         c->Eref += m * h_of_t(mat, 25.0);
         c->lat0 += m * mat.L * (1.0 - f_s);
@@ -238,7 +245,8 @@ void upload_layout_t(fem_ctx *c, const Layout &L) {
     int64_t sz[B_COUNT];
     layout_sizes(c, L, sz);
     HIPCHECK(hipMemsetAsync(c->ptr[B_DIAG], 0, sz[B_DIAG], c->stream));
-    HIPCHECK(hipMemsetAsync(c->ptr[B_QACC], 0, sz[B_QACC], c->stream));
+    if (sz[B_QNODE]) HIPCHECK(hipMemsetAsync(c->ptr[B_QNODE], 0, sz[B_QNODE], c->stream));
+    h2d(c, B_SEG, L.seg_begin.data(), (int64_t)L.seg_begin.size() * 4);
     // the host vectors above must outlive the copies
     HIPCHECK(hipStreamSynchronize(c->stream));
 }
@@ -271,7 +279,9 @@ void fill_dev(fem_ctx *c, const Candidate &cd) {
     d.link_node = (const int32_t *)c->ptr[B_LINK_NODE];
     d.link_w = c->ptr[B_LINK_W];
     d.diag = (double *)c->ptr[B_DIAG];
-    d.qacc = (double *)c->ptr[B_QACC];
+    d.qnode = (double *)c->ptr[B_QNODE];
+    d.seg_begin = (const int32_t *)c->ptr[B_SEG];
+    d.n_seg = (int64_t)L.seg_scen.size();
     d.n_inflow = L.n_inflow;
     d.n_mat = (int32_t)c->prob.mats.size();
     d.n_private = L.n_private;
@@ -292,8 +302,6 @@ void fill_dev(fem_ctx *c, const Candidate &cd) {
         d.fx_inv = std::ldexp(1.0, -S);
         d.fx_limit = (float)std::ldexp(1.0, 50 - S);
     }
-    const bool blocked = d.scatter == FEM_SCATTER_LDS_BLOCKED;
-    d.node_blocks = node_grid(blocked ? d.N - d.n_private : d.N);
     c->dev = d;
 }
 
@@ -304,13 +312,17 @@ void reset_graph(fem_ctx *c) {
     c->graph = nullptr;
 }
 
-void set_dt(fem_ctx *c, double dt) {
-    if (dt == c->dt_cur) return;
-    for (size_t q = 0; q < c->prob.mats.size(); ++q) c->mats_host[q] = make_mat(c->prob.mats[q], dt);
+// time step of every scenario, written into the material table the kernels read
+void set_dt_scen(fem_ctx *c, const std::vector<double> &dt) {
+    if (dt == c->dt_s) return;
+    for (size_t q = 0; q < c->prob.mats.size(); ++q)
+        c->mats_host[q] = make_mat(c->prob.mats[q], dt[c->prob.scen_of_mat((int32_t)q)]);
     h2d(c, B_MATS, c->mats_host.data(), (int64_t)(c->mats_host.size() * sizeof(MatDev)));
     HIPCHECK(hipStreamSynchronize(c->stream));
-    c->dt_cur = dt;
+    c->dt_s = dt;
 }
+
+void set_dt(fem_ctx *c, double dt) { set_dt_scen(c, std::vector<double>(c->prob.n_scen, dt)); }
 
 void eager_steps(fem_ctx *c, int64_t n) {
     for (int64_t s = 0; s < n; ++s) {
@@ -628,7 +640,7 @@ int fem_bind_buffers(fem_ctx *ctx, void *const *dev_ptrs, int32_t n) {
             if (mx + 1024 > cap) throw PrepError{FEM_E_UNSUPPORTED, "block LDS footprint above the device limit"};
             HIPCHECK(set_block_lds_limit(ctx->opt.precision, ctx->prob.nen, mx));
         }
-        ctx->dt_cur = -1.0;
+        ctx->dt_s.clear();
         if (ctx->cands.size() > 1) {
             // timed trial steps per candidate layout; keep the fastest
             const double dt = 0.5 * ctx->base.dt_bound;
@@ -661,10 +673,10 @@ int fem_bind_buffers(fem_ctx *ctx, void *const *dev_ptrs, int32_t n) {
         if (ctx->opt.precision == FEM_PREC_FP64) upload_layout_t<double>(ctx, ctx->L());
         else upload_layout_t<float>(ctx, ctx->L());
         fill_dev(ctx, ctx->cands[ctx->chosen]);
-        ctx->dt_cur = -1.0;
+        ctx->dt_s.clear();
+        ctx->time_s.assign(ctx->prob.n_scen, 0.0);
         ctx->parity = 0;
         ctx->steps = 0;
-        ctx->time = 0.0;
         // drop the layouts that lost the trial
         Candidate keep = std::move(ctx->cands[ctx->chosen]);
         ctx->cands.clear();
@@ -692,8 +704,52 @@ int fem_step(fem_ctx *ctx, double dt, int64_t n_steps) {
         set_dt(ctx, dt);
         run_steps(ctx, n_steps);
         ctx->steps += n_steps;
-        ctx->time += dt * (double)n_steps;
+        for (double &t : ctx->time_s) t += dt * (double)n_steps;
     });
+}
+
+int fem_step_batch(fem_ctx *ctx, const double *dt_per_scenario, int64_t n_steps) {
+    if (!ctx || !dt_per_scenario) return set_err(FEM_E_INVALID_ARG, "null argument");
+    return guarded([&] {
+        check_bound(ctx, ST_BOUND);
+        if (n_steps < 0) throw PrepError{FEM_E_INVALID_ARG, "n_steps must be >= 0"};
+        std::vector<double> dt(dt_per_scenario, dt_per_scenario + ctx->prob.n_scen);
+        for (int32_t sc = 0; sc < ctx->prob.n_scen; ++sc) {
+            if (!(dt[sc] > 0) || !std::isfinite(dt[sc])) throw PrepError{FEM_E_INVALID_ARG, "every dt must be > 0"};
+            if (dt[sc] > ctx->base.dt_scen[sc] && !ctx->opt.allow_unstable)
+                throw PrepError{FEM_E_UNSTABLE, "dt of scenario " + std::to_string(sc) + " above its stability bound"};
+        }
+        set_dt_scen(ctx, dt);
+        run_steps(ctx, n_steps);
+        ctx->steps += n_steps;
+        for (int32_t sc = 0; sc < ctx->prob.n_scen; ++sc) ctx->time_s[sc] += dt[sc] * (double)n_steps;
+    });
+}
+
+int fem_set_scenarios(fem_ctx *ctx, int32_t n_scen, const int32_t *material_scenario) {
+    if (!ctx) return set_err(FEM_E_INVALID_ARG, "ctx is null");
+    return guarded([&] {
+        if (ctx->stage != ST_NEW) throw PrepError{FEM_E_STATE, "scenarios must be set before fem_finalize"};
+        if (ctx->prob.mats.empty()) throw PrepError{FEM_E_STATE, "set the materials first"};
+        if (n_scen < 1 || !material_scenario) throw PrepError{FEM_E_INVALID_ARG, "bad scenario table"};
+        std::vector<int32_t> ms(material_scenario, material_scenario + ctx->prob.mats.size());
+        std::vector<char> used(n_scen, 0);
+        for (int32_t sc : ms) {
+            if (sc < 0 || sc >= n_scen) throw PrepError{FEM_E_INVALID_ARG, "scenario id out of range"};
+            used[sc] = 1;
+        }
+        for (char u : used)
+            if (!u) throw PrepError{FEM_E_INVALID_ARG, "every scenario needs at least one material"};
+        ctx->prob.n_scen = n_scen;
+        ctx->prob.mat_scen = std::move(ms);
+    });
+}
+
+int fem_stable_dt_scenarios(const fem_ctx *ctx, double *dt_bounds) {
+    if (!ctx || !dt_bounds) return set_err(FEM_E_INVALID_ARG, "null argument");
+    if (ctx->stage < ST_FINAL) return set_err(FEM_E_STATE, "call fem_finalize first");
+    for (int32_t sc = 0; sc < ctx->prob.n_scen; ++sc) dt_bounds[sc] = ctx->base.dt_scen[sc];
+    return FEM_OK;
 }
 
 }  // extern "C"
@@ -755,66 +811,123 @@ int fem_read_H(fem_ctx *ctx, double *H_host) {
     });
 }
 
+}  // extern "C"
+
+namespace {
+
+// FP64 energy balance per scenario (reps[n_scen]): on-demand state reduction
+// over single-scenario node segments plus the per-node inflow sums, all summed
+// on the host in a fixed order
+void energy_scenarios(fem_ctx *ctx, fem_energy_report *reps) {
+    const int32_t ns = ctx->prob.n_scen;
+    const Layout &L = ctx->L();
+    const int64_t S = (int64_t)L.seg_scen.size(), Q = L.n_inflow;
+    std::vector<double> dg(S * NDIAG), qn(Q);
+    HIPCHECK(enqueue_state_diag(ctx->dev, ctx->parity, ctx->stream));
+    HIPCHECK(hipMemcpyAsync(dg.data(), ctx->ptr[B_DIAG], S * NDIAG * 8, hipMemcpyDeviceToHost, ctx->stream));
+    if (Q) HIPCHECK(hipMemcpyAsync(qn.data(), ctx->ptr[B_QNODE], Q * 8, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHECK(hipStreamSynchronize(ctx->stream));
+    HIPCHECK(hipGetLastError());
+    for (int32_t sc = 0; sc < ns; ++sc) {
+        std::memset(&reps[sc], 0, sizeof(fem_energy_report));
+        reps[sc].E0 = ctx->E0_s[sc];
+        reps[sc].T_min = INFINITY;
+        reps[sc].T_max = -INFINITY;
+        reps[sc].steps = ctx->steps;
+        reps[sc].time = ctx->time_s[sc];
+    }
+    std::vector<double> nl(ns, 0.0), nf(ns, 0.0);
+    for (int64_t g = 0; g < S; ++g) {
+        fem_energy_report &r = reps[L.seg_scen[g]];
+        const double *v = &dg[g * NDIAG];
+        r.E += v[DG_E];
+        r.latent += v[DG_LAT];
+        r.T_min = std::min(r.T_min, v[DG_TMIN]);
+        r.T_max = std::max(r.T_max, v[DG_TMAX]);
+        nl[L.seg_scen[g]] += v[DG_NLIQ];
+        nf[L.seg_scen[g]] += v[DG_NONFIN];
+    }
+    for (int64_t q = 0; q < Q; ++q)
+        reps[ctx->prob.scen_of_mat((int32_t)(L.nflag[L.bc_first + q] & NODE_MAT_MASK))].Q_cum += qn[q];
+    for (int32_t sc = 0; sc < ns; ++sc) {
+        fem_energy_report &r = reps[sc];
+        r.n_liquid = (int64_t)nl[sc];
+        r.nonfinite = (int64_t)nf[sc];
+        r.residual = std::fabs(r.E - r.E0 - r.Q_cum) / std::fabs(r.E0 - ctx->Eref_s[sc]);
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
 int fem_energy(fem_ctx *ctx, fem_energy_report *rep) {
     if (!ctx || !rep) return set_err(FEM_E_INVALID_ARG, "null argument");
     return guarded([&] {
         check_bound(ctx, ST_BOUND);
+        std::vector<fem_energy_report> r(ctx->prob.n_scen);
+        energy_scenarios(ctx, r.data());
+        // the whole problem: sums over scenarios in order
         std::memset(rep, 0, sizeof(*rep));
-        rep->E0 = ctx->E0;
-        rep->steps = ctx->steps;
-        rep->time = ctx->time;
-        const int64_t S = node_grid(ctx->dev.N), Q = ctx->dev.node_blocks;
-        std::vector<double> dg(S * NDIAG), qa(2 * Q);
-        HIPCHECK(enqueue_state_diag(ctx->dev, ctx->parity, ctx->stream));
-        HIPCHECK(hipMemcpyAsync(dg.data(), ctx->ptr[B_DIAG], S * NDIAG * 8, hipMemcpyDeviceToHost, ctx->stream));
-        HIPCHECK(hipMemcpyAsync(qa.data(), ctx->ptr[B_QACC], 2 * Q * 8, hipMemcpyDeviceToHost, ctx->stream));
-        HIPCHECK(hipStreamSynchronize(ctx->stream));
-        HIPCHECK(hipGetLastError());
-        double qc = 0, E = 0, lat = 0, nl = 0, nf = 0, tmin = INFINITY, tmax = -INFINITY;
-        for (int64_t b = 0; b < Q; ++b) qc += qa[2 * b + 1];
-        for (int64_t b = 0; b < S; ++b) {
-            const double *v = &dg[b * NDIAG];
-            E += v[DG_E];
-            lat += v[DG_LAT];
-            nl += v[DG_NLIQ];
-            nf += v[DG_NONFIN];
-            tmin = std::min(tmin, v[DG_TMIN]);
-            tmax = std::max(tmax, v[DG_TMAX]);
+        rep->T_min = INFINITY;
+        rep->T_max = -INFINITY;
+        double Eref = 0.0;
+        for (int32_t sc = 0; sc < ctx->prob.n_scen; ++sc) {
+            rep->E += r[sc].E;
+            rep->E0 += r[sc].E0;
+            rep->latent += r[sc].latent;
+            rep->Q_cum += r[sc].Q_cum;
+            rep->T_min = std::min(rep->T_min, r[sc].T_min);
+            rep->T_max = std::max(rep->T_max, r[sc].T_max);
+            rep->n_liquid += r[sc].n_liquid;
+            rep->nonfinite += r[sc].nonfinite;
+            rep->time = std::max(rep->time, r[sc].time);
+            Eref += ctx->Eref_s[sc];
         }
-        rep->Q_cum = qc;
-        rep->E = E;
-        rep->latent = lat;
-        rep->T_min = tmin;
-        rep->T_max = tmax;
-        rep->n_liquid = (int64_t)nl;
-        rep->nonfinite = (int64_t)nf;
-        rep->residual = std::fabs(rep->E - ctx->E0 - rep->Q_cum) / std::fabs(ctx->E0 - ctx->Eref);
+        rep->steps = ctx->steps;
+        rep->residual = std::fabs(rep->E - rep->E0 - rep->Q_cum) / std::fabs(rep->E0 - Eref);
         if (rep->nonfinite > 0 || !std::isfinite(rep->E))
             throw PrepError{FEM_E_NONFINITE, "the state holds non-finite enthalpy at " + std::to_string(rep->nonfinite) + " nodes"};
     });
 }
 
-// checkpoint layout: header, H, T (both buffers), fs, inflow accumulators
+int fem_energy_scenarios(fem_ctx *ctx, fem_energy_report *reps) {
+    if (!ctx || !reps) return set_err(FEM_E_INVALID_ARG, "null argument");
+    return guarded([&] {
+        check_bound(ctx, ST_BOUND);
+        energy_scenarios(ctx, reps);
+        for (int32_t sc = 0; sc < ctx->prob.n_scen; ++sc)
+            if (reps[sc].nonfinite > 0 || !std::isfinite(reps[sc].E))
+                throw PrepError{FEM_E_NONFINITE, "scenario " + std::to_string(sc) + " holds non-finite enthalpy"};
+    });
+}
+
+// checkpoint layout: header, H, T (both buffers), fs, per-node inflow sums,
+// simulated time of every scenario
 struct CkptHeader {
-    uint64_t magic, N, prec, slots;
+    uint64_t magic, N, prec, n_inflow, n_scen;
     int64_t parity, steps;
-    double time, E0, Eref, lat0;
 };
-constexpr uint64_t CKPT_MAGIC = 0x31504B434D454643ull;
+constexpr uint64_t CKPT_MAGIC = 0x32504B434D454643ull;
+
+int64_t ckpt_bytes(const fem_ctx *ctx) {
+    const int64_t N = ctx->L().N, R = (int64_t)ctx->rsize();
+    return (int64_t)sizeof(CkptHeader) + N * 8 + 2 * N * R + N * R + ctx->L().n_inflow * 8 + ctx->prob.n_scen * 8;
+}
 
 int fem_read_state(fem_ctx *ctx, void *buf, int64_t *bytes) {
     if (!ctx || !bytes) return set_err(FEM_E_INVALID_ARG, "null argument");
     return guarded([&] {
         check_bound(ctx, ST_BOUND);
-        const int64_t N = ctx->L().N, R = (int64_t)ctx->rsize(), S = 2 * ctx->dev.node_blocks;
-        const int64_t need = (int64_t)sizeof(CkptHeader) + N * 8 + 2 * N * R + N * R + S * 8;
+        const int64_t N = ctx->L().N, R = (int64_t)ctx->rsize(), Q = ctx->L().n_inflow;
+        const int64_t need = ckpt_bytes(ctx);
         if (!buf) {
             *bytes = need;
             return;
         }
         if (*bytes < need) throw PrepError{FEM_E_INVALID_ARG, "checkpoint buffer too small"};
-        CkptHeader h{CKPT_MAGIC, (uint64_t)N, (uint64_t)ctx->opt.precision, (uint64_t)S, ctx->parity, ctx->steps,
-                     ctx->time, ctx->E0, ctx->Eref, ctx->lat0};
+        CkptHeader h{CKPT_MAGIC, (uint64_t)N, (uint64_t)ctx->opt.precision, (uint64_t)Q, (uint64_t)ctx->prob.n_scen,
+                     ctx->parity, ctx->steps};
         char *p = (char *)buf;
         std::memcpy(p, &h, sizeof h);
         p += sizeof h;
@@ -824,7 +937,9 @@ int fem_read_state(fem_ctx *ctx, void *buf, int64_t *bytes) {
         p += 2 * N * R;
         HIPCHECK(hipMemcpyAsync(p, ctx->ptr[B_FS], N * R, hipMemcpyDeviceToHost, ctx->stream));
         p += N * R;
-        HIPCHECK(hipMemcpyAsync(p, ctx->ptr[B_QACC], S * 8, hipMemcpyDeviceToHost, ctx->stream));
+        if (Q) HIPCHECK(hipMemcpyAsync(p, ctx->ptr[B_QNODE], Q * 8, hipMemcpyDeviceToHost, ctx->stream));
+        p += Q * 8;
+        std::memcpy(p, ctx->time_s.data(), ctx->prob.n_scen * 8);
         HIPCHECK(hipStreamSynchronize(ctx->stream));
         *bytes = need;
     });
@@ -834,12 +949,12 @@ int fem_write_state(fem_ctx *ctx, const void *buf, int64_t bytes) {
     if (!ctx || !buf) return set_err(FEM_E_INVALID_ARG, "null argument");
     return guarded([&] {
         check_bound(ctx, ST_BOUND);
-        const int64_t N = ctx->L().N, R = (int64_t)ctx->rsize(), S = 2 * ctx->dev.node_blocks;
-        const int64_t need = (int64_t)sizeof(CkptHeader) + N * 8 + 2 * N * R + N * R + S * 8;
-        if (bytes < need) throw PrepError{FEM_E_INVALID_ARG, "checkpoint too small"};
+        const int64_t N = ctx->L().N, R = (int64_t)ctx->rsize(), Q = ctx->L().n_inflow;
+        if (bytes < ckpt_bytes(ctx)) throw PrepError{FEM_E_INVALID_ARG, "checkpoint too small"};
         CkptHeader h;
         std::memcpy(&h, buf, sizeof h);
-        if (h.magic != CKPT_MAGIC || h.N != (uint64_t)N || h.prec != (uint64_t)ctx->opt.precision || h.slots != (uint64_t)S)
+        if (h.magic != CKPT_MAGIC || h.N != (uint64_t)N || h.prec != (uint64_t)ctx->opt.precision ||
+            h.n_inflow != (uint64_t)Q || h.n_scen != (uint64_t)ctx->prob.n_scen)
             throw PrepError{FEM_E_INVALID_ARG, "checkpoint does not match this context"};
         const char *p = (const char *)buf + sizeof h;
         HIPCHECK(hipMemcpyAsync(ctx->ptr[B_H], p, N * 8, hipMemcpyHostToDevice, ctx->stream));
@@ -848,14 +963,12 @@ int fem_write_state(fem_ctx *ctx, const void *buf, int64_t bytes) {
         p += 2 * N * R;
         HIPCHECK(hipMemcpyAsync(ctx->ptr[B_FS], p, N * R, hipMemcpyHostToDevice, ctx->stream));
         p += N * R;
-        HIPCHECK(hipMemcpyAsync(ctx->ptr[B_QACC], p, S * 8, hipMemcpyHostToDevice, ctx->stream));
+        if (Q) HIPCHECK(hipMemcpyAsync(ctx->ptr[B_QNODE], p, Q * 8, hipMemcpyHostToDevice, ctx->stream));
+        p += Q * 8;
+        std::memcpy(ctx->time_s.data(), p, ctx->prob.n_scen * 8);
         HIPCHECK(hipStreamSynchronize(ctx->stream));
         ctx->parity = (int)h.parity;
         ctx->steps = h.steps;
-        ctx->time = h.time;
-        ctx->E0 = h.E0;
-        ctx->Eref = h.Eref;
-        ctx->lat0 = h.lat0;
     });
 }
 
@@ -891,7 +1004,7 @@ int fem_time_kernels(fem_ctx *ctx, double dt, int64_t n_steps, fem_kernel_times 
         }
         for (auto &e : ev) (void)hipEventDestroy(e);
         ctx->steps += n_steps;
-        ctx->time += dt * (double)n_steps;
+        for (double &t : ctx->time_s) t += dt * (double)n_steps;
         const Layout &L = ctx->L();
         const double R = (double)ctx->rsize();
         const double gather = 4.0 * R + 4.0;             // xyz + T read + flags

@@ -358,74 +358,54 @@ __global__ __launch_bounds__(1024) void k_block(Dev d, int parity) {
 
 // node phase: all nodes (COMBINE = false: residual from r[N], which is reset)
 // or the shared nodes of the blocked layout (COMBINE = true: sum of the
-// node's contiguous partials, in block order).  Workgroups covering nodes
-// with boundary inflow (the first n_inflow slots) reduce it in FP64.
+// node's contiguous partials, in block order).  The first n_inflow slots may
+// carry boundary inflow (Robin faces, reactions of fixed temperatures); each
+// of them accumulates its own FP64 sum of dt * inflow, so no reduction runs
+// per step and the total does not depend on the schedule.
 template <class R, bool COMBINE>
 __global__ __launch_bounds__(NODE_THREADS) void k_nodes(Dev d, int parity) {
     __shared__ MatDev s_mats[LDS_MATS];
-    __shared__ double s_q[NODE_THREADS / 64][2];
     const int64_t count = COMBINE ? d.N - d.n_private : d.N;
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool inflow_block = (int64_t)blockIdx.x * blockDim.x < d.n_inflow;
-    double cum_old = 0.0;
-    if (inflow_block && threadIdx.x == 0) cum_old = d.qacc[2 * blockIdx.x + 1];   // issued early
     const MatDev *mats = stage_mats(d, s_mats);
     __syncthreads();
-    double q = 0.0, qdt = 0.0;
-    if (s < count) {
-        const int64_t g = d.bc_first + s;
-        const R *Tc = (const R *)d.T + parity * d.N;
-        R *Tn = (R *)d.T + (1 - parity) * d.N;
-        const uint32_t f = d.flags[g];
-        R r;
-        if (COMBINE) {
-            // most shared nodes sit in two to four blocks: issue the first
-            // four loads together, then sum in block order
-            const R *P = (const R *)d.partials;
-            const int32_t k0 = d.comb_ptr[s], k1 = d.comb_ptr[s + 1];
-            const R p0 = P[k0];                        // every shared node has a partial
-            const R p1 = k0 + 1 < k1 ? P[k0 + 1] : R(0);
-            const R p2 = k0 + 2 < k1 ? P[k0 + 2] : R(0);
-            const R p3 = k0 + 3 < k1 ? P[k0 + 3] : R(0);
-            r = ((p0 + p1) + p2) + p3;
-            for (int32_t k = k0 + 4; k < k1; ++k) r += P[k];
-        } else {
-            R *rr = (R *)d.r;
-            r = rr[g];
-            rr[g] = R(0);
-        }
-        if (f & NODE_BC) q = boundary_terms<R>(d, s, Tc[g], Tc, r);
-        if (f & NODE_FIXED) q -= (double)r;     // reaction of a fixed temperature
-        else Node<R>::update(d, mats, g, r, f, Tn);
-        qdt = q * mats[f & NODE_MAT_MASK].dt;
+    if (s >= count) return;
+    const int64_t g = d.bc_first + s;
+    const R *Tc = (const R *)d.T + parity * d.N;
+    R *Tn = (R *)d.T + (1 - parity) * d.N;
+    const uint32_t f = d.flags[g];
+    R r;
+    if (COMBINE) {
+        // most shared nodes sit in two to four blocks: issue the first four
+        // loads together, then sum in block order
+        const R *P = (const R *)d.partials;
+        const int32_t k0 = d.comb_ptr[s], k1 = d.comb_ptr[s + 1];
+        const R p0 = P[k0];                        // every shared node has a partial
+        const R p1 = k0 + 1 < k1 ? P[k0 + 1] : R(0);
+        const R p2 = k0 + 2 < k1 ? P[k0 + 2] : R(0);
+        const R p3 = k0 + 3 < k1 ? P[k0 + 3] : R(0);
+        r = ((p0 + p1) + p2) + p3;
+        for (int32_t k = k0 + 4; k < k1; ++k) r += P[k];
+    } else {
+        R *rr = (R *)d.r;
+        r = rr[g];
+        rr[g] = R(0);
     }
-    if (inflow_block) {
-        q = wave_sum(q);
-        qdt = wave_sum(qdt);
-        if ((threadIdx.x & 63) == 0) {
-            s_q[threadIdx.x >> 6][0] = q;
-            s_q[threadIdx.x >> 6][1] = qdt;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double Q = 0.0, QD = 0.0;
-            for (int w = 0; w < NODE_THREADS / 64; ++w) {
-                Q += s_q[w][0];
-                QD += s_q[w][1];
-            }
-            d.qacc[2 * blockIdx.x] = Q;
-            d.qacc[2 * blockIdx.x + 1] = cum_old + QD;
-        }
-    }
+    double q = 0.0;
+    if (f & NODE_BC) q = boundary_terms<R>(d, s, Tc[g], Tc, r);
+    if (f & NODE_FIXED) q -= (double)r;     // reaction of a fixed temperature
+    else Node<R>::update(d, mats, g, r, f, Tn);
+    if (s < d.n_inflow) d.qnode[s] += q * mats[f & NODE_MAT_MASK].dt;
 }
 
-// state diagnostics on demand: E, latent heat, T range, liquid and non-finite counts
+// state diagnostics on demand: one workgroup per single-scenario node segment
+// (E, latent heat still to release, T range, liquid and non-finite counts)
 template <class R>
 __global__ __launch_bounds__(NODE_THREADS) void k_state(Dev d, int parity) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     DiagAcc acc;
     acc.init();
-    if (i < d.N) {
+    const int32_t n0 = d.seg_begin[blockIdx.x], n1 = d.seg_begin[blockIdx.x + 1];
+    for (int64_t i = n0 + (int64_t)threadIdx.x; i < n1; i += blockDim.x) {
         const uint32_t f = d.flags[i];
         const MatDev &M = d.mats[f & NODE_MAT_MASK];
         double H;
@@ -439,12 +419,12 @@ __global__ __launch_bounds__(NODE_THREADS) void k_state(Dev d, int parity) {
         const double T = (double)((const R *)d.T)[parity * d.N + i];
         double Th, fs;
         t_of_h(M, H, Th, fs);
-        acc.v[DG_E] = m * H;
-        acc.v[DG_LAT] = m * M.L * (1.0 - fs);
-        acc.v[DG_TMIN] = T;
-        acc.v[DG_TMAX] = T;
-        acc.v[DG_NLIQ] = (M.latent && fs < 1.0) ? 1.0 : 0.0;
-        acc.v[DG_NONFIN] = isfinite(H) ? 0.0 : 1.0;
+        acc.v[DG_E] += m * H;
+        acc.v[DG_LAT] += m * M.L * (1.0 - fs);
+        acc.v[DG_TMIN] = fmin(acc.v[DG_TMIN], T);
+        acc.v[DG_TMAX] = fmax(acc.v[DG_TMAX], T);
+        acc.v[DG_NLIQ] += (M.latent && fs < 1.0) ? 1.0 : 0.0;
+        acc.v[DG_NONFIN] += isfinite(H) ? 0.0 : 1.0;
     }
     reduce_diag(d, acc, blockIdx.x);
 }
@@ -504,7 +484,7 @@ hipError_t enqueue_step(const Dev &d, int parity, hipStream_t s, hipEvent_t *ev)
 }
 
 hipError_t enqueue_state_diag(const Dev &d, int parity, hipStream_t s) {
-    const unsigned grid = (unsigned)node_grid(d.N);
+    const unsigned grid = (unsigned)d.n_seg;
     if (d.prec == FEM_PREC_FP64) hipLaunchKernelGGL((k_state<double>), dim3(grid), dim3(NODE_THREADS), 0, s, d, parity);
     else hipLaunchKernelGGL((k_state<float>), dim3(grid), dim3(NODE_THREADS), 0, s, d, parity);
     return hipGetLastError();

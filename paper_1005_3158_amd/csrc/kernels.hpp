@@ -46,9 +46,11 @@ struct Dev {
     const int32_t *link_ptr = nullptr, *link_node = nullptr;
     const void *link_w = nullptr;       // R per link
     // diagnostics
-    double *diag = nullptr;             // state diagnostics: NDIAG per node-grid workgroup
-    double *qacc = nullptr;             // per node-kernel workgroup: inflow of the last step, sum of dt * inflow
+    double *diag = nullptr;             // state diagnostics: NDIAG per node segment
+    double *qnode = nullptr;            // per inflow slot: sum over steps of dt * boundary inflow
     int64_t n_inflow = 0;               // node-kernel slots 0..n_inflow-1 may carry boundary inflow
+    const int32_t *seg_begin = nullptr; // single-scenario node segments
+    int64_t n_seg = 0;
     int32_t n_mat = 0;
     // sizes and launch shape
     int64_t n_private = 0, n_blocks = 0, n_bc_slots = 0, bc_first = 0;

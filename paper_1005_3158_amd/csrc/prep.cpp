@@ -136,6 +136,11 @@ void prep_base(const Problem &p, Base &b) {
     }
     for (int64_t i = 0; i < N; ++i)
         if (b.nmat[i] < 0) fail(FEM_E_MESH, "node " + std::to_string(i) + " is in no element");
+    if (!p.mat_scen.empty()) {
+        if ((int64_t)p.mat_scen.size() != (int64_t)p.mats.size()) fail(FEM_E_STATE, "scenario table does not match the materials");
+        for (int32_t sc : p.mat_scen)
+            if (sc < 0 || sc >= p.n_scen) fail(FEM_E_INVALID_ARG, "scenario id out of range");
+    }
     tm.mark("node materials");
     // lumped capacitance, element orientation
     b.m.assign(N, 0.0);
@@ -196,6 +201,8 @@ void prep_base(const Problem &p, Base &b) {
         const int32_t *fa = &p.if_a[3 * f], *fb = &p.if_b[3 * f];
         for (int a = 0; a < 3; ++a)
             if (fa[a] < 0 || fa[a] >= N || fb[a] < 0 || fb[a] >= N) fail(FEM_E_MESH, "interface face node out of range");
+        if (p.scen_of_mat(b.nmat[fa[0]]) != p.scen_of_mat(b.nmat[fb[0]]))
+            fail(FEM_E_MESH, "interface pair " + std::to_string(f) + " joins two scenarios");
         double A = face_area(p.xyz, fa, 3);
         double w = p.if_h[f] * A / 9.0;
         for (int a = 0; a < 3; ++a)
@@ -224,10 +231,12 @@ void prep_base(const Problem &p, Base &b) {
     node_elem_csr(p, ptr, inc);
     tm.mark("node-element lists");
     double lam = 0.0;
+    std::vector<double> lam_s(p.n_scen, 0.0);
 #pragma omp parallel
     {
         std::vector<int32_t> cols;
         std::vector<double> vals;
+        std::vector<double> lam_st(p.n_scen, 0.0);
         double lam_t = 0.0, eabs_t = 0.0;
 #pragma omp for schedule(dynamic, 4096)
         for (int64_t i = 0; i < N; ++i) {
@@ -257,14 +266,19 @@ void prep_base(const Problem &p, Base &b) {
             for (int32_t s = b.lptr[i]; s < b.lptr[i + 1]; ++s) row += 2.0 * b.lw[s];
             double li = row / (b.m[i] * p.mats[b.nmat[i]].c);
             if (li > lam_t) lam_t = li;
+            const int32_t sc = p.scen_of_mat(b.nmat[i]);
+            if (li > lam_st[sc]) lam_st[sc] = li;
         }
 #pragma omp critical
         {
             if (lam_t > lam) lam = lam_t;
             if (eabs_t > b.elem_abs_max) b.elem_abs_max = eabs_t;
+            for (int32_t sc = 0; sc < p.n_scen; ++sc) lam_s[sc] = std::max(lam_s[sc], lam_st[sc]);
         }
     }
     b.dt_bound = lam > 0 ? 2.0 / lam : INFINITY;
+    b.dt_scen.resize(p.n_scen);
+    for (int32_t sc = 0; sc < p.n_scen; ++sc) b.dt_scen[sc] = lam_s[sc] > 0 ? 2.0 / lam_s[sc] : INFINITY;
     // temperature span of the data: initial field, fixed values, ambient temperatures
     double tlo = INFINITY, thi = -INFINITY;
     for (int64_t i = 0; i < N; ++i) {
@@ -563,6 +577,24 @@ void prep_order(const Problem &p, const Base &b, int ordering, Ordering &ord) {
     tm.mark("node ordering");
     ord.eorder = element_order(p, ord.perm, ordering);
     tm.mark("element ordering");
+    if (p.n_scen > 1) {
+        // a batch is numbered scenario by scenario (the ordering applies
+        // inside each scenario), so no block ever spans two scenarios
+        std::vector<int32_t> nm(p.N, 0);
+        for (int64_t e = 0; e < p.E; ++e)
+            for (int a = 0; a < p.nen; ++a) nm[p.conn[e * p.nen + a]] = p.emat[e];
+        std::vector<uint64_t> key(p.N);
+        for (int64_t i = 0; i < p.N; ++i) key[i] = ((uint64_t)p.scen_of_mat(nm[i]) << 32) | (uint32_t)ord.perm[i];
+        std::vector<int32_t> idx = sort_by_key<int32_t>(key);
+        for (int64_t r = 0; r < p.N; ++r) ord.perm[idx[r]] = (int32_t)r;
+        std::vector<uint64_t> ekey(p.E);
+        for (int64_t r = 0; r < p.E; ++r) ekey[r] = ((uint64_t)p.scen_of_mat(p.emat[ord.eorder[r]]) << 40) | (uint64_t)r;
+        std::vector<int64_t> eidx = sort_by_key<int64_t>(ekey);
+        std::vector<int64_t> e2(p.E);
+        for (int64_t r = 0; r < p.E; ++r) e2[r] = ord.eorder[eidx[r]];
+        ord.eorder.swap(e2);
+        tm.mark("scenario-major order");
+    }
 }
 
 void prep_layout(const Problem &p, const Base &b, const PrepOptions &o, const Ordering &ord, Layout &L) {
@@ -586,12 +618,15 @@ void prep_layout(const Problem &p, const Base &b, const PrepOptions &o, const Or
         std::vector<int64_t> stamp(N, -1);
         std::vector<std::pair<int64_t, int64_t>> blk;  // (first slot in eorder, count)
         int64_t cur = 0, nloc = 0, start = 0;
+        int32_t cur_scen = E ? p.scen_of_mat(p.emat[eorder[0]]) : 0;
         for (int64_t s = 0; s < E; ++s) {
             const int32_t *c = &p.conn[eorder[s] * nen];
             int nnew = 0;
             for (int a = 0; a < nen; ++a) nnew += stamp[c[a]] != cur;
             int64_t cnt = s - start;
-            if (cnt > 0 && (cnt + 1 > o.block_elems || nloc + nnew > o.max_local_nodes)) {
+            const int32_t sc = p.scen_of_mat(p.emat[eorder[s]]);
+            if (cnt > 0 && (cnt + 1 > o.block_elems || nloc + nnew > o.max_local_nodes || sc != cur_scen)) {
+                cur_scen = sc;
                 blk.push_back({start, cnt});
                 ++cur;
                 start = s;
@@ -816,6 +851,17 @@ void prep_layout(const Problem &p, const Base &b, const PrepOptions &o, const Or
     // a private node never carries boundary terms
     for (int64_t n = 0; n < L.n_private; ++n)
         if (has_bc(L.iperm[n]) || b.fixed[L.iperm[n]]) fail(FEM_E_MESH, "internal: boundary node classed private");
+    // scenario segments of the final numbering
+    L.seg_begin.clear();
+    L.seg_scen.clear();
+    for (int64_t n = 0; n < N; ++n) {
+        const int32_t sc = p.scen_of_mat(b.nmat[L.iperm[n]]);
+        if (L.seg_scen.empty() || sc != L.seg_scen.back() || n - L.seg_begin.back() >= SEG_NODES) {
+            L.seg_begin.push_back((int32_t)n);
+            L.seg_scen.push_back(sc);
+        }
+    }
+    L.seg_begin.push_back((int32_t)N);
     L.bw_before = bandwidth(p, b, nullptr);
     L.bw_after = bandwidth(p, b, &L.perm);
 }

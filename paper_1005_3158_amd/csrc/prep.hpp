@@ -25,6 +25,9 @@ struct Problem {
     std::vector<int32_t> if_a, if_b;
     std::vector<double> if_h;
     std::vector<double> T0;
+    int32_t n_scen = 1;
+    std::vector<int32_t> mat_scen;    // scenario of every material (empty: all in scenario 0)
+    int32_t scen_of_mat(int32_t m) const { return mat_scen.empty() ? 0 : mat_scen[m]; }
 };
 
 // node flag bits stored next to the material id
@@ -66,6 +69,10 @@ struct Layout {
     std::vector<BlockInfo> blocks;
     int64_t n_private = 0;            // nodes 0..n_private-1 are private to one block
     int64_t n_inflow = 0;             // node-kernel slots 0..n_inflow-1 may carry boundary inflow
+    // node ranges of one scenario each (at most SEG_NODES long) for the
+    // deterministic per-scenario state reductions
+    std::vector<int32_t> seg_begin;   // n_seg + 1
+    std::vector<int32_t> seg_scen;    // n_seg
     std::vector<int32_t> sh_list;     // per block: global ids of its shared nodes
     std::vector<uint16_t> lconn;      // per element: local ids in its block
     std::vector<int32_t> comb_ptr;    // per shared node: its partials are [comb_ptr[s], comb_ptr[s+1])
@@ -77,6 +84,8 @@ struct Layout {
     double setup_seconds = 0;
     int64_t block_elems = 0;
 };
+
+constexpr int SEG_NODES = 4096;
 
 struct PrepOptions {
     int ordering = FEM_ORDER_HILBERT;
@@ -105,6 +114,7 @@ struct Base {
     std::vector<double> lw;
     double dt_bound = 0;
     bool any_robin = false;
+    std::vector<double> dt_scen;      // stability bound of every scenario
     double elem_abs_max = 0;          // max_i sum_{e at i} sum_j |K^e_ij|  (W/K)
     double T_span = 1;                // span of initial, fixed and ambient temperatures (K)
 };
