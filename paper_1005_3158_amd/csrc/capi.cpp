@@ -1,124 +1,22 @@
 // C interface of the casting step (include/castfem.h).
-#include <hip/hip_runtime.h>
+#include "ctx.hpp"
 
-#include <algorithm>
-#include <chrono>
-#include <cmath>
-#include <cstring>
-#include <string>
-#include <vector>
-
-#include "../../include/castfem.h"
-#include "kernels.hpp"
-#include "prep.hpp"
-
-using namespace castfem;
+namespace castfem {
 
 namespace {
-
 thread_local std::string g_err;
+}
 
 int set_err(int code, const std::string &msg) {
     g_err = msg;
     return code;
 }
 
-#define HIPCHECK(x)                                                                                   \
-    do {                                                                                              \
-        hipError_t e_ = (x);                                                                          \
-        if (e_ != hipSuccess) throw PrepError{FEM_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_)}; \
-    } while (0)
+const char *last_error() { return g_err.c_str(); }
 
-enum Stage { ST_NEW = 0, ST_FINAL = 1, ST_BOUND = 2 };
+}  // namespace castfem
 
-enum Buf {
-    B_NODE_X, B_T, B_H, B_INV_M, B_FS, B_MATS, B_CONN, B_R, B_LCONN, B_BLOCKS, B_SH_LIST, B_PARTIALS,
-    B_COMB_PTR, B_SH_POS, B_ROBIN, B_LINK_PTR, B_LINK_NODE, B_LINK_W, B_DIAG, B_QNODE, B_FLAGS, B_SEG, B_COUNT
-};
-const char *BUF_NAMES[B_COUNT] = {"node_x", "T", "H", "inv_m", "fs", "mats", "conn", "r", "lconn", "blocks",
-                                  "sh_list", "partials", "comb_ptr", "sh_pos", "robin", "link_ptr",
-                                  "link_node", "link_w", "diag", "qnode", "flags", "segments"};
-constexpr int64_t ALIGN = 256;
-constexpr int GRAPH_STEPS = 16;  // steps per captured graph (even: both parities)
-constexpr size_t MAX_BLOCK_LDS = 160 * 1024 - 2048;  // gfx950 LDS per workgroup, less static use
-
-struct Candidate {
-    PrepOptions o;
-    int threads = 256;
-    Layout L;
-    double ms = -1;
-};
-
-MatDev make_mat(const fem_material &m, double dt) {
-    MatDev d{};
-    d.c = m.c;
-    d.inv_c = 1.0 / m.c;
-    d.Ts = m.T_sol;
-    d.Tl = m.T_liq;
-    d.L = m.L;
-    d.Hs = m.c * m.T_sol;
-    d.Hl = m.c * m.T_liq + m.L;
-    d.latent = m.L > 0 ? 1 : 0;
-    d.slope = (m.L > 0 && m.T_liq > m.T_sol) ? (m.T_liq - m.T_sol) / (m.c * (m.T_liq - m.T_sol) + m.L) : 0.0;
-    d.inv_dH = m.L > 0 ? 1.0 / (d.Hl - d.Hs) : 0.0;
-    d.dt = dt;
-    d.k = m.k;
-    d.kf = (float)m.k;
-    d.dtf = (float)dt;
-    return d;
-}
-
-// enthalpy relation on the host (initial state and read-back of fraction solid)
-double h_of_t(const fem_material &m, double T) {
-    double g = 0.0;
-    if (m.L > 0 && T > m.T_sol) g = T >= m.T_liq ? 1.0 : (T - m.T_sol) / (m.T_liq - m.T_sol);
-    return m.c * T + m.L * g;
-}
-
-void t_of_h(const MatDev &M, double H, double &T, double &fs) {
-    if (!M.latent || H <= M.Hs) {
-        T = H * M.inv_c;
-        fs = 1.0;
-    } else if (H >= M.Hl) {
-        T = (H - M.L) * M.inv_c;
-        fs = 0.0;
-    } else {
-        T = M.Ts + (H - M.Hs) * M.slope;
-        fs = 1.0 - (H - M.Hs) * M.inv_dH;
-    }
-}
-
-}  // namespace
-
-struct fem_ctx {
-    fem_options opt{};
-    Problem prob;
-    bool have_mesh = false;
-    Stage stage = ST_NEW;
-    Base base;
-    std::vector<Candidate> cands;
-    int chosen = 0;
-    hipStream_t stream = nullptr;
-    int64_t sizes[B_COUNT] = {};
-    void *ptr[B_COUNT] = {};
-    Dev dev;
-    std::vector<MatDev> mats_host;
-    int parity = 0;
-    int64_t steps = 0;
-    double E0 = 0, Eref = 0, lat0 = 0, tmin0 = 0, tmax0 = 0;
-    int64_t nliq0 = 0;
-    // per scenario (a single problem is scenario 0)
-    std::vector<double> E0_s, Eref_s, time_s, dt_s;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t gexec = nullptr;
-    double setup_seconds = 0;
-
-    Layout &L() { return cands[chosen].L; }
-    const Layout &L() const { return cands[chosen].L; }
-    size_t rsize() const { return opt.precision == FEM_PREC_FP64 ? 8 : 4; }
-};
-
-namespace {
+namespace castfem {
 
 int64_t rup(int64_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
@@ -359,23 +257,6 @@ void check_bound(fem_ctx *c, int fn_stage) {
     if (c->stage < fn_stage) throw PrepError{FEM_E_STATE, "call out of order: the context is not bound yet"};
 }
 
-template <class F>
-int guarded(F &&f) {
-    try {
-        f();
-        g_err.clear();
-        return FEM_OK;
-    } catch (const PrepError &e) {
-        return set_err(e.code, e.msg);
-    } catch (const std::bad_alloc &) {
-        return set_err(FEM_E_INVALID_ARG, "host allocation failed");
-    } catch (const std::exception &e) {
-        return set_err(FEM_E_INVALID_ARG, e.what());
-    } catch (...) {
-        return set_err(FEM_E_INVALID_ARG, "unknown error");
-    }
-}
-
 void fill_report(const fem_ctx *c, fem_prep_report *rep) {
     std::memset(rep, 0, sizeof(*rep));
     const Layout &L = c->L();
@@ -394,12 +275,12 @@ void fill_report(const fem_ctx *c, fem_prep_report *rep) {
     rep->setup_seconds = c->setup_seconds;
 }
 
-}  // namespace
+}  // namespace castfem
 
 // =================================================================== C ABI
 extern "C" {
 
-const char *fem_last_error(void) { return g_err.c_str(); }
+const char *fem_last_error(void) { return castfem::last_error(); }
 
 int fem_create(fem_ctx **out, const fem_options *opt) {
     if (!out) return set_err(FEM_E_INVALID_ARG, "out is null");
@@ -813,7 +694,7 @@ int fem_read_H(fem_ctx *ctx, double *H_host) {
 
 }  // extern "C"
 
-namespace {
+namespace castfem {
 
 // FP64 energy balance per scenario (reps[n_scen]): on-demand state reduction
 // over single-scenario node segments plus the per-node inflow sums, all summed
@@ -857,7 +738,7 @@ void energy_scenarios(fem_ctx *ctx, fem_energy_report *reps) {
     }
 }
 
-}  // namespace
+}  // namespace castfem
 
 extern "C" {
 

@@ -1,0 +1,147 @@
+// Internal state of a castfem context, shared by the C interface of the
+// explicit step (capi.cpp) and of the learned surrogate (surrogate.cpp).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/castfem.h"
+#include "kernels.hpp"
+#include "prep.hpp"
+
+namespace castfem {
+
+// thread-local message of the last failing call; returns `code`
+int set_err(int code, const std::string &msg);
+const char *last_error();
+
+#define HIPCHECK(x)                                                                                   \
+    do {                                                                                              \
+        hipError_t e_ = (x);                                                                          \
+        if (e_ != hipSuccess) throw PrepError{FEM_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+
+enum Stage { ST_NEW = 0, ST_FINAL = 1, ST_BOUND = 2 };
+
+enum Buf {
+    B_NODE_X, B_T, B_H, B_INV_M, B_FS, B_MATS, B_CONN, B_R, B_LCONN, B_BLOCKS, B_SH_LIST, B_PARTIALS,
+    B_COMB_PTR, B_SH_POS, B_ROBIN, B_LINK_PTR, B_LINK_NODE, B_LINK_W, B_DIAG, B_QNODE, B_FLAGS, B_SEG, B_COUNT
+};
+inline const char *const BUF_NAMES[B_COUNT] = {"node_x", "T", "H", "inv_m", "fs", "mats", "conn", "r", "lconn", "blocks",
+                                  "sh_list", "partials", "comb_ptr", "sh_pos", "robin", "link_ptr",
+                                  "link_node", "link_w", "diag", "qnode", "flags", "segments"};
+constexpr int64_t ALIGN = 256;
+constexpr int GRAPH_STEPS = 16;  // steps per captured graph (even: both parities)
+constexpr size_t MAX_BLOCK_LDS = 160 * 1024 - 2048;  // gfx950 LDS per workgroup, less static use
+
+struct Candidate {
+    PrepOptions o;
+    int threads = 256;
+    Layout L;
+    double ms = -1;
+};
+
+inline MatDev make_mat(const fem_material &m, double dt) {
+    MatDev d{};
+    d.c = m.c;
+    d.inv_c = 1.0 / m.c;
+    d.Ts = m.T_sol;
+    d.Tl = m.T_liq;
+    d.L = m.L;
+    d.Hs = m.c * m.T_sol;
+    d.Hl = m.c * m.T_liq + m.L;
+    d.latent = m.L > 0 ? 1 : 0;
+    d.slope = (m.L > 0 && m.T_liq > m.T_sol) ? (m.T_liq - m.T_sol) / (m.c * (m.T_liq - m.T_sol) + m.L) : 0.0;
+    d.inv_dH = m.L > 0 ? 1.0 / (d.Hl - d.Hs) : 0.0;
+    d.dt = dt;
+    d.k = m.k;
+    d.kf = (float)m.k;
+    d.dtf = (float)dt;
+    return d;
+}
+
+// enthalpy relation on the host (initial state and read-back of fraction solid)
+inline double h_of_t(const fem_material &m, double T) {
+    double g = 0.0;
+    if (m.L > 0 && T > m.T_sol) g = T >= m.T_liq ? 1.0 : (T - m.T_sol) / (m.T_liq - m.T_sol);
+    return m.c * T + m.L * g;
+}
+
+inline void t_of_h(const MatDev &M, double H, double &T, double &fs) {
+    if (!M.latent || H <= M.Hs) {
+        T = H * M.inv_c;
+        fs = 1.0;
+    } else if (H >= M.Hl) {
+        T = (H - M.L) * M.inv_c;
+        fs = 0.0;
+    } else {
+        T = M.Ts + (H - M.Hs) * M.slope;
+        fs = 1.0 - (H - M.Hs) * M.inv_dH;
+    }
+}
+
+}  // namespace castfem
+
+using namespace castfem;
+
+struct fem_ctx {
+    fem_options opt{};
+    Problem prob;
+    bool have_mesh = false;
+    Stage stage = ST_NEW;
+    Base base;
+    std::vector<Candidate> cands;
+    int chosen = 0;
+    hipStream_t stream = nullptr;
+    int64_t sizes[B_COUNT] = {};
+    void *ptr[B_COUNT] = {};
+    Dev dev;
+    std::vector<MatDev> mats_host;
+    int parity = 0;
+    int64_t steps = 0;
+    double E0 = 0, Eref = 0, lat0 = 0, tmin0 = 0, tmax0 = 0;
+    int64_t nliq0 = 0;
+    // per scenario (a single problem is scenario 0)
+    std::vector<double> E0_s, Eref_s, time_s, dt_s;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    double setup_seconds = 0;
+
+    Layout &L() { return cands[chosen].L; }
+    const Layout &L() const { return cands[chosen].L; }
+    size_t rsize() const { return opt.precision == FEM_PREC_FP64 ? 8 : 4; }
+};
+
+
+namespace castfem {
+
+// helpers of capi.cpp used by the surrogate interface
+void set_dt(fem_ctx *c, double dt);
+void eager_steps(fem_ctx *c, int64_t n);
+void run_steps(fem_ctx *c, int64_t n);
+void check_bound(fem_ctx *c, int fn_stage);
+void energy_scenarios(fem_ctx *ctx, fem_energy_report *reps);
+
+template <class F>
+int guarded(F &&f) {
+    try {
+        f();
+        set_err(FEM_OK, "");
+        return FEM_OK;
+    } catch (const PrepError &e) {
+        return set_err(e.code, e.msg);
+    } catch (const std::bad_alloc &) {
+        return set_err(FEM_E_INVALID_ARG, "host allocation failed");
+    } catch (const std::exception &e) {
+        return set_err(FEM_E_INVALID_ARG, e.what());
+    } catch (...) {
+        return set_err(FEM_E_INVALID_ARG, "unknown error");
+    }
+}
+
+}  // namespace castfem
