@@ -221,6 +221,33 @@ def config4_trajectory(seed, n=16):
     return hex_cube(n=n, T_pour=T_pour, noise_amp=0.0, dirichlet_x0=None, robin_x0=(h, 25.0))
 
 
+def chill_batch(seeds, n=16):
+    """config4_trajectory of every seed as one disjoint problem (scenario s = seeds[s],
+    material s); meta['scenarios'] lists node0/node1, T_pour and h of each."""
+    parts, sc = [], []
+    n0 = 0
+    for s, seed in enumerate(seeds):
+        p = config4_trajectory(seed, n)
+        T_pour, h = chill_params(seed)
+        N = p["xyz"].shape[0]
+        sc.append(dict(seed=int(seed), T_pour=T_pour, h=h, node0=n0, node1=n0 + N))
+        parts.append((p, n0))
+        n0 += N
+    cat = lambda key: np.concatenate([q[key] for q, _ in parts], axis=0)
+    prob = dict(
+        elem_type=8,
+        xyz=cat("xyz"),
+        conn=np.concatenate([q["conn"] + off for q, off in parts], axis=0).astype(np.int32),
+        elem_mat=np.concatenate([q["elem_mat"] + s for s, (q, _) in enumerate(parts)]).astype(np.int32),
+        materials=np.array([ALLOY] * len(parts), dtype=np.float64),
+        T0=cat("T0"),
+        flux_faces=np.concatenate([q["flux_faces"] + off for q, off in parts], axis=0).astype(np.int32),
+        flux_q=cat("flux_q"), flux_h=cat("flux_h"), flux_Tinf=cat("flux_Tinf"),
+        mat_scenario=np.arange(len(parts), dtype=np.int32),
+        meta=dict(kind="chill_batch", n=n, scenarios=sc))
+    return _empty_faces(prob)
+
+
 def batch_scenarios(n_scen=256, seed=4, elems_range=(20000, 400000), n_range=None):
     """Parameters of a batch of casting scenarios (one dict per scenario).
 

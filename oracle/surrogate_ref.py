@@ -27,15 +27,132 @@ Network (width W, L message-passing layers, ReLU):
     h_l = h_{l-1} + relu([h_{l-1}, a_l] W_l + b_l)      l = 1..L
     y   = h_L w_out + b_out
 
-Loss over the nodes of one sample: mean_i (y_i - t_i)^2 with the target
-t_i = (H_true_i - base_i) / (c_i DH_SCALE).
+Loss over the nodes of one sample, either in enthalpy, mean_i (y_i - t_i)^2 with
+t_i = (H_true_i - base_i) / (c_i DH_SCALE), or in temperature,
+mean_i ((T(H_pred_i) - T(H_true_i)) / DT_SCALE)^2.
 """
 import numpy as np
+
+from . import oracle as orc
 
 T_REF = 25.0
 T_SCALE = 700.0
 DH_SCALE = 10.0   # K of sensible heat per unit of network output
+DT_SCALE = 10.0   # K per unit of the temperature loss
 N_FEAT = 8
+
+
+def _tri_area(x):
+    return 0.5 * np.linalg.norm(np.cross(x[:, 1] - x[:, 0], x[:, 2] - x[:, 0]), axis=1)
+
+
+def _face_area(x):
+    """Triangle area, or for a quad half the norm of the cross product of its diagonals."""
+    if x.shape[1] == 3:
+        return _tri_area(x)
+    return 0.5 * np.linalg.norm(np.cross(x[:, 2] - x[:, 0], x[:, 3] - x[:, 1]), axis=1)
+
+
+def node_strengths(prob):
+    """Per node (input numbering): m_i c_i, the Robin coefficient b_i = sum over
+    flux faces at i of (A_f / nodes per face) h_f, the interface weight sum
+    sum_j w_ij = sum over contact pairs at i of h A / 3, and sum_j |K_ij| of the
+    assembled conduction matrix (element matrices from the oracle)."""
+    P = orc.Problem(prob)
+    N = P.n_nodes
+    xyz = np.asarray(prob["xyz"], np.float64)
+    conn = np.asarray(prob["conn"], np.int64)
+    mats = np.asarray(prob["materials"], np.float64).reshape(-1, 6)
+    nmat = orc.node_material(P)
+    mc = orc.lumped_mass(P) * mats[nmat, 2]
+    b = np.zeros(N)
+    ff = np.asarray(prob.get("flux_faces", np.zeros((0, 3))), np.int64)
+    if ff.size:
+        A = _face_area(xyz[ff])
+        np.add.at(b, ff, (A * np.asarray(prob["flux_h"], np.float64) / ff.shape[1])[:, None] * np.ones(ff.shape[1]))
+    w = np.zeros(N)
+    fa = np.asarray(prob.get("if_a", np.zeros((0, 3))), np.int64)
+    if fa.size:
+        fb = np.asarray(prob["if_b"], np.int64)
+        g = np.asarray(prob["if_h"], np.float64) * _tri_area(xyz[fa]) / 3.0
+        np.add.at(w, fa, g[:, None] * np.ones(3))
+        np.add.at(w, fb, g[:, None] * np.ones(3))
+    ke = orc.tet_ke if conn.shape[1] == 4 else orc.hex_ke
+    emat = np.asarray(prob["elem_mat"], np.int64)
+    rows, cols, vals = [], [], []
+    for e in range(conn.shape[0]):
+        K, _ = ke(xyz[conn[e]], mats[emat[e], 0])
+        rows.append(np.repeat(conn[e], conn.shape[1]))
+        cols.append(np.tile(conn[e], conn.shape[1]))
+        vals.append(K.ravel())
+    rows, cols, vals = np.concatenate(rows), np.concatenate(cols), np.concatenate(vals)
+    key = rows * N + cols
+    uk, inv = np.unique(key, return_inverse=True)
+    assembled = np.zeros(uk.size)
+    np.add.at(assembled, inv, vals)
+    kabs = np.zeros(N)
+    np.add.at(kabs, uk // N, np.abs(assembled))
+    return dict(mc=mc, robin_b=b, iface_w=w, kabs=kabs, node_mat=nmat)
+
+
+def features(prob, H0, H1, dt, horizon=16, strengths=None):
+    """The 8 node features of the module docstring for one pair of states (FP64)."""
+    st = node_strengths(prob) if strengths is None else strengths
+    mats = np.asarray(prob["materials"], np.float64).reshape(-1, 6)
+    nm = st["node_mat"]
+    H0 = np.asarray(H0, np.float64)
+    H1 = np.asarray(H1, np.float64)
+    T1 = np.array([orc.T_of_H(mats[m], h)[0] for m, h in zip(nm, H1)])
+    fs1 = np.array([orc.fs_of_H(mats[m], h)[0] for m, h in zip(nm, H1)])
+    c = mats[nm, 2]
+    X = np.empty((H1.size, N_FEAT))
+    X[:, 0] = (T1 - T_REF) / T_SCALE
+    X[:, 1] = fs1
+    X[:, 2] = (mats[nm, 5] > 0).astype(np.float64)
+    X[:, 3] = st["robin_b"] * dt / st["mc"]
+    X[:, 4] = 2.0 * st["iface_w"] * dt / st["mc"]
+    X[:, 5] = st["kabs"] * dt / st["mc"]
+    X[:, 6] = horizon * (H1 - H0) / (c * T_SCALE)
+    X[:, 7] = 1.0
+    return X
+
+
+def base_and_target(prob, H0, H1, Ht, horizon=16):
+    """Extrapolated base H1 + (horizon - 1)(H1 - H0) and the target (Ht - base) / (c DH_SCALE)."""
+    mats = np.asarray(prob["materials"], np.float64).reshape(-1, 6)
+    c = mats[orc.node_material(orc.Problem(prob)), 2]
+    H0, H1, Ht = (np.asarray(a, np.float64) for a in (H0, H1, Ht))
+    base = H1 + (horizon - 1) * (H1 - H0)
+    return base, (Ht - base) / (c * DH_SCALE), c
+
+
+def flatten_params(p, layers):
+    """Parameter dict -> one vector in the order W_in, b_in, (W_l, b_l)..., w_out, b_out."""
+    parts = [p["W_in"].ravel(), p["b_in"]]
+    for l in range(layers):
+        parts += [p["W%d" % l].ravel(), p["b%d" % l]]
+    parts += [p["w_out"], p["b_out"]]
+    return np.concatenate(parts)
+
+
+def unflatten_params(v, width, layers):
+    v = np.asarray(v, np.float64)
+    p, o = {}, 0
+
+    def take(name, shape):
+        nonlocal o
+        n = int(np.prod(shape))
+        p[name] = v[o:o + n].reshape(shape)
+        o += n
+    take("W_in", (N_FEAT, width))
+    take("b_in", (width,))
+    for l in range(layers):
+        take("W%d" % l, (2 * width, width))
+        take("b%d" % l, (width,))
+    take("w_out", (width,))
+    take("b_out", (1,))
+    assert o == v.size
+    return p
 
 
 def graph_mean_operator(conn, n_nodes):
@@ -99,11 +216,38 @@ def forward(p, X, ptr, col, layers):
     return y, cache
 
 
+def h_loss(t):
+    """Enthalpy loss mean (y - t)^2 and its derivative in y."""
+    def f(y):
+        return float(np.mean((y - t) ** 2)), 2.0 * (y - t) / y.size
+    return f
+
+
+def t_loss(prob, base, H_true):
+    """Temperature loss mean ((T(base + c DH_SCALE y) - T(H_true)) / DT_SCALE)^2 and its
+    derivative in y, through the slope of the branch of T(H) the prediction lies on
+    (1/c outside the mushy range, (T_liq - T_sol) / (c (T_liq - T_sol) + L) inside)."""
+    P = orc.Problem(prob)
+    mats = np.asarray(prob["materials"], np.float64).reshape(-1, 6)
+    m = mats[orc.node_material(P)]
+    c, Ts, Tl, L = m[:, 2], m[:, 3], m[:, 4], m[:, 5]
+    mushy_slope = np.where(L > 0, (Tl - Ts) / (c * (Tl - Ts) + L), 0.0)
+    T_true, _ = orc.state_T(P, H_true)
+    scale = c * DH_SCALE
+
+    def f(y):
+        Hp = base + scale * y
+        Tp, fs = orc.state_T(P, Hp)
+        slope = np.where((L > 0) & (fs > 0) & (fs < 1), mushy_slope, 1.0 / c)
+        e = (Tp - T_true) / DT_SCALE
+        return float(np.mean(e ** 2)), 2.0 * e / y.size * slope * scale / DT_SCALE
+    return f
+
+
 def loss_and_grad(p, X, t, ptr, col, layers):
+    """Loss and parameter gradient; t is the H-loss target array or a loss callable y -> (loss, dL/dy)."""
     y, c = forward(p, X, ptr, col, layers)
-    n = y.size
-    loss = float(np.mean((y - t) ** 2))
-    dy = 2.0 * (y - t) / n
+    loss, dy = (t if callable(t) else h_loss(t))(y)
     g = {"w_out": c["hs"][-1].T @ dy, "b_out": np.array([dy.sum()])}
     dh = np.outer(dy, p["w_out"])
     width = p["b_in"].size

@@ -33,7 +33,9 @@ EXPORTS = [
     "fem_query_buffers", "fem_bind_buffers", "fem_get_report", "fem_stable_dt", "fem_step", "fem_read_T",
     "fem_read_fs", "fem_read_H", "fem_energy", "fem_read_state", "fem_write_state", "fem_get_node_perm",
     "fem_time_kernels", "fem_copy_kernel", "fem_set_scenarios", "fem_stable_dt_scenarios", "fem_step_batch",
-    "fem_energy_scenarios",
+    "fem_energy_scenarios", "fem_sur_create", "fem_sur_destroy", "fem_sur_query_buffers", "fem_sur_bind_buffers",
+    "fem_sur_n_params", "fem_sur_get_params", "fem_sur_set_params", "fem_sur_features", "fem_sur_loss_grad",
+    "fem_sur_train", "fem_sur_predict", "fem_snapshot_H", "fem_advance",
 ]
 
 
@@ -77,6 +79,17 @@ class fem_kernel_times(C.Structure):
                 ("launches_combine", C.c_int64), ("bytes_element", C.c_double), ("bytes_combine", C.c_double)]
 
 
+class fem_sur_options(C.Structure):
+    _fields_ = [("width", C.c_int32), ("layers", C.c_int32), ("horizon", C.c_int32), ("max_samples", C.c_int32),
+                ("train", C.c_int32), ("loss", C.c_int32), ("reserved", C.c_int32 * 6), ("seed", C.c_uint64)]
+
+
+class fem_advance_report(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("plain_steps", C.c_int64), ("jumps_accepted", C.c_int64),
+                ("jumps_rejected", C.c_int64), ("solid", C.c_int32), ("pad", C.c_int32),
+                ("wall_seconds", C.c_double), ("max_residual", C.c_double), ("reserved", C.c_int64 * 4)]
+
+
 def _as_dict(s):
     return {k: (list(getattr(s, k)) if k == "reserved" else getattr(s, k)) for k, _ in s._fields_ if k != "reserved"}
 
@@ -106,6 +119,14 @@ def lib():
             "fem_time_kernels": [vp, dp, i64, vp], "fem_copy_kernel": [vp, vp, vp, i64, i32, vp],
             "fem_set_scenarios": [vp, i32, vp], "fem_stable_dt_scenarios": [vp, vp],
             "fem_step_batch": [vp, vp, i64], "fem_energy_scenarios": [vp, vp],
+            "fem_sur_create": [vp, vp, vp], "fem_sur_destroy": [vp], "fem_sur_query_buffers": [vp, vp, vp],
+            "fem_sur_bind_buffers": [vp, vp, i32], "fem_sur_n_params": [vp, vp],
+            "fem_sur_get_params": [vp, vp, i64], "fem_sur_set_params": [vp, vp, i64],
+            "fem_sur_features": [vp, vp, vp, i64, i64, vp],
+            "fem_sur_loss_grad": [vp, vp, vp, vp, i64, i64, vp, vp],
+            "fem_sur_train": [vp, vp, vp, vp, i64, i64, i32, i32, C.c_float, C.c_float, C.c_uint64, vp],
+            "fem_sur_predict": [vp, vp, vp, i64, i64, vp], "fem_snapshot_H": [vp, vp],
+            "fem_advance": [vp, vp, vp, i64, i32, dp, dp, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -296,6 +317,90 @@ def fem_copy_kernel(ctx, dst_ptr, src_ptr, nbytes, repeats):
     return ms.value
 
 
+# ------------------------------------------------------------ surrogate
+FEM_SUR_LOSS_H, FEM_SUR_LOSS_T = 0, 1
+
+
+def fem_sur_create(ctx, width=64, layers=3, horizon=16, max_samples=1, train=False, seed=0, loss=FEM_SUR_LOSS_H):
+    o = fem_sur_options()
+    o.width, o.layers, o.horizon, o.max_samples, o.train, o.seed = width, layers, horizon, max_samples, int(train), seed
+    o.loss = loss
+    s = C.c_void_p()
+    _call("fem_sur_create", C.byref(s), ctx, C.byref(o))
+    return s
+
+
+def fem_sur_destroy(s):
+    _call("fem_sur_destroy", s)
+
+
+def fem_sur_query_buffers(s):
+    n = C.c_int32(0)
+    _call("fem_sur_query_buffers", s, None, C.byref(n))
+    arr = (fem_buffer_desc * n.value)()
+    _call("fem_sur_query_buffers", s, arr, C.byref(n))
+    return [(d.name.decode(), d.bytes, d.alignment) for d in arr]
+
+
+def fem_sur_bind_buffers(s, ptrs):
+    arr = (C.c_void_p * len(ptrs))(*[C.c_void_p(p) if p else None for p in ptrs])
+    _call("fem_sur_bind_buffers", s, arr, len(ptrs))
+
+
+def fem_sur_n_params(s):
+    n = C.c_int64()
+    _call("fem_sur_n_params", s, C.byref(n))
+    return n.value
+
+
+def fem_sur_get_params(s):
+    out = np.empty(fem_sur_n_params(s), np.float32)
+    _call("fem_sur_get_params", s, _p(out), out.size)
+    return out
+
+
+def fem_sur_set_params(s, params):
+    p = np.ascontiguousarray(params, np.float32)
+    _call("fem_sur_set_params", s, _p(p), p.size)
+
+
+def fem_sur_features(s, H0_ptr, H1_ptr, stride, slots, n_nodes):
+    out = np.empty((slots * n_nodes, 8), np.float32)
+    _call("fem_sur_features", s, C.c_void_p(H0_ptr), C.c_void_p(H1_ptr), int(stride), int(slots), _p(out))
+    return out
+
+
+def fem_sur_loss_grad(s, H0_ptr, H1_ptr, Ht_ptr, stride, slots):
+    g = np.empty(fem_sur_n_params(s), np.float32)
+    loss = C.c_double()
+    _call("fem_sur_loss_grad", s, C.c_void_p(H0_ptr), C.c_void_p(H1_ptr), C.c_void_p(Ht_ptr), int(stride),
+          int(slots), C.byref(loss), _p(g))
+    return loss.value, g
+
+
+def fem_sur_train(s, H0_ptr, H1_ptr, Ht_ptr, stride, n_samples, batch, epochs, lr, lr_final, seed):
+    losses = np.zeros(max(int(epochs), 1), np.float64)
+    _call("fem_sur_train", s, C.c_void_p(H0_ptr), C.c_void_p(H1_ptr), C.c_void_p(Ht_ptr), int(stride),
+          int(n_samples), int(batch), int(epochs), float(lr), float(lr_final), int(seed), _p(losses))
+    return losses[:int(epochs)]
+
+
+def fem_sur_predict(s, H0_ptr, H1_ptr, stride, slots, out_ptr):
+    _call("fem_sur_predict", s, C.c_void_p(H0_ptr), C.c_void_p(H1_ptr), int(stride), int(slots), C.c_void_p(out_ptr))
+
+
+def fem_snapshot_H(ctx, out_ptr):
+    _call("fem_snapshot_H", ctx, C.c_void_p(out_ptr))
+
+
+def fem_advance(ctx, sur, dt_per_scenario, max_steps, until_solid=True, energy_tol=1e-4, fs_tol=1e-6):
+    dt = np.ascontiguousarray(np.atleast_1d(dt_per_scenario), np.float64)
+    rep = fem_advance_report()
+    _call("fem_advance", ctx, sur, _p(dt), int(max_steps), int(bool(until_solid)), float(energy_tol),
+          float(fs_tol), C.byref(rep))
+    return _as_dict(rep)
+
+
 # ------------------------------------------------------------ convenience
 def make_options(precision=FEM_PREC_FP32_KAHAN, ordering=FEM_ORDER_HILBERT, scatter=FEM_SCATTER_LDS_BLOCKED,
                  block_elems=0, device=0, allow_unstable=False, lds_bytes=0, threads=0):
@@ -321,6 +426,20 @@ def setup_problem(ctx, prob):
     return fem_finalize(ctx)
 
 
+def _allocate(torch, device, descs):
+    """torch-owned device buffers for a list of (name, bytes, alignment); returns (tensors, aligned pointers)."""
+    bufs, ptrs = [], []
+    for name, nbytes, align in descs:
+        if nbytes:
+            t = torch.empty(nbytes + align, dtype=torch.uint8, device=device)
+            p = t.data_ptr()
+            bufs.append(t)
+            ptrs.append(p + (-p) % align)
+        else:
+            ptrs.append(0)
+    return bufs, ptrs
+
+
 class Solver:
     """One casting problem on one GPU: torch allocates the device buffers and
     the stream, the library borrows them."""
@@ -338,17 +457,7 @@ class Solver:
         self.report = setup_problem(self.ctx, prob)
         self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
         fem_set_stream(self.ctx, self.stream.cuda_stream)
-        self.buffers = []
-        ptrs = []
-        for name, nbytes, align in fem_query_buffers(self.ctx):
-            if nbytes:
-                t = torch.empty(nbytes + align, dtype=torch.uint8, device=self.device)
-                p = t.data_ptr()
-                off = (-p) % align
-                self.buffers.append(t)
-                ptrs.append(p + off)
-            else:
-                ptrs.append(0)
+        self.buffers, ptrs = _allocate(torch, self.device, fem_query_buffers(self.ctx))
         fem_bind_buffers(self.ctx, ptrs)
         self.report = fem_get_report(self.ctx)
 
@@ -382,6 +491,17 @@ class Solver:
     def node_perm(self):
         return fem_get_node_perm(self.ctx, self.n_nodes)
 
+    def snapshot_H(self, out):
+        """Current enthalpy (device numbering) into the float32 CUDA tensor `out` (n_nodes)."""
+        assert out.dtype == self.torch.float32 and out.is_cuda and out.numel() >= self.n_nodes
+        self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
+        fem_snapshot_H(self.ctx, out.data_ptr())
+        self.torch.cuda.current_stream(self.device).wait_stream(self.stream)
+
+    def advance(self, dt_per_scenario, max_steps, surrogate=None, until_solid=True, energy_tol=1e-4, fs_tol=1e-6):
+        return fem_advance(self.ctx, surrogate.sur if surrogate is not None else None, dt_per_scenario, max_steps,
+                           until_solid, energy_tol, fs_tol)
+
     def synchronize(self):
         self.stream.synchronize()
 
@@ -390,6 +510,60 @@ class Solver:
             self.synchronize()
             fem_destroy(self.ctx)
             self.ctx = None
+            self.buffers = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Surrogate:
+    """The learned surrogate of a Solver; torch allocates its device buffers."""
+
+    def __init__(self, solver, layers=3, horizon=16, max_samples=1, train=False, seed=0, loss=FEM_SUR_LOSS_H):
+        self.solver = solver
+        self.torch = solver.torch
+        self.n_nodes = solver.n_nodes
+        self.sur = fem_sur_create(solver.ctx, 64, layers, horizon, max_samples, train, seed, loss)
+        self.buffers, ptrs = _allocate(self.torch, solver.device, fem_sur_query_buffers(self.sur))
+        fem_sur_bind_buffers(self.sur, ptrs)
+
+    def _sync_in(self):
+        self.solver.stream.wait_stream(self.torch.cuda.current_stream(self.solver.device))
+
+    def params(self):
+        return fem_sur_get_params(self.sur)
+
+    def set_params(self, p):
+        fem_sur_set_params(self.sur, p)
+
+    def features(self, H0, H1, slots=1):
+        self._sync_in()
+        return fem_sur_features(self.sur, H0.data_ptr(), H1.data_ptr(), self.n_nodes if slots == 1 else H0.stride(0),
+                                slots, self.n_nodes)
+
+    def loss_grad(self, H0, H1, Ht, stride=None, slots=1):
+        self._sync_in()
+        return fem_sur_loss_grad(self.sur, H0.data_ptr(), H1.data_ptr(), Ht.data_ptr(),
+                                 self.n_nodes if stride is None else stride, slots)
+
+    def train(self, H0, H1, Ht, stride, n_samples, batch=1, epochs=1, lr=1e-3, lr_final=1e-5, seed=0):
+        self._sync_in()
+        return fem_sur_train(self.sur, H0.data_ptr(), H1.data_ptr(), Ht.data_ptr(), stride, n_samples, batch,
+                             epochs, lr, lr_final, seed)
+
+    def predict(self, H0, H1, out, stride=None, slots=1):
+        self._sync_in()
+        fem_sur_predict(self.sur, H0.data_ptr(), H1.data_ptr(), self.n_nodes if stride is None else stride, slots,
+                        out.data_ptr())
+
+    def close(self):
+        if self.sur is not None:
+            self.solver.synchronize()
+            fem_sur_destroy(self.sur)
+            self.sur = None
             self.buffers = []
 
     def __del__(self):

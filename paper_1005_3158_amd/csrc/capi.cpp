@@ -556,6 +556,7 @@ int fem_bind_buffers(fem_ctx *ctx, void *const *dev_ptrs, int32_t n) {
         fill_dev(ctx, ctx->cands[ctx->chosen]);
         ctx->dt_s.clear();
         ctx->time_s.assign(ctx->prob.n_scen, 0.0);
+        ctx->Qx_s.assign(ctx->prob.n_scen, 0.0);
         ctx->parity = 0;
         ctx->steps = 0;
         // drop the layouts that lost the trial
@@ -732,6 +733,7 @@ void energy_scenarios(fem_ctx *ctx, fem_energy_report *reps) {
         reps[ctx->prob.scen_of_mat((int32_t)(L.nflag[L.bc_first + q] & NODE_MAT_MASK))].Q_cum += qn[q];
     for (int32_t sc = 0; sc < ns; ++sc) {
         fem_energy_report &r = reps[sc];
+        r.Q_cum += ctx->Qx_s[sc];
         r.n_liquid = (int64_t)nl[sc];
         r.nonfinite = (int64_t)nf[sc];
         r.residual = std::fabs(r.E - r.E0 - r.Q_cum) / std::fabs(r.E0 - ctx->Eref_s[sc]);
@@ -793,7 +795,7 @@ constexpr uint64_t CKPT_MAGIC = 0x32504B434D454643ull;
 
 int64_t ckpt_bytes(const fem_ctx *ctx) {
     const int64_t N = ctx->L().N, R = (int64_t)ctx->rsize();
-    return (int64_t)sizeof(CkptHeader) + N * 8 + 2 * N * R + N * R + ctx->L().n_inflow * 8 + ctx->prob.n_scen * 8;
+    return (int64_t)sizeof(CkptHeader) + N * 8 + 2 * N * R + N * R + ctx->L().n_inflow * 8 + 2 * ctx->prob.n_scen * 8;
 }
 
 int fem_read_state(fem_ctx *ctx, void *buf, int64_t *bytes) {
@@ -821,6 +823,8 @@ int fem_read_state(fem_ctx *ctx, void *buf, int64_t *bytes) {
         if (Q) HIPCHECK(hipMemcpyAsync(p, ctx->ptr[B_QNODE], Q * 8, hipMemcpyDeviceToHost, ctx->stream));
         p += Q * 8;
         std::memcpy(p, ctx->time_s.data(), ctx->prob.n_scen * 8);
+        p += ctx->prob.n_scen * 8;
+        std::memcpy(p, ctx->Qx_s.data(), ctx->prob.n_scen * 8);
         HIPCHECK(hipStreamSynchronize(ctx->stream));
         *bytes = need;
     });
@@ -847,6 +851,8 @@ int fem_write_state(fem_ctx *ctx, const void *buf, int64_t bytes) {
         if (Q) HIPCHECK(hipMemcpyAsync(ctx->ptr[B_QNODE], p, Q * 8, hipMemcpyHostToDevice, ctx->stream));
         p += Q * 8;
         std::memcpy(ctx->time_s.data(), p, ctx->prob.n_scen * 8);
+        p += ctx->prob.n_scen * 8;
+        std::memcpy(ctx->Qx_s.data(), p, ctx->prob.n_scen * 8);
         HIPCHECK(hipStreamSynchronize(ctx->stream));
         ctx->parity = (int)h.parity;
         ctx->steps = h.steps;

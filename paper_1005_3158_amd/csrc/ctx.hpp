@@ -108,6 +108,7 @@ struct fem_ctx {
     int64_t nliq0 = 0;
     // per scenario (a single problem is scenario 0)
     std::vector<double> E0_s, Eref_s, time_s, dt_s;
+    std::vector<double> Qx_s;   // boundary inflow estimated over steps the surrogate jumped
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     double setup_seconds = 0;
@@ -122,6 +123,7 @@ namespace castfem {
 
 // helpers of capi.cpp used by the surrogate interface
 void set_dt(fem_ctx *c, double dt);
+void set_dt_scen(fem_ctx *c, const std::vector<double> &dt);
 void eager_steps(fem_ctx *c, int64_t n);
 void run_steps(fem_ctx *c, int64_t n);
 void check_bound(fem_ctx *c, int fn_stage);

@@ -232,6 +232,7 @@ void prep_base(const Problem &p, Base &b) {
     tm.mark("node-element lists");
     double lam = 0.0;
     std::vector<double> lam_s(p.n_scen, 0.0);
+    b.kabs.assign(N, 0.0);
 #pragma omp parallel
     {
         std::vector<int32_t> cols;
@@ -261,8 +262,10 @@ void prep_base(const Problem &p, Base &b) {
                 }
             }
             if (eabs > eabs_t) eabs_t = eabs;
-            double row = b.robin_b[i];
-            for (double v : vals) row += std::fabs(v);
+            double kabs = 0.0;
+            for (double v : vals) kabs += std::fabs(v);
+            b.kabs[i] = kabs;
+            double row = b.robin_b[i] + kabs;
             for (int32_t s = b.lptr[i]; s < b.lptr[i + 1]; ++s) row += 2.0 * b.lw[s];
             double li = row / (b.m[i] * p.mats[b.nmat[i]].c);
             if (li > lam_t) lam_t = li;

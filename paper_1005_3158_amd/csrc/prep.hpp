@@ -115,6 +115,7 @@ struct Base {
     double dt_bound = 0;
     bool any_robin = false;
     std::vector<double> dt_scen;      // stability bound of every scenario
+    std::vector<double> kabs;         // sum_j |K_ij| of the assembled conduction operator per node
     double elem_abs_max = 0;          // max_i sum_{e at i} sum_j |K^e_ij|  (W/K)
     double T_span = 1;                // span of initial, fixed and ambient temperatures (K)
 };

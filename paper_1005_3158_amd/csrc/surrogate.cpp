@@ -1,0 +1,583 @@
+// C interface of the learned surrogate: device buffers, parameters, training
+// on device-resident solver states, prediction, and the accelerated advance
+// that checks every jump in FP64 and falls back to plain explicit steps.
+#include <omp.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "ctx.hpp"
+#include "surrogate.hpp"
+
+using namespace castfem;
+using namespace castfem::sur;
+
+namespace {
+
+enum SBuf {
+    S_NBR_PTR, S_NBR, S_INV_DEG, S_COEF, S_PARAMS, S_GRADS, S_ADAM_M, S_ADAM_V, S_WBF, S_X, S_ZIN, S_U, S_Z,
+    S_HL, S_Y, S_BASE, S_SCALE, S_TARGET, S_DH, S_DZ, S_DU, S_PARTIALS, S_LOSS, S_IDX, S_H0, S_H1, S_CHECK,
+    S_COUNT
+};
+const char *const SBUF_NAMES[S_COUNT] = {"nbr_ptr", "nbr", "inv_deg", "coef", "params", "grads", "adam_m",
+                                         "adam_v", "weights_bf16", "X", "Z_in", "U", "Z", "H_last", "y",
+                                         "base", "scale", "target", "dH", "dZ", "dU", "partials", "loss_part",
+                                         "sample_idx", "H0", "H1", "check"};
+
+// counter-based generator (SplitMix64 of seed and counter) for the
+// initial parameters and the sample shuffles
+inline uint64_t mix64(uint64_t z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+inline double unit(uint64_t seed, uint64_t stream, uint64_t k) {
+    return ((mix64(mix64(seed ^ (stream * 0xD1B54A32D192ED03ull)) + k) >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+}
+inline double normal(uint64_t seed, uint64_t stream, uint64_t k) {   // Box-Muller
+    const double u1 = unit(seed, stream, 2 * k), u2 = unit(seed, stream, 2 * k + 1);
+    return std::sqrt(-2.0 * std::log(u1)) * std::cos(6.283185307179586 * u2);
+}
+
+}  // namespace
+
+struct fem_sur {
+    fem_ctx *ctx = nullptr;
+    fem_sur_options opt{};
+    int64_t N = 0, rows = 0, nnz = 0, nb = 0;
+    ParamLayout pl;
+    std::vector<int32_t> nbr_ptr, nbr;
+    std::vector<float> inv_deg, coef;
+    int64_t sizes[S_COUNT] = {};
+    void *ptr[S_COUNT] = {};
+    bool bound = false;
+    SurDev d;
+    int adam_t = 0;
+};
+
+namespace {
+
+int64_t aligned(int64_t b) { return (b + ALIGN - 1) / ALIGN * ALIGN; }
+
+void sur_sizes(fem_sur *s) {
+    const int64_t N = s->N, R = s->rows, W = WIDTH, L = s->opt.layers, P = s->pl.total;
+    const bool tr = s->opt.train != 0;
+    int64_t *z = s->sizes;
+    std::fill(z, z + S_COUNT, 0);
+    z[S_NBR_PTR] = (N + 1) * 4;
+    z[S_NBR] = s->nnz * 4;
+    z[S_INV_DEG] = N * 4;
+    z[S_COEF] = N * 16;
+    z[S_PARAMS] = P * 4;
+    z[S_WBF] = (W * KIN + L * 2 * (2 * W * W)) * 2;
+    z[S_X] = R * KIN * 2;
+    z[S_ZIN] = R * W * 2;
+    z[S_U] = L * R * 2 * W * 2;
+    z[S_Z] = L * R * W * 2;
+    z[S_HL] = R * W * 2;
+    z[S_Y] = R * 4;
+    z[S_BASE] = R * 8;
+    z[S_SCALE] = R * 4;
+    z[S_H0] = N * 8;
+    z[S_H1] = N * 8;
+    z[S_CHECK] = check_blocks(N) * 4;
+    if (tr) {
+        z[S_GRADS] = P * 4;
+        z[S_ADAM_M] = P * 4;
+        z[S_ADAM_V] = P * 4;
+        z[S_TARGET] = R * 4;
+        z[S_DH] = R * W * 4;
+        z[S_DZ] = R * W * 2;
+        z[S_DU] = R * 2 * W * 4;
+        z[S_PARTIALS] = s->nb * (2 * W * W) * 4;
+        z[S_LOSS] = ((R + 255) / 256) * 8;
+        z[S_IDX] = (int64_t)s->opt.max_samples * 4;
+    }
+}
+
+// mesh neighbours (nodes sharing an element) in device numbering, as CSR
+void build_graph(fem_sur *s) {
+    const Layout &L = s->ctx->L();
+    const int64_t N = L.N, E = L.E;
+    const int nen = L.nen;
+    std::vector<int64_t> cnt(N + 1, 0);
+    for (int64_t k = 0; k < E * nen; ++k) ++cnt[L.conn[k] + 1];
+    for (int64_t i = 0; i < N; ++i) cnt[i + 1] += cnt[i];
+    std::vector<int64_t> inc(E * nen);
+    {
+        std::vector<int64_t> at(cnt.begin(), cnt.end() - 1);
+        for (int64_t k = 0; k < E * nen; ++k) inc[at[L.conn[k]]++] = k / nen;
+    }
+    std::vector<std::vector<int32_t>> nb(N);
+#pragma omp parallel for schedule(dynamic, 1024)
+    for (int64_t i = 0; i < N; ++i) {
+        std::vector<int32_t> &v = nb[i];
+        for (int64_t q = cnt[i]; q < cnt[i + 1]; ++q)
+            for (int a = 0; a < nen; ++a) {
+                const int32_t j = L.conn[inc[q] * nen + a];
+                if (j != i) v.push_back(j);
+            }
+        std::sort(v.begin(), v.end());
+        v.erase(std::unique(v.begin(), v.end()), v.end());
+    }
+    s->nbr_ptr.assign(N + 1, 0);
+    for (int64_t i = 0; i < N; ++i) s->nbr_ptr[i + 1] = s->nbr_ptr[i] + (int32_t)nb[i].size();
+    s->nnz = s->nbr_ptr[N];
+    s->nbr.resize(s->nnz);
+    s->inv_deg.resize(N);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < N; ++i) {
+        std::copy(nb[i].begin(), nb[i].end(), s->nbr.begin() + s->nbr_ptr[i]);
+        s->inv_deg[i] = nb[i].empty() ? 0.0f : 1.0f / (float)nb[i].size();
+    }
+}
+
+// per-node strengths over m_i c_i: Robin, interface, conduction
+void build_coef(fem_sur *s) {
+    const fem_ctx *c = s->ctx;
+    const Layout &L = c->L();
+    const Base &b = c->base;
+    s->coef.assign(L.N * 4, 0.0f);
+    for (int64_t g = 0; g < L.N; ++g) {
+        const int32_t o = L.iperm[g];
+        const double mc = b.m[o] * c->prob.mats[b.nmat[o]].c;
+        double wl = 0.0;
+        for (int32_t k = b.lptr[o]; k < b.lptr[o + 1]; ++k) wl += b.lw[k];
+        s->coef[4 * g + 0] = (float)(b.robin_b[o] / mc);
+        s->coef[4 * g + 1] = (float)(2.0 * wl / mc);
+        s->coef[4 * g + 2] = (float)(b.kabs[o] / mc);
+    }
+}
+
+void init_params(fem_sur *s, std::vector<float> &p) {
+    const ParamLayout &pl = s->pl;
+    const uint64_t seed = s->opt.seed;
+    p.assign(pl.total, 0.0f);
+    const double s_in = std::sqrt(2.0 / NFEAT), s_l = std::sqrt(1.0 / (2 * WIDTH));
+    for (int64_t k = 0; k < NFEAT * WIDTH; ++k) p[pl.w_in + k] = (float)(s_in * normal(seed, 1, k));
+    for (int l = 0; l < pl.layers; ++l)
+        for (int64_t k = 0; k < 2 * WIDTH * WIDTH; ++k) p[pl.w[l] + k] = (float)(s_l * normal(seed, 2 + l, k));
+    for (int64_t k = 0; k < WIDTH; ++k) p[pl.w_out + k] = (float)(0.01 * normal(seed, 9, k));
+}
+
+void fill_surdev(fem_sur *s) {
+    SurDev &d = s->d;
+    fem_ctx *c = s->ctx;
+    const int64_t R = s->rows, W = WIDTH;
+    d = SurDev{};
+    d.N = s->N;
+    d.layers = s->opt.layers;
+    d.horizon = s->opt.horizon;
+    d.loss_mode = s->opt.loss;
+    d.pl = s->pl;
+    d.nbr_ptr = (const int32_t *)s->ptr[S_NBR_PTR];
+    d.nbr = (const int32_t *)s->ptr[S_NBR];
+    d.inv_deg = (const float *)s->ptr[S_INV_DEG];
+    d.coef = (const float *)s->ptr[S_COEF];
+    d.flags = (const uint32_t *)c->ptr[B_FLAGS];
+    d.mats = c->ptr[B_MATS];
+    d.params = (float *)s->ptr[S_PARAMS];
+    d.grads = (float *)s->ptr[S_GRADS];
+    d.adam_m = (float *)s->ptr[S_ADAM_M];
+    d.adam_v = (float *)s->ptr[S_ADAM_V];
+    bf16 *wb = (bf16 *)s->ptr[S_WBF];
+    d.wt_in = wb;
+    wb += W * KIN;
+    for (int l = 0; l < d.layers; ++l) {
+        d.wt[l] = wb;
+        wb += 2 * W * W;
+        d.wr[l] = wb;
+        wb += 2 * W * W;
+    }
+    d.rows = R;
+    d.X = (bf16 *)s->ptr[S_X];
+    d.Zin = (bf16 *)s->ptr[S_ZIN];
+    for (int l = 0; l < d.layers; ++l) {
+        d.U[l] = (bf16 *)s->ptr[S_U] + l * R * 2 * W;
+        d.Z[l] = (bf16 *)s->ptr[S_Z] + l * R * W;
+    }
+    d.HL = (bf16 *)s->ptr[S_HL];
+    d.y = (float *)s->ptr[S_Y];
+    d.base = (double *)s->ptr[S_BASE];
+    d.scale = (float *)s->ptr[S_SCALE];
+    d.target = (float *)s->ptr[S_TARGET];
+    d.dH = (float *)s->ptr[S_DH];
+    d.dZ = (bf16 *)s->ptr[S_DZ];
+    d.dU = (float *)s->ptr[S_DU];
+    d.partials = (float *)s->ptr[S_PARTIALS];
+    d.n_partial_blocks = s->nb;
+    d.loss_part = (double *)s->ptr[S_LOSS];
+    d.H0 = (double *)s->ptr[S_H0];
+    d.H1 = (double *)s->ptr[S_H1];
+    d.check = (int32_t *)s->ptr[S_CHECK];
+}
+
+void need_bound(const fem_sur *s) {
+    if (!s->bound) throw PrepError{FEM_E_STATE, "call fem_sur_bind_buffers first"};
+}
+void need_train(const fem_sur *s) {
+    need_bound(s);
+    if (!s->opt.train) throw PrepError{FEM_E_STATE, "the surrogate was created without training buffers"};
+}
+void check_slots(const fem_sur *s, int64_t slots) {
+    if (slots < 1 || slots > s->opt.max_samples)
+        throw PrepError{FEM_E_INVALID_ARG, "between 1 and max_samples states per call"};
+}
+
+void upload_params(fem_sur *s, const float *p) {
+    HIPCHECK(hipMemcpyAsync(s->ptr[S_PARAMS], p, s->pl.total * 4, hipMemcpyHostToDevice, s->ctx->stream));
+    HIPCHECK(refresh_bf16(s->d, s->ctx->stream));
+    HIPCHECK(hipStreamSynchronize(s->ctx->stream));
+}
+
+// one forward and backward pass over `slots` states; loss partials left on the device
+void pass(fem_sur *s, const float *H0, const float *H1, const float *Ht, int64_t stride, const int32_t *idx,
+          int64_t slots) {
+    hipStream_t st = s->ctx->stream;
+    const int64_t R = slots * s->N;
+    HIPCHECK(features(s->d, H0, H1, 0, Ht, stride, idx, slots, st));
+    HIPCHECK(forward(s->d, R, st));
+    HIPCHECK(loss_and_dy(s->d, R, st));
+    HIPCHECK(backward(s->d, R, st));
+}
+
+double loss_of(fem_sur *s, int64_t R) {
+    const int64_t nl = (R + 255) / 256;
+    std::vector<double> lp(nl);
+    HIPCHECK(hipMemcpyAsync(lp.data(), s->ptr[S_LOSS], nl * 8, hipMemcpyDeviceToHost, s->ctx->stream));
+    HIPCHECK(hipStreamSynchronize(s->ctx->stream));
+    double sum = 0.0;
+    for (double v : lp) sum += v;
+    return sum / (double)R;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fem_sur_create(fem_sur **out, fem_ctx *ctx, const fem_sur_options *o) {
+    if (!out || !ctx || !o) return set_err(FEM_E_INVALID_ARG, "null argument");
+    *out = nullptr;
+    return guarded([&] {
+        check_bound(ctx, ST_BOUND);
+        if (o->width != WIDTH) throw PrepError{FEM_E_UNSUPPORTED, "width must be 64"};
+        if (o->layers < 1 || o->layers > MAX_LAYERS) throw PrepError{FEM_E_INVALID_ARG, "layers must be 1..4"};
+        if (o->horizon < 2) throw PrepError{FEM_E_INVALID_ARG, "horizon must be >= 2"};
+        if (o->max_samples < 1) throw PrepError{FEM_E_INVALID_ARG, "max_samples must be >= 1"};
+        if (o->loss != FEM_SUR_LOSS_H && o->loss != FEM_SUR_LOSS_T) throw PrepError{FEM_E_INVALID_ARG, "unknown loss"};
+        for (int32_t r : o->reserved)
+            if (r) throw PrepError{FEM_E_INVALID_ARG, "reserved fields must be zero"};
+        if ((int64_t)o->max_samples * ctx->L().N > (int64_t)1 << 31)
+            throw PrepError{FEM_E_INVALID_ARG, "max_samples * n_nodes must stay below 2^31 rows"};
+        fem_sur *s = new fem_sur;
+        s->ctx = ctx;
+        s->opt = *o;
+        s->N = ctx->L().N;
+        s->rows = (int64_t)o->max_samples * s->N;
+        s->nb = (s->rows + GRAD_ROWS - 1) / GRAD_ROWS;
+        s->pl.build(o->layers);
+        try {
+            build_graph(s);
+            build_coef(s);
+            sur_sizes(s);
+        } catch (...) {
+            delete s;
+            throw;
+        }
+        *out = s;
+    });
+}
+
+int fem_sur_destroy(fem_sur *s) {
+    delete s;
+    return FEM_OK;
+}
+
+int fem_sur_query_buffers(const fem_sur *s, fem_buffer_desc *d, int32_t *n) {
+    if (!s || !n) return set_err(FEM_E_INVALID_ARG, "null argument");
+    if (!d) {
+        *n = S_COUNT;
+        return FEM_OK;
+    }
+    if (*n < S_COUNT) return set_err(FEM_E_INVALID_ARG, "descriptor array too small");
+    for (int k = 0; k < S_COUNT; ++k) {
+        std::memset(&d[k], 0, sizeof(fem_buffer_desc));
+        std::strncpy(d[k].name, SBUF_NAMES[k], sizeof(d[k].name) - 1);
+        d[k].bytes = s->sizes[k] ? aligned(s->sizes[k]) : 0;
+        d[k].alignment = ALIGN;
+    }
+    *n = S_COUNT;
+    return FEM_OK;
+}
+
+int fem_sur_bind_buffers(fem_sur *s, void *const *dev_ptrs, int32_t n) {
+    if (!s || !dev_ptrs) return set_err(FEM_E_INVALID_ARG, "null argument");
+    return guarded([&] {
+        if (n != S_COUNT) throw PrepError{FEM_E_INVALID_ARG, "expected " + std::to_string(S_COUNT) + " buffers"};
+        for (int k = 0; k < S_COUNT; ++k) {
+            if (s->sizes[k] && !dev_ptrs[k]) throw PrepError{FEM_E_INVALID_ARG, std::string("buffer ") + SBUF_NAMES[k] + " is null"};
+            if ((uintptr_t)dev_ptrs[k] % ALIGN) throw PrepError{FEM_E_INVALID_ARG, std::string("buffer ") + SBUF_NAMES[k] + " is misaligned"};
+            s->ptr[k] = s->sizes[k] ? dev_ptrs[k] : nullptr;
+        }
+        fill_surdev(s);
+        hipStream_t st = s->ctx->stream;
+        HIPCHECK(hipMemcpyAsync(s->ptr[S_NBR_PTR], s->nbr_ptr.data(), s->sizes[S_NBR_PTR], hipMemcpyHostToDevice, st));
+        if (s->nnz) HIPCHECK(hipMemcpyAsync(s->ptr[S_NBR], s->nbr.data(), s->sizes[S_NBR], hipMemcpyHostToDevice, st));
+        HIPCHECK(hipMemcpyAsync(s->ptr[S_INV_DEG], s->inv_deg.data(), s->sizes[S_INV_DEG], hipMemcpyHostToDevice, st));
+        HIPCHECK(hipMemcpyAsync(s->ptr[S_COEF], s->coef.data(), s->sizes[S_COEF], hipMemcpyHostToDevice, st));
+        if (s->opt.train) {
+            HIPCHECK(hipMemsetAsync(s->ptr[S_ADAM_M], 0, s->sizes[S_ADAM_M], st));
+            HIPCHECK(hipMemsetAsync(s->ptr[S_ADAM_V], 0, s->sizes[S_ADAM_V], st));
+        }
+        std::vector<float> p;
+        init_params(s, p);
+        s->bound = true;
+        s->adam_t = 0;
+        upload_params(s, p.data());
+    });
+}
+
+int fem_sur_n_params(const fem_sur *s, int64_t *n) {
+    if (!s || !n) return set_err(FEM_E_INVALID_ARG, "null argument");
+    *n = s->pl.total;
+    return FEM_OK;
+}
+
+int fem_sur_get_params(fem_sur *s, float *host, int64_t n) {
+    if (!s || !host) return set_err(FEM_E_INVALID_ARG, "null argument");
+    return guarded([&] {
+        need_bound(s);
+        if (n != s->pl.total) throw PrepError{FEM_E_INVALID_ARG, "parameter count mismatch"};
+        HIPCHECK(hipMemcpyAsync(host, s->ptr[S_PARAMS], n * 4, hipMemcpyDeviceToHost, s->ctx->stream));
+        HIPCHECK(hipStreamSynchronize(s->ctx->stream));
+    });
+}
+
+int fem_sur_set_params(fem_sur *s, const float *host, int64_t n) {
+    if (!s || !host) return set_err(FEM_E_INVALID_ARG, "null argument");
+    return guarded([&] {
+        need_bound(s);
+        if (n != s->pl.total) throw PrepError{FEM_E_INVALID_ARG, "parameter count mismatch"};
+        for (int64_t k = 0; k < n; ++k)
+            if (!std::isfinite(host[k])) throw PrepError{FEM_E_INVALID_ARG, "parameters must be finite"};
+        upload_params(s, host);
+        s->adam_t = 0;
+        if (s->opt.train) {
+            HIPCHECK(hipMemsetAsync(s->ptr[S_ADAM_M], 0, s->sizes[S_ADAM_M], s->ctx->stream));
+            HIPCHECK(hipMemsetAsync(s->ptr[S_ADAM_V], 0, s->sizes[S_ADAM_V], s->ctx->stream));
+            HIPCHECK(hipStreamSynchronize(s->ctx->stream));
+        }
+    });
+}
+
+int fem_sur_features(fem_sur *s, const float *H0, const float *H1, int64_t stride, int64_t slots, float *X_host) {
+    if (!s || !H0 || !H1 || !X_host) return set_err(FEM_E_INVALID_ARG, "null argument");
+    return guarded([&] {
+        need_bound(s);
+        check_slots(s, slots);
+        const int64_t R = slots * s->N;
+        HIPCHECK(features(s->d, H0, H1, 0, nullptr, stride, nullptr, slots, s->ctx->stream));
+        std::vector<bf16> x(R * KIN);
+        HIPCHECK(hipMemcpyAsync(x.data(), s->ptr[S_X], R * KIN * 2, hipMemcpyDeviceToHost, s->ctx->stream));
+        HIPCHECK(hipStreamSynchronize(s->ctx->stream));
+        for (int64_t r = 0; r < R; ++r)
+            for (int k = 0; k < NFEAT; ++k) {
+                const uint32_t u = (uint32_t)x[r * KIN + k] << 16;
+                float f;
+                std::memcpy(&f, &u, 4);
+                X_host[r * NFEAT + k] = f;
+            }
+    });
+}
+
+int fem_sur_loss_grad(fem_sur *s, const float *H0, const float *H1, const float *Ht, int64_t stride, int64_t slots,
+                      double *loss, float *grad_host) {
+    if (!s || !H0 || !H1 || !Ht || !loss || !grad_host) return set_err(FEM_E_INVALID_ARG, "null argument");
+    return guarded([&] {
+        need_train(s);
+        check_slots(s, slots);
+        pass(s, H0, H1, Ht, stride, nullptr, slots);
+        HIPCHECK(hipMemcpyAsync(grad_host, s->ptr[S_GRADS], s->pl.total * 4, hipMemcpyDeviceToHost, s->ctx->stream));
+        *loss = loss_of(s, slots * s->N);
+    });
+}
+
+int fem_sur_train(fem_sur *s, const float *H0, const float *H1, const float *Ht, int64_t stride, int64_t n_samples,
+                  int32_t batch, int32_t epochs, float lr, float lr_final, uint64_t seed, double *loss_per_epoch) {
+    if (!s || !H0 || !H1 || !Ht) return set_err(FEM_E_INVALID_ARG, "null argument");
+    return guarded([&] {
+        need_train(s);
+        check_slots(s, batch);
+        if (n_samples < 1 || epochs < 0 || !(lr > 0) || !(lr_final > 0))
+            throw PrepError{FEM_E_INVALID_ARG, "need n_samples >= 1, epochs >= 0 and positive rates"};
+        if (n_samples > INT32_MAX) throw PrepError{FEM_E_INVALID_ARG, "too many samples"};
+        hipStream_t st = s->ctx->stream;
+        const int64_t per_epoch = (n_samples + batch - 1) / batch;
+        const int64_t total = per_epoch * epochs;
+        int64_t it = 0;
+        std::vector<int32_t> perm(n_samples);
+        for (int32_t e = 0; e < epochs; ++e) {
+            // shuffle: sort by a counter-based key (seed, epoch, sample)
+            std::vector<uint64_t> key(n_samples);
+            for (int64_t k = 0; k < n_samples; ++k) key[k] = mix64(mix64(seed + 0x632BE59BD9B4E019ull * (e + 1)) ^ (uint64_t)k);
+            std::iota(perm.begin(), perm.end(), 0);
+            std::sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+            double lsum = 0.0;
+            int64_t lrows = 0;
+            for (int64_t b0 = 0; b0 < n_samples; b0 += batch) {
+                const int64_t slots = std::min<int64_t>(batch, n_samples - b0);
+                HIPCHECK(hipMemcpyAsync(s->ptr[S_IDX], perm.data() + b0, slots * 4, hipMemcpyHostToDevice, st));
+                pass(s, H0, H1, Ht, stride, (const int32_t *)s->ptr[S_IDX], slots);
+                // cosine decay from lr to lr_final over all iterations
+                const double fr = total > 1 ? (double)it / (double)(total - 1) : 0.0;
+                const float rate = (float)(lr_final + 0.5 * (lr - lr_final) * (1.0 + std::cos(3.141592653589793 * fr)));
+                HIPCHECK(adam(s->d, rate, 0.9f, 0.999f, 1e-8f, ++s->adam_t, st));
+                HIPCHECK(refresh_bf16(s->d, st));
+                lsum += loss_of(s, slots * s->N) * (double)(slots * s->N);
+                lrows += slots * s->N;
+                ++it;
+            }
+            if (loss_per_epoch) loss_per_epoch[e] = lsum / (double)lrows;
+        }
+        HIPCHECK(hipStreamSynchronize(st));
+    });
+}
+
+int fem_sur_predict(fem_sur *s, const float *H0, const float *H1, int64_t stride, int64_t slots, double *H_out) {
+    if (!s || !H0 || !H1 || !H_out) return set_err(FEM_E_INVALID_ARG, "null argument");
+    return guarded([&] {
+        need_bound(s);
+        check_slots(s, slots);
+        hipStream_t st = s->ctx->stream;
+        const int64_t R = slots * s->N;
+        HIPCHECK(features(s->d, H0, H1, 0, nullptr, stride, nullptr, slots, st));
+        HIPCHECK(forward(s->d, R, st));
+        HIPCHECK(apply(s->d, R, H_out, st));
+        HIPCHECK(hipStreamSynchronize(st));
+    });
+}
+
+int fem_snapshot_H(fem_ctx *ctx, float *H_dev) {
+    if (!ctx || !H_dev) return set_err(FEM_E_INVALID_ARG, "null argument");
+    return guarded([&] {
+        check_bound(ctx, ST_BOUND);
+        HIPCHECK(state_to_f32(ctx->dev, H_dev, ctx->stream));
+    });
+}
+
+int fem_advance(fem_ctx *ctx, fem_sur *s, const double *dt_per_scenario, int64_t max_steps, int32_t until_solid,
+                double energy_tol, double fs_tol, fem_advance_report *rep) {
+    if (!ctx || !dt_per_scenario || !rep) return set_err(FEM_E_INVALID_ARG, "null argument");
+    return guarded([&] {
+        const auto t0 = std::chrono::steady_clock::now();
+        check_bound(ctx, ST_BOUND);
+        if (s) {
+            need_bound(s);
+            if (s->ctx != ctx) throw PrepError{FEM_E_INVALID_ARG, "the surrogate belongs to another context"};
+        }
+        if (max_steps < 0 || !(energy_tol > 0) || !(fs_tol >= 0))
+            throw PrepError{FEM_E_INVALID_ARG, "need max_steps >= 0, energy_tol > 0, fs_tol >= 0"};
+        const int32_t ns = ctx->prob.n_scen;
+        std::vector<double> dt(dt_per_scenario, dt_per_scenario + ns);
+        for (int32_t sc = 0; sc < ns; ++sc) {
+            if (!(dt[sc] > 0) || !std::isfinite(dt[sc])) throw PrepError{FEM_E_INVALID_ARG, "every dt must be > 0"};
+            if (dt[sc] > ctx->base.dt_scen[sc] && !ctx->opt.allow_unstable)
+                throw PrepError{FEM_E_UNSTABLE, "dt of scenario " + std::to_string(sc) + " above its stability bound"};
+        }
+        set_dt_scen(ctx, dt);
+        std::memset(rep, 0, sizeof(*rep));
+        const int64_t H = s ? s->opt.horizon : GRAPH_STEPS;
+        hipStream_t st = ctx->stream;
+        std::vector<fem_energy_report> er(ns);
+        energy_scenarios(ctx, er.data());
+        auto all_solid = [&] {
+            for (const fem_energy_report &r : er)
+                if (r.n_liquid) return false;
+            return true;
+        };
+        auto advance_clock = [&](int64_t n) {
+            ctx->steps += n;
+            for (int32_t sc = 0; sc < ns; ++sc) ctx->time_s[sc] += dt[sc] * (double)n;
+            rep->steps += n;
+        };
+        std::vector<double> E_prev(ns), Q_prev(ns), rate_prev(ns, NAN);
+        for (int32_t sc = 0; sc < ns; ++sc) {
+            E_prev[sc] = er[sc].E;
+            Q_prev[sc] = er[sc].Q_cum;
+        }
+        const int64_t nchk = check_blocks(ctx->L().N);
+        std::vector<int32_t> chk(nchk);
+        while (!(until_solid && all_solid()) && rep->steps + H <= max_steps) {
+            if (!s) {
+                run_steps(ctx, H);
+                advance_clock(H);
+                rep->plain_steps += H;
+                energy_scenarios(ctx, er.data());
+                continue;
+            }
+            // one plain step from H0 to H1, then the network jumps H - 1 steps further
+            HIPCHECK(state_to_f64(ctx->dev, s->d.H0, st));
+            run_steps(ctx, 1);
+            advance_clock(1);
+            rep->plain_steps += 1;
+            HIPCHECK(state_to_f64(ctx->dev, s->d.H1, st));
+            HIPCHECK(features(s->d, s->d.H0, s->d.H1, 1, nullptr, s->N, nullptr, 1, st));
+            HIPCHECK(forward(s->d, s->N, st));
+            HIPCHECK(write_jump(s->d, ctx->dev, ctx->parity, (float)fs_tol, st));
+            HIPCHECK(hipMemcpyAsync(chk.data(), s->ptr[S_CHECK], nchk * 4, hipMemcpyDeviceToHost, st));
+            energy_scenarios(ctx, er.data());       // synchronises
+            int64_t bad = 0;
+            for (int32_t v : chk) bad += v;
+            // FP64 gate of the jump: energy change against the boundary inflow
+            // extrapolated from the plain step (linear trend of the per-step
+            // inflow when the previous jump supplies one)
+            bool ok = bad == 0;
+            std::vector<double> est(ns), res(ns);
+            for (int32_t sc = 0; sc < ns && ok; ++sc) {
+                const fem_energy_report &r = er[sc];
+                const double rate = r.Q_cum - Q_prev[sc];
+                const double m = (double)(H - 1);
+                est[sc] = m * rate + (std::isnan(rate_prev[sc]) ? 0.0 : (rate - rate_prev[sc]) / (double)H * m * (double)H / 2.0);
+                res[sc] = std::fabs((r.E - E_prev[sc]) - (rate + est[sc])) / std::fabs(E_prev[sc] - ctx->Eref_s[sc]);
+                if (r.nonfinite || !(res[sc] <= energy_tol)) ok = false;
+            }
+            if (ok) {
+                for (int32_t sc = 0; sc < ns; ++sc) {
+                    const double rate = er[sc].Q_cum - Q_prev[sc];
+                    ctx->Qx_s[sc] += est[sc];
+                    E_prev[sc] = er[sc].E;
+                    Q_prev[sc] = er[sc].Q_cum + est[sc];
+                    rate_prev[sc] = rate;
+                    er[sc].Q_cum += est[sc];
+                    rep->max_residual = std::max(rep->max_residual, res[sc]);
+                }
+                advance_clock(H - 1);
+                ++rep->jumps_accepted;
+            } else {
+                HIPCHECK(restore_h1(s->d, ctx->dev, ctx->parity, st));
+                run_steps(ctx, H - 1);
+                advance_clock(H - 1);
+                rep->plain_steps += H - 1;
+                ++rep->jumps_rejected;
+                const std::vector<double> Q_start(Q_prev);
+                energy_scenarios(ctx, er.data());
+                for (int32_t sc = 0; sc < ns; ++sc) {
+                    E_prev[sc] = er[sc].E;
+                    rate_prev[sc] = (er[sc].Q_cum - Q_start[sc]) / (double)H;
+                    Q_prev[sc] = er[sc].Q_cum;
+                }
+            }
+        }
+        HIPCHECK(hipStreamSynchronize(st));
+        rep->solid = all_solid() ? 1 : 0;
+        rep->wall_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    });
+}
+
+}  // extern "C"

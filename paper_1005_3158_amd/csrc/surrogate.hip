@@ -1,0 +1,519 @@
+// gfx950 kernels of the message-passing surrogate: features, BF16 MFMA
+// products (forward, data gradient, weight gradient), mean-neighbour
+// aggregation and its transpose, output layer and loss, Adam.
+#include "surrogate.hpp"
+
+#include <algorithm>
+
+#include "kernels.hpp"
+
+namespace castfem {
+namespace sur {
+namespace {
+
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float bf2f(bf16 b) { return __uint_as_float((uint32_t)b << 16); }
+
+// round to nearest even (NaN stays NaN)
+__device__ __forceinline__ bf16 f2bf(float f) {
+    const uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (bf16)((u >> 16) | 0x40u);
+    return (bf16)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+__device__ __forceinline__ s4 load_s4(const bf16 *p) {
+    const uint2 v = *(const uint2 *)p;
+    s4 r;
+    r[0] = (short)(v.x & 0xffff);
+    r[1] = (short)(v.x >> 16);
+    r[2] = (short)(v.y & 0xffff);
+    r[3] = (short)(v.y >> 16);
+    return r;
+}
+
+// enthalpy relation of the node's material (as in the explicit step)
+__device__ __forceinline__ void t_of_h(const MatDev &M, double H, double &T, double &fs) {
+    if (!M.latent || H <= M.Hs) {
+        T = H * M.inv_c;
+        fs = 1.0;
+    } else if (H >= M.Hl) {
+        T = (H - M.L) * M.inv_c;
+        fs = 0.0;
+    } else {
+        T = M.Ts + (H - M.Hs) * M.slope;
+        fs = 1.0 - (H - M.Hs) * M.inv_dH;
+    }
+}
+
+// ---------------------------------------------------------------- features
+// Row r = q N + i holds node i of state slot q; the state is sample idx[q]
+// (q without a list), read at offset sample * stride of H0 / H1 / Ht.
+template <class HT>
+__global__ __launch_bounds__(256) void k_features(SurDev s, const HT *H0, const HT *H1, const float *Ht,
+                                                  int64_t stride, const int32_t *idx, int64_t slots) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= slots * s.N) return;
+    const int64_t q = r / s.N, i = r - q * s.N;
+    const int64_t at = (idx ? (int64_t)idx[q] : q) * stride + i;
+    const MatDev &M = ((const MatDev *)s.mats)[s.flags[i] & NODE_MAT_MASK];
+    const double h0 = (double)H0[at], h1 = (double)H1[at];
+    double T1, fs1;
+    t_of_h(M, h1, T1, fs1);
+    const float4 co = ((const float4 *)s.coef)[i];
+    const double c = M.c, dt = M.dt, hz = (double)s.horizon;
+    float x[NFEAT];
+    x[0] = (float)((T1 - T_REF) / T_SCALE);
+    x[1] = (float)fs1;
+    x[2] = M.latent ? 1.0f : 0.0f;
+    x[3] = (float)(co.x * dt);
+    x[4] = (float)(co.y * dt);
+    x[5] = (float)(co.z * dt);
+    x[6] = (float)(hz * (h1 - h0) / (c * T_SCALE));
+    x[7] = 1.0f;
+    uint32_t w[KIN / 2];
+    for (int k = 0; k < NFEAT / 2; ++k) w[k] = (uint32_t)f2bf(x[2 * k]) | ((uint32_t)f2bf(x[2 * k + 1]) << 16);
+    for (int k = NFEAT / 2; k < KIN / 2; ++k) w[k] = 0;
+    uint4 *out = (uint4 *)(s.X + r * KIN);
+    out[0] = make_uint4(w[0], w[1], w[2], w[3]);
+    out[1] = make_uint4(w[4], w[5], w[6], w[7]);
+    s.base[r] = h1 + (hz - 1.0) * (h1 - h0);
+    s.scale[r] = (float)(c * DH_SCALE);
+    if (Ht) {
+        if (s.loss_mode == LOSS_T) {
+            double Tt, fst;
+            t_of_h(M, (double)Ht[at], Tt, fst);
+            s.target[r] = (float)Tt;
+        } else {
+            s.target[r] = (float)(((double)Ht[at] - s.base[r]) / (c * DH_SCALE));
+        }
+    }
+}
+
+// ---------------------------------------------------------------- products
+// C[R x NOUT] = A[R x K] B[K x NOUT], B given transposed (Bt: NOUT x K, row-major).
+// One wavefront computes 16 rows; MFMA operands follow the 16x16x16 layout:
+// lane l holds A[l%16][4(l/16)+j], B[4(l/16)+j][l%16], D[4(l/16)+j][l%16].
+// MODE 0: z = C + bias -> Zout, h = relu(z) -> Hout
+// MODE 1: z = C + bias -> Zout, h = Hprev + relu(z) -> Hout
+// MODE 2: C -> Cout (FP32)
+template <int NOUT, int MODE>
+__global__ __launch_bounds__(256) void k_gemm(const bf16 *__restrict__ A, int lda, int K, const bf16 *__restrict__ Bt,
+                                              const float *__restrict__ bias, int64_t R, bf16 *Zout,
+                                              const bf16 *Hprev, int ldhp, bf16 *Hout, int ldh, float *Cout, int ldc) {
+    constexpr int NT = NOUT / 16;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t row0 = (int64_t)blockIdx.x * 64 + wave * 16;
+    const int ar = lane & 15, kq = (lane >> 4) * 4;
+    const int64_t arow = row0 + ar;
+    f4 acc[NT];
+    for (int t = 0; t < NT; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        s4 a = {0, 0, 0, 0};
+        if (arow < R) a = load_s4(A + arow * lda + k0 + kq);
+        for (int t = 0; t < NT; ++t) {
+            const s4 b = load_s4(Bt + (int64_t)(t * 16 + ar) * K + k0 + kq);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+        }
+    }
+    for (int t = 0; t < NT; ++t) {
+        const int col = t * 16 + ar;
+        for (int j = 0; j < 4; ++j) {
+            const int64_t row = row0 + kq + j;
+            if (row >= R) continue;
+            const float v = acc[t][j];
+            if constexpr (MODE == 2) {
+                Cout[row * ldc + col] = v;
+            } else {
+                const float z = v + bias[col];
+                Zout[row * NOUT + col] = f2bf(z);
+                const float act = z > 0.f ? z : 0.f;
+                const float h = MODE == 0 ? act : bf2f(Hprev[row * ldhp + col]) + act;
+                Hout[row * ldh + col] = f2bf(h);
+            }
+        }
+    }
+}
+
+// partial weight gradients: P[wg][KA x 64] = sum over the workgroup's rows of
+// A[r][f] B[r][c] (A: R x KA with row stride lda, B: R x 64); MFMA K runs over rows
+template <int KA>
+__global__ __launch_bounds__(256) void k_wgrad(const bf16 *__restrict__ A, int lda, const bf16 *__restrict__ B,
+                                               int64_t R, float *__restrict__ P) {
+    constexpr int FT = KA / 16;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int mi = lane & 15, kq = (lane >> 4) * 4;
+    const int c = wave * 16 + mi;            // this wave's output columns
+    f4 acc[FT];
+    for (int t = 0; t < FT; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
+    const int64_t r_begin = (int64_t)blockIdx.x * GRAD_ROWS;
+    const int64_t r_end = std::min<int64_t>(R, r_begin + GRAD_ROWS);
+    for (int64_t r0 = r_begin; r0 < r_end; r0 += 16) {
+        s4 b;
+        for (int j = 0; j < 4; ++j) {
+            const int64_t r = r0 + kq + j;
+            b[j] = r < r_end ? (short)B[r * WIDTH + c] : (short)0;
+        }
+        for (int t = 0; t < FT; ++t) {
+            s4 a;
+            for (int j = 0; j < 4; ++j) {
+                const int64_t r = r0 + kq + j;
+                a[j] = r < r_end ? (short)A[r * lda + t * 16 + mi] : (short)0;
+            }
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+        }
+    }
+    float *out = P + (int64_t)blockIdx.x * KA * WIDTH;
+    for (int t = 0; t < FT; ++t)
+        for (int j = 0; j < 4; ++j) out[(t * 16 + kq + j) * WIDTH + wave * 16 + mi] = acc[t][j];
+}
+
+// column sums of B (R x 64) per workgroup chunk
+__global__ __launch_bounds__(256) void k_colsum(const bf16 *__restrict__ B, int64_t R, float *__restrict__ P) {
+    __shared__ float part[4][WIDTH];
+    const int c = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int64_t r_begin = (int64_t)blockIdx.x * GRAD_ROWS;
+    const int64_t r_end = std::min<int64_t>(R, r_begin + GRAD_ROWS);
+    float acc = 0.f;
+    for (int64_t r = r_begin + q; r < r_end; r += 4) acc += bf2f(B[r * WIDTH + c]);
+    part[q][c] = acc;
+    __syncthreads();
+    if (q == 0) P[(int64_t)blockIdx.x * WIDTH + c] = ((part[0][c] + part[1][c]) + part[2][c]) + part[3][c];
+}
+
+// sum of the workgroup partials in workgroup order into grads[off + k], k < n
+// (rows of a partial are `ld` floats apart; only the first `rows` rows are kept)
+__global__ void k_reduce(const float *__restrict__ P, int64_t nblk, int64_t per, int keep, float *__restrict__ out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= keep) return;
+    float s = 0.f;
+    for (int64_t b = 0; b < nblk; ++b) s += P[b * per + k];
+    out[k] = s;
+}
+
+// ---------------------------------------------------------------- graph
+// U[r][WIDTH + c] = mean over neighbours j of U[j][c], rows of one sample at a time
+__global__ __launch_bounds__(256) void k_agg(SurDev s, bf16 *U, int64_t R) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t r = t >> 3;
+    const int ch = (int)(t & 7);
+    if (r >= R) return;
+    const int64_t i = r % s.N, base = r - i;
+    float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int32_t q = s.nbr_ptr[i]; q < s.nbr_ptr[i + 1]; ++q) {
+        const uint4 v = *(const uint4 *)(U + (base + s.nbr[q]) * 2 * WIDTH + ch * 8);
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+        for (int k = 0; k < 4; ++k) {
+            acc[2 * k] += bf2f((bf16)(w[k] & 0xffff));
+            acc[2 * k + 1] += bf2f((bf16)(w[k] >> 16));
+        }
+    }
+    const float id = s.inv_deg[i];
+    uint32_t o[4];
+    for (int k = 0; k < 4; ++k) o[k] = (uint32_t)f2bf(acc[2 * k] * id) | ((uint32_t)f2bf(acc[2 * k + 1] * id) << 16);
+    *(uint4 *)(U + r * 2 * WIDTH + WIDTH + ch * 8) = make_uint4(o[0], o[1], o[2], o[3]);
+}
+
+// dH[j] += dU[j][:WIDTH] + sum over neighbours i of dU[i][WIDTH:] / deg_i  (transpose of the mean)
+__global__ __launch_bounds__(256) void k_aggT(SurDev s, const float *dU, float *dH, int64_t R) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t r = t / WIDTH;
+    const int c = (int)(t % WIDTH);
+    if (r >= R) return;
+    const int64_t j = r % s.N, base = r - j;
+    float acc = dH[r * WIDTH + c] + dU[r * 2 * WIDTH + c];
+    for (int32_t q = s.nbr_ptr[j]; q < s.nbr_ptr[j + 1]; ++q) {
+        const int64_t i = s.nbr[q];
+        acc += dU[(base + i) * 2 * WIDTH + WIDTH + c] * s.inv_deg[i];
+    }
+    dH[r * WIDTH + c] = acc;
+}
+
+// dZ = dH where z > 0, else 0 (BF16)
+__global__ __launch_bounds__(256) void k_relu_back(const float *dH, const bf16 *Z, bf16 *dZ, int64_t n) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) dZ[k] = bf2f(Z[k]) > 0.f ? f2bf(dH[k]) : (bf16)0;
+}
+
+// ---------------------------------------------------------------- output, loss
+__global__ __launch_bounds__(256) void k_out(SurDev s, int64_t R) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    const float *w = s.params + s.pl.w_out;
+    float acc = s.params[s.pl.b_out];
+    const bf16 *h = s.HL + r * WIDTH;
+    for (int c = 0; c < WIDTH; ++c) acc += bf2f(h[c]) * w[c];
+    s.y[r] = acc;
+}
+
+// per row: error e and dL/dy of the loss sum_r e_r^2 / R.
+// LOSS_H: e = y - t.  LOSS_T: e = (T(base + scale y) - T_t) / DT_SCALE, with the
+// slope of the branch of T(H) the prediction lies on.
+// Writes the per-workgroup loss partial, dy (into y) and dH = dy w_out.
+__global__ __launch_bounds__(256) void k_loss(SurDev s, int64_t R) {
+    __shared__ double part[4];
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double e2 = 0.0;
+    if (r < R) {
+        float dy;
+        if (s.loss_mode == LOSS_T) {
+            const MatDev &M = ((const MatDev *)s.mats)[s.flags[r % s.N] & NODE_MAT_MASK];
+            const double Hp = s.base[r] + (double)s.scale[r] * (double)s.y[r];
+            double Tp, fsp;
+            t_of_h(M, Hp, Tp, fsp);
+            const double dTdH = (!M.latent || Hp <= M.Hs || Hp >= M.Hl) ? M.inv_c : M.slope;
+            const double e = (Tp - (double)s.target[r]) / DT_SCALE;
+            e2 = e * e;
+            dy = (float)(2.0 * e / (double)R * dTdH * (double)s.scale[r] / DT_SCALE);
+        } else {
+            const float e = s.y[r] - s.target[r];
+            e2 = (double)e * (double)e;
+            dy = 2.f * e / (float)R;
+        }
+        s.y[r] = dy;
+        const float *w = s.params + s.pl.w_out;
+        for (int c = 0; c < WIDTH; ++c) s.dH[r * WIDTH + c] = dy * w[c];
+    }
+    for (int off = 32; off > 0; off >>= 1) e2 += __shfl_down(e2, off, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = e2;
+    __syncthreads();
+    if (threadIdx.x == 0) s.loss_part[blockIdx.x] = ((part[0] + part[1]) + part[2]) + part[3];
+}
+
+// partials of dw_out = sum_r HL[r] dy[r] and db_out = sum_r dy[r]
+__global__ __launch_bounds__(256) void k_out_grad(SurDev s, int64_t R, float *P) {
+    __shared__ float part[4][WIDTH + 1];
+    const int c = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int64_t r_begin = (int64_t)blockIdx.x * GRAD_ROWS;
+    const int64_t r_end = std::min<int64_t>(R, r_begin + GRAD_ROWS);
+    float acc = 0.f, accb = 0.f;
+    for (int64_t r = r_begin + q; r < r_end; r += 4) {
+        const float dy = s.y[r];
+        acc += bf2f(s.HL[r * WIDTH + c]) * dy;
+        if (c == 0) accb += dy;
+    }
+    part[q][c] = acc;
+    if (c == 0) part[q][WIDTH] = accb;
+    __syncthreads();
+    if (q == 0) {
+        P[(int64_t)blockIdx.x * (WIDTH + 1) + c] = ((part[0][c] + part[1][c]) + part[2][c]) + part[3][c];
+        if (c == 0)
+            P[(int64_t)blockIdx.x * (WIDTH + 1) + WIDTH] =
+                ((part[0][WIDTH] + part[1][WIDTH]) + part[2][WIDTH]) + part[3][WIDTH];
+    }
+}
+
+__global__ void k_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2,
+                       float eps, float c1, float c2) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const float gk = g[k];
+    const float mk = b1 * m[k] + (1.f - b1) * gk;
+    const float vk = b2 * v[k] + (1.f - b2) * gk * gk;
+    m[k] = mk;
+    v[k] = vk;
+    p[k] -= lr * (mk / c1) / (sqrtf(vk / c2) + eps);
+}
+
+__global__ void k_refresh(SurDev s) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const float *p = s.params;
+    if (t < WIDTH * KIN) {                                  // W_in^T, zero-padded
+        const int c = t / KIN, f = t % KIN;
+        s.wt_in[t] = f < NFEAT ? f2bf(p[s.pl.w_in + f * WIDTH + c]) : (bf16)0;
+    }
+    for (int l = 0; l < s.layers; ++l) {
+        if (t < 2 * WIDTH * WIDTH) {
+            const int c = t / (2 * WIDTH), k = t % (2 * WIDTH);   // wt[l][c][k] = W_l[k][c]
+            s.wt[l][t] = f2bf(p[s.pl.w[l] + k * WIDTH + c]);
+            s.wr[l][t] = f2bf(p[s.pl.w[l] + t]);                 // row-major copy
+        }
+    }
+}
+
+__global__ void k_apply(SurDev s, int64_t R, double *H) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < R) H[r] = s.base[r] + (double)s.scale[r] * (double)s.y[r];
+}
+
+// ---------------------------------------------------------------- solver state
+template <class OUT>
+__global__ __launch_bounds__(256) void k_state_out(Dev d, OUT *out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= d.N) return;
+    double h;
+    if (d.prec == FEM_PREC_FP64) {
+        h = ((const double *)d.H)[i];
+    } else {
+        const float2 v = ((const float2 *)d.H)[i];
+        h = (double)v.x + (double)v.y;
+    }
+    out[i] = (OUT)h;
+}
+
+// H of a free node := Hn (FP32: hi/lo split of the FP64 value), with T and fs
+template <class R>
+__device__ __forceinline__ void set_node(const Dev &d, int64_t i, const MatDev &M, double Hn, R *Tc) {
+    double T, fs;
+    t_of_h(M, Hn, T, fs);
+    if constexpr (sizeof(R) == 8) {
+        ((double *)d.H)[i] = Hn;
+    } else {
+        const float hi = (float)Hn;
+        ((float2 *)d.H)[i] = make_float2(hi, (float)(Hn - (double)hi));
+    }
+    Tc[i] = (R)T;
+    ((R *)d.fs)[i] = (R)fs;
+}
+
+template <class R>
+__global__ __launch_bounds__(256) void k_write_jump(SurDev s, Dev d, int parity, float fs_tol) {
+    __shared__ int cnt[4];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int bad = 0;
+    if (i < d.N) {
+        const uint32_t f = d.flags[i];
+        if (!(f & NODE_FIXED)) {
+            const MatDev &M = d.mats[f & NODE_MAT_MASK];
+            const double Hn = s.base[i] + (double)s.scale[i] * (double)s.y[i];
+            set_node<R>(d, i, M, Hn, (R *)d.T + parity * d.N);
+            if (M.latent) {
+                double T0, fs0, T1, fs1;
+                t_of_h(M, s.H1[i], T0, fs0);
+                t_of_h(M, Hn, T1, fs1);
+                bad = (fs1 < fs0 - (double)fs_tol || !(Hn == Hn)) ? 1 : 0;
+            } else {
+                bad = !(Hn == Hn) ? 1 : 0;
+            }
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) bad += __shfl_down(bad, off, 64);
+    if ((threadIdx.x & 63) == 0) cnt[threadIdx.x >> 6] = bad;
+    __syncthreads();
+    if (threadIdx.x == 0) s.check[blockIdx.x] = cnt[0] + cnt[1] + cnt[2] + cnt[3];
+}
+
+template <class R>
+__global__ __launch_bounds__(256) void k_restore(SurDev s, Dev d, int parity) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= d.N) return;
+    const uint32_t f = d.flags[i];
+    if (f & NODE_FIXED) return;
+    set_node<R>(d, i, d.mats[f & NODE_MAT_MASK], s.H1[i], (R *)d.T + parity * d.N);
+}
+
+inline unsigned grid_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+hipError_t features(const SurDev &s, const void *H0, const void *H1, int h_is_double, const float *Ht,
+                    int64_t stride, const int32_t *idx, int64_t slots, hipStream_t st) {
+    const unsigned g = grid_for(slots * s.N, 256);
+    if (h_is_double)
+        hipLaunchKernelGGL(k_features<double>, dim3(g), dim3(256), 0, st, s, (const double *)H0, (const double *)H1,
+                           Ht, stride, idx, slots);
+    else
+        hipLaunchKernelGGL(k_features<float>, dim3(g), dim3(256), 0, st, s, (const float *)H0, (const float *)H1,
+                           Ht, stride, idx, slots);
+    return hipGetLastError();
+}
+
+hipError_t forward(const SurDev &s, int64_t R, hipStream_t st) {
+    const unsigned g = grid_for(R, 64);
+    // encoder into the first half of U_0
+    hipLaunchKernelGGL((k_gemm<WIDTH, 0>), dim3(g), dim3(256), 0, st, s.X, KIN, KIN, s.wt_in,
+                       s.params + s.pl.b_in, R, s.Zin, (const bf16 *)nullptr, 0, s.U[0], 2 * WIDTH, (float *)nullptr, 0);
+    for (int l = 0; l < s.layers; ++l) {
+        hipLaunchKernelGGL(k_agg, dim3(grid_for(R * 8, 256)), dim3(256), 0, st, s, s.U[l], R);
+        bf16 *hout = l + 1 < s.layers ? s.U[l + 1] : s.HL;
+        const int ldh = l + 1 < s.layers ? 2 * WIDTH : WIDTH;
+        hipLaunchKernelGGL((k_gemm<WIDTH, 1>), dim3(g), dim3(256), 0, st, s.U[l], 2 * WIDTH, 2 * WIDTH, s.wt[l],
+                           s.params + s.pl.b[l], R, s.Z[l], s.U[l], 2 * WIDTH, hout, ldh, (float *)nullptr, 0);
+    }
+    hipLaunchKernelGGL(k_out, dim3(grid_for(R, 256)), dim3(256), 0, st, s, R);
+    return hipGetLastError();
+}
+
+hipError_t loss_and_dy(const SurDev &s, int64_t R, hipStream_t st) {
+    hipLaunchKernelGGL(k_loss, dim3(grid_for(R, 256)), dim3(256), 0, st, s, R);
+    return hipGetLastError();
+}
+
+hipError_t backward(const SurDev &s, int64_t R, hipStream_t st) {
+    const int64_t nb = (R + GRAD_ROWS - 1) / GRAD_ROWS;
+    float *P = s.partials;
+    // output layer
+    hipLaunchKernelGGL(k_out_grad, dim3((unsigned)nb), dim3(256), 0, st, s, R, P);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(WIDTH + 1), 0, st, P, nb, (int64_t)(WIDTH + 1), WIDTH + 1,
+                       s.grads + s.pl.w_out);
+    for (int l = s.layers - 1; l >= 0; --l) {
+        hipLaunchKernelGGL(k_relu_back, dim3(grid_for(R * WIDTH, 256)), dim3(256), 0, st, s.dH, s.Z[l], s.dZ,
+                           R * WIDTH);
+        hipLaunchKernelGGL((k_wgrad<2 * WIDTH>), dim3((unsigned)nb), dim3(256), 0, st, s.U[l], 2 * WIDTH, s.dZ, R, P);
+        hipLaunchKernelGGL(k_reduce, dim3(grid_for(2 * WIDTH * WIDTH, 256)), dim3(256), 0, st, P, nb,
+                           (int64_t)(2 * WIDTH * WIDTH), 2 * WIDTH * WIDTH, s.grads + s.pl.w[l]);
+        hipLaunchKernelGGL(k_colsum, dim3((unsigned)nb), dim3(256), 0, st, s.dZ, R, P);
+        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(WIDTH), 0, st, P, nb, (int64_t)WIDTH, WIDTH, s.grads + s.pl.b[l]);
+        hipLaunchKernelGGL((k_gemm<2 * WIDTH, 2>), dim3(grid_for(R, 64)), dim3(256), 0, st, s.dZ, WIDTH, WIDTH,
+                           s.wr[l], (const float *)nullptr, R, (bf16 *)nullptr, (const bf16 *)nullptr, 0,
+                           (bf16 *)nullptr, 0, s.dU, 2 * WIDTH);
+        hipLaunchKernelGGL(k_aggT, dim3(grid_for(R * WIDTH, 256)), dim3(256), 0, st, s, s.dU, s.dH, R);
+    }
+    // encoder
+    hipLaunchKernelGGL(k_relu_back, dim3(grid_for(R * WIDTH, 256)), dim3(256), 0, st, s.dH, s.Zin, s.dZ, R * WIDTH);
+    hipLaunchKernelGGL((k_wgrad<KIN>), dim3((unsigned)nb), dim3(256), 0, st, s.X, KIN, s.dZ, R, P);
+    hipLaunchKernelGGL(k_reduce, dim3(grid_for(NFEAT * WIDTH, 256)), dim3(256), 0, st, P, nb, (int64_t)(KIN * WIDTH),
+                       NFEAT * WIDTH, s.grads + s.pl.w_in);
+    hipLaunchKernelGGL(k_colsum, dim3((unsigned)nb), dim3(256), 0, st, s.dZ, R, P);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(WIDTH), 0, st, P, nb, (int64_t)WIDTH, WIDTH, s.grads + s.pl.b_in);
+    return hipGetLastError();
+}
+
+hipError_t adam(const SurDev &s, float lr, float b1, float b2, float eps, int step, hipStream_t st) {
+    const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+    hipLaunchKernelGGL(k_adam, dim3(grid_for(s.pl.total, 256)), dim3(256), 0, st, s.params, s.grads, s.adam_m,
+                       s.adam_v, s.pl.total, lr, b1, b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t refresh_bf16(const SurDev &s, hipStream_t st) {
+    hipLaunchKernelGGL(k_refresh, dim3(grid_for(2 * WIDTH * WIDTH, 256)), dim3(256), 0, st, s);
+    return hipGetLastError();
+}
+
+hipError_t apply(const SurDev &s, int64_t R, double *H_out, hipStream_t st) {
+    hipLaunchKernelGGL(k_apply, dim3(grid_for(R, 256)), dim3(256), 0, st, s, R, H_out);
+    return hipGetLastError();
+}
+
+hipError_t state_to_f64(const Dev &d, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_state_out<double>, dim3(grid_for(d.N, 256)), dim3(256), 0, st, d, out);
+    return hipGetLastError();
+}
+
+hipError_t state_to_f32(const Dev &d, float *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_state_out<float>, dim3(grid_for(d.N, 256)), dim3(256), 0, st, d, out);
+    return hipGetLastError();
+}
+
+hipError_t write_jump(const SurDev &s, const Dev &d, int parity, float fs_tol, hipStream_t st) {
+    const dim3 g((unsigned)check_blocks(d.N));
+    if (d.prec == FEM_PREC_FP64)
+        hipLaunchKernelGGL(k_write_jump<double>, g, dim3(256), 0, st, s, d, parity, fs_tol);
+    else
+        hipLaunchKernelGGL(k_write_jump<float>, g, dim3(256), 0, st, s, d, parity, fs_tol);
+    return hipGetLastError();
+}
+
+hipError_t restore_h1(const SurDev &s, const Dev &d, int parity, hipStream_t st) {
+    const dim3 g((unsigned)check_blocks(d.N));
+    if (d.prec == FEM_PREC_FP64)
+        hipLaunchKernelGGL(k_restore<double>, g, dim3(256), 0, st, s, d, parity);
+    else
+        hipLaunchKernelGGL(k_restore<float>, g, dim3(256), 0, st, s, d, parity);
+    return hipGetLastError();
+}
+
+}  // namespace sur
+}  // namespace castfem

@@ -1,0 +1,115 @@
+// Device layout and launchers of the message-passing surrogate (gfx950).
+//
+// Network (width WIDTH, LAYERS message-passing layers), per node row r:
+//   h_0 = relu(X W_in + b_in)                      X: 8 features padded to 16
+//   h_l = h_{l-1} + relu([h_{l-1}, A h_{l-1}] W_l + b_l)     A: mean over mesh neighbours
+//   y   = h_L . w_out + b_out
+// Activations are BF16, products run on MFMA (v_mfma_f32_16x16x16_bf16) with
+// FP32 accumulation; parameters, gradients and Adam moments are FP32.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "kernels.hpp"
+
+namespace castfem {
+namespace sur {
+
+constexpr int WIDTH = 64;
+constexpr int NFEAT = 8;        // input features
+constexpr int KIN = 16;         // features padded to the MFMA K step
+constexpr int MAX_LAYERS = 4;
+constexpr float T_REF = 25.0f, T_SCALE = 700.0f, DH_SCALE = 10.0f, DT_SCALE = 10.0f;
+enum { LOSS_H = 0, LOSS_T = 1 };
+
+typedef uint16_t bf16;
+
+// parameter offsets in the FP32 parameter vector
+struct ParamLayout {
+    int layers = 3;
+    int64_t w_in = 0, b_in = 0, w[MAX_LAYERS] = {}, b[MAX_LAYERS] = {}, w_out = 0, b_out = 0, total = 0;
+    void build(int L) {
+        layers = L;
+        int64_t o = 0;
+        w_in = o;  o += NFEAT * WIDTH;          // row-major [NFEAT x WIDTH]
+        b_in = o;  o += WIDTH;
+        for (int l = 0; l < L; ++l) {
+            w[l] = o;  o += 2 * WIDTH * WIDTH;  // row-major [2 WIDTH x WIDTH]
+            b[l] = o;  o += WIDTH;
+        }
+        w_out = o; o += WIDTH;
+        b_out = o; o += 1;
+        total = o;
+    }
+};
+
+struct SurDev {
+    int64_t N = 0;            // nodes of the mesh (device numbering of the context)
+    int layers = 3;
+    int horizon = 16;         // explicit steps per jump
+    int loss_mode = LOSS_H;   // LOSS_H: target (Ht - base) / (c DH_SCALE); LOSS_T: target T(Ht)
+    ParamLayout pl;
+    // graph: mean over mesh neighbours
+    const int32_t *nbr_ptr = nullptr, *nbr = nullptr;
+    const float *inv_deg = nullptr;
+    // per-node strengths per unit time (times dt: per step), N x 4:
+    // b_i / (m_i c_i), 2 sum_j w_ij / (m_i c_i), sum_j |K_ij| / (m_i c_i), 0
+    const float *coef = nullptr;
+    const uint32_t *flags = nullptr;      // N: material | flags (shared with the context)
+    const void *mats = nullptr;           // MatDev table of the context
+    // parameters
+    float *params = nullptr, *grads = nullptr, *adam_m = nullptr, *adam_v = nullptr;
+    bf16 *wt_in = nullptr;                // [WIDTH x KIN]   W_in transposed, zero-padded
+    bf16 *wt[MAX_LAYERS] = {};            // [WIDTH x 2 WIDTH] W_l transposed
+    bf16 *wr[MAX_LAYERS] = {};            // [2 WIDTH x WIDTH] W_l as is (for dU = dZ W_l^T)
+    // activations for R rows
+    int64_t rows = 0;                     // capacity in rows
+    bf16 *X = nullptr;                    // R x KIN
+    bf16 *Zin = nullptr;                  // R x WIDTH pre-activation of the encoder
+    bf16 *U[MAX_LAYERS] = {};             // R x 2 WIDTH: [h_{l-1}, A h_{l-1}]
+    bf16 *Z[MAX_LAYERS] = {};             // R x WIDTH pre-activations
+    bf16 *HL = nullptr;                   // R x WIDTH last hidden state
+    float *y = nullptr;                   // R outputs
+    double *base = nullptr;               // R: extrapolated enthalpy
+    float *scale = nullptr;               // R: c_i * DH_SCALE
+    float *target = nullptr;              // R: training target (see loss_mode)
+    // backward
+    float *dH = nullptr;                  // R x WIDTH
+    bf16 *dZ = nullptr;                   // R x WIDTH
+    float *dU = nullptr;                  // R x 2 WIDTH
+    float *partials = nullptr;            // reduction partials
+    int64_t n_partial_blocks = 0;
+    double *loss_part = nullptr;          // per workgroup loss partials
+    // jumps of the solver state
+    double *H0 = nullptr, *H1 = nullptr;  // N: the two explicit states a jump starts from
+    int32_t *check = nullptr;             // per workgroup: nodes whose fraction solid fell
+};
+
+// rows handled by one workgroup of the weight-gradient product
+constexpr int GRAD_ROWS = 2048;
+
+// features, extrapolated base, scale and (Ht != null) targets of `slots`
+// states: slot q is sample idx[q] (q if idx is null) at offset sample * stride
+hipError_t features(const SurDev &s, const void *H0, const void *H1, int h_is_double, const float *Ht,
+                    int64_t stride, const int32_t *idx, int64_t slots, hipStream_t st);
+hipError_t forward(const SurDev &s, int64_t rows, hipStream_t st);
+hipError_t loss_and_dy(const SurDev &s, int64_t rows, hipStream_t st);      // writes loss partials, dH of the output
+hipError_t backward(const SurDev &s, int64_t rows, hipStream_t st);
+hipError_t adam(const SurDev &s, float lr, float b1, float b2, float eps, int step, hipStream_t st);
+hipError_t refresh_bf16(const SurDev &s, hipStream_t st);
+hipError_t apply(const SurDev &s, int64_t rows, double *H_out, hipStream_t st);   // H = base + scale * y
+
+// solver state <-> surrogate (d: the context's device layout, T buffer `parity`)
+hipError_t state_to_f64(const Dev &d, double *out, hipStream_t st);
+hipError_t state_to_f32(const Dev &d, float *out, hipStream_t st);
+// write H = base + scale * y (one state slot) into the solver state with its T
+// and fraction solid; counts per workgroup the nodes whose fraction solid
+// fell by more than fs_tol below that of s.H1
+hipError_t write_jump(const SurDev &s, const Dev &d, int parity, float fs_tol, hipStream_t st);
+// put the state back to s.H1
+hipError_t restore_h1(const SurDev &s, const Dev &d, int parity, hipStream_t st);
+inline int64_t check_blocks(int64_t N) { return (N + 255) / 256; }
+
+}  // namespace sur
+}  // namespace castfem

@@ -51,3 +51,114 @@ def test_gradients_match_central_differences(layers):
             val[ix] = old
             fd = (lp - lm) / (2 * eps)
             assert g[name][ix] == pytest.approx(fd, rel=1e-5, abs=1e-9), (name, ix)
+
+
+def test_parameter_vector_layout():
+    p = S.init_params(64, 3, 0)
+    v = S.flatten_params(p, 3)
+    assert v.size == 8 * 64 + 64 + 3 * (128 * 64 + 64) + 64 + 1
+    q = S.unflatten_params(v, 64, 3)
+    for k in p:
+        assert np.array_equal(p[k], q[k])
+
+
+def test_conduction_strength_of_an_interior_hex_node():
+    # trilinear cube of side h: K_ii = kh/3, face diagonals and body diagonal -kh/12,
+    # edge neighbours 0; an interior node of a uniform grid gathers 8 elements, so
+    # sum_j |K_ij| = kh (8/3 + 12/6 + 8/12) = 16 kh / 3 and m_i = rho h^3
+    n, L = 4, 0.1
+    p = configs.hex_cube(n=n, length=L, noise_amp=0.0, dirichlet_x0=None)
+    st = S.node_strengths(p)
+    k, rho, c = configs.ALLOY[:3]
+    h = L / n
+    xyz = p["xyz"]
+    interior = np.all((xyz > 1e-9) & (xyz < L - 1e-9), axis=1)
+    dt = 0.1
+    H = np.full(xyz.shape[0], 900.0 * 700.0)
+    X = S.features(p, H, H, dt, strengths=st)
+    assert np.allclose(X[interior, 5], 16.0 / 3.0 * k * dt / (rho * c * h * h), rtol=1e-12)
+    assert np.allclose(st["kabs"][interior], 16.0 / 3.0 * k * h, rtol=1e-12)
+    # a corner node sits in one element: sum_j |K_ij| = kh (1/3 + 4/12)
+    corner = np.all(np.isclose(xyz, 0.0), axis=1)
+    assert st["kabs"][corner][0] == pytest.approx(2.0 / 3.0 * k * h, rel=1e-12)
+    assert np.all(X[:, 3] == 0) and np.all(X[:, 4] == 0)
+
+
+def test_robin_strength_on_the_chill_face():
+    # interior node of the x = 0 face: four quads of area h^2 each give h^2 h_c / 4,
+    # and the lumped weight of a face node is rho h^3 / 2
+    n, L, hc = 4, 0.1, 1234.0
+    p = configs.hex_cube(n=n, length=L, noise_amp=0.0, dirichlet_x0=None, robin_x0=(hc, 25.0))
+    st = S.node_strengths(p)
+    rho, c = configs.ALLOY[1:3]
+    h = L / n
+    xyz = p["xyz"]
+    face = np.isclose(xyz[:, 0], 0.0) & np.all((xyz[:, 1:] > 1e-9) & (xyz[:, 1:] < L - 1e-9), axis=1)
+    dt = 0.2
+    H = np.full(xyz.shape[0], 900.0 * 700.0)
+    X = S.features(p, H, H, dt, strengths=st)
+    assert np.allclose(X[face, 3], 2.0 * hc * dt / (rho * c * h), rtol=1e-12)
+    assert np.all(X[~np.isclose(xyz[:, 0], 0.0), 3] == 0)
+
+
+def test_interface_strength_sums_to_h_times_area():
+    # unjittered cube region [0.2, 0.8]^3 of the 0.1 m domain: area 6 (0.06)^2 per side
+    hi = 800.0
+    p = configs.tet_casting(n=5, jitter=0, region="cube", h_interface=hi, permute=False)
+    st = S.node_strengths(p)
+    nm = st["node_mat"]
+    area = 6 * 0.06 ** 2
+    assert st["iface_w"][nm == 0].sum() == pytest.approx(hi * area, rel=1e-12)
+    assert st["iface_w"][nm == 1].sum() == pytest.approx(hi * area, rel=1e-12)
+
+
+def test_temperature_and_rate_features():
+    p = configs.hex_cube(n=2, noise_amp=0.0, dirichlet_x0=None)
+    mat = configs.ALLOY
+    c, Ts, Tl, L = mat[2], mat[3], mat[4], mat[5]
+    N = p["xyz"].shape[0]
+    H1 = np.full(N, c * Ts + 0.25 * L + 0.25 * c * (Tl - Ts))   # a quarter of the way through the mushy zone
+    H0 = H1 + 160.0
+    X = S.features(p, H0, H1, 0.1, horizon=16)
+    assert np.allclose(X[:, 0], (Ts + 0.25 * (Tl - Ts) - S.T_REF) / S.T_SCALE, rtol=1e-12)
+    assert np.allclose(X[:, 1], 0.75, rtol=1e-12)
+    assert np.all(X[:, 2] == 1) and np.all(X[:, 7] == 1)
+    assert np.allclose(X[:, 6], 16 * (-160.0) / (c * S.T_SCALE), rtol=1e-12)
+    base, t, cc = S.base_and_target(p, H0, H1, H1, horizon=16)
+    assert np.allclose(base, H1 - 15 * 160.0) and np.allclose(t * cc * S.DH_SCALE, 15 * 160.0)
+
+
+def test_temperature_loss_gradient_matches_central_differences(orc):
+    # states away from the kinks of T(H): the loss is smooth there
+    p = configs.hex_cube(n=3, noise_amp=0.0, dirichlet_x0=None)
+    N = p["xyz"].shape[0]
+    ptr, col = S.graph_mean_operator(p["conn"], N)
+    rng = np.random.default_rng(5)
+    c, Ts, Tl, L = configs.ALLOY[2:]
+    Hs, Hl = c * Ts, c * Tl + L
+    kind = rng.integers(0, 3, N)                        # solid, mushy, liquid nodes
+    base = np.where(kind == 0, c * rng.uniform(300, 590, N),
+                    np.where(kind == 1, rng.uniform(Hs + 2e4, Hl - 2e4, N), rng.uniform(Hl + 2e4, Hl + 5e4, N)))
+    H_true = base + rng.normal(0, 2000, N)
+    X = rng.normal(0, 1, (N, S.N_FEAT))
+    layers = 2
+    params = S.init_params(8, layers, 1)
+    params["w_out"] = rng.normal(0, 0.05, 8)
+    f = S.t_loss(p, base, H_true)
+    loss, g, y = S.loss_and_grad(params, X, f, ptr, col, layers)
+    assert np.max(np.abs(y)) * c * S.DH_SCALE < 1.5e4   # predictions stay on their branch
+    eps = 1e-6
+    for name in ("W_in", "W1", "w_out", "b_out"):
+        val = params[name]
+        for ix in [tuple(rng.integers(0, s) for s in val.shape) for _ in range(3)]:
+            old = val[ix]
+            val[ix] = old + eps
+            lp = S.loss_and_grad(params, X, f, ptr, col, layers)[0]
+            val[ix] = old - eps
+            lm = S.loss_and_grad(params, X, f, ptr, col, layers)[0]
+            val[ix] = old
+            assert g[name][ix] == pytest.approx((lp - lm) / (2 * eps), rel=1e-5, abs=1e-10), (name, ix)
+    # the loss is the mean squared temperature error in units of DT_SCALE
+    T_pred, _ = orc.state_T(p, base + c * S.DH_SCALE * y)
+    T_true, _ = orc.state_T(p, H_true)
+    assert loss == pytest.approx(np.mean(((T_pred - T_true) / S.DT_SCALE) ** 2), rel=1e-12)
