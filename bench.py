@@ -95,8 +95,13 @@ def main():
     ap.add_argument("--scatter", default="lds", choices=["lds", "atomic", "colored"])
     ap.add_argument("--ordering", default="hilbert", choices=["none", "rcm", "morton", "hilbert"])
     ap.add_argument("--block-nodes", type=int, default=0, help="LDS block node cap (0 = autotune)")
-    ap.add_argument("--workload", default="tet128", choices=["tet128", "batch"],
-                    help="tet128: the 128^3 cast/mould mesh; batch: 256 scenarios of 20k-400k tets")
+    ap.add_argument("--workload", default="tet128", choices=["tet128", "batch", "surrogate"],
+                    help="tet128: the 128^3 cast/mould mesh; batch: 256 scenarios of 20k-400k tets; "
+                         "surrogate: train on chill-cube trajectories, then time-to-solidify plain vs surrogate")
+    ap.add_argument("--train-traj", type=int, default=500, help="surrogate: training trajectories (seeds 5000+)")
+    ap.add_argument("--held-out", type=int, default=50, help="surrogate: held-out trajectories (seeds 5500+)")
+    ap.add_argument("--epochs", type=int, default=30, help="surrogate: training epochs")
+    ap.add_argument("--loss", default="T", choices=["H", "T"], help="surrogate: training loss")
     ap.add_argument("--quiet", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -114,6 +119,8 @@ def main():
 
     if args.workload == "batch":
         return bench_batch(args, log)
+    if args.workload == "surrogate":
+        return bench_surrogate(args, log)
     t0 = time.time()
     prob = configs.config2(n=args.n)
     t_gen = time.time() - t0
@@ -281,6 +288,108 @@ def bench_batch(args, log):
         "worst_scenario_energy_residual": worst,
     }
     s.close()
+    print(json.dumps(out), flush=True)
+
+
+def generate_states(solver, dt, max_snap):
+    """Device states H^{16k}, H^{16k+1}, H^{16k+2} of every scenario, k = 0.., until all are solid."""
+    import torch
+    S = torch.empty((max_snap + 1, 3, solver.n_nodes), dtype=torch.float32, device=solver.device)
+    k = 0
+    while k < max_snap:
+        for j in range(3):
+            solver.snapshot_H(S[k, j])
+            solver.step_batch(dt, 1 if j < 2 else 14)
+        k += 1
+        if k % 16 == 0 and all(r["n_liquid"] == 0 for r in solver.energy_scenarios()):
+            break
+    solver.snapshot_H(S[k, 0])
+    return S, k
+
+
+def bench_surrogate(args, log):
+    """Config-4 surrogate: train on chill-cube trajectories of the GPU solver (seeds
+    5000..), then run every held-out trajectory (seeds 5500..) to full solidification
+    plainly and with the surrogate; the plain run judges the error."""
+    import torch
+    from castgen import configs
+    from paper_1005_3158_amd import castfem as cf
+
+    t0 = time.perf_counter()
+    b = configs.chill_batch(list(range(5000, 5000 + args.train_traj)))
+    gen = cf.Solver(b, precision=cf.FEM_PREC_FP32_KAHAN)
+    dt = 0.9 * gen.stable_dt_scenarios()
+    S, n = generate_states(gen, dt, 320)
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    log("training data: %d trajectories x %d states (%d nodes each), %.1f s" % (args.train_traj, n, gen.n_nodes, t_gen))
+    loss = cf.FEM_SUR_LOSS_T if args.loss == "T" else cf.FEM_SUR_LOSS_H
+    sur = cf.Surrogate(gen, layers=3, max_samples=1, train=True, seed=11, loss=loss)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = sur.train(S[0, 0], S[0, 1], S[0, 2], S[1, 0], 3 * gen.n_nodes, n, batch=1, epochs=args.epochs,
+                       lr=2e-3, lr_final=2e-5, seed=3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    params = sur.params()
+    rows = args.epochs * n * gen.n_nodes
+    log("training: %d epochs in %.1f s (%.3g rows/s), loss %.4g -> %.4g" % (args.epochs, t_train, rows / t_train, losses[0], losses[-1]))
+    sur.close()
+    gen.close()
+    del S
+
+    res = []
+    for seed in range(5500, 5500 + args.held_out):
+        p = configs.config4_trajectory(seed)
+        plain = cf.Solver(p, precision=cf.FEM_PREC_FP32_KAHAN)
+        dt1 = 0.9 * plain.stable_dt()
+        plain.advance(dt1, 32, None, until_solid=False)           # warm-up: graph capture
+        plain.close()
+        plain = cf.Solver(p, precision=cf.FEM_PREC_FP32_KAHAN)
+        rp = plain.advance(dt1, 10 ** 6, None, until_solid=True)
+        acc = cf.Solver(p, precision=cf.FEM_PREC_FP32_KAHAN)
+        sa = cf.Surrogate(acc, layers=3)
+        sa.set_params(params)
+        ra = acc.advance(dt1, 10 ** 6, sa, until_solid=True)
+        if ra["steps"] <= rp["steps"]:
+            ref = cf.Solver(p, precision=cf.FEM_PREC_FP32_KAHAN)
+            ref.step(dt1, ra["steps"])
+            T_ref = ref.T()
+            ref.close()
+        else:
+            plain.step(dt1, ra["steps"] - rp["steps"])
+            T_ref = plain.T()
+        err = float(np.max(np.abs(acc.T() - T_ref)))
+        res.append(dict(seed=seed, plain_s=rp["wall_seconds"], sur_s=ra["wall_seconds"], plain_steps=rp["steps"],
+                        sur_steps=ra["steps"], computed=ra["plain_steps"], kept=ra["jumps_accepted"],
+                        rejected=ra["jumps_rejected"], err_K=err, residual=acc.energy()["residual"]))
+        log("seed %d: plain %d steps %.4f s; surrogate %d steps (%d computed, %d/%d jumps kept) %.4f s; max|dT| %.3f K"
+            % (seed, rp["steps"], rp["wall_seconds"], ra["steps"], ra["plain_steps"], ra["jumps_accepted"],
+               ra["jumps_accepted"] + ra["jumps_rejected"], ra["wall_seconds"], err))
+        sa.close()
+        acc.close()
+        plain.close()
+    t_plain = sum(r["plain_s"] for r in res)
+    t_sur = sum(r["sur_s"] for r in res)
+    errs = np.array([r["err_K"] for r in res])
+    out = {
+        "metric": "time-to-solidify, surrogate-accelerated vs plain explicit (max |T_sur - T_plain| at the end)",
+        "value": t_plain / t_sur, "unit": "x (plain wall-clock / surrogate wall-clock)", "n_gpus": 1,
+        "steps": int(sum(r["sur_steps"] for r in res)), "warmup": 32, "ms_per_step": None, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16 net (f32 accumulate), f32+compensated explicit state, f64 gates",
+        "data": "synthetic",
+        "config": {"workload": "16^3 hex alloy cube with a convective chill on x=0 (config 4): train on %d trajectories, "
+                               "%d held-out trajectories run to full solidification" % (args.train_traj, args.held_out),
+                   "layers": 3, "width": 64, "horizon": 16, "epochs": args.epochs, "loss": args.loss,
+                   "energy_tol": 1e-4, "fs_tol": 1e-6},
+        "plain_seconds": t_plain, "surrogate_seconds": t_sur,
+        "max_err_K": float(errs.max()), "median_err_K": float(np.median(errs)),
+        "within_0p5K": int(np.sum(errs <= 0.5)), "n_held_out": len(res),
+        "jumps_kept": int(sum(r["kept"] for r in res)), "jumps_rejected": int(sum(r["rejected"] for r in res)),
+        "explicit_steps_computed_frac": float(sum(r["computed"] for r in res) / sum(r["sur_steps"] for r in res)),
+        "train": {"trajectories": args.train_traj, "states": n, "generate_s": t_gen, "train_s": t_train,
+                  "rows_per_s": rows / t_train, "loss_first": float(losses[0]), "loss_last": float(losses[-1])},
+    }
     print(json.dumps(out), flush=True)
 
 

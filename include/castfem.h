@@ -232,19 +232,20 @@ int fem_copy_kernel(fem_ctx *ctx, void *dst, const void *src, int64_t bytes, int
 /* ------------------------------------------------------------ surrogate */
 /* A learned message-passing surrogate that jumps the enthalpy state `horizon`
  * explicit steps ahead (not part of the paper; the explicit step of Eq. 14 is
- * its fallback and judge).  From two consecutive explicit states H0 = H^n,
- * H1 = H^{n+1} it predicts, per node i,
- *   H^{n+horizon}_i = H1_i + (horizon - 1)(H1_i - H0_i) + 10 c_i y_i,
+ * its fallback and judge).  From three consecutive explicit states H0 = H^n,
+ * H1 = H^{n+1}, H2 = H^{n+2} it predicts, per node i, with m = horizon - 2,
+ * r = H2 - H1 and a = (H2 - H1) - (H1 - H0),
+ *   H^{n+horizon}_i = H2_i + m r_i + m (m + 1) / 2 a_i + 10 c_i y_i,
  * y = output of a network of `layers` residual message-passing layers of
  * width 64 over the mesh graph (nodes sharing an element, mean aggregation):
  *   h_0 = relu(x W_in + b_in);  h_l = h_{l-1} + relu([h_{l-1}, mean_nbr h_{l-1}] W_l + b_l);
  *   y = h_L . w_out + b_out.
- * Node features x (8): (T(H1) - 25)/700, fs(H1), latent-heat flag, Robin,
+ * Node features x (9): (T(H2) - 25)/700, fs(H2), latent-heat flag, Robin,
  * interface and conduction strengths b_i dt/(m_i c_i), 2 sum w_ij dt/(m_i c_i),
- * sum_j |K_ij| dt/(m_i c_i), horizon (H1 - H0)/(700 c_i), 1.
+ * sum_j |K_ij| dt/(m_i c_i), horizon r/(700 c_i), horizon^2 a/(1400 c_i), 1.
  * Activations and weights are BF16 on the matrix cores with FP32
  * accumulation; parameters, gradients and Adam moments are FP32.
- * Parameters are one FP32 vector: W_in [8 x 64] row-major, b_in [64], then per
+ * Parameters are one FP32 vector: W_in [9 x 64] row-major, b_in [64], then per
  * layer W_l [128 x 64] row-major and b_l [64], then w_out [64], b_out [1].
  * State arrays passed in are float32 device arrays in the context's device
  * numbering (fem_get_node_perm); state q of a call starts at q * stride.
@@ -261,7 +262,7 @@ enum { FEM_SUR_LOSS_H = 0, FEM_SUR_LOSS_T = 1 };
 typedef struct {
     int32_t width;         /* must be 64 */
     int32_t layers;        /* 1..4 */
-    int32_t horizon;       /* explicit steps per jump, >= 2 */
+    int32_t horizon;       /* explicit steps per chunk (two computed, the rest jumped), >= 3 */
     int32_t max_samples;   /* states per forward / backward pass (rows = max_samples * n_nodes < 2^31) */
     int32_t train;         /* nonzero: size the training buffers too */
     int32_t loss;          /* FEM_SUR_LOSS_*: what the training loss measures */
@@ -278,7 +279,9 @@ typedef struct {
     int32_t pad;
     double wall_seconds;   /* host wall-clock of the call */
     double max_residual;   /* largest energy residual of an accepted jump */
-    int64_t reserved[4];
+    int64_t rejected_fs;   /* jumps rejected by the fraction-solid (or NaN) check */
+    int64_t rejected_energy; /* jumps rejected by the energy residual */
+    int64_t reserved[2];
 } fem_advance_report;
 
 /* Surrogate on a bound context (graph and node strengths from its layout). */
@@ -293,33 +296,36 @@ int fem_sur_n_params(const fem_sur *s, int64_t *n);
  * resets the Adam moments.  Synchronous. */
 int fem_sur_get_params(fem_sur *s, float *host, int64_t n);
 int fem_sur_set_params(fem_sur *s, const float *host, int64_t n);
-/* Features (as rounded to BF16) of `slots` states: X_host[slots * n_nodes * 8]. */
-int fem_sur_features(fem_sur *s, const float *H0, const float *H1, int64_t stride, int64_t slots, float *X_host);
+/* Features (as rounded to BF16) of `slots` states: X_host[slots * n_nodes * 9]. */
+int fem_sur_features(fem_sur *s, const float *H0, const float *H1, const float *H2, int64_t stride, int64_t slots,
+                     float *X_host);
 /* Training loss (fem_sur_options.loss) over all nodes of `slots` states and its
  * gradient with respect to the parameters (grad_host: n_params floats). */
-int fem_sur_loss_grad(fem_sur *s, const float *H0, const float *H1, const float *Ht, int64_t stride, int64_t slots,
-                      double *loss, float *grad_host);
-/* Adam training: `epochs` passes over n_samples (H0, H1, Ht) triples in a
+int fem_sur_loss_grad(fem_sur *s, const float *H0, const float *H1, const float *H2, const float *Ht, int64_t stride,
+                      int64_t slots, double *loss, float *grad_host);
+/* Adam training: `epochs` passes over n_samples (H0, H1, H2, Ht) states in a
  * seeded shuffled order, `batch` states per step, learning rate decaying from
  * lr to lr_final on a cosine.  loss_per_epoch (may be NULL): epochs doubles. */
-int fem_sur_train(fem_sur *s, const float *H0, const float *H1, const float *Ht, int64_t stride, int64_t n_samples,
-                  int32_t batch, int32_t epochs, float lr, float lr_final, uint64_t seed, double *loss_per_epoch);
+int fem_sur_train(fem_sur *s, const float *H0, const float *H1, const float *H2, const float *Ht, int64_t stride,
+                  int64_t n_samples, int32_t batch, int32_t epochs, float lr, float lr_final, uint64_t seed,
+                  double *loss_per_epoch);
 /* Predicted H^{n+horizon} of `slots` states into H_out (device, slots * n_nodes doubles). */
-int fem_sur_predict(fem_sur *s, const float *H0, const float *H1, int64_t stride, int64_t slots, double *H_out);
+int fem_sur_predict(fem_sur *s, const float *H0, const float *H1, const float *H2, int64_t stride, int64_t slots,
+                    double *H_out);
 /* Current enthalpy of every node (device numbering) into a float32 device array. */
 int fem_snapshot_H(fem_ctx *ctx, float *H_dev);
 /* Advance every scenario (dt_per_scenario[n_scen]) in chunks of `horizon`
  * steps (16 without a surrogate) until max_steps or, with until_solid, until
  * every phase-change node has fraction solid 1 (checked after every chunk).
- * s == NULL: plain explicit steps.  Otherwise each chunk takes one explicit
- * step and lets the surrogate jump the remaining horizon - 1 steps.  The jump
+ * s == NULL: plain explicit steps.  Otherwise each chunk takes two explicit
+ * steps and lets the surrogate jump the remaining horizon - 2 steps.  The jump
  * is kept only if, in every scenario, |dE - dQ| / |E_n - E_ref| <= energy_tol,
  * with dE the FP64 energy change over the chunk, dQ the boundary inflow of
- * the explicit step plus its linear extrapolation over the jumped steps, E_n
+ * the explicit steps plus its linear extrapolation over the jumped steps, E_n
  * the energy at the start of the chunk and E_ref that of the whole scenario at
  * 25 C, no
  * enthalpy is NaN or Inf and no phase-change node's fraction solid fell by
- * more than fs_tol; otherwise the state returns to H1 and horizon - 1 plain
+ * more than fs_tol; otherwise the state returns to H2 and horizon - 2 plain
  * steps follow.  The extrapolated inflow of kept jumps enters Q_cum of the
  * energy reports.  Synchronous. */
 int fem_advance(fem_ctx *ctx, fem_sur *s, const double *dt_per_scenario, int64_t max_steps, int32_t until_solid,

@@ -4,21 +4,23 @@ TEST INFRASTRUCTURE ONLY: it judges the gradients of the GPU training kernels
 and is itself checked against central finite differences.
 
 The surrogate jumps the enthalpy state `horizon` explicit steps ahead.  Given
-two consecutive plain states H0 = H^n and H1 = H^{n+1} it predicts
+three consecutive plain states H0 = H^n, H1 = H^{n+1}, H2 = H^{n+2} it predicts,
+with m = horizon - 2, r = H2 - H1 and a = (H2 - H1) - (H1 - H0),
 
-    H^{n+horizon} ~ H1 + (horizon - 1) (H1 - H0) + c_i * DH_SCALE * y_i,
+    H^{n+horizon} ~ H2 + m r + m (m + 1) / 2 a + c_i * DH_SCALE * y_i,
 
-a linear extrapolation in time corrected by the network output y_i of node i.
-Per-node input features (8):
+the quadratic extrapolation in time through the three states, corrected by the
+network output y_i of node i.  Per-node input features (9):
 
-    x0 = (T(H1) - T_REF) / T_SCALE          temperature
-    x1 = fs(H1)                             fraction solid
+    x0 = (T(H2) - T_REF) / T_SCALE          temperature
+    x1 = fs(H2)                             fraction solid
     x2 = 1 if the node's material has latent heat else 0
     x3 = b_i dt / (m_i c_i)                 Robin strength per step
     x4 = 2 sum_j w_ij dt / (m_i c_i)        interface strength per step
     x5 = sum_j |K_ij| dt / (m_i c_i)        conduction strength per step
-    x6 = horizon (H1 - H0) / (c_i T_SCALE)  extrapolated change over the horizon
-    x7 = 1
+    x6 = horizon r / (c_i T_SCALE)          rate over the horizon
+    x7 = horizon^2 a / (2 c_i T_SCALE)      curvature over the horizon
+    x8 = 1
 
 Network (width W, L message-passing layers, ReLU):
 
@@ -39,7 +41,7 @@ T_REF = 25.0
 T_SCALE = 700.0
 DH_SCALE = 10.0   # K of sensible heat per unit of network output
 DT_SCALE = 10.0   # K per unit of the temperature loss
-N_FEAT = 8
+N_FEAT = 9
 
 
 def _tri_area(x):
@@ -95,34 +97,34 @@ def node_strengths(prob):
     return dict(mc=mc, robin_b=b, iface_w=w, kabs=kabs, node_mat=nmat)
 
 
-def features(prob, H0, H1, dt, horizon=16, strengths=None):
-    """The 8 node features of the module docstring for one pair of states (FP64)."""
+def features(prob, H0, H1, H2, dt, horizon=16, strengths=None):
+    """The node features of the module docstring for one triple of states (FP64)."""
     st = node_strengths(prob) if strengths is None else strengths
     mats = np.asarray(prob["materials"], np.float64).reshape(-1, 6)
     nm = st["node_mat"]
-    H0 = np.asarray(H0, np.float64)
-    H1 = np.asarray(H1, np.float64)
-    T1 = np.array([orc.T_of_H(mats[m], h)[0] for m, h in zip(nm, H1)])
-    fs1 = np.array([orc.fs_of_H(mats[m], h)[0] for m, h in zip(nm, H1)])
+    H0, H1, H2 = (np.asarray(a, np.float64) for a in (H0, H1, H2))
+    T2, fs2 = orc.state_T(orc.Problem(prob), H2)
     c = mats[nm, 2]
-    X = np.empty((H1.size, N_FEAT))
-    X[:, 0] = (T1 - T_REF) / T_SCALE
-    X[:, 1] = fs1
+    X = np.empty((H2.size, N_FEAT))
+    X[:, 0] = (T2 - T_REF) / T_SCALE
+    X[:, 1] = fs2
     X[:, 2] = (mats[nm, 5] > 0).astype(np.float64)
     X[:, 3] = st["robin_b"] * dt / st["mc"]
     X[:, 4] = 2.0 * st["iface_w"] * dt / st["mc"]
     X[:, 5] = st["kabs"] * dt / st["mc"]
-    X[:, 6] = horizon * (H1 - H0) / (c * T_SCALE)
-    X[:, 7] = 1.0
+    X[:, 6] = horizon * (H2 - H1) / (c * T_SCALE)
+    X[:, 7] = horizon ** 2 * ((H2 - H1) - (H1 - H0)) / (2.0 * c * T_SCALE)
+    X[:, 8] = 1.0
     return X
 
 
-def base_and_target(prob, H0, H1, Ht, horizon=16):
-    """Extrapolated base H1 + (horizon - 1)(H1 - H0) and the target (Ht - base) / (c DH_SCALE)."""
+def base_and_target(prob, H0, H1, H2, Ht, horizon=16):
+    """Quadratic extrapolation through H0, H1, H2 to step `horizon` and the target (Ht - base) / (c DH_SCALE)."""
     mats = np.asarray(prob["materials"], np.float64).reshape(-1, 6)
     c = mats[orc.node_material(orc.Problem(prob)), 2]
-    H0, H1, Ht = (np.asarray(a, np.float64) for a in (H0, H1, Ht))
-    base = H1 + (horizon - 1) * (H1 - H0)
+    H0, H1, H2, Ht = (np.asarray(a, np.float64) for a in (H0, H1, H2, Ht))
+    m = horizon - 2
+    base = H2 + m * (H2 - H1) + 0.5 * m * (m + 1) * ((H2 - H1) - (H1 - H0))
     return base, (Ht - base) / (c * DH_SCALE), c
 
 
@@ -198,20 +200,49 @@ def init_params(width, layers, seed):
     return p
 
 
-def forward(p, X, ptr, col, layers):
-    cache = {}
-    z = X @ p["W_in"] + p["b_in"]
-    h = np.maximum(z, 0.0)
-    cache["z_in"] = z
+def bf16_round(x):
+    """Round to the nearest BF16 value (8 significant bits, ties to even), returned as float64."""
+    u = np.asarray(x, np.float32).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _identity(x):
+    return x
+
+
+def projection_weights(prob, strengths=None):
+    """w_i = m_i c_i / sum_j m_j c_j over the free nodes (0 at fixed-temperature nodes)."""
+    st = node_strengths(prob) if strengths is None else strengths
+    w = st["mc"].copy()
+    d = np.asarray(prob.get("dirichlet_nodes", np.zeros(0, np.int64)), np.int64)
+    w[d] = 0.0
+    return w / w.sum()
+
+
+def forward(p, X, ptr, col, layers, bf16=False, proj_w=None):
+    """Forward pass.  With bf16=True the operands the GPU keeps in BF16 (features, weight
+    matrices, pre-activations, hidden states, aggregated states) are rounded to BF16 where
+    the GPU rounds them; sums stay exact.  With proj_w the output is made energy-neutral:
+    y - sum_j w_j y_j, so that sum_i w_i y_i = 0 (w sums to 1)."""
+    r = bf16_round if bf16 else _identity
+    W = {k: (r(v) if k.startswith("W") else v) for k, v in p.items()}
+    cache = {"r": r, "W": W}
+    X = r(X)
+    z = X @ W["W_in"] + p["b_in"]
+    h = r(np.maximum(z, 0.0))
+    cache["X"], cache["z_in"] = X, r(z)
     hs = [h]
     for l in range(layers):
-        a = apply_mean(ptr, col, h)
+        a = r(apply_mean(ptr, col, h))
         u = np.concatenate([h, a], axis=1)
-        z = u @ p["W%d" % l] + p["b%d" % l]
-        cache["u%d" % l], cache["z%d" % l] = u, z
-        h = h + np.maximum(z, 0.0)
+        z = u @ W["W%d" % l] + p["b%d" % l]
+        cache["u%d" % l], cache["z%d" % l] = u, r(z)
+        h = r(h + np.maximum(z, 0.0))
         hs.append(h)
     y = h @ p["w_out"] + p["b_out"][0]
+    if proj_w is not None:
+        y = y - np.dot(proj_w, y)
     cache["hs"] = hs
     return y, cache
 
@@ -244,21 +275,26 @@ def t_loss(prob, base, H_true):
     return f
 
 
-def loss_and_grad(p, X, t, ptr, col, layers):
-    """Loss and parameter gradient; t is the H-loss target array or a loss callable y -> (loss, dL/dy)."""
-    y, c = forward(p, X, ptr, col, layers)
+def loss_and_grad(p, X, t, ptr, col, layers, bf16=False, proj_w=None):
+    """Loss and parameter gradient; t is the H-loss target array or a loss callable y -> (loss, dL/dy).
+    bf16=True also rounds the backward operands the GPU keeps in BF16 (the pre-activation
+    gradients dz); proj_w as in forward."""
+    y, c = forward(p, X, ptr, col, layers, bf16, proj_w)
+    r, W = c["r"], c["W"]
     loss, dy = (t if callable(t) else h_loss(t))(y)
+    if proj_w is not None:
+        dy = dy - proj_w * dy.sum()
     g = {"w_out": c["hs"][-1].T @ dy, "b_out": np.array([dy.sum()])}
     dh = np.outer(dy, p["w_out"])
     width = p["b_in"].size
     for l in reversed(range(layers)):
         z = c["z%d" % l]
-        dz = dh * (z > 0)
+        dz = r(dh * (z > 0))
         g["W%d" % l] = c["u%d" % l].T @ dz
         g["b%d" % l] = dz.sum(axis=0)
-        du = dz @ p["W%d" % l].T
+        du = dz @ W["W%d" % l].T
         dh = dh + du[:, :width] + apply_mean_T(ptr, col, du[:, width:])
-    dz = dh * (c["z_in"] > 0)
-    g["W_in"] = X.T @ dz
+    dz = r(dh * (c["z_in"] > 0))
+    g["W_in"] = c["X"].T @ dz
     g["b_in"] = dz.sum(axis=0)
     return loss, g, y

@@ -87,7 +87,8 @@ class fem_sur_options(C.Structure):
 class fem_advance_report(C.Structure):
     _fields_ = [("steps", C.c_int64), ("plain_steps", C.c_int64), ("jumps_accepted", C.c_int64),
                 ("jumps_rejected", C.c_int64), ("solid", C.c_int32), ("pad", C.c_int32),
-                ("wall_seconds", C.c_double), ("max_residual", C.c_double), ("reserved", C.c_int64 * 4)]
+                ("wall_seconds", C.c_double), ("max_residual", C.c_double), ("rejected_fs", C.c_int64),
+                ("rejected_energy", C.c_int64), ("reserved", C.c_int64 * 2)]
 
 
 def _as_dict(s):
@@ -122,10 +123,10 @@ def lib():
             "fem_sur_create": [vp, vp, vp], "fem_sur_destroy": [vp], "fem_sur_query_buffers": [vp, vp, vp],
             "fem_sur_bind_buffers": [vp, vp, i32], "fem_sur_n_params": [vp, vp],
             "fem_sur_get_params": [vp, vp, i64], "fem_sur_set_params": [vp, vp, i64],
-            "fem_sur_features": [vp, vp, vp, i64, i64, vp],
-            "fem_sur_loss_grad": [vp, vp, vp, vp, i64, i64, vp, vp],
-            "fem_sur_train": [vp, vp, vp, vp, i64, i64, i32, i32, C.c_float, C.c_float, C.c_uint64, vp],
-            "fem_sur_predict": [vp, vp, vp, i64, i64, vp], "fem_snapshot_H": [vp, vp],
+            "fem_sur_features": [vp, vp, vp, vp, i64, i64, vp],
+            "fem_sur_loss_grad": [vp, vp, vp, vp, vp, i64, i64, vp, vp],
+            "fem_sur_train": [vp, vp, vp, vp, vp, i64, i64, i32, i32, C.c_float, C.c_float, C.c_uint64, vp],
+            "fem_sur_predict": [vp, vp, vp, vp, i64, i64, vp], "fem_snapshot_H": [vp, vp],
             "fem_advance": [vp, vp, vp, i64, i32, dp, dp, vp],
         }
         for name, args in sig.items():
@@ -364,29 +365,34 @@ def fem_sur_set_params(s, params):
     _call("fem_sur_set_params", s, _p(p), p.size)
 
 
-def fem_sur_features(s, H0_ptr, H1_ptr, stride, slots, n_nodes):
-    out = np.empty((slots * n_nodes, 8), np.float32)
-    _call("fem_sur_features", s, C.c_void_p(H0_ptr), C.c_void_p(H1_ptr), int(stride), int(slots), _p(out))
+N_FEAT = 9
+
+
+def fem_sur_features(s, H0_ptr, H1_ptr, H2_ptr, stride, slots, n_nodes):
+    out = np.empty((slots * n_nodes, N_FEAT), np.float32)
+    _call("fem_sur_features", s, C.c_void_p(H0_ptr), C.c_void_p(H1_ptr), C.c_void_p(H2_ptr), int(stride), int(slots),
+          _p(out))
     return out
 
 
-def fem_sur_loss_grad(s, H0_ptr, H1_ptr, Ht_ptr, stride, slots):
+def fem_sur_loss_grad(s, H0_ptr, H1_ptr, H2_ptr, Ht_ptr, stride, slots):
     g = np.empty(fem_sur_n_params(s), np.float32)
     loss = C.c_double()
-    _call("fem_sur_loss_grad", s, C.c_void_p(H0_ptr), C.c_void_p(H1_ptr), C.c_void_p(Ht_ptr), int(stride),
-          int(slots), C.byref(loss), _p(g))
+    _call("fem_sur_loss_grad", s, C.c_void_p(H0_ptr), C.c_void_p(H1_ptr), C.c_void_p(H2_ptr), C.c_void_p(Ht_ptr),
+          int(stride), int(slots), C.byref(loss), _p(g))
     return loss.value, g
 
 
-def fem_sur_train(s, H0_ptr, H1_ptr, Ht_ptr, stride, n_samples, batch, epochs, lr, lr_final, seed):
+def fem_sur_train(s, H0_ptr, H1_ptr, H2_ptr, Ht_ptr, stride, n_samples, batch, epochs, lr, lr_final, seed):
     losses = np.zeros(max(int(epochs), 1), np.float64)
-    _call("fem_sur_train", s, C.c_void_p(H0_ptr), C.c_void_p(H1_ptr), C.c_void_p(Ht_ptr), int(stride),
-          int(n_samples), int(batch), int(epochs), float(lr), float(lr_final), int(seed), _p(losses))
+    _call("fem_sur_train", s, C.c_void_p(H0_ptr), C.c_void_p(H1_ptr), C.c_void_p(H2_ptr), C.c_void_p(Ht_ptr),
+          int(stride), int(n_samples), int(batch), int(epochs), float(lr), float(lr_final), int(seed), _p(losses))
     return losses[:int(epochs)]
 
 
-def fem_sur_predict(s, H0_ptr, H1_ptr, stride, slots, out_ptr):
-    _call("fem_sur_predict", s, C.c_void_p(H0_ptr), C.c_void_p(H1_ptr), int(stride), int(slots), C.c_void_p(out_ptr))
+def fem_sur_predict(s, H0_ptr, H1_ptr, H2_ptr, stride, slots, out_ptr):
+    _call("fem_sur_predict", s, C.c_void_p(H0_ptr), C.c_void_p(H1_ptr), C.c_void_p(H2_ptr), int(stride), int(slots),
+          C.c_void_p(out_ptr))
 
 
 def fem_snapshot_H(ctx, out_ptr):
@@ -539,25 +545,42 @@ class Surrogate:
     def set_params(self, p):
         fem_sur_set_params(self.sur, p)
 
-    def features(self, H0, H1, slots=1):
-        self._sync_in()
-        return fem_sur_features(self.sur, H0.data_ptr(), H1.data_ptr(), self.n_nodes if slots == 1 else H0.stride(0),
-                                slots, self.n_nodes)
+    def _states(self, tensors, stride, slots):
+        """Device pointers of float32 CUDA tensors (or views), each checked to reach `slots`
+        states `stride` floats apart within its storage."""
+        need = (slots - 1) * stride + self.n_nodes
+        for t in tensors:
+            assert t.dtype == self.torch.float32 and t.is_cuda and t.is_contiguous()
+            st = t.untyped_storage()
+            avail = (st.data_ptr() + st.nbytes() - t.data_ptr()) // 4
+            if avail < need:
+                raise ValueError("state tensor too small for %d states of stride %d" % (slots, stride))
+        return [t.data_ptr() for t in tensors]
 
-    def loss_grad(self, H0, H1, Ht, stride=None, slots=1):
+    def features(self, H0, H1, H2, stride=None, slots=1):
+        stride = self.n_nodes if stride is None else stride
+        ptrs = self._states((H0, H1, H2), stride, slots)
         self._sync_in()
-        return fem_sur_loss_grad(self.sur, H0.data_ptr(), H1.data_ptr(), Ht.data_ptr(),
-                                 self.n_nodes if stride is None else stride, slots)
+        return fem_sur_features(self.sur, *ptrs, stride, slots, self.n_nodes)
 
-    def train(self, H0, H1, Ht, stride, n_samples, batch=1, epochs=1, lr=1e-3, lr_final=1e-5, seed=0):
+    def loss_grad(self, H0, H1, H2, Ht, stride=None, slots=1):
+        stride = self.n_nodes if stride is None else stride
+        ptrs = self._states((H0, H1, H2, Ht), stride, slots)
         self._sync_in()
-        return fem_sur_train(self.sur, H0.data_ptr(), H1.data_ptr(), Ht.data_ptr(), stride, n_samples, batch,
-                             epochs, lr, lr_final, seed)
+        return fem_sur_loss_grad(self.sur, *ptrs, stride, slots)
 
-    def predict(self, H0, H1, out, stride=None, slots=1):
+    def train(self, H0, H1, H2, Ht, stride, n_samples, batch=1, epochs=1, lr=1e-3, lr_final=1e-5, seed=0):
+        """Tensors may be views into one buffer (e.g. states [k][0..2] with Ht = the next [k][0])."""
+        ptrs = self._states((H0, H1, H2, Ht), stride, n_samples)
         self._sync_in()
-        fem_sur_predict(self.sur, H0.data_ptr(), H1.data_ptr(), self.n_nodes if stride is None else stride, slots,
-                        out.data_ptr())
+        return fem_sur_train(self.sur, *ptrs, stride, n_samples, batch, epochs, lr, lr_final, seed)
+
+    def predict(self, H0, H1, H2, out, stride=None, slots=1):
+        stride = self.n_nodes if stride is None else stride
+        ptrs = self._states((H0, H1, H2), stride, slots)
+        assert out.dtype == self.torch.float64 and out.is_cuda and out.numel() >= slots * self.n_nodes
+        self._sync_in()
+        fem_sur_predict(self.sur, *ptrs, stride, slots, out.data_ptr())
 
     def close(self):
         if self.sur is not None:

@@ -700,16 +700,29 @@ namespace castfem {
 // FP64 energy balance per scenario (reps[n_scen]): on-demand state reduction
 // over single-scenario node segments plus the per-node inflow sums, all summed
 // on the host in a fixed order
+void energy_copies(fem_ctx *ctx, std::vector<double> &dg, std::vector<double> &qn) {
+    const Layout &L = ctx->L();
+    const int64_t S = (int64_t)L.seg_scen.size(), Q = L.n_inflow;
+    dg.resize(S * NDIAG);
+    qn.resize(Q);
+    HIPCHECK(hipMemcpyAsync(dg.data(), ctx->ptr[B_DIAG], S * NDIAG * 8, hipMemcpyDeviceToHost, ctx->stream));
+    if (Q) HIPCHECK(hipMemcpyAsync(qn.data(), ctx->ptr[B_QNODE], Q * 8, hipMemcpyDeviceToHost, ctx->stream));
+}
+
 void energy_scenarios(fem_ctx *ctx, fem_energy_report *reps) {
+    std::vector<double> dg, qn;
+    HIPCHECK(enqueue_state_diag(ctx->dev, ctx->parity, ctx->stream));
+    energy_copies(ctx, dg, qn);
+    HIPCHECK(hipStreamSynchronize(ctx->stream));
+    HIPCHECK(hipGetLastError());
+    energy_reduce(ctx, dg, qn, reps);
+}
+
+void energy_reduce(const fem_ctx *ctx, const std::vector<double> &dg, const std::vector<double> &qn,
+                   fem_energy_report *reps) {
     const int32_t ns = ctx->prob.n_scen;
     const Layout &L = ctx->L();
     const int64_t S = (int64_t)L.seg_scen.size(), Q = L.n_inflow;
-    std::vector<double> dg(S * NDIAG), qn(Q);
-    HIPCHECK(enqueue_state_diag(ctx->dev, ctx->parity, ctx->stream));
-    HIPCHECK(hipMemcpyAsync(dg.data(), ctx->ptr[B_DIAG], S * NDIAG * 8, hipMemcpyDeviceToHost, ctx->stream));
-    if (Q) HIPCHECK(hipMemcpyAsync(qn.data(), ctx->ptr[B_QNODE], Q * 8, hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHECK(hipStreamSynchronize(ctx->stream));
-    HIPCHECK(hipGetLastError());
     for (int32_t sc = 0; sc < ns; ++sc) {
         std::memset(&reps[sc], 0, sizeof(fem_energy_report));
         reps[sc].E0 = ctx->E0_s[sc];

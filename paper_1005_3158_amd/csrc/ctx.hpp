@@ -128,6 +128,12 @@ void eager_steps(fem_ctx *c, int64_t n);
 void run_steps(fem_ctx *c, int64_t n);
 void check_bound(fem_ctx *c, int fn_stage);
 void energy_scenarios(fem_ctx *ctx, fem_energy_report *reps);
+// the parts of energy_scenarios: device-to-host copies of the state
+// diagnostics and inflow (enqueued; valid after a stream sync), and the
+// fixed-order host reduction into per-scenario reports
+void energy_copies(fem_ctx *ctx, std::vector<double> &dg, std::vector<double> &qn);
+void energy_reduce(const fem_ctx *ctx, const std::vector<double> &dg, const std::vector<double> &qn,
+                   fem_energy_report *reps);
 
 template <class F>
 int guarded(F &&f) {

@@ -21,13 +21,14 @@ namespace {
 
 enum SBuf {
     S_NBR_PTR, S_NBR, S_INV_DEG, S_COEF, S_PARAMS, S_GRADS, S_ADAM_M, S_ADAM_V, S_WBF, S_X, S_ZIN, S_U, S_Z,
-    S_HL, S_Y, S_BASE, S_SCALE, S_TARGET, S_DH, S_DZ, S_DU, S_PARTIALS, S_LOSS, S_IDX, S_H0, S_H1, S_CHECK,
-    S_COUNT
+    S_HL, S_Y, S_BASE, S_SCALE, S_TARGET, S_DH, S_DZ, S_DU, S_PARTIALS, S_LOSS, S_IDX, S_H0, S_H1, S_H2, S_CHECK,
+    S_SCEN, S_SCEN_SEG_PTR, S_SCEN_SEG, S_SEG_PART, S_SCEN_SUM, S_COUNT
 };
 const char *const SBUF_NAMES[S_COUNT] = {"nbr_ptr", "nbr", "inv_deg", "coef", "params", "grads", "adam_m",
                                          "adam_v", "weights_bf16", "X", "Z_in", "U", "Z", "H_last", "y",
                                          "base", "scale", "target", "dH", "dZ", "dU", "partials", "loss_part",
-                                         "sample_idx", "H0", "H1", "check"};
+                                         "sample_idx", "H0", "H1", "H2", "check", "scenario",
+                                         "scen_seg_ptr", "scen_seg", "seg_part", "scen_sum"};
 
 // counter-based generator (SplitMix64 of seed and counter) for the
 // initial parameters and the sample shuffles
@@ -54,11 +55,27 @@ struct fem_sur {
     ParamLayout pl;
     std::vector<int32_t> nbr_ptr, nbr;
     std::vector<float> inv_deg, coef;
+    std::vector<int32_t> scen, scen_seg_ptr, scen_seg;
+    int64_t n_seg = 0, n_scen = 1;
     int64_t sizes[S_COUNT] = {};
     void *ptr[S_COUNT] = {};
     bool bound = false;
     SurDev d;
     int adam_t = 0;
+    // captured graphs of the accelerated advance, per starting T parity:
+    // the jump chunk (two steps, inference, checks, diagnostics) and the
+    // horizon - 2 fallback steps
+    hipGraph_t graph[2][2] = {};
+    hipGraphExec_t exec[2][2] = {};
+    float graph_fs_tol = -1.0f;
+    ~fem_sur() {
+        for (auto &row : exec)
+            for (hipGraphExec_t &e : row)
+                if (e) (void)hipGraphExecDestroy(e);
+        for (auto &row : graph)
+            for (hipGraph_t &g : row)
+                if (g) (void)hipGraphDestroy(g);
+    }
 };
 
 namespace {
@@ -86,7 +103,13 @@ void sur_sizes(fem_sur *s) {
     z[S_SCALE] = R * 4;
     z[S_H0] = N * 8;
     z[S_H1] = N * 8;
+    z[S_H2] = N * 8;
     z[S_CHECK] = check_blocks(N) * 4;
+    z[S_SCEN] = N * 4;
+    z[S_SCEN_SEG_PTR] = (s->n_scen + 1) * 4;
+    z[S_SCEN_SEG] = s->n_seg * 4;
+    z[S_SEG_PART] = (int64_t)s->opt.max_samples * s->n_seg * 8;
+    z[S_SCEN_SUM] = (int64_t)s->opt.max_samples * s->n_scen * 8;
     if (tr) {
         z[S_GRADS] = P * 4;
         z[S_ADAM_M] = P * 4;
@@ -95,7 +118,7 @@ void sur_sizes(fem_sur *s) {
         z[S_DH] = R * W * 4;
         z[S_DZ] = R * W * 2;
         z[S_DU] = R * 2 * W * 4;
-        z[S_PARTIALS] = s->nb * (2 * W * W) * 4;
+        z[S_PARTIALS] = s->nb * (2 * W * W + W) * 4;
         z[S_LOSS] = ((R + 255) / 256) * 8;
         z[S_IDX] = (int64_t)s->opt.max_samples * 4;
     }
@@ -138,12 +161,16 @@ void build_graph(fem_sur *s) {
     }
 }
 
-// per-node strengths over m_i c_i: Robin, interface, conduction
+// per-node strengths over m_i c_i (Robin, interface, conduction), the scenario
+// of every node and the weights m_i c_i / sum over its scenario's free nodes
 void build_coef(fem_sur *s) {
     const fem_ctx *c = s->ctx;
     const Layout &L = c->L();
     const Base &b = c->base;
+    const int32_t ns = c->prob.n_scen;
     s->coef.assign(L.N * 4, 0.0f);
+    s->scen.assign(L.N, 0);
+    std::vector<double> tot(ns, 0.0);
     for (int64_t g = 0; g < L.N; ++g) {
         const int32_t o = L.iperm[g];
         const double mc = b.m[o] * c->prob.mats[b.nmat[o]].c;
@@ -152,7 +179,24 @@ void build_coef(fem_sur *s) {
         s->coef[4 * g + 0] = (float)(b.robin_b[o] / mc);
         s->coef[4 * g + 1] = (float)(2.0 * wl / mc);
         s->coef[4 * g + 2] = (float)(b.kabs[o] / mc);
+        s->scen[g] = c->prob.scen_of_mat(b.nmat[o]);
+        if (!(L.nflag[g] & NODE_FIXED)) tot[s->scen[g]] += mc;
     }
+    for (int64_t g = 0; g < L.N; ++g) {
+        const int32_t o = L.iperm[g];
+        const double mc = b.m[o] * c->prob.mats[b.nmat[o]].c;
+        const double t = tot[s->scen[g]];
+        s->coef[4 * g + 3] = (L.nflag[g] & NODE_FIXED) || !(t > 0) ? 0.0f : (float)(mc / t);
+    }
+    // segments of every scenario (the context's single-scenario node segments)
+    s->n_seg = (int64_t)L.seg_scen.size();
+    s->n_scen = ns;
+    s->scen_seg_ptr.assign(ns + 1, 0);
+    for (int32_t sc : L.seg_scen) ++s->scen_seg_ptr[sc + 1];
+    for (int32_t k = 0; k < ns; ++k) s->scen_seg_ptr[k + 1] += s->scen_seg_ptr[k];
+    s->scen_seg.resize(s->n_seg);
+    std::vector<int32_t> at(s->scen_seg_ptr.begin(), s->scen_seg_ptr.end() - 1);
+    for (int64_t g = 0; g < s->n_seg; ++g) s->scen_seg[at[L.seg_scen[g]]++] = (int32_t)g;
 }
 
 void init_params(fem_sur *s, std::vector<float> &p) {
@@ -163,7 +207,7 @@ void init_params(fem_sur *s, std::vector<float> &p) {
     for (int64_t k = 0; k < NFEAT * WIDTH; ++k) p[pl.w_in + k] = (float)(s_in * normal(seed, 1, k));
     for (int l = 0; l < pl.layers; ++l)
         for (int64_t k = 0; k < 2 * WIDTH * WIDTH; ++k) p[pl.w[l] + k] = (float)(s_l * normal(seed, 2 + l, k));
-    for (int64_t k = 0; k < WIDTH; ++k) p[pl.w_out + k] = (float)(0.01 * normal(seed, 9, k));
+    // w_out = 0, b_out = 0: an untrained network predicts the extrapolation itself
 }
 
 void fill_surdev(fem_sur *s) {
@@ -215,7 +259,16 @@ void fill_surdev(fem_sur *s) {
     d.loss_part = (double *)s->ptr[S_LOSS];
     d.H0 = (double *)s->ptr[S_H0];
     d.H1 = (double *)s->ptr[S_H1];
+    d.H2 = (double *)s->ptr[S_H2];
     d.check = (int32_t *)s->ptr[S_CHECK];
+    d.scen = (const int32_t *)s->ptr[S_SCEN];
+    d.seg_begin = (const int32_t *)c->ptr[B_SEG];
+    d.n_seg = s->n_seg;
+    d.n_scen = s->n_scen;
+    d.scen_seg_ptr = (const int32_t *)s->ptr[S_SCEN_SEG_PTR];
+    d.scen_seg = (const int32_t *)s->ptr[S_SCEN_SEG];
+    d.seg_part = (double *)s->ptr[S_SEG_PART];
+    d.scen_sum = (double *)s->ptr[S_SCEN_SUM];
 }
 
 void need_bound(const fem_sur *s) {
@@ -237,11 +290,11 @@ void upload_params(fem_sur *s, const float *p) {
 }
 
 // one forward and backward pass over `slots` states; loss partials left on the device
-void pass(fem_sur *s, const float *H0, const float *H1, const float *Ht, int64_t stride, const int32_t *idx,
-          int64_t slots) {
+void pass(fem_sur *s, const float *H0, const float *H1, const float *H2, const float *Ht, int64_t stride,
+          const int32_t *idx, int64_t slots) {
     hipStream_t st = s->ctx->stream;
     const int64_t R = slots * s->N;
-    HIPCHECK(features(s->d, H0, H1, 0, Ht, stride, idx, slots, st));
+    HIPCHECK(features(s->d, H0, H1, H2, 0, Ht, stride, idx, slots, st));
     HIPCHECK(forward(s->d, R, st));
     HIPCHECK(loss_and_dy(s->d, R, st));
     HIPCHECK(backward(s->d, R, st));
@@ -257,6 +310,71 @@ double loss_of(fem_sur *s, int64_t R) {
     return sum / (double)R;
 }
 
+// work of one chunk of the accelerated advance starting from T parity p:
+// H0 = H^n, step, H1, step, H2, inference, the jump written into the state
+// with its fraction-solid check, and the state diagnostics of the result
+void enqueue_jump(fem_sur *s, int p, float fs_tol) {
+    fem_ctx *c = s->ctx;
+    hipStream_t st = c->stream;
+    HIPCHECK(state_to_f64(c->dev, s->d.H0, st));
+    HIPCHECK(enqueue_step(c->dev, p, st, nullptr));
+    HIPCHECK(state_to_f64(c->dev, s->d.H1, st));
+    HIPCHECK(enqueue_step(c->dev, p ^ 1, st, nullptr));
+    HIPCHECK(state_to_f64(c->dev, s->d.H2, st));
+    HIPCHECK(features(s->d, s->d.H0, s->d.H1, s->d.H2, 1, nullptr, s->N, nullptr, 1, st));
+    HIPCHECK(forward(s->d, s->N, st));
+    HIPCHECK(write_jump(s->d, c->dev, p, fs_tol, st));
+    HIPCHECK(enqueue_state_diag(c->dev, p, st));
+}
+
+// the fallback of a rejected jump: back to H2, then horizon - 2 explicit steps
+void enqueue_fallback(fem_sur *s, int p) {
+    fem_ctx *c = s->ctx;
+    HIPCHECK(restore_h2(s->d, c->dev, p, c->stream));
+    for (int k = 0; k < s->opt.horizon - 2; ++k) HIPCHECK(enqueue_step(c->dev, p ^ (k & 1), c->stream, nullptr));
+}
+
+// run `what` (0: jump, 1: fallback) from parity p through a graph captured on first use
+void run_chunk(fem_sur *s, int what, int p, float fs_tol) {
+    fem_ctx *c = s->ctx;
+    auto enqueue = [&] {
+        if (what == 0) enqueue_jump(s, p, fs_tol);
+        else enqueue_fallback(s, p);
+    };
+    if (!c->stream) {                       // the null stream cannot be captured
+        enqueue();
+        return;
+    }
+    if (what == 0 && fs_tol != s->graph_fs_tol) {   // the tolerance is a kernel argument
+        for (int q = 0; q < 2; ++q) {
+            if (s->exec[0][q]) HIPCHECK(hipGraphExecDestroy(s->exec[0][q]));
+            if (s->graph[0][q]) HIPCHECK(hipGraphDestroy(s->graph[0][q]));
+            s->exec[0][q] = nullptr;
+            s->graph[0][q] = nullptr;
+        }
+        s->graph_fs_tol = fs_tol;
+    }
+    if (!s->exec[what][p]) {
+        HIPCHECK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        std::string err;
+        try {
+            enqueue();
+        } catch (const PrepError &e) {
+            err = e.msg;
+        }
+        hipGraph_t g = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+        if (!err.empty()) {
+            if (g) (void)hipGraphDestroy(g);
+            throw PrepError{FEM_E_HIP, err};
+        }
+        HIPCHECK(e2);
+        s->graph[what][p] = g;
+        HIPCHECK(hipGraphInstantiate(&s->exec[what][p], g, nullptr, nullptr, 0));
+    }
+    HIPCHECK(hipGraphLaunch(s->exec[what][p], c->stream));
+}
+
 }  // namespace
 
 extern "C" {
@@ -268,8 +386,8 @@ int fem_sur_create(fem_sur **out, fem_ctx *ctx, const fem_sur_options *o) {
         check_bound(ctx, ST_BOUND);
         if (o->width != WIDTH) throw PrepError{FEM_E_UNSUPPORTED, "width must be 64"};
         if (o->layers < 1 || o->layers > MAX_LAYERS) throw PrepError{FEM_E_INVALID_ARG, "layers must be 1..4"};
-        if (o->horizon < 2) throw PrepError{FEM_E_INVALID_ARG, "horizon must be >= 2"};
-        if (o->max_samples < 1) throw PrepError{FEM_E_INVALID_ARG, "max_samples must be >= 1"};
+        if (o->horizon < 3) throw PrepError{FEM_E_INVALID_ARG, "horizon must be >= 3"};
+        if (o->max_samples < 1 || o->max_samples > 65535) throw PrepError{FEM_E_INVALID_ARG, "max_samples must be 1..65535"};
         if (o->loss != FEM_SUR_LOSS_H && o->loss != FEM_SUR_LOSS_T) throw PrepError{FEM_E_INVALID_ARG, "unknown loss"};
         for (int32_t r : o->reserved)
             if (r) throw PrepError{FEM_E_INVALID_ARG, "reserved fields must be zero"};
@@ -331,6 +449,10 @@ int fem_sur_bind_buffers(fem_sur *s, void *const *dev_ptrs, int32_t n) {
         if (s->nnz) HIPCHECK(hipMemcpyAsync(s->ptr[S_NBR], s->nbr.data(), s->sizes[S_NBR], hipMemcpyHostToDevice, st));
         HIPCHECK(hipMemcpyAsync(s->ptr[S_INV_DEG], s->inv_deg.data(), s->sizes[S_INV_DEG], hipMemcpyHostToDevice, st));
         HIPCHECK(hipMemcpyAsync(s->ptr[S_COEF], s->coef.data(), s->sizes[S_COEF], hipMemcpyHostToDevice, st));
+        HIPCHECK(hipMemcpyAsync(s->ptr[S_SCEN], s->scen.data(), s->sizes[S_SCEN], hipMemcpyHostToDevice, st));
+        HIPCHECK(hipMemcpyAsync(s->ptr[S_SCEN_SEG_PTR], s->scen_seg_ptr.data(), s->sizes[S_SCEN_SEG_PTR],
+                                hipMemcpyHostToDevice, st));
+        HIPCHECK(hipMemcpyAsync(s->ptr[S_SCEN_SEG], s->scen_seg.data(), s->sizes[S_SCEN_SEG], hipMemcpyHostToDevice, st));
         if (s->opt.train) {
             HIPCHECK(hipMemsetAsync(s->ptr[S_ADAM_M], 0, s->sizes[S_ADAM_M], st));
             HIPCHECK(hipMemsetAsync(s->ptr[S_ADAM_V], 0, s->sizes[S_ADAM_V], st));
@@ -376,13 +498,14 @@ int fem_sur_set_params(fem_sur *s, const float *host, int64_t n) {
     });
 }
 
-int fem_sur_features(fem_sur *s, const float *H0, const float *H1, int64_t stride, int64_t slots, float *X_host) {
-    if (!s || !H0 || !H1 || !X_host) return set_err(FEM_E_INVALID_ARG, "null argument");
+int fem_sur_features(fem_sur *s, const float *H0, const float *H1, const float *H2, int64_t stride, int64_t slots,
+                     float *X_host) {
+    if (!s || !H0 || !H1 || !H2 || !X_host) return set_err(FEM_E_INVALID_ARG, "null argument");
     return guarded([&] {
         need_bound(s);
         check_slots(s, slots);
         const int64_t R = slots * s->N;
-        HIPCHECK(features(s->d, H0, H1, 0, nullptr, stride, nullptr, slots, s->ctx->stream));
+        HIPCHECK(features(s->d, H0, H1, H2, 0, nullptr, stride, nullptr, slots, s->ctx->stream));
         std::vector<bf16> x(R * KIN);
         HIPCHECK(hipMemcpyAsync(x.data(), s->ptr[S_X], R * KIN * 2, hipMemcpyDeviceToHost, s->ctx->stream));
         HIPCHECK(hipStreamSynchronize(s->ctx->stream));
@@ -396,21 +519,22 @@ int fem_sur_features(fem_sur *s, const float *H0, const float *H1, int64_t strid
     });
 }
 
-int fem_sur_loss_grad(fem_sur *s, const float *H0, const float *H1, const float *Ht, int64_t stride, int64_t slots,
-                      double *loss, float *grad_host) {
-    if (!s || !H0 || !H1 || !Ht || !loss || !grad_host) return set_err(FEM_E_INVALID_ARG, "null argument");
+int fem_sur_loss_grad(fem_sur *s, const float *H0, const float *H1, const float *H2, const float *Ht, int64_t stride,
+                      int64_t slots, double *loss, float *grad_host) {
+    if (!s || !H0 || !H1 || !H2 || !Ht || !loss || !grad_host) return set_err(FEM_E_INVALID_ARG, "null argument");
     return guarded([&] {
         need_train(s);
         check_slots(s, slots);
-        pass(s, H0, H1, Ht, stride, nullptr, slots);
+        pass(s, H0, H1, H2, Ht, stride, nullptr, slots);
         HIPCHECK(hipMemcpyAsync(grad_host, s->ptr[S_GRADS], s->pl.total * 4, hipMemcpyDeviceToHost, s->ctx->stream));
         *loss = loss_of(s, slots * s->N);
     });
 }
 
-int fem_sur_train(fem_sur *s, const float *H0, const float *H1, const float *Ht, int64_t stride, int64_t n_samples,
-                  int32_t batch, int32_t epochs, float lr, float lr_final, uint64_t seed, double *loss_per_epoch) {
-    if (!s || !H0 || !H1 || !Ht) return set_err(FEM_E_INVALID_ARG, "null argument");
+int fem_sur_train(fem_sur *s, const float *H0, const float *H1, const float *H2, const float *Ht, int64_t stride,
+                  int64_t n_samples, int32_t batch, int32_t epochs, float lr, float lr_final, uint64_t seed,
+                  double *loss_per_epoch) {
+    if (!s || !H0 || !H1 || !H2 || !Ht) return set_err(FEM_E_INVALID_ARG, "null argument");
     return guarded([&] {
         need_train(s);
         check_slots(s, batch);
@@ -433,7 +557,7 @@ int fem_sur_train(fem_sur *s, const float *H0, const float *H1, const float *Ht,
             for (int64_t b0 = 0; b0 < n_samples; b0 += batch) {
                 const int64_t slots = std::min<int64_t>(batch, n_samples - b0);
                 HIPCHECK(hipMemcpyAsync(s->ptr[S_IDX], perm.data() + b0, slots * 4, hipMemcpyHostToDevice, st));
-                pass(s, H0, H1, Ht, stride, (const int32_t *)s->ptr[S_IDX], slots);
+                pass(s, H0, H1, H2, Ht, stride, (const int32_t *)s->ptr[S_IDX], slots);
                 // cosine decay from lr to lr_final over all iterations
                 const double fr = total > 1 ? (double)it / (double)(total - 1) : 0.0;
                 const float rate = (float)(lr_final + 0.5 * (lr - lr_final) * (1.0 + std::cos(3.141592653589793 * fr)));
@@ -449,14 +573,15 @@ int fem_sur_train(fem_sur *s, const float *H0, const float *H1, const float *Ht,
     });
 }
 
-int fem_sur_predict(fem_sur *s, const float *H0, const float *H1, int64_t stride, int64_t slots, double *H_out) {
-    if (!s || !H0 || !H1 || !H_out) return set_err(FEM_E_INVALID_ARG, "null argument");
+int fem_sur_predict(fem_sur *s, const float *H0, const float *H1, const float *H2, int64_t stride, int64_t slots,
+                    double *H_out) {
+    if (!s || !H0 || !H1 || !H2 || !H_out) return set_err(FEM_E_INVALID_ARG, "null argument");
     return guarded([&] {
         need_bound(s);
         check_slots(s, slots);
         hipStream_t st = s->ctx->stream;
         const int64_t R = slots * s->N;
-        HIPCHECK(features(s->d, H0, H1, 0, nullptr, stride, nullptr, slots, st));
+        HIPCHECK(features(s->d, H0, H1, H2, 0, nullptr, stride, nullptr, slots, st));
         HIPCHECK(forward(s->d, R, st));
         HIPCHECK(apply(s->d, R, H_out, st));
         HIPCHECK(hipStreamSynchronize(st));
@@ -513,6 +638,7 @@ int fem_advance(fem_ctx *ctx, fem_sur *s, const double *dt_per_scenario, int64_t
         }
         const int64_t nchk = check_blocks(ctx->L().N);
         std::vector<int32_t> chk(nchk);
+        std::vector<double> dg, qn;
         while (!(until_solid && all_solid()) && rep->steps + H <= max_steps) {
             if (!s) {
                 run_steps(ctx, H);
@@ -521,55 +647,56 @@ int fem_advance(fem_ctx *ctx, fem_sur *s, const double *dt_per_scenario, int64_t
                 energy_scenarios(ctx, er.data());
                 continue;
             }
-            // one plain step from H0 to H1, then the network jumps H - 1 steps further
-            HIPCHECK(state_to_f64(ctx->dev, s->d.H0, st));
-            run_steps(ctx, 1);
-            advance_clock(1);
-            rep->plain_steps += 1;
-            HIPCHECK(state_to_f64(ctx->dev, s->d.H1, st));
-            HIPCHECK(features(s->d, s->d.H0, s->d.H1, 1, nullptr, s->N, nullptr, 1, st));
-            HIPCHECK(forward(s->d, s->N, st));
-            HIPCHECK(write_jump(s->d, ctx->dev, ctx->parity, (float)fs_tol, st));
+            // two plain steps (H0 -> H1 -> H2), then the network jumps H - 2 steps further
+            run_chunk(s, 0, ctx->parity, (float)fs_tol);      // the T parity is back after two steps
+            advance_clock(2);
+            rep->plain_steps += 2;
             HIPCHECK(hipMemcpyAsync(chk.data(), s->ptr[S_CHECK], nchk * 4, hipMemcpyDeviceToHost, st));
-            energy_scenarios(ctx, er.data());       // synchronises
+            energy_copies(ctx, dg, qn);
+            HIPCHECK(hipStreamSynchronize(st));
+            energy_reduce(ctx, dg, qn, er.data());
             int64_t bad = 0;
             for (int32_t v : chk) bad += v;
-            // FP64 gate of the jump: energy change against the boundary inflow
-            // extrapolated from the plain step (linear trend of the per-step
-            // inflow when the previous jump supplies one)
+            // FP64 gate of the jump: energy change over the chunk against the
+            // boundary inflow of the two plain steps plus its extrapolation over
+            // the jumped ones (mean rate of the plain steps, and the trend from
+            // the previous chunk's rate when there is one)
+            const double m = (double)(H - 2);
             bool ok = bad == 0;
-            std::vector<double> est(ns), res(ns);
+            if (!ok) ++rep->rejected_fs;
+            std::vector<double> est(ns), res(ns), rate(ns);
             for (int32_t sc = 0; sc < ns && ok; ++sc) {
                 const fem_energy_report &r = er[sc];
-                const double rate = r.Q_cum - Q_prev[sc];
-                const double m = (double)(H - 1);
-                est[sc] = m * rate + (std::isnan(rate_prev[sc]) ? 0.0 : (rate - rate_prev[sc]) / (double)H * m * (double)H / 2.0);
-                res[sc] = std::fabs((r.E - E_prev[sc]) - (rate + est[sc])) / std::fabs(E_prev[sc] - ctx->Eref_s[sc]);
-                if (r.nonfinite || !(res[sc] <= energy_tol)) ok = false;
+                rate[sc] = 0.5 * (r.Q_cum - Q_prev[sc]);
+                const double slope = std::isnan(rate_prev[sc]) ? 0.0 : (rate[sc] - rate_prev[sc]) / (double)H;
+                est[sc] = m * rate[sc] + slope * (0.5 * m * (m - 1.0) + 1.5 * m);
+                res[sc] = std::fabs((r.E - E_prev[sc]) - (2.0 * rate[sc] + est[sc])) / std::fabs(E_prev[sc] - ctx->Eref_s[sc]);
+                if (r.nonfinite || !(res[sc] <= energy_tol)) {
+                    ok = false;
+                    ++rep->rejected_energy;
+                }
             }
             if (ok) {
                 for (int32_t sc = 0; sc < ns; ++sc) {
-                    const double rate = er[sc].Q_cum - Q_prev[sc];
                     ctx->Qx_s[sc] += est[sc];
                     E_prev[sc] = er[sc].E;
                     Q_prev[sc] = er[sc].Q_cum + est[sc];
-                    rate_prev[sc] = rate;
+                    rate_prev[sc] = rate[sc];
                     er[sc].Q_cum += est[sc];
                     rep->max_residual = std::max(rep->max_residual, res[sc]);
                 }
-                advance_clock(H - 1);
+                advance_clock(H - 2);
                 ++rep->jumps_accepted;
             } else {
-                HIPCHECK(restore_h1(s->d, ctx->dev, ctx->parity, st));
-                run_steps(ctx, H - 1);
-                advance_clock(H - 1);
-                rep->plain_steps += H - 1;
+                run_chunk(s, 1, ctx->parity, (float)fs_tol);
+                ctx->parity ^= (int)((H - 2) & 1);
+                advance_clock(H - 2);
+                rep->plain_steps += H - 2;
                 ++rep->jumps_rejected;
-                const std::vector<double> Q_start(Q_prev);
                 energy_scenarios(ctx, er.data());
                 for (int32_t sc = 0; sc < ns; ++sc) {
                     E_prev[sc] = er[sc].E;
-                    rate_prev[sc] = (er[sc].Q_cum - Q_start[sc]) / (double)H;
+                    rate_prev[sc] = NAN;
                     Q_prev[sc] = er[sc].Q_cum;
                 }
             }

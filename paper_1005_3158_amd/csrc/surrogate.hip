@@ -48,37 +48,43 @@ __device__ __forceinline__ void t_of_h(const MatDev &M, double H, double &T, dou
 }
 
 // ---------------------------------------------------------------- features
-// Row r = q N + i holds node i of state slot q; the state is sample idx[q]
-// (q without a list), read at offset sample * stride of H0 / H1 / Ht.
+// Row r = q N + i holds node i of state slot q; the slot is sample idx[q]
+// (q without a list), read at offset sample * stride of H0 / H1 / H2 / Ht,
+// three consecutive explicit states and the state `horizon` steps after H0.
 template <class HT>
-__global__ __launch_bounds__(256) void k_features(SurDev s, const HT *H0, const HT *H1, const float *Ht,
+__global__ __launch_bounds__(256) void k_features(SurDev s, const HT *H0, const HT *H1, const HT *H2, const float *Ht,
                                                   int64_t stride, const int32_t *idx, int64_t slots) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= slots * s.N) return;
     const int64_t q = r / s.N, i = r - q * s.N;
     const int64_t at = (idx ? (int64_t)idx[q] : q) * stride + i;
     const MatDev &M = ((const MatDev *)s.mats)[s.flags[i] & NODE_MAT_MASK];
-    const double h0 = (double)H0[at], h1 = (double)H1[at];
-    double T1, fs1;
-    t_of_h(M, h1, T1, fs1);
+    const double h0 = (double)H0[at], h1 = (double)H1[at], h2 = (double)H2[at];
+    const double rate = h2 - h1, acc = (h2 - h1) - (h1 - h0);
+    double T2, fs2;
+    t_of_h(M, h2, T2, fs2);
     const float4 co = ((const float4 *)s.coef)[i];
-    const double c = M.c, dt = M.dt, hz = (double)s.horizon;
+    const double c = M.c, dt = M.dt, hz = (double)s.horizon, m = hz - 2.0;
     float x[NFEAT];
-    x[0] = (float)((T1 - T_REF) / T_SCALE);
-    x[1] = (float)fs1;
+    x[0] = (float)((T2 - T_REF) / T_SCALE);
+    x[1] = (float)fs2;
     x[2] = M.latent ? 1.0f : 0.0f;
     x[3] = (float)(co.x * dt);
     x[4] = (float)(co.y * dt);
     x[5] = (float)(co.z * dt);
-    x[6] = (float)(hz * (h1 - h0) / (c * T_SCALE));
-    x[7] = 1.0f;
+    x[6] = (float)(hz * rate / (c * T_SCALE));
+    x[7] = (float)(0.5 * hz * hz * acc / (c * T_SCALE));
+    x[8] = 1.0f;
     uint32_t w[KIN / 2];
-    for (int k = 0; k < NFEAT / 2; ++k) w[k] = (uint32_t)f2bf(x[2 * k]) | ((uint32_t)f2bf(x[2 * k + 1]) << 16);
-    for (int k = NFEAT / 2; k < KIN / 2; ++k) w[k] = 0;
+    for (int k = 0; k < KIN / 2; ++k) {
+        const float lo = 2 * k < NFEAT ? x[2 * k] : 0.0f, hi = 2 * k + 1 < NFEAT ? x[2 * k + 1] : 0.0f;
+        w[k] = (uint32_t)f2bf(lo) | ((uint32_t)f2bf(hi) << 16);
+    }
     uint4 *out = (uint4 *)(s.X + r * KIN);
     out[0] = make_uint4(w[0], w[1], w[2], w[3]);
     out[1] = make_uint4(w[4], w[5], w[6], w[7]);
-    s.base[r] = h1 + (hz - 1.0) * (h1 - h0);
+    // quadratic extrapolation through the three states
+    s.base[r] = h2 + m * rate + 0.5 * m * (m + 1.0) * acc;
     s.scale[r] = (float)(c * DH_SCALE);
     if (Ht) {
         if (s.loss_mode == LOSS_T) {
@@ -136,50 +142,65 @@ __global__ __launch_bounds__(256) void k_gemm(const bf16 *__restrict__ A, int ld
     }
 }
 
-// partial weight gradients: P[wg][KA x 64] = sum over the workgroup's rows of
-// A[r][f] B[r][c] (A: R x KA with row stride lda, B: R x 64); MFMA K runs over rows
+// partial weight and bias gradients of one workgroup's GRAD_ROWS rows:
+// P[wg][f][c] = sum_r A[r][f] B[r][c] (A: R x KA, row stride lda; B: R x 64)
+// and Pb[wg][c] = sum_r B[r][c].  The rows are the MFMA K dimension, so 64-row
+// chunks of A and B are staged transposed in LDS: the four consecutive rows a
+// lane needs are then one 8-byte LDS read.  Wave w owns columns 16w..16w+15.
 template <int KA>
 __global__ __launch_bounds__(256) void k_wgrad(const bf16 *__restrict__ A, int lda, const bf16 *__restrict__ B,
-                                               int64_t R, float *__restrict__ P) {
-    constexpr int FT = KA / 16;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+                                               int64_t R, float *__restrict__ P, float *__restrict__ Pb) {
+    constexpr int FT = KA / 16, CH = 64, LDR = CH + 8;
+    __shared__ __align__(16) bf16 At[KA][LDR];
+    __shared__ __align__(16) bf16 Bt[WIDTH][LDR];
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
     const int mi = lane & 15, kq = (lane >> 4) * 4;
-    const int c = wave * 16 + mi;            // this wave's output columns
     f4 acc[FT];
-    for (int t = 0; t < FT; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int ft = 0; ft < FT; ++ft) acc[ft] = f4{0.f, 0.f, 0.f, 0.f};
+    float bsum = 0.f;
     const int64_t r_begin = (int64_t)blockIdx.x * GRAD_ROWS;
     const int64_t r_end = std::min<int64_t>(R, r_begin + GRAD_ROWS);
-    for (int64_t r0 = r_begin; r0 < r_end; r0 += 16) {
-        s4 b;
-        for (int j = 0; j < 4; ++j) {
-            const int64_t r = r0 + kq + j;
-            b[j] = r < r_end ? (short)B[r * WIDTH + c] : (short)0;
-        }
-        for (int t = 0; t < FT; ++t) {
-            s4 a;
-            for (int j = 0; j < 4; ++j) {
-                const int64_t r = r0 + kq + j;
-                a[j] = r < r_end ? (short)A[r * lda + t * 16 + mi] : (short)0;
+    for (int64_t r0 = r_begin; r0 < r_end; r0 += CH) {
+        constexpr int AV = KA / 8;   // 16-byte vectors per row of A
+        for (int v = t; v < CH * AV; v += 256) {
+            const int rr = v / AV, f8 = (v % AV) * 8;
+            const int64_t r = r0 + rr;
+            uint4 w = make_uint4(0, 0, 0, 0);
+            if (r < r_end) w = *(const uint4 *)(A + r * lda + f8);
+            const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+            for (int k = 0; k < 4; ++k) {
+                At[f8 + 2 * k][rr] = (bf16)(ws[k] & 0xffffu);
+                At[f8 + 2 * k + 1][rr] = (bf16)(ws[k] >> 16);
             }
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
         }
+        for (int v = t; v < CH * (WIDTH / 8); v += 256) {
+            const int rr = v / (WIDTH / 8), c8 = (v % (WIDTH / 8)) * 8;
+            const int64_t r = r0 + rr;
+            uint4 w = make_uint4(0, 0, 0, 0);
+            if (r < r_end) w = *(const uint4 *)(B + r * WIDTH + c8);
+            const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+            for (int k = 0; k < 4; ++k) {
+                Bt[c8 + 2 * k][rr] = (bf16)(ws[k] & 0xffffu);
+                Bt[c8 + 2 * k + 1][rr] = (bf16)(ws[k] >> 16);
+            }
+        }
+        __syncthreads();
+        for (int kk = 0; kk < CH; kk += 16) {
+            const s4 b = *(const s4 *)&Bt[wave * 16 + mi][kk + kq];
+            for (int j = 0; j < 4; ++j) bsum += bf2f((bf16)b[j]);
+            for (int ft = 0; ft < FT; ++ft) {
+                const s4 a = *(const s4 *)&At[ft * 16 + mi][kk + kq];
+                acc[ft] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[ft], 0, 0, 0);
+            }
+        }
+        __syncthreads();
     }
     float *out = P + (int64_t)blockIdx.x * KA * WIDTH;
-    for (int t = 0; t < FT; ++t)
-        for (int j = 0; j < 4; ++j) out[(t * 16 + kq + j) * WIDTH + wave * 16 + mi] = acc[t][j];
-}
-
-// column sums of B (R x 64) per workgroup chunk
-__global__ __launch_bounds__(256) void k_colsum(const bf16 *__restrict__ B, int64_t R, float *__restrict__ P) {
-    __shared__ float part[4][WIDTH];
-    const int c = threadIdx.x & 63, q = threadIdx.x >> 6;
-    const int64_t r_begin = (int64_t)blockIdx.x * GRAD_ROWS;
-    const int64_t r_end = std::min<int64_t>(R, r_begin + GRAD_ROWS);
-    float acc = 0.f;
-    for (int64_t r = r_begin + q; r < r_end; r += 4) acc += bf2f(B[r * WIDTH + c]);
-    part[q][c] = acc;
-    __syncthreads();
-    if (q == 0) P[(int64_t)blockIdx.x * WIDTH + c] = ((part[0][c] + part[1][c]) + part[2][c]) + part[3][c];
+    for (int ft = 0; ft < FT; ++ft)
+        for (int j = 0; j < 4; ++j) out[(ft * 16 + kq + j) * WIDTH + wave * 16 + mi] = acc[ft][j];
+    bsum += __shfl_down(bsum, 32, 64);
+    bsum += __shfl_down(bsum, 16, 64);
+    if (lane < 16) Pb[(int64_t)blockIdx.x * WIDTH + wave * 16 + mi] = bsum;
 }
 
 // sum of the workgroup partials in workgroup order into grads[off + k], k < n
@@ -247,10 +268,57 @@ __global__ __launch_bounds__(256) void k_out(SurDev s, int64_t R) {
     s.y[r] = acc;
 }
 
-// per row: error e and dL/dy of the loss sum_r e_r^2 / R.
+// ---------------------------------------------------------------- energy-neutral correction
+// seg_part[q][g] = sum over the nodes i of segment g of (w ? w_i : 1) v[q N + i]
+__global__ __launch_bounds__(256) void k_seg_sum(SurDev s, const float *v, int weighted) {
+    __shared__ double part[4];
+    const int64_t g = blockIdx.x, q = blockIdx.y;
+    const int32_t b = s.seg_begin[g], e = s.seg_begin[g + 1];
+    double acc = 0.0;
+    for (int32_t i = b + (int32_t)threadIdx.x; i < e; i += blockDim.x) {
+        const double w = weighted ? (double)((const float4 *)s.coef)[i].w : 1.0;
+        acc += w * (double)v[q * s.N + i];
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) s.seg_part[q * s.n_seg + g] = ((part[0] + part[1]) + part[2]) + part[3];
+}
+
+// scen_sum[q][c] = sum of the segment partials of scenario c, in segment order
+__global__ void k_scen_sum(SurDev s, int64_t slots) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= slots * s.n_scen) return;
+    const int64_t q = t / s.n_scen, c = t - q * s.n_scen;
+    double acc = 0.0;
+    for (int32_t k = s.scen_seg_ptr[c]; k < s.scen_seg_ptr[c + 1]; ++k) acc += s.seg_part[q * s.n_seg + s.scen_seg[k]];
+    s.scen_sum[t] = acc;
+}
+
+// forward: y_i -= sum_j w_j y_j over the node's scenario (sum_i w_i y_i becomes 0)
+__global__ __launch_bounds__(256) void k_proj_fwd(SurDev s, int64_t R) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    const int64_t q = r / s.N, i = r - q * s.N;
+    s.y[r] = (float)((double)s.y[r] - s.scen_sum[q * s.n_scen + s.scen[i]]);
+}
+
+// backward: with g = dL/dy (in y), dL/dy_raw_k = g_k - w_k sum_i g_i; dH = dy_raw w_out
+__global__ __launch_bounds__(256) void k_proj_bwd(SurDev s, int64_t R) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    const int64_t q = r / s.N, i = r - q * s.N;
+    const double w = (double)((const float4 *)s.coef)[i].w;
+    const float dy = (float)((double)s.y[r] - w * s.scen_sum[q * s.n_scen + s.scen[i]]);
+    s.y[r] = dy;
+    const float *wo = s.params + s.pl.w_out;
+    for (int c = 0; c < WIDTH; ++c) s.dH[r * WIDTH + c] = dy * wo[c];
+}
+
+// per row: error e and dL/dy of the loss sum_r e_r^2 / R, with y the projected output.
 // LOSS_H: e = y - t.  LOSS_T: e = (T(base + scale y) - T_t) / DT_SCALE, with the
 // slope of the branch of T(H) the prediction lies on.
-// Writes the per-workgroup loss partial, dy (into y) and dH = dy w_out.
+// Writes the per-workgroup loss partial and dL/dy (into y).
 __global__ __launch_bounds__(256) void k_loss(SurDev s, int64_t R) {
     __shared__ double part[4];
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -272,8 +340,6 @@ __global__ __launch_bounds__(256) void k_loss(SurDev s, int64_t R) {
             dy = 2.f * e / (float)R;
         }
         s.y[r] = dy;
-        const float *w = s.params + s.pl.w_out;
-        for (int c = 0; c < WIDTH; ++c) s.dH[r * WIDTH + c] = dy * w[c];
     }
     for (int off = 32; off > 0; off >>= 1) e2 += __shfl_down(e2, off, 64);
     if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = e2;
@@ -380,7 +446,7 @@ __global__ __launch_bounds__(256) void k_write_jump(SurDev s, Dev d, int parity,
             set_node<R>(d, i, M, Hn, (R *)d.T + parity * d.N);
             if (M.latent) {
                 double T0, fs0, T1, fs1;
-                t_of_h(M, s.H1[i], T0, fs0);
+                t_of_h(M, s.H2[i], T0, fs0);
                 t_of_h(M, Hn, T1, fs1);
                 bad = (fs1 < fs0 - (double)fs_tol || !(Hn == Hn)) ? 1 : 0;
             } else {
@@ -400,22 +466,22 @@ __global__ __launch_bounds__(256) void k_restore(SurDev s, Dev d, int parity) {
     if (i >= d.N) return;
     const uint32_t f = d.flags[i];
     if (f & NODE_FIXED) return;
-    set_node<R>(d, i, d.mats[f & NODE_MAT_MASK], s.H1[i], (R *)d.T + parity * d.N);
+    set_node<R>(d, i, d.mats[f & NODE_MAT_MASK], s.H2[i], (R *)d.T + parity * d.N);
 }
 
 inline unsigned grid_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
 
-hipError_t features(const SurDev &s, const void *H0, const void *H1, int h_is_double, const float *Ht,
-                    int64_t stride, const int32_t *idx, int64_t slots, hipStream_t st) {
+hipError_t features(const SurDev &s, const void *H0, const void *H1, const void *H2, int h_is_double,
+                    const float *Ht, int64_t stride, const int32_t *idx, int64_t slots, hipStream_t st) {
     const unsigned g = grid_for(slots * s.N, 256);
     if (h_is_double)
         hipLaunchKernelGGL(k_features<double>, dim3(g), dim3(256), 0, st, s, (const double *)H0, (const double *)H1,
-                           Ht, stride, idx, slots);
+                           (const double *)H2, Ht, stride, idx, slots);
     else
         hipLaunchKernelGGL(k_features<float>, dim3(g), dim3(256), 0, st, s, (const float *)H0, (const float *)H1,
-                           Ht, stride, idx, slots);
+                           (const float *)H2, Ht, stride, idx, slots);
     return hipGetLastError();
 }
 
@@ -432,17 +498,26 @@ hipError_t forward(const SurDev &s, int64_t R, hipStream_t st) {
                            s.params + s.pl.b[l], R, s.Z[l], s.U[l], 2 * WIDTH, hout, ldh, (float *)nullptr, 0);
     }
     hipLaunchKernelGGL(k_out, dim3(grid_for(R, 256)), dim3(256), 0, st, s, R);
+    const int64_t slots = R / s.N;
+    hipLaunchKernelGGL(k_seg_sum, dim3((unsigned)s.n_seg, (unsigned)slots), dim3(256), 0, st, s, (const float *)s.y, 1);
+    hipLaunchKernelGGL(k_scen_sum, dim3(grid_for(slots * s.n_scen, 256)), dim3(256), 0, st, s, slots);
+    hipLaunchKernelGGL(k_proj_fwd, dim3(grid_for(R, 256)), dim3(256), 0, st, s, R);
     return hipGetLastError();
 }
 
 hipError_t loss_and_dy(const SurDev &s, int64_t R, hipStream_t st) {
     hipLaunchKernelGGL(k_loss, dim3(grid_for(R, 256)), dim3(256), 0, st, s, R);
+    const int64_t slots = R / s.N;
+    hipLaunchKernelGGL(k_seg_sum, dim3((unsigned)s.n_seg, (unsigned)slots), dim3(256), 0, st, s, (const float *)s.y, 0);
+    hipLaunchKernelGGL(k_scen_sum, dim3(grid_for(slots * s.n_scen, 256)), dim3(256), 0, st, s, slots);
+    hipLaunchKernelGGL(k_proj_bwd, dim3(grid_for(R, 256)), dim3(256), 0, st, s, R);
     return hipGetLastError();
 }
 
 hipError_t backward(const SurDev &s, int64_t R, hipStream_t st) {
     const int64_t nb = (R + GRAD_ROWS - 1) / GRAD_ROWS;
-    float *P = s.partials;
+    float *P = s.partials;                                             // nb x 2 WIDTH x WIDTH
+    float *Pb = s.partials + s.n_partial_blocks * 2 * WIDTH * WIDTH;   // nb x WIDTH
     // output layer
     hipLaunchKernelGGL(k_out_grad, dim3((unsigned)nb), dim3(256), 0, st, s, R, P);
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(WIDTH + 1), 0, st, P, nb, (int64_t)(WIDTH + 1), WIDTH + 1,
@@ -450,11 +525,10 @@ hipError_t backward(const SurDev &s, int64_t R, hipStream_t st) {
     for (int l = s.layers - 1; l >= 0; --l) {
         hipLaunchKernelGGL(k_relu_back, dim3(grid_for(R * WIDTH, 256)), dim3(256), 0, st, s.dH, s.Z[l], s.dZ,
                            R * WIDTH);
-        hipLaunchKernelGGL((k_wgrad<2 * WIDTH>), dim3((unsigned)nb), dim3(256), 0, st, s.U[l], 2 * WIDTH, s.dZ, R, P);
+        hipLaunchKernelGGL((k_wgrad<2 * WIDTH>), dim3((unsigned)nb), dim3(256), 0, st, s.U[l], 2 * WIDTH, s.dZ, R, P, Pb);
         hipLaunchKernelGGL(k_reduce, dim3(grid_for(2 * WIDTH * WIDTH, 256)), dim3(256), 0, st, P, nb,
                            (int64_t)(2 * WIDTH * WIDTH), 2 * WIDTH * WIDTH, s.grads + s.pl.w[l]);
-        hipLaunchKernelGGL(k_colsum, dim3((unsigned)nb), dim3(256), 0, st, s.dZ, R, P);
-        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(WIDTH), 0, st, P, nb, (int64_t)WIDTH, WIDTH, s.grads + s.pl.b[l]);
+        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(WIDTH), 0, st, Pb, nb, (int64_t)WIDTH, WIDTH, s.grads + s.pl.b[l]);
         hipLaunchKernelGGL((k_gemm<2 * WIDTH, 2>), dim3(grid_for(R, 64)), dim3(256), 0, st, s.dZ, WIDTH, WIDTH,
                            s.wr[l], (const float *)nullptr, R, (bf16 *)nullptr, (const bf16 *)nullptr, 0,
                            (bf16 *)nullptr, 0, s.dU, 2 * WIDTH);
@@ -462,11 +536,10 @@ hipError_t backward(const SurDev &s, int64_t R, hipStream_t st) {
     }
     // encoder
     hipLaunchKernelGGL(k_relu_back, dim3(grid_for(R * WIDTH, 256)), dim3(256), 0, st, s.dH, s.Zin, s.dZ, R * WIDTH);
-    hipLaunchKernelGGL((k_wgrad<KIN>), dim3((unsigned)nb), dim3(256), 0, st, s.X, KIN, s.dZ, R, P);
+    hipLaunchKernelGGL((k_wgrad<KIN>), dim3((unsigned)nb), dim3(256), 0, st, s.X, KIN, s.dZ, R, P, Pb);
     hipLaunchKernelGGL(k_reduce, dim3(grid_for(NFEAT * WIDTH, 256)), dim3(256), 0, st, P, nb, (int64_t)(KIN * WIDTH),
                        NFEAT * WIDTH, s.grads + s.pl.w_in);
-    hipLaunchKernelGGL(k_colsum, dim3((unsigned)nb), dim3(256), 0, st, s.dZ, R, P);
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(WIDTH), 0, st, P, nb, (int64_t)WIDTH, WIDTH, s.grads + s.pl.b_in);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(WIDTH), 0, st, Pb, nb, (int64_t)WIDTH, WIDTH, s.grads + s.pl.b_in);
     return hipGetLastError();
 }
 
@@ -506,7 +579,7 @@ hipError_t write_jump(const SurDev &s, const Dev &d, int parity, float fs_tol, h
     return hipGetLastError();
 }
 
-hipError_t restore_h1(const SurDev &s, const Dev &d, int parity, hipStream_t st) {
+hipError_t restore_h2(const SurDev &s, const Dev &d, int parity, hipStream_t st) {
     const dim3 g((unsigned)check_blocks(d.N));
     if (d.prec == FEM_PREC_FP64)
         hipLaunchKernelGGL(k_restore<double>, g, dim3(256), 0, st, s, d, parity);

@@ -1,7 +1,7 @@
 // Device layout and launchers of the message-passing surrogate (gfx950).
 //
 // Network (width WIDTH, LAYERS message-passing layers), per node row r:
-//   h_0 = relu(X W_in + b_in)                      X: 8 features padded to 16
+//   h_0 = relu(X W_in + b_in)                      X: 9 features padded to 16
 //   h_l = h_{l-1} + relu([h_{l-1}, A h_{l-1}] W_l + b_l)     A: mean over mesh neighbours
 //   y   = h_L . w_out + b_out
 // Activations are BF16, products run on MFMA (v_mfma_f32_16x16x16_bf16) with
@@ -17,7 +17,7 @@ namespace castfem {
 namespace sur {
 
 constexpr int WIDTH = 64;
-constexpr int NFEAT = 8;        // input features
+constexpr int NFEAT = 9;        // input features
 constexpr int KIN = 16;         // features padded to the MFMA K step
 constexpr int MAX_LAYERS = 4;
 constexpr float T_REF = 25.0f, T_SCALE = 700.0f, DH_SCALE = 10.0f, DT_SCALE = 10.0f;
@@ -54,8 +54,17 @@ struct SurDev {
     const int32_t *nbr_ptr = nullptr, *nbr = nullptr;
     const float *inv_deg = nullptr;
     // per-node strengths per unit time (times dt: per step), N x 4:
-    // b_i / (m_i c_i), 2 sum_j w_ij / (m_i c_i), sum_j |K_ij| / (m_i c_i), 0
+    // b_i / (m_i c_i), 2 sum_j w_ij / (m_i c_i), sum_j |K_ij| / (m_i c_i),
+    // and the projection weight m_i c_i / sum over the node's scenario (0 at fixed nodes)
     const float *coef = nullptr;
+    // energy-neutral correction: per node its scenario; node segments of one
+    // scenario each (the context's), and the segments of every scenario (CSR)
+    const int32_t *scen = nullptr;
+    const int32_t *seg_begin = nullptr;
+    int64_t n_seg = 0, n_scen = 1;
+    const int32_t *scen_seg_ptr = nullptr, *scen_seg = nullptr;
+    double *seg_part = nullptr;           // slots x n_seg
+    double *scen_sum = nullptr;           // slots x n_scen
     const uint32_t *flags = nullptr;      // N: material | flags (shared with the context)
     const void *mats = nullptr;           // MatDev table of the context
     // parameters
@@ -82,7 +91,7 @@ struct SurDev {
     int64_t n_partial_blocks = 0;
     double *loss_part = nullptr;          // per workgroup loss partials
     // jumps of the solver state
-    double *H0 = nullptr, *H1 = nullptr;  // N: the two explicit states a jump starts from
+    double *H0 = nullptr, *H1 = nullptr, *H2 = nullptr;  // N: the three explicit states a jump starts from
     int32_t *check = nullptr;             // per workgroup: nodes whose fraction solid fell
 };
 
@@ -91,8 +100,8 @@ constexpr int GRAD_ROWS = 2048;
 
 // features, extrapolated base, scale and (Ht != null) targets of `slots`
 // states: slot q is sample idx[q] (q if idx is null) at offset sample * stride
-hipError_t features(const SurDev &s, const void *H0, const void *H1, int h_is_double, const float *Ht,
-                    int64_t stride, const int32_t *idx, int64_t slots, hipStream_t st);
+hipError_t features(const SurDev &s, const void *H0, const void *H1, const void *H2, int h_is_double,
+                    const float *Ht, int64_t stride, const int32_t *idx, int64_t slots, hipStream_t st);
 hipError_t forward(const SurDev &s, int64_t rows, hipStream_t st);
 hipError_t loss_and_dy(const SurDev &s, int64_t rows, hipStream_t st);      // writes loss partials, dH of the output
 hipError_t backward(const SurDev &s, int64_t rows, hipStream_t st);
@@ -105,10 +114,10 @@ hipError_t state_to_f64(const Dev &d, double *out, hipStream_t st);
 hipError_t state_to_f32(const Dev &d, float *out, hipStream_t st);
 // write H = base + scale * y (one state slot) into the solver state with its T
 // and fraction solid; counts per workgroup the nodes whose fraction solid
-// fell by more than fs_tol below that of s.H1
+// fell by more than fs_tol below that of s.H2
 hipError_t write_jump(const SurDev &s, const Dev &d, int parity, float fs_tol, hipStream_t st);
-// put the state back to s.H1
-hipError_t restore_h1(const SurDev &s, const Dev &d, int parity, hipStream_t st);
+// put the state back to s.H2
+hipError_t restore_h2(const SurDev &s, const Dev &d, int parity, hipStream_t st);
 inline int64_t check_blocks(int64_t N) { return (N + 255) / 256; }
 
 }  // namespace sur

@@ -27,7 +27,7 @@ def chill(orc):
     dt = 0.9 * orc.stable_dt(p)
     H = {0: orc.initial_H(p)}
     at = 0
-    for n in (32, 33, 48, 160, 161, 176):
+    for n in (32, 33, 34, 48, 160, 161, 162, 176):
         H[n], _, _ = orc.run(p, dt, n - at, H=H[at])
         at = n
     H = {k: v.astype(np.float32) for k, v in H.items()}      # the GPU takes float32 states
@@ -68,8 +68,9 @@ def ref_params(seed=7):
 
 def test_features_match_the_oracle(chill, gpu):
     H = chill["H"]
-    X = gpu["sur"].features(gpu["dev"](H[32]), gpu["dev"](H[33]))[gpu["perm"]]
-    Xr = S.features(chill["p"], H[32].astype(np.float64), H[33].astype(np.float64), chill["dt"], strengths=chill["st"])
+    X = gpu["sur"].features(gpu["dev"](H[32]), gpu["dev"](H[33]), gpu["dev"](H[34]))[gpu["perm"]]
+    Xr = S.features(chill["p"], H[32].astype(np.float64), H[33].astype(np.float64), H[34].astype(np.float64),
+                    chill["dt"], strengths=chill["st"])
     # BF16 keeps 8 significant bits: relative error <= 2^-9 after round-to-nearest
     err = np.abs(X - Xr)
     assert np.all(err <= 2.0 ** -8 * np.abs(Xr) + 1e-30), float(np.max(err / (np.abs(Xr) + 1e-30)))
@@ -77,17 +78,19 @@ def test_features_match_the_oracle(chill, gpu):
     assert np.all(Xr[:, 6] <= 0) and np.any(Xr[:, 6] < 0)   # the cube only cools
 
 
-def _ref_loss_grad(chill, vparams, triples, loss_kind="H"):
-    """Mean over the states of the FP64 reference loss and gradient."""
+def _ref_loss_grad(chill, vparams, triples, loss_kind="H", bf16=False):
+    """Mean over the states of the reference loss and gradient (FP64, or with the
+    kernels' BF16 rounding points)."""
     p = chill["p"]
     ptr, col = S.graph_mean_operator(p["conn"], p["xyz"].shape[0])
     loss, grad = 0.0, None
-    for h0, h1, ht in triples:
-        h0, h1, ht = (a.astype(np.float64) for a in (h0, h1, ht))
-        X = S.features(p, h0, h1, chill["dt"], strengths=chill["st"])
-        base, t, _ = S.base_and_target(p, h0, h1, ht)
+    for h0, h1, h2, ht in triples:
+        h0, h1, h2, ht = (a.astype(np.float64) for a in (h0, h1, h2, ht))
+        X = S.features(p, h0, h1, h2, chill["dt"], strengths=chill["st"])
+        base, t, _ = S.base_and_target(p, h0, h1, h2, ht)
         f = t if loss_kind == "H" else S.t_loss(p, base, ht)
-        l, g, _ = S.loss_and_grad(vparams, X, f, ptr, col, LAYERS)
+        l, g, _ = S.loss_and_grad(vparams, X, f, ptr, col, LAYERS, bf16=bf16,
+                                  proj_w=S.projection_weights(p, chill["st"]))
         gv = S.flatten_params(g, LAYERS)
         loss += l / len(triples)
         grad = gv / len(triples) if grad is None else grad + gv / len(triples)
@@ -97,7 +100,7 @@ def _ref_loss_grad(chill, vparams, triples, loss_kind="H"):
 def _blocks():
     """(name, slice) of every parameter block in the flat vector."""
     out, o = [], 0
-    for name, n in [("W_in", 8 * 64), ("b_in", 64)] + sum([[("W%d" % l, 128 * 64), ("b%d" % l, 64)]
+    for name, n in [("W_in", 9 * 64), ("b_in", 64)] + sum([[("W%d" % l, 128 * 64), ("b%d" % l, 64)]
                                                           for l in range(LAYERS)], []) + [("w_out", 64), ("b_out", 1)]:
         out.append((name, slice(o, o + n)))
         o += n
@@ -107,36 +110,49 @@ def _blocks():
 @pytest.mark.parametrize("slots,loss_kind", [(1, "H"), (2, "H"), (2, "T")])
 def test_loss_and_gradients_match_the_fp64_reference(chill, gpu, slots, loss_kind):
     H = chill["H"]
-    triples = [(H[32], H[33], H[48]), (H[160], H[161], H[176])][:slots]
+    triples = [(H[32], H[33], H[34], H[48]), (H[160], H[161], H[162], H[176])][:slots]
     v32, vp = ref_params()
     sur = gpu["sur"] if loss_kind == "H" else gpu["sur_t"]
     sur.set_params(v32)
     H0 = gpu["dev"](*[t[0] for t in triples])
     H1 = gpu["dev"](*[t[1] for t in triples])
-    Ht = gpu["dev"](*[t[2] for t in triples])
-    loss, g = sur.loss_grad(H0, H1, Ht, stride=gpu["solver"].n_nodes, slots=slots)
+    H2 = gpu["dev"](*[t[2] for t in triples])
+    Ht = gpu["dev"](*[t[3] for t in triples])
+    loss, g = sur.loss_grad(H0, H1, H2, Ht, stride=gpu["solver"].n_nodes, slots=slots)
     loss_r, g_r = _ref_loss_grad(chill, vp, triples, loss_kind)
-    print("loss gpu %.6e ref %.6e" % (loss, loss_r))
-    assert loss == pytest.approx(loss_r, rel=2e-2)
-    # BF16 operands with FP32 accumulation: every block within 5% (relative L2)
+    loss_b, g_b = _ref_loss_grad(chill, vp, triples, loss_kind, bf16=True)
+    print("loss gpu %.6e ref %.6e ref(bf16) %.6e" % (loss, loss_r, loss_b))
+    assert loss == pytest.approx(loss_b, rel=1e-3)
+    assert loss == pytest.approx(loss_r, rel=0.1)
+    # against the reference with the same BF16 rounding points: only the FP32
+    # summation order differs; against exact FP64: the BF16 rounding itself,
+    # amplified by cancellation in the sums of the deepest (encoder) gradients
+    gnorm = np.linalg.norm(g_r)
     for name, sl in _blocks():
-        rel = np.linalg.norm(g[sl] - g_r[sl]) / max(np.linalg.norm(g_r[sl]), 1e-30)
-        print("%-6s |g| %.3e  rel err %.2e" % (name, np.linalg.norm(g_r[sl]), rel))
-        assert rel <= 5e-2, name
-    cos = float(np.dot(g, g_r) / (np.linalg.norm(g) * np.linalg.norm(g_r)))
-    assert cos >= 0.998
+        if name == "b_out":
+            # the energy-neutral projection removes any constant output: zero gradient
+            assert np.all(np.abs(g[sl]) <= 1e-6 * gnorm) and np.all(np.abs(g_r[sl]) <= 1e-12 * gnorm)
+            continue
+        nr = np.linalg.norm(g_r[sl])
+        rel_b = np.linalg.norm(g[sl] - g_b[sl]) / nr
+        rel = np.linalg.norm(g[sl] - g_r[sl]) / nr
+        print("%-6s |g| %.3e  vs bf16 ref %.2e  vs fp64 ref %.2e" % (name, nr, rel_b, rel))
+        assert rel_b <= 5e-3, name
+        assert rel <= 0.15, name
+    cos = float(np.dot(g, g_r) / (np.linalg.norm(g) * gnorm))
+    assert cos >= 0.99
 
 
-def test_zero_network_predicts_the_linear_extrapolation(chill, gpu):
+def test_zero_network_predicts_the_quadratic_extrapolation(chill, gpu):
     import torch
     H = chill["H"]
     sur = gpu["sur"]
     sur.set_params(np.zeros(sur.params().size, np.float32))
     out = torch.empty(gpu["solver"].n_nodes, dtype=torch.float64, device=gpu["solver"].device)
-    sur.predict(gpu["dev"](H[32]), gpu["dev"](H[33]), out)
+    sur.predict(gpu["dev"](H[32]), gpu["dev"](H[33]), gpu["dev"](H[34]), out)
     got = out.cpu().numpy()[gpu["perm"]]
-    h0, h1 = H[32].astype(np.float64), H[33].astype(np.float64)
-    assert np.allclose(got, h1 + 15.0 * (h1 - h0), rtol=1e-15, atol=0)
+    h0, h1, h2 = H[32].astype(np.float64), H[33].astype(np.float64), H[34].astype(np.float64)
+    assert np.allclose(got, h2 + 14.0 * (h2 - h1) + 105.0 * ((h2 - h1) - (h1 - h0)), rtol=1e-15, atol=0)
 
 
 def test_parameters_round_trip_and_errors(gpu):
@@ -151,15 +167,21 @@ def test_parameters_round_trip_and_errors(gpu):
         sur.set_params(bad)
     with pytest.raises(cf.FemError):
         sur.set_params(v[:-1])
-    z = gpu["dev"](np.zeros(gpu["solver"].n_nodes, np.float32))
+    zero = np.zeros(gpu["solver"].n_nodes, np.float32)
+    z = gpu["dev"](zero, zero, zero)
     with pytest.raises(cf.FemError):           # 3 states exceed max_samples = 2
-        sur.loss_grad(z, z, z, slots=3)
+        sur.loss_grad(z, z, z, z, slots=3)
+    with pytest.raises(ValueError):            # the tensors hold 3 states, not 4
+        sur.loss_grad(z, z, z, z, slots=4)
 
 
 # ------------------------------------------------------------------ gates and fallback
-def _const_net(sur, b_out):
+def _anti_diffusive_net(sur, gain):
+    """y_i = gain (T_i - 25) / 700 through one hidden unit; the energy-neutral projection
+    then leaves gain (T_i - mean T) / 700: hot nodes heat up, cold ones cool down."""
     v = np.zeros(sur.params().size, np.float32)
-    v[-1] = b_out                               # y = b_out at every node
+    v[0] = 1.0                                  # W_in[feature 0][unit 0]
+    v[-65] = gain                               # w_out[0]
     sur.set_params(v)
 
 
@@ -169,10 +191,10 @@ def test_rejected_jumps_reproduce_the_plain_run_bitwise(orc):
     dt = 0.9 * orc.stable_dt(p)
     a = cf.Solver(p, precision=cf.FEM_PREC_FP32_KAHAN)
     sur = cf.Surrogate(a, layers=LAYERS)
-    _const_net(sur, 50.0)                       # +500 K of sensible heat: fails the energy gate
-    rep = a.advance(dt, 160, sur, until_solid=False)
+    # no energy residual is that small: every jump falls back to plain steps
+    rep = a.advance(dt, 160, sur, until_solid=False, energy_tol=1e-300)
     assert rep["jumps_accepted"] == 0 and rep["jumps_rejected"] == 10
-    assert rep["steps"] == 160 and rep["plain_steps"] == 160
+    assert rep["steps"] == 160 and rep["plain_steps"] == 160 and rep["rejected_energy"] + rep["rejected_fs"] == 10
     b = cf.Solver(p, precision=cf.FEM_PREC_FP32_KAHAN)
     b.step(dt, 160)
     assert np.array_equal(a.H(), b.H()) and np.array_equal(a.T(), b.T()) and np.array_equal(a.fs(), b.fs())
@@ -193,13 +215,12 @@ def test_fraction_solid_gate(orc):
     assert np.any((fs > 0) & (fs < 1))          # a mushy zone exists
     ck = cf.fem_read_state(s.ctx)
     sur = cf.Surrogate(s, layers=LAYERS)
-    _const_net(sur, 10.0)                       # +100 K beyond the extrapolation: re-melts the mushy zone
+    _anti_diffusive_net(sur, 1000.0)            # re-melts the hotter part of the mushy zone
     rep = s.advance(dt, 64, sur, until_solid=False, energy_tol=1e9, fs_tol=1e-6)
-    assert rep["jumps_accepted"] == 0 and rep["jumps_rejected"] == 4
+    assert rep["jumps_accepted"] == 0 and rep["jumps_rejected"] == 4 and rep["rejected_fs"] == 4
     cf.fem_write_state(s.ctx, ck)
     rep = s.advance(dt, 64, sur, until_solid=False, energy_tol=1e9, fs_tol=1.0)
-    assert rep["jumps_accepted"] == 4 and rep["plain_steps"] == 4
-    # the kept jumps carry their extrapolated inflow into the energy budget
+    assert rep["jumps_accepted"] == 4 and rep["plain_steps"] == 8
     e = s.energy()
     assert e["steps"] == 664 and e["time"] == pytest.approx(664 * dt, rel=1e-12)
     sur.close()

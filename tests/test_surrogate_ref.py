@@ -34,10 +34,16 @@ def test_mean_operator_and_transpose():
     assert np.allclose(S.apply_mean(ptr, col, ones), 1.0)
 
 
-@pytest.mark.parametrize("layers", [1, 3])
-def test_gradients_match_central_differences(layers):
+@pytest.mark.parametrize("layers,project", [(1, False), (3, False), (3, True)])
+def test_gradients_match_central_differences(layers, project):
     params, X, t, ptr, col, layers = small_case(layers=layers)
-    loss, g, _ = S.loss_and_grad(params, X, t, ptr, col, layers)
+    w = None
+    if project:
+        w = np.random.default_rng(9).uniform(0.5, 1.5, t.size)
+        w /= w.sum()
+    loss, g, y = S.loss_and_grad(params, X, t, ptr, col, layers, proj_w=w)
+    if project:
+        assert abs(np.dot(w, y)) <= 1e-14 * np.abs(y).max()
     rng = np.random.default_rng(3)
     eps = 1e-6
     for name, val in params.items():
@@ -45,9 +51,9 @@ def test_gradients_match_central_differences(layers):
         for ix in idx:
             old = val[ix]
             val[ix] = old + eps
-            lp, _, _ = S.loss_and_grad(params, X, t, ptr, col, layers)
+            lp, _, _ = S.loss_and_grad(params, X, t, ptr, col, layers, proj_w=w)
             val[ix] = old - eps
-            lm, _, _ = S.loss_and_grad(params, X, t, ptr, col, layers)
+            lm, _, _ = S.loss_and_grad(params, X, t, ptr, col, layers, proj_w=w)
             val[ix] = old
             fd = (lp - lm) / (2 * eps)
             assert g[name][ix] == pytest.approx(fd, rel=1e-5, abs=1e-9), (name, ix)
@@ -56,7 +62,7 @@ def test_gradients_match_central_differences(layers):
 def test_parameter_vector_layout():
     p = S.init_params(64, 3, 0)
     v = S.flatten_params(p, 3)
-    assert v.size == 8 * 64 + 64 + 3 * (128 * 64 + 64) + 64 + 1
+    assert v.size == 9 * 64 + 64 + 3 * (128 * 64 + 64) + 64 + 1
     q = S.unflatten_params(v, 64, 3)
     for k in p:
         assert np.array_equal(p[k], q[k])
@@ -75,7 +81,7 @@ def test_conduction_strength_of_an_interior_hex_node():
     interior = np.all((xyz > 1e-9) & (xyz < L - 1e-9), axis=1)
     dt = 0.1
     H = np.full(xyz.shape[0], 900.0 * 700.0)
-    X = S.features(p, H, H, dt, strengths=st)
+    X = S.features(p, H, H, H, dt, strengths=st)
     assert np.allclose(X[interior, 5], 16.0 / 3.0 * k * dt / (rho * c * h * h), rtol=1e-12)
     assert np.allclose(st["kabs"][interior], 16.0 / 3.0 * k * h, rtol=1e-12)
     # a corner node sits in one element: sum_j |K_ij| = kh (1/3 + 4/12)
@@ -96,7 +102,7 @@ def test_robin_strength_on_the_chill_face():
     face = np.isclose(xyz[:, 0], 0.0) & np.all((xyz[:, 1:] > 1e-9) & (xyz[:, 1:] < L - 1e-9), axis=1)
     dt = 0.2
     H = np.full(xyz.shape[0], 900.0 * 700.0)
-    X = S.features(p, H, H, dt, strengths=st)
+    X = S.features(p, H, H, H, dt, strengths=st)
     assert np.allclose(X[face, 3], 2.0 * hc * dt / (rho * c * h), rtol=1e-12)
     assert np.all(X[~np.isclose(xyz[:, 0], 0.0), 3] == 0)
 
@@ -117,15 +123,23 @@ def test_temperature_and_rate_features():
     mat = configs.ALLOY
     c, Ts, Tl, L = mat[2], mat[3], mat[4], mat[5]
     N = p["xyz"].shape[0]
-    H1 = np.full(N, c * Ts + 0.25 * L + 0.25 * c * (Tl - Ts))   # a quarter of the way through the mushy zone
-    H0 = H1 + 160.0
-    X = S.features(p, H0, H1, 0.1, horizon=16)
+    H2 = np.full(N, c * Ts + 0.25 * L + 0.25 * c * (Tl - Ts))   # a quarter of the way through the mushy zone
+    H1 = H2 + 160.0
+    H0 = H1 + 170.0                                                # the cooling slows down by 10 J/kg per step
+    X = S.features(p, H0, H1, H2, 0.1, horizon=16)
     assert np.allclose(X[:, 0], (Ts + 0.25 * (Tl - Ts) - S.T_REF) / S.T_SCALE, rtol=1e-12)
     assert np.allclose(X[:, 1], 0.75, rtol=1e-12)
-    assert np.all(X[:, 2] == 1) and np.all(X[:, 7] == 1)
+    assert np.all(X[:, 2] == 1) and np.all(X[:, 8] == 1)
     assert np.allclose(X[:, 6], 16 * (-160.0) / (c * S.T_SCALE), rtol=1e-12)
-    base, t, cc = S.base_and_target(p, H0, H1, H1, horizon=16)
-    assert np.allclose(base, H1 - 15 * 160.0) and np.allclose(t * cc * S.DH_SCALE, 15 * 160.0)
+    assert np.allclose(X[:, 7], 128 * 10.0 / (c * S.T_SCALE), rtol=1e-12)
+    # the quadratic through (0, H0), (1, H1), (2, H2) at 16: Lagrange weights 105, -224, 120
+    base, t, cc = S.base_and_target(p, H0, H1, H2, H2, horizon=16)
+    assert np.allclose(base, 105 * H0 - 224 * H1 + 120 * H2, rtol=1e-13)
+    # an exactly quadratic history is reproduced: H(k) = A + B k + C k^2
+    k = np.arange(17.0)
+    hist = 6e5 - 150.0 * k + 2.5 * k ** 2
+    b2, _, _ = S.base_and_target(p, np.full(N, hist[0]), np.full(N, hist[1]), np.full(N, hist[2]), np.full(N, hist[16]))
+    assert np.allclose(b2, hist[16], rtol=1e-14)
 
 
 def test_temperature_loss_gradient_matches_central_differences(orc):
@@ -162,3 +176,30 @@ def test_temperature_loss_gradient_matches_central_differences(orc):
     T_pred, _ = orc.state_T(p, base + c * S.DH_SCALE * y)
     T_true, _ = orc.state_T(p, H_true)
     assert loss == pytest.approx(np.mean(((T_pred - T_true) / S.DT_SCALE) ** 2), rel=1e-12)
+
+
+def test_bf16_rounding_is_round_to_nearest_even():
+    x = np.array([1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, -(1.0 + 2.0 ** -7), 1.0 + 2.0 ** -8 + 2.0 ** -20, 3.0e38, 0.0])
+    got = S.bf16_round(x)
+    want = [1.0, 1.0 + 2.0 ** -6, -(1.0 + 2.0 ** -7), 1.0 + 2.0 ** -7, np.float32(3.0e38), 0.0]
+    assert got[:4].tolist() == want[:4] and got[5] == 0.0
+    assert abs(got[4] - 3.0e38) <= 3.0e38 * 2.0 ** -8
+
+
+def test_bf16_reference_stays_close_to_exact():
+    params, X, t, ptr, col, layers = small_case(width=64)
+    _, g, _ = S.loss_and_grad(params, X, t, ptr, col, layers)
+    _, gb, _ = S.loss_and_grad(params, X, t, ptr, col, layers, bf16=True)
+    for k in g:
+        assert np.linalg.norm(gb[k] - g[k]) <= 0.05 * np.linalg.norm(g[k]) + 1e-12, k
+
+
+def test_projection_weights_of_the_chill_cube():
+    # uniform hex grid, one material: m_i c_i is rho c h^3 times 1, 1/2, 1/4 or 1/8
+    p = configs.hex_cube(n=4, noise_amp=0.0, dirichlet_x0=25.0)
+    w = S.projection_weights(p)
+    assert w.sum() == pytest.approx(1.0, rel=1e-14)
+    assert np.all(w[p["dirichlet_nodes"]] == 0)
+    free = np.setdiff1d(np.arange(w.size), p["dirichlet_nodes"])
+    ratio = w[free] / w[free].max()
+    assert set(np.round(ratio, 12)) <= {1.0, 0.5, 0.25, 0.125}

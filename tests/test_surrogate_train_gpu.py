@@ -21,16 +21,15 @@ def _cf():
 
 
 def generate(solver, dt, max_snap):
-    """States H^{16k} and H^{16k+1} of every scenario until all are solid (or max_snap)."""
+    """States H^{16k}, H^{16k+1}, H^{16k+2} of every scenario until all are solid (or max_snap)."""
     import torch
     N = solver.n_nodes
-    S = torch.empty((max_snap + 1, 2, N), dtype=torch.float32, device=solver.device)
+    S = torch.empty((max_snap + 1, 3, N), dtype=torch.float32, device=solver.device)
     k = 0
     while k < max_snap:
-        solver.snapshot_H(S[k, 0])
-        solver.step_batch(dt, 1)
-        solver.snapshot_H(S[k, 1])
-        solver.step_batch(dt, 15)
+        for j in range(3):
+            solver.snapshot_H(S[k, j])
+            solver.step_batch(dt, 1 if j < 2 else 14)
         k += 1
         if all(r["n_liquid"] == 0 for r in solver.energy_scenarios()):
             break
@@ -46,7 +45,7 @@ def trained():
     dt = 0.9 * solver.stable_dt_scenarios()
     S, n = generate(solver, dt, MAX_SNAP)
     sur = cf.Surrogate(solver, layers=3, max_samples=1, train=True, seed=11)
-    losses = sur.train(S[0, 0], S[0, 1], S[1, 0], 2 * solver.n_nodes, n, batch=1, epochs=30,
+    losses = sur.train(S[0, 0], S[0, 1], S[0, 2], S[1, 0], 3 * solver.n_nodes, n, batch=1, epochs=30,
                        lr=2e-3, lr_final=2e-5, seed=3)
     params = sur.params()
     sur.close()
@@ -69,7 +68,7 @@ def test_trained_network_beats_linear_extrapolation_on_held_out_data(trained, or
     starts = [64, 480, 960, 1440]
     H, at = {0: orc.initial_H(p)}, 0
     for n0 in starts:
-        for n in (n0, n0 + 1, n0 + 16):
+        for n in (n0, n0 + 1, n0 + 2, n0 + 16):
             H[n], _, _ = orc.run(p, dt, n - at, H=H[at])
             at = n
     s = cf.Solver(p, precision=cf.FEM_PREC_FP32_KAHAN)
@@ -86,11 +85,12 @@ def test_trained_network_beats_linear_extrapolation_on_held_out_data(trained, or
 
     H0 = dev([H[n] for n in starts])
     H1 = dev([H[n + 1] for n in starts])
+    H2 = dev([H[n + 2] for n in starts])
     out = torch.empty(len(starts) * N, dtype=torch.float64, device=s.device)
     errs = {}
     for name, params in (("extrapolation", np.zeros_like(trained["params"])), ("trained", trained["params"])):
         sur.set_params(params)
-        sur.predict(H0, H1, out, stride=N, slots=len(starts))
+        sur.predict(H0, H1, H2, out, stride=N, slots=len(starts))
         got = out.cpu().numpy().reshape(len(starts), N)[:, perm]
         e = []
         for q, n0 in enumerate(starts):
