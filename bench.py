@@ -341,18 +341,18 @@ def bench_surrogate(args, log):
     res = []
     for seed in range(5500, 5500 + args.held_out):
         p = configs.config4_trajectory(seed)
-        plain = cf.Solver(p, precision=cf.FEM_PREC_FP32_KAHAN)
+        plain = cf.Solver(p, precision=cf.FEM_PREC_FP32_KAHAN, lds_bytes=cf.lds_for_nodes(256))
         dt1 = 0.9 * plain.stable_dt()
         plain.advance(dt1, 32, None, until_solid=False)           # warm-up: graph capture
         plain.close()
-        plain = cf.Solver(p, precision=cf.FEM_PREC_FP32_KAHAN)
+        plain = cf.Solver(p, precision=cf.FEM_PREC_FP32_KAHAN, lds_bytes=cf.lds_for_nodes(256))
         rp = plain.advance(dt1, 10 ** 6, None, until_solid=True)
-        acc = cf.Solver(p, precision=cf.FEM_PREC_FP32_KAHAN)
+        acc = cf.Solver(p, precision=cf.FEM_PREC_FP32_KAHAN, lds_bytes=cf.lds_for_nodes(256))
         sa = cf.Surrogate(acc, layers=3)
         sa.set_params(params)
         ra = acc.advance(dt1, 10 ** 6, sa, until_solid=True)
         if ra["steps"] <= rp["steps"]:
-            ref = cf.Solver(p, precision=cf.FEM_PREC_FP32_KAHAN)
+            ref = cf.Solver(p, precision=cf.FEM_PREC_FP32_KAHAN, lds_bytes=cf.lds_for_nodes(256))
             ref.step(dt1, ra["steps"])
             T_ref = ref.T()
             ref.close()

@@ -235,7 +235,9 @@ int fem_copy_kernel(fem_ctx *ctx, void *dst, const void *src, int64_t bytes, int
  * its fallback and judge).  From three consecutive explicit states H0 = H^n,
  * H1 = H^{n+1}, H2 = H^{n+2} it predicts, per node i, with m = horizon - 2,
  * r = H2 - H1 and a = (H2 - H1) - (H1 - H0),
- *   H^{n+horizon}_i = H2_i + m r_i + m (m + 1) / 2 a_i + 10 c_i y_i,
+ *   H^{n+horizon}_i = base_i + 10 c_i y_i,
+ * base = H2 + m r (linear extrapolation, the default) or
+ * base = H2 + m r + m (m + 1) / 2 a (quadratic; fem_sur_options.extrapolation),
  * y = output of a network of `layers` residual message-passing layers of
  * width 64 over the mesh graph (nodes sharing an element, mean aggregation):
  *   h_0 = relu(x W_in + b_in);  h_l = h_{l-1} + relu([h_{l-1}, mean_nbr h_{l-1}] W_l + b_l);
@@ -256,8 +258,11 @@ typedef struct fem_sur fem_sur;
 /* Training loss, a mean over all nodes of the states of a step:
  *   FEM_SUR_LOSS_H: (y - t)^2 with t = (Ht - base) / (10 c), the enthalpy error;
  *   FEM_SUR_LOSS_T: ((T(base + 10 c y) - T(Ht)) / 10 K)^2, the temperature error
- *   (gradient through the branch of T(H) the prediction lies on). */
-enum { FEM_SUR_LOSS_H = 0, FEM_SUR_LOSS_T = 1 };
+ *   (gradient through the branch of T(H) the prediction lies on);
+ *   FEM_SUR_LOSS_HUBER: the enthalpy error e = y - t with e^2 replaced by
+ *   0.1 (2|e| - 0.1) beyond |e| = 0.1 (1 K of sensible heat). */
+enum { FEM_SUR_LOSS_H = 0, FEM_SUR_LOSS_T = 1, FEM_SUR_LOSS_HUBER = 2 };
+enum { FEM_SUR_EXTRAP_LINEAR = 0, FEM_SUR_EXTRAP_QUADRATIC = 1 };
 
 typedef struct {
     int32_t width;         /* must be 64 */
@@ -266,7 +271,8 @@ typedef struct {
     int32_t max_samples;   /* states per forward / backward pass (rows = max_samples * n_nodes < 2^31) */
     int32_t train;         /* nonzero: size the training buffers too */
     int32_t loss;          /* FEM_SUR_LOSS_*: what the training loss measures */
-    int32_t reserved[6];   /* must be zero */
+    int32_t extrapolation; /* FEM_SUR_EXTRAP_*: the base the network corrects */
+    int32_t reserved[5];   /* must be zero */
     uint64_t seed;         /* initial parameters (He-normal, counter-based generator) */
 } fem_sur_options;
 

@@ -7,10 +7,10 @@ The surrogate jumps the enthalpy state `horizon` explicit steps ahead.  Given
 three consecutive plain states H0 = H^n, H1 = H^{n+1}, H2 = H^{n+2} it predicts,
 with m = horizon - 2, r = H2 - H1 and a = (H2 - H1) - (H1 - H0),
 
-    H^{n+horizon} ~ H2 + m r + m (m + 1) / 2 a + c_i * DH_SCALE * y_i,
+    H^{n+horizon} ~ base + c_i * DH_SCALE * y_i,   base = H2 + m r  [+ m (m + 1) / 2 a],
 
-the quadratic extrapolation in time through the three states, corrected by the
-network output y_i of node i.  Per-node input features (9):
+the linear (or quadratic) extrapolation in time, corrected by the network
+output y_i of node i.  Per-node input features (9):
 
     x0 = (T(H2) - T_REF) / T_SCALE          temperature
     x1 = fs(H2)                             fraction solid
@@ -118,13 +118,16 @@ def features(prob, H0, H1, H2, dt, horizon=16, strengths=None):
     return X
 
 
-def base_and_target(prob, H0, H1, H2, Ht, horizon=16):
-    """Quadratic extrapolation through H0, H1, H2 to step `horizon` and the target (Ht - base) / (c DH_SCALE)."""
+def base_and_target(prob, H0, H1, H2, Ht, horizon=16, quadratic=False):
+    """Extrapolation to step `horizon` (linear through H1, H2, or quadratic through H0, H1, H2)
+    and the target (Ht - base) / (c DH_SCALE)."""
     mats = np.asarray(prob["materials"], np.float64).reshape(-1, 6)
     c = mats[orc.node_material(orc.Problem(prob)), 2]
     H0, H1, H2, Ht = (np.asarray(a, np.float64) for a in (H0, H1, H2, Ht))
     m = horizon - 2
-    base = H2 + m * (H2 - H1) + 0.5 * m * (m + 1) * ((H2 - H1) - (H1 - H0))
+    base = H2 + m * (H2 - H1)
+    if quadratic:
+        base = base + 0.5 * m * (m + 1) * ((H2 - H1) - (H1 - H0))
     return base, (Ht - base) / (c * DH_SCALE), c
 
 
@@ -251,6 +254,19 @@ def h_loss(t):
     """Enthalpy loss mean (y - t)^2 and its derivative in y."""
     def f(y):
         return float(np.mean((y - t) ** 2)), 2.0 * (y - t) / y.size
+    return f
+
+
+HUBER_DELTA = 0.1
+
+
+def huber_loss(t, delta=HUBER_DELTA):
+    """mean of e^2 (|e| <= delta) or delta (2|e| - delta), e = y - t, and its derivative."""
+    def f(y):
+        e = y - t
+        a = np.abs(e)
+        L = np.where(a <= delta, e * e, delta * (2.0 * a - delta))
+        return float(np.mean(L)), 2.0 * np.clip(e, -delta, delta) / y.size
     return f
 
 

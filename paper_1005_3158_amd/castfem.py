@@ -81,7 +81,8 @@ class fem_kernel_times(C.Structure):
 
 class fem_sur_options(C.Structure):
     _fields_ = [("width", C.c_int32), ("layers", C.c_int32), ("horizon", C.c_int32), ("max_samples", C.c_int32),
-                ("train", C.c_int32), ("loss", C.c_int32), ("reserved", C.c_int32 * 6), ("seed", C.c_uint64)]
+                ("train", C.c_int32), ("loss", C.c_int32), ("extrapolation", C.c_int32), ("reserved", C.c_int32 * 5),
+                ("seed", C.c_uint64)]
 
 
 class fem_advance_report(C.Structure):
@@ -319,13 +320,15 @@ def fem_copy_kernel(ctx, dst_ptr, src_ptr, nbytes, repeats):
 
 
 # ------------------------------------------------------------ surrogate
-FEM_SUR_LOSS_H, FEM_SUR_LOSS_T = 0, 1
+FEM_SUR_LOSS_H, FEM_SUR_LOSS_T, FEM_SUR_LOSS_HUBER = 0, 1, 2
+FEM_SUR_EXTRAP_LINEAR, FEM_SUR_EXTRAP_QUADRATIC = 0, 1
 
 
-def fem_sur_create(ctx, width=64, layers=3, horizon=16, max_samples=1, train=False, seed=0, loss=FEM_SUR_LOSS_H):
+def fem_sur_create(ctx, width=64, layers=3, horizon=16, max_samples=1, train=False, seed=0, loss=FEM_SUR_LOSS_H,
+                   extrapolation=FEM_SUR_EXTRAP_LINEAR):
     o = fem_sur_options()
     o.width, o.layers, o.horizon, o.max_samples, o.train, o.seed = width, layers, horizon, max_samples, int(train), seed
-    o.loss = loss
+    o.loss, o.extrapolation = loss, extrapolation
     s = C.c_void_p()
     _call("fem_sur_create", C.byref(s), ctx, C.byref(o))
     return s
@@ -528,11 +531,12 @@ class Solver:
 class Surrogate:
     """The learned surrogate of a Solver; torch allocates its device buffers."""
 
-    def __init__(self, solver, layers=3, horizon=16, max_samples=1, train=False, seed=0, loss=FEM_SUR_LOSS_H):
+    def __init__(self, solver, layers=3, horizon=16, max_samples=1, train=False, seed=0, loss=FEM_SUR_LOSS_H,
+                 extrapolation=FEM_SUR_EXTRAP_LINEAR):
         self.solver = solver
         self.torch = solver.torch
         self.n_nodes = solver.n_nodes
-        self.sur = fem_sur_create(solver.ctx, 64, layers, horizon, max_samples, train, seed, loss)
+        self.sur = fem_sur_create(solver.ctx, 64, layers, horizon, max_samples, train, seed, loss, extrapolation)
         self.buffers, ptrs = _allocate(self.torch, solver.device, fem_sur_query_buffers(self.sur))
         fem_sur_bind_buffers(self.sur, ptrs)
 

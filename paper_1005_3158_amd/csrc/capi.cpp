@@ -422,9 +422,11 @@ int fem_finalize(fem_ctx *ctx, fem_prep_report *rep) {
         const size_t per = lds_per_node(ctx->opt.precision);
         const int thr = ctx->opt.threads ? ctx->opt.threads : 256;
         if (ctx->opt.scatter == FEM_SCATTER_LDS_BLOCKED && ctx->opt.block_elems == 0 && ctx->opt.lds_bytes == 0) {
-            // autotune over block node sets (the paper's timed search over the block count)
-            for (int64_t nodes : {512, 640, 768, 1024, 1536}) {
+            // autotune over block node sets (the paper's timed search over the block count);
+            // small meshes also try small blocks, so that more compute units take part
+            for (int64_t nodes : {128, 256, 512, 640, 768, 1024, 1536}) {
                 if ((size_t)nodes * per > MAX_BLOCK_LDS) continue;
+                if (nodes < 512 && ctx->prob.N > 512 * 512) continue;
                 Candidate c;
                 c.o.ordering = ctx->opt.ordering;
                 c.o.scatter = ctx->opt.scatter;

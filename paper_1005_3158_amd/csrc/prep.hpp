@@ -85,7 +85,7 @@ struct Layout {
     int64_t block_elems = 0;
 };
 
-constexpr int SEG_NODES = 4096;
+constexpr int SEG_NODES = 1024;
 
 struct PrepOptions {
     int ordering = FEM_ORDER_HILBERT;

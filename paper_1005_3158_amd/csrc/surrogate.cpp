@@ -219,6 +219,7 @@ void fill_surdev(fem_sur *s) {
     d.layers = s->opt.layers;
     d.horizon = s->opt.horizon;
     d.loss_mode = s->opt.loss;
+    d.quadratic = s->opt.extrapolation == FEM_SUR_EXTRAP_QUADRATIC ? 1 : 0;
     d.pl = s->pl;
     d.nbr_ptr = (const int32_t *)s->ptr[S_NBR_PTR];
     d.nbr = (const int32_t *)s->ptr[S_NBR];
@@ -295,7 +296,7 @@ void pass(fem_sur *s, const float *H0, const float *H1, const float *H2, const f
     hipStream_t st = s->ctx->stream;
     const int64_t R = slots * s->N;
     HIPCHECK(features(s->d, H0, H1, H2, 0, Ht, stride, idx, slots, st));
-    HIPCHECK(forward(s->d, R, st));
+    HIPCHECK(forward(s->d, R, 1, 1, st));
     HIPCHECK(loss_and_dy(s->d, R, st));
     HIPCHECK(backward(s->d, R, st));
 }
@@ -322,7 +323,7 @@ void enqueue_jump(fem_sur *s, int p, float fs_tol) {
     HIPCHECK(enqueue_step(c->dev, p ^ 1, st, nullptr));
     HIPCHECK(state_to_f64(c->dev, s->d.H2, st));
     HIPCHECK(features(s->d, s->d.H0, s->d.H1, s->d.H2, 1, nullptr, s->N, nullptr, 1, st));
-    HIPCHECK(forward(s->d, s->N, st));
+    HIPCHECK(forward(s->d, s->N, 0, 0, st));
     HIPCHECK(write_jump(s->d, c->dev, p, fs_tol, st));
     HIPCHECK(enqueue_state_diag(c->dev, p, st));
 }
@@ -388,7 +389,10 @@ int fem_sur_create(fem_sur **out, fem_ctx *ctx, const fem_sur_options *o) {
         if (o->layers < 1 || o->layers > MAX_LAYERS) throw PrepError{FEM_E_INVALID_ARG, "layers must be 1..4"};
         if (o->horizon < 3) throw PrepError{FEM_E_INVALID_ARG, "horizon must be >= 3"};
         if (o->max_samples < 1 || o->max_samples > 65535) throw PrepError{FEM_E_INVALID_ARG, "max_samples must be 1..65535"};
-        if (o->loss != FEM_SUR_LOSS_H && o->loss != FEM_SUR_LOSS_T) throw PrepError{FEM_E_INVALID_ARG, "unknown loss"};
+        if (o->loss != FEM_SUR_LOSS_H && o->loss != FEM_SUR_LOSS_T && o->loss != FEM_SUR_LOSS_HUBER)
+            throw PrepError{FEM_E_INVALID_ARG, "unknown loss"};
+        if (o->extrapolation != FEM_SUR_EXTRAP_LINEAR && o->extrapolation != FEM_SUR_EXTRAP_QUADRATIC)
+            throw PrepError{FEM_E_INVALID_ARG, "unknown extrapolation"};
         for (int32_t r : o->reserved)
             if (r) throw PrepError{FEM_E_INVALID_ARG, "reserved fields must be zero"};
         if ((int64_t)o->max_samples * ctx->L().N > (int64_t)1 << 31)
@@ -582,7 +586,7 @@ int fem_sur_predict(fem_sur *s, const float *H0, const float *H1, const float *H
         hipStream_t st = s->ctx->stream;
         const int64_t R = slots * s->N;
         HIPCHECK(features(s->d, H0, H1, H2, 0, nullptr, stride, nullptr, slots, st));
-        HIPCHECK(forward(s->d, R, st));
+        HIPCHECK(forward(s->d, R, 0, 1, st));
         HIPCHECK(apply(s->d, R, H_out, st));
         HIPCHECK(hipStreamSynchronize(st));
     });

@@ -83,8 +83,8 @@ __global__ __launch_bounds__(256) void k_features(SurDev s, const HT *H0, const 
     uint4 *out = (uint4 *)(s.X + r * KIN);
     out[0] = make_uint4(w[0], w[1], w[2], w[3]);
     out[1] = make_uint4(w[4], w[5], w[6], w[7]);
-    // quadratic extrapolation through the three states
-    s.base[r] = h2 + m * rate + 0.5 * m * (m + 1.0) * acc;
+    // linear extrapolation through H1, H2, or quadratic through H0, H1, H2
+    s.base[r] = s.quadratic ? h2 + m * rate + 0.5 * m * (m + 1.0) * acc : h2 + m * rate;
     s.scale[r] = (float)(c * DH_SCALE);
     if (Ht) {
         if (s.loss_mode == LOSS_T) {
@@ -92,7 +92,7 @@ __global__ __launch_bounds__(256) void k_features(SurDev s, const HT *H0, const 
             t_of_h(M, (double)Ht[at], Tt, fst);
             s.target[r] = (float)Tt;
         } else {
-            s.target[r] = (float)(((double)Ht[at] - s.base[r]) / (c * DH_SCALE));
+            s.target[r] = (float)(((double)Ht[at] - s.base[r]) / (c * DH_SCALE));   // LOSS_H, LOSS_HUBER
         }
     }
 }
@@ -133,7 +133,7 @@ __global__ __launch_bounds__(256) void k_gemm(const bf16 *__restrict__ A, int ld
                 Cout[row * ldc + col] = v;
             } else {
                 const float z = v + bias[col];
-                Zout[row * NOUT + col] = f2bf(z);
+                if (Zout) Zout[row * NOUT + col] = f2bf(z);
                 const float act = z > 0.f ? z : 0.f;
                 const float h = MODE == 0 ? act : bf2f(Hprev[row * ldhp + col]) + act;
                 Hout[row * ldh + col] = f2bf(h);
@@ -214,26 +214,107 @@ __global__ void k_reduce(const float *__restrict__ P, int64_t nblk, int64_t per,
 }
 
 // ---------------------------------------------------------------- graph
-// U[r][WIDTH + c] = mean over neighbours j of U[j][c], rows of one sample at a time
-__global__ __launch_bounds__(256) void k_agg(SurDev s, bf16 *U, int64_t R) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t r = t >> 3;
-    const int ch = (int)(t & 7);
-    if (r >= R) return;
-    const int64_t i = r % s.N, base = r - i;
-    float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int32_t q = s.nbr_ptr[i]; q < s.nbr_ptr[i + 1]; ++q) {
-        const uint4 v = *(const uint4 *)(U + (base + s.nbr[q]) * 2 * WIDTH + ch * 8);
-        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-        for (int k = 0; k < 4; ++k) {
-            acc[2 * k] += bf2f((bf16)(w[k] & 0xffff));
-            acc[2 * k + 1] += bf2f((bf16)(w[k] >> 16));
+// One message-passing layer for 64 rows per workgroup (16 per wavefront):
+// h_{l-1} of the rows and the mean of h_{l-1} over their mesh neighbours are
+// put side by side in LDS, then [h, a] W_l runs on MFMA with the A operand read
+// from LDS.  Epilogue: z = . + b_l (kept in Z[l] when store), h_l = h_{l-1} +
+// relu(z) into U[l+1] (or H_last).  With store the mean is also written into
+// the second half of U[l] (the weight gradient reads it).
+__global__ __launch_bounds__(256) void k_layer(SurDev s, int l, int64_t R, int store) {
+    constexpr int LDU = 2 * WIDTH + 8;
+    __shared__ __align__(16) bf16 Ut[64][LDU];
+    __shared__ __align__(16) bf16 Wt[WIDTH][LDU];      // W_l^T, row n holds W_l[:, n]
+    const bf16 *__restrict__ U = s.U[l];
+    const int t = threadIdx.x;
+    const int64_t row0 = (int64_t)blockIdx.x * 64;
+    for (int v = t; v < WIDTH * (2 * WIDTH / 8); v += 256) {
+        const int n = v / (2 * WIDTH / 8), k8 = (v % (2 * WIDTH / 8)) * 8;
+        *(uint4 *)&Wt[n][k8] = *(const uint4 *)(s.wt[l] + n * 2 * WIDTH + k8);
+    }
+    // own rows: 64 x 64 BF16 as 512 16-byte words, and the neighbour means of 8 channels each
+    for (int v = t; v < 512; v += 256) {
+        const int rr = v >> 3, c8 = (v & 7) * 8;
+        const int64_t r = row0 + rr;
+        uint4 own = make_uint4(0, 0, 0, 0), mean = make_uint4(0, 0, 0, 0);
+        if (r < R) {
+            own = *(const uint4 *)(U + r * 2 * WIDTH + c8);
+            const int64_t i = r % s.N, base = r - i;
+            float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            const int32_t q0 = s.nbr_ptr[i], q1 = s.nbr_ptr[i + 1];
+            int32_t q = q0;
+            for (; q + 4 <= q1; q += 4) {
+                uint4 w[4];
+                for (int u = 0; u < 4; ++u) w[u] = *(const uint4 *)(U + (base + s.nbr[q + u]) * 2 * WIDTH + c8);
+                for (int u = 0; u < 4; ++u) {
+                    const uint32_t x[4] = {w[u].x, w[u].y, w[u].z, w[u].w};
+                    for (int k = 0; k < 4; ++k) {
+                        acc[2 * k] += bf2f((bf16)(x[k] & 0xffffu));
+                        acc[2 * k + 1] += bf2f((bf16)(x[k] >> 16));
+                    }
+                }
+            }
+            for (; q < q1; ++q) {
+                const uint4 w = *(const uint4 *)(U + (base + s.nbr[q]) * 2 * WIDTH + c8);
+                const uint32_t x[4] = {w.x, w.y, w.z, w.w};
+                for (int k = 0; k < 4; ++k) {
+                    acc[2 * k] += bf2f((bf16)(x[k] & 0xffffu));
+                    acc[2 * k + 1] += bf2f((bf16)(x[k] >> 16));
+                }
+            }
+            const float id = s.inv_deg[i];
+            uint32_t o[4];
+            for (int k = 0; k < 4; ++k)
+                o[k] = (uint32_t)f2bf(acc[2 * k] * id) | ((uint32_t)f2bf(acc[2 * k + 1] * id) << 16);
+            mean = make_uint4(o[0], o[1], o[2], o[3]);
+            if (store) *(uint4 *)(s.U[l] + r * 2 * WIDTH + WIDTH + c8) = mean;
+        }
+        *(uint4 *)&Ut[rr][c8] = own;
+        *(uint4 *)&Ut[rr][WIDTH + c8] = mean;
+    }
+    __syncthreads();
+    constexpr int NT = WIDTH / 16, K = 2 * WIDTH;
+    const int wave = t >> 6, lane = t & 63;
+    const int ar = lane & 15, kq = (lane >> 4) * 4;
+    f4 acc[NT];
+    for (int n = 0; n < NT; ++n) acc[n] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        const s4 a = *(const s4 *)&Ut[wave * 16 + ar][k0 + kq];
+        for (int n = 0; n < NT; ++n) {
+            const s4 b = *(const s4 *)&Wt[n * 16 + ar][k0 + kq];
+            acc[n] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[n], 0, 0, 0);
         }
     }
-    const float id = s.inv_deg[i];
-    uint32_t o[4];
-    for (int k = 0; k < 4; ++k) o[k] = (uint32_t)f2bf(acc[2 * k] * id) | ((uint32_t)f2bf(acc[2 * k + 1] * id) << 16);
-    *(uint4 *)(U + r * 2 * WIDTH + WIDTH + ch * 8) = make_uint4(o[0], o[1], o[2], o[3]);
+    const float *bias = s.params + s.pl.b[l];
+    const bool last = l + 1 == s.layers;
+    bf16 *hout = last ? s.HL : s.U[l + 1];
+    const int ldh = last ? WIDTH : 2 * WIDTH;
+    const float *wo = s.params + s.pl.w_out;
+    float yp[4] = {0.f, 0.f, 0.f, 0.f};   // last layer: this lane's part of y for rows kq + j
+    for (int n = 0; n < NT; ++n) {
+        const int col = n * 16 + ar;
+        for (int j = 0; j < 4; ++j) {
+            const int rr = wave * 16 + kq + j;
+            const int64_t row = row0 + rr;
+            const float z = acc[n][j] + bias[col];
+            const bf16 hb = f2bf(bf2f(Ut[rr][col]) + (z > 0.f ? z : 0.f));
+            yp[j] += bf2f(hb) * wo[col];
+            if (row >= R) continue;
+            if (store) s.Z[l][row * WIDTH + col] = f2bf(z);
+            hout[row * ldh + col] = hb;
+        }
+    }
+    if (last) {
+        // y = h_L . w_out + b_out: sum over the 16 lanes that hold the same rows
+        for (int j = 0; j < 4; ++j)
+            for (int off = 8; off > 0; off >>= 1) yp[j] += __shfl_xor(yp[j], off, 16);
+        if (ar == 0) {
+            const float b_out = s.params[s.pl.b_out];
+            for (int j = 0; j < 4; ++j) {
+                const int64_t row = row0 + wave * 16 + kq + j;
+                if (row < R) s.y[row] = yp[j] + b_out;
+            }
+        }
+    }
 }
 
 // dH[j] += dU[j][:WIDTH] + sum over neighbours i of dU[i][WIDTH:] / deg_i  (transpose of the mean)
@@ -255,17 +336,6 @@ __global__ __launch_bounds__(256) void k_aggT(SurDev s, const float *dU, float *
 __global__ __launch_bounds__(256) void k_relu_back(const float *dH, const bf16 *Z, bf16 *dZ, int64_t n) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k < n) dZ[k] = bf2f(Z[k]) > 0.f ? f2bf(dH[k]) : (bf16)0;
-}
-
-// ---------------------------------------------------------------- output, loss
-__global__ __launch_bounds__(256) void k_out(SurDev s, int64_t R) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= R) return;
-    const float *w = s.params + s.pl.w_out;
-    float acc = s.params[s.pl.b_out];
-    const bf16 *h = s.HL + r * WIDTH;
-    for (int c = 0; c < WIDTH; ++c) acc += bf2f(h[c]) * w[c];
-    s.y[r] = acc;
 }
 
 // ---------------------------------------------------------------- energy-neutral correction
@@ -317,7 +387,8 @@ __global__ __launch_bounds__(256) void k_proj_bwd(SurDev s, int64_t R) {
 
 // per row: error e and dL/dy of the loss sum_r e_r^2 / R, with y the projected output.
 // LOSS_H: e = y - t.  LOSS_T: e = (T(base + scale y) - T_t) / DT_SCALE, with the
-// slope of the branch of T(H) the prediction lies on.
+// slope of the branch of T(H) the prediction lies on.  LOSS_HUBER: e = y - t,
+// e^2 replaced by delta (2|e| - delta) beyond |e| = delta.
 // Writes the per-workgroup loss partial and dL/dy (into y).
 __global__ __launch_bounds__(256) void k_loss(SurDev s, int64_t R) {
     __shared__ double part[4];
@@ -334,6 +405,10 @@ __global__ __launch_bounds__(256) void k_loss(SurDev s, int64_t R) {
             const double e = (Tp - (double)s.target[r]) / DT_SCALE;
             e2 = e * e;
             dy = (float)(2.0 * e / (double)R * dTdH * (double)s.scale[r] / DT_SCALE);
+        } else if (s.loss_mode == LOSS_HUBER) {
+            const float e = s.y[r] - s.target[r], a = fabsf(e);
+            e2 = a <= HUBER_DELTA ? (double)e * (double)e : (double)HUBER_DELTA * (2.0 * (double)a - (double)HUBER_DELTA);
+            dy = 2.f * fminf(fmaxf(e, -HUBER_DELTA), HUBER_DELTA) / (float)R;
         } else {
             const float e = s.y[r] - s.target[r];
             e2 = (double)e * (double)e;
@@ -442,7 +517,7 @@ __global__ __launch_bounds__(256) void k_write_jump(SurDev s, Dev d, int parity,
         const uint32_t f = d.flags[i];
         if (!(f & NODE_FIXED)) {
             const MatDev &M = d.mats[f & NODE_MAT_MASK];
-            const double Hn = s.base[i] + (double)s.scale[i] * (double)s.y[i];
+            const double Hn = s.base[i] + (double)s.scale[i] * ((double)s.y[i] - s.scen_sum[s.scen[i]]);
             set_node<R>(d, i, M, Hn, (R *)d.T + parity * d.N);
             if (M.latent) {
                 double T0, fs0, T1, fs1;
@@ -485,23 +560,17 @@ hipError_t features(const SurDev &s, const void *H0, const void *H1, const void 
     return hipGetLastError();
 }
 
-hipError_t forward(const SurDev &s, int64_t R, hipStream_t st) {
+hipError_t forward(const SurDev &s, int64_t R, int store, int project, hipStream_t st) {
     const unsigned g = grid_for(R, 64);
     // encoder into the first half of U_0
     hipLaunchKernelGGL((k_gemm<WIDTH, 0>), dim3(g), dim3(256), 0, st, s.X, KIN, KIN, s.wt_in,
-                       s.params + s.pl.b_in, R, s.Zin, (const bf16 *)nullptr, 0, s.U[0], 2 * WIDTH, (float *)nullptr, 0);
-    for (int l = 0; l < s.layers; ++l) {
-        hipLaunchKernelGGL(k_agg, dim3(grid_for(R * 8, 256)), dim3(256), 0, st, s, s.U[l], R);
-        bf16 *hout = l + 1 < s.layers ? s.U[l + 1] : s.HL;
-        const int ldh = l + 1 < s.layers ? 2 * WIDTH : WIDTH;
-        hipLaunchKernelGGL((k_gemm<WIDTH, 1>), dim3(g), dim3(256), 0, st, s.U[l], 2 * WIDTH, 2 * WIDTH, s.wt[l],
-                           s.params + s.pl.b[l], R, s.Z[l], s.U[l], 2 * WIDTH, hout, ldh, (float *)nullptr, 0);
-    }
-    hipLaunchKernelGGL(k_out, dim3(grid_for(R, 256)), dim3(256), 0, st, s, R);
+                       s.params + s.pl.b_in, R, store ? s.Zin : (bf16 *)nullptr, (const bf16 *)nullptr, 0, s.U[0],
+                       2 * WIDTH, (float *)nullptr, 0);
+    for (int l = 0; l < s.layers; ++l) hipLaunchKernelGGL(k_layer, dim3(g), dim3(256), 0, st, s, l, R, store);
     const int64_t slots = R / s.N;
     hipLaunchKernelGGL(k_seg_sum, dim3((unsigned)s.n_seg, (unsigned)slots), dim3(256), 0, st, s, (const float *)s.y, 1);
     hipLaunchKernelGGL(k_scen_sum, dim3(grid_for(slots * s.n_scen, 256)), dim3(256), 0, st, s, slots);
-    hipLaunchKernelGGL(k_proj_fwd, dim3(grid_for(R, 256)), dim3(256), 0, st, s, R);
+    if (project) hipLaunchKernelGGL(k_proj_fwd, dim3(grid_for(R, 256)), dim3(256), 0, st, s, R);
     return hipGetLastError();
 }
 

@@ -21,7 +21,8 @@ constexpr int NFEAT = 9;        // input features
 constexpr int KIN = 16;         // features padded to the MFMA K step
 constexpr int MAX_LAYERS = 4;
 constexpr float T_REF = 25.0f, T_SCALE = 700.0f, DH_SCALE = 10.0f, DT_SCALE = 10.0f;
-enum { LOSS_H = 0, LOSS_T = 1 };
+enum { LOSS_H = 0, LOSS_T = 1, LOSS_HUBER = 2 };
+constexpr float HUBER_DELTA = 0.1f;   // Huber loss: quadratic within 0.1 output units (1 K of sensible heat)
 
 typedef uint16_t bf16;
 
@@ -48,7 +49,8 @@ struct SurDev {
     int64_t N = 0;            // nodes of the mesh (device numbering of the context)
     int layers = 3;
     int horizon = 16;         // explicit steps per jump
-    int loss_mode = LOSS_H;   // LOSS_H: target (Ht - base) / (c DH_SCALE); LOSS_T: target T(Ht)
+    int loss_mode = LOSS_H;   // LOSS_H, LOSS_HUBER: target (Ht - base) / (c DH_SCALE); LOSS_T: target T(Ht)
+    int quadratic = 0;        // base: 0 linear through H1, H2; 1 quadratic through H0, H1, H2
     ParamLayout pl;
     // graph: mean over mesh neighbours
     const int32_t *nbr_ptr = nullptr, *nbr = nullptr;
@@ -102,7 +104,10 @@ constexpr int GRAD_ROWS = 2048;
 // states: slot q is sample idx[q] (q if idx is null) at offset sample * stride
 hipError_t features(const SurDev &s, const void *H0, const void *H1, const void *H2, int h_is_double,
                     const float *Ht, int64_t stride, const int32_t *idx, int64_t slots, hipStream_t st);
-hipError_t forward(const SurDev &s, int64_t rows, hipStream_t st);
+// store: keep what the backward pass needs (pre-activations, neighbour means);
+// project: apply the energy-neutral projection to y (otherwise only the
+// per-scenario sums are formed, for write_jump to subtract)
+hipError_t forward(const SurDev &s, int64_t rows, int store, int project, hipStream_t st);
 hipError_t loss_and_dy(const SurDev &s, int64_t rows, hipStream_t st);      // writes loss partials, dH of the output
 hipError_t backward(const SurDev &s, int64_t rows, hipStream_t st);
 hipError_t adam(const SurDev &s, float lr, float b1, float b2, float eps, int step, hipStream_t st);
@@ -112,9 +117,10 @@ hipError_t apply(const SurDev &s, int64_t rows, double *H_out, hipStream_t st); 
 // solver state <-> surrogate (d: the context's device layout, T buffer `parity`)
 hipError_t state_to_f64(const Dev &d, double *out, hipStream_t st);
 hipError_t state_to_f32(const Dev &d, float *out, hipStream_t st);
-// write H = base + scale * y (one state slot) into the solver state with its T
-// and fraction solid; counts per workgroup the nodes whose fraction solid
-// fell by more than fs_tol below that of s.H2
+// write H = base + scale * (y - the scenario's sum of w y) (one state slot,
+// unprojected y) into the solver state with its T and fraction solid; counts
+// per workgroup the nodes whose fraction solid fell by more than fs_tol below
+// that of s.H2
 hipError_t write_jump(const SurDev &s, const Dev &d, int parity, float fs_tol, hipStream_t st);
 // put the state back to s.H2
 hipError_t restore_h2(const SurDev &s, const Dev &d, int parity, hipStream_t st);

@@ -133,13 +133,20 @@ def test_temperature_and_rate_features():
     assert np.allclose(X[:, 6], 16 * (-160.0) / (c * S.T_SCALE), rtol=1e-12)
     assert np.allclose(X[:, 7], 128 * 10.0 / (c * S.T_SCALE), rtol=1e-12)
     # the quadratic through (0, H0), (1, H1), (2, H2) at 16: Lagrange weights 105, -224, 120
-    base, t, cc = S.base_and_target(p, H0, H1, H2, H2, horizon=16)
+    base, t, cc = S.base_and_target(p, H0, H1, H2, H2, horizon=16, quadratic=True)
     assert np.allclose(base, 105 * H0 - 224 * H1 + 120 * H2, rtol=1e-13)
-    # an exactly quadratic history is reproduced: H(k) = A + B k + C k^2
+    lin, t, cc = S.base_and_target(p, H0, H1, H2, H2, horizon=16)
+    assert np.allclose(lin, 15 * H2 - 14 * H1, rtol=1e-13)
+    assert np.allclose(t * cc * S.DH_SCALE, H2 - lin)
+    # an exactly quadratic history is reproduced by the quadratic base, a linear one by both
     k = np.arange(17.0)
     hist = 6e5 - 150.0 * k + 2.5 * k ** 2
-    b2, _, _ = S.base_and_target(p, np.full(N, hist[0]), np.full(N, hist[1]), np.full(N, hist[2]), np.full(N, hist[16]))
+    h = [np.full(N, hist[j]) for j in (0, 1, 2, 16)]
+    b2, _, _ = S.base_and_target(p, *h, quadratic=True)
     assert np.allclose(b2, hist[16], rtol=1e-14)
+    line = 6e5 - 150.0 * k
+    h = [np.full(N, line[j]) for j in (0, 1, 2, 16)]
+    assert np.allclose(S.base_and_target(p, *h)[0], line[16], rtol=1e-14)
 
 
 def test_temperature_loss_gradient_matches_central_differences(orc):
@@ -203,3 +210,27 @@ def test_projection_weights_of_the_chill_cube():
     free = np.setdiff1d(np.arange(w.size), p["dirichlet_nodes"])
     ratio = w[free] / w[free].max()
     assert set(np.round(ratio, 12)) <= {1.0, 0.5, 0.25, 0.125}
+
+
+def test_huber_loss_gradient_matches_central_differences():
+    params, X, t, ptr, col, layers = small_case(layers=2)
+    t = 3.0 * t                                  # both branches of the Huber loss occur
+    f = S.huber_loss(t)
+    loss, g, y = S.loss_and_grad(params, X, f, ptr, col, layers)
+    e = np.abs(y - t)
+    assert np.any(e < S.HUBER_DELTA) and np.any(e > S.HUBER_DELTA)
+    rng = np.random.default_rng(4)
+    eps = 1e-6
+    for name in ("W_in", "W0", "w_out", "b_out"):
+        val = params[name]
+        for ix in [tuple(rng.integers(0, s) for s in val.shape) for _ in range(3)]:
+            old = val[ix]
+            val[ix] = old + eps
+            lp = S.loss_and_grad(params, X, f, ptr, col, layers)[0]
+            val[ix] = old - eps
+            lm = S.loss_and_grad(params, X, f, ptr, col, layers)[0]
+            val[ix] = old
+            assert g[name][ix] == pytest.approx((lp - lm) / (2 * eps), rel=1e-5, abs=1e-10), (name, ix)
+    # within delta it is the squared error
+    small = S.huber_loss(y + 0.01)
+    assert small(y)[0] == pytest.approx(1e-4, rel=1e-9)

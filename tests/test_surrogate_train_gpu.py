@@ -20,6 +20,12 @@ def _cf():
     return cf
 
 
+def _fixed_layout(cf):
+    """FP32 blocked step with a pinned block size: solvers compared bit for bit must
+    share one partition (the autotuner times its candidates and may pick another)."""
+    return dict(precision=cf.FEM_PREC_FP32_KAHAN, lds_bytes=cf.lds_for_nodes(256))
+
+
 def generate(solver, dt, max_snap):
     """States H^{16k}, H^{16k+1}, H^{16k+2} of every scenario until all are solid (or max_snap)."""
     import torch
@@ -71,7 +77,7 @@ def test_trained_network_beats_linear_extrapolation_on_held_out_data(trained, or
         for n in (n0, n0 + 1, n0 + 2, n0 + 16):
             H[n], _, _ = orc.run(p, dt, n - at, H=H[at])
             at = n
-    s = cf.Solver(p, precision=cf.FEM_PREC_FP32_KAHAN)
+    s = cf.Solver(p, **_fixed_layout(cf))
     s.step(dt, 0)
     sur = cf.Surrogate(s, layers=3, max_samples=len(starts))
     perm = s.node_perm()
@@ -108,13 +114,13 @@ def test_accelerated_run_against_the_plain_run(trained, orc):
     cf = _cf()
     p = configs.config4_trajectory(HELD_OUT)
     dt = 0.9 * orc.stable_dt(p)
-    plain = cf.Solver(p, precision=cf.FEM_PREC_FP32_KAHAN)
+    plain = cf.Solver(p, **_fixed_layout(cf))
     rp = plain.advance(dt, 200000, None, until_solid=True)
-    acc = cf.Solver(p, precision=cf.FEM_PREC_FP32_KAHAN)
+    acc = cf.Solver(p, **_fixed_layout(cf))
     sur = cf.Surrogate(acc, layers=3)
     sur.set_params(trained["params"])
     ra = acc.advance(dt, 200000, sur, until_solid=True)
-    ref = cf.Solver(p, precision=cf.FEM_PREC_FP32_KAHAN)
+    ref = cf.Solver(p, **_fixed_layout(cf))
     ref.step(dt, ra["steps"])
     err = float(np.max(np.abs(acc.T() - ref.T())))
     print("plain: %d steps %.3f s; surrogate: %d steps (%d computed, %d/%d jumps kept) %.3f s; "
