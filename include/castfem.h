@@ -287,7 +287,8 @@ typedef struct {
     double max_residual;   /* largest energy residual of an accepted jump */
     int64_t rejected_fs;   /* jumps rejected by the fraction-solid (or NaN) check */
     int64_t rejected_energy; /* jumps rejected by the energy residual */
-    int64_t reserved[2];
+    int64_t rejected_verify; /* jumps rejected by the one-step verification */
+    int64_t reserved[1];
 } fem_advance_report;
 
 /* Surrogate on a bound context (graph and node strengths from its layout). */
@@ -318,24 +319,39 @@ int fem_sur_train(fem_sur *s, const float *H0, const float *H1, const float *H2,
 /* Predicted H^{n+horizon} of `slots` states into H_out (device, slots * n_nodes doubles). */
 int fem_sur_predict(fem_sur *s, const float *H0, const float *H1, const float *H2, int64_t stride, int64_t slots,
                     double *H_out);
+/* Training data from explicit trajectories that also pass through the
+ * network's own jumps: n_chunks chunks of `horizon` explicit steps of every
+ * scenario (dt_per_scenario[n_scen]); chunk k writes H^n, H^{n+1}, H^{n+2} and
+ * H^{n+horizon} (float32, device numbering) to S_dev[(4k + j) * n_nodes ...].
+ * With jump_every = J > 0, every J-th chunk is followed by returning to
+ * H^{n+2} and jumping with the current network (as fem_advance would, without
+ * the gates), so that the next chunks start from a jumped state.  Advances
+ * the context's state and clock.  Synchronous. */
+int fem_sur_generate(fem_sur *s, const double *dt_per_scenario, int64_t n_chunks, int32_t jump_every, float *S_dev);
 /* Current enthalpy of every node (device numbering) into a float32 device array. */
 int fem_snapshot_H(fem_ctx *ctx, float *H_dev);
-/* Advance every scenario (dt_per_scenario[n_scen]) in chunks of `horizon`
- * steps (16 without a surrogate) until max_steps or, with until_solid, until
- * every phase-change node has fraction solid 1 (checked after every chunk).
- * s == NULL: plain explicit steps.  Otherwise each chunk takes two explicit
- * steps and lets the surrogate jump the remaining horizon - 2 steps.  The jump
- * is kept only if, in every scenario, |dE - dQ| / |E_n - E_ref| <= energy_tol,
- * with dE the FP64 energy change over the chunk, dQ the boundary inflow of
- * the explicit steps plus its linear extrapolation over the jumped steps, E_n
- * the energy at the start of the chunk and E_ref that of the whole scenario at
- * 25 C, no
- * enthalpy is NaN or Inf and no phase-change node's fraction solid fell by
- * more than fs_tol; otherwise the state returns to H2 and horizon - 2 plain
- * steps follow.  The extrapolated inflow of kept jumps enters Q_cum of the
- * energy reports.  Synchronous. */
+/* Advance every scenario (dt_per_scenario[n_scen]) until max_steps or, with
+ * until_solid, until every phase-change node has fraction solid 1 (checked
+ * after every chunk).  s == NULL: plain explicit steps in chunks of 16.
+ * Otherwise chunks of `horizon` steps: explicit steps to H^n, H^{n+1},
+ * H^{n+2}, the surrogate's jump to H^{n+horizon}, and one explicit step from
+ * the jump (which is also the next chunk's first step).  The jump is kept only
+ * if, in every scenario:
+ *   - no phase-change node's fraction solid fell by more than fs_tol below its
+ *     value at H^{n+2}, and no enthalpy is NaN or Inf;
+ *   - the explicit step from the jump agrees with the extrapolation: at every
+ *     free node |dT/dH| |dH - dH_ext| <= verify_tol (K), dH_ext the increment
+ *     the extrapolation implies for that step (a wrong jump relaxes fast in
+ *     the first explicit step after it);
+ *   - |dE - dQ| / |E_n - E_ref| <= energy_tol, with dE the FP64 energy change
+ *     since the last check, dQ the exact boundary inflow of the explicit steps
+ *     in between plus their mean rate over the jumped steps, E_n the energy at
+ *     the last check and E_ref that of the scenario at 25 C.
+ * A rejected jump returns the state to H^{n+2} and horizon - 2 explicit steps
+ * follow.  The extrapolated inflow of kept jumps enters Q_cum of the energy
+ * reports.  Synchronous. */
 int fem_advance(fem_ctx *ctx, fem_sur *s, const double *dt_per_scenario, int64_t max_steps, int32_t until_solid,
-                double energy_tol, double fs_tol, fem_advance_report *rep);
+                double energy_tol, double fs_tol, double verify_tol, fem_advance_report *rep);
 
 #ifdef __cplusplus
 }

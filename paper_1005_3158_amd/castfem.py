@@ -35,7 +35,7 @@ EXPORTS = [
     "fem_time_kernels", "fem_copy_kernel", "fem_set_scenarios", "fem_stable_dt_scenarios", "fem_step_batch",
     "fem_energy_scenarios", "fem_sur_create", "fem_sur_destroy", "fem_sur_query_buffers", "fem_sur_bind_buffers",
     "fem_sur_n_params", "fem_sur_get_params", "fem_sur_set_params", "fem_sur_features", "fem_sur_loss_grad",
-    "fem_sur_train", "fem_sur_predict", "fem_snapshot_H", "fem_advance",
+    "fem_sur_train", "fem_sur_predict", "fem_snapshot_H", "fem_advance", "fem_sur_generate",
 ]
 
 
@@ -89,7 +89,7 @@ class fem_advance_report(C.Structure):
     _fields_ = [("steps", C.c_int64), ("plain_steps", C.c_int64), ("jumps_accepted", C.c_int64),
                 ("jumps_rejected", C.c_int64), ("solid", C.c_int32), ("pad", C.c_int32),
                 ("wall_seconds", C.c_double), ("max_residual", C.c_double), ("rejected_fs", C.c_int64),
-                ("rejected_energy", C.c_int64), ("reserved", C.c_int64 * 2)]
+                ("rejected_energy", C.c_int64), ("rejected_verify", C.c_int64), ("reserved", C.c_int64 * 1)]
 
 
 def _as_dict(s):
@@ -128,7 +128,7 @@ def lib():
             "fem_sur_loss_grad": [vp, vp, vp, vp, vp, i64, i64, vp, vp],
             "fem_sur_train": [vp, vp, vp, vp, vp, i64, i64, i32, i32, C.c_float, C.c_float, C.c_uint64, vp],
             "fem_sur_predict": [vp, vp, vp, vp, i64, i64, vp], "fem_snapshot_H": [vp, vp],
-            "fem_advance": [vp, vp, vp, i64, i32, dp, dp, vp],
+            "fem_advance": [vp, vp, vp, i64, i32, dp, dp, dp, vp], "fem_sur_generate": [vp, vp, i64, i32, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -398,15 +398,20 @@ def fem_sur_predict(s, H0_ptr, H1_ptr, H2_ptr, stride, slots, out_ptr):
           C.c_void_p(out_ptr))
 
 
+def fem_sur_generate(s, dt_per_scenario, n_chunks, jump_every, S_ptr):
+    dt = np.ascontiguousarray(np.atleast_1d(dt_per_scenario), np.float64)
+    _call("fem_sur_generate", s, _p(dt), int(n_chunks), int(jump_every), C.c_void_p(S_ptr))
+
+
 def fem_snapshot_H(ctx, out_ptr):
     _call("fem_snapshot_H", ctx, C.c_void_p(out_ptr))
 
 
-def fem_advance(ctx, sur, dt_per_scenario, max_steps, until_solid=True, energy_tol=1e-4, fs_tol=1e-6):
+def fem_advance(ctx, sur, dt_per_scenario, max_steps, until_solid=True, energy_tol=1e-4, fs_tol=1e-6, verify_tol=1.0):
     dt = np.ascontiguousarray(np.atleast_1d(dt_per_scenario), np.float64)
     rep = fem_advance_report()
     _call("fem_advance", ctx, sur, _p(dt), int(max_steps), int(bool(until_solid)), float(energy_tol),
-          float(fs_tol), C.byref(rep))
+          float(fs_tol), float(verify_tol), C.byref(rep))
     return _as_dict(rep)
 
 
@@ -507,9 +512,10 @@ class Solver:
         fem_snapshot_H(self.ctx, out.data_ptr())
         self.torch.cuda.current_stream(self.device).wait_stream(self.stream)
 
-    def advance(self, dt_per_scenario, max_steps, surrogate=None, until_solid=True, energy_tol=1e-4, fs_tol=1e-6):
+    def advance(self, dt_per_scenario, max_steps, surrogate=None, until_solid=True, energy_tol=1e-4, fs_tol=1e-6,
+                verify_tol=1.0):
         return fem_advance(self.ctx, surrogate.sur if surrogate is not None else None, dt_per_scenario, max_steps,
-                           until_solid, energy_tol, fs_tol)
+                           until_solid, energy_tol, fs_tol, verify_tol)
 
     def synchronize(self):
         self.stream.synchronize()
@@ -578,6 +584,15 @@ class Surrogate:
         ptrs = self._states((H0, H1, H2, Ht), stride, n_samples)
         self._sync_in()
         return fem_sur_train(self.sur, *ptrs, stride, n_samples, batch, epochs, lr, lr_final, seed)
+
+    def generate(self, dt_per_scenario, n_chunks, jump_every, S):
+        """Chunks of explicit states (H^n, H^n+1, H^n+2, H^n+horizon) into S, a float32 CUDA
+        tensor of shape (>= n_chunks, 4, n_nodes); see fem_sur_generate."""
+        assert S.dtype == self.torch.float32 and S.is_cuda and S.is_contiguous()
+        assert S.dim() == 3 and S.shape[0] >= n_chunks and S.shape[1] == 4 and S.shape[2] == self.n_nodes
+        self._sync_in()
+        fem_sur_generate(self.sur, dt_per_scenario, n_chunks, jump_every, S.data_ptr())
+        self.torch.cuda.current_stream(self.solver.device).wait_stream(self.solver.stream)
 
     def predict(self, H0, H1, H2, out, stride=None, slots=1):
         stride = self.n_nodes if stride is None else stride

@@ -21,13 +21,13 @@ namespace {
 
 enum SBuf {
     S_NBR_PTR, S_NBR, S_INV_DEG, S_COEF, S_PARAMS, S_GRADS, S_ADAM_M, S_ADAM_V, S_WBF, S_X, S_ZIN, S_U, S_Z,
-    S_HL, S_Y, S_BASE, S_SCALE, S_TARGET, S_DH, S_DZ, S_DU, S_PARTIALS, S_LOSS, S_IDX, S_H0, S_H1, S_H2, S_CHECK,
+    S_HL, S_Y, S_BASE, S_SCALE, S_TARGET, S_DH, S_DZ, S_DU, S_PARTIALS, S_LOSS, S_IDX, S_PARTIALS2, S_DY, S_H0, S_H1, S_H2, S_HN, S_REXT, S_QSAVE, S_CHECK,
     S_SCEN, S_SCEN_SEG_PTR, S_SCEN_SEG, S_SEG_PART, S_SCEN_SUM, S_COUNT
 };
 const char *const SBUF_NAMES[S_COUNT] = {"nbr_ptr", "nbr", "inv_deg", "coef", "params", "grads", "adam_m",
                                          "adam_v", "weights_bf16", "X", "Z_in", "U", "Z", "H_last", "y",
                                          "base", "scale", "target", "dH", "dZ", "dU", "partials", "loss_part",
-                                         "sample_idx", "H0", "H1", "H2", "check", "scenario",
+                                         "sample_idx", "partials2", "dy", "H0", "H1", "H2", "H_pred", "r_ext", "q_saved", "check", "scenario",
                                          "scen_seg_ptr", "scen_seg", "seg_part", "scen_sum"};
 
 // counter-based generator (SplitMix64 of seed and counter) for the
@@ -62,12 +62,12 @@ struct fem_sur {
     bool bound = false;
     SurDev d;
     int adam_t = 0;
-    // captured graphs of the accelerated advance, per starting T parity:
-    // the jump chunk (two steps, inference, checks, diagnostics) and the
-    // horizon - 2 fallback steps
-    hipGraph_t graph[2][2] = {};
-    hipGraphExec_t exec[2][2] = {};
-    float graph_fs_tol = -1.0f;
+    // captured graphs of the accelerated advance, per starting T parity: a
+    // jump chunk from a fresh state, a jump chunk continuing after a kept
+    // jump, and the horizon - 2 fallback steps
+    hipGraph_t graph[3][2] = {};
+    hipGraphExec_t exec[3][2] = {};
+    float graph_fs_tol = -1.0f, graph_verify_tol = -1.0f;
     ~fem_sur() {
         for (auto &row : exec)
             for (hipGraphExec_t &e : row)
@@ -104,7 +104,10 @@ void sur_sizes(fem_sur *s) {
     z[S_H0] = N * 8;
     z[S_H1] = N * 8;
     z[S_H2] = N * 8;
-    z[S_CHECK] = check_blocks(N) * 4;
+    z[S_HN] = N * 8;
+    z[S_REXT] = N * 8;
+    z[S_QSAVE] = s->ctx->L().n_inflow * 8;
+    z[S_CHECK] = 2 * check_blocks(N) * 4;
     z[S_SCEN] = N * 4;
     z[S_SCEN_SEG_PTR] = (s->n_scen + 1) * 4;
     z[S_SCEN_SEG] = s->n_seg * 4;
@@ -121,6 +124,8 @@ void sur_sizes(fem_sur *s) {
         z[S_PARTIALS] = s->nb * (2 * W * W + W) * 4;
         z[S_LOSS] = ((R + 255) / 256) * 8;
         z[S_IDX] = (int64_t)s->opt.max_samples * 4;
+        z[S_PARTIALS2] = ((s->nb + PARTIAL_GROUP - 1) / PARTIAL_GROUP) * (2 * W * W) * 4;
+        z[S_DY] = R * 4;
     }
 }
 
@@ -256,11 +261,15 @@ void fill_surdev(fem_sur *s) {
     d.dZ = (bf16 *)s->ptr[S_DZ];
     d.dU = (float *)s->ptr[S_DU];
     d.partials = (float *)s->ptr[S_PARTIALS];
+    d.partials2 = (float *)s->ptr[S_PARTIALS2];
+    d.dy = (float *)s->ptr[S_DY];
     d.n_partial_blocks = s->nb;
     d.loss_part = (double *)s->ptr[S_LOSS];
     d.H0 = (double *)s->ptr[S_H0];
     d.H1 = (double *)s->ptr[S_H1];
     d.H2 = (double *)s->ptr[S_H2];
+    d.Hn = (double *)s->ptr[S_HN];
+    d.rext = (double *)s->ptr[S_REXT];
     d.check = (int32_t *)s->ptr[S_CHECK];
     d.scen = (const int32_t *)s->ptr[S_SCEN];
     d.seg_begin = (const int32_t *)c->ptr[B_SEG];
@@ -311,49 +320,74 @@ double loss_of(fem_sur *s, int64_t R) {
     return sum / (double)R;
 }
 
-// work of one chunk of the accelerated advance starting from T parity p:
-// H0 = H^n, step, H1, step, H2, inference, the jump written into the state
-// with its fraction-solid check, and the state diagnostics of the result
-void enqueue_jump(fem_sur *s, int p, float fs_tol) {
+enum ChunkKind { CHUNK_FRESH = 0, CHUNK_FALLBACK = 1, CHUNK_CONT = 2 };
+
+// work of one jump chunk from T parity p.
+// Fresh (the state is H^n): H0 = H^n, step, H1, step, H2.  Continued (the
+// previous jump was kept, the state is H^{n+1} and s.Hn holds H^n): H0 = s.Hn,
+// H1 = the state, step, H2.  Then inference, the jump written into the state
+// with its f_s check, one explicit step from the prediction and its
+// verification, and the state diagnostics of the result.
+void enqueue_jump(fem_sur *s, int p, bool cont, float fs_tol, float verify_tol) {
     fem_ctx *c = s->ctx;
     hipStream_t st = c->stream;
-    HIPCHECK(state_to_f64(c->dev, s->d.H0, st));
-    HIPCHECK(enqueue_step(c->dev, p, st, nullptr));
+    int q = p;
+    if (!cont) {
+        HIPCHECK(state_to_f64(c->dev, s->d.H0, st));
+        HIPCHECK(enqueue_step(c->dev, q, st, nullptr));
+        q ^= 1;
+    }
     HIPCHECK(state_to_f64(c->dev, s->d.H1, st));
-    HIPCHECK(enqueue_step(c->dev, p ^ 1, st, nullptr));
+    HIPCHECK(enqueue_step(c->dev, q, st, nullptr));
+    q ^= 1;
     HIPCHECK(state_to_f64(c->dev, s->d.H2, st));
-    HIPCHECK(features(s->d, s->d.H0, s->d.H1, s->d.H2, 1, nullptr, s->N, nullptr, 1, st));
+    // the inflow sums at H2, for a fallback to start from
+    const int64_t Q = c->L().n_inflow;
+    // (whole 16-byte words: both buffers are padded to 256 bytes)
+    if (Q) HIPCHECK(enqueue_copy(s->ptr[S_QSAVE], c->ptr[B_QNODE], (Q * 8 + 15) / 16, st));
+    HIPCHECK(features(s->d, cont ? s->d.Hn : s->d.H0, s->d.H1, s->d.H2, 1, nullptr, s->N, nullptr, 1, st));
     HIPCHECK(forward(s->d, s->N, 0, 0, st));
-    HIPCHECK(write_jump(s->d, c->dev, p, fs_tol, st));
-    HIPCHECK(enqueue_state_diag(c->dev, p, st));
+    HIPCHECK(write_jump(s->d, c->dev, q, fs_tol, st));
+    HIPCHECK(enqueue_step(c->dev, q, st, nullptr));
+    q ^= 1;
+    HIPCHECK(verify_jump(s->d, c->dev, verify_tol, st));
+    HIPCHECK(enqueue_state_diag(c->dev, q, st));
 }
 
-// the fallback of a rejected jump: back to H2, then horizon - 2 explicit steps
+// the fallback of a rejected jump: back to H2 (T parity p), then horizon - 2 explicit steps
 void enqueue_fallback(fem_sur *s, int p) {
     fem_ctx *c = s->ctx;
     HIPCHECK(restore_h2(s->d, c->dev, p, c->stream));
+    const int64_t Q = c->L().n_inflow;
+    if (Q) HIPCHECK(enqueue_copy(c->ptr[B_QNODE], s->ptr[S_QSAVE], (Q * 8 + 15) / 16, c->stream));
     for (int k = 0; k < s->opt.horizon - 2; ++k) HIPCHECK(enqueue_step(c->dev, p ^ (k & 1), c->stream, nullptr));
 }
 
-// run `what` (0: jump, 1: fallback) from parity p through a graph captured on first use
-void run_chunk(fem_sur *s, int what, int p, float fs_tol) {
+void drop_graph(fem_sur *s, int what, int p) {
+    if (s->exec[what][p]) HIPCHECK(hipGraphExecDestroy(s->exec[what][p]));
+    if (s->graph[what][p]) HIPCHECK(hipGraphDestroy(s->graph[what][p]));
+    s->exec[what][p] = nullptr;
+    s->graph[what][p] = nullptr;
+}
+
+// run a chunk of kind `what` from parity p through a graph captured on first use
+void run_chunk(fem_sur *s, int what, int p, float fs_tol, float verify_tol) {
     fem_ctx *c = s->ctx;
     auto enqueue = [&] {
-        if (what == 0) enqueue_jump(s, p, fs_tol);
-        else enqueue_fallback(s, p);
+        if (what == CHUNK_FALLBACK) enqueue_fallback(s, p);
+        else enqueue_jump(s, p, what == CHUNK_CONT, fs_tol, verify_tol);
     };
     if (!c->stream) {                       // the null stream cannot be captured
         enqueue();
         return;
     }
-    if (what == 0 && fs_tol != s->graph_fs_tol) {   // the tolerance is a kernel argument
+    if (fs_tol != s->graph_fs_tol || verify_tol != s->graph_verify_tol) {   // tolerances are kernel arguments
         for (int q = 0; q < 2; ++q) {
-            if (s->exec[0][q]) HIPCHECK(hipGraphExecDestroy(s->exec[0][q]));
-            if (s->graph[0][q]) HIPCHECK(hipGraphDestroy(s->graph[0][q]));
-            s->exec[0][q] = nullptr;
-            s->graph[0][q] = nullptr;
+            drop_graph(s, CHUNK_FRESH, q);
+            drop_graph(s, CHUNK_CONT, q);
         }
         s->graph_fs_tol = fs_tol;
+        s->graph_verify_tol = verify_tol;
     }
     if (!s->exec[what][p]) {
         HIPCHECK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
@@ -600,8 +634,55 @@ int fem_snapshot_H(fem_ctx *ctx, float *H_dev) {
     });
 }
 
+int fem_sur_generate(fem_sur *s, const double *dt_per_scenario, int64_t n_chunks, int32_t jump_every, float *S_dev) {
+    if (!s || !dt_per_scenario || !S_dev) return set_err(FEM_E_INVALID_ARG, "null argument");
+    return guarded([&] {
+        need_bound(s);
+        fem_ctx *ctx = s->ctx;
+        if (n_chunks < 0 || jump_every < 0) throw PrepError{FEM_E_INVALID_ARG, "need n_chunks >= 0 and jump_every >= 0"};
+        const int32_t ns = ctx->prob.n_scen;
+        std::vector<double> dt(dt_per_scenario, dt_per_scenario + ns);
+        for (int32_t sc = 0; sc < ns; ++sc) {
+            if (!(dt[sc] > 0) || !std::isfinite(dt[sc])) throw PrepError{FEM_E_INVALID_ARG, "every dt must be > 0"};
+            if (dt[sc] > ctx->base.dt_scen[sc] && !ctx->opt.allow_unstable)
+                throw PrepError{FEM_E_UNSTABLE, "dt of scenario " + std::to_string(sc) + " above its stability bound"};
+        }
+        set_dt_scen(ctx, dt);
+        hipStream_t st = ctx->stream;
+        const int64_t N = s->N, H = s->opt.horizon;
+        auto clock = [&](int64_t n) {
+            ctx->steps += n;
+            for (int32_t sc = 0; sc < ns; ++sc) ctx->time_s[sc] += dt[sc] * (double)n;
+        };
+        for (int64_t k = 0; k < n_chunks; ++k) {
+            float *S = S_dev + k * 4 * N;
+            HIPCHECK(state_to_f32(ctx->dev, S, st));
+            HIPCHECK(state_to_f64(ctx->dev, s->d.H0, st));
+            run_steps(ctx, 1);
+            HIPCHECK(state_to_f32(ctx->dev, S + N, st));
+            HIPCHECK(state_to_f64(ctx->dev, s->d.H1, st));
+            run_steps(ctx, 1);
+            HIPCHECK(state_to_f32(ctx->dev, S + 2 * N, st));
+            HIPCHECK(state_to_f64(ctx->dev, s->d.H2, st));
+            run_steps(ctx, H - 2);
+            HIPCHECK(state_to_f32(ctx->dev, S + 3 * N, st));
+            clock(H);
+            if (jump_every > 0 && k % jump_every == jump_every - 1) {
+                // continue from the network's jump instead of the explicit state
+                const int p = ctx->parity ^ (int)((H - 2) & 1);   // T parity at H2
+                HIPCHECK(restore_h2(s->d, ctx->dev, p, st));
+                ctx->parity = p;
+                HIPCHECK(features(s->d, s->d.H0, s->d.H1, s->d.H2, 1, nullptr, N, nullptr, 1, st));
+                HIPCHECK(forward(s->d, N, 0, 0, st));
+                HIPCHECK(write_jump(s->d, ctx->dev, p, 1.0f, st));
+            }
+        }
+        HIPCHECK(hipStreamSynchronize(st));
+    });
+}
+
 int fem_advance(fem_ctx *ctx, fem_sur *s, const double *dt_per_scenario, int64_t max_steps, int32_t until_solid,
-                double energy_tol, double fs_tol, fem_advance_report *rep) {
+                double energy_tol, double fs_tol, double verify_tol, fem_advance_report *rep) {
     if (!ctx || !dt_per_scenario || !rep) return set_err(FEM_E_INVALID_ARG, "null argument");
     return guarded([&] {
         const auto t0 = std::chrono::steady_clock::now();
@@ -610,8 +691,8 @@ int fem_advance(fem_ctx *ctx, fem_sur *s, const double *dt_per_scenario, int64_t
             need_bound(s);
             if (s->ctx != ctx) throw PrepError{FEM_E_INVALID_ARG, "the surrogate belongs to another context"};
         }
-        if (max_steps < 0 || !(energy_tol > 0) || !(fs_tol >= 0))
-            throw PrepError{FEM_E_INVALID_ARG, "need max_steps >= 0, energy_tol > 0, fs_tol >= 0"};
+        if (max_steps < 0 || !(energy_tol > 0) || !(fs_tol >= 0) || !(verify_tol > 0))
+            throw PrepError{FEM_E_INVALID_ARG, "need max_steps >= 0, energy_tol > 0, fs_tol >= 0, verify_tol > 0"};
         const int32_t ns = ctx->prob.n_scen;
         std::vector<double> dt(dt_per_scenario, dt_per_scenario + ns);
         for (int32_t sc = 0; sc < ns; ++sc) {
@@ -635,15 +716,16 @@ int fem_advance(fem_ctx *ctx, fem_sur *s, const double *dt_per_scenario, int64_t
             for (int32_t sc = 0; sc < ns; ++sc) ctx->time_s[sc] += dt[sc] * (double)n;
             rep->steps += n;
         };
-        std::vector<double> E_prev(ns), Q_prev(ns), rate_prev(ns, NAN);
+        std::vector<double> E_prev(ns), Q_prev(ns);
         for (int32_t sc = 0; sc < ns; ++sc) {
             E_prev[sc] = er[sc].E;
             Q_prev[sc] = er[sc].Q_cum;
         }
         const int64_t nchk = check_blocks(ctx->L().N);
-        std::vector<int32_t> chk(nchk);
+        std::vector<int32_t> chk(2 * nchk);
         std::vector<double> dg, qn;
-        while (!(until_solid && all_solid()) && rep->steps + H <= max_steps) {
+        bool cont = false;     // the last jump was kept: the state is one step past it, s->d.Hn holds it
+        while (!(until_solid && all_solid()) && rep->steps + ((s && !cont) ? H + 1 : H) <= max_steps) {
             if (!s) {
                 run_steps(ctx, H);
                 advance_clock(H);
@@ -651,30 +733,40 @@ int fem_advance(fem_ctx *ctx, fem_sur *s, const double *dt_per_scenario, int64_t
                 energy_scenarios(ctx, er.data());
                 continue;
             }
-            // two plain steps (H0 -> H1 -> H2), then the network jumps H - 2 steps further
-            run_chunk(s, 0, ctx->parity, (float)fs_tol);      // the T parity is back after two steps
-            advance_clock(2);
-            rep->plain_steps += 2;
-            HIPCHECK(hipMemcpyAsync(chk.data(), s->ptr[S_CHECK], nchk * 4, hipMemcpyDeviceToHost, st));
+            // explicit steps to H0, H1, H2 (one of them is already done after a kept
+            // jump), the network's jump over H - 2 steps, one explicit step from it
+            const int p = ctx->parity;
+            const int n_plain = cont ? 2 : 3;
+            const int p_h2 = cont ? p ^ 1 : p;           // T parity of the state H2
+            run_chunk(s, cont ? CHUNK_CONT : CHUNK_FRESH, p, (float)fs_tol, (float)verify_tol);
+            ctx->parity = p ^ (n_plain & 1);
+            rep->plain_steps += n_plain;
+            HIPCHECK(hipMemcpyAsync(chk.data(), s->ptr[S_CHECK], 2 * nchk * 4, hipMemcpyDeviceToHost, st));
             energy_copies(ctx, dg, qn);
             HIPCHECK(hipStreamSynchronize(st));
             energy_reduce(ctx, dg, qn, er.data());
-            int64_t bad = 0;
-            for (int32_t v : chk) bad += v;
-            // FP64 gate of the jump: energy change over the chunk against the
-            // boundary inflow of the two plain steps plus its extrapolation over
-            // the jumped ones (mean rate of the plain steps, and the trend from
-            // the previous chunk's rate when there is one)
-            const double m = (double)(H - 2);
-            bool ok = bad == 0;
-            if (!ok) ++rep->rejected_fs;
-            std::vector<double> est(ns), res(ns), rate(ns);
+            int64_t bad_fs = 0, bad_verify = 0;
+            for (int64_t k = 0; k < nchk; ++k) {
+                bad_fs += chk[k];
+                bad_verify += chk[nchk + k];
+            }
+            bool ok = true;
+            if (bad_fs) {
+                ok = false;
+                ++rep->rejected_fs;
+            } else if (bad_verify) {
+                ok = false;
+                ++rep->rejected_verify;
+            }
+            // FP64 energy gate: the energy change since the last check against the
+            // inflow of the explicit steps in between (exact, per node) plus their
+            // mean rate over the H - 2 jumped steps, which they bracket
+            std::vector<double> est(ns), res(ns);
             for (int32_t sc = 0; sc < ns && ok; ++sc) {
                 const fem_energy_report &r = er[sc];
-                rate[sc] = 0.5 * (r.Q_cum - Q_prev[sc]);
-                const double slope = std::isnan(rate_prev[sc]) ? 0.0 : (rate[sc] - rate_prev[sc]) / (double)H;
-                est[sc] = m * rate[sc] + slope * (0.5 * m * (m - 1.0) + 1.5 * m);
-                res[sc] = std::fabs((r.E - E_prev[sc]) - (2.0 * rate[sc] + est[sc])) / std::fabs(E_prev[sc] - ctx->Eref_s[sc]);
+                const double q_plain = r.Q_cum - Q_prev[sc];
+                est[sc] = (double)(H - 2) * q_plain / (double)n_plain;
+                res[sc] = std::fabs((r.E - E_prev[sc]) - (q_plain + est[sc])) / std::fabs(E_prev[sc] - ctx->Eref_s[sc]);
                 if (r.nonfinite || !(res[sc] <= energy_tol)) {
                     ok = false;
                     ++rep->rejected_energy;
@@ -685,24 +777,24 @@ int fem_advance(fem_ctx *ctx, fem_sur *s, const double *dt_per_scenario, int64_t
                     ctx->Qx_s[sc] += est[sc];
                     E_prev[sc] = er[sc].E;
                     Q_prev[sc] = er[sc].Q_cum + est[sc];
-                    rate_prev[sc] = rate[sc];
                     er[sc].Q_cum += est[sc];
                     rep->max_residual = std::max(rep->max_residual, res[sc]);
                 }
-                advance_clock(H - 2);
+                advance_clock(cont ? H : H + 1);
                 ++rep->jumps_accepted;
+                cont = true;
             } else {
-                run_chunk(s, 1, ctx->parity, (float)fs_tol);
-                ctx->parity ^= (int)((H - 2) & 1);
-                advance_clock(H - 2);
+                run_chunk(s, CHUNK_FALLBACK, p_h2, (float)fs_tol, (float)verify_tol);
+                ctx->parity = p_h2 ^ (int)((H - 2) & 1);
+                advance_clock(cont ? H - 1 : H);
                 rep->plain_steps += H - 2;
                 ++rep->jumps_rejected;
                 energy_scenarios(ctx, er.data());
                 for (int32_t sc = 0; sc < ns; ++sc) {
                     E_prev[sc] = er[sc].E;
-                    rate_prev[sc] = NAN;
                     Q_prev[sc] = er[sc].Q_cum;
                 }
+                cont = false;
             }
         }
         HIPCHECK(hipStreamSynchronize(st));

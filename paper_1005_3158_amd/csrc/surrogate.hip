@@ -85,6 +85,8 @@ __global__ __launch_bounds__(256) void k_features(SurDev s, const HT *H0, const 
     out[1] = make_uint4(w[4], w[5], w[6], w[7]);
     // linear extrapolation through H1, H2, or quadratic through H0, H1, H2
     s.base[r] = s.quadratic ? h2 + m * rate + 0.5 * m * (m + 1.0) * acc : h2 + m * rate;
+    // the increment of the step after the horizon that the extrapolation implies
+    if (r < s.N) s.rext[r] = s.quadratic ? rate + (m + 1.0) * acc : rate;
     s.scale[r] = (float)(c * DH_SCALE);
     if (Ht) {
         if (s.loss_mode == LOSS_T) {
@@ -203,13 +205,32 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16 *__restrict__ A, int l
     if (lane < 16) Pb[(int64_t)blockIdx.x * WIDTH + wave * 16 + mi] = bsum;
 }
 
-// sum of the workgroup partials in workgroup order into grads[off + k], k < n
-// (rows of a partial are `ld` floats apart; only the first `rows` rows are kept)
-__global__ void k_reduce(const float *__restrict__ P, int64_t nblk, int64_t per, int keep, float *__restrict__ out) {
+// Deterministic sum of the workgroup partials P[b][k] (b < nblk, partials `per`
+// floats apart) into out[k], k < keep, in two passes: groups of PARTIAL_GROUP
+// partials in order into P2[g][k], then the groups in order.
+
+__global__ void k_reduce_groups(const float *__restrict__ P, int64_t nblk, int64_t per, int keep,
+                                float *__restrict__ P2) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= keep) return;
+    const int64_t b0 = (int64_t)blockIdx.y * PARTIAL_GROUP, b1 = std::min<int64_t>(nblk, b0 + PARTIAL_GROUP);
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+    int64_t b = b0;
+    for (; b + 4 <= b1; b += 4) {
+        a0 += P[b * per + k];
+        a1 += P[(b + 1) * per + k];
+        a2 += P[(b + 2) * per + k];
+        a3 += P[(b + 3) * per + k];
+    }
+    for (; b < b1; ++b) a0 += P[b * per + k];
+    P2[(int64_t)blockIdx.y * keep + k] = (a0 + a1) + (a2 + a3);
+}
+
+__global__ void k_reduce_final(const float *__restrict__ P2, int64_t ngroups, int keep, float *__restrict__ out) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= keep) return;
     float s = 0.f;
-    for (int64_t b = 0; b < nblk; ++b) s += P[b * per + k];
+    for (int64_t g = 0; g < ngroups; ++g) s += P2[g * keep + k];
     out[k] = s;
 }
 
@@ -317,19 +338,47 @@ __global__ __launch_bounds__(256) void k_layer(SurDev s, int l, int64_t R, int s
     }
 }
 
-// dH[j] += dU[j][:WIDTH] + sum over neighbours i of dU[i][WIDTH:] / deg_i  (transpose of the mean)
+// dH[j] += dU[j][:WIDTH] + sum over neighbours i of dU[i][WIDTH:] / deg_i  (transpose of
+// the mean; the graph is symmetric).  Sixteen threads per row, four channels each.
 __global__ __launch_bounds__(256) void k_aggT(SurDev s, const float *dU, float *dH, int64_t R) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t r = t / WIDTH;
-    const int c = (int)(t % WIDTH);
+    const int64_t r = t >> 4;
+    const int c4 = (int)(t & 15) * 4;
     if (r >= R) return;
     const int64_t j = r % s.N, base = r - j;
-    float acc = dH[r * WIDTH + c] + dU[r * 2 * WIDTH + c];
-    for (int32_t q = s.nbr_ptr[j]; q < s.nbr_ptr[j + 1]; ++q) {
-        const int64_t i = s.nbr[q];
-        acc += dU[(base + i) * 2 * WIDTH + WIDTH + c] * s.inv_deg[i];
+    float4 acc = *(const float4 *)(dH + r * WIDTH + c4);
+    const float4 own = *(const float4 *)(dU + r * 2 * WIDTH + c4);
+    acc.x += own.x;
+    acc.y += own.y;
+    acc.z += own.z;
+    acc.w += own.w;
+    const int32_t q0 = s.nbr_ptr[j], q1 = s.nbr_ptr[j + 1];
+    int32_t q = q0;
+    for (; q + 4 <= q1; q += 4) {
+        float4 v[4];
+        float w[4];
+        for (int u = 0; u < 4; ++u) {
+            const int64_t i = s.nbr[q + u];
+            v[u] = *(const float4 *)(dU + (base + i) * 2 * WIDTH + WIDTH + c4);
+            w[u] = s.inv_deg[i];
+        }
+        for (int u = 0; u < 4; ++u) {
+            acc.x += v[u].x * w[u];
+            acc.y += v[u].y * w[u];
+            acc.z += v[u].z * w[u];
+            acc.w += v[u].w * w[u];
+        }
     }
-    dH[r * WIDTH + c] = acc;
+    for (; q < q1; ++q) {
+        const int64_t i = s.nbr[q];
+        const float4 v = *(const float4 *)(dU + (base + i) * 2 * WIDTH + WIDTH + c4);
+        const float w = s.inv_deg[i];
+        acc.x += v.x * w;
+        acc.y += v.y * w;
+        acc.z += v.z * w;
+        acc.w += v.w * w;
+    }
+    *(float4 *)(dH + r * WIDTH + c4) = acc;
 }
 
 // dZ = dH where z > 0, else 0 (BF16)
@@ -373,16 +422,19 @@ __global__ __launch_bounds__(256) void k_proj_fwd(SurDev s, int64_t R) {
     s.y[r] = (float)((double)s.y[r] - s.scen_sum[q * s.n_scen + s.scen[i]]);
 }
 
-// backward: with g = dL/dy (in y), dL/dy_raw_k = g_k - w_k sum_i g_i; dH = dy_raw w_out
+// backward: with g = dL/dy (in y), dL/dy_raw_k = g_k - w_k sum_i g_i into dy, and
+// dH = dy_raw w_out.  Sixteen threads per row, four channels each.
 __global__ __launch_bounds__(256) void k_proj_bwd(SurDev s, int64_t R) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t r = t >> 4;
+    const int c4 = (int)(t & 15) * 4;
     if (r >= R) return;
     const int64_t q = r / s.N, i = r - q * s.N;
     const double w = (double)((const float4 *)s.coef)[i].w;
     const float dy = (float)((double)s.y[r] - w * s.scen_sum[q * s.n_scen + s.scen[i]]);
-    s.y[r] = dy;
-    const float *wo = s.params + s.pl.w_out;
-    for (int c = 0; c < WIDTH; ++c) s.dH[r * WIDTH + c] = dy * wo[c];
+    if (c4 == 0) s.dy[r] = dy;
+    const float4 wo = *(const float4 *)(s.params + s.pl.w_out + c4);
+    *(float4 *)(s.dH + r * WIDTH + c4) = make_float4(dy * wo.x, dy * wo.y, dy * wo.z, dy * wo.w);
 }
 
 // per row: error e and dL/dy of the loss sum_r e_r^2 / R, with y the projected output.
@@ -422,7 +474,7 @@ __global__ __launch_bounds__(256) void k_loss(SurDev s, int64_t R) {
     if (threadIdx.x == 0) s.loss_part[blockIdx.x] = ((part[0] + part[1]) + part[2]) + part[3];
 }
 
-// partials of dw_out = sum_r HL[r] dy[r] and db_out = sum_r dy[r]
+// partials of dw_out = sum_r HL[r] dy[r] and db_out = sum_r dy[r] (dy of the unprojected output)
 __global__ __launch_bounds__(256) void k_out_grad(SurDev s, int64_t R, float *P) {
     __shared__ float part[4][WIDTH + 1];
     const int c = threadIdx.x & 63, q = threadIdx.x >> 6;
@@ -430,7 +482,7 @@ __global__ __launch_bounds__(256) void k_out_grad(SurDev s, int64_t R, float *P)
     const int64_t r_end = std::min<int64_t>(R, r_begin + GRAD_ROWS);
     float acc = 0.f, accb = 0.f;
     for (int64_t r = r_begin + q; r < r_end; r += 4) {
-        const float dy = s.y[r];
+        const float dy = s.dy[r];
         acc += bf2f(s.HL[r * WIDTH + c]) * dy;
         if (c == 0) accb += dy;
     }
@@ -515,9 +567,12 @@ __global__ __launch_bounds__(256) void k_write_jump(SurDev s, Dev d, int parity,
     int bad = 0;
     if (i < d.N) {
         const uint32_t f = d.flags[i];
-        if (!(f & NODE_FIXED)) {
+        if (f & NODE_FIXED) {
+            s.Hn[i] = s.H2[i];
+        } else {
             const MatDev &M = d.mats[f & NODE_MAT_MASK];
             const double Hn = s.base[i] + (double)s.scale[i] * ((double)s.y[i] - s.scen_sum[s.scen[i]]);
+            s.Hn[i] = Hn;
             set_node<R>(d, i, M, Hn, (R *)d.T + parity * d.N);
             if (M.latent) {
                 double T0, fs0, T1, fs1;
@@ -542,6 +597,34 @@ __global__ __launch_bounds__(256) void k_restore(SurDev s, Dev d, int parity) {
     const uint32_t f = d.flags[i];
     if (f & NODE_FIXED) return;
     set_node<R>(d, i, d.mats[f & NODE_MAT_MASK], s.H2[i], (R *)d.T + parity * d.N);
+}
+
+template <class R>
+__global__ __launch_bounds__(256) void k_verify(SurDev s, Dev d, float tol) {
+    __shared__ int cnt[4];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int bad = 0;
+    if (i < d.N) {
+        const uint32_t f = d.flags[i];
+        if (!(f & NODE_FIXED)) {
+            const MatDev &M = d.mats[f & NODE_MAT_MASK];
+            double H;
+            if constexpr (sizeof(R) == 8) {
+                H = ((const double *)d.H)[i];
+            } else {
+                const float2 v = ((const float2 *)d.H)[i];
+                H = (double)v.x + (double)v.y;
+            }
+            const double Hp = s.Hn[i];
+            const double dTdH = (!M.latent || Hp <= M.Hs || Hp >= M.Hl) ? M.inv_c : M.slope;
+            const double dev = dTdH * fabs((H - Hp) - s.rext[i]);
+            bad = (dev > (double)tol || !(dev == dev)) ? 1 : 0;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) bad += __shfl_down(bad, off, 64);
+    if ((threadIdx.x & 63) == 0) cnt[threadIdx.x >> 6] = bad;
+    __syncthreads();
+    if (threadIdx.x == 0) s.check[check_blocks(d.N) + blockIdx.x] = cnt[0] + cnt[1] + cnt[2] + cnt[3];
 }
 
 inline unsigned grid_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
@@ -579,8 +662,18 @@ hipError_t loss_and_dy(const SurDev &s, int64_t R, hipStream_t st) {
     const int64_t slots = R / s.N;
     hipLaunchKernelGGL(k_seg_sum, dim3((unsigned)s.n_seg, (unsigned)slots), dim3(256), 0, st, s, (const float *)s.y, 0);
     hipLaunchKernelGGL(k_scen_sum, dim3(grid_for(slots * s.n_scen, 256)), dim3(256), 0, st, s, slots);
-    hipLaunchKernelGGL(k_proj_bwd, dim3(grid_for(R, 256)), dim3(256), 0, st, s, R);
+    hipLaunchKernelGGL(k_proj_bwd, dim3(grid_for(R * 16, 256)), dim3(256), 0, st, s, R);
     return hipGetLastError();
+}
+
+// deterministic two-pass sum of nblk workgroup partials into out[0..keep)
+static void reduce_partials(const SurDev &s, const float *P, int64_t nblk, int64_t per, int keep, float *out,
+                            hipStream_t st) {
+    const int64_t ng = (nblk + PARTIAL_GROUP - 1) / PARTIAL_GROUP;
+    hipLaunchKernelGGL(k_reduce_groups, dim3(grid_for(keep, 256), (unsigned)ng), dim3(256), 0, st, P, nblk, per, keep,
+                       s.partials2);
+    hipLaunchKernelGGL(k_reduce_final, dim3(grid_for(keep, 256)), dim3(256), 0, st, (const float *)s.partials2, ng,
+                       keep, out);
 }
 
 hipError_t backward(const SurDev &s, int64_t R, hipStream_t st) {
@@ -589,26 +682,23 @@ hipError_t backward(const SurDev &s, int64_t R, hipStream_t st) {
     float *Pb = s.partials + s.n_partial_blocks * 2 * WIDTH * WIDTH;   // nb x WIDTH
     // output layer
     hipLaunchKernelGGL(k_out_grad, dim3((unsigned)nb), dim3(256), 0, st, s, R, P);
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(WIDTH + 1), 0, st, P, nb, (int64_t)(WIDTH + 1), WIDTH + 1,
-                       s.grads + s.pl.w_out);
+    reduce_partials(s, P, nb, WIDTH + 1, WIDTH + 1, s.grads + s.pl.w_out, st);
     for (int l = s.layers - 1; l >= 0; --l) {
         hipLaunchKernelGGL(k_relu_back, dim3(grid_for(R * WIDTH, 256)), dim3(256), 0, st, s.dH, s.Z[l], s.dZ,
                            R * WIDTH);
         hipLaunchKernelGGL((k_wgrad<2 * WIDTH>), dim3((unsigned)nb), dim3(256), 0, st, s.U[l], 2 * WIDTH, s.dZ, R, P, Pb);
-        hipLaunchKernelGGL(k_reduce, dim3(grid_for(2 * WIDTH * WIDTH, 256)), dim3(256), 0, st, P, nb,
-                           (int64_t)(2 * WIDTH * WIDTH), 2 * WIDTH * WIDTH, s.grads + s.pl.w[l]);
-        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(WIDTH), 0, st, Pb, nb, (int64_t)WIDTH, WIDTH, s.grads + s.pl.b[l]);
+        reduce_partials(s, P, nb, 2 * WIDTH * WIDTH, 2 * WIDTH * WIDTH, s.grads + s.pl.w[l], st);
+        reduce_partials(s, Pb, nb, WIDTH, WIDTH, s.grads + s.pl.b[l], st);
         hipLaunchKernelGGL((k_gemm<2 * WIDTH, 2>), dim3(grid_for(R, 64)), dim3(256), 0, st, s.dZ, WIDTH, WIDTH,
                            s.wr[l], (const float *)nullptr, R, (bf16 *)nullptr, (const bf16 *)nullptr, 0,
                            (bf16 *)nullptr, 0, s.dU, 2 * WIDTH);
-        hipLaunchKernelGGL(k_aggT, dim3(grid_for(R * WIDTH, 256)), dim3(256), 0, st, s, s.dU, s.dH, R);
+        hipLaunchKernelGGL(k_aggT, dim3(grid_for(R * 16, 256)), dim3(256), 0, st, s, s.dU, s.dH, R);
     }
     // encoder
     hipLaunchKernelGGL(k_relu_back, dim3(grid_for(R * WIDTH, 256)), dim3(256), 0, st, s.dH, s.Zin, s.dZ, R * WIDTH);
     hipLaunchKernelGGL((k_wgrad<KIN>), dim3((unsigned)nb), dim3(256), 0, st, s.X, KIN, s.dZ, R, P, Pb);
-    hipLaunchKernelGGL(k_reduce, dim3(grid_for(NFEAT * WIDTH, 256)), dim3(256), 0, st, P, nb, (int64_t)(KIN * WIDTH),
-                       NFEAT * WIDTH, s.grads + s.pl.w_in);
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(WIDTH), 0, st, Pb, nb, (int64_t)WIDTH, WIDTH, s.grads + s.pl.b_in);
+    reduce_partials(s, P, nb, KIN * WIDTH, NFEAT * WIDTH, s.grads + s.pl.w_in, st);
+    reduce_partials(s, Pb, nb, WIDTH, WIDTH, s.grads + s.pl.b_in, st);
     return hipGetLastError();
 }
 
@@ -645,6 +735,13 @@ hipError_t write_jump(const SurDev &s, const Dev &d, int parity, float fs_tol, h
         hipLaunchKernelGGL(k_write_jump<double>, g, dim3(256), 0, st, s, d, parity, fs_tol);
     else
         hipLaunchKernelGGL(k_write_jump<float>, g, dim3(256), 0, st, s, d, parity, fs_tol);
+    return hipGetLastError();
+}
+
+hipError_t verify_jump(const SurDev &s, const Dev &d, float tol, hipStream_t st) {
+    const dim3 g((unsigned)check_blocks(d.N));
+    if (d.prec == FEM_PREC_FP64) hipLaunchKernelGGL(k_verify<double>, g, dim3(256), 0, st, s, d, tol);
+    else hipLaunchKernelGGL(k_verify<float>, g, dim3(256), 0, st, s, d, tol);
     return hipGetLastError();
 }
 

@@ -90,15 +90,20 @@ struct SurDev {
     bf16 *dZ = nullptr;                   // R x WIDTH
     float *dU = nullptr;                  // R x 2 WIDTH
     float *partials = nullptr;            // reduction partials
+    float *partials2 = nullptr;           // second pass of the reduction of partials
+    float *dy = nullptr;                  // R: dL/dy of the unprojected output
     int64_t n_partial_blocks = 0;
     double *loss_part = nullptr;          // per workgroup loss partials
     // jumps of the solver state
     double *H0 = nullptr, *H1 = nullptr, *H2 = nullptr;  // N: the three explicit states a jump starts from
-    int32_t *check = nullptr;             // per workgroup: nodes whose fraction solid fell
+    double *Hn = nullptr;                 // N: the predicted state (the next chunk's H0)
+    double *rext = nullptr;               // N: increment the extrapolation expects one step past the horizon
+    int32_t *check = nullptr;             // 2 x per workgroup: nodes whose f_s fell; nodes failing the verification
 };
 
 // rows handled by one workgroup of the weight-gradient product
-constexpr int GRAD_ROWS = 2048;
+constexpr int GRAD_ROWS = 512;
+constexpr int PARTIAL_GROUP = 64;     // partials summed per group in the first reduction pass
 
 // features, extrapolated base, scale and (Ht != null) targets of `slots`
 // states: slot q is sample idx[q] (q if idx is null) at offset sample * stride
@@ -124,7 +129,11 @@ hipError_t state_to_f32(const Dev &d, float *out, hipStream_t st);
 hipError_t write_jump(const SurDev &s, const Dev &d, int parity, float fs_tol, hipStream_t st);
 // put the state back to s.H2
 hipError_t restore_h2(const SurDev &s, const Dev &d, int parity, hipStream_t st);
-inline int64_t check_blocks(int64_t N) { return (N + 255) / 256; }
+// after one explicit step from the predicted state s.Hn: count per workgroup
+// the free nodes whose increment departs from the extrapolated one, s.rext, by
+// more than tol (in K: |dT/dH (s.Hn)| |(H - s.Hn) - s.rext| > tol)
+hipError_t verify_jump(const SurDev &s, const Dev &d, float tol, hipStream_t st);
+__host__ __device__ inline int64_t check_blocks(int64_t N) { return (N + 255) / 256; }
 
 }  // namespace sur
 }  // namespace castfem

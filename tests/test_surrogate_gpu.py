@@ -204,10 +204,12 @@ def test_rejected_jumps_reproduce_the_plain_run_bitwise(orc):
     dt = 0.9 * orc.stable_dt(p)
     a = cf.Solver(p, **_fixed_layout(cf))
     sur = cf.Surrogate(a, layers=LAYERS)
-    # no energy residual is that small: every jump falls back to plain steps
-    rep = a.advance(dt, 160, sur, until_solid=False, energy_tol=1e-300)
+    # no energy residual is that small: every jump falls back to plain steps (a chunk
+    # takes 3 explicit steps, the last from the jump, then 14 from H^{n+2})
+    rep = a.advance(dt, 161, sur, until_solid=False, energy_tol=1e-300)
     assert rep["jumps_accepted"] == 0 and rep["jumps_rejected"] == 10
-    assert rep["steps"] == 160 and rep["plain_steps"] == 160 and rep["rejected_energy"] + rep["rejected_fs"] == 10
+    assert rep["steps"] == 160 and rep["plain_steps"] == 170
+    assert rep["rejected_energy"] + rep["rejected_fs"] + rep["rejected_verify"] == 10
     b = cf.Solver(p, **_fixed_layout(cf))
     b.step(dt, 160)
     assert np.array_equal(a.H(), b.H()) and np.array_equal(a.T(), b.T()) and np.array_equal(a.fs(), b.fs())
@@ -229,14 +231,36 @@ def test_fraction_solid_gate(orc):
     ck = cf.fem_read_state(s.ctx)
     sur = cf.Surrogate(s, layers=LAYERS)
     _anti_diffusive_net(sur, 1000.0)            # re-melts the hotter part of the mushy zone
-    rep = s.advance(dt, 64, sur, until_solid=False, energy_tol=1e9, fs_tol=1e-6)
+    rep = s.advance(dt, 65, sur, until_solid=False, energy_tol=1e9, fs_tol=1e-6, verify_tol=1e9)
     assert rep["jumps_accepted"] == 0 and rep["jumps_rejected"] == 4 and rep["rejected_fs"] == 4
     cf.fem_write_state(s.ctx, ck)
     # the same jump from the same state passes once the f_s tolerance is lifted
-    rep = s.advance(dt, 16, sur, until_solid=False, energy_tol=1e9, fs_tol=1.0)
-    assert rep["jumps_accepted"] == 1 and rep["plain_steps"] == 2
+    rep = s.advance(dt, 17, sur, until_solid=False, energy_tol=1e9, fs_tol=1.0, verify_tol=1e9)
+    assert rep["jumps_accepted"] == 1 and rep["plain_steps"] == 3 and rep["steps"] == 17
     e = s.energy()
-    assert e["steps"] == 616 and e["time"] == pytest.approx(616 * dt, rel=1e-12)
+    assert e["steps"] == 617 and e["time"] == pytest.approx(617 * dt, rel=1e-12)
+    sur.close()
+    s.close()
+
+
+def test_verification_gate(orc):
+    """A jump with a temperature error of a few K relaxes in the first explicit step
+    after it; the verification catches it although energy and f_s checks are off."""
+    cf = _cf()
+    p = configs.config4_trajectory(5001)
+    dt = 0.9 * orc.stable_dt(p)
+    s = cf.Solver(p, **_fixed_layout(cf))
+    s.step(dt, 600)
+    ck = cf.fem_read_state(s.ctx)
+    sur = cf.Surrogate(s, layers=LAYERS)
+    _anti_diffusive_net(sur, 10.0)              # (T - mean T) / 7: several K at the hot and cold ends
+    rep = s.advance(dt, 65, sur, until_solid=False, energy_tol=1e9, fs_tol=1.0, verify_tol=1.0)
+    assert rep["jumps_accepted"] == 0 and rep["rejected_verify"] == 4
+    cf.fem_write_state(s.ctx, ck)
+    rep = s.advance(dt, 65, sur, until_solid=False, energy_tol=1e9, fs_tol=1.0, verify_tol=1e9)
+    assert rep["jumps_accepted"] == 4 and rep["rejected_verify"] == 0
+    # after kept jumps a chunk continues from the explicit step past the jump: 17 + 3 x 16 steps
+    assert rep["steps"] == 65 and rep["plain_steps"] == 3 + 3 * 2
     sur.close()
     s.close()
 
@@ -256,3 +280,40 @@ def test_plain_advance_matches_fem_step_and_stops_when_solid(orc):
     assert np.array_equal(a.H(), b.H())
     a.close()
     b.close()
+
+
+def test_generator_chunks_are_explicit_trajectories(orc):
+    import torch
+    cf = _cf()
+    p = configs.config4_trajectory(5003, n=6)
+    dt = 0.9 * orc.stable_dt(p)
+    a = cf.Solver(p, **_fixed_layout(cf))
+    sur = cf.Surrogate(a, layers=LAYERS)
+    S = torch.empty((3, 4, a.n_nodes), dtype=torch.float32, device=a.device)
+    sur.generate(dt, 3, 0, S)                   # no jumps: one explicit trajectory of 48 steps
+    b = cf.Solver(p, **_fixed_layout(cf))
+    perm = b.node_perm()
+    got = S.cpu().numpy()
+    at = 0
+    for k in range(3):
+        for j, n in enumerate((0, 1, 2, 16)):
+            step = 16 * k + n
+            b.step(dt, step - at)
+            at = step
+            assert np.array_equal(got[k, j][perm], b.H().astype(np.float32)), (k, j)
+    assert a.energy()["steps"] == 48
+    # with jumps: the chunk after a jump starts from the network's prediction
+    c = cf.Solver(p, **_fixed_layout(cf))
+    sc = cf.Surrogate(c, layers=LAYERS)
+    S2 = torch.empty((2, 4, c.n_nodes), dtype=torch.float32, device=c.device)
+    sc.generate(dt, 2, 1, S2)
+    g2 = S2.cpu().numpy()
+    assert np.array_equal(g2[0], got[0])        # first chunk identical
+    H0, H1, H2 = (g2[0, j].astype(np.float64) for j in range(3))
+    # untrained: the extrapolation of the exact states, here of their float32 snapshots
+    # (29 half-ulps of ~1e6 J/kg, at most 1.8 J/kg, apart)
+    assert np.allclose(g2[1, 0], H2 + 14.0 * (H2 - H1), rtol=0, atol=4.0)
+    for x in (sur, sc):
+        x.close()
+    for x in (a, b, c):
+        x.close()
