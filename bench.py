@@ -102,9 +102,12 @@ def main():
                     help="tet128: the 128^3 cast/mould mesh; batch: 256 scenarios of 20k-400k tets; "
                          "surrogate: train on chill-cube trajectories, then time-to-solidify plain vs surrogate")
     ap.add_argument("--train-traj", type=int, default=500, help="surrogate: training trajectories (seeds 5000+)")
-    ap.add_argument("--held-out", type=int, default=50, help="surrogate: held-out trajectories (seeds 5500+)")
-    ap.add_argument("--epochs", type=int, default=10, help="surrogate: training epochs per round")
-    ap.add_argument("--rounds", type=int, default=2, help="surrogate: training rounds (later ones through jumps)")
+    ap.add_argument("--held-out", type=int, default=None,
+                    help="surrogate: held-out trajectories (seeds 5500+); default 50, or 20 inside the default run")
+    ap.add_argument("--epochs", type=int, default=8, help="surrogate: training epochs per round")
+    ap.add_argument("--rounds", type=int, default=1, help="surrogate: training rounds (later ones through jumps)")
+    ap.add_argument("--verify-tol", type=float, default=3.0, help="surrogate: one-step verification tolerance (K)")
+    ap.add_argument("--no-surrogate", action="store_true", help="default run: skip the surrogate comparison")
     ap.add_argument("--lr", type=float, default=1e-3, help="surrogate: initial learning rate")
     ap.add_argument("--loss", default="huber", choices=["H", "T", "huber"], help="surrogate: training loss")
     ap.add_argument("--extrapolation", default="quadratic", choices=["linear", "quadratic"],
@@ -127,6 +130,8 @@ def main():
     if args.workload == "batch":
         return bench_batch(args, log)
     if args.workload == "surrogate":
+        if args.held_out is None:
+            args.held_out = 50
         return bench_surrogate(args, log)
     t0 = time.time()
     prob = configs.config2(n=args.n)
@@ -248,6 +253,15 @@ def main():
         "energy_residual": en["residual"],
     }
     s.close()
+    if not args.no_surrogate:
+        # the metric's second part: time to solidify, plain vs surrogate, judged by the plain run
+        if args.held_out is None:
+            args.held_out = 20
+        sur = run_surrogate(args, log)
+        keep = ("metric", "value", "unit", "plain_seconds", "surrogate_seconds", "max_err_K", "median_err_K",
+                "within_0p5K", "n_held_out", "jumps_kept", "jumps_rejected", "explicit_steps_computed_frac",
+                "train", "inference", "config")
+        out["surrogate"] = {k: sur[k] for k in keep}
     print(json.dumps(out), flush=True)
 
 
@@ -300,9 +314,14 @@ def bench_batch(args, log):
 
 
 def bench_surrogate(args, log):
+    """The surrogate comparison as its own JSON line."""
+    print(json.dumps(run_surrogate(args, log)), flush=True)
+
+
+def run_surrogate(args, log):
     """Config-4 surrogate: train on chill-cube trajectories of the GPU solver (seeds
-    5000..), a first round on explicit trajectories and a second on trajectories
-    that pass through the network's own jumps; then run every held-out trajectory
+    5000..), on explicit trajectories (and, with more rounds, on trajectories that
+    pass through the network's own jumps); then run every held-out trajectory
     (seeds 5500..) to full solidification plainly and with the surrogate.  The
     plain run judges the error."""
     import torch
@@ -369,7 +388,7 @@ def bench_surrogate(args, log):
         acc = cf.Solver(p, precision=cf.FEM_PREC_FP32_KAHAN, lds_bytes=lds)
         sa = cf.Surrogate(acc, layers=3, extrapolation=extrap)
         sa.set_params(params)
-        ra = acc.advance(dt1, 10 ** 6, sa, until_solid=True)
+        ra = acc.advance(dt1, 10 ** 6, sa, until_solid=True, verify_tol=args.verify_tol)
         if ra["steps"] <= rp["steps"]:
             ref = cf.Solver(p, precision=cf.FEM_PREC_FP32_KAHAN, lds_bytes=lds)
             ref.step(dt1, ra["steps"])
@@ -402,7 +421,8 @@ def bench_surrogate(args, log):
         "config": {"workload": "16^3 hex alloy cube with a convective chill on x=0: train on %d trajectories, "
                                "%d held-out trajectories run to full solidification" % (args.train_traj, args.held_out),
                    "layers": 3, "width": 64, "horizon": 16, "epochs": args.epochs, "rounds": args.rounds,
-                   "loss": args.loss, "extrapolation": args.extrapolation, "energy_tol": 1e-4, "fs_tol": 1e-6},
+                   "loss": args.loss, "extrapolation": args.extrapolation, "energy_tol": 1e-4, "fs_tol": 1e-6,
+                   "verify_tol_K": args.verify_tol},
         "plain_seconds": t_plain, "surrogate_seconds": t_sur,
         "max_err_K": float(errs.max()), "median_err_K": float(np.median(errs)),
         "within_0p5K": int(np.sum(errs <= 0.5)), "n_held_out": len(res),
@@ -413,7 +433,7 @@ def bench_surrogate(args, log):
         "inference": inf,
         "per_trajectory": res,
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 if __name__ == "__main__":

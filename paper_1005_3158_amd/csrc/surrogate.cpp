@@ -410,6 +410,37 @@ void run_chunk(fem_sur *s, int what, int p, float fs_tol, float verify_tol) {
     HIPCHECK(hipGraphLaunch(s->exec[what][p], c->stream));
 }
 
+// page-locked staging of the per-chunk read-back (check counts, state
+// diagnostics, inflow sums): one stream synchronisation per chunk
+struct Staging {
+    void *p = nullptr;
+    size_t chk = 0, dg = 0, qn = 0;
+    Staging(size_t chk_bytes, size_t dg_bytes, size_t qn_bytes) : chk(chk_bytes), dg(dg_bytes), qn(qn_bytes) {
+        HIPCHECK(hipHostMalloc(&p, std::max<size_t>(chk + dg + qn, 64), hipHostMallocDefault));
+    }
+    ~Staging() {
+        if (p) (void)hipHostFree(p);
+    }
+    char *at(size_t off) { return (char *)p + off; }
+};
+
+// enqueue the copies of the state diagnostics and inflow sums of ctx (and the
+// check counts of s, if any) into the staging buffer
+void stage_copies(fem_ctx *ctx, fem_sur *s, Staging &sg) {
+    hipStream_t st = ctx->stream;
+    if (s && sg.chk) HIPCHECK(hipMemcpyAsync(sg.at(0), s->ptr[S_CHECK], sg.chk, hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipMemcpyAsync(sg.at(sg.chk), ctx->ptr[B_DIAG], sg.dg, hipMemcpyDeviceToHost, st));
+    if (sg.qn) HIPCHECK(hipMemcpyAsync(sg.at(sg.chk + sg.dg), ctx->ptr[B_QNODE], sg.qn, hipMemcpyDeviceToHost, st));
+}
+
+// after a stream sync: the per-scenario energy reports from the staged copies
+void staged_energy(fem_ctx *ctx, Staging &sg, std::vector<double> &dg, std::vector<double> &qn,
+                   fem_energy_report *er) {
+    dg.assign((const double *)sg.at(sg.chk), (const double *)sg.at(sg.chk + sg.dg));
+    qn.assign((const double *)sg.at(sg.chk + sg.dg), (const double *)sg.at(sg.chk + sg.dg + sg.qn));
+    energy_reduce(ctx, dg, qn, er);
+}
+
 }  // namespace
 
 extern "C" {
@@ -722,15 +753,22 @@ int fem_advance(fem_ctx *ctx, fem_sur *s, const double *dt_per_scenario, int64_t
             Q_prev[sc] = er[sc].Q_cum;
         }
         const int64_t nchk = check_blocks(ctx->L().N);
-        std::vector<int32_t> chk(2 * nchk);
         std::vector<double> dg, qn;
+        Staging sg(s ? 2 * nchk * 4 : 0, ctx->L().seg_scen.size() * NDIAG * 8, ctx->L().n_inflow * 8);
+        // plain chunk: steps, diagnostics, one read-back
+        auto plain_chunk = [&](int64_t n) {
+            run_steps(ctx, n);
+            HIPCHECK(enqueue_state_diag(ctx->dev, ctx->parity, st));
+            stage_copies(ctx, nullptr, sg);
+            HIPCHECK(hipStreamSynchronize(st));
+            staged_energy(ctx, sg, dg, qn, er.data());
+        };
         bool cont = false;     // the last jump was kept: the state is one step past it, s->d.Hn holds it
         while (!(until_solid && all_solid()) && rep->steps + ((s && !cont) ? H + 1 : H) <= max_steps) {
             if (!s) {
-                run_steps(ctx, H);
+                plain_chunk(H);
                 advance_clock(H);
                 rep->plain_steps += H;
-                energy_scenarios(ctx, er.data());
                 continue;
             }
             // explicit steps to H0, H1, H2 (one of them is already done after a kept
@@ -741,10 +779,10 @@ int fem_advance(fem_ctx *ctx, fem_sur *s, const double *dt_per_scenario, int64_t
             run_chunk(s, cont ? CHUNK_CONT : CHUNK_FRESH, p, (float)fs_tol, (float)verify_tol);
             ctx->parity = p ^ (n_plain & 1);
             rep->plain_steps += n_plain;
-            HIPCHECK(hipMemcpyAsync(chk.data(), s->ptr[S_CHECK], 2 * nchk * 4, hipMemcpyDeviceToHost, st));
-            energy_copies(ctx, dg, qn);
+            stage_copies(ctx, s, sg);
             HIPCHECK(hipStreamSynchronize(st));
-            energy_reduce(ctx, dg, qn, er.data());
+            staged_energy(ctx, sg, dg, qn, er.data());
+            const int32_t *chk = (const int32_t *)sg.at(0);
             int64_t bad_fs = 0, bad_verify = 0;
             for (int64_t k = 0; k < nchk; ++k) {
                 bad_fs += chk[k];
@@ -789,7 +827,10 @@ int fem_advance(fem_ctx *ctx, fem_sur *s, const double *dt_per_scenario, int64_t
                 advance_clock(cont ? H - 1 : H);
                 rep->plain_steps += H - 2;
                 ++rep->jumps_rejected;
-                energy_scenarios(ctx, er.data());
+                HIPCHECK(enqueue_state_diag(ctx->dev, ctx->parity, st));
+                stage_copies(ctx, nullptr, sg);
+                HIPCHECK(hipStreamSynchronize(st));
+                staged_energy(ctx, sg, dg, qn, er.data());
                 for (int32_t sc = 0; sc < ns; ++sc) {
                     E_prev[sc] = er[sc].E;
                     Q_prev[sc] = er[sc].Q_cum;

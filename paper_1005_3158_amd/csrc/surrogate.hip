@@ -235,26 +235,30 @@ __global__ void k_reduce_final(const float *__restrict__ P2, int64_t ngroups, in
 }
 
 // ---------------------------------------------------------------- graph
-// One message-passing layer for 64 rows per workgroup (16 per wavefront):
-// h_{l-1} of the rows and the mean of h_{l-1} over their mesh neighbours are
-// put side by side in LDS, then [h, a] W_l runs on MFMA with the A operand read
-// from LDS.  Epilogue: z = . + b_l (kept in Z[l] when store), h_l = h_{l-1} +
-// relu(z) into U[l+1] (or H_last).  With store the mean is also written into
-// the second half of U[l] (the weight gradient reads it).
+// One message-passing layer for 32 rows per workgroup: h_{l-1} of the rows and
+// the mean of h_{l-1} over their mesh neighbours (one 8-channel task per
+// thread, eight neighbours in flight) are put side by side in LDS with W_l^T,
+// then [h, a] W_l runs on MFMA: wave w takes rows 16 (w & 1).. and output
+// columns 32 (w >> 1)...  Epilogue: z = . + b_l (kept in Z[l] when store),
+// h_l = h_{l-1} + relu(z) into U[l+1] (or H_last); the last layer also forms
+// y = h_L . w_out + b_out.  With store the mean is also written into the
+// second half of U[l] (the weight gradient reads it).
+constexpr int LAYER_ROWS = 32;
+
 __global__ __launch_bounds__(256) void k_layer(SurDev s, int l, int64_t R, int store) {
     constexpr int LDU = 2 * WIDTH + 8;
-    __shared__ __align__(16) bf16 Ut[64][LDU];
+    __shared__ __align__(16) bf16 Ut[LAYER_ROWS][LDU];
     __shared__ __align__(16) bf16 Wt[WIDTH][LDU];      // W_l^T, row n holds W_l[:, n]
+    __shared__ float ypart[2][LAYER_ROWS];
     const bf16 *__restrict__ U = s.U[l];
     const int t = threadIdx.x;
-    const int64_t row0 = (int64_t)blockIdx.x * 64;
+    const int64_t row0 = (int64_t)blockIdx.x * LAYER_ROWS;
     for (int v = t; v < WIDTH * (2 * WIDTH / 8); v += 256) {
         const int n = v / (2 * WIDTH / 8), k8 = (v % (2 * WIDTH / 8)) * 8;
         *(uint4 *)&Wt[n][k8] = *(const uint4 *)(s.wt[l] + n * 2 * WIDTH + k8);
     }
-    // own rows: 64 x 64 BF16 as 512 16-byte words, and the neighbour means of 8 channels each
-    for (int v = t; v < 512; v += 256) {
-        const int rr = v >> 3, c8 = (v & 7) * 8;
+    {
+        const int rr = t >> 3, c8 = (t & 7) * 8;
         const int64_t r = row0 + rr;
         uint4 own = make_uint4(0, 0, 0, 0), mean = make_uint4(0, 0, 0, 0);
         if (r < R) {
@@ -263,10 +267,10 @@ __global__ __launch_bounds__(256) void k_layer(SurDev s, int l, int64_t R, int s
             float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
             const int32_t q0 = s.nbr_ptr[i], q1 = s.nbr_ptr[i + 1];
             int32_t q = q0;
-            for (; q + 4 <= q1; q += 4) {
-                uint4 w[4];
-                for (int u = 0; u < 4; ++u) w[u] = *(const uint4 *)(U + (base + s.nbr[q + u]) * 2 * WIDTH + c8);
-                for (int u = 0; u < 4; ++u) {
+            for (; q + 8 <= q1; q += 8) {
+                uint4 w[8];
+                for (int u = 0; u < 8; ++u) w[u] = *(const uint4 *)(U + (base + s.nbr[q + u]) * 2 * WIDTH + c8);
+                for (int u = 0; u < 8; ++u) {
                     const uint32_t x[4] = {w[u].x, w[u].y, w[u].z, w[u].w};
                     for (int k = 0; k < 4; ++k) {
                         acc[2 * k] += bf2f((bf16)(x[k] & 0xffffu));
@@ -293,15 +297,15 @@ __global__ __launch_bounds__(256) void k_layer(SurDev s, int l, int64_t R, int s
         *(uint4 *)&Ut[rr][WIDTH + c8] = mean;
     }
     __syncthreads();
-    constexpr int NT = WIDTH / 16, K = 2 * WIDTH;
+    constexpr int K = 2 * WIDTH;
     const int wave = t >> 6, lane = t & 63;
     const int ar = lane & 15, kq = (lane >> 4) * 4;
-    f4 acc[NT];
-    for (int n = 0; n < NT; ++n) acc[n] = f4{0.f, 0.f, 0.f, 0.f};
+    const int rt = wave & 1, nt0 = (wave >> 1) * 2;
+    f4 acc[2] = {f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}};
     for (int k0 = 0; k0 < K; k0 += 16) {
-        const s4 a = *(const s4 *)&Ut[wave * 16 + ar][k0 + kq];
-        for (int n = 0; n < NT; ++n) {
-            const s4 b = *(const s4 *)&Wt[n * 16 + ar][k0 + kq];
+        const s4 a = *(const s4 *)&Ut[rt * 16 + ar][k0 + kq];
+        for (int n = 0; n < 2; ++n) {
+            const s4 b = *(const s4 *)&Wt[(nt0 + n) * 16 + ar][k0 + kq];
             acc[n] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[n], 0, 0, 0);
         }
     }
@@ -311,10 +315,10 @@ __global__ __launch_bounds__(256) void k_layer(SurDev s, int l, int64_t R, int s
     const int ldh = last ? WIDTH : 2 * WIDTH;
     const float *wo = s.params + s.pl.w_out;
     float yp[4] = {0.f, 0.f, 0.f, 0.f};   // last layer: this lane's part of y for rows kq + j
-    for (int n = 0; n < NT; ++n) {
-        const int col = n * 16 + ar;
+    for (int n = 0; n < 2; ++n) {
+        const int col = (nt0 + n) * 16 + ar;
         for (int j = 0; j < 4; ++j) {
-            const int rr = wave * 16 + kq + j;
+            const int rr = rt * 16 + kq + j;
             const int64_t row = row0 + rr;
             const float z = acc[n][j] + bias[col];
             const bf16 hb = f2bf(bf2f(Ut[rr][col]) + (z > 0.f ? z : 0.f));
@@ -325,15 +329,15 @@ __global__ __launch_bounds__(256) void k_layer(SurDev s, int l, int64_t R, int s
         }
     }
     if (last) {
-        // y = h_L . w_out + b_out: sum over the 16 lanes that hold the same rows
+        // y = h_L . w_out + b_out: the 16 lanes holding a row, then the two waves holding its columns
         for (int j = 0; j < 4; ++j)
             for (int off = 8; off > 0; off >>= 1) yp[j] += __shfl_xor(yp[j], off, 16);
-        if (ar == 0) {
-            const float b_out = s.params[s.pl.b_out];
-            for (int j = 0; j < 4; ++j) {
-                const int64_t row = row0 + wave * 16 + kq + j;
-                if (row < R) s.y[row] = yp[j] + b_out;
-            }
+        if (ar == 0)
+            for (int j = 0; j < 4; ++j) ypart[wave >> 1][rt * 16 + kq + j] = yp[j];
+        __syncthreads();
+        if (t < LAYER_ROWS) {
+            const int64_t row = row0 + t;
+            if (row < R) s.y[row] = (ypart[0][t] + ypart[1][t]) + s.params[s.pl.b_out];
         }
     }
 }
@@ -649,7 +653,8 @@ hipError_t forward(const SurDev &s, int64_t R, int store, int project, hipStream
     hipLaunchKernelGGL((k_gemm<WIDTH, 0>), dim3(g), dim3(256), 0, st, s.X, KIN, KIN, s.wt_in,
                        s.params + s.pl.b_in, R, store ? s.Zin : (bf16 *)nullptr, (const bf16 *)nullptr, 0, s.U[0],
                        2 * WIDTH, (float *)nullptr, 0);
-    for (int l = 0; l < s.layers; ++l) hipLaunchKernelGGL(k_layer, dim3(g), dim3(256), 0, st, s, l, R, store);
+    const unsigned gl = grid_for(R, LAYER_ROWS);
+    for (int l = 0; l < s.layers; ++l) hipLaunchKernelGGL(k_layer, dim3(gl), dim3(256), 0, st, s, l, R, store);
     const int64_t slots = R / s.N;
     hipLaunchKernelGGL(k_seg_sum, dim3((unsigned)s.n_seg, (unsigned)slots), dim3(256), 0, st, s, (const float *)s.y, 1);
     hipLaunchKernelGGL(k_scen_sum, dim3(grid_for(slots * s.n_scen, 256)), dim3(256), 0, st, s, slots);
