@@ -107,6 +107,8 @@ def main():
     ap.add_argument("--epochs", type=int, default=8, help="surrogate: training epochs per round")
     ap.add_argument("--rounds", type=int, default=1, help="surrogate: training rounds (later ones through jumps)")
     ap.add_argument("--verify-tol", type=float, default=3.0, help="surrogate: one-step verification tolerance (K)")
+    ap.add_argument("--fs-tol", type=float, default=1e-4,
+                    help="surrogate: largest fall of a node's fraction solid a kept jump may cause")
     ap.add_argument("--no-surrogate", action="store_true", help="default run: skip the surrogate comparison")
     ap.add_argument("--lr", type=float, default=1e-3, help="surrogate: initial learning rate")
     ap.add_argument("--loss", default="huber", choices=["H", "T", "huber"], help="surrogate: training loss")
@@ -388,7 +390,7 @@ def run_surrogate(args, log):
         acc = cf.Solver(p, precision=cf.FEM_PREC_FP32_KAHAN, lds_bytes=lds)
         sa = cf.Surrogate(acc, layers=3, extrapolation=extrap)
         sa.set_params(params)
-        ra = acc.advance(dt1, 10 ** 6, sa, until_solid=True, verify_tol=args.verify_tol)
+        ra = acc.advance(dt1, 10 ** 6, sa, until_solid=True, verify_tol=args.verify_tol, fs_tol=args.fs_tol)
         if ra["steps"] <= rp["steps"]:
             ref = cf.Solver(p, precision=cf.FEM_PREC_FP32_KAHAN, lds_bytes=lds)
             ref.step(dt1, ra["steps"])
@@ -421,7 +423,7 @@ def run_surrogate(args, log):
         "config": {"workload": "16^3 hex alloy cube with a convective chill on x=0: train on %d trajectories, "
                                "%d held-out trajectories run to full solidification" % (args.train_traj, args.held_out),
                    "layers": 3, "width": 64, "horizon": 16, "epochs": args.epochs, "rounds": args.rounds,
-                   "loss": args.loss, "extrapolation": args.extrapolation, "energy_tol": 1e-4, "fs_tol": 1e-6,
+                   "loss": args.loss, "extrapolation": args.extrapolation, "energy_tol": 1e-4, "fs_tol": args.fs_tol,
                    "verify_tol_K": args.verify_tol},
         "plain_seconds": t_plain, "surrogate_seconds": t_sur,
         "max_err_K": float(errs.max()), "median_err_K": float(np.median(errs)),

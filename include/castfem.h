@@ -234,20 +234,29 @@ int fem_copy_kernel(fem_ctx *ctx, void *dst, const void *src, int64_t bytes, int
  * explicit steps ahead (not part of the paper; the explicit step of Eq. 14 is
  * its fallback and judge).  From three consecutive explicit states H0 = H^n,
  * H1 = H^{n+1}, H2 = H^{n+2} it predicts, per node i, with m = horizon - 2,
- * r = H2 - H1 and a = (H2 - H1) - (H1 - H0),
- *   H^{n+horizon}_i = base_i + 10 c_i y_i,
+ * q = m (m + 1) / 2, r = H2 - H1 and a = (H2 - H1) - (H1 - H0),
+ *   H^{n+horizon}_i = base_i + mu_i s_i (y_i - ybar),
  * base = H2 + m r (linear extrapolation, the default) or
- * base = H2 + m r + m (m + 1) / 2 a (quadratic; fem_sur_options.extrapolation),
+ * base = H2 + m r + q a (quadratic; fem_sur_options.extrapolation).
+ * s_i = |m r_i| + |q a_i| + 0.01 K c_i is the node's activity over the window;
+ * mu_i = 1 at a free phase-change node whose H2 lies within 2 (|m r_i| + |q a_i|)
+ * of the solidus enthalpy c T_sol or the liquidus enthalpy c T_liq + L,
+ * else 0: the network corrects the
+ * extrapolation only where a kink of T(H) makes it fail.  ybar is the mean of
+ * y weighted by m_i mu_i s_i over the node's scenario (m_i the lumped mass),
+ * which makes the correction energy-neutral.
  * y = output of a network of `layers` residual message-passing layers of
  * width 64 over the mesh graph (nodes sharing an element, mean aggregation):
  *   h_0 = relu(x W_in + b_in);  h_l = h_{l-1} + relu([h_{l-1}, mean_nbr h_{l-1}] W_l + b_l);
  *   y = h_L . w_out + b_out.
- * Node features x (9): (T(H2) - 25)/700, fs(H2), latent-heat flag, Robin,
+ * Node features x (12): (T(H2) - 25)/700, fs(H2), latent-heat flag, Robin,
  * interface and conduction strengths b_i dt/(m_i c_i), 2 sum w_ij dt/(m_i c_i),
- * sum_j |K_ij| dt/(m_i c_i), horizon r/(700 c_i), horizon^2 a/(1400 c_i), 1.
+ * sum_j |K_ij| dt/(m_i c_i), m r / s, q a / s, 1, ln(s / (c 1 K)) / 8, and
+ * clip((H2 - H_liq) / s, -4, 4) / 4, clip((H2 - H_sol) / s, -4, 4) / 4 (0 for
+ * materials without latent heat).
  * Activations and weights are BF16 on the matrix cores with FP32
  * accumulation; parameters, gradients and Adam moments are FP32.
- * Parameters are one FP32 vector: W_in [9 x 64] row-major, b_in [64], then per
+ * Parameters are one FP32 vector: W_in [12 x 64] row-major, b_in [64], then per
  * layer W_l [128 x 64] row-major and b_l [64], then w_out [64], b_out [1].
  * State arrays passed in are float32 device arrays in the context's device
  * numbering (fem_get_node_perm); state q of a call starts at q * stride.
@@ -255,12 +264,13 @@ int fem_copy_kernel(fem_ctx *ctx, void *dst, const void *src, int64_t bytes, int
  * its last fem_step, fem_step_batch or fem_advance call. */
 typedef struct fem_sur fem_sur;
 
-/* Training loss, a mean over all nodes of the states of a step:
- *   FEM_SUR_LOSS_H: (y - t)^2 with t = (Ht - base) / (10 c), the enthalpy error;
- *   FEM_SUR_LOSS_T: ((T(base + 10 c y) - T(Ht)) / 10 K)^2, the temperature error
+/* Training loss, a mean over all nodes of the states of a step, with y' = y - ybar:
+ *   FEM_SUR_LOSS_H: mu (y' - t)^2 with t = (Ht - base) / s, the enthalpy error
+ *   relative to the node's activity;
+ *   FEM_SUR_LOSS_T: ((T(base + mu s y') - T(Ht)) / 10 K)^2, the temperature error
  *   (gradient through the branch of T(H) the prediction lies on);
- *   FEM_SUR_LOSS_HUBER: the enthalpy error e = y - t with e^2 replaced by
- *   0.1 (2|e| - 0.1) beyond |e| = 0.1 (1 K of sensible heat). */
+ *   FEM_SUR_LOSS_HUBER: the enthalpy error e = y' - t with e^2 replaced by
+ *   0.1 (2|e| - 0.1) beyond |e| = 0.1, at masked nodes. */
 enum { FEM_SUR_LOSS_H = 0, FEM_SUR_LOSS_T = 1, FEM_SUR_LOSS_HUBER = 2 };
 enum { FEM_SUR_EXTRAP_LINEAR = 0, FEM_SUR_EXTRAP_QUADRATIC = 1 };
 
@@ -303,7 +313,7 @@ int fem_sur_n_params(const fem_sur *s, int64_t *n);
  * resets the Adam moments.  Synchronous. */
 int fem_sur_get_params(fem_sur *s, float *host, int64_t n);
 int fem_sur_set_params(fem_sur *s, const float *host, int64_t n);
-/* Features (as rounded to BF16) of `slots` states: X_host[slots * n_nodes * 9]. */
+/* Features (as rounded to BF16) of `slots` states: X_host[slots * n_nodes * 12]. */
 int fem_sur_features(fem_sur *s, const float *H0, const float *H1, const float *H2, int64_t stride, int64_t slots,
                      float *X_host);
 /* Training loss (fem_sur_options.loss) over all nodes of `slots` states and its

@@ -4,23 +4,36 @@ TEST INFRASTRUCTURE ONLY: it judges the gradients of the GPU training kernels
 and is itself checked against central finite differences.
 
 The surrogate jumps the enthalpy state `horizon` explicit steps ahead.  Given
-three consecutive plain states H0 = H^n, H1 = H^{n+1}, H2 = H^{n+2} it predicts,
-with m = horizon - 2, r = H2 - H1 and a = (H2 - H1) - (H1 - H0),
+three consecutive plain states H0 = H^n, H1 = H^{n+1}, H2 = H^{n+2}, with
+m = horizon - 2, q = m (m + 1) / 2, r = H2 - H1 and a = (H2 - H1) - (H1 - H0),
+it predicts
 
-    H^{n+horizon} ~ base + c_i * DH_SCALE * y_i,   base = H2 + m r  [+ m (m + 1) / 2 a],
+    H^{n+horizon} ~ base_i + mu_i s_i y'_i,   base = H2 + m r  [+ q a],
 
 the linear (or quadratic) extrapolation in time, corrected by the network
-output y_i of node i.  Per-node input features (9):
+output where the extrapolation is known to fail: near the kinks of the
+enthalpy relation.  s_i = |m r_i| + |q a_i| + c_i EPS_T is the node's
+activity over the window (enthalpy units), and the mask mu_i is 1 at a free
+phase-change node whose enthalpy lies within REACH activities of the solidus
+or liquidus enthalpy (c T_sol, c T_liq + L), else 0.  Elsewhere the jump is
+the extrapolation itself.  y' is the network output made energy-neutral over
+the masked nodes of the scenario: y' = y - sum_j w_j y_j with
+w_j = m_j mu_j s_j / sum_k m_k mu_k s_k, so that sum_i m_i mu_i s_i y'_i = 0.
 
-    x0 = (T(H2) - T_REF) / T_SCALE          temperature
-    x1 = fs(H2)                             fraction solid
-    x2 = 1 if the node's material has latent heat else 0
-    x3 = b_i dt / (m_i c_i)                 Robin strength per step
-    x4 = 2 sum_j w_ij dt / (m_i c_i)        interface strength per step
-    x5 = sum_j |K_ij| dt / (m_i c_i)        conduction strength per step
-    x6 = horizon r / (c_i T_SCALE)          rate over the horizon
-    x7 = horizon^2 a / (2 c_i T_SCALE)      curvature over the horizon
-    x8 = 1
+Per-node input features (12):
+
+    x0  = (T(H2) - T_REF) / T_SCALE         temperature
+    x1  = fs(H2)                            fraction solid
+    x2  = 1 if the node's material has latent heat else 0
+    x3  = b_i dt / (m_i c_i)                Robin strength per step
+    x4  = 2 sum_j w_ij dt / (m_i c_i)       interface strength per step
+    x5  = sum_j |K_ij| dt / (m_i c_i)       conduction strength per step
+    x6  = m r / s                           rate over the window, relative
+    x7  = q a / s                           curvature over the window, relative
+    x8  = 1
+    x9  = ln(s / (c * 1 K)) / 8             activity in kelvin, logarithmic
+    x10 = clip((H2 - H_liq) / s, -4, 4) / 4 distance to the liquidus (0 without latent heat)
+    x11 = clip((H2 - H_sol) / s, -4, 4) / 4 distance to the solidus (0 without latent heat)
 
 Network (width W, L message-passing layers, ReLU):
 
@@ -29,9 +42,9 @@ Network (width W, L message-passing layers, ReLU):
     h_l = h_{l-1} + relu([h_{l-1}, a_l] W_l + b_l)      l = 1..L
     y   = h_L w_out + b_out
 
-Loss over the nodes of one sample, either in enthalpy, mean_i (y_i - t_i)^2 with
-t_i = (H_true_i - base_i) / (c_i DH_SCALE), or in temperature,
-mean_i ((T(H_pred_i) - T(H_true_i)) / DT_SCALE)^2.
+Loss over the rows of one sample, a mean over all rows of the masked terms:
+in enthalpy, mu_i (y'_i - t_i)^2 with t_i = (H_true_i - base_i) / s_i (or its
+Huber form), or in temperature, ((T(H_pred_i) - T(H_true_i)) / DT_SCALE)^2.
 """
 import numpy as np
 
@@ -39,9 +52,10 @@ from . import oracle as orc
 
 T_REF = 25.0
 T_SCALE = 700.0
-DH_SCALE = 10.0   # K of sensible heat per unit of network output
 DT_SCALE = 10.0   # K per unit of the temperature loss
-N_FEAT = 9
+EPS_T = 0.01      # K: activity floor of the correction scale
+REACH = 2.0       # a kink within REACH activities of H2 enables the correction
+N_FEAT = 12
 
 
 def _tri_area(x):
@@ -97,38 +111,68 @@ def node_strengths(prob):
     return dict(mc=mc, robin_b=b, iface_w=w, kabs=kabs, node_mat=nmat)
 
 
+def _materials(prob, strengths):
+    mats = np.asarray(prob["materials"], np.float64).reshape(-1, 6)
+    return mats[strengths["node_mat"]]
+
+
+def activity(prob, H0, H1, H2, horizon=16, strengths=None):
+    """Per node: the activity s, the mask mu (bool) and the kink enthalpies (H_sol, H_liq)."""
+    st = node_strengths(prob) if strengths is None else strengths
+    m_ = _materials(prob, st)
+    c, Ts, Tl, L = m_[:, 2], m_[:, 3], m_[:, 4], m_[:, 5]
+    H0, H1, H2 = (np.asarray(a, np.float64) for a in (H0, H1, H2))
+    m = horizon - 2
+    q = 0.5 * m * (m + 1)
+    r = H2 - H1
+    a = (H2 - H1) - (H1 - H0)
+    span = np.abs(m * r) + np.abs(q * a)
+    s = span + c * EPS_T
+    H_sol, H_liq = c * Ts, c * Tl + L
+    free = np.ones(H2.size, bool)
+    free[np.asarray(prob.get("dirichlet_nodes", np.zeros(0, np.int64)), np.int64)] = False
+    near = (np.abs(H2 - H_liq) < REACH * span) | (np.abs(H2 - H_sol) < REACH * span)
+    mu = free & (L > 0) & near
+    return s, mu, H_sol, H_liq
+
+
 def features(prob, H0, H1, H2, dt, horizon=16, strengths=None):
     """The node features of the module docstring for one triple of states (FP64)."""
     st = node_strengths(prob) if strengths is None else strengths
-    mats = np.asarray(prob["materials"], np.float64).reshape(-1, 6)
-    nm = st["node_mat"]
+    m_ = _materials(prob, st)
+    c, L = m_[:, 2], m_[:, 5]
     H0, H1, H2 = (np.asarray(a, np.float64) for a in (H0, H1, H2))
+    s, _, H_sol, H_liq = activity(prob, H0, H1, H2, horizon, st)
     T2, fs2 = orc.state_T(orc.Problem(prob), H2)
-    c = mats[nm, 2]
+    m = horizon - 2
+    q = 0.5 * m * (m + 1)
+    lat = L > 0
     X = np.empty((H2.size, N_FEAT))
     X[:, 0] = (T2 - T_REF) / T_SCALE
     X[:, 1] = fs2
-    X[:, 2] = (mats[nm, 5] > 0).astype(np.float64)
+    X[:, 2] = lat.astype(np.float64)
     X[:, 3] = st["robin_b"] * dt / st["mc"]
     X[:, 4] = 2.0 * st["iface_w"] * dt / st["mc"]
     X[:, 5] = st["kabs"] * dt / st["mc"]
-    X[:, 6] = horizon * (H2 - H1) / (c * T_SCALE)
-    X[:, 7] = horizon ** 2 * ((H2 - H1) - (H1 - H0)) / (2.0 * c * T_SCALE)
+    X[:, 6] = m * (H2 - H1) / s
+    X[:, 7] = q * ((H2 - H1) - (H1 - H0)) / s
     X[:, 8] = 1.0
+    X[:, 9] = np.log(s / c) / 8.0
+    X[:, 10] = np.where(lat, np.clip((H2 - H_liq) / s, -4.0, 4.0) / 4.0, 0.0)
+    X[:, 11] = np.where(lat, np.clip((H2 - H_sol) / s, -4.0, 4.0) / 4.0, 0.0)
     return X
 
 
-def base_and_target(prob, H0, H1, H2, Ht, horizon=16, quadratic=False):
-    """Extrapolation to step `horizon` (linear through H1, H2, or quadratic through H0, H1, H2)
-    and the target (Ht - base) / (c DH_SCALE)."""
-    mats = np.asarray(prob["materials"], np.float64).reshape(-1, 6)
-    c = mats[orc.node_material(orc.Problem(prob)), 2]
+def base_and_target(prob, H0, H1, H2, Ht, horizon=16, quadratic=False, strengths=None):
+    """Extrapolation to step `horizon` (linear through H1, H2, or quadratic through H0, H1, H2),
+    the target (Ht - base) / s, and the correction scale mu s."""
     H0, H1, H2, Ht = (np.asarray(a, np.float64) for a in (H0, H1, H2, Ht))
     m = horizon - 2
     base = H2 + m * (H2 - H1)
     if quadratic:
         base = base + 0.5 * m * (m + 1) * ((H2 - H1) - (H1 - H0))
-    return base, (Ht - base) / (c * DH_SCALE), c
+    s, mu, _, _ = activity(prob, H0, H1, H2, horizon, strengths)
+    return base, (Ht - base) / s, np.where(mu, s, 0.0)
 
 
 def flatten_params(p, layers):
@@ -214,13 +258,14 @@ def _identity(x):
     return x
 
 
-def projection_weights(prob, strengths=None):
-    """w_i = m_i c_i / sum_j m_j c_j over the free nodes (0 at fixed-temperature nodes)."""
+def projection_weights(prob, scale, strengths=None):
+    """w_i = m_i scale_i / sum_j m_j scale_j (m the lumped mass, scale = mu s); all zero when
+    no node is masked."""
     st = node_strengths(prob) if strengths is None else strengths
-    w = st["mc"].copy()
-    d = np.asarray(prob.get("dirichlet_nodes", np.zeros(0, np.int64)), np.int64)
-    w[d] = 0.0
-    return w / w.sum()
+    c = _materials(prob, st)[:, 2]
+    w = st["mc"] / c * np.asarray(scale, np.float64)
+    tot = w.sum()
+    return w / tot if tot > 0 else np.zeros_like(w)
 
 
 def forward(p, X, ptr, col, layers, bf16=False, proj_w=None):
@@ -250,28 +295,32 @@ def forward(p, X, ptr, col, layers, bf16=False, proj_w=None):
     return y, cache
 
 
-def h_loss(t):
-    """Enthalpy loss mean (y - t)^2 and its derivative in y."""
+def h_loss(t, mask=None):
+    """Enthalpy loss mean(mu (y - t)^2) over all rows and its derivative in y."""
+    mu = np.ones_like(t) if mask is None else np.asarray(mask, np.float64)
+
     def f(y):
-        return float(np.mean((y - t) ** 2)), 2.0 * (y - t) / y.size
+        return float(np.mean(mu * (y - t) ** 2)), 2.0 * mu * (y - t) / y.size
     return f
 
 
 HUBER_DELTA = 0.1
 
 
-def huber_loss(t, delta=HUBER_DELTA):
-    """mean of e^2 (|e| <= delta) or delta (2|e| - delta), e = y - t, and its derivative."""
+def huber_loss(t, mask=None, delta=HUBER_DELTA):
+    """mean of mu (e^2 (|e| <= delta) or delta (2|e| - delta)), e = y - t, and its derivative."""
+    mu = np.ones_like(t) if mask is None else np.asarray(mask, np.float64)
+
     def f(y):
         e = y - t
         a = np.abs(e)
         L = np.where(a <= delta, e * e, delta * (2.0 * a - delta))
-        return float(np.mean(L)), 2.0 * np.clip(e, -delta, delta) / y.size
+        return float(np.mean(mu * L)), 2.0 * mu * np.clip(e, -delta, delta) / y.size
     return f
 
 
-def t_loss(prob, base, H_true):
-    """Temperature loss mean ((T(base + c DH_SCALE y) - T(H_true)) / DT_SCALE)^2 and its
+def t_loss(prob, base, H_true, scale):
+    """Temperature loss mean ((T(base + scale y) - T(H_true)) / DT_SCALE)^2 and its
     derivative in y, through the slope of the branch of T(H) the prediction lies on
     (1/c outside the mushy range, (T_liq - T_sol) / (c (T_liq - T_sol) + L) inside)."""
     P = orc.Problem(prob)
@@ -280,7 +329,7 @@ def t_loss(prob, base, H_true):
     c, Ts, Tl, L = m[:, 2], m[:, 3], m[:, 4], m[:, 5]
     mushy_slope = np.where(L > 0, (Tl - Ts) / (c * (Tl - Ts) + L), 0.0)
     T_true, _ = orc.state_T(P, H_true)
-    scale = c * DH_SCALE
+    scale = np.asarray(scale, np.float64)
 
     def f(y):
         Hp = base + scale * y

@@ -368,7 +368,7 @@ def fem_sur_set_params(s, params):
     _call("fem_sur_set_params", s, _p(p), p.size)
 
 
-N_FEAT = 9
+N_FEAT = 12
 
 
 def fem_sur_features(s, H0_ptr, H1_ptr, H2_ptr, stride, slots, n_nodes):
@@ -407,7 +407,7 @@ def fem_snapshot_H(ctx, out_ptr):
     _call("fem_snapshot_H", ctx, C.c_void_p(out_ptr))
 
 
-def fem_advance(ctx, sur, dt_per_scenario, max_steps, until_solid=True, energy_tol=1e-4, fs_tol=1e-6, verify_tol=1.0):
+def fem_advance(ctx, sur, dt_per_scenario, max_steps, until_solid=True, energy_tol=1e-4, fs_tol=1e-4, verify_tol=3.0):
     dt = np.ascontiguousarray(np.atleast_1d(dt_per_scenario), np.float64)
     rep = fem_advance_report()
     _call("fem_advance", ctx, sur, _p(dt), int(max_steps), int(bool(until_solid)), float(energy_tol),
@@ -512,8 +512,8 @@ class Solver:
         fem_snapshot_H(self.ctx, out.data_ptr())
         self.torch.cuda.current_stream(self.device).wait_stream(self.stream)
 
-    def advance(self, dt_per_scenario, max_steps, surrogate=None, until_solid=True, energy_tol=1e-4, fs_tol=1e-6,
-                verify_tol=1.0):
+    def advance(self, dt_per_scenario, max_steps, surrogate=None, until_solid=True, energy_tol=1e-4, fs_tol=1e-4,
+                verify_tol=3.0):
         return fem_advance(self.ctx, surrogate.sur if surrogate is not None else None, dt_per_scenario, max_steps,
                            until_solid, energy_tol, fs_tol, verify_tol)
 

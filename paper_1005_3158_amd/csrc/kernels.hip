@@ -443,6 +443,21 @@ __global__ __launch_bounds__(256) void k_copy(float4 *__restrict__ dst, const fl
     for (; i < n; i += stride) dst[i] = src[i];
 }
 
+// the read-back of one check: integer check counts, per-segment diagnostics and
+// per-node inflow sums gathered into one page-locked host buffer that the
+// device writes directly (each part at a 16-byte aligned offset)
+__global__ __launch_bounds__(256) void k_stage(int32_t *__restrict__ dst_chk, const int32_t *__restrict__ chk,
+                                               int64_t n_chk, double *__restrict__ dst_dg,
+                                               const double *__restrict__ dg, int64_t n_dg,
+                                               double *__restrict__ dst_qn, const double *__restrict__ qn,
+                                               int64_t n_qn) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t i = t; i < n_chk; i += stride) dst_chk[i] = chk[i];
+    for (int64_t i = t; i < n_dg; i += stride) dst_dg[i] = dg[i];
+    for (int64_t i = t; i < n_qn; i += stride) dst_qn[i] = qn[i];
+}
+
 template <class R, int NEN>
 hipError_t step_t(const Dev &d, int parity, hipStream_t s, hipEvent_t *ev) {
     if (ev) (void)hipEventRecord(ev[0], s);
@@ -495,6 +510,14 @@ hipError_t set_block_lds_limit(int prec, int nen, size_t bytes) {
     if (prec == FEM_PREC_FP64) f = nen == 4 ? (const void *)k_block<double, 4> : (const void *)k_block<double, 8>;
     else f = nen == 4 ? (const void *)k_block<float, 4> : (const void *)k_block<float, 8>;
     return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+hipError_t enqueue_stage(int32_t *dst_chk, const int32_t *chk, int64_t n_chk, double *dst_dg, const double *dg,
+                         int64_t n_dg, double *dst_qn, const double *qn, int64_t n_qn, hipStream_t s) {
+    const int64_t n = std::max(n_chk, std::max(n_dg, n_qn));
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 1024));
+    hipLaunchKernelGGL(k_stage, dim3(grid), dim3(256), 0, s, dst_chk, chk, n_chk, dst_dg, dg, n_dg, dst_qn, qn, n_qn);
+    return hipGetLastError();
 }
 
 hipError_t enqueue_copy(void *dst, const void *src, int64_t n16, hipStream_t s) {

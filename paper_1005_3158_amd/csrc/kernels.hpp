@@ -80,5 +80,8 @@ hipError_t enqueue_state_diag(const Dev &d, int parity, hipStream_t s);
 hipError_t set_block_lds_limit(int prec, int nen, size_t bytes);
 // Plain vector copy of n16 16-byte words.
 hipError_t enqueue_copy(void *dst, const void *src, int64_t n16, hipStream_t s);
+// Copy check counts, diagnostics and inflow sums into page-locked host memory the device can write.
+hipError_t enqueue_stage(int32_t *dst_chk, const int32_t *chk, int64_t n_chk, double *dst_dg, const double *dg,
+                         int64_t n_dg, double *dst_qn, const double *qn, int64_t n_qn, hipStream_t s);
 
 }  // namespace castfem

@@ -111,8 +111,8 @@ void sur_sizes(fem_sur *s) {
     z[S_SCEN] = N * 4;
     z[S_SCEN_SEG_PTR] = (s->n_scen + 1) * 4;
     z[S_SCEN_SEG] = s->n_seg * 4;
-    z[S_SEG_PART] = (int64_t)s->opt.max_samples * s->n_seg * 8;
-    z[S_SCEN_SUM] = (int64_t)s->opt.max_samples * s->n_scen * 8;
+    z[S_SEG_PART] = (int64_t)s->opt.max_samples * s->n_seg * 16;
+    z[S_SCEN_SUM] = (int64_t)s->opt.max_samples * s->n_scen * 16;
     if (tr) {
         z[S_GRADS] = P * 4;
         z[S_ADAM_M] = P * 4;
@@ -167,7 +167,8 @@ void build_graph(fem_sur *s) {
 }
 
 // per-node strengths over m_i c_i (Robin, interface, conduction), the scenario
-// of every node and the weights m_i c_i / sum over its scenario's free nodes
+// of every node and its lumped mass over the sum of its scenario's free nodes
+// (the mass part of the projection weight m_i mu_i s_i)
 void build_coef(fem_sur *s) {
     const fem_ctx *c = s->ctx;
     const Layout &L = c->L();
@@ -185,13 +186,11 @@ void build_coef(fem_sur *s) {
         s->coef[4 * g + 1] = (float)(2.0 * wl / mc);
         s->coef[4 * g + 2] = (float)(b.kabs[o] / mc);
         s->scen[g] = c->prob.scen_of_mat(b.nmat[o]);
-        if (!(L.nflag[g] & NODE_FIXED)) tot[s->scen[g]] += mc;
+        if (!(L.nflag[g] & NODE_FIXED)) tot[s->scen[g]] += b.m[o];
     }
     for (int64_t g = 0; g < L.N; ++g) {
-        const int32_t o = L.iperm[g];
-        const double mc = b.m[o] * c->prob.mats[b.nmat[o]].c;
         const double t = tot[s->scen[g]];
-        s->coef[4 * g + 3] = (L.nflag[g] & NODE_FIXED) || !(t > 0) ? 0.0f : (float)(mc / t);
+        s->coef[4 * g + 3] = (L.nflag[g] & NODE_FIXED) || !(t > 0) ? 0.0f : (float)(b.m[L.iperm[g]] / t);
     }
     // segments of every scenario (the context's single-scenario node segments)
     s->n_seg = (int64_t)L.seg_scen.size();
@@ -411,33 +410,50 @@ void run_chunk(fem_sur *s, int what, int p, float fs_tol, float verify_tol) {
 }
 
 // page-locked staging of the per-chunk read-back (check counts, state
-// diagnostics, inflow sums): one stream synchronisation per chunk
+// diagnostics, inflow sums), written by one device kernel: one launch and one
+// stream synchronisation per check
 struct Staging {
     void *p = nullptr;
-    size_t chk = 0, dg = 0, qn = 0;
-    Staging(size_t chk_bytes, size_t dg_bytes, size_t qn_bytes) : chk(chk_bytes), dg(dg_bytes), qn(qn_bytes) {
-        HIPCHECK(hipHostMalloc(&p, std::max<size_t>(chk + dg + qn, 64), hipHostMallocDefault));
+    char *dev = nullptr;                  // the same memory as the device addresses it
+    size_t n_chk = 0, n_dg = 0, n_qn = 0; // element counts
+    size_t off_dg = 0, off_qn = 0;        // 16-byte aligned byte offsets
+    Staging(size_t chk_count, size_t dg_count, size_t qn_count) : n_chk(chk_count), n_dg(dg_count), n_qn(qn_count) {
+        auto up16 = [](size_t b) { return (b + 15) & ~(size_t)15; };
+        off_dg = up16(n_chk * 4);
+        off_qn = off_dg + up16(n_dg * 8);
+        const size_t bytes = std::max<size_t>(off_qn + up16(n_qn * 8), 64);
+        HIPCHECK(hipHostMalloc(&p, bytes, hipHostMallocMapped | hipHostMallocCoherent));
+        void *d = nullptr;
+        const hipError_t e = hipHostGetDevicePointer(&d, p, 0);
+        if (e != hipSuccess) {
+            (void)hipHostFree(p);
+            p = nullptr;
+            HIPCHECK(e);
+        }
+        dev = (char *)d;
     }
     ~Staging() {
         if (p) (void)hipHostFree(p);
     }
-    char *at(size_t off) { return (char *)p + off; }
+    const int32_t *chk() const { return (const int32_t *)p; }
+    const double *dg() const { return (const double *)((const char *)p + off_dg); }
+    const double *qn() const { return (const double *)((const char *)p + off_qn); }
 };
 
-// enqueue the copies of the state diagnostics and inflow sums of ctx (and the
-// check counts of s, if any) into the staging buffer
+// enqueue the staging of the state diagnostics and inflow sums of ctx (and the
+// check counts of s, if any)
 void stage_copies(fem_ctx *ctx, fem_sur *s, Staging &sg) {
-    hipStream_t st = ctx->stream;
-    if (s && sg.chk) HIPCHECK(hipMemcpyAsync(sg.at(0), s->ptr[S_CHECK], sg.chk, hipMemcpyDeviceToHost, st));
-    HIPCHECK(hipMemcpyAsync(sg.at(sg.chk), ctx->ptr[B_DIAG], sg.dg, hipMemcpyDeviceToHost, st));
-    if (sg.qn) HIPCHECK(hipMemcpyAsync(sg.at(sg.chk + sg.dg), ctx->ptr[B_QNODE], sg.qn, hipMemcpyDeviceToHost, st));
+    const bool chk = s && sg.n_chk;
+    HIPCHECK(enqueue_stage((int32_t *)sg.dev, chk ? (const int32_t *)s->ptr[S_CHECK] : nullptr, chk ? sg.n_chk : 0,
+                           (double *)(sg.dev + sg.off_dg), (const double *)ctx->ptr[B_DIAG], sg.n_dg,
+                           (double *)(sg.dev + sg.off_qn), (const double *)ctx->ptr[B_QNODE], sg.n_qn, ctx->stream));
 }
 
-// after a stream sync: the per-scenario energy reports from the staged copies
+// after a stream sync: the per-scenario energy reports from the staged values
 void staged_energy(fem_ctx *ctx, Staging &sg, std::vector<double> &dg, std::vector<double> &qn,
                    fem_energy_report *er) {
-    dg.assign((const double *)sg.at(sg.chk), (const double *)sg.at(sg.chk + sg.dg));
-    qn.assign((const double *)sg.at(sg.chk + sg.dg), (const double *)sg.at(sg.chk + sg.dg + sg.qn));
+    dg.assign(sg.dg(), sg.dg() + sg.n_dg);
+    qn.assign(sg.qn(), sg.qn() + sg.n_qn);
     energy_reduce(ctx, dg, qn, er);
 }
 
@@ -754,7 +770,7 @@ int fem_advance(fem_ctx *ctx, fem_sur *s, const double *dt_per_scenario, int64_t
         }
         const int64_t nchk = check_blocks(ctx->L().N);
         std::vector<double> dg, qn;
-        Staging sg(s ? 2 * nchk * 4 : 0, ctx->L().seg_scen.size() * NDIAG * 8, ctx->L().n_inflow * 8);
+        Staging sg(s ? 2 * nchk : 0, ctx->L().seg_scen.size() * NDIAG, ctx->L().n_inflow);
         // plain chunk: steps, diagnostics, one read-back
         auto plain_chunk = [&](int64_t n) {
             run_steps(ctx, n);
@@ -782,7 +798,7 @@ int fem_advance(fem_ctx *ctx, fem_sur *s, const double *dt_per_scenario, int64_t
             stage_copies(ctx, s, sg);
             HIPCHECK(hipStreamSynchronize(st));
             staged_energy(ctx, sg, dg, qn, er.data());
-            const int32_t *chk = (const int32_t *)sg.at(0);
+            const int32_t *chk = sg.chk();
             int64_t bad_fs = 0, bad_verify = 0;
             for (int64_t k = 0; k < nchk; ++k) {
                 bad_fs += chk[k];

@@ -64,7 +64,13 @@ __global__ __launch_bounds__(256) void k_features(SurDev s, const HT *H0, const 
     double T2, fs2;
     t_of_h(M, h2, T2, fs2);
     const float4 co = ((const float4 *)s.coef)[i];
-    const double c = M.c, dt = M.dt, hz = (double)s.horizon, m = hz - 2.0;
+    const double c = M.c, dt = M.dt, m = (double)s.horizon - 2.0, qm = 0.5 * m * (m + 1.0);
+    // activity over the window and the kinks within reach of it
+    const double span = fabs(m * rate) + fabs(qm * acc);
+    const double sa = span + c * EPS_T;
+    const bool free = !(s.flags[i] & NODE_FIXED);
+    const bool near = fabs(h2 - M.Hl) < REACH * span || fabs(h2 - M.Hs) < REACH * span;
+    const bool mu = free && M.latent && near;
     float x[NFEAT];
     x[0] = (float)((T2 - T_REF) / T_SCALE);
     x[1] = (float)fs2;
@@ -72,9 +78,12 @@ __global__ __launch_bounds__(256) void k_features(SurDev s, const HT *H0, const 
     x[3] = (float)(co.x * dt);
     x[4] = (float)(co.y * dt);
     x[5] = (float)(co.z * dt);
-    x[6] = (float)(hz * rate / (c * T_SCALE));
-    x[7] = (float)(0.5 * hz * hz * acc / (c * T_SCALE));
+    x[6] = (float)(m * rate / sa);
+    x[7] = (float)(qm * acc / sa);
     x[8] = 1.0f;
+    x[9] = (float)(log(sa / c) / 8.0);
+    x[10] = M.latent ? (float)(fmin(fmax((h2 - M.Hl) / sa, -4.0), 4.0) / 4.0) : 0.0f;
+    x[11] = M.latent ? (float)(fmin(fmax((h2 - M.Hs) / sa, -4.0), 4.0) / 4.0) : 0.0f;
     uint32_t w[KIN / 2];
     for (int k = 0; k < KIN / 2; ++k) {
         const float lo = 2 * k < NFEAT ? x[2 * k] : 0.0f, hi = 2 * k + 1 < NFEAT ? x[2 * k + 1] : 0.0f;
@@ -84,17 +93,17 @@ __global__ __launch_bounds__(256) void k_features(SurDev s, const HT *H0, const 
     out[0] = make_uint4(w[0], w[1], w[2], w[3]);
     out[1] = make_uint4(w[4], w[5], w[6], w[7]);
     // linear extrapolation through H1, H2, or quadratic through H0, H1, H2
-    s.base[r] = s.quadratic ? h2 + m * rate + 0.5 * m * (m + 1.0) * acc : h2 + m * rate;
+    s.base[r] = s.quadratic ? h2 + m * rate + qm * acc : h2 + m * rate;
     // the increment of the step after the horizon that the extrapolation implies
     if (r < s.N) s.rext[r] = s.quadratic ? rate + (m + 1.0) * acc : rate;
-    s.scale[r] = (float)(c * DH_SCALE);
+    s.scale[r] = mu ? (float)sa : 0.0f;
     if (Ht) {
         if (s.loss_mode == LOSS_T) {
             double Tt, fst;
             t_of_h(M, (double)Ht[at], Tt, fst);
             s.target[r] = (float)Tt;
         } else {
-            s.target[r] = (float)(((double)Ht[at] - s.base[r]) / (c * DH_SCALE));   // LOSS_H, LOSS_HUBER
+            s.target[r] = (float)(((double)Ht[at] - s.base[r]) / sa);   // LOSS_H, LOSS_HUBER
         }
     }
 }
@@ -392,50 +401,79 @@ __global__ __launch_bounds__(256) void k_relu_back(const float *dH, const bf16 *
 }
 
 // ---------------------------------------------------------------- energy-neutral correction
-// seg_part[q][g] = sum over the nodes i of segment g of (w ? w_i : 1) v[q N + i]
+// weighted (forward): seg_part[q][g] = (sum w_i v_i, sum w_i) over the nodes i
+// of segment g, w_i = m_i mu_i s_i (coef.w times scale); otherwise (backward)
+// the plain sum of v in the first slot
 __global__ __launch_bounds__(256) void k_seg_sum(SurDev s, const float *v, int weighted) {
-    __shared__ double part[4];
+    __shared__ double part[2][4];
     const int64_t g = blockIdx.x, q = blockIdx.y;
     const int32_t b = s.seg_begin[g], e = s.seg_begin[g + 1];
-    double acc = 0.0;
+    double acc = 0.0, accw = 0.0;
     for (int32_t i = b + (int32_t)threadIdx.x; i < e; i += blockDim.x) {
-        const double w = weighted ? (double)((const float4 *)s.coef)[i].w : 1.0;
-        acc += w * (double)v[q * s.N + i];
+        if (weighted) {
+            const double w = (double)((const float4 *)s.coef)[i].w * (double)s.scale[q * s.N + i];
+            acc += w * (double)v[q * s.N + i];
+            accw += w;
+        } else {
+            acc += (double)v[q * s.N + i];
+        }
     }
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+    for (int off = 32; off > 0; off >>= 1) {
+        acc += __shfl_down(acc, off, 64);
+        accw += __shfl_down(accw, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        part[0][threadIdx.x >> 6] = acc;
+        part[1][threadIdx.x >> 6] = accw;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) s.seg_part[q * s.n_seg + g] = ((part[0] + part[1]) + part[2]) + part[3];
+    if (threadIdx.x == 0) {
+        double *o = s.seg_part + 2 * (q * s.n_seg + g);
+        o[0] = ((part[0][0] + part[0][1]) + part[0][2]) + part[0][3];
+        o[1] = ((part[1][0] + part[1][1]) + part[1][2]) + part[1][3];
+    }
 }
 
-// scen_sum[q][c] = sum of the segment partials of scenario c, in segment order
-__global__ void k_scen_sum(SurDev s, int64_t slots) {
+// the segment partials of every scenario summed in segment order; weighted:
+// scen_sum[q][c] = (sum w y / sum w, sum w) (0 for the mean where nothing is
+// masked), otherwise the first slot alone takes the plain sum
+__global__ void k_scen_sum(SurDev s, int64_t slots, int weighted) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= slots * s.n_scen) return;
     const int64_t q = t / s.n_scen, c = t - q * s.n_scen;
-    double acc = 0.0;
-    for (int32_t k = s.scen_seg_ptr[c]; k < s.scen_seg_ptr[c + 1]; ++k) acc += s.seg_part[q * s.n_seg + s.scen_seg[k]];
-    s.scen_sum[t] = acc;
+    double acc = 0.0, accw = 0.0;
+    for (int32_t k = s.scen_seg_ptr[c]; k < s.scen_seg_ptr[c + 1]; ++k) {
+        const double *p = s.seg_part + 2 * (q * s.n_seg + s.scen_seg[k]);
+        acc += p[0];
+        accw += p[1];
+    }
+    if (weighted) {
+        s.scen_sum[2 * t] = accw > 0.0 ? acc / accw : 0.0;
+        s.scen_sum[2 * t + 1] = accw;
+    } else {
+        s.scen_sum[2 * t] = acc;
+    }
 }
 
-// forward: y_i -= sum_j w_j y_j over the node's scenario (sum_i w_i y_i becomes 0)
+// forward: y_i -= the weighted mean of y over the node's scenario (sum_i w_i y_i becomes 0)
 __global__ __launch_bounds__(256) void k_proj_fwd(SurDev s, int64_t R) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= R) return;
     const int64_t q = r / s.N, i = r - q * s.N;
-    s.y[r] = (float)((double)s.y[r] - s.scen_sum[q * s.n_scen + s.scen[i]]);
+    s.y[r] = (float)((double)s.y[r] - s.scen_sum[2 * (q * s.n_scen + s.scen[i])]);
 }
 
-// backward: with g = dL/dy (in y), dL/dy_raw_k = g_k - w_k sum_i g_i into dy, and
-// dH = dy_raw w_out.  Sixteen threads per row, four channels each.
+// backward: with g = dL/dy (in y), dL/dy_raw_k = g_k - (w_k / sum w) sum_i g_i into dy,
+// and dH = dy_raw w_out.  Sixteen threads per row, four channels each.
 __global__ __launch_bounds__(256) void k_proj_bwd(SurDev s, int64_t R) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t r = t >> 4;
     const int c4 = (int)(t & 15) * 4;
     if (r >= R) return;
     const int64_t q = r / s.N, i = r - q * s.N;
-    const double w = (double)((const float4 *)s.coef)[i].w;
-    const float dy = (float)((double)s.y[r] - w * s.scen_sum[q * s.n_scen + s.scen[i]]);
+    const double *ss = s.scen_sum + 2 * (q * s.n_scen + s.scen[i]);
+    const double w = ss[1] > 0.0 ? (double)((const float4 *)s.coef)[i].w * (double)s.scale[r] / ss[1] : 0.0;
+    const float dy = (float)((double)s.y[r] - w * ss[0]);
     if (c4 == 0) s.dy[r] = dy;
     const float4 wo = *(const float4 *)(s.params + s.pl.w_out + c4);
     *(float4 *)(s.dH + r * WIDTH + c4) = make_float4(dy * wo.x, dy * wo.y, dy * wo.z, dy * wo.w);
@@ -461,6 +499,8 @@ __global__ __launch_bounds__(256) void k_loss(SurDev s, int64_t R) {
             const double e = (Tp - (double)s.target[r]) / DT_SCALE;
             e2 = e * e;
             dy = (float)(2.0 * e / (double)R * dTdH * (double)s.scale[r] / DT_SCALE);
+        } else if (!(s.scale[r] > 0.f)) {
+            dy = 0.f;                                  // unmasked: the extrapolation stands
         } else if (s.loss_mode == LOSS_HUBER) {
             const float e = s.y[r] - s.target[r], a = fabsf(e);
             e2 = a <= HUBER_DELTA ? (double)e * (double)e : (double)HUBER_DELTA * (2.0 * (double)a - (double)HUBER_DELTA);
@@ -575,7 +615,7 @@ __global__ __launch_bounds__(256) void k_write_jump(SurDev s, Dev d, int parity,
             s.Hn[i] = s.H2[i];
         } else {
             const MatDev &M = d.mats[f & NODE_MAT_MASK];
-            const double Hn = s.base[i] + (double)s.scale[i] * ((double)s.y[i] - s.scen_sum[s.scen[i]]);
+            const double Hn = s.base[i] + (double)s.scale[i] * ((double)s.y[i] - s.scen_sum[2 * s.scen[i]]);
             s.Hn[i] = Hn;
             set_node<R>(d, i, M, Hn, (R *)d.T + parity * d.N);
             if (M.latent) {
@@ -657,7 +697,7 @@ hipError_t forward(const SurDev &s, int64_t R, int store, int project, hipStream
     for (int l = 0; l < s.layers; ++l) hipLaunchKernelGGL(k_layer, dim3(gl), dim3(256), 0, st, s, l, R, store);
     const int64_t slots = R / s.N;
     hipLaunchKernelGGL(k_seg_sum, dim3((unsigned)s.n_seg, (unsigned)slots), dim3(256), 0, st, s, (const float *)s.y, 1);
-    hipLaunchKernelGGL(k_scen_sum, dim3(grid_for(slots * s.n_scen, 256)), dim3(256), 0, st, s, slots);
+    hipLaunchKernelGGL(k_scen_sum, dim3(grid_for(slots * s.n_scen, 256)), dim3(256), 0, st, s, slots, 1);
     if (project) hipLaunchKernelGGL(k_proj_fwd, dim3(grid_for(R, 256)), dim3(256), 0, st, s, R);
     return hipGetLastError();
 }
@@ -666,7 +706,7 @@ hipError_t loss_and_dy(const SurDev &s, int64_t R, hipStream_t st) {
     hipLaunchKernelGGL(k_loss, dim3(grid_for(R, 256)), dim3(256), 0, st, s, R);
     const int64_t slots = R / s.N;
     hipLaunchKernelGGL(k_seg_sum, dim3((unsigned)s.n_seg, (unsigned)slots), dim3(256), 0, st, s, (const float *)s.y, 0);
-    hipLaunchKernelGGL(k_scen_sum, dim3(grid_for(slots * s.n_scen, 256)), dim3(256), 0, st, s, slots);
+    hipLaunchKernelGGL(k_scen_sum, dim3(grid_for(slots * s.n_scen, 256)), dim3(256), 0, st, s, slots, 0);
     hipLaunchKernelGGL(k_proj_bwd, dim3(grid_for(R * 16, 256)), dim3(256), 0, st, s, R);
     return hipGetLastError();
 }

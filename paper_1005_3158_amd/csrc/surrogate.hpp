@@ -1,11 +1,17 @@
 // Device layout and launchers of the message-passing surrogate (gfx950).
 //
 // Network (width WIDTH, LAYERS message-passing layers), per node row r:
-//   h_0 = relu(X W_in + b_in)                      X: 9 features padded to 16
+//   h_0 = relu(X W_in + b_in)                      X: 12 features padded to 16
 //   h_l = h_{l-1} + relu([h_{l-1}, A h_{l-1}] W_l + b_l)     A: mean over mesh neighbours
 //   y   = h_L . w_out + b_out
 // Activations are BF16, products run on MFMA (v_mfma_f32_16x16x16_bf16) with
 // FP32 accumulation; parameters, gradients and Adam moments are FP32.
+//
+// The jump H = base + mu s (y - ybar): base the time extrapolation over the
+// window, s = |m r| + |q a| + c EPS_T the node's activity over it, mu = 1 at a
+// free phase-change node whose H2 lies within REACH activities of a kink of
+// T(H) (the only places the extrapolation fails), else 0, and ybar the
+// m mu s weighted mean of y over the scenario (energy-neutral correction).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -17,12 +23,14 @@ namespace castfem {
 namespace sur {
 
 constexpr int WIDTH = 64;
-constexpr int NFEAT = 9;        // input features
+constexpr int NFEAT = 12;       // input features
 constexpr int KIN = 16;         // features padded to the MFMA K step
 constexpr int MAX_LAYERS = 4;
-constexpr float T_REF = 25.0f, T_SCALE = 700.0f, DH_SCALE = 10.0f, DT_SCALE = 10.0f;
+constexpr float T_REF = 25.0f, T_SCALE = 700.0f, DT_SCALE = 10.0f;
+constexpr double EPS_T = 0.01;   // K: activity floor of the correction scale
+constexpr double REACH = 2.0;    // a kink within REACH activities of H2 enables the correction
 enum { LOSS_H = 0, LOSS_T = 1, LOSS_HUBER = 2 };
-constexpr float HUBER_DELTA = 0.1f;   // Huber loss: quadratic within 0.1 output units (1 K of sensible heat)
+constexpr float HUBER_DELTA = 0.1f;   // Huber loss: quadratic within a tenth of the node's activity
 
 typedef uint16_t bf16;
 
@@ -49,7 +57,7 @@ struct SurDev {
     int64_t N = 0;            // nodes of the mesh (device numbering of the context)
     int layers = 3;
     int horizon = 16;         // explicit steps per jump
-    int loss_mode = LOSS_H;   // LOSS_H, LOSS_HUBER: target (Ht - base) / (c DH_SCALE); LOSS_T: target T(Ht)
+    int loss_mode = LOSS_H;   // LOSS_H, LOSS_HUBER: target (Ht - base) / s; LOSS_T: target T(Ht)
     int quadratic = 0;        // base: 0 linear through H1, H2; 1 quadratic through H0, H1, H2
     ParamLayout pl;
     // graph: mean over mesh neighbours
@@ -57,7 +65,7 @@ struct SurDev {
     const float *inv_deg = nullptr;
     // per-node strengths per unit time (times dt: per step), N x 4:
     // b_i / (m_i c_i), 2 sum_j w_ij / (m_i c_i), sum_j |K_ij| / (m_i c_i),
-    // and the projection weight m_i c_i / sum over the node's scenario (0 at fixed nodes)
+    // and the lumped mass m_i / sum over the node's scenario (0 at fixed nodes)
     const float *coef = nullptr;
     // energy-neutral correction: per node its scenario; node segments of one
     // scenario each (the context's), and the segments of every scenario (CSR)
@@ -65,8 +73,8 @@ struct SurDev {
     const int32_t *seg_begin = nullptr;
     int64_t n_seg = 0, n_scen = 1;
     const int32_t *scen_seg_ptr = nullptr, *scen_seg = nullptr;
-    double *seg_part = nullptr;           // slots x n_seg
-    double *scen_sum = nullptr;           // slots x n_scen
+    double *seg_part = nullptr;           // slots x n_seg x 2
+    double *scen_sum = nullptr;           // slots x n_scen x 2: the projected sum and sum m mu s
     const uint32_t *flags = nullptr;      // N: material | flags (shared with the context)
     const void *mats = nullptr;           // MatDev table of the context
     // parameters
@@ -83,7 +91,7 @@ struct SurDev {
     bf16 *HL = nullptr;                   // R x WIDTH last hidden state
     float *y = nullptr;                   // R outputs
     double *base = nullptr;               // R: extrapolated enthalpy
-    float *scale = nullptr;               // R: c_i * DH_SCALE
+    float *scale = nullptr;               // R: mu_i s_i (0 where the extrapolation stands)
     float *target = nullptr;              // R: training target (see loss_mode)
     // backward
     float *dH = nullptr;                  // R x WIDTH
@@ -122,7 +130,7 @@ hipError_t apply(const SurDev &s, int64_t rows, double *H_out, hipStream_t st); 
 // solver state <-> surrogate (d: the context's device layout, T buffer `parity`)
 hipError_t state_to_f64(const Dev &d, double *out, hipStream_t st);
 hipError_t state_to_f32(const Dev &d, float *out, hipStream_t st);
-// write H = base + scale * (y - the scenario's sum of w y) (one state slot,
+// write H = base + scale * (y - the scenario's weighted mean of y) (one state slot,
 // unprojected y) into the solver state with its T and fraction solid; counts
 // per workgroup the nodes whose fraction solid fell by more than fs_tol below
 // that of s.H2

@@ -83,6 +83,9 @@ def test_features_match_the_oracle(chill, gpu):
     assert np.all(err <= 2.0 ** -8 * np.abs(Xr) + 1e-30), float(np.max(err / (np.abs(Xr) + 1e-30)))
     assert np.count_nonzero(Xr[:, 3]) == 17 * 17     # the chill face
     assert np.all(Xr[:, 6] <= 0) and np.any(Xr[:, 6] < 0)   # the cube only cools
+    # the correction scale: the activity at the nodes near a kink, 0 elsewhere
+    _, _, scale = S.base_and_target(chill["p"], H[32], H[33], H[34], H[48], strengths=chill["st"])
+    assert 0 < np.count_nonzero(scale) < scale.size
 
 
 def _ref_loss_grad(chill, vparams, triples, loss_kind="H", bf16=False):
@@ -94,10 +97,12 @@ def _ref_loss_grad(chill, vparams, triples, loss_kind="H", bf16=False):
     for h0, h1, h2, ht in triples:
         h0, h1, h2, ht = (a.astype(np.float64) for a in (h0, h1, h2, ht))
         X = S.features(p, h0, h1, h2, chill["dt"], strengths=chill["st"])
-        base, t, _ = S.base_and_target(p, h0, h1, h2, ht)
-        f = t if loss_kind == "H" else (S.huber_loss(t) if loss_kind == "U" else S.t_loss(p, base, ht))
+        base, t, scale = S.base_and_target(p, h0, h1, h2, ht, strengths=chill["st"])
+        mask = scale > 0
+        assert mask.any()
+        f = {"H": S.h_loss(t, mask), "U": S.huber_loss(t, mask), "T": S.t_loss(p, base, ht, scale)}[loss_kind]
         l, g, _ = S.loss_and_grad(vparams, X, f, ptr, col, LAYERS, bf16=bf16,
-                                  proj_w=S.projection_weights(p, chill["st"]))
+                                  proj_w=S.projection_weights(p, scale, chill["st"]))
         gv = S.flatten_params(g, LAYERS)
         loss += l / len(triples)
         grad = gv / len(triples) if grad is None else grad + gv / len(triples)
@@ -107,7 +112,7 @@ def _ref_loss_grad(chill, vparams, triples, loss_kind="H", bf16=False):
 def _blocks():
     """(name, slice) of every parameter block in the flat vector."""
     out, o = [], 0
-    for name, n in [("W_in", 9 * 64), ("b_in", 64)] + sum([[("W%d" % l, 128 * 64), ("b%d" % l, 64)]
+    for name, n in [("W_in", 12 * 64), ("b_in", 64)] + sum([[("W%d" % l, 128 * 64), ("b%d" % l, 64)]
                                                           for l in range(LAYERS)], []) + [("w_out", 64), ("b_out", 1)]:
         out.append((name, slice(o, o + n)))
         o += n
@@ -133,8 +138,8 @@ def test_loss_and_gradients_match_the_fp64_reference(chill, gpu, slots, loss_kin
     # summation order differs: that is the parity bar.  Against exact FP64 the
     # BF16 rounding itself shows, amplified by cancellation in the gradient sums
     # (the projection makes dL/dy sum to zero per scenario): the reference's own
-    # BF16-vs-FP64 deviation on these states is up to 10 % in the loss, 27 % in a
-    # block and cosine 0.980, and the bounds below carry a margin over that.
+    # BF16-vs-FP64 deviation on these states is up to 6 % in the loss, 46 % in a
+    # block and cosine 0.965, and the bounds below carry a margin over that.
     assert loss == pytest.approx(loss_b, rel=1e-3)
     assert loss == pytest.approx(loss_r, rel=0.15)
     gnorm = np.linalg.norm(g_r)
@@ -147,10 +152,13 @@ def test_loss_and_gradients_match_the_fp64_reference(chill, gpu, slots, loss_kin
         rel_b = np.linalg.norm(g[sl] - g_b[sl]) / nr
         rel = np.linalg.norm(g[sl] - g_r[sl]) / nr
         print("%-6s |g| %.3e  vs bf16 ref %.2e  vs fp64 ref %.2e" % (name, nr, rel_b, rel))
-        assert rel_b <= 5e-3, name
-        assert rel <= 0.35, name
+        # a pre-activation whose FP32 sum lands on the other side of a BF16 rounding
+        # boundary (or of 0 at a ReLU) moves by one BF16 ulp: ~1e-3 of the gradient norm
+        # in absolute terms, ~6e-3 of a block the Huber clip has made small
+        assert rel_b <= 1e-2, name
+        assert rel <= 0.6, name
     cos = float(np.dot(g, g_r) / (np.linalg.norm(g) * gnorm))
-    assert cos >= 0.97
+    assert cos >= 0.95
 
 
 @pytest.mark.parametrize("quadratic", [False, True])
@@ -189,15 +197,6 @@ def test_parameters_round_trip_and_errors(gpu):
 
 
 # ------------------------------------------------------------------ gates and fallback
-def _anti_diffusive_net(sur, gain):
-    """y_i = gain (T_i - 25) / 700 through one hidden unit; the energy-neutral projection
-    then leaves gain (T_i - mean T) / 700: hot nodes heat up, cold ones cool down."""
-    v = np.zeros(sur.params().size, np.float32)
-    v[0] = 1.0                                  # W_in[feature 0][unit 0]
-    v[-65] = gain                               # w_out[0]
-    sur.set_params(v)
-
-
 def test_rejected_jumps_reproduce_the_plain_run_bitwise(orc):
     cf = _cf()
     p = configs.config4_trajectory(5001)
@@ -221,20 +220,23 @@ def test_rejected_jumps_reproduce_the_plain_run_bitwise(orc):
 
 
 def test_fraction_solid_gate(orc):
+    """An alloy cube in a sand mould re-melts a little next to the interface (f_s falls by up
+    to ~5e-3 within 16 steps at step 600 of the FP64 oracle's run), and the extrapolation
+    carries that fall into the jump: the gate rejects it, and lets the same jump through
+    once the tolerance is lifted."""
     cf = _cf()
-    p = configs.config4_trajectory(5001)
+    p = configs.tet_casting(n=10, region="cube", h_interface=1000.0)
     dt = 0.9 * orc.stable_dt(p)
     s = cf.Solver(p, **_fixed_layout(cf))
     s.step(dt, 600)
     fs = s.fs()
     assert np.any((fs > 0) & (fs < 1))          # a mushy zone exists
     ck = cf.fem_read_state(s.ctx)
-    sur = cf.Surrogate(s, layers=LAYERS)
-    _anti_diffusive_net(sur, 1000.0)            # re-melts the hotter part of the mushy zone
-    rep = s.advance(dt, 65, sur, until_solid=False, energy_tol=1e9, fs_tol=1e-6, verify_tol=1e9)
-    assert rep["jumps_accepted"] == 0 and rep["jumps_rejected"] == 4 and rep["rejected_fs"] == 4
+    sur = cf.Surrogate(s, layers=LAYERS)        # untrained: the jump is the extrapolation
+    rep = s.advance(dt, 17, sur, until_solid=False, energy_tol=1e9, fs_tol=1e-6, verify_tol=1e9)
+    assert rep["jumps_accepted"] == 0 and rep["jumps_rejected"] == 1 and rep["rejected_fs"] == 1
+    assert rep["steps"] == 16 and rep["plain_steps"] == 17
     cf.fem_write_state(s.ctx, ck)
-    # the same jump from the same state passes once the f_s tolerance is lifted
     rep = s.advance(dt, 17, sur, until_solid=False, energy_tol=1e9, fs_tol=1.0, verify_tol=1e9)
     assert rep["jumps_accepted"] == 1 and rep["plain_steps"] == 3 and rep["steps"] == 17
     e = s.energy()
@@ -244,18 +246,17 @@ def test_fraction_solid_gate(orc):
 
 
 def test_verification_gate(orc):
-    """A jump with a temperature error of a few K relaxes in the first explicit step
-    after it; the verification catches it although energy and f_s checks are off."""
+    """In the first steps of the chill the node rates change fast: the extrapolation of the
+    first chunk is off by far more than 1 K at the chill face and relaxes in the explicit
+    step after it; the verification catches it although energy and f_s checks are off."""
     cf = _cf()
     p = configs.config4_trajectory(5001)
     dt = 0.9 * orc.stable_dt(p)
     s = cf.Solver(p, **_fixed_layout(cf))
-    s.step(dt, 600)
     ck = cf.fem_read_state(s.ctx)
     sur = cf.Surrogate(s, layers=LAYERS)
-    _anti_diffusive_net(sur, 10.0)              # (T - mean T) / 7: several K at the hot and cold ends
-    rep = s.advance(dt, 65, sur, until_solid=False, energy_tol=1e9, fs_tol=1.0, verify_tol=1.0)
-    assert rep["jumps_accepted"] == 0 and rep["rejected_verify"] == 4
+    rep = s.advance(dt, 17, sur, until_solid=False, energy_tol=1e9, fs_tol=1.0, verify_tol=1.0)
+    assert rep["jumps_accepted"] == 0 and rep["rejected_verify"] == 1
     cf.fem_write_state(s.ctx, ck)
     rep = s.advance(dt, 65, sur, until_solid=False, energy_tol=1e9, fs_tol=1.0, verify_tol=1e9)
     assert rep["jumps_accepted"] == 4 and rep["rejected_verify"] == 0

@@ -37,32 +37,49 @@ def test_mean_operator_and_transpose():
 @pytest.mark.parametrize("layers,project", [(1, False), (3, False), (3, True)])
 def test_gradients_match_central_differences(layers, project):
     params, X, t, ptr, col, layers = small_case(layers=layers)
-    w = None
+    w, f = None, None
     if project:
-        w = np.random.default_rng(9).uniform(0.5, 1.5, t.size)
+        # the projection over a masked subset, and the loss over the same subset
+        rng = np.random.default_rng(9)
+        mask = rng.uniform(size=t.size) < 0.6
+        w = np.where(mask, rng.uniform(0.5, 1.5, t.size), 0.0)
         w /= w.sum()
-    loss, g, y = S.loss_and_grad(params, X, t, ptr, col, layers, proj_w=w)
+        f = S.h_loss(t, mask)
+    loss, g, y = S.loss_and_grad(params, X, t if f is None else f, ptr, col, layers, proj_w=w)
     if project:
         assert abs(np.dot(w, y)) <= 1e-14 * np.abs(y).max()
     rng = np.random.default_rng(3)
     eps = 1e-6
+
+    def L():
+        return S.loss_and_grad(params, X, t if f is None else f, ptr, col, layers, proj_w=w)[0]
     for name, val in params.items():
         idx = [tuple(rng.integers(0, s) for s in val.shape) for _ in range(4)]
         for ix in idx:
             old = val[ix]
             val[ix] = old + eps
-            lp, _, _ = S.loss_and_grad(params, X, t, ptr, col, layers, proj_w=w)
+            lp = L()
             val[ix] = old - eps
-            lm, _, _ = S.loss_and_grad(params, X, t, ptr, col, layers, proj_w=w)
+            lm = L()
             val[ix] = old
             fd = (lp - lm) / (2 * eps)
             assert g[name][ix] == pytest.approx(fd, rel=1e-5, abs=1e-9), (name, ix)
 
 
+def test_masked_loss_ignores_unmasked_rows():
+    params, X, t, ptr, col, layers = small_case(layers=2)
+    mask = np.arange(t.size) % 3 == 0
+    f = S.h_loss(t, mask)
+    loss, _, y = S.loss_and_grad(params, X, f, ptr, col, layers)
+    assert loss == pytest.approx(np.sum((y - t)[mask] ** 2) / t.size, rel=1e-13)
+    t2 = np.where(mask, t, t + 100.0)                # unmasked targets do not matter
+    assert S.loss_and_grad(params, X, S.h_loss(t2, mask), ptr, col, layers)[0] == pytest.approx(loss, rel=1e-13)
+
+
 def test_parameter_vector_layout():
     p = S.init_params(64, 3, 0)
     v = S.flatten_params(p, 3)
-    assert v.size == 9 * 64 + 64 + 3 * (128 * 64 + 64) + 64 + 1
+    assert v.size == 12 * 64 + 64 + 3 * (128 * 64 + 64) + 64 + 1
     q = S.unflatten_params(v, 64, 3)
     for k in p:
         assert np.array_equal(p[k], q[k])
@@ -122,22 +139,34 @@ def test_temperature_and_rate_features():
     p = configs.hex_cube(n=2, noise_amp=0.0, dirichlet_x0=None)
     mat = configs.ALLOY
     c, Ts, Tl, L = mat[2], mat[3], mat[4], mat[5]
+    Hs, Hl = c * Ts, c * Tl + L
     N = p["xyz"].shape[0]
-    H2 = np.full(N, c * Ts + 0.25 * L + 0.25 * c * (Tl - Ts))   # a quarter of the way through the mushy zone
+    H2 = np.full(N, Hs + 0.25 * (Hl - Hs))                        # a quarter of the way through the mushy zone
     H1 = H2 + 160.0
     H0 = H1 + 170.0                                                # the cooling slows down by 10 J/kg per step
     X = S.features(p, H0, H1, H2, 0.1, horizon=16)
     assert np.allclose(X[:, 0], (Ts + 0.25 * (Tl - Ts) - S.T_REF) / S.T_SCALE, rtol=1e-12)
     assert np.allclose(X[:, 1], 0.75, rtol=1e-12)
     assert np.all(X[:, 2] == 1) and np.all(X[:, 8] == 1)
-    assert np.allclose(X[:, 6], 16 * (-160.0) / (c * S.T_SCALE), rtol=1e-12)
-    assert np.allclose(X[:, 7], 128 * 10.0 / (c * S.T_SCALE), rtol=1e-12)
+    # activity over the window: |14 r| + |105 a| + c EPS_T with r = -160, a = 10
+    s = 14 * 160.0 + 105 * 10.0 + c * S.EPS_T
+    assert np.allclose(X[:, 6], 14 * (-160.0) / s, rtol=1e-12)
+    assert np.allclose(X[:, 7], 105 * 10.0 / s, rtol=1e-12)
+    assert np.allclose(X[:, 9], np.log(s / c) / 8, rtol=1e-12)
+    assert np.allclose(X[:, 10], -1.0) and np.allclose(X[:, 11], 1.0)    # both kinks beyond 4 activities
     # the quadratic through (0, H0), (1, H1), (2, H2) at 16: Lagrange weights 105, -224, 120
-    base, t, cc = S.base_and_target(p, H0, H1, H2, H2, horizon=16, quadratic=True)
+    base, t, scale = S.base_and_target(p, H0, H1, H2, H2, horizon=16, quadratic=True)
     assert np.allclose(base, 105 * H0 - 224 * H1 + 120 * H2, rtol=1e-13)
-    lin, t, cc = S.base_and_target(p, H0, H1, H2, H2, horizon=16)
+    lin, t, scale = S.base_and_target(p, H0, H1, H2, H2, horizon=16)
     assert np.allclose(lin, 15 * H2 - 14 * H1, rtol=1e-13)
-    assert np.allclose(t * cc * S.DH_SCALE, H2 - lin)
+    assert np.allclose(t * s, H2 - lin)
+    assert np.all(scale == 0)                      # no kink within reach: the jump is the extrapolation
+    # 1000 J/kg above the liquidus, the same history: the liquidus is within reach
+    d = Hl + 1000.0 - H2
+    X = S.features(p, H0 + d, H1 + d, H2 + d, 0.1, horizon=16)
+    assert np.allclose(X[:, 10], 1000.0 / s / 4, rtol=1e-12) and np.allclose(X[:, 11], 1.0)
+    _, _, scale = S.base_and_target(p, H0 + d, H1 + d, H2 + d, H2 + d, horizon=16)
+    assert np.allclose(scale, s, rtol=1e-13)
     # an exactly quadratic history is reproduced by the quadratic base, a linear one by both
     k = np.arange(17.0)
     hist = 6e5 - 150.0 * k + 2.5 * k ** 2
@@ -147,6 +176,25 @@ def test_temperature_and_rate_features():
     line = 6e5 - 150.0 * k
     h = [np.full(N, line[j]) for j in (0, 1, 2, 16)]
     assert np.allclose(S.base_and_target(p, *h)[0], line[16], rtol=1e-14)
+
+
+def test_mask_of_a_cube_in_a_mould():
+    # alloy cube in sand: only free alloy nodes near a kink carry a correction
+    p = configs.tet_casting(n=5, jitter=0, region="cube", h_interface=800.0, permute=False)
+    st = S.node_strengths(p)
+    mats = np.asarray(p["materials"], np.float64).reshape(-1, 6)[st["node_mat"]]
+    c, Ts, Tl, L = mats[:, 2], mats[:, 3], mats[:, 4], mats[:, 5]
+    N = c.size
+    H2 = c * Tl + L + 50.0                                      # 50 J/kg above the liquidus
+    H1 = H2 + 30.0
+    H0 = H1 + 30.0                                              # activity 14 * 30 + c EPS_T
+    s, mu, H_sol, H_liq = S.activity(p, H0, H1, H2, 16, st)
+    assert np.allclose(s, 14 * 30.0 + c * S.EPS_T, rtol=1e-13)
+    assert np.array_equal(mu, L > 0)                           # the mould has no kink
+    assert np.allclose(H_liq[L > 0], H2[L > 0] - 50.0)
+    # far above the liquidus nothing is masked
+    s2, mu2, _, _ = S.activity(p, H0 + 1e5, H1 + 1e5, H2 + 1e5, 16, st)
+    assert not mu2.any()
 
 
 def test_temperature_loss_gradient_matches_central_differences(orc):
@@ -165,9 +213,10 @@ def test_temperature_loss_gradient_matches_central_differences(orc):
     layers = 2
     params = S.init_params(8, layers, 1)
     params["w_out"] = rng.normal(0, 0.05, 8)
-    f = S.t_loss(p, base, H_true)
+    scale = rng.uniform(5e3, 1.5e4, N)
+    f = S.t_loss(p, base, H_true, scale)
     loss, g, y = S.loss_and_grad(params, X, f, ptr, col, layers)
-    assert np.max(np.abs(y)) * c * S.DH_SCALE < 1.5e4   # predictions stay on their branch
+    assert np.max(np.abs(y * scale)) < 1.5e4            # predictions stay on their branch
     eps = 1e-6
     for name in ("W_in", "W1", "w_out", "b_out"):
         val = params[name]
@@ -180,7 +229,7 @@ def test_temperature_loss_gradient_matches_central_differences(orc):
             val[ix] = old
             assert g[name][ix] == pytest.approx((lp - lm) / (2 * eps), rel=1e-5, abs=1e-10), (name, ix)
     # the loss is the mean squared temperature error in units of DT_SCALE
-    T_pred, _ = orc.state_T(p, base + c * S.DH_SCALE * y)
+    T_pred, _ = orc.state_T(p, base + scale * y)
     T_true, _ = orc.state_T(p, H_true)
     assert loss == pytest.approx(np.mean(((T_pred - T_true) / S.DT_SCALE) ** 2), rel=1e-12)
 
@@ -202,14 +251,25 @@ def test_bf16_reference_stays_close_to_exact():
 
 
 def test_projection_weights_of_the_chill_cube():
-    # uniform hex grid, one material: m_i c_i is rho c h^3 times 1, 1/2, 1/4 or 1/8
+    # uniform hex grid, one material: the lumped mass is rho h^3 times 1, 1/2, 1/4 or 1/8
     p = configs.hex_cube(n=4, noise_amp=0.0, dirichlet_x0=25.0)
-    w = S.projection_weights(p)
+    N = p["xyz"].shape[0]
+    free = np.setdiff1d(np.arange(N), p["dirichlet_nodes"])
+    scale = np.zeros(N)
+    scale[free] = 7.0
+    w = S.projection_weights(p, scale)
     assert w.sum() == pytest.approx(1.0, rel=1e-14)
     assert np.all(w[p["dirichlet_nodes"]] == 0)
-    free = np.setdiff1d(np.arange(w.size), p["dirichlet_nodes"])
     ratio = w[free] / w[free].max()
     assert set(np.round(ratio, 12)) <= {1.0, 0.5, 0.25, 0.125}
+    # a masked subset with different scales: w proportional to m scale on it, 0 elsewhere
+    sc = np.zeros(N)
+    sc[free[::2]] = np.linspace(1.0, 3.0, free[::2].size)
+    w = S.projection_weights(p, sc)
+    assert w.sum() == pytest.approx(1.0, rel=1e-14) and np.all(w[sc == 0] == 0)
+    m = S.node_strengths(p)["mc"]
+    assert np.allclose(w[sc > 0] / (m[sc > 0] * sc[sc > 0]), w[free[0]] / (m[free[0]] * sc[free[0]]), rtol=1e-12)
+    assert np.all(S.projection_weights(p, np.zeros(N)) == 0)
 
 
 def test_huber_loss_gradient_matches_central_differences():
