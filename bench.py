@@ -107,7 +107,7 @@ def main():
     ap.add_argument("--epochs", type=int, default=8, help="surrogate: training epochs per round")
     ap.add_argument("--rounds", type=int, default=1, help="surrogate: training rounds (later ones through jumps)")
     ap.add_argument("--verify-tol", type=float, default=3.0, help="surrogate: one-step verification tolerance (K)")
-    ap.add_argument("--fs-tol", type=float, default=1e-4,
+    ap.add_argument("--fs-tol", type=float, default=1e-6,
                     help="surrogate: largest fall of a node's fraction solid a kept jump may cause")
     ap.add_argument("--no-surrogate", action="store_true", help="default run: skip the surrogate comparison")
     ap.add_argument("--lr", type=float, default=1e-3, help="surrogate: initial learning rate")

@@ -407,7 +407,7 @@ def fem_snapshot_H(ctx, out_ptr):
     _call("fem_snapshot_H", ctx, C.c_void_p(out_ptr))
 
 
-def fem_advance(ctx, sur, dt_per_scenario, max_steps, until_solid=True, energy_tol=1e-4, fs_tol=1e-4, verify_tol=3.0):
+def fem_advance(ctx, sur, dt_per_scenario, max_steps, until_solid=True, energy_tol=1e-4, fs_tol=1e-6, verify_tol=3.0):
     dt = np.ascontiguousarray(np.atleast_1d(dt_per_scenario), np.float64)
     rep = fem_advance_report()
     _call("fem_advance", ctx, sur, _p(dt), int(max_steps), int(bool(until_solid)), float(energy_tol),
@@ -512,7 +512,7 @@ class Solver:
         fem_snapshot_H(self.ctx, out.data_ptr())
         self.torch.cuda.current_stream(self.device).wait_stream(self.stream)
 
-    def advance(self, dt_per_scenario, max_steps, surrogate=None, until_solid=True, energy_tol=1e-4, fs_tol=1e-4,
+    def advance(self, dt_per_scenario, max_steps, surrogate=None, until_solid=True, energy_tol=1e-4, fs_tol=1e-6,
                 verify_tol=3.0):
         return fem_advance(self.ctx, surrogate.sur if surrogate is not None else None, dt_per_scenario, max_steps,
                            until_solid, energy_tol, fs_tol, verify_tol)

@@ -405,26 +405,36 @@ __global__ __launch_bounds__(NODE_THREADS) void k_state(Dev d, int parity) {
     DiagAcc acc;
     acc.init();
     const int32_t n0 = d.seg_begin[blockIdx.x], n1 = d.seg_begin[blockIdx.x + 1];
-    for (int64_t i = n0 + (int64_t)threadIdx.x; i < n1; i += blockDim.x) {
-        const uint32_t f = d.flags[i];
-        const MatDev &M = d.mats[f & NODE_MAT_MASK];
-        double H;
-        if constexpr (std::is_same<R, float>::value) {
-            const float2 h = ((const float2 *)d.H)[i];
-            H = (double)h.x + (double)h.y;
-        } else {
-            H = ((const double *)d.H)[i];
+    // four nodes per thread per pass, their loads issued together
+    constexpr int U = 4;
+    for (int64_t i0 = n0 + (int64_t)threadIdx.x; i0 < n1; i0 += U * (int64_t)blockDim.x) {
+        uint32_t f[U];
+        double H[U], m[U], T[U];
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = i0 + u * (int64_t)blockDim.x;
+            const int64_t j = i < n1 ? i : i0;            // a valid node, not counted below
+            f[u] = d.flags[j];
+            if constexpr (std::is_same<R, float>::value) {
+                const float2 h = ((const float2 *)d.H)[j];
+                H[u] = (double)h.x + (double)h.y;
+            } else {
+                H[u] = ((const double *)d.H)[j];
+            }
+            m[u] = 1.0 / (double)((const R *)d.inv_m)[j];
+            T[u] = (double)((const R *)d.T)[parity * d.N + j];
         }
-        const double m = 1.0 / (double)((const R *)d.inv_m)[i];
-        const double T = (double)((const R *)d.T)[parity * d.N + i];
-        double Th, fs;
-        t_of_h(M, H, Th, fs);
-        acc.v[DG_E] += m * H;
-        acc.v[DG_LAT] += m * M.L * (1.0 - fs);
-        acc.v[DG_TMIN] = fmin(acc.v[DG_TMIN], T);
-        acc.v[DG_TMAX] = fmax(acc.v[DG_TMAX], T);
-        acc.v[DG_NLIQ] += (M.latent && fs < 1.0) ? 1.0 : 0.0;
-        acc.v[DG_NONFIN] += isfinite(H) ? 0.0 : 1.0;
+        for (int u = 0; u < U; ++u) {
+            if (i0 + u * (int64_t)blockDim.x >= n1) break;
+            const MatDev &M = d.mats[f[u] & NODE_MAT_MASK];
+            double Th, fs;
+            t_of_h(M, H[u], Th, fs);
+            acc.v[DG_E] += m[u] * H[u];
+            acc.v[DG_LAT] += m[u] * M.L * (1.0 - fs);
+            acc.v[DG_TMIN] = fmin(acc.v[DG_TMIN], T[u]);
+            acc.v[DG_TMAX] = fmax(acc.v[DG_TMAX], T[u]);
+            acc.v[DG_NLIQ] += (M.latent && fs < 1.0) ? 1.0 : 0.0;
+            acc.v[DG_NONFIN] += isfinite(H[u]) ? 0.0 : 1.0;
+        }
     }
     reduce_diag(d, acc, blockIdx.x);
 }

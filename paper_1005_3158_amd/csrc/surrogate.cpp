@@ -332,18 +332,15 @@ void enqueue_jump(fem_sur *s, int p, bool cont, float fs_tol, float verify_tol) 
     hipStream_t st = c->stream;
     int q = p;
     if (!cont) {
-        HIPCHECK(state_to_f64(c->dev, s->d.H0, st));
+        HIPCHECK(state_to_f64(c->dev, s->d.H0, nullptr, st));
         HIPCHECK(enqueue_step(c->dev, q, st, nullptr));
         q ^= 1;
     }
-    HIPCHECK(state_to_f64(c->dev, s->d.H1, st));
+    HIPCHECK(state_to_f64(c->dev, s->d.H1, nullptr, st));
     HIPCHECK(enqueue_step(c->dev, q, st, nullptr));
     q ^= 1;
-    HIPCHECK(state_to_f64(c->dev, s->d.H2, st));
-    // the inflow sums at H2, for a fallback to start from
-    const int64_t Q = c->L().n_inflow;
-    // (whole 16-byte words: both buffers are padded to 256 bytes)
-    if (Q) HIPCHECK(enqueue_copy(s->ptr[S_QSAVE], c->ptr[B_QNODE], (Q * 8 + 15) / 16, st));
+    // H2, and the inflow sums at H2 for a fallback to start from
+    HIPCHECK(state_to_f64(c->dev, s->d.H2, c->L().n_inflow ? (double *)s->ptr[S_QSAVE] : nullptr, st));
     HIPCHECK(features(s->d, cont ? s->d.Hn : s->d.H0, s->d.H1, s->d.H2, 1, nullptr, s->N, nullptr, 1, st));
     HIPCHECK(forward(s->d, s->N, 0, 0, st));
     HIPCHECK(write_jump(s->d, c->dev, q, fs_tol, st));
@@ -356,9 +353,7 @@ void enqueue_jump(fem_sur *s, int p, bool cont, float fs_tol, float verify_tol) 
 // the fallback of a rejected jump: back to H2 (T parity p), then horizon - 2 explicit steps
 void enqueue_fallback(fem_sur *s, int p) {
     fem_ctx *c = s->ctx;
-    HIPCHECK(restore_h2(s->d, c->dev, p, c->stream));
-    const int64_t Q = c->L().n_inflow;
-    if (Q) HIPCHECK(enqueue_copy(c->ptr[B_QNODE], s->ptr[S_QSAVE], (Q * 8 + 15) / 16, c->stream));
+    HIPCHECK(restore_h2(s->d, c->dev, p, c->L().n_inflow ? (const double *)s->ptr[S_QSAVE] : nullptr, c->stream));
     for (int k = 0; k < s->opt.horizon - 2; ++k) HIPCHECK(enqueue_step(c->dev, p ^ (k & 1), c->stream, nullptr));
 }
 
@@ -704,20 +699,20 @@ int fem_sur_generate(fem_sur *s, const double *dt_per_scenario, int64_t n_chunks
         for (int64_t k = 0; k < n_chunks; ++k) {
             float *S = S_dev + k * 4 * N;
             HIPCHECK(state_to_f32(ctx->dev, S, st));
-            HIPCHECK(state_to_f64(ctx->dev, s->d.H0, st));
+            HIPCHECK(state_to_f64(ctx->dev, s->d.H0, nullptr, st));
             run_steps(ctx, 1);
             HIPCHECK(state_to_f32(ctx->dev, S + N, st));
-            HIPCHECK(state_to_f64(ctx->dev, s->d.H1, st));
+            HIPCHECK(state_to_f64(ctx->dev, s->d.H1, nullptr, st));
             run_steps(ctx, 1);
             HIPCHECK(state_to_f32(ctx->dev, S + 2 * N, st));
-            HIPCHECK(state_to_f64(ctx->dev, s->d.H2, st));
+            HIPCHECK(state_to_f64(ctx->dev, s->d.H2, nullptr, st));
             run_steps(ctx, H - 2);
             HIPCHECK(state_to_f32(ctx->dev, S + 3 * N, st));
             clock(H);
             if (jump_every > 0 && k % jump_every == jump_every - 1) {
                 // continue from the network's jump instead of the explicit state
                 const int p = ctx->parity ^ (int)((H - 2) & 1);   // T parity at H2
-                HIPCHECK(restore_h2(s->d, ctx->dev, p, st));
+                HIPCHECK(restore_h2(s->d, ctx->dev, p, nullptr, st));
                 ctx->parity = p;
                 HIPCHECK(features(s->d, s->d.H0, s->d.H1, s->d.H2, 1, nullptr, N, nullptr, 1, st));
                 HIPCHECK(forward(s->d, N, 0, 0, st));

@@ -125,7 +125,11 @@ __global__ __launch_bounds__(256) void k_gemm(const bf16 *__restrict__ A, int ld
     const int ar = lane & 15, kq = (lane >> 4) * 4;
     const int64_t arow = row0 + ar;
     f4 acc[NT];
-    for (int t = 0; t < NT; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
+    float bcol[NT];                     // the epilogue's bias, loaded with the operands
+    for (int t = 0; t < NT; ++t) {
+        acc[t] = f4{0.f, 0.f, 0.f, 0.f};
+        bcol[t] = MODE == 2 ? 0.f : bias[t * 16 + ar];
+    }
     for (int k0 = 0; k0 < K; k0 += 16) {
         s4 a = {0, 0, 0, 0};
         if (arow < R) a = load_s4(A + arow * lda + k0 + kq);
@@ -143,7 +147,7 @@ __global__ __launch_bounds__(256) void k_gemm(const bf16 *__restrict__ A, int ld
             if constexpr (MODE == 2) {
                 Cout[row * ldc + col] = v;
             } else {
-                const float z = v + bias[col];
+                const float z = v + bcol[t];
                 if (Zout) Zout[row * NOUT + col] = f2bf(z);
                 const float act = z > 0.f ? z : 0.f;
                 const float h = MODE == 0 ? act : bf2f(Hprev[row * ldhp + col]) + act;
@@ -262,9 +266,13 @@ __global__ __launch_bounds__(256) void k_layer(SurDev s, int l, int64_t R, int s
     const bf16 *__restrict__ U = s.U[l];
     const int t = threadIdx.x;
     const int64_t row0 = (int64_t)blockIdx.x * LAYER_ROWS;
-    for (int v = t; v < WIDTH * (2 * WIDTH / 8); v += 256) {
-        const int n = v / (2 * WIDTH / 8), k8 = (v % (2 * WIDTH / 8)) * 8;
-        *(uint4 *)&Wt[n][k8] = *(const uint4 *)(s.wt[l] + n * 2 * WIDTH + k8);
+    // W_l^T: all four 16-byte pieces of this thread in flight at once, stored to
+    // LDS only after the neighbour loads below have been issued
+    constexpr int WPIECES = WIDTH * (2 * WIDTH / 8) / 256;
+    uint4 wv[WPIECES];
+    for (int j = 0; j < WPIECES; ++j) {
+        const int v = t + 256 * j;
+        wv[j] = *(const uint4 *)(s.wt[l] + (v / (2 * WIDTH / 8)) * 2 * WIDTH + (v % (2 * WIDTH / 8)) * 8);
     }
     {
         const int rr = t >> 3, c8 = (t & 7) * 8;
@@ -275,24 +283,23 @@ __global__ __launch_bounds__(256) void k_layer(SurDev s, int l, int64_t R, int s
             const int64_t i = r % s.N, base = r - i;
             float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
             const int32_t q0 = s.nbr_ptr[i], q1 = s.nbr_ptr[i + 1];
-            int32_t q = q0;
-            for (; q + 8 <= q1; q += 8) {
-                uint4 w[8];
-                for (int u = 0; u < 8; ++u) w[u] = *(const uint4 *)(U + (base + s.nbr[q + u]) * 2 * WIDTH + c8);
-                for (int u = 0; u < 8; ++u) {
-                    const uint32_t x[4] = {w[u].x, w[u].y, w[u].z, w[u].w};
-                    for (int k = 0; k < 4; ++k) {
-                        acc[2 * k] += bf2f((bf16)(x[k] & 0xffffu));
-                        acc[2 * k + 1] += bf2f((bf16)(x[k] >> 16));
+            // 32 neighbour indices at once (a clamped index past the end repeats
+            // the first neighbour and is not summed), then their rows 16 at a time:
+            // three load latencies per 32 neighbours instead of two per 8
+            for (int32_t q = q0; q < q1; q += 32) {
+                int32_t id[32];
+                for (int u = 0; u < 32; ++u) id[u] = s.nbr[q + u < q1 ? q + u : q0];
+                for (int h = 0; h < 32; h += 16) {
+                    uint4 w[16];
+                    for (int u = 0; u < 16; ++u) w[u] = *(const uint4 *)(U + (base + id[h + u]) * 2 * WIDTH + c8);
+                    for (int u = 0; u < 16; ++u) {
+                        const bool in = q + h + u < q1;
+                        const uint32_t x[4] = {w[u].x, w[u].y, w[u].z, w[u].w};
+                        for (int k = 0; k < 4; ++k) {
+                            if (in) acc[2 * k] += bf2f((bf16)(x[k] & 0xffffu));
+                            if (in) acc[2 * k + 1] += bf2f((bf16)(x[k] >> 16));
+                        }
                     }
-                }
-            }
-            for (; q < q1; ++q) {
-                const uint4 w = *(const uint4 *)(U + (base + s.nbr[q]) * 2 * WIDTH + c8);
-                const uint32_t x[4] = {w.x, w.y, w.z, w.w};
-                for (int k = 0; k < 4; ++k) {
-                    acc[2 * k] += bf2f((bf16)(x[k] & 0xffffu));
-                    acc[2 * k + 1] += bf2f((bf16)(x[k] >> 16));
                 }
             }
             const float id = s.inv_deg[i];
@@ -304,6 +311,10 @@ __global__ __launch_bounds__(256) void k_layer(SurDev s, int l, int64_t R, int s
         }
         *(uint4 *)&Ut[rr][c8] = own;
         *(uint4 *)&Ut[rr][WIDTH + c8] = mean;
+    }
+    for (int j = 0; j < WPIECES; ++j) {
+        const int v = t + 256 * j;
+        *(uint4 *)&Wt[v / (2 * WIDTH / 8)][(v % (2 * WIDTH / 8)) * 8] = wv[j];
     }
     __syncthreads();
     constexpr int K = 2 * WIDTH;
@@ -409,13 +420,26 @@ __global__ __launch_bounds__(256) void k_seg_sum(SurDev s, const float *v, int w
     const int64_t g = blockIdx.x, q = blockIdx.y;
     const int32_t b = s.seg_begin[g], e = s.seg_begin[g + 1];
     double acc = 0.0, accw = 0.0;
-    for (int32_t i = b + (int32_t)threadIdx.x; i < e; i += blockDim.x) {
-        if (weighted) {
-            const double w = (double)((const float4 *)s.coef)[i].w * (double)s.scale[q * s.N + i];
-            acc += w * (double)v[q * s.N + i];
-            accw += w;
-        } else {
-            acc += (double)v[q * s.N + i];
+    // four nodes per thread per pass, their loads issued together
+    constexpr int U = 4;
+    for (int32_t i0 = b + (int32_t)threadIdx.x; i0 < e; i0 += U * (int32_t)blockDim.x) {
+        float vv[U], cw[U], sc[U];
+        for (int u = 0; u < U; ++u) {
+            const int32_t i = i0 + u * (int32_t)blockDim.x;
+            const int32_t j = i < e ? i : i0;              // a valid node, not counted below
+            vv[u] = v[q * s.N + j];
+            cw[u] = weighted ? ((const float4 *)s.coef)[j].w : 1.0f;
+            sc[u] = weighted ? s.scale[q * s.N + j] : 1.0f;
+        }
+        for (int u = 0; u < U; ++u) {
+            if (i0 + u * (int32_t)blockDim.x >= e) break;
+            if (weighted) {
+                const double w = (double)cw[u] * (double)sc[u];
+                acc += w * (double)vv[u];
+                accw += w;
+            } else {
+                acc += (double)vv[u];
+            }
         }
     }
     for (int off = 32; off > 0; off >>= 1) {
@@ -575,9 +599,12 @@ __global__ void k_apply(SurDev s, int64_t R, double *H) {
 }
 
 // ---------------------------------------------------------------- solver state
+// the state's enthalpy into out; with keep, also the node inflow sums into keep
+// (the state a rejected jump returns to)
 template <class OUT>
-__global__ __launch_bounds__(256) void k_state_out(Dev d, OUT *out) {
+__global__ __launch_bounds__(256) void k_state_out(Dev d, OUT *out, double *keep) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (keep && i < d.n_inflow) keep[i] = d.qnode[i];
     if (i >= d.N) return;
     double h;
     if (d.prec == FEM_PREC_FP64) {
@@ -635,8 +662,9 @@ __global__ __launch_bounds__(256) void k_write_jump(SurDev s, Dev d, int parity,
 }
 
 template <class R>
-__global__ __launch_bounds__(256) void k_restore(SurDev s, Dev d, int parity) {
+__global__ __launch_bounds__(256) void k_restore(SurDev s, Dev d, int parity, const double *kept_qnode) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (kept_qnode && i < d.n_inflow) d.qnode[i] = kept_qnode[i];
     if (i >= d.N) return;
     const uint32_t f = d.flags[i];
     if (f & NODE_FIXED) return;
@@ -764,13 +792,14 @@ hipError_t apply(const SurDev &s, int64_t R, double *H_out, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t state_to_f64(const Dev &d, double *out, hipStream_t st) {
-    hipLaunchKernelGGL(k_state_out<double>, dim3(grid_for(d.N, 256)), dim3(256), 0, st, d, out);
+hipError_t state_to_f64(const Dev &d, double *out, double *keep_qnode, hipStream_t st) {
+    const int64_t n = keep_qnode ? std::max<int64_t>(d.N, d.n_inflow) : d.N;
+    hipLaunchKernelGGL(k_state_out<double>, dim3(grid_for(n, 256)), dim3(256), 0, st, d, out, keep_qnode);
     return hipGetLastError();
 }
 
 hipError_t state_to_f32(const Dev &d, float *out, hipStream_t st) {
-    hipLaunchKernelGGL(k_state_out<float>, dim3(grid_for(d.N, 256)), dim3(256), 0, st, d, out);
+    hipLaunchKernelGGL(k_state_out<float>, dim3(grid_for(d.N, 256)), dim3(256), 0, st, d, out, (double *)nullptr);
     return hipGetLastError();
 }
 
@@ -790,12 +819,13 @@ hipError_t verify_jump(const SurDev &s, const Dev &d, float tol, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t restore_h2(const SurDev &s, const Dev &d, int parity, hipStream_t st) {
-    const dim3 g((unsigned)check_blocks(d.N));
+hipError_t restore_h2(const SurDev &s, const Dev &d, int parity, const double *kept_qnode, hipStream_t st) {
+    const int64_t n = kept_qnode ? std::max<int64_t>(d.N, d.n_inflow) : d.N;
+    const dim3 g((unsigned)grid_for(n, 256));
     if (d.prec == FEM_PREC_FP64)
-        hipLaunchKernelGGL(k_restore<double>, g, dim3(256), 0, st, s, d, parity);
+        hipLaunchKernelGGL(k_restore<double>, g, dim3(256), 0, st, s, d, parity, kept_qnode);
     else
-        hipLaunchKernelGGL(k_restore<float>, g, dim3(256), 0, st, s, d, parity);
+        hipLaunchKernelGGL(k_restore<float>, g, dim3(256), 0, st, s, d, parity, kept_qnode);
     return hipGetLastError();
 }
 

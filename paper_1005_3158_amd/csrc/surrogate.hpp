@@ -128,7 +128,8 @@ hipError_t refresh_bf16(const SurDev &s, hipStream_t st);
 hipError_t apply(const SurDev &s, int64_t rows, double *H_out, hipStream_t st);   // H = base + scale * y
 
 // solver state <-> surrogate (d: the context's device layout, T buffer `parity`)
-hipError_t state_to_f64(const Dev &d, double *out, hipStream_t st);
+// (keep_qnode, if not null: also the per-node inflow sums, d.n_inflow doubles)
+hipError_t state_to_f64(const Dev &d, double *out, double *keep_qnode, hipStream_t st);
 hipError_t state_to_f32(const Dev &d, float *out, hipStream_t st);
 // write H = base + scale * (y - the scenario's weighted mean of y) (one state slot,
 // unprojected y) into the solver state with its T and fraction solid; counts
@@ -136,7 +137,8 @@ hipError_t state_to_f32(const Dev &d, float *out, hipStream_t st);
 // that of s.H2
 hipError_t write_jump(const SurDev &s, const Dev &d, int parity, float fs_tol, hipStream_t st);
 // put the state back to s.H2
-hipError_t restore_h2(const SurDev &s, const Dev &d, int parity, hipStream_t st);
+// (kept_qnode, if not null: also the per-node inflow sums saved with H2)
+hipError_t restore_h2(const SurDev &s, const Dev &d, int parity, const double *kept_qnode, hipStream_t st);
 // after one explicit step from the predicted state s.Hn: count per workgroup
 // the free nodes whose increment departs from the extrapolated one, s.rext, by
 // more than tol (in K: |dT/dH (s.Hn)| |(H - s.Hn) - s.rext| > tol)
