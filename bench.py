@@ -262,7 +262,7 @@ def main():
         sur = run_surrogate(args, log)
         keep = ("metric", "value", "unit", "plain_seconds", "surrogate_seconds", "max_err_K", "median_err_K",
                 "within_0p5K", "n_held_out", "jumps_kept", "jumps_rejected", "explicit_steps_computed_frac",
-                "train", "inference", "config")
+                "train", "inference", "extrapolation_only", "config")
         out["surrogate"] = {k: sur[k] for k in keep}
     print(json.dumps(out), flush=True)
 
@@ -387,30 +387,35 @@ def run_surrogate(args, log):
         plain.close()
         plain = cf.Solver(p, precision=cf.FEM_PREC_FP32_KAHAN, lds_bytes=lds)
         rp = plain.advance(dt1, 10 ** 6, None, until_solid=True)
+        # the same gates with the untrained network (w_out = 0): the extrapolation alone
+        ex = cf.Solver(p, precision=cf.FEM_PREC_FP32_KAHAN, lds_bytes=lds)
+        se = cf.Surrogate(ex, layers=3, extrapolation=extrap)
+        re_ = ex.advance(dt1, 10 ** 6, se, until_solid=True, verify_tol=args.verify_tol, fs_tol=args.fs_tol)
         acc = cf.Solver(p, precision=cf.FEM_PREC_FP32_KAHAN, lds_bytes=lds)
         sa = cf.Surrogate(acc, layers=3, extrapolation=extrap)
         sa.set_params(params)
         ra = acc.advance(dt1, 10 ** 6, sa, until_solid=True, verify_tol=args.verify_tol, fs_tol=args.fs_tol)
-        if ra["steps"] <= rp["steps"]:
+        def plain_T(n):
+            # the plain run's T after n steps (a run may stop a chunk later than the plain one)
             ref = cf.Solver(p, precision=cf.FEM_PREC_FP32_KAHAN, lds_bytes=lds)
-            ref.step(dt1, ra["steps"])
-            T_ref = ref.T()
+            ref.step(dt1, n)
+            T = ref.T()
             ref.close()
-        else:
-            plain.step(dt1, ra["steps"] - rp["steps"])
-            T_ref = plain.T()
-        dT = np.abs(acc.T() - T_ref)
+            return T
+        dT = np.abs(acc.T() - plain_T(ra["steps"]))
+        dTe = np.abs(ex.T() - plain_T(re_["steps"]))
         res.append(dict(seed=seed, plain_s=rp["wall_seconds"], sur_s=ra["wall_seconds"], plain_steps=rp["steps"],
                         sur_steps=ra["steps"], computed=ra["plain_steps"], kept=ra["jumps_accepted"],
                         rejected=ra["jumps_rejected"], err_K=float(dT.max()), rms_K=float(np.sqrt(np.mean(dT ** 2))),
-                        residual=acc.energy()["residual"]))
+                        residual=acc.energy()["residual"], extrap_s=re_["wall_seconds"], extrap_kept=re_["jumps_accepted"],
+                        extrap_rejected=re_["jumps_rejected"], extrap_err_K=float(dTe.max())))
         log("seed %d: plain %d steps %.4f s; surrogate %d steps (%d computed, %d/%d jumps kept) %.4f s; "
-            "max|dT| %.3f K rms %.3f K" % (seed, rp["steps"], rp["wall_seconds"], ra["steps"], ra["plain_steps"],
-                                           ra["jumps_accepted"], ra["jumps_accepted"] + ra["jumps_rejected"],
-                                           ra["wall_seconds"], res[-1]["err_K"], res[-1]["rms_K"]))
-        sa.close()
-        acc.close()
-        plain.close()
+            "max|dT| %.3f K rms %.3f K; extrapolation only %.4f s, max|dT| %.3f K"
+            % (seed, rp["steps"], rp["wall_seconds"], ra["steps"], ra["plain_steps"], ra["jumps_accepted"],
+               ra["jumps_accepted"] + ra["jumps_rejected"], ra["wall_seconds"], res[-1]["err_K"], res[-1]["rms_K"],
+               re_["wall_seconds"], res[-1]["extrap_err_K"]))
+        for x in (sa, se, acc, ex, plain):
+            x.close()
     t_plain = sum(r["plain_s"] for r in res)
     t_sur = sum(r["sur_s"] for r in res)
     errs = np.array([r["err_K"] for r in res])
@@ -433,6 +438,13 @@ def run_surrogate(args, log):
         "train": {"trajectories": args.train_traj, "chunks": n_chunks, "generate_s": t_gen, "train_s": t_train,
                   "rows_per_s": rows / t_train, "loss_first": losses[0], "loss_last": losses[-1]},
         "inference": inf,
+        "extrapolation_only": {
+            "what": "the same gates and chunks with the untrained network (w_out = 0)",
+            "value": t_plain / sum(r["extrap_s"] for r in res),
+            "max_err_K": float(max(r["extrap_err_K"] for r in res)),
+            "within_0p5K": int(sum(r["extrap_err_K"] <= 0.5 for r in res)),
+            "jumps_kept": int(sum(r["extrap_kept"] for r in res)),
+            "jumps_rejected": int(sum(r["extrap_rejected"] for r in res))},
         "per_trajectory": res,
     }
     return out
