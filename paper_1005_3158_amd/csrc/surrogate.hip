@@ -302,10 +302,16 @@ __global__ __launch_bounds__(256) void k_layer(SurDev s, int l, int64_t R, int s
                     }
                 }
             }
-            const float id = s.inv_deg[i];
+            // the mean as a correctly rounded division of the exact FP32 sum (the BF16
+            // neighbour values add exactly), so that its BF16 rounding matches that of
+            // the exact mean; a product with a rounded 1/deg lands on the other side of
+            // a rounding tie, which the repeated values of a mesh make frequent
+            const float dg = (float)(q1 - q0);
             uint32_t o[4];
-            for (int k = 0; k < 4; ++k)
-                o[k] = (uint32_t)f2bf(acc[2 * k] * id) | ((uint32_t)f2bf(acc[2 * k + 1] * id) << 16);
+            for (int k = 0; k < 4; ++k) {
+                const float m0 = q1 > q0 ? acc[2 * k] / dg : 0.f, m1 = q1 > q0 ? acc[2 * k + 1] / dg : 0.f;
+                o[k] = (uint32_t)f2bf(m0) | ((uint32_t)f2bf(m1) << 16);
+            }
             mean = make_uint4(o[0], o[1], o[2], o[3]);
             if (store) *(uint4 *)(s.U[l] + r * 2 * WIDTH + WIDTH + c8) = mean;
         }

@@ -140,7 +140,7 @@ def test_loss_and_gradients_match_the_fp64_reference(chill, gpu, slots, loss_kin
     # (the projection makes dL/dy sum to zero per scenario): the reference's own
     # BF16-vs-FP64 deviation on these states is up to 6 % in the loss, 46 % in a
     # block and cosine 0.965, and the bounds below carry a margin over that.
-    assert loss == pytest.approx(loss_b, rel=1e-3)
+    assert loss == pytest.approx(loss_b, rel=1e-5)
     assert loss == pytest.approx(loss_r, rel=0.15)
     gnorm = np.linalg.norm(g_r)
     for name, sl in _blocks():
@@ -152,10 +152,10 @@ def test_loss_and_gradients_match_the_fp64_reference(chill, gpu, slots, loss_kin
         rel_b = np.linalg.norm(g[sl] - g_b[sl]) / nr
         rel = np.linalg.norm(g[sl] - g_r[sl]) / nr
         print("%-6s |g| %.3e  vs bf16 ref %.2e  vs fp64 ref %.2e" % (name, nr, rel_b, rel))
-        # a pre-activation whose FP32 sum lands on the other side of a BF16 rounding
-        # boundary (or of 0 at a ReLU) moves by one BF16 ulp: ~1e-3 of the gradient norm
-        # in absolute terms, ~6e-3 of a block the Huber clip has made small
-        assert rel_b <= 1e-2, name
+        # the hidden states agree bit for bit; what remains is the FP32 summation order
+        # of the products (~1e-5), which the Huber loss's clip raises to ~7e-4 of its
+        # small gradients (an FP32-product emulation of the reference shows the same)
+        assert rel_b <= 2e-3, name
         assert rel <= 0.6, name
     cos = float(np.dot(g, g_r) / (np.linalg.norm(g) * gnorm))
     assert cos >= 0.95
