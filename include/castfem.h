@@ -313,6 +313,15 @@ int fem_sur_n_params(const fem_sur *s, int64_t *n);
  * resets the Adam moments.  Synchronous. */
 int fem_sur_get_params(fem_sur *s, float *host, int64_t n);
 int fem_sur_set_params(fem_sur *s, const float *host, int64_t n);
+/* Write the parameters to a file (path: NUL-terminated; created or replaced):
+ * the bytes "CASTSUR1", int32 width, layers, horizon, extrapolation, int64
+ * n_params, then n_params FP32 values, all in host byte order.  Load reads
+ * such a file into a surrogate of the same width, layers, horizon and
+ * extrapolation (FEM_E_INVALID_ARG otherwise, or for a truncated or oversized
+ * file, leaving the parameters unchanged) and clears the Adam moments, as
+ * fem_sur_set_params does.  Synchronous. */
+int fem_sur_save(fem_sur *s, const char *path);
+int fem_sur_load(fem_sur *s, const char *path);
 /* Features (as rounded to BF16) of `slots` states: X_host[slots * n_nodes * 12]. */
 int fem_sur_features(fem_sur *s, const float *H0, const float *H1, const float *H2, int64_t stride, int64_t slots,
                      float *X_host);

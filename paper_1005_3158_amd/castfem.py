@@ -35,7 +35,8 @@ EXPORTS = [
     "fem_time_kernels", "fem_copy_kernel", "fem_set_scenarios", "fem_stable_dt_scenarios", "fem_step_batch",
     "fem_energy_scenarios", "fem_sur_create", "fem_sur_destroy", "fem_sur_query_buffers", "fem_sur_bind_buffers",
     "fem_sur_n_params", "fem_sur_get_params", "fem_sur_set_params", "fem_sur_features", "fem_sur_loss_grad",
-    "fem_sur_train", "fem_sur_predict", "fem_snapshot_H", "fem_advance", "fem_sur_generate",
+    "fem_sur_train", "fem_sur_predict", "fem_snapshot_H", "fem_advance", "fem_sur_generate", "fem_sur_save",
+    "fem_sur_load",
 ]
 
 
@@ -129,6 +130,7 @@ def lib():
             "fem_sur_train": [vp, vp, vp, vp, vp, i64, i64, i32, i32, C.c_float, C.c_float, C.c_uint64, vp],
             "fem_sur_predict": [vp, vp, vp, vp, i64, i64, vp], "fem_snapshot_H": [vp, vp],
             "fem_advance": [vp, vp, vp, i64, i32, dp, dp, dp, vp], "fem_sur_generate": [vp, vp, i64, i32, vp],
+            "fem_sur_save": [vp, C.c_char_p], "fem_sur_load": [vp, C.c_char_p],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -363,6 +365,14 @@ def fem_sur_get_params(s):
     return out
 
 
+def fem_sur_save(s, path):
+    _call("fem_sur_save", s, os.fsencode(path))
+
+
+def fem_sur_load(s, path):
+    _call("fem_sur_load", s, os.fsencode(path))
+
+
 def fem_sur_set_params(s, params):
     p = np.ascontiguousarray(params, np.float32)
     _call("fem_sur_set_params", s, _p(p), p.size)
@@ -554,6 +564,12 @@ class Surrogate:
 
     def set_params(self, p):
         fem_sur_set_params(self.sur, p)
+
+    def save(self, path):
+        fem_sur_save(self.sur, path)
+
+    def load(self, path):
+        fem_sur_load(self.sur, path)
 
     def _states(self, tensors, stride, slots):
         """Device pointers of float32 CUDA tensors (or views), each checked to reach `slots`

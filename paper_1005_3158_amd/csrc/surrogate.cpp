@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <numeric>
 #include <string>
@@ -452,6 +453,38 @@ void staged_energy(fem_ctx *ctx, Staging &sg, std::vector<double> &dg, std::vect
     energy_reduce(ctx, dg, qn, er);
 }
 
+// FP32 parameters into the surrogate (BF16 copies refreshed), Adam moments cleared
+void set_params(fem_sur *s, const float *host, int64_t n) {
+    need_bound(s);
+    if (n != s->pl.total) throw PrepError{FEM_E_INVALID_ARG, "parameter count mismatch"};
+    for (int64_t k = 0; k < n; ++k)
+        if (!std::isfinite(host[k])) throw PrepError{FEM_E_INVALID_ARG, "parameters must be finite"};
+    upload_params(s, host);
+    s->adam_t = 0;
+    if (s->opt.train) {
+        HIPCHECK(hipMemsetAsync(s->ptr[S_ADAM_M], 0, s->sizes[S_ADAM_M], s->ctx->stream));
+        HIPCHECK(hipMemsetAsync(s->ptr[S_ADAM_V], 0, s->sizes[S_ADAM_V], s->ctx->stream));
+        HIPCHECK(hipStreamSynchronize(s->ctx->stream));
+    }
+}
+
+// parameter file: this header, then n_params FP32 values (host byte order)
+struct ParamFileHeader {
+    char magic[8];
+    int32_t width, layers, horizon, extrapolation;
+    int64_t n_params;
+};
+ParamFileHeader file_header(const fem_sur *s) {
+    ParamFileHeader h{};
+    std::memcpy(h.magic, "CASTSUR1", 8);
+    h.width = s->opt.width;
+    h.layers = s->opt.layers;
+    h.horizon = s->opt.horizon;
+    h.extrapolation = s->opt.extrapolation;
+    h.n_params = s->pl.total;
+    return h;
+}
+
 }  // namespace
 
 extern "C" {
@@ -563,18 +596,45 @@ int fem_sur_get_params(fem_sur *s, float *host, int64_t n) {
 
 int fem_sur_set_params(fem_sur *s, const float *host, int64_t n) {
     if (!s || !host) return set_err(FEM_E_INVALID_ARG, "null argument");
+    return guarded([&] { set_params(s, host, n); });
+}
+
+int fem_sur_save(fem_sur *s, const char *path) {
+    if (!s || !path) return set_err(FEM_E_INVALID_ARG, "null argument");
     return guarded([&] {
         need_bound(s);
-        if (n != s->pl.total) throw PrepError{FEM_E_INVALID_ARG, "parameter count mismatch"};
-        for (int64_t k = 0; k < n; ++k)
-            if (!std::isfinite(host[k])) throw PrepError{FEM_E_INVALID_ARG, "parameters must be finite"};
-        upload_params(s, host);
-        s->adam_t = 0;
-        if (s->opt.train) {
-            HIPCHECK(hipMemsetAsync(s->ptr[S_ADAM_M], 0, s->sizes[S_ADAM_M], s->ctx->stream));
-            HIPCHECK(hipMemsetAsync(s->ptr[S_ADAM_V], 0, s->sizes[S_ADAM_V], s->ctx->stream));
-            HIPCHECK(hipStreamSynchronize(s->ctx->stream));
+        std::vector<float> p(s->pl.total);
+        HIPCHECK(hipMemcpyAsync(p.data(), s->ptr[S_PARAMS], p.size() * 4, hipMemcpyDeviceToHost, s->ctx->stream));
+        HIPCHECK(hipStreamSynchronize(s->ctx->stream));
+        const ParamFileHeader h = file_header(s);
+        FILE *f = std::fopen(path, "wb");
+        if (!f) throw PrepError{FEM_E_INVALID_ARG, std::string("cannot open ") + path + " for writing"};
+        const bool ok = std::fwrite(&h, sizeof(h), 1, f) == 1 && std::fwrite(p.data(), 4, p.size(), f) == p.size();
+        if (std::fclose(f) != 0 || !ok) throw PrepError{FEM_E_INVALID_ARG, std::string("cannot write ") + path};
+    });
+}
+
+int fem_sur_load(fem_sur *s, const char *path) {
+    if (!s || !path) return set_err(FEM_E_INVALID_ARG, "null argument");
+    return guarded([&] {
+        need_bound(s);
+        FILE *f = std::fopen(path, "rb");
+        if (!f) throw PrepError{FEM_E_INVALID_ARG, std::string("cannot open ") + path};
+        ParamFileHeader h{};
+        std::vector<float> p;
+        bool ok = std::fread(&h, sizeof(h), 1, f) == 1;
+        const ParamFileHeader want = file_header(s);
+        const bool same = ok && std::memcmp(h.magic, want.magic, sizeof(h.magic)) == 0 && h.width == want.width &&
+                          h.layers == want.layers && h.horizon == want.horizon &&
+                          h.extrapolation == want.extrapolation && h.n_params == want.n_params;
+        if (same) {
+            p.resize(h.n_params);
+            ok = std::fread(p.data(), 4, p.size(), f) == p.size() && std::fgetc(f) == EOF;
         }
+        std::fclose(f);
+        if (!same) throw PrepError{FEM_E_INVALID_ARG, std::string(path) + ": not parameters of a surrogate of this shape"};
+        if (!ok) throw PrepError{FEM_E_INVALID_ARG, std::string(path) + ": truncated or oversized parameter file"};
+        set_params(s, p.data(), (int64_t)p.size());
     });
 }
 

@@ -196,6 +196,31 @@ def test_parameters_round_trip_and_errors(gpu):
         sur.loss_grad(z, z, z, z, slots=4)
 
 
+def test_parameter_file_round_trip(gpu, tmp_path):
+    cf = gpu["cf"]
+    v, _ = ref_params(5)
+    gpu["sur"].set_params(v)
+    path = tmp_path / "net.castsur"
+    gpu["sur"].save(path)
+    assert path.stat().st_size == 32 + 4 * v.size
+    other = cf.Surrogate(gpu["solver"], layers=LAYERS, seed=9)
+    other.load(path)
+    assert np.array_equal(other.params(), v)
+    shallow = cf.Surrogate(gpu["solver"], layers=2)
+    with pytest.raises(cf.FemError):           # another shape
+        shallow.load(path)
+    cut = tmp_path / "cut.castsur"
+    cut.write_bytes(path.read_bytes()[:-4])
+    before = other.params()
+    with pytest.raises(cf.FemError):           # truncated: parameters left as they were
+        other.load(cut)
+    assert np.array_equal(other.params(), before)
+    with pytest.raises(cf.FemError):
+        other.load(tmp_path / "missing.castsur")
+    for x in (other, shallow):
+        x.close()
+
+
 # ------------------------------------------------------------------ gates and fallback
 def test_rejected_jumps_reproduce_the_plain_run_bitwise(orc):
     cf = _cf()
