@@ -117,8 +117,7 @@ def main():
     ap.add_argument("--quiet", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: the explicit step is built and measured on a single MI355X; "
-              "a multi-GPU run is not part of this build", file=sys.stderr)
+        print("bench.py measures one GPU (one MI355X); runs on several GPUs are not supported", file=sys.stderr)
         sys.exit(2)
 
     def log(*a):
@@ -256,7 +255,7 @@ def main():
     }
     s.close()
     if not args.no_surrogate:
-        # the metric's second part: time to solidify, plain vs surrogate, judged by the plain run
+        # the metric's second part: time to solidify, plain vs surrogate, measured against the plain run
         if args.held_out is None:
             args.held_out = 20
         sur = run_surrogate(args, log)
@@ -325,7 +324,7 @@ def run_surrogate(args, log):
     5000..), on explicit trajectories (and, with more rounds, on trajectories that
     pass through the network's own jumps); then run every held-out trajectory
     (seeds 5500..) to full solidification plainly and with the surrogate.  The
-    plain run judges the error."""
+    plain run is the reference for the error."""
     import torch
     from castgen import configs
     from paper_1005_3158_amd import castfem as cf

@@ -232,9 +232,9 @@ int fem_copy_kernel(fem_ctx *ctx, void *dst, const void *src, int64_t bytes, int
 /* ------------------------------------------------------------ surrogate */
 /* A learned message-passing surrogate that jumps the enthalpy state `horizon`
  * explicit steps ahead (not part of the paper; the explicit step of Eq. 14 is
- * its fallback and judge).  From three consecutive explicit states H0 = H^n,
- * H1 = H^{n+1}, H2 = H^{n+2} it predicts, per node i, with m = horizon - 2,
- * q = m (m + 1) / 2, r = H2 - H1 and a = (H2 - H1) - (H1 - H0),
+ * its fallback and the reference for its error).  From three consecutive
+ * explicit states H0 = H^n, H1 = H^{n+1}, H2 = H^{n+2} it predicts, per node i,
+ * with m = horizon - 2, q = m (m + 1) / 2, r = H2 - H1 and a = (H2 - H1) - (H1 - H0),
  *   H^{n+horizon}_i = base_i + mu_i s_i (y_i - ybar),
  * base = H2 + m r (linear extrapolation, the default) or
  * base = H2 + m r + q a (quadratic; fem_sur_options.extrapolation).

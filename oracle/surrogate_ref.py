@@ -1,6 +1,6 @@
 """FP64 CPU reference of the message-passing surrogate (forward, loss, backward).
 
-TEST INFRASTRUCTURE ONLY: it judges the gradients of the GPU training kernels
+TEST INFRASTRUCTURE ONLY: it is the reference for the gradients of the GPU training kernels
 and is itself checked against central finite differences.
 
 The surrogate jumps the enthalpy state `horizon` explicit steps ahead.  Given

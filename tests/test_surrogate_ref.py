@@ -1,4 +1,4 @@
-"""The FP64 reference surrogate (the judge of the GPU training kernels) checked
+"""The FP64 reference surrogate (the reference for the GPU training kernels) checked
 against central finite differences of its own loss."""
 import numpy as np
 import pytest

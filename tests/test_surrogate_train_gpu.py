@@ -1,6 +1,6 @@
 """Training of the surrogate on trajectories of the GPU solver (a reduced set of
 config-4 chill trajectories), what it gains over the extrapolation it corrects,
-and the accelerated run judged by the plain one."""
+and the accelerated run measured against the plain one."""
 import numpy as np
 import pytest
 
