@@ -66,3 +66,38 @@ def test_four_hundred_full_size_steps_keep_energy_and_are_reproducible(config2, 
         finally:
             s.close()
     assert np.array_equal(H[0], H[1])
+
+
+def test_full_size_batch_matches_sampled_scenarios_run_alone(orc):
+    """The 256-scenario batch (about 5.5e7 tets, 1.06e7 nodes) as the benchmark runs it
+    (autotuned block size, per-scenario dt): the smallest, the median and the largest
+    scenario against the oracle run on that scenario alone, at every node, and every
+    scenario's FP64 energy balance."""
+    from paper_1005_3158_amd import castfem as cf
+    b = configs.batch()
+    sc = b["meta"]["scenarios"]
+    s = cf.Solver(b, precision=cf.FEM_PREC_FP32_KAHAN, scatter=cf.FEM_SCATTER_LDS_BLOCKED)
+    try:
+        print("config 3: %d tets, %d nodes, %d blocks of <= %d nodes" % (s.n_elems, s.n_nodes, s.report["n_blocks"],
+                                                                        s.report["max_local_nodes"]), flush=True)
+        dt = 0.9 * s.stable_dt_scenarios()
+        steps = 20
+        s.step_batch(dt, steps)
+        T, fs = s.T(), s.fs()
+        reps = s.energy_scenarios()
+    finally:
+        s.close()
+    assert max(r["residual"] for r in reps) <= 1e-9
+    assert all(r["nonfinite"] == 0 for r in reps)
+    sizes = np.array([sp["elem1"] - sp["elem0"] for sp in sc])
+    order = np.argsort(sizes)
+    for k in (order[0], order[len(order) // 2], order[-1]):
+        sp = sc[k]
+        mold = (sp["k_mold"],) + configs.SAND[1:]
+        p = configs.tet_casting(n=sp["n"], region="cube", jitter_seed=sp["seed"], perm_seed=sp["seed"],
+                                T_pour=sp["T_pour"], h_interface=sp["h_interface"], alloy=configs.ALLOY, mold=mold)
+        _, T_ref, fs_ref = orc.run(p, dt[k], steps)
+        err = float(np.max(np.abs(T[sp["node0"]:sp["node1"]] - T_ref)))
+        print("scenario %d (%d tets, dt %.3e s): max|T - oracle| %.3e K" % (k, sizes[k], dt[k], err), flush=True)
+        assert err <= 1e-3
+        assert float(np.max(np.abs(fs[sp["node0"]:sp["node1"]] - fs_ref))) <= 1e-4
