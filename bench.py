@@ -83,7 +83,9 @@ def traffic_from_counters(fetch_dir, write_dir, block_nodes, kernel_key="k_block
 
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--traffic-from":
-        traffic_from_counters(sys.argv[2], sys.argv[3], int(sys.argv[4]))
+        # --traffic-from FETCH_DIR WRITE_DIR BLOCK_NODES [RECORD_NAME]
+        traffic_from_counters(sys.argv[2], sys.argv[3], int(sys.argv[4]),
+                              out_name=sys.argv[5] if len(sys.argv) > 5 else "block_element_config2")
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,8 +100,9 @@ def main():
                     help="LDS block node cap (0 = autotune).  Default: 512 on the benchmark mesh, what the autotuner "
                          "picks there, pinned so that the committed traffic counters match the timed kernel; "
                          "autotuned for the batch")
-    ap.add_argument("--workload", default="tet128", choices=["tet128", "batch", "surrogate"],
-                    help="tet128: the 128^3 cast/mould mesh; batch: 256 scenarios of 20k-400k tets; "
+    ap.add_argument("--workload", default="tet128", choices=["tet128", "tet256", "batch", "surrogate"],
+                    help="tet128: the 128^3 cast/mould mesh; tet256: the 256^3 mesh with eight seeded casting "
+                         "boxes (beyond the last-level cache); batch: 256 scenarios of 20k-400k tets; "
                          "surrogate: train on chill-cube trajectories, then time-to-solidify plain vs surrogate")
     ap.add_argument("--train-traj", type=int, default=500, help="surrogate: training trajectories (seeds 5000+)")
     ap.add_argument("--held-out", type=int, default=None,
@@ -134,8 +137,12 @@ def main():
         if args.held_out is None:
             args.held_out = 50
         return bench_surrogate(args, log)
+    big = args.workload == "tet256"
+    if big:
+        args.no_surrogate = True
+        args.cpu_steps = 0            # ~40 s per FP64 oracle step on one core at this size
     t0 = time.time()
-    prob = configs.config2(n=args.n)
+    prob = configs.config5() if big else configs.config2(n=args.n)
     t_gen = time.time() - t0
     E, N = prob["conn"].shape[0], prob["xyz"].shape[0]
     log("inputs: %d tets, %d nodes (%.1f s)" % (E, N, t_gen))
@@ -156,7 +163,7 @@ def main():
     log("setup %.1f s (host prep %.1f s): blocks %d, shared %.3f, max local nodes %d"
         % (t_setup, rep["setup_seconds"], rep["n_blocks"], rep["shared_fraction"], rep["max_local_nodes"]))
     dt_bound = s.stable_dt()
-    if args.n == 128:
+    if args.n == 128 and not big:
         ref = golden["config2"]["dt_bound"]
         if abs(dt_bound - ref) > 1e-9 * ref:
             raise SystemExit("stability bound %.17g differs from the oracle's %.17g" % (dt_bound, ref))
@@ -183,7 +190,7 @@ def main():
     ach_e = kt["bytes_element"] / (kt["ms_element"] * 1e-3) / 1e9
     ach_c = kt["bytes_combine"] / (kt["ms_combine"] * 1e-3) / 1e9 if kt["ms_combine"] > 0 else None
     log("element kernel %.4f ms (%.1f GB/s alg), node kernel %.4f ms" % (kt["ms_element"], ach_e, kt["ms_combine"]))
-    traffic = load_traffic("block_element_config2", rep["max_local_nodes"])
+    traffic = load_traffic("block_element_config5" if big else "block_element_config2", rep["max_local_nodes"])
 
     # plain copy ceiling on this device
     nbytes = 1 << 30
@@ -228,8 +235,10 @@ def main():
         "dtype": "f32 (compensated enthalpy, f64 T(H) and reductions)",
         "data": "synthetic",
         "config": {
-            "workload": "128^3 jittered Kuhn tets (%d tets, %d nodes), alloy cube in sand mould, h_i=1000, "
-                        "random input numbering, %s ordering, %s scatter, dt=0.9 x bound" % (E, N, args.ordering, args.scatter),
+            "workload": ("256^3 jittered Kuhn tets (%d tets, %d nodes), eight seeded alloy boxes in sand mould"
+                         if big else "128^3 jittered Kuhn tets (%d tets, %d nodes), alloy cube in sand mould") % (E, N) +
+                        ", h_i=1000, random input numbering, %s ordering, %s scatter, dt=0.9 x bound"
+                        % (args.ordering, args.scatter),
             "n_elems": E, "n_nodes": N, "dt": dt, "block_nodes": rep["max_local_nodes"], "n_blocks": rep["n_blocks"],
             "shared_fraction": rep["shared_fraction"], "setup_s": t_setup,
         },
