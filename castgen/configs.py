@@ -129,6 +129,43 @@ def hex_bar(nx=64, ny=4, nz=4, lx=0.4, ly=0.025, lz=0.025, T_init=700.0, T_wall=
     return _empty_faces(prob)
 
 
+def box_kuhn_conn(nx, ny, nz):
+    """Kuhn split of the boxes of box_hex_grid(nx, ny, nz, ...): six positively
+    oriented tetrahedra per box, ids as in box_hex_grid."""
+    mx, my = nx + 1, ny + 1
+    c = np.arange(nx * ny * nz, dtype=np.int64)
+    base = c % nx + mx * ((c // nx) % ny + my * (c // (nx * ny)))
+    tets = []
+    for order, odd in meshes._AXIS_ORDERS:
+        v = [0, 0, 0]
+        path = [tuple(v)]
+        for ax in order:
+            v = list(v)
+            v[ax] = 1
+            path.append(tuple(v))
+        if odd:
+            path[1], path[2] = path[2], path[1]
+        tets.append([a + mx * (b + my * cc) for (a, b, cc) in path])
+    return (base[:, None, None] + np.array(tets, dtype=np.int64)[None]).reshape(-1, 4)
+
+
+def tet_bar(nx=64, ny=1, nz=1, lx=0.1, ly=None, lz=None, T_init=700.0, T_wall=25.0, material=ALLOY):
+    """hex_bar split into Kuhn tetrahedra (fixed temperature on x = 0)."""
+    h = lx / nx
+    ly = h * ny if ly is None else ly
+    lz = h * nz if lz is None else lz
+    xyz, _, (i, j, k) = box_hex_grid(nx, ny, nz, lx, ly, lz)
+    conn = box_kuhn_conn(nx, ny, nz)
+    d = np.nonzero(i == 0)[0]
+    prob = dict(elem_type=4, xyz=xyz, conn=conn.astype(np.int32),
+                elem_mat=np.zeros(conn.shape[0], np.int32),
+                materials=np.array([material], dtype=np.float64),
+                T0=np.full(xyz.shape[0], float(T_init)),
+                dirichlet_nodes=d.astype(np.int32), dirichlet_T=np.full(d.size, float(T_wall)),
+                meta=dict(kind="tet_bar", nx=nx, ny=ny, nz=nz, lx=lx))
+    return _empty_faces(prob)
+
+
 def tet_casting(n=128, length=0.1, region="cube", cube=(0.2, 0.8), boxes_seed=6, n_boxes=8,
                 jitter=0.2, jitter_seed=2, perm_seed=3, T_pour=700.0, T_mold=25.0,
                 h_interface=1000.0, alloy=ALLOY, mold=SAND, permute=True):

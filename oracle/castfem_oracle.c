@@ -550,6 +550,130 @@ done:
     return rc;
 }
 
+/* ------------------------------------- apparent heat capacity (Eq. 6-7) */
+
+/* gradients of the four shape functions of a linear tetrahedron; *vol = volume */
+static int tet_grads(const double x[12], double g[4][3], double *vol)
+{
+    static const double dN[4][3] = {{-1, -1, -1}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+    double J[3][3], Ji[3][3];
+    jacobian(4, x, dN, J);
+    double d = det3(J);
+    if (!(d > 0.0)) return ORC_ERR_MESH;
+    inv3(J, Ji);
+    phys_grad(4, Ji, dN, g);
+    *vol = d / 6.0;
+    return 0;
+}
+
+/* Lemmon's element value of dH/dT (Eq. 7): |grad H| / |grad T| with H and T
+ * interpolated linearly from the nodal values, so both gradients are constant
+ * on the element.  Where grad T vanishes the ratio is undefined and the slope of
+ * the enthalpy relation at the mean nodal temperature is taken: c + L/(T_liq -
+ * T_sol) strictly inside the mushy interval, c elsewhere. */
+int orc_lemmon_capacity(const double x[12], const double mat[6], const double T[4], const double H[4],
+                        double *c_app)
+{
+    double g[4][3], V;
+    double c = mat[2], Ts = mat[3], Tl = mat[4], L = mat[5];
+    if (L > 0.0 && !(Tl > Ts)) return ORC_ERR_ARG;
+    int rc = tet_grads(x, g, &V);
+    if (rc) return rc;
+    /* the shape functions sum to one, so the gradients are sums over the
+     * differences to node 0; a uniform field then has exactly zero gradient */
+    double gT[3] = {0, 0, 0}, gH[3] = {0, 0, 0};
+    for (int a = 1; a < 4; ++a)
+        for (int i = 0; i < 3; ++i) {
+            gT[i] += (T[a] - T[0]) * g[a][i];
+            gH[i] += (H[a] - H[0]) * g[a][i];
+        }
+    double nT = gT[0] * gT[0] + gT[1] * gT[1] + gT[2] * gT[2];
+    double nH = gH[0] * gH[0] + gH[1] * gH[1] + gH[2] * gH[2];
+    if (nT > 0.0) {
+        *c_app = sqrt(nH / nT);
+    } else {
+        double Tm = (T[0] + T[1] + T[2] + T[3]) / 4.0;
+        *c_app = (L > 0.0 && Tm > Ts && Tm < Tl) ? c + L / (Tl - Ts) : c;
+    }
+    return 0;
+}
+
+/* lumped capacitance C_i = sum over elements at i of rho C_app V / 4 (row-sum
+ * lumping of the element capacitance rho C_app int N_a N_b dV) */
+static int apparent_lumped(const orc_problem *p, const double *T, const double *H, double *C)
+{
+    for (int64_t i = 0; i < p->n_nodes; ++i) C[i] = 0.0;
+    for (int64_t e = 0; e < p->n_elems; ++e) {
+        double x[12], Te[4], He[4], g[4][3], V, capp;
+        int rc = gather_x(p, e, x);
+        if (rc) return rc;
+        int32_t mt = p->elem_mat[e];
+        if (mt < 0 || mt >= p->n_mat) return ORC_ERR_MESH;
+        const int32_t *cn = p->conn + 4 * e;
+        for (int a = 0; a < 4; ++a) {
+            Te[a] = T[cn[a]];
+            He[a] = H[cn[a]];
+        }
+        if ((rc = orc_lemmon_capacity(x, p->materials + 6 * mt, Te, He, &capp))) return rc;
+        if ((rc = tet_grads(x, g, &V))) return rc;
+        for (int a = 0; a < 4; ++a) C[cn[a]] += p->materials[6 * mt + 1] * capp * V / 4.0;
+    }
+    return 0;
+}
+
+int orc_apparent_capacity(const orc_problem *p, const double *H, double *C)
+{
+    if (p->elem_type != 4) return ORC_ERR_ARG;
+    double *T = malloc(p->n_nodes * sizeof(double));
+    if (!T) return ORC_ERR_ARG;
+    int rc = orc_state_T(p, H, T, NULL);
+    if (rc == 0) rc = apparent_lumped(p, T, H, C);
+    free(T);
+    return rc;
+}
+
+int orc_run_apparent(const orc_problem *p, double dt, int64_t n_steps, double *H, double *diag)
+{
+    if (p->elem_type != 4) return ORC_ERR_ARG;
+    for (int32_t q = 0; q < p->n_mat; ++q)
+        if (p->materials[6 * q + 5] > 0.0 && !(p->materials[6 * q + 4] > p->materials[6 * q + 3]))
+            return ORC_ERR_ARG;
+    int64_t N = p->n_nodes;
+    double *m = malloc(N * sizeof(double));
+    double *T = malloc(N * sizeof(double));
+    double *r = malloc(N * sizeof(double));
+    double *Cn = malloc(N * sizeof(double));
+    int32_t *nmat = malloc(N * sizeof(int32_t));
+    unsigned char *fixed = dirichlet_mask(p);
+    int rc = 0;
+    if (!m || !T || !r || !Cn || !nmat || !fixed) { rc = ORC_ERR_ARG; goto done; }
+    if ((rc = orc_lumped_mass(p, m))) goto done;
+    if ((rc = orc_node_material(p, nmat))) goto done;
+    double Eref = 0.0, E0 = NAN, Qcum = 0.0;
+    for (int64_t i = 0; i < N; ++i)
+        if (nmat[i] >= 0) Eref += m[i] * orc_H_of_T(p->materials + 6 * nmat[i], 25.0);
+    for (int64_t n = 0; n <= n_steps; ++n) {
+        state_T_nm(p, nmat, H, T, NULL);
+        /* r^n = F^n - K T^n, as in the enthalpy form */
+        if ((rc = orc_residual(p, T, r))) goto done;
+        double Q = boundary_inflow(p, T, r);
+        if (diag) {
+            fill_diag(p, nmat, m, H, T, Q, Qcum, E0, Eref, diag + n * ORC_NDIAG);
+            if (n == 0) E0 = diag[ORC_D_E];
+        }
+        if (n == n_steps) break;
+        /* C^n from the current field (Eq. 7, lumped), then Eq. 14:
+         * T^{n+1} = T^n + dt (C^n)^-1 r^n, and the state keeps H(T^{n+1}) */
+        if ((rc = apparent_lumped(p, T, H, Cn))) goto done;
+        for (int64_t i = 0; i < N; ++i)
+            if (!fixed[i] && nmat[i] >= 0) H[i] = orc_H_of_T(p->materials + 6 * nmat[i], T[i] + dt * r[i] / Cn[i]);
+        Qcum += dt * Q;
+    }
+done:
+    free(m); free(T); free(r); free(Cn); free(nmat); free(fixed);
+    return rc;
+}
+
 /* ----------------------------------------------- partitioned algorithm */
 
 int orc_run_partitioned(const orc_problem *p, int32_t n_parts, const int32_t *elem_part,

@@ -19,7 +19,10 @@
  *   - the fully explicit update (Eq. 10 with theta = 0, i.e. Eq. 14),
  *     assembled element by element (Eq. 15-18), written here for the nodal
  *     enthalpy state: H_i += dt * r_i / m_i with r = F - K T;
- *   - the partition-local sums with shared-node exchange of Eq. 19-22.
+ *   - the partition-local sums with shared-node exchange of Eq. 19-22;
+ *   - the paper's own latent-heat treatment as a second mode: the apparent heat
+ *     capacity form of Eq. 6 with Lemmon's element-wise dH/dT of Eq. 7, lumped
+ *     and re-assembled every step, advancing T by Eq. 14.
  * Every routine is a direct loop over elements, faces or nodes in double
  * precision with no blocking, fusion or reordering.
  *
@@ -102,6 +105,18 @@ int orc_run(const orc_problem *p, double dt, int64_t n_steps, double *H, double 
    shared nodes.  Face terms are given to partition (face index mod n_parts). */
 int orc_run_partitioned(const orc_problem *p, int32_t n_parts, const int32_t *elem_part,
                         double dt, int64_t n_steps, double *H);
+
+/* Apparent heat capacity (Eq. 6) with Lemmon's element value of dH/dT (Eq. 7),
+ * linear tetrahedra only; materials with L > 0 need T_liq > T_sol.
+ * orc_lemmon_capacity: C_app of one element from nodal T and H (x as for orc_tet_ke).
+ * orc_apparent_capacity: row-sum lumped C_i = sum_e rho C_app V / 4 (J/K) of a state.
+ * orc_run_apparent: n explicit steps T^{n+1} = T^n + dt r^n / C^n (Eq. 14 with C
+ * re-assembled from the current field every step), the state kept as H = H(T);
+ * diag as for orc_run. */
+int orc_lemmon_capacity(const double x[12], const double mat[6], const double T[4], const double H[4],
+                        double *c_app);
+int orc_apparent_capacity(const orc_problem *p, const double *H, double *C);
+int orc_run_apparent(const orc_problem *p, double dt, int64_t n_steps, double *H, double *diag);
 
 #ifdef __cplusplus
 }

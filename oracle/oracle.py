@@ -208,3 +208,35 @@ def run_partitioned(prob, elem_part, n_parts, dt, n_steps, H=None):
     _check(lib().orc_run_partitioned(P.ref, C.c_int32(n_parts), _ptr(ep), C.c_double(dt),
                                      C.c_int64(n_steps), _ptr(H)), "run_partitioned")
     return H
+
+
+def lemmon_capacity(x, mat, T, H):
+    """Lemmon's dH/dT of one linear tetrahedron (Eq. 7) from nodal T and H."""
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(12)
+    a, pm = _mat(mat)
+    T = np.ascontiguousarray(T, dtype=np.float64).reshape(4)
+    H = np.ascontiguousarray(H, dtype=np.float64).reshape(4)
+    c = C.c_double()
+    _check(lib().orc_lemmon_capacity(_ptr(x), pm, _ptr(T), _ptr(H), C.byref(c)), "lemmon_capacity")
+    return c.value
+
+
+def apparent_capacity(prob, H):
+    """Row-sum lumped apparent capacitance C_i (J/K) of the state H (tetrahedra)."""
+    P = _as_problem(prob)
+    H = np.ascontiguousarray(H, dtype=np.float64)
+    Cn = np.zeros(P.n_nodes)
+    _check(lib().orc_apparent_capacity(P.ref, _ptr(H), _ptr(Cn)), "apparent_capacity")
+    return Cn
+
+
+def run_apparent(prob, dt, n_steps, H=None, diag=False):
+    """n explicit steps of the apparent-heat-capacity mode (Eq. 6-7, Eq. 14) from H
+    (default: the initial state).  Returns (H, T, fs[, diag]) as run()."""
+    P = _as_problem(prob)
+    H = initial_H(P) if H is None else np.array(H, dtype=np.float64)
+    D = np.zeros((n_steps + 1, ORC_NDIAG)) if diag else None
+    _check(lib().orc_run_apparent(P.ref, C.c_double(dt), C.c_int64(n_steps), _ptr(H),
+                                  _ptr(D) if diag else None), "run_apparent")
+    T, fs = state_T(P, H)
+    return (H, T, fs, D) if diag else (H, T, fs)
