@@ -28,21 +28,25 @@ METRIC = "element-steps/s + HBM GB/s %peak; surrogate vs plain time-to-solidify 
 HBM_PEAK_GBS = 8000.0
 
 
-def kernel_hash():
+ENTHALPY_SOURCES = ("kernels.hip", "kernels.hpp", "elem.hpp")
+APPARENT_SOURCES = ("apparent.hip", "apparent.hpp", "kernels.hpp", "elem.hpp")
+
+
+def kernel_hash(sources=ENTHALPY_SOURCES):
     h = hashlib.sha256()
-    for f in ("kernels.hip", "kernels.hpp", "elem.hpp"):
+    for f in sources:
         h.update(open(os.path.join(ROOT, "paper_1005_3158_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
 
-def load_traffic(kind, block_nodes):
+def load_traffic(kind, block_nodes, sources=ENTHALPY_SOURCES):
     """HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs, if they
     were taken on the current kernel source with the same block size."""
     path = os.path.join(ROOT, "profiles", "traffic_%s.json" % kind)
     if not os.path.exists(path):
         return None
     t = json.load(open(path))
-    if t.get("kernel_hash") != kernel_hash() or t.get("block_nodes") != block_nodes:
+    if t.get("kernel_hash") != kernel_hash(sources) or t.get("block_nodes") != block_nodes:
         return None
     return t.get("bytes_per_launch")
 
@@ -69,7 +73,8 @@ def traffic_from_counters(fetch_dir, write_dir, block_nodes, kernel_key="k_block
     gib_kib = float(1 << 20)
     fetch_scale, write_scale = gib_kib / cf_, gib_kib / cw
     out = {
-        "kernel": kernel_key, "kernel_hash": kernel_hash(), "block_nodes": block_nodes, "dispatches": nk,
+        "kernel": kernel_key, "block_nodes": block_nodes, "dispatches": nk,
+        "kernel_hash": kernel_hash(APPARENT_SOURCES if "app" in kernel_key else ENTHALPY_SOURCES),
         "fetch_kib_raw": kf, "write_kib_raw": kw, "copy_fetch_kib": cf_, "copy_write_kib": cw,
         "fetch_scale": fetch_scale, "write_scale": write_scale,
         "bytes_per_launch": 1024.0 * (kf * fetch_scale + kw * write_scale),
@@ -83,9 +88,10 @@ def traffic_from_counters(fetch_dir, write_dir, block_nodes, kernel_key="k_block
 
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--traffic-from":
-        # --traffic-from FETCH_DIR WRITE_DIR BLOCK_NODES [RECORD_NAME]
+        # --traffic-from FETCH_DIR WRITE_DIR BLOCK_NODES [RECORD_NAME [KERNEL_NAME]]
         traffic_from_counters(sys.argv[2], sys.argv[3], int(sys.argv[4]),
-                              out_name=sys.argv[5] if len(sys.argv) > 5 else "block_element_config2")
+                              out_name=sys.argv[5] if len(sys.argv) > 5 else "block_element_config2",
+                              kernel_key=sys.argv[6] if len(sys.argv) > 6 else "k_block<float, 4>")
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,10 +106,14 @@ def main():
                     help="LDS block node cap (0 = autotune).  Default: 512 on the benchmark mesh, what the autotuner "
                          "picks there, pinned so that the committed traffic counters match the timed kernel; "
                          "autotuned for the batch")
-    ap.add_argument("--workload", default="tet128", choices=["tet128", "tet256", "batch", "surrogate"],
+    ap.add_argument("--workload", default="tet128", choices=["tet128", "tet256", "batch", "surrogate", "apparent"],
                     help="tet128: the 128^3 cast/mould mesh; tet256: the 256^3 mesh with eight seeded casting "
                          "boxes (beyond the last-level cache); batch: 256 scenarios of 20k-400k tets; "
-                         "surrogate: train on chill-cube trajectories, then time-to-solidify plain vs surrogate")
+                         "surrogate: train on chill-cube trajectories, then time-to-solidify plain vs surrogate; "
+                         "apparent: the 128^3 mesh stepped in the apparent-heat-capacity form, compared with "
+                         "the enthalpy form")
+    ap.add_argument("--compare-steps", type=int, default=20000,
+                    help="apparent: steps of both forms compared for energy drift and front position")
     ap.add_argument("--train-traj", type=int, default=500, help="surrogate: training trajectories (seeds 5000+)")
     ap.add_argument("--held-out", type=int, default=None,
                     help="surrogate: held-out trajectories (seeds 5500+); default 50, or 20 inside the default run")
@@ -137,6 +147,8 @@ def main():
         if args.held_out is None:
             args.held_out = 50
         return bench_surrogate(args, log)
+    if args.workload == "apparent":
+        return bench_apparent(args, log)
     big = args.workload == "tet256"
     if big:
         args.no_surrogate = True
@@ -272,6 +284,110 @@ def main():
                 "within_0p5K", "n_held_out", "jumps_kept", "jumps_rejected", "explicit_steps_computed_frac",
                 "train", "inference", "timing", "extrapolation_only", "config")
         out["surrogate"] = {k: sur[k] for k in keep}
+    print(json.dumps(out), flush=True)
+
+
+def bench_apparent(args, log):
+    """The 128^3 cast/mould mesh in the apparent-heat-capacity form (Eq. 6 with
+    Lemmon's element dH/dT, Eq. 7): timed steps, the element kernel against the
+    HBM roofline, a full-size parity spot check against the oracle's apparent
+    form, and the energy drift and solidification progress of both forms."""
+    import torch
+    from castgen import configs
+    from paper_1005_3158_amd import castfem as cf
+
+    prob = configs.config2(n=args.n)
+    E, N = prob["conn"].shape[0], prob["xyz"].shape[0]
+    block_nodes = 512 if args.block_nodes is None else args.block_nodes
+    app = dict(precision=cf.FEM_PREC_FP32_KAHAN, latent_model=cf.FEM_LATENT_APPARENT,
+               lds_bytes=36 * block_nodes)
+    t0 = time.time()
+    s = cf.Solver(prob, **app)
+    t_setup = time.time() - t0
+    rep = s.report
+    dt = 0.9 * s.stable_dt()
+    log("apparent form: %d tets, %d nodes; setup %.1f s, blocks %d, max local nodes %d"
+        % (E, N, t_setup, rep["n_blocks"], rep["max_local_nodes"]))
+    s.step(dt, args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(dt, args.steps)
+    torch.cuda.synchronize()
+    t_run = time.perf_counter() - t0
+    value = E * args.steps / t_run
+    eff_gbs = (16.0 * E + 44.0 * N) * args.steps / t_run / 1e9
+    kt = cf.fem_time_kernels(s.ctx, dt, args.profile_steps)
+    ach_e = kt["bytes_element"] / (kt["ms_element"] * 1e-3) / 1e9
+    ach_c = kt["bytes_combine"] / (kt["ms_combine"] * 1e-3) / 1e9 if kt["ms_combine"] > 0 else None
+    log("steps %d in %.4f s: %.3f ms/step, %.4g element-steps/s; element kernel %.4f ms (%.1f GB/s alg), "
+        "node kernel %.4f ms" % (args.steps, t_run, 1e3 * t_run / args.steps, value, kt["ms_element"], ach_e,
+                                 kt["ms_combine"]))
+    s.close()
+
+    # both forms from the same initial state over the same steps
+    cmp = {}
+    for name, opts in (("enthalpy", dict(precision=cf.FEM_PREC_FP32_KAHAN, lds_bytes=cf.lds_for_nodes(block_nodes))),
+                       ("apparent", app)):
+        r = cf.Solver(prob, **opts)
+        r.step(dt, args.compare_steps)
+        en = r.energy()
+        cmp[name] = dict(T=r.T(), fs=r.fs(), residual=en["residual"], n_liquid=en["n_liquid"],
+                         latent_J=en["latent"])
+        r.close()
+    dT = np.abs(cmp["apparent"]["T"] - cmp["enthalpy"]["T"])
+    comparison = {
+        "steps": args.compare_steps, "t_s": args.compare_steps * dt,
+        "energy_residual": {k: cmp[k]["residual"] for k in cmp},
+        "n_liquid": {k: cmp[k]["n_liquid"] for k in cmp},
+        "latent_J_left": {k: cmp[k]["latent_J"] for k in cmp},
+        "max_abs_dT_K": float(np.max(dT)), "rms_dT_K": float(np.sqrt(np.mean(dT ** 2))),
+        "mean_fs": {k: float(np.mean(cmp[k]["fs"])) for k in cmp},
+    }
+    log("after %d steps: energy residual enthalpy %.2e, apparent %.2e; liquid nodes %d vs %d; max|dT| %.3f K"
+        % (args.compare_steps, comparison["energy_residual"]["enthalpy"], comparison["energy_residual"]["apparent"],
+           comparison["n_liquid"]["enthalpy"], comparison["n_liquid"]["apparent"], comparison["max_abs_dT_K"]))
+
+    cpu = parity = None
+    if args.cpu_steps > 0:
+        from oracle import oracle
+        k = args.cpu_steps
+        g = cf.Solver(prob, **app)
+        g.step(dt, k)
+        T_gpu = g.T()
+        g.close()
+        P = oracle.Problem(prob)
+        t0 = time.perf_counter()
+        _, T_ref, _ = oracle.run_apparent(P, dt, k)
+        t_cpu = time.perf_counter() - t0
+        cpu = {"value": E * k / t_cpu, "unit": "element-steps/s", "cores": 1, "kind": "oracle",
+               "sample": "%d apparent-capacity steps of the full 128^3 mesh from the initial state (FP64, one "
+                         "thread, including its lumping and initial enthalpy), %.1f s" % (k, t_cpu)}
+        parity = {"steps": k, "max_abs_dT_K": float(np.max(np.abs(T_gpu - T_ref)))}
+        log("oracle: %d steps in %.1f s; max|T_gpu - T_oracle| = %.3e K" % (k, t_cpu, parity["max_abs_dT_K"]))
+
+    traffic = load_traffic("block_apparent_config2", rep["max_local_nodes"], APPARENT_SOURCES)
+    out = {
+        "metric": METRIC, "value": value, "unit": "element-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * t_run / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 (compensated enthalpy state, f64 T update and reductions)", "data": "synthetic",
+        "config": {
+            "workload": "128^3 jittered Kuhn tets (%d tets, %d nodes), alloy cube in sand mould, apparent heat "
+                        "capacity with Lemmon's element dH/dT, Hilbert ordering, LDS-blocked scatter, "
+                        "dt=0.9 x bound" % (E, N),
+            "n_elems": E, "n_nodes": N, "dt": dt, "block_nodes": rep["max_local_nodes"],
+            "n_blocks": rep["n_blocks"], "setup_s": t_setup,
+        },
+        "effective_GBps": eff_gbs, "effective_frac_hbm": eff_gbs / HBM_PEAK_GBS,
+        "roofline": {
+            "bound": "hbm", "kernel": "k_block_app<float> (blocked residual + Lemmon capacitance + private update)",
+            "achieved": ach_e, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach_e / HBM_PEAK_GBS,
+            "traffic": traffic, "ms_per_launch": kt["ms_element"], "alg_bytes_per_launch": kt["bytes_element"],
+            "node_kernel": {"ms_per_launch": kt["ms_combine"], "alg_bytes_per_launch": kt["bytes_combine"],
+                            "achieved": ach_c},
+        },
+        "cpu_baseline": cpu, "parity": parity, "vs_enthalpy": comparison,
+    }
     print(json.dumps(out), flush=True)
 
 

@@ -57,6 +57,19 @@ enum { FEM_TET4 = 4, FEM_HEX8 = 8 };
 enum { FEM_PREC_FP64 = 0, FEM_PREC_FP32_KAHAN = 1 };
 enum { FEM_ORDER_NONE = 0, FEM_ORDER_RCM = 1, FEM_ORDER_MORTON = 2, FEM_ORDER_HILBERT = 3 };
 enum { FEM_SCATTER_GLOBAL_ATOMIC = 0, FEM_SCATTER_LDS_BLOCKED = 1, FEM_SCATTER_COLORED = 2 };
+/* Latent-heat model.
+ * ENTHALPY: the nodal enthalpy is advanced, H_i += dt r_i / m_i, T = T(H)
+ *   (Eq. 5 and Eq. 11); conserves energy exactly.
+ * APPARENT: the paper's apparent heat capacity (Eq. 6) with Lemmon's element
+ *   value of dH/dT (Eq. 7): per element C_app = |grad H| / |grad T| from the
+ *   linear interpolants of the nodal H(T_j) and T_j (where grad T = 0, the slope
+ *   of H(T) at the element's mean temperature), lumped to
+ *   C_i = sum_e rho C_app V / 4 and re-assembled every step; the update is
+ *   T_i += dt r_i / C_i (Eq. 14) and the state keeps H_i = H(T_i), so energy is
+ *   no longer conserved exactly where elements straddle the solidus or
+ *   liquidus.  Linear tetrahedra and the LDS-blocked scatter only; a material
+ *   with L > 0 needs T_liq > T_sol.  Not accepted by the surrogate. */
+enum { FEM_LATENT_ENTHALPY = 0, FEM_LATENT_APPARENT = 1 };
 
 typedef struct fem_ctx fem_ctx;
 
@@ -69,7 +82,8 @@ typedef struct {
     int32_t allow_unstable;  /* nonzero: fem_step accepts dt above the bound */
     int32_t lds_bytes;       /* LDS-blocked: LDS budget per workgroup; 0 = default */
     int32_t threads;         /* LDS-blocked: threads per workgroup; 0 = default (256) */
-    int32_t reserved[8];     /* must be zero */
+    int32_t latent_model;    /* FEM_LATENT_*; 0 = enthalpy */
+    int32_t reserved[7];     /* must be zero */
 } fem_options;
 
 /* One material: conductivity k (W/mK), density rho (kg/m^3), specific heat c
@@ -223,7 +237,8 @@ int fem_get_node_perm(const fem_ctx *ctx, int32_t *perm);
 /* ------------------------------------------------------------ measurement */
 /* Run n_steps without a graph, bracketing every kernel with HIP events on the
  * context stream, and return the mean launch durations and the algorithmic
- * bytes per launch (16 B per element, 48 B per node split between kernels). */
+ * bytes per launch (16 B per element, 48 B per node split between kernels;
+ * 44 B per node in the apparent-capacity form, which reads no 1/m_i). */
 int fem_time_kernels(fem_ctx *ctx, double dt, int64_t n_steps, fem_kernel_times *out);
 /* Device-to-device copy of `bytes` (multiple of 16) by a plain vector kernel on
  * the context stream; the reference for measured bandwidth and counters. */

@@ -19,6 +19,7 @@ FEM_TET4, FEM_HEX8 = 4, 8
 FEM_PREC_FP64, FEM_PREC_FP32_KAHAN = 0, 1
 FEM_ORDER_NONE, FEM_ORDER_RCM, FEM_ORDER_MORTON, FEM_ORDER_HILBERT = 0, 1, 2, 3
 FEM_SCATTER_GLOBAL_ATOMIC, FEM_SCATTER_LDS_BLOCKED, FEM_SCATTER_COLORED = 0, 1, 2
+FEM_LATENT_ENTHALPY, FEM_LATENT_APPARENT = 0, 1
 # LDS bytes per block-local node of the blocked element kernel, by precision
 LDS_PER_NODE = {FEM_PREC_FP64: 48, FEM_PREC_FP32_KAHAN: 28}
 
@@ -49,7 +50,8 @@ class FemError(RuntimeError):
 class fem_options(C.Structure):
     _fields_ = [("device", C.c_int32), ("precision", C.c_int32), ("ordering", C.c_int32),
                 ("scatter", C.c_int32), ("block_elems", C.c_int32), ("allow_unstable", C.c_int32),
-                ("lds_bytes", C.c_int32), ("threads", C.c_int32), ("reserved", C.c_int32 * 8)]
+                ("lds_bytes", C.c_int32), ("threads", C.c_int32), ("latent_model", C.c_int32),
+                ("reserved", C.c_int32 * 7)]
 
 
 class fem_material(C.Structure):
@@ -427,10 +429,12 @@ def fem_advance(ctx, sur, dt_per_scenario, max_steps, until_solid=True, energy_t
 
 # ------------------------------------------------------------ convenience
 def make_options(precision=FEM_PREC_FP32_KAHAN, ordering=FEM_ORDER_HILBERT, scatter=FEM_SCATTER_LDS_BLOCKED,
-                 block_elems=0, device=0, allow_unstable=False, lds_bytes=0, threads=0):
+                 block_elems=0, device=0, allow_unstable=False, lds_bytes=0, threads=0,
+                 latent_model=FEM_LATENT_ENTHALPY):
     o = fem_options()
     o.device, o.precision, o.ordering, o.scatter = device, precision, ordering, scatter
     o.block_elems, o.allow_unstable, o.lds_bytes, o.threads = block_elems, int(allow_unstable), lds_bytes, threads
+    o.latent_model = latent_model
     return o
 
 

@@ -43,6 +43,10 @@ void layout_sizes(const fem_ctx *c, const Layout &L, int64_t *sz) {
         sz[B_PARTIALS] = np * R;
         sz[B_COMB_PTR] = (N - L.n_private + 1) * 4;
         sz[B_SH_POS] = np * 4;
+        if (c->apparent()) {
+            sz[B_CAP_PARTIALS] = np * R;
+            sz[B_APP_MATS] = (int64_t)c->prob.mats.size() * (int64_t)sizeof(AppMat);
+        }
     }
     sz[B_ROBIN] = (int64_t)L.robin_a.size() * 2 * R;
     sz[B_LINK_PTR] = (L.n_bc_slots + 1) * 4;
@@ -81,7 +85,9 @@ void upload_layout_t(fem_ctx *c, const Layout &L) {
         v.x = (R)L.xyz[3 * n];
         v.y = (R)L.xyz[3 * n + 1];
         v.z = (R)L.xyz[3 * n + 2];
-        v.w = (R)c->prob.mats[f & NODE_MAT_MASK].k;   // conductivity of the node's material
+        // conductivity of the node's material; the apparent-capacity kernel
+        // takes the material index instead
+        v.w = c->apparent() ? (R)(f & NODE_MAT_MASK) : (R)c->prob.mats[f & NODE_MAT_MASK].k;
         nx[n] = v;
         im[n] = (R)(1.0 / L.m[n]);
         const fem_material &mat = c->prob.mats[f & NODE_MAT_MASK];
@@ -121,6 +127,7 @@ void upload_layout_t(fem_ctx *c, const Layout &L) {
     h2d(c, B_FS, fs.data(), N * (int64_t)sizeof(R));
     h2d(c, B_FLAGS, L.nflag.data(), N * 4);
     std::vector<R> rob(L.robin_a.size() * 2), lw(L.link_w.size());
+    std::vector<BlockInfo> blocks_app;
     for (size_t s = 0; s < L.robin_a.size(); ++s) {
         rob[2 * s] = (R)L.robin_a[s];
         rob[2 * s + 1] = (R)L.robin_b[s];
@@ -132,13 +139,54 @@ void upload_layout_t(fem_ctx *c, const Layout &L) {
     h2d(c, B_LINK_W, lw.data(), (int64_t)lw.size() * (int64_t)sizeof(R));
     if (c->opt.scatter == FEM_SCATTER_LDS_BLOCKED) {
         h2d(c, B_LCONN, L.lconn.data(), (int64_t)L.lconn.size() * 2);
-        h2d(c, B_BLOCKS, L.blocks.data(), (int64_t)L.blocks.size() * (int64_t)sizeof(BlockInfo));
+        if (c->apparent()) {
+            // the apparent-capacity kernels read the material of a block whose
+            // nodes all share one once per block (pad0; -1 for mixed blocks)
+            blocks_app = L.blocks;
+            for (BlockInfo &b : blocks_app) {
+                int32_t m = -1;
+                bool mixed = false;
+                auto see = [&](int64_t g) {
+                    const int32_t q = (int32_t)(L.nflag[g] & NODE_MAT_MASK);
+                    if (m < 0) m = q;
+                    else if (q != m) mixed = true;
+                };
+                for (int32_t i = 0; i < b.n_int; ++i) see((int64_t)b.int_base + i);
+                for (int32_t i = 0; i < b.n_sh; ++i) see(L.sh_list[b.sh_begin + i]);
+                b.pad0 = mixed ? -1 : m;
+            }
+            h2d(c, B_BLOCKS, blocks_app.data(), (int64_t)blocks_app.size() * (int64_t)sizeof(BlockInfo));
+        } else {
+            h2d(c, B_BLOCKS, L.blocks.data(), (int64_t)L.blocks.size() * (int64_t)sizeof(BlockInfo));
+        }
         h2d(c, B_SH_LIST, L.sh_list.data(), (int64_t)L.sh_list.size() * 4);
         h2d(c, B_COMB_PTR, L.comb_ptr.data(), (int64_t)L.comb_ptr.size() * 4);
         h2d(c, B_SH_POS, L.sh_pos.data(), (int64_t)L.sh_pos.size() * 4);
     } else {
         h2d(c, B_CONN, L.conn.data(), (int64_t)L.conn.size() * 4);
         HIPCHECK(hipMemsetAsync(c->ptr[B_R], 0, N * sizeof(R), c->stream));
+    }
+    std::vector<AppMat> am;
+    if (c->apparent()) {
+        for (const fem_material &m : c->prob.mats) {
+            AppMat a{};
+            a.k = m.k;
+            a.rho = m.rho;
+            a.c = m.c;
+            a.L = m.L;
+            a.Ts = m.T_sol;
+            a.Tl = m.T_liq;
+            a.inv_dT = m.L > 0 ? 1.0 / (m.T_liq - m.T_sol) : 0.0;
+            a.kf = (float)a.k;
+            a.rhof = (float)a.rho;
+            a.cf = (float)a.c;
+            a.Lf = (float)a.L;
+            a.Tsf = (float)a.Ts;
+            a.Tlf = (float)a.Tl;
+            a.inv_dTf = (float)a.inv_dT;
+            am.push_back(a);
+        }
+        h2d(c, B_APP_MATS, am.data(), (int64_t)(am.size() * sizeof(AppMat)));
     }
     int64_t sz[B_COUNT];
     layout_sizes(c, L, sz);
@@ -201,6 +249,65 @@ void fill_dev(fem_ctx *c, const Candidate &cd) {
         d.fx_limit = (float)std::ldexp(1.0, 50 - S);
     }
     c->dev = d;
+    if (c->apparent()) {
+        AppDev a;
+        a.d = d;
+        a.d.lds_bytes = (size_t)L.max_local * lds_per_node_apparent(d.prec);
+        a.cap_partials = c->ptr[B_CAP_PARTIALS];
+        a.amats = (const AppMat *)c->ptr[B_APP_MATS];
+        // capacitance sums: every element share is positive and each node's
+        // sum is at most cap_bound; a margin of 4 keeps them below 2^50
+        const double bound = 4.0 * std::max(c->cap_bound, 1e-300);
+        const int S = std::min(80, (int)std::floor(std::log2(std::ldexp(1.0, 50) / bound)));
+        a.cx_scale = std::ldexp(1.0, S);
+        a.cx_inv = std::ldexp(1.0, -S);
+        a.cx_limit = (float)std::ldexp(1.0, 50 - S);
+        c->app = a;
+    }
+}
+
+hipError_t enqueue_ctx_step(const fem_ctx *c, int parity, hipStream_t s, hipEvent_t *ev) {
+    return c->apparent() ? enqueue_step_apparent(c->app, parity, s, ev) : enqueue_step(c->dev, parity, s, ev);
+}
+
+// Bound on the lumped apparent capacitance of any node: an element's Lemmon
+// ratio |A W a| / |A a| (A = [c_1 c_2 c_3], W = diag of dH/dT over the nodal
+// differences a) is at most max dH/dT times ||A|| ||A^-1||, and A^-1 = [d_j]^T / D;
+// the Frobenius norms bound both.
+double apparent_cap_bound(const Problem &p) {
+    std::vector<double> acc(p.N, 0.0);
+    for (int64_t e = 0; e < p.E; ++e) {
+        const int32_t *cn = &p.conn[4 * e];
+        const double *x0 = &p.xyz[3 * cn[0]];
+        double d[3][3];
+        for (int j = 0; j < 3; ++j)
+            for (int i = 0; i < 3; ++i) d[j][i] = p.xyz[3 * cn[j + 1] + i] - x0[i];
+        auto cross = [](const double *a, const double *b, double *o) {
+            o[0] = a[1] * b[2] - a[2] * b[1];
+            o[1] = a[2] * b[0] - a[0] * b[2];
+            o[2] = a[0] * b[1] - a[1] * b[0];
+        };
+        double cv[3][3];
+        cross(d[1], d[2], cv[0]);
+        cross(d[2], d[0], cv[1]);
+        cross(d[0], d[1], cv[2]);
+        const double D = d[0][0] * cv[0][0] + d[0][1] * cv[0][1] + d[0][2] * cv[0][2];
+        double nc = 0, nd = 0;
+        for (int j = 0; j < 3; ++j)
+            for (int i = 0; i < 3; ++i) {
+                nc += cv[j][i] * cv[j][i];
+                nd += d[j][i] * d[j][i];
+            }
+        const fem_material &m = p.mats[p.emat[e]];
+        const double wmax = m.c + (m.L > 0 ? m.L / (m.T_liq - m.T_sol) : 0.0);
+        // rho * wmax * (||A|| ||A^-1||) * V / 4 with ||A^-1|| = sqrt(nd) / |D| and V / 4 = |D| / 24
+        const double share = m.rho * wmax * std::sqrt(nc * nd) / 24.0;
+        (void)D;
+        for (int a = 0; a < 4; ++a) acc[cn[a]] += share;
+    }
+    double mx = 0;
+    for (double v : acc) mx = std::max(mx, v);
+    return mx;
 }
 
 void reset_graph(fem_ctx *c) {
@@ -224,7 +331,7 @@ void set_dt(fem_ctx *c, double dt) { set_dt_scen(c, std::vector<double>(c->prob.
 
 void eager_steps(fem_ctx *c, int64_t n) {
     for (int64_t s = 0; s < n; ++s) {
-        HIPCHECK(enqueue_step(c->dev, c->parity, c->stream, nullptr));
+        HIPCHECK(enqueue_ctx_step(c, c->parity, c->stream, nullptr));
         c->parity ^= 1;
     }
 }
@@ -241,7 +348,7 @@ void run_steps(fem_ctx *c, int64_t n) {
     if (!c->gexec) {
         HIPCHECK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
         hipError_t err = hipSuccess;
-        for (int s = 0; s < GRAPH_STEPS && err == hipSuccess; ++s) err = enqueue_step(c->dev, s & 1, c->stream, nullptr);
+        for (int s = 0; s < GRAPH_STEPS && err == hipSuccess; ++s) err = enqueue_ctx_step(c, s & 1, c->stream, nullptr);
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(c->stream, &g);
         HIPCHECK(err);
@@ -298,6 +405,8 @@ int fem_create(fem_ctx **out, const fem_options *opt) {
             throw PrepError{FEM_E_INVALID_ARG, "unknown scatter"};
         if (o.block_elems < 0 || o.lds_bytes < 0 || o.threads < 0) throw PrepError{FEM_E_INVALID_ARG, "negative size option"};
         if (o.threads && (o.threads % 64 || o.threads > 1024)) throw PrepError{FEM_E_INVALID_ARG, "threads must be a multiple of 64 up to 1024"};
+        if (o.latent_model != FEM_LATENT_ENTHALPY && o.latent_model != FEM_LATENT_APPARENT)
+            throw PrepError{FEM_E_INVALID_ARG, "unknown latent-heat model"};
         for (int r : o.reserved)
             if (r) throw PrepError{FEM_E_INVALID_ARG, "reserved option fields must be zero"};
         fem_ctx *c = new fem_ctx();
@@ -414,12 +523,20 @@ int fem_finalize(fem_ctx *ctx, fem_prep_report *rep) {
         if (ctx->stage != ST_NEW) throw PrepError{FEM_E_STATE, "already finalized"};
         if (!ctx->have_mesh) throw PrepError{FEM_E_STATE, "no mesh uploaded"};
         auto t0 = std::chrono::steady_clock::now();
+        if (ctx->apparent()) {
+            if (ctx->prob.nen != FEM_TET4) throw PrepError{FEM_E_UNSUPPORTED, "apparent capacity: linear tetrahedra only"};
+            if (ctx->opt.scatter != FEM_SCATTER_LDS_BLOCKED)
+                throw PrepError{FEM_E_UNSUPPORTED, "apparent capacity: LDS-blocked scatter only"};
+            for (const fem_material &m : ctx->prob.mats)
+                if (m.L > 0 && !(m.T_liq > m.T_sol))
+                    throw PrepError{FEM_E_UNSUPPORTED, "apparent capacity needs T_liq > T_sol where L > 0"};
+        }
         Base base;
         prep_base(ctx->prob, base);
         Ordering ord;
         prep_order(ctx->prob, base, ctx->opt.ordering, ord);
         std::vector<Candidate> cands;
-        const size_t per = lds_per_node(ctx->opt.precision);
+        const size_t per = ctx->apparent() ? lds_per_node_apparent(ctx->opt.precision) : lds_per_node(ctx->opt.precision);
         const int thr = ctx->opt.threads ? ctx->opt.threads : 256;
         if (ctx->opt.scatter == FEM_SCATTER_LDS_BLOCKED && ctx->opt.block_elems == 0 && ctx->opt.lds_bytes == 0) {
             // autotune over block node sets (the paper's timed search over the block count);
@@ -469,6 +586,7 @@ int fem_finalize(fem_ctx *ctx, fem_prep_report *rep) {
             layout_sizes(ctx, c.L, sz);
             for (int b = 0; b < B_COUNT; ++b) ctx->sizes[b] = std::max(ctx->sizes[b], sz[b]);
         }
+        ctx->cap_bound = ctx->apparent() ? apparent_cap_bound(ctx->prob) : 0.0;
         ctx->mats_host.resize(ctx->prob.mats.size());
         for (size_t q = 0; q < ctx->prob.mats.size(); ++q) ctx->mats_host[q] = make_mat(ctx->prob.mats[q], 0.0);
         ctx->setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -518,10 +636,12 @@ int fem_bind_buffers(fem_ctx *ctx, void *const *dev_ptrs, int32_t n) {
             hipDeviceProp_t prop;
             HIPCHECK(hipGetDeviceProperties(&prop, ctx->opt.device));
             size_t mx = 0;
-            for (const Candidate &c : ctx->cands) mx = std::max(mx, (size_t)c.L.max_local * lds_per_node(ctx->opt.precision));
+            const size_t per = ctx->apparent() ? lds_per_node_apparent(ctx->opt.precision) : lds_per_node(ctx->opt.precision);
+            for (const Candidate &c : ctx->cands) mx = std::max(mx, (size_t)c.L.max_local * per);
             const size_t cap = prop.maxSharedMemoryPerMultiProcessor ? prop.maxSharedMemoryPerMultiProcessor : prop.sharedMemPerBlock;
             if (mx + 1024 > cap) throw PrepError{FEM_E_UNSUPPORTED, "block LDS footprint above the device limit"};
-            HIPCHECK(set_block_lds_limit(ctx->opt.precision, ctx->prob.nen, mx));
+            if (ctx->apparent()) HIPCHECK(set_apparent_lds_limit(ctx->opt.precision, mx));
+            else HIPCHECK(set_block_lds_limit(ctx->opt.precision, ctx->prob.nen, mx));
         }
         ctx->dt_s.clear();
         if (ctx->cands.size() > 1) {
@@ -892,7 +1012,7 @@ int fem_time_kernels(fem_ctx *ctx, double dt, int64_t n_steps, fem_kernel_times 
         std::vector<hipEvent_t> ev(4 * n_steps);
         for (auto &e : ev) HIPCHECK(hipEventCreate(&e));
         for (int64_t s = 0; s < n_steps; ++s) {
-            HIPCHECK(enqueue_step(ctx->dev, ctx->parity, ctx->stream, &ev[4 * s]));
+            HIPCHECK(enqueue_ctx_step(ctx, ctx->parity, ctx->stream, &ev[4 * s]));
             ctx->parity ^= 1;
         }
         HIPCHECK(hipEventSynchronize(ev.back()));
@@ -910,7 +1030,8 @@ int fem_time_kernels(fem_ctx *ctx, double dt, int64_t n_steps, fem_kernel_times 
         const Layout &L = ctx->L();
         const double R = (double)ctx->rsize();
         const double gather = 4.0 * R + 4.0;             // xyz + T read + flags
-        const double update = R + 16.0 + 2.0 * R;        // 1/m, H read+write, T and fs write
+        // 1/m (enthalpy form only), H read+write, T and fs write
+        const double update = (ctx->apparent() ? 0.0 : R) + 16.0 + 2.0 * R;
         const double elem = 4.0 * L.nen;                 // connectivity
         const bool blocked = ctx->opt.scatter == FEM_SCATTER_LDS_BLOCKED;
         const double upd_k1 = blocked ? (double)L.n_private : 0.0;

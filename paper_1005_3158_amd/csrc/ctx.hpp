@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/castfem.h"
+#include "apparent.hpp"
 #include "kernels.hpp"
 #include "prep.hpp"
 
@@ -30,11 +31,13 @@ enum Stage { ST_NEW = 0, ST_FINAL = 1, ST_BOUND = 2 };
 
 enum Buf {
     B_NODE_X, B_T, B_H, B_INV_M, B_FS, B_MATS, B_CONN, B_R, B_LCONN, B_BLOCKS, B_SH_LIST, B_PARTIALS,
-    B_COMB_PTR, B_SH_POS, B_ROBIN, B_LINK_PTR, B_LINK_NODE, B_LINK_W, B_DIAG, B_QNODE, B_FLAGS, B_SEG, B_COUNT
+    B_COMB_PTR, B_SH_POS, B_ROBIN, B_LINK_PTR, B_LINK_NODE, B_LINK_W, B_DIAG, B_QNODE, B_FLAGS, B_SEG,
+    B_CAP_PARTIALS, B_APP_MATS, B_COUNT
 };
 inline const char *const BUF_NAMES[B_COUNT] = {"node_x", "T", "H", "inv_m", "fs", "mats", "conn", "r", "lconn", "blocks",
                                   "sh_list", "partials", "comb_ptr", "sh_pos", "robin", "link_ptr",
-                                  "link_node", "link_w", "diag", "qnode", "flags", "segments"};
+                                  "link_node", "link_w", "diag", "qnode", "flags", "segments",
+                                  "cap_partials", "app_mats"};
 constexpr int64_t ALIGN = 256;
 constexpr int GRAPH_STEPS = 16;  // steps per captured graph (even: both parities)
 constexpr size_t MAX_BLOCK_LDS = 160 * 1024 - 2048;  // gfx950 LDS per workgroup, less static use
@@ -101,6 +104,8 @@ struct fem_ctx {
     int64_t sizes[B_COUNT] = {};
     void *ptr[B_COUNT] = {};
     Dev dev;
+    AppDev app;                 // apparent-capacity mode: the step's view of the buffers
+    double cap_bound = 0;       // apparent mode: bound on any node's lumped capacitance (J/K)
     std::vector<MatDev> mats_host;
     int parity = 0;
     int64_t steps = 0;
@@ -116,6 +121,7 @@ struct fem_ctx {
     Layout &L() { return cands[chosen].L; }
     const Layout &L() const { return cands[chosen].L; }
     size_t rsize() const { return opt.precision == FEM_PREC_FP64 ? 8 : 4; }
+    bool apparent() const { return opt.latent_model == FEM_LATENT_APPARENT; }
 };
 
 
@@ -125,6 +131,8 @@ namespace castfem {
 void set_dt(fem_ctx *c, double dt);
 void set_dt_scen(fem_ctx *c, const std::vector<double> &dt);
 void eager_steps(fem_ctx *c, int64_t n);
+// one step of the context's latent-heat model (see enqueue_step)
+hipError_t enqueue_ctx_step(const fem_ctx *c, int parity, hipStream_t s, hipEvent_t *ev);
 void run_steps(fem_ctx *c, int64_t n);
 void check_bound(fem_ctx *c, int fn_stage);
 void energy_scenarios(fem_ctx *ctx, fem_energy_report *reps);

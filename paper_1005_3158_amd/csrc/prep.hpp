@@ -40,7 +40,7 @@ struct BlockInfo {        // one LDS element block (8 ints, 32 bytes)
     int32_t n_int;        // private nodes: local ids 0..n_int-1
     int32_t sh_begin;     // offset of its shared-node list (and partial slots)
     int32_t n_sh;         // shared nodes: local ids n_int..n_int+n_sh-1
-    int32_t pad0, pad1;
+    int32_t pad0, pad1;   // pad0: in the apparent-capacity form, the block's one material or -1
 };
 
 struct Layout {

@@ -141,3 +141,33 @@ def test_buffer_query_shapes():
         cf.fem_bind_buffers(ctx, [0] * 3)
     assert e.value.code == -1
     cf.fem_destroy(ctx)
+
+
+def test_apparent_mode_options_and_buffers():
+    """The apparent-capacity mode: unknown model ids, hexahedra, other scatters and
+    isothermal latent materials are refused; a tet problem gets the extra
+    capacitance partials and material table."""
+    with pytest.raises(cf.FemError) as e:
+        cf.fem_create(cf.make_options(latent_model=5))
+    assert e.value.code == -1
+    app = cf.FEM_LATENT_APPARENT
+    for prob, opts in ((configs.config1(), {}),
+                       (configs.config2(n=6), dict(scatter=cf.FEM_SCATTER_COLORED)),
+                       (configs.config2(n=6), dict(scatter=cf.FEM_SCATTER_GLOBAL_ATOMIC)),
+                       (configs.tet_bar(nx=4, material=(150.0, 2700.0, 900.0, 660.0, 660.0, 3.9e5)), {})):
+        ctx = cf.fem_create(cf.make_options(latent_model=app, **opts))
+        with pytest.raises(cf.FemError) as e:
+            cf.setup_problem(ctx, prob)
+        assert e.value.code == -7
+        cf.fem_destroy(ctx)
+    p = configs.config2(n=6)
+    sizes = {}
+    for model in (cf.FEM_LATENT_ENTHALPY, app):
+        ctx = cf.fem_create(cf.make_options(latent_model=model, lds_bytes=36 * 200))
+        rep = cf.setup_problem(ctx, p)
+        sizes[model] = ({n: b for n, b, a in cf.fem_query_buffers(ctx)}, rep)
+        cf.fem_destroy(ctx)
+    bufs, rep = sizes[app]
+    assert bufs["cap_partials"] >= 4 * rep["n_partials"] > 0
+    assert bufs["app_mats"] > 0
+    assert sizes[cf.FEM_LATENT_ENTHALPY][0]["cap_partials"] == 0
