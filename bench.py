@@ -322,6 +322,12 @@ def bench_apparent(args, log):
     log("steps %d in %.4f s: %.3f ms/step, %.4g element-steps/s; element kernel %.4f ms (%.1f GB/s alg), "
         "node kernel %.4f ms" % (args.steps, t_run, 1e3 * t_run / args.steps, value, kt["ms_element"], ach_e,
                                  kt["ms_combine"]))
+    # plain copy ceiling (also the reference that scales the traffic counters)
+    nbytes = 1 << 30
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    copy_gbs = 2 * nbytes / (cf.fem_copy_kernel(s.ctx, dst.data_ptr(), src.data_ptr(), nbytes, 20) * 1e-3) / 1e9
+    del src, dst
     s.close()
 
     # both forms from the same initial state over the same steps
@@ -378,7 +384,7 @@ def bench_apparent(args, log):
             "n_elems": E, "n_nodes": N, "dt": dt, "block_nodes": rep["max_local_nodes"],
             "n_blocks": rep["n_blocks"], "setup_s": t_setup,
         },
-        "effective_GBps": eff_gbs, "effective_frac_hbm": eff_gbs / HBM_PEAK_GBS,
+        "effective_GBps": eff_gbs, "effective_frac_hbm": eff_gbs / HBM_PEAK_GBS, "copy_kernel_GBps": copy_gbs,
         "roofline": {
             "bound": "hbm", "kernel": "k_block_app<float> (blocked residual + Lemmon capacitance + private update)",
             "achieved": ach_e, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach_e / HBM_PEAK_GBS,
