@@ -224,6 +224,93 @@ def tet_casting(n=128, length=0.1, region="cube", cube=(0.2, 0.8), boxes_seed=6,
     return prob
 
 
+def boundary_triangles(conn):
+    """Faces of a tet mesh that belong to one tetrahedron only, (n, 3) node ids."""
+    f = np.concatenate([conn[:, [1, 2, 3]], conn[:, [0, 2, 3]], conn[:, [0, 1, 3]], conn[:, [0, 1, 2]]])
+    s = np.sort(f, axis=1)
+    _, inv, cnt = np.unique(s, axis=0, return_inverse=True, return_counts=True)
+    return f[cnt[inv.ravel()] == 1]
+
+
+def _jitter_interior(xyz, conn, interior, h, amp, seed, stream):
+    """U(+-amp h) per coordinate on the interior nodes; the nodes of any tet left with
+    6V < 0.1 h^3 go back to their grid position until none is left."""
+    off = rng.uniform(seed, stream, xyz.size, -amp * h, amp * h).reshape(xyz.shape)
+    off[~interior] = 0.0
+    while True:
+        x = xyz + off
+        bad = meshes._six_volume(x, conn) < 0.1 * h ** 3
+        if not np.any(bad):
+            return x
+        off[conn[bad].ravel()] = 0.0
+
+
+def tet_casting_nonmatching(n_cast=12, n_mold=8, length=0.1, cube=(0.25, 0.75), T_pour=700.0, T_mold=25.0,
+                            h_interface=1000.0, alloy=ALLOY, mold=SAND, jitter=0.15, jitter_seed=2, perm_seed=3,
+                            permute=True):
+    """A casting cube and its sand mould meshed separately (the paper's cast and mould
+    grids with no coincident interface nodes).
+
+    Mould: Kuhn tets of an n_mold^3 grid of [0, length]^3 without the cells of the cube
+    [cube[0], cube[1]]^3 (whose faces must lie on grid planes).  Casting: Kuhn tets of an
+    n_cast^3 grid of the cube itself.  The two meshes share no nodes; every boundary
+    triangle on the cube's surface is a contact face, side 0 for the mould and side 1 for
+    the casting, with coefficient h_interface; the sister pairing is left to the solver.
+    Nodes off every boundary plane are jittered by U(+-jitter h).
+    """
+    lo, hi = cube
+    if abs(lo * n_mold - round(lo * n_mold)) > 1e-9 or abs(hi * n_mold - round(hi * n_mold)) > 1e-9:
+        raise ValueError("the cube must lie on mould grid planes")
+    # mould part
+    cm = meshes.kuhn_conn(n_mold)
+    keep = ~np.repeat(meshes.cube_region_cells(n_mold, lo, hi), 6)
+    cm = cm[keep]
+    used = np.unique(cm)
+    ids = np.full((n_mold + 1) ** 3, -1, np.int64)
+    ids[used] = np.arange(used.size)
+    cm = ids[cm]
+    g = np.stack(meshes.grid_ids(n_mold), axis=1)[used]
+    xm = meshes.grid_xyz(n_mold, 1.0)[used] * length
+    planes_m = {0, int(round(lo * n_mold)), int(round(hi * n_mold)), n_mold}
+    inner_m = np.ones(used.size, dtype=bool)
+    for ax in range(3):
+        inner_m &= ~np.isin(g[:, ax], list(planes_m))
+    xm = _jitter_interior(xm, cm, inner_m, length / n_mold, jitter, jitter_seed, 30)
+    # casting part
+    cc = meshes.kuhn_conn(n_cast)
+    gc = np.stack(meshes.grid_ids(n_cast), axis=1)
+    xc = (lo + (hi - lo) * meshes.grid_xyz(n_cast, 1.0)) * length
+    inner_c = np.all((gc > 0) & (gc < n_cast), axis=1)
+    xc = _jitter_interior(xc, cc, inner_c, (hi - lo) * length / n_cast, jitter, jitter_seed, 31)
+    nm = xm.shape[0]
+    xyz = np.concatenate([xm, xc], axis=0)
+    conn = np.concatenate([cm, cc + nm], axis=0)
+    elem_mat = np.concatenate([np.ones(cm.shape[0], np.int32), np.zeros(cc.shape[0], np.int32)])
+    # contact faces: mould boundary triangles on the cube surface, then every casting boundary triangle
+    bm = boundary_triangles(cm)
+    c3 = xm[bm]
+    tol = 1e-9 * length
+    inside = np.all((c3 >= lo * length - tol) & (c3 <= hi * length + tol), axis=(1, 2))
+    bm = bm[inside]
+    bc = boundary_triangles(cc) + nm
+    faces = np.concatenate([bm, bc], axis=0)
+    side = np.concatenate([np.zeros(bm.shape[0], np.int32), np.ones(bc.shape[0], np.int32)])
+    N = xyz.shape[0]
+    T0 = np.concatenate([np.full(nm, float(T_mold)), np.full(xc.shape[0], float(T_pour))])
+    prob = dict(elem_type=4, xyz=xyz, conn=conn.astype(np.int32), elem_mat=elem_mat,
+                materials=np.array([alloy, mold], dtype=np.float64), T0=T0,
+                contact_faces=faces.astype(np.int32), contact_side=side,
+                contact_h=np.full(faces.shape[0], float(h_interface)),
+                meta=dict(kind="tet_casting_nonmatching", n_cast=n_cast, n_mold=n_mold, length=length, cube=cube,
+                          jitter=jitter, jitter_seed=jitter_seed, perm_seed=perm_seed))
+    prob = _empty_faces(prob)
+    if permute:
+        node_perm = rng.permutation(perm_seed, 0, N)
+        elem_perm = rng.permutation(perm_seed, 1, conn.shape[0])
+        prob = meshes.apply_permutations(prob, node_perm, elem_perm)
+    return prob
+
+
 def config1(**kw):
     """16^3 hex8 alloy cube, noise seed 1, 25 C on x = 0, adiabatic elsewhere."""
     return hex_cube(**kw)

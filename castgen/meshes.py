@@ -217,7 +217,7 @@ def apply_permutations(prob, node_perm, elem_perm):
     out["T0"] = prob["T0"][inv]
     out["conn"] = node_perm[prob["conn"][elem_perm]].astype(np.int32)
     out["elem_mat"] = prob["elem_mat"][elem_perm]
-    for key in ("dirichlet_nodes", "flux_faces", "if_a", "if_b"):
+    for key in ("dirichlet_nodes", "flux_faces", "if_a", "if_b", "contact_faces"):
         if key in prob and prob[key] is not None and np.size(prob[key]):
             out[key] = node_perm[prob[key]].astype(np.int32)
     return out

@@ -282,6 +282,42 @@ static int check_faces(const orc_problem *p)
             return ORC_ERR_MESH;
     for (int64_t d = 0; d < p->n_dir; ++d)
         if (p->dir_nodes[d] < 0 || p->dir_nodes[d] >= p->n_nodes) return ORC_ERR_MESH;
+    for (int64_t f = 0; f < p->n_contact; ++f) {
+        for (int a = 0; a < 3; ++a)
+            if (p->contact_faces[3 * f + a] < 0 || p->contact_faces[3 * f + a] >= p->n_nodes) return ORC_ERR_MESH;
+        if (p->contact_side[f] != 0 && p->contact_side[f] != 1) return ORC_ERR_ARG;
+    }
+    return 0;
+}
+
+static void face_centroid(const orc_problem *p, int64_t f, double c[3])
+{
+    const int32_t *fn = p->contact_faces + 3 * f;
+    for (int j = 0; j < 3; ++j)
+        c[j] = ((p->xyz[3 * fn[0] + j] + p->xyz[3 * fn[1] + j]) + p->xyz[3 * fn[2] + j]) / 3.0;
+}
+
+int orc_contact_sisters(const orc_problem *p, int32_t *sister)
+{
+    int rc = check_faces(p);
+    if (rc) return rc;
+    for (int64_t f = 0; f < p->n_contact; ++f) {
+        double a[3], b[3], best = INFINITY;
+        int64_t arg = -1;
+        face_centroid(p, f, a);
+        for (int64_t g = 0; g < p->n_contact; ++g) {
+            if (p->contact_side[g] == p->contact_side[f]) continue;
+            face_centroid(p, g, b);
+            double dx = a[0] - b[0], dy = a[1] - b[1], dz = a[2] - b[2];
+            double d2 = (dx * dx + dy * dy) + dz * dz;
+            if (d2 < best) {
+                best = d2;
+                arg = g;
+            }
+        }
+        if (arg < 0) return ORC_ERR_MESH;   /* no face on the other side */
+        sister[f] = (int32_t)arg;
+    }
     return 0;
 }
 
@@ -311,6 +347,26 @@ static void add_interface_pair(const orc_problem *p, int64_t f, const double *T,
     }
 }
 
+/* contact face f: each of its nodes sees the mean temperature of the sister
+ * face as ambient, r_i += h (A_f / 3)(Tbar_sister - T_i), A_f the face's own area */
+static void add_contact_face(const orc_problem *p, int64_t f, const double *T, double *r)
+{
+    const int32_t *fa = p->contact_faces + 3 * f, *fs = p->contact_faces + 3 * p->contact_sister[f];
+    double A = face_area(p->xyz, fa, 3);
+    double ts = (T[fs[0]] + T[fs[1]] + T[fs[2]]) / 3.0;
+    for (int a = 0; a < 3; ++a) r[fa[a]] += p->contact_h[f] * (A / 3.0) * (ts - T[fa[a]]);
+}
+
+static int check_sisters(const orc_problem *p)
+{
+    if (p->n_contact > 0 && !p->contact_sister) return ORC_ERR_ARG;
+    for (int64_t f = 0; f < p->n_contact; ++f) {
+        int32_t s = p->contact_sister[f];
+        if (s < 0 || s >= p->n_contact || p->contact_side[s] == p->contact_side[f]) return ORC_ERR_ARG;
+    }
+    return 0;
+}
+
 /* ------------------------------------------------------------ residual */
 
 int orc_residual(const orc_problem *p, const double *T, double *r)
@@ -318,6 +374,7 @@ int orc_residual(const orc_problem *p, const double *T, double *r)
     int nen = p->elem_type;
     if (nen != 4 && nen != 8) return ORC_ERR_ARG;
     int rc = check_faces(p);
+    if (rc == 0) rc = check_sisters(p);
     if (rc) return rc;
     for (int64_t i = 0; i < p->n_nodes; ++i) r[i] = 0.0;
     double Ke[64];
@@ -333,6 +390,7 @@ int orc_residual(const orc_problem *p, const double *T, double *r)
     }
     for (int64_t f = 0; f < p->n_flux; ++f) add_flux_face(p, f, T, r);
     for (int64_t f = 0; f < p->n_if; ++f) add_interface_pair(p, f, T, r);
+    for (int64_t f = 0; f < p->n_contact; ++f) add_contact_face(p, f, T, r);
     return 0;
 }
 
@@ -379,6 +437,12 @@ int orc_stable_dt(const orc_problem *p, double *dt_bound)
             extra[p->if_a[3 * f + a]] += 2.0 * p->if_h[f] * A / 3.0;
             extra[p->if_b[3 * f + a]] += 2.0 * p->if_h[f] * A / 3.0;
         }
+    }
+    /* a contact face adds h A / 3 to the diagonal of each of its nodes and the
+     * same in total to the off-diagonals (its sister's three nodes) */
+    for (int64_t f = 0; f < p->n_contact; ++f) {
+        double A = face_area(p->xyz, p->contact_faces + 3 * f, 3);
+        for (int a = 0; a < 3; ++a) extra[p->contact_faces[3 * f + a]] += 2.0 * p->contact_h[f] * A / 3.0;
     }
     {
         double lam = 0.0;
@@ -685,6 +749,7 @@ int orc_run_partitioned(const orc_problem *p, int32_t n_parts, const int32_t *el
     for (int64_t e = 0; e < E; ++e)
         if (elem_part[e] < 0 || elem_part[e] >= n_parts) return ORC_ERR_ARG;
     int rc = check_faces(p);
+    if (rc == 0) rc = check_sisters(p);
     if (rc) return rc;
     /* per partition: local capacitance C^l and local residual R^l over all nodes
      * (only the nodes of the partition are ever non-zero) */
@@ -718,6 +783,7 @@ int orc_run_partitioned(const orc_problem *p, int32_t n_parts, const int32_t *el
         }
         for (int64_t f = 0; f < p->n_flux; ++f) add_flux_face(p, f, T, Rl + (size_t)(f % n_parts) * N);
         for (int64_t f = 0; f < p->n_if; ++f) add_interface_pair(p, f, T, Rl + (size_t)(f % n_parts) * N);
+        for (int64_t f = 0; f < p->n_contact; ++f) add_contact_face(p, f, T, Rl + (size_t)(f % n_parts) * N);
         /* exchange: sum the partition-local values at every node, then update */
         for (int64_t i = 0; i < N; ++i) {
             if (fixed[i] || nmat[i] < 0) continue;

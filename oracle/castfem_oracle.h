@@ -58,6 +58,14 @@ typedef struct {
     int64_t n_if;
     const int32_t *if_a, *if_b; /* n_if x 3 each: matched faces on the two sides */
     const double *if_h;
+    /* contact faces of non-matching meshes: triangles on side 0 or 1 of a contact
+     * surface; the sister of each face (orc_contact_sisters) must be given before
+     * any residual is evaluated */
+    int64_t n_contact;
+    const int32_t *contact_faces;   /* n_contact x 3 */
+    const int32_t *contact_side;    /* n_contact, 0 or 1 */
+    const double *contact_h;        /* n_contact */
+    const int32_t *contact_sister;  /* n_contact, or NULL when n_contact == 0 */
 } orc_problem;
 
 /* per-state diagnostics written by orc_run, ORC_NDIAG doubles per state */
@@ -90,7 +98,13 @@ double orc_fs_of_H(const double mat[6], double H);
 int orc_lumped_mass(const orc_problem *p, double *m);
 /* Material of every node (-1 for nodes in no element); error if a node has two. */
 int orc_node_material(const orc_problem *p, int32_t *node_mat);
-/* r = F(T) - K T: element conduction, flux faces, interface pairs. */
+/* Sister of every contact face (end of Sec. 3: the closest element of the other
+ * region, found once at the start): the face of the other side whose centroid
+ * (x0 + x1 + x2) / 3 is nearest in squared Euclidean distance, ties to the lower
+ * face index; by brute force over all pairs. */
+int orc_contact_sisters(const orc_problem *p, int32_t *sister);
+/* r = F(T) - K T: element conduction, flux faces, interface pairs and contact
+ * faces (node i of face f: h_f (A_f / 3) (mean T of the sister face - T_i)). */
 int orc_residual(const orc_problem *p, const double *T, double *r);
 /* Explicit stability bound 2 / lambda_hat with the Gershgorin estimate of M^-1 K. */
 int orc_stable_dt(const orc_problem *p, double *dt_bound);

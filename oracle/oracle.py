@@ -53,6 +53,8 @@ class _Problem(C.Structure):
         ("n_flux", C.c_int64), ("flux_npf", C.c_int32), ("flux_faces", C.c_void_p),
         ("flux_q", C.c_void_p), ("flux_h", C.c_void_p), ("flux_Tinf", C.c_void_p),
         ("n_if", C.c_int64), ("if_a", C.c_void_p), ("if_b", C.c_void_p), ("if_h", C.c_void_p),
+        ("n_contact", C.c_int64), ("contact_faces", C.c_void_p), ("contact_side", C.c_void_p),
+        ("contact_h", C.c_void_p), ("contact_sister", C.c_void_p),
     ]
 
 
@@ -61,7 +63,9 @@ def _ptr(a):
 
 
 class Problem:
-    """Holds contiguous copies of a problem dict and the C struct pointing at them."""
+    """Holds contiguous copies of a problem dict and the C struct pointing at them.
+    Contact faces (non-matching meshes) get their sisters by the oracle's brute-force
+    search when the problem is built."""
 
     def __init__(self, prob):
         f8 = lambda k: np.ascontiguousarray(prob[k], dtype=np.float64)
@@ -83,7 +87,21 @@ class Problem:
             ff.shape[0] if ff.size else 0, ff.shape[1] if ff.ndim == 2 else 3, _ptr(ff),
             _ptr(k["flux_q"]), _ptr(k["flux_h"]), _ptr(k["flux_Tinf"]),
             k["if_a"].shape[0] if k["if_a"].size else 0, _ptr(k["if_a"]), _ptr(k["if_b"]),
-            _ptr(k["if_h"]))
+            _ptr(k["if_h"]), 0, None, None, None, None)
+        cf = prob.get("contact_faces")
+        if cf is not None and np.size(cf):
+            k["contact_faces"] = np.ascontiguousarray(cf, dtype=np.int32).reshape(-1, 3)
+            k["contact_side"] = np.ascontiguousarray(prob["contact_side"], dtype=np.int32)
+            k["contact_h"] = np.ascontiguousarray(prob["contact_h"], dtype=np.float64)
+            n = k["contact_faces"].shape[0]
+            self.s.n_contact = n
+            self.s.contact_faces = _ptr(k["contact_faces"])
+            self.s.contact_side = _ptr(k["contact_side"])
+            self.s.contact_h = _ptr(k["contact_h"])
+            k["contact_sister"] = np.zeros(n, np.int32)
+            _check(lib().orc_contact_sisters(C.byref(self.s), _ptr(k["contact_sister"])), "contact_sisters")
+            self.s.contact_sister = _ptr(k["contact_sister"])
+        self.sisters = k.get("contact_sister")
 
     @property
     def ref(self):
@@ -240,3 +258,8 @@ def run_apparent(prob, dt, n_steps, H=None, diag=False):
                                   _ptr(D) if diag else None), "run_apparent")
     T, fs = state_T(P, H)
     return (H, T, fs, D) if diag else (H, T, fs)
+
+
+def contact_sisters(prob):
+    """Sister face of every contact face (brute-force closest centroid, other side)."""
+    return _as_problem(prob).sisters
