@@ -224,9 +224,15 @@ def tet_casting(n=128, length=0.1, region="cube", cube=(0.2, 0.8), boxes_seed=6,
     return prob
 
 
-def boundary_triangles(conn):
-    """Faces of a tet mesh that belong to one tetrahedron only, (n, 3) node ids."""
+def plane_triangles(conn, on_plane):
+    """Faces of a tet mesh whose three nodes lie on one of the given planes
+    (on_plane: list of per-node boolean masks) and that belong to one
+    tetrahedron only, (n, 3) node ids."""
     f = np.concatenate([conn[:, [1, 2, 3]], conn[:, [0, 2, 3]], conn[:, [0, 1, 3]], conn[:, [0, 1, 2]]])
+    ok = np.zeros(f.shape[0], dtype=bool)
+    for m in on_plane:
+        ok |= np.all(m[f], axis=1)
+    f = f[ok]
     s = np.sort(f, axis=1)
     _, inv, cnt = np.unique(s, axis=0, return_inverse=True, return_counts=True)
     return f[cnt[inv.ravel()] == 1]
@@ -286,13 +292,11 @@ def tet_casting_nonmatching(n_cast=12, n_mold=8, length=0.1, cube=(0.25, 0.75), 
     xyz = np.concatenate([xm, xc], axis=0)
     conn = np.concatenate([cm, cc + nm], axis=0)
     elem_mat = np.concatenate([np.ones(cm.shape[0], np.int32), np.zeros(cc.shape[0], np.int32)])
-    # contact faces: mould boundary triangles on the cube surface, then every casting boundary triangle
-    bm = boundary_triangles(cm)
-    c3 = xm[bm]
-    tol = 1e-9 * length
-    inside = np.all((c3 >= lo * length - tol) & (c3 <= hi * length + tol), axis=(1, 2))
-    bm = bm[inside]
-    bc = boundary_triangles(cc) + nm
+    # contact faces: mould triangles on the cube's six faces, then the casting's boundary triangles
+    a, b = int(round(lo * n_mold)), int(round(hi * n_mold))
+    in_sq = [np.all((np.delete(g, ax, axis=1) >= a) & (np.delete(g, ax, axis=1) <= b), axis=1) for ax in range(3)]
+    bm = plane_triangles(cm, [(g[:, ax] == v) & in_sq[ax] for ax in range(3) for v in (a, b)])
+    bc = plane_triangles(cc, [gc[:, ax] == v for ax in range(3) for v in (0, n_cast)]) + nm
     faces = np.concatenate([bm, bc], axis=0)
     side = np.concatenate([np.zeros(bm.shape[0], np.int32), np.ones(bc.shape[0], np.int32)])
     N = xyz.shape[0]

@@ -106,7 +106,9 @@ typedef struct {
     double shared_fraction;      /* n_shared / n_nodes */
     double dt_bound;             /* explicit stability bound (s) */
     double setup_seconds;        /* host time of fem_finalize */
-    int64_t reserved[4];
+    double contact_search_seconds;   /* host time of the sister search (fem_set_contact) */
+    int64_t n_contact;           /* contact faces */
+    int64_t reserved[2];
 } fem_prep_report;
 
 typedef struct {
@@ -175,6 +177,21 @@ int fem_set_flux_faces(fem_ctx *ctx, int64_t nf, int32_t nodes_per_face, const i
  * other face - T_i), A the area of face_a. */
 int fem_set_interface(fem_ctx *ctx, int64_t npairs, const int32_t *face_a, const int32_t *face_b,
                       const double *h_i);
+/* Cast/mould contact on non-matching meshes (Eq. 8 with the sister element of
+ * the end of Sec. 3): nf triangles face_nodes[3], each on side 0 or 1 of a
+ * contact surface, with coefficient h.  fem_finalize gives every face a sister:
+ * the face of the other side, in the same scenario, whose centroid
+ * ((x_0 + x_1) + x_2) / 3 is nearest in squared Euclidean distance (FP64; ties
+ * go to the lower face index), found by a uniform-grid search over the
+ * centroids.  Node i of face f then receives h_f (A_f / 3) (mean T of the
+ * sister's nodes - T_i), A_f the area of f itself.  The two sides of a
+ * non-matching surface do not exchange equal and opposite heat, so energy is
+ * not conserved exactly (fem_energy reports the drift).  May be combined with
+ * fem_set_interface.  Errors: FEM_E_MESH if a face has no face of the other
+ * side in its scenario. */
+int fem_set_contact(fem_ctx *ctx, int64_t nf, const int32_t *face_nodes, const int32_t *side, const double *h);
+/* After fem_finalize: the sister of every contact face (nf int32, caller-owned). */
+int fem_get_sisters(const fem_ctx *ctx, int32_t *sister);
 /* Initial temperature of every node (Eq. 2); fixed nodes take their value. */
 int fem_set_initial_T(fem_ctx *ctx, const double *T0);
 /* Batch of independent casting scenarios in one mesh: material_scenario[m]

@@ -297,28 +297,50 @@ static void face_centroid(const orc_problem *p, int64_t f, double c[3])
         c[j] = ((p->xyz[3 * fn[0] + j] + p->xyz[3 * fn[1] + j]) + p->xyz[3 * fn[2] + j]) / 3.0;
 }
 
-int orc_contact_sisters(const orc_problem *p, int32_t *sister)
+/* the sister of face f by a scan over every face of the other side (centroids c) */
+static int64_t sister_of(const orc_problem *p, int64_t f, const double *c)
+{
+    double best = INFINITY;
+    int64_t arg = -1;
+    const double *a = c + 3 * f;
+    for (int64_t g = 0; g < p->n_contact; ++g) {
+        if (p->contact_side[g] == p->contact_side[f]) continue;
+        const double *b = c + 3 * g;
+        double dx = a[0] - b[0], dy = a[1] - b[1], dz = a[2] - b[2];
+        double d2 = (dx * dx + dy * dy) + dz * dz;
+        if (d2 < best) {
+            best = d2;
+            arg = g;
+        }
+    }
+    return arg;
+}
+
+int orc_contact_sisters_of(const orc_problem *p, int64_t n, const int64_t *faces, int32_t *sister)
 {
     int rc = check_faces(p);
     if (rc) return rc;
-    for (int64_t f = 0; f < p->n_contact; ++f) {
-        double a[3], b[3], best = INFINITY;
-        int64_t arg = -1;
-        face_centroid(p, f, a);
-        for (int64_t g = 0; g < p->n_contact; ++g) {
-            if (p->contact_side[g] == p->contact_side[f]) continue;
-            face_centroid(p, g, b);
-            double dx = a[0] - b[0], dy = a[1] - b[1], dz = a[2] - b[2];
-            double d2 = (dx * dx + dy * dy) + dz * dz;
-            if (d2 < best) {
-                best = d2;
-                arg = g;
-            }
-        }
-        if (arg < 0) return ORC_ERR_MESH;   /* no face on the other side */
-        sister[f] = (int32_t)arg;
+    double *c = malloc((size_t)(3 * p->n_contact + 1) * sizeof(double));
+    if (!c) return ORC_ERR_ARG;
+    for (int64_t f = 0; f < p->n_contact; ++f) face_centroid(p, f, c + 3 * f);
+    for (int64_t k = 0; k < n && rc == 0; ++k) {
+        if (faces[k] < 0 || faces[k] >= p->n_contact) { rc = ORC_ERR_ARG; break; }
+        int64_t s = sister_of(p, faces[k], c);
+        if (s < 0) rc = ORC_ERR_MESH;   /* no face on the other side */
+        else sister[k] = (int32_t)s;
     }
-    return 0;
+    free(c);
+    return rc;
+}
+
+int orc_contact_sisters(const orc_problem *p, int32_t *sister)
+{
+    int64_t *all = malloc((size_t)(p->n_contact + 1) * sizeof(int64_t));
+    if (!all) return ORC_ERR_ARG;
+    for (int64_t f = 0; f < p->n_contact; ++f) all[f] = f;
+    int rc = orc_contact_sisters_of(p, p->n_contact, all, sister);
+    free(all);
+    return rc;
 }
 
 /* flux face f: r_i += (A/n)(-q - h (T_i - Tinf)) at each of its n nodes (nodal quadrature) */

@@ -103,6 +103,8 @@ int orc_node_material(const orc_problem *p, int32_t *node_mat);
  * (x0 + x1 + x2) / 3 is nearest in squared Euclidean distance, ties to the lower
  * face index; by brute force over all pairs. */
 int orc_contact_sisters(const orc_problem *p, int32_t *sister);
+/* The same search for the n faces listed in `faces` only (sister[k] for faces[k]). */
+int orc_contact_sisters_of(const orc_problem *p, int64_t n, const int64_t *faces, int32_t *sister);
 /* r = F(T) - K T: element conduction, flux faces, interface pairs and contact
  * faces (node i of face f: h_f (A_f / 3) (mean T of the sister face - T_i)). */
 int orc_residual(const orc_problem *p, const double *T, double *r);

@@ -263,3 +263,18 @@ def run_apparent(prob, dt, n_steps, H=None, diag=False):
 def contact_sisters(prob):
     """Sister face of every contact face (brute-force closest centroid, other side)."""
     return _as_problem(prob).sisters
+
+
+def contact_sisters_of(prob, faces):
+    """Sisters of the listed contact faces only, by the same brute-force search
+    (for meshes whose all-pairs search would take long).  prob: a problem dict."""
+    x = np.ascontiguousarray(prob["xyz"], dtype=np.float64)
+    cf = np.ascontiguousarray(prob["contact_faces"], dtype=np.int32).reshape(-1, 3)
+    side = np.ascontiguousarray(prob["contact_side"], dtype=np.int32)
+    s = _Problem()
+    s.elem_type, s.n_nodes, s.xyz = 4, x.shape[0], _ptr(x)
+    s.n_contact, s.contact_faces, s.contact_side = cf.shape[0], _ptr(cf), _ptr(side)
+    f = np.ascontiguousarray(faces, dtype=np.int64)
+    out = np.zeros(f.size, np.int32)
+    _check(lib().orc_contact_sisters_of(C.byref(s), C.c_int64(f.size), _ptr(f), _ptr(out)), "contact_sisters_of")
+    return out

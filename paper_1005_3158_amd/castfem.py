@@ -37,7 +37,7 @@ EXPORTS = [
     "fem_energy_scenarios", "fem_sur_create", "fem_sur_destroy", "fem_sur_query_buffers", "fem_sur_bind_buffers",
     "fem_sur_n_params", "fem_sur_get_params", "fem_sur_set_params", "fem_sur_features", "fem_sur_loss_grad",
     "fem_sur_train", "fem_sur_predict", "fem_snapshot_H", "fem_advance", "fem_sur_generate", "fem_sur_save",
-    "fem_sur_load",
+    "fem_sur_load", "fem_set_contact", "fem_get_sisters",
 ]
 
 
@@ -64,7 +64,8 @@ class fem_prep_report(C.Structure):
                 ("n_shared", C.c_int64), ("n_partials", C.c_int64), ("max_local_nodes", C.c_int64),
                 ("n_colors", C.c_int64), ("bandwidth_before", C.c_int64), ("bandwidth_after", C.c_int64),
                 ("block_elems", C.c_int64), ("shared_fraction", C.c_double), ("dt_bound", C.c_double),
-                ("setup_seconds", C.c_double), ("reserved", C.c_int64 * 4)]
+                ("setup_seconds", C.c_double), ("contact_search_seconds", C.c_double), ("n_contact", C.c_int64),
+                ("reserved", C.c_int64 * 2)]
 
 
 class fem_buffer_desc(C.Structure):
@@ -133,6 +134,7 @@ def lib():
             "fem_sur_predict": [vp, vp, vp, vp, i64, i64, vp], "fem_snapshot_H": [vp, vp],
             "fem_advance": [vp, vp, vp, i64, i32, dp, dp, dp, vp], "fem_sur_generate": [vp, vp, i64, i32, vp],
             "fem_sur_save": [vp, C.c_char_p], "fem_sur_load": [vp, C.c_char_p],
+            "fem_set_contact": [vp, i64, vp, vp, vp], "fem_get_sisters": [vp, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -204,6 +206,19 @@ def fem_set_interface(ctx, face_a, face_b, h):
     b = np.ascontiguousarray(face_b, np.int32)
     hh = np.ascontiguousarray(h, np.float64)
     _call("fem_set_interface", ctx, hh.size, _p(a), _p(b), _p(hh))
+
+
+def fem_set_contact(ctx, faces, side, h):
+    f = np.ascontiguousarray(faces, np.int32).reshape(-1, 3)
+    sd = np.ascontiguousarray(side, np.int32)
+    hh = np.ascontiguousarray(h, np.float64)
+    _call("fem_set_contact", ctx, hh.size, _p(f), _p(sd), _p(hh))
+
+
+def fem_get_sisters(ctx, n):
+    out = np.empty(n, np.int32)
+    _call("fem_get_sisters", ctx, _p(out))
+    return out
 
 
 def fem_set_initial_T(ctx, T0):
@@ -448,6 +463,8 @@ def setup_problem(ctx, prob):
         fem_set_flux_faces(ctx, prob["flux_faces"], prob["flux_q"], prob["flux_h"], prob["flux_Tinf"])
     if np.size(prob.get("if_h", [])):
         fem_set_interface(ctx, prob["if_a"], prob["if_b"], prob["if_h"])
+    if np.size(prob.get("contact_h", [])):
+        fem_set_contact(ctx, prob["contact_faces"], prob["contact_side"], prob["contact_h"])
     fem_set_initial_T(ctx, prob["T0"])
     if "mat_scenario" in prob:
         fem_set_scenarios(ctx, prob["mat_scenario"])

@@ -380,6 +380,8 @@ void fill_report(const fem_ctx *c, fem_prep_report *rep) {
     rep->shared_fraction = L.N ? (double)rep->n_shared / (double)L.N : 0.0;
     rep->dt_bound = c->base.dt_bound;
     rep->setup_seconds = c->setup_seconds;
+    rep->contact_search_seconds = c->base.sister_seconds;
+    rep->n_contact = (int64_t)c->base.sisters.size();
 }
 
 }  // namespace castfem
@@ -505,6 +507,30 @@ int fem_set_interface(fem_ctx *ctx, int64_t npairs, const int32_t *face_a, const
         p.if_b.assign(face_b, face_b + 3 * npairs);
         p.if_h.assign(h_i, h_i + npairs);
     });
+}
+
+int fem_set_contact(fem_ctx *ctx, int64_t nf, const int32_t *face_nodes, const int32_t *side, const double *h) {
+    if (!ctx) return set_err(FEM_E_INVALID_ARG, "ctx is null");
+    return guarded([&] {
+        if (ctx->stage != ST_NEW) throw PrepError{FEM_E_STATE, "contact faces must be given before fem_finalize"};
+        if (nf < 0 || (nf > 0 && (!face_nodes || !side || !h))) throw PrepError{FEM_E_INVALID_ARG, "bad contact faces"};
+        if (nf >= INT32_MAX / 3) throw PrepError{FEM_E_UNSUPPORTED, "too many contact faces"};
+        for (int64_t f = 0; f < nf; ++f) {
+            if (!std::isfinite(h[f]) || h[f] < 0) throw PrepError{FEM_E_INVALID_ARG, "contact h must be finite, >= 0"};
+            if (side[f] != 0 && side[f] != 1) throw PrepError{FEM_E_INVALID_ARG, "contact side must be 0 or 1"};
+        }
+        Problem &p = ctx->prob;
+        p.contact_faces.assign(face_nodes, face_nodes + 3 * nf);
+        p.contact_side.assign(side, side + nf);
+        p.contact_h.assign(h, h + nf);
+    });
+}
+
+int fem_get_sisters(const fem_ctx *ctx, int32_t *sister) {
+    if (!ctx || !sister) return set_err(FEM_E_INVALID_ARG, "null argument");
+    if (ctx->stage < ST_FINAL) return set_err(FEM_E_STATE, "call fem_finalize first");
+    if (!ctx->base.sisters.empty()) std::memcpy(sister, ctx->base.sisters.data(), ctx->base.sisters.size() * sizeof(int32_t));
+    return FEM_OK;
 }
 
 int fem_set_initial_T(fem_ctx *ctx, const double *T0) {

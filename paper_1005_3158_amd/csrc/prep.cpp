@@ -211,6 +211,27 @@ void prep_base(const Problem &p, Base &b) {
                 t.push_back({fb[c], fa[a], w});
             }
     }
+    // contact faces of non-matching meshes: node i of face f takes w = h A_f / 9
+    // towards each node of f's sister (one direction only: the sister's own
+    // links go to its own sister, so the exchange is not symmetric)
+    const int64_t ncf = (int64_t)p.contact_h.size();
+    if (ncf > 0) {
+        for (int64_t f = 0; f < 3 * ncf; ++f)
+            if (p.contact_faces[f] < 0 || p.contact_faces[f] >= N) fail(FEM_E_MESH, "contact face node out of range");
+        const auto ts0 = std::chrono::steady_clock::now();
+        contact_sisters(p, b.nmat, b.sisters);
+        b.sister_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - ts0).count();
+        tm.mark("sister search");
+        t.reserve(t.size() + ncf * 9);
+        for (int64_t f = 0; f < ncf; ++f) {
+            const int32_t *fa = &p.contact_faces[3 * f], *fs = &p.contact_faces[3 * b.sisters[f]];
+            const double w = p.contact_h[f] * face_area(p.xyz, fa, 3) / 9.0;
+            for (int a = 0; a < 3; ++a)
+                for (int c = 0; c < 3; ++c) t.push_back({fa[a], fs[c], w});
+        }
+    } else {
+        b.sisters.clear();
+    }
     std::sort(t.begin(), t.end(), [](const Trip &x, const Trip &y) { return x.i != y.i ? x.i < y.i : x.j < y.j; });
     b.lptr.assign(N + 1, 0);
     b.lnode.clear();
@@ -294,6 +315,105 @@ void prep_base(const Problem &p, Base &b) {
     }
     b.T_span = std::max(thi - tlo, 1.0);
     tm.mark("stability bound");
+}
+
+// Uniform grid over the face centroids (cell size = the mean longest edge, so a
+// cell holds a few centroids of a surface mesh); cells are found by binary
+// search in the centroids sorted by cell key.  A query visits the rings of cells
+// around its own (Chebyshev distance r = 0, 1, ...) and stops once no unvisited
+// cell can hold a centroid closer than the best so far: every centroid in a cell
+// at ring distance r + 1 or more lies at least r times the cell size away.
+void contact_sisters(const Problem &p, const std::vector<int32_t> &nmat, std::vector<int32_t> &sister) {
+    const int64_t nf = (int64_t)p.contact_h.size();
+    if ((int64_t)p.contact_side.size() != nf || (int64_t)p.contact_faces.size() != 3 * nf)
+        fail(FEM_E_INVALID_ARG, "contact arrays of different lengths");
+    std::vector<double> c(3 * nf);
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY}, edge = 0.0;
+    for (int64_t f = 0; f < nf; ++f) {
+        const int32_t *fn = &p.contact_faces[3 * f];
+        for (int j = 0; j < 3; ++j) {
+            c[3 * f + j] = ((p.xyz[3 * fn[0] + j] + p.xyz[3 * fn[1] + j]) + p.xyz[3 * fn[2] + j]) / 3.0;
+            lo[j] = std::min(lo[j], c[3 * f + j]);
+            hi[j] = std::max(hi[j], c[3 * f + j]);
+        }
+        double e = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            const V3<double> d = sub3(node_x(p.xyz, fn[(a + 1) % 3]), node_x(p.xyz, fn[a]));
+            e = std::max(e, std::sqrt(dot3(d, d)));
+        }
+        edge += e;
+        if (p.contact_side[f] != 0 && p.contact_side[f] != 1) fail(FEM_E_INVALID_ARG, "contact side must be 0 or 1");
+    }
+    double cell = nf ? edge / (double)nf : 1.0;
+    int64_t dim[3];
+    for (;;) {
+        if (!(cell > 0) || !std::isfinite(cell)) cell = 1.0;
+        double cells = 1.0;
+        for (int j = 0; j < 3; ++j) {
+            dim[j] = (int64_t)std::floor((hi[j] - lo[j]) / cell) + 1;
+            cells *= (double)dim[j];
+        }
+        if (cells < 1e15) break;
+        cell *= 2.0;
+    }
+    auto cell_of = [&](const double *x, int j) {
+        return std::min<int64_t>(dim[j] - 1, std::max<int64_t>(0, (int64_t)std::floor((x[j] - lo[j]) / cell)));
+    };
+    auto key_of = [&](int64_t ix, int64_t iy, int64_t iz) { return (uint64_t)((ix * dim[1] + iy) * dim[2] + iz); };
+    // per side: faces sorted by cell key
+    std::vector<std::pair<uint64_t, int32_t>> grid[2];
+    for (int64_t f = 0; f < nf; ++f) {
+        const double *x = &c[3 * f];
+        grid[p.contact_side[f]].push_back({key_of(cell_of(x, 0), cell_of(x, 1), cell_of(x, 2)), (int32_t)f});
+    }
+    for (auto &g : grid) std::sort(g.begin(), g.end());
+    auto scen = [&](int64_t f) { return p.scen_of_mat(nmat[p.contact_faces[3 * f]]); };
+    sister.assign(nf, -1);
+    const int64_t rmax = std::max(dim[0], std::max(dim[1], dim[2]));
+    bool missing = false;
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t f = 0; f < nf; ++f) {
+        const auto &g = grid[1 - p.contact_side[f]];
+        const double *a = &c[3 * f];
+        const int64_t q[3] = {cell_of(a, 0), cell_of(a, 1), cell_of(a, 2)};
+        const int32_t sf = scen(f);
+        double best = INFINITY;
+        int64_t arg = -1;
+        for (int64_t r = 0; r <= rmax; ++r) {
+            for (int64_t ix = q[0] - r; ix <= q[0] + r; ++ix) {
+                if (ix < 0 || ix >= dim[0]) continue;
+                for (int64_t iy = q[1] - r; iy <= q[1] + r; ++iy) {
+                    if (iy < 0 || iy >= dim[1]) continue;
+                    const bool face_xy = ix == q[0] - r || ix == q[0] + r || iy == q[1] - r || iy == q[1] + r;
+                    for (int64_t iz = q[2] - r; iz <= q[2] + r; iz += (face_xy ? 1 : 2 * r > 0 ? 2 * r : 1)) {
+                        if (iz < 0 || iz >= dim[2]) continue;
+                        const uint64_t k = key_of(ix, iy, iz);
+                        auto it = std::lower_bound(g.begin(), g.end(), std::make_pair(k, (int32_t)INT32_MIN));
+                        for (; it != g.end() && it->first == k; ++it) {
+                            const int64_t h = it->second;
+                            if (scen(h) != sf) continue;
+                            const double *b = &c[3 * h];
+                            const double dx = a[0] - b[0], dy = a[1] - b[1], dz = a[2] - b[2];
+                            const double d2 = (dx * dx + dy * dy) + dz * dz;
+                            if (d2 < best || (d2 == best && h < arg)) {
+                                best = d2;
+                                arg = h;
+                            }
+                        }
+                    }
+                }
+            }
+            const double reach = (double)r * cell;
+            if (arg >= 0 && best < reach * reach * (1.0 - 1e-9)) break;
+        }
+        if (arg < 0) {
+#pragma omp atomic write
+            missing = true;
+        } else {
+            sister[f] = (int32_t)arg;
+        }
+    }
+    if (missing) fail(FEM_E_MESH, "a contact face has no face on the other side in its scenario");
 }
 
 int64_t bandwidth(const Problem &p, const Base &b, const std::vector<int32_t> *perm) {

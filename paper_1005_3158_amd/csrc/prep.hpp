@@ -24,6 +24,8 @@ struct Problem {
     std::vector<double> flux_q, flux_h, flux_Tinf;
     std::vector<int32_t> if_a, if_b;
     std::vector<double> if_h;
+    std::vector<int32_t> contact_faces, contact_side;   // non-matching contact: triangles and their side
+    std::vector<double> contact_h;
     std::vector<double> T0;
     int32_t n_scen = 1;
     std::vector<int32_t> mat_scen;    // scenario of every material (empty: all in scenario 0)
@@ -116,6 +118,8 @@ struct Base {
     bool any_robin = false;
     std::vector<double> dt_scen;      // stability bound of every scenario
     std::vector<double> kabs;         // sum_j |K_ij| of the assembled conduction operator per node
+    std::vector<int32_t> sisters;     // per contact face: the closest face of the other side
+    double sister_seconds = 0;        // host time of the sister search
     double elem_abs_max = 0;          // max_i sum_{e at i} sum_j |K^e_ij|  (W/K)
     double T_span = 1;                // span of initial, fixed and ambient temperatures (K)
 };
@@ -131,6 +135,10 @@ void prep_order(const Problem &p, const Base &b, int ordering, Ordering &ord);  
 void prep_layout(const Problem &p, const Base &b, const PrepOptions &o, const Ordering &ord,
                  Layout &L);                                                    // throws PrepError
 int64_t bandwidth(const Problem &p, const Base &b, const std::vector<int32_t> *perm);
+
+// Sister of every contact face: the face of the other side in the same scenario
+// whose centroid is nearest (squared distance in FP64, ties to the lower index).
+void contact_sisters(const Problem &p, const std::vector<int32_t> &nmat, std::vector<int32_t> &sister);  // throws
 
 // orderings (exposed for testing through the C interface report)
 std::vector<int32_t> order_rcm(const Problem &p, const Base &b);

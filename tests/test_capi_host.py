@@ -171,3 +171,42 @@ def test_apparent_mode_options_and_buffers():
     assert bufs["cap_partials"] >= 4 * rep["n_partials"] > 0
     assert bufs["app_mats"] > 0
     assert sizes[cf.FEM_LATENT_ENTHALPY][0]["cap_partials"] == 0
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(n_cast=8, n_mold=4, cube=(0.25, 0.75), jitter=0.0, permute=False),
+                                dict(n_cast=10, n_mold=8, jitter=0.2, jitter_seed=5, perm_seed=6),
+                                dict(n_cast=24, n_mold=12, jitter=0.1)])
+def test_grid_sister_search_equals_the_oracle_brute_force(orc, kw):
+    """The library's grid search and the oracle's all-pairs search pick the same
+    sister for every contact face, ties included (structured faces are
+    equidistant from several faces of the other side)."""
+    p = configs.tet_casting_nonmatching(**kw)
+    ctx = cf.fem_create(cf.make_options(scatter=cf.FEM_SCATTER_GLOBAL_ATOMIC))
+    rep = cf.setup_problem(ctx, p)
+    s = cf.fem_get_sisters(ctx, p["contact_faces"].shape[0])
+    cf.fem_destroy(ctx)
+    assert np.array_equal(s, orc.contact_sisters(p))
+    assert rep["dt_bound"] == pytest.approx(orc.stable_dt(p), rel=1e-12)
+
+
+def test_matched_faces_given_as_contact_find_their_partners():
+    p = configs.tet_casting(n=10)
+    n = p["if_a"].shape[0]
+    ctx = cf.fem_create(cf.make_options(scatter=cf.FEM_SCATTER_GLOBAL_ATOMIC))
+    cf.fem_upload_mesh(ctx, 4, p["xyz"], p["conn"], p["elem_mat"])
+    cf.fem_set_materials(ctx, p["materials"])
+    cf.fem_set_contact(ctx, np.concatenate([p["if_a"], p["if_b"]]), np.repeat([0, 1], n), np.full(2 * n, 1000.0))
+    cf.fem_set_initial_T(ctx, p["T0"])
+    cf.fem_finalize(ctx)
+    s = cf.fem_get_sisters(ctx, 2 * n)
+    cf.fem_destroy(ctx)
+    assert np.array_equal(s, np.concatenate([np.arange(n, 2 * n), np.arange(n)]))
+    with pytest.raises(cf.FemError) as e:
+        ctx = cf.fem_create(None)
+        cf.fem_upload_mesh(ctx, 4, p["xyz"], p["conn"], p["elem_mat"])
+        cf.fem_set_materials(ctx, p["materials"])
+        cf.fem_set_contact(ctx, p["if_a"], np.zeros(n, np.int32), np.full(n, 1000.0))   # one side only
+        cf.fem_set_initial_T(ctx, p["T0"])
+        cf.fem_finalize(ctx)
+    assert e.value.code == -2
+    cf.fem_destroy(ctx)
