@@ -760,6 +760,190 @@ done:
     return rc;
 }
 
+/* ------------------------------- temperature- and time-dependent properties */
+
+double orc_table(const double *tab, double x)
+{
+    int n = (int)tab[0];
+    const double *xs = tab + 1, *ys = tab + 9;
+    if (x <= xs[0]) return ys[0];
+    if (x >= xs[n - 1]) return ys[n - 1];
+    int j = 0;
+    while (!(x < xs[j + 1])) ++j;
+    return ys[j] + (ys[j + 1] - ys[j]) * (x - xs[j]) / (xs[j + 1] - xs[j]);
+}
+
+static int table_ok(const double *tab)
+{
+    if (!tab) return 1;
+    int n = (int)tab[0];
+    if (n < 0 || n > 8 || (double)n != tab[0]) return 0;
+    for (int j = 0; j + 1 < n; ++j)
+        if (!(tab[1 + j] < tab[2 + j])) return 0;
+    return 1;
+}
+
+static int has(const double *tab) { return tab && tab[0] > 0; }
+
+static int check_var(const orc_problem *p, const orc_varprops *v)
+{
+    if (!table_ok(v->h_of_T) || !table_ok(v->h_of_t) || !table_ok(v->dir_of_t)) return ORC_ERR_ARG;
+    if (v->k_of_T)
+        for (int32_t q = 0; q < p->n_mat; ++q)
+            if (!table_ok(v->k_of_T + ORC_TABLE * q)) return ORC_ERR_ARG;
+    return 0;
+}
+
+/* interface coefficient factor of the node pair (i, j) at time t */
+static double h_factor(const orc_varprops *v, double Ti, double Tj, double t)
+{
+    double f = 1.0;
+    if (has(v->h_of_T)) f *= orc_table(v->h_of_T, (Ti + Tj) / 2.0);
+    if (has(v->h_of_t)) f *= orc_table(v->h_of_t, t);
+    return f;
+}
+
+int orc_residual_var(const orc_problem *p, const orc_varprops *v, const double *T, double t, double *r)
+{
+    int nen = p->elem_type;
+    if (nen != 4 && nen != 8) return ORC_ERR_ARG;
+    int rc = check_faces(p);
+    if (rc == 0) rc = check_sisters(p);
+    if (rc == 0) rc = check_var(p, v);
+    if (rc) return rc;
+    for (int64_t i = 0; i < p->n_nodes; ++i) r[i] = 0.0;
+    double Ke[64];
+    for (int64_t e = 0; e < p->n_elems; ++e) {
+        const int32_t *cn = p->conn + e * nen;
+        int32_t mt = p->elem_mat[e];
+        if (mt < 0 || mt >= p->n_mat) return ORC_ERR_MESH;
+        /* K^e is linear in k: build it for k = 1 and scale by k(mean T^n of the element) */
+        double x[24];
+        if ((rc = gather_x(p, e, x))) return rc;
+        rc = nen == 4 ? orc_tet_ke(x, 1.0, Ke, NULL) : orc_hex_ke(x, 1.0, Ke, NULL);
+        if (rc) return rc;
+        double k = p->materials[6 * mt + 0];
+        if (v->k_of_T && has(v->k_of_T + ORC_TABLE * mt)) {
+            double Tm = 0.0;
+            for (int a = 0; a < nen; ++a) Tm += T[cn[a]];
+            k = orc_table(v->k_of_T + ORC_TABLE * mt, Tm / nen);
+        }
+        for (int a = 0; a < nen; ++a) {
+            double s = 0.0;
+            for (int b = 0; b < nen; ++b) s += Ke[nen * a + b] * T[cn[b]];
+            r[cn[a]] -= k * s;
+        }
+    }
+    for (int64_t f = 0; f < p->n_flux; ++f) add_flux_face(p, f, T, r);
+    /* interface pairs and contact faces, node pair by node pair: node i of a face
+     * and node j of the face it sees exchange h f_ij (A/9)(T_j - T_i) */
+    for (int64_t f = 0; f < p->n_if; ++f) {
+        const int32_t *fa = p->if_a + 3 * f, *fb = p->if_b + 3 * f;
+        double A = face_area(p->xyz, fa, 3);
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                int32_t i = fa[a], j = fb[b];
+                double w = p->if_h[f] * (A / 9.0) * h_factor(v, T[i], T[j], t);
+                r[i] += w * (T[j] - T[i]);
+                r[j] += w * (T[i] - T[j]);
+            }
+    }
+    for (int64_t f = 0; f < p->n_contact; ++f) {
+        const int32_t *fa = p->contact_faces + 3 * f, *fs = p->contact_faces + 3 * p->contact_sister[f];
+        double A = face_area(p->xyz, fa, 3);
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                int32_t i = fa[a], j = fs[b];
+                r[i] += p->contact_h[f] * (A / 9.0) * h_factor(v, T[i], T[j], t) * (T[j] - T[i]);
+            }
+    }
+    return 0;
+}
+
+/* the largest value a table (or its constant) takes */
+static double table_max(const double *tab, double constant)
+{
+    if (!has(tab)) return constant;
+    double m = tab[9];
+    for (int j = 1; j < (int)tab[0]; ++j) m = fmax(m, tab[9 + j]);
+    return m;
+}
+
+/* Gershgorin bound with every property at its largest value: the conduction part
+ * of a material scaled by max k / k, the interface parts by the largest factors */
+int orc_stable_dt_var(const orc_problem *p, const orc_varprops *v, double *dt_bound)
+{
+    int rc = check_var(p, v);
+    if (rc) return rc;
+    int32_t nm = p->n_mat;
+    double *mats = malloc((size_t)(6 * nm + 1) * sizeof(double));
+    double *ifh = malloc((size_t)(p->n_if + 1) * sizeof(double));
+    double *ch = malloc((size_t)(p->n_contact + 1) * sizeof(double));
+    if (!mats || !ifh || !ch) { free(mats); free(ifh); free(ch); return ORC_ERR_ARG; }
+    for (int32_t q = 0; q < nm; ++q) {
+        for (int j = 0; j < 6; ++j) mats[6 * q + j] = p->materials[6 * q + j];
+        if (v->k_of_T) mats[6 * q] = table_max(v->k_of_T + ORC_TABLE * q, mats[6 * q]);
+    }
+    double hf = table_max(v->h_of_T, 1.0) * table_max(v->h_of_t, 1.0);
+    for (int64_t f = 0; f < p->n_if; ++f) ifh[f] = p->if_h[f] * hf;
+    for (int64_t f = 0; f < p->n_contact; ++f) ch[f] = p->contact_h[f] * hf;
+    orc_problem q = *p;
+    q.materials = mats;
+    q.if_h = ifh;
+    q.contact_h = ch;
+    rc = orc_stable_dt(&q, dt_bound);
+    free(mats); free(ifh); free(ch);
+    return rc;
+}
+
+int orc_run_var(const orc_problem *p, const orc_varprops *v, double t0, double dt, int64_t n_steps, double *H,
+                double *diag)
+{
+    int64_t N = p->n_nodes;
+    double *m = malloc(N * sizeof(double));
+    double *T = malloc(N * sizeof(double));
+    double *r = malloc(N * sizeof(double));
+    int32_t *nmat = malloc(N * sizeof(int32_t));
+    int rc = check_var(p, v);
+    if (!m || !T || !r || !nmat) rc = ORC_ERR_ARG;
+    if (rc) goto done;
+    if ((rc = orc_lumped_mass(p, m))) goto done;
+    if ((rc = orc_node_material(p, nmat))) goto done;
+    double Eref = 0.0, E0 = NAN, Qcum = 0.0;
+    for (int64_t i = 0; i < N; ++i)
+        if (nmat[i] >= 0) Eref += m[i] * orc_H_of_T(p->materials + 6 * nmat[i], 25.0);
+    for (int64_t n = 0; n <= n_steps; ++n) {
+        double t = t0 + (double)n * dt;
+        state_T_nm(p, nmat, H, T, NULL);
+        if ((rc = orc_residual_var(p, v, T, t, r))) goto done;
+        double Q = boundary_inflow(p, T, r);
+        if (diag) {
+            fill_diag(p, nmat, m, H, T, Q, Qcum, E0, Eref, diag + n * ORC_NDIAG);
+            if (n == 0) E0 = diag[ORC_D_E];
+        }
+        if (n == n_steps) break;
+        /* free nodes: H += dt r / m; fixed nodes: H(T_D + shift(t + dt)), whose
+         * change the boundary supplies */
+        unsigned char *fixed = dirichlet_mask(p);
+        if (!fixed) { rc = ORC_ERR_ARG; goto done; }
+        for (int64_t i = 0; i < N; ++i)
+            if (!fixed[i] && nmat[i] >= 0) H[i] = H[i] + dt * r[i] / m[i];
+        free(fixed);
+        double shift = has(v->dir_of_t) ? orc_table(v->dir_of_t, t + dt) : 0.0;
+        for (int64_t d = 0; d < p->n_dir; ++d) {
+            int32_t i = p->dir_nodes[d];
+            if (nmat[i] < 0) continue;
+            double Hn = orc_H_of_T(p->materials + 6 * nmat[i], p->dir_T[d] + shift);
+            Qcum += m[i] * (Hn - H[i]);
+            H[i] = Hn;
+        }
+        Qcum += dt * Q;
+    }
+done:
+    free(m); free(T); free(r); free(nmat);
+    return rc;
+}
+
 /* ----------------------------------------------- partitioned algorithm */
 
 int orc_run_partitioned(const orc_problem *p, int32_t n_parts, const int32_t *elem_part,

@@ -134,6 +134,37 @@ int orc_lemmon_capacity(const double x[12], const double mat[6], const double T[
 int orc_apparent_capacity(const orc_problem *p, const double *H, double *C);
 int orc_run_apparent(const orc_problem *p, double dt, int64_t n_steps, double *H, double *diag);
 
+/* Temperature- and time-dependent properties (Sec. 2 after Eq. 1, Eq. 3 with
+ * f(x, t), Eq. 8 with h_i(t, T)).  A table is ORC_TABLE doubles {n, x_0..x_7,
+ * y_0..y_7}: n points with increasing x, linear in between and constant beyond
+ * the ends; n = 0 leaves the quantity constant.
+ *   k_of_T:   n_mat tables, the conductivity of each material against T; an
+ *             element takes k at the mean of its nodal T^n (K re-weighted per
+ *             element per step);
+ *   h_of_T:   factor on every interface coefficient (matched pairs and contact
+ *             faces) against T: each node-to-node coupling i-j of a face uses the
+ *             factor at (T_i + T_j) / 2;
+ *   h_of_t:   factor on every interface coefficient against time;
+ *   dir_of_t: shift added to every fixed temperature against time:
+ *             T_i(t) = T_D,i + shift(t).
+ * orc_residual_var: r = F - K T at time t with these properties.
+ * orc_run_var: n explicit steps from time t0 (the state H must hold the fixed
+ *   temperatures of t0); the prescribed change of a fixed node's enthalpy counts
+ *   as boundary inflow in the diagnostics. */
+enum { ORC_TABLE = 17 };
+typedef struct {
+    const double *k_of_T;     /* n_mat x ORC_TABLE, or NULL */
+    const double *h_of_T;     /* ORC_TABLE, or NULL */
+    const double *h_of_t;     /* ORC_TABLE, or NULL */
+    const double *dir_of_t;   /* ORC_TABLE, or NULL */
+} orc_varprops;
+
+double orc_table(const double *tab, double x);
+int orc_residual_var(const orc_problem *p, const orc_varprops *v, const double *T, double t, double *r);
+int orc_stable_dt_var(const orc_problem *p, const orc_varprops *v, double *dt_bound);
+int orc_run_var(const orc_problem *p, const orc_varprops *v, double t0, double dt, int64_t n_steps, double *H,
+                double *diag);
+
 #ifdef __cplusplus
 }
 #endif

@@ -278,3 +278,82 @@ def contact_sisters_of(prob, faces):
     out = np.zeros(f.size, np.int32)
     _check(lib().orc_contact_sisters_of(C.byref(s), C.c_int64(f.size), _ptr(f), _ptr(out)), "contact_sisters_of")
     return out
+
+
+# ------------------------------------------- temperature- and time-dependent properties
+ORC_TABLE = 17
+
+
+class _VarProps(C.Structure):
+    _fields_ = [("k_of_T", C.c_void_p), ("h_of_T", C.c_void_p), ("h_of_t", C.c_void_p), ("dir_of_t", C.c_void_p)]
+
+
+def table(points):
+    """[(x, y), ...] (at most 8, increasing x) -> the oracle's 17-double table; None -> n = 0."""
+    t = np.zeros(ORC_TABLE)
+    if points is not None and len(points):
+        pts = np.asarray(points, dtype=np.float64).reshape(-1, 2)
+        t[0] = pts.shape[0]
+        t[1:1 + pts.shape[0]] = pts[:, 0]
+        t[9:9 + pts.shape[0]] = pts[:, 1]
+    return t
+
+
+class VarProps:
+    """k_of_T: per material a point list or None; h_of_T, h_of_t, dir_of_t: point lists or None."""
+
+    def __init__(self, n_mat, k_of_T=None, h_of_T=None, h_of_t=None, dir_of_t=None):
+        self.k = np.concatenate([table(k_of_T[q] if k_of_T else None) for q in range(n_mat)])
+        self.hT, self.ht, self.dt = table(h_of_T), table(h_of_t), table(dir_of_t)
+        self.s = _VarProps(_ptr(self.k), _ptr(self.hT), _ptr(self.ht), _ptr(self.dt))
+
+    @property
+    def ref(self):
+        return C.byref(self.s)
+
+
+def table_value(points, x):
+    lib().orc_table.restype = C.c_double
+    t = table(points)
+    return lib().orc_table(_ptr(t), C.c_double(x))
+
+
+def residual_var(prob, props, T, t):
+    P = _as_problem(prob)
+    T = np.ascontiguousarray(T, dtype=np.float64)
+    r = np.zeros(P.n_nodes)
+    _check(lib().orc_residual_var(P.ref, props.ref, _ptr(T), C.c_double(t), _ptr(r)), "residual_var")
+    return r
+
+
+def stable_dt_var(prob, props):
+    P = _as_problem(prob)
+    dt = C.c_double()
+    _check(lib().orc_stable_dt_var(P.ref, props.ref, C.byref(dt)), "stable_dt_var")
+    return dt.value
+
+
+def initial_H_var(prob, props, t0=0.0):
+    """Initial enthalpy with every fixed node at T_D + shift(t0)."""
+    P = _as_problem(prob)
+    H = initial_H(P)
+    if P.keep["dir_nodes"].size and props.dt[0] > 0:
+        lib().orc_table.restype = C.c_double
+        shift = lib().orc_table(_ptr(props.dt), C.c_double(t0))
+        nm = node_material(P)
+        mats = P.keep["materials"]
+        for i, TD in zip(P.keep["dir_nodes"], P.keep["dir_T"]):
+            H[i] = H_of_T(mats[nm[i]], TD + shift)[0]
+    return H
+
+
+def run_var(prob, props, dt, n_steps, H=None, t0=0.0, diag=False):
+    """n explicit steps with temperature- and time-dependent properties from time t0.
+    Returns (H, T, fs[, diag]) as run()."""
+    P = _as_problem(prob)
+    H = initial_H_var(P, props, t0) if H is None else np.array(H, dtype=np.float64)
+    D = np.zeros((n_steps + 1, ORC_NDIAG)) if diag else None
+    _check(lib().orc_run_var(P.ref, props.ref, C.c_double(t0), C.c_double(dt), C.c_int64(n_steps), _ptr(H),
+                             _ptr(D) if diag else None), "run_var")
+    T, fs = state_T(P, H)
+    return (H, T, fs, D) if diag else (H, T, fs)
