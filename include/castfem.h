@@ -73,6 +73,13 @@ enum { FEM_LATENT_ENTHALPY = 0, FEM_LATENT_APPARENT = 1 };
 
 typedef struct fem_ctx fem_ctx;
 
+/* A piecewise-linear table: n points (at most 8) with increasing x, linear
+ * between them and constant beyond the ends; n = 0 means "not given". */
+typedef struct {
+    int32_t n, pad;
+    double x[8], y[8];
+} fem_table;
+
 typedef struct {
     int32_t device;          /* HIP device ordinal */
     int32_t precision;       /* FEM_PREC_* */
@@ -192,6 +199,24 @@ int fem_set_interface(fem_ctx *ctx, int64_t npairs, const int32_t *face_a, const
 int fem_set_contact(fem_ctx *ctx, int64_t nf, const int32_t *face_nodes, const int32_t *side, const double *h);
 /* After fem_finalize: the sister of every contact face (nf int32, caller-owned). */
 int fem_get_sisters(const fem_ctx *ctx, int32_t *sister);
+/* Temperature- and time-dependent properties (Sec. 2 after Eq. 1; Eq. 3 with
+ * f(x, t); Eq. 8 and the remark after it), any of them NULL or n = 0 for none:
+ *   k_of_T[n_mat]: conductivity of each material against T (W/mK); each element
+ *     takes k at the mean of its nodal T^n, so K is re-weighted per element and
+ *     step;
+ *   h_of_T: factor on every interface coefficient (fem_set_interface and
+ *     fem_set_contact) against temperature; the coupling of node i to node j of
+ *     the face it sees uses the factor at (T_i + T_j) / 2;
+ *   h_of_t: factor on every interface coefficient against time t (s);
+ *   dir_of_t: shift added to every fixed temperature: T_i(t) = T_D,i + shift(t);
+ *     the prescribed change of a fixed node's enthalpy counts as boundary inflow.
+ * Time starts at 0 at fem_bind_buffers and advances by dt per step on the
+ * device.  The stability bound takes every property at its largest value.
+ * Supported with one scenario, the enthalpy form and the LDS-blocked scatter;
+ * the surrogate and fem_write_state refuse such a context (FEM_E_UNSUPPORTED).
+ * Call before fem_finalize. */
+int fem_set_variable_properties(fem_ctx *ctx, int32_t n_mat, const fem_table *k_of_T, const fem_table *h_of_T,
+                                const fem_table *h_of_t, const fem_table *dir_of_t);
 /* Initial temperature of every node (Eq. 2); fixed nodes take their value. */
 int fem_set_initial_T(fem_ctx *ctx, const double *T0);
 /* Batch of independent casting scenarios in one mesh: material_scenario[m]

@@ -15,7 +15,8 @@ DEVICE = ["-x", "hip", "--offload-arch=" + ARCH, "-munsafe-fp-atomics",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 HOST = ["-x", "hip", "--offload-arch=" + ARCH, "--offload-host-only", "-fopenmp"]
 
-SOURCES = [("kernels.hip", DEVICE), ("apparent.hip", DEVICE), ("surrogate.hip", DEVICE), ("capi.cpp", HOST),
+SOURCES = [("kernels.hip", DEVICE), ("apparent.hip", DEVICE), ("varprops.hip", DEVICE), ("surrogate.hip", DEVICE),
+           ("capi.cpp", HOST),
            ("prep.cpp", HOST),
            ("surrogate.cpp", HOST)]
 

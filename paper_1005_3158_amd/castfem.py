@@ -37,7 +37,7 @@ EXPORTS = [
     "fem_energy_scenarios", "fem_sur_create", "fem_sur_destroy", "fem_sur_query_buffers", "fem_sur_bind_buffers",
     "fem_sur_n_params", "fem_sur_get_params", "fem_sur_set_params", "fem_sur_features", "fem_sur_loss_grad",
     "fem_sur_train", "fem_sur_predict", "fem_snapshot_H", "fem_advance", "fem_sur_generate", "fem_sur_save",
-    "fem_sur_load", "fem_set_contact", "fem_get_sisters",
+    "fem_sur_load", "fem_set_contact", "fem_get_sisters", "fem_set_variable_properties",
 ]
 
 
@@ -45,6 +45,20 @@ class FemError(RuntimeError):
     def __init__(self, code, fn, msg):
         super().__init__("%s failed: %s (%s)" % (fn, msg, ERRORS.get(code, code)))
         self.code = code
+
+
+class fem_table(C.Structure):
+    _fields_ = [("n", C.c_int32), ("pad", C.c_int32), ("x", C.c_double * 8), ("y", C.c_double * 8)]
+
+
+def make_table(points):
+    """[(x, y), ...] with increasing x (at most 8) -> fem_table; None -> n = 0."""
+    t = fem_table()
+    if points is not None:
+        for j, (x, y) in enumerate(points):
+            t.x[j], t.y[j] = x, y
+        t.n = len(points)
+    return t
 
 
 class fem_options(C.Structure):
@@ -135,6 +149,7 @@ def lib():
             "fem_advance": [vp, vp, vp, i64, i32, dp, dp, dp, vp], "fem_sur_generate": [vp, vp, i64, i32, vp],
             "fem_sur_save": [vp, C.c_char_p], "fem_sur_load": [vp, C.c_char_p],
             "fem_set_contact": [vp, i64, vp, vp, vp], "fem_get_sisters": [vp, vp],
+            "fem_set_variable_properties": [vp, i32, vp, vp, vp, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -213,6 +228,14 @@ def fem_set_contact(ctx, faces, side, h):
     sd = np.ascontiguousarray(side, np.int32)
     hh = np.ascontiguousarray(h, np.float64)
     _call("fem_set_contact", ctx, hh.size, _p(f), _p(sd), _p(hh))
+
+
+def fem_set_variable_properties(ctx, n_mat, k_of_T=None, h_of_T=None, h_of_t=None, dir_of_t=None):
+    """k_of_T: per material a point list or None; the others: point lists or None."""
+    ks = (fem_table * n_mat)(*[make_table(k_of_T[q] if k_of_T else None) for q in range(n_mat)])
+    tabs = [make_table(t) for t in (h_of_T, h_of_t, dir_of_t)]
+    _call("fem_set_variable_properties", ctx, int(n_mat), C.cast(ks, C.c_void_p),
+          *[C.cast(C.byref(t), C.c_void_p) for t in tabs])
 
 
 def fem_get_sisters(ctx, n):
@@ -465,6 +488,8 @@ def setup_problem(ctx, prob):
         fem_set_interface(ctx, prob["if_a"], prob["if_b"], prob["if_h"])
     if np.size(prob.get("contact_h", [])):
         fem_set_contact(ctx, prob["contact_faces"], prob["contact_side"], prob["contact_h"])
+    if prob.get("varprops"):
+        fem_set_variable_properties(ctx, len(prob["materials"]), **prob["varprops"])
     fem_set_initial_T(ctx, prob["T0"])
     if "mat_scenario" in prob:
         fem_set_scenarios(ctx, prob["mat_scenario"])

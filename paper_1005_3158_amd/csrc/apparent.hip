@@ -13,88 +13,26 @@
 // The update T += dt r / C (Eq. 14 with the re-assembled C of Eq. 6) runs in
 // FP64 from T(H) of the stored state, and the state stores H(T_new).
 //
-// The small helpers below (workgroup-to-XCD mapping, fixed-point rounding,
-// enthalpy relation, boundary terms) are the constructions of the enthalpy
-// kernels, repeated here so that those kernels stay byte-for-byte as profiled.
 #include "apparent.hpp"
 
 #include <cfloat>
 #include <type_traits>
 
 #include "elem.hpp"
+#include "step_common.hpp"
 
 namespace castfem {
 namespace {
 
-template <class R> struct VT;
-template <> struct VT<float> { using V4 = float4; using V2 = float2; };
-template <> struct VT<double> { using V4 = double4; using V2 = double2; };
-
-// contiguous ranges of logical blocks per XCD (workgroups are dispatched
-// round-robin over the 8 XCDs), so that neighbouring blocks share an L2
-__device__ __forceinline__ int xcd_remap(int w, int n) {
-    const int x = w & 7, i = w >> 3;
-    const int q = n >> 3, rem = n & 7;
-    return x * q + min(x, rem) + i;
-}
-
-// round(r * scale) as a two's-complement integer via the 1.5 * 2^52 shift
-__device__ __forceinline__ long long fx_from(float r, double scale) {
-    const double magic = 6755399441055744.0;
-    const double x = __builtin_fma((double)r, scale, magic);
-    return __double_as_longlong(x) - __double_as_longlong(magic);
-}
-__device__ __forceinline__ float fx_to(long long q, double inv_scale) { return (float)((double)q * inv_scale); }
-
-// enthalpy relation (Eq. 11, linear latent release) and its inverse
-__device__ __forceinline__ void t_of_h(const MatDev &M, double H, double &T, double &fs) {
-    if (!M.latent || H <= M.Hs) {
-        T = H * M.inv_c;
-        fs = 1.0;
-    } else if (H >= M.Hl) {
-        T = (H - M.L) * M.inv_c;
-        fs = 0.0;
-    } else {
-        T = M.Ts + (H - M.Hs) * M.slope;
-        fs = 1.0 - (H - M.Hs) * M.inv_dH;
-    }
-}
-__device__ __forceinline__ double h_of_t(const MatDev &M, double T) {
-    double g = 0.0;
-    if (M.latent && T > M.Ts) g = T >= M.Tl ? 1.0 : (T - M.Ts) / (M.Tl - M.Ts);
-    return M.c * T + M.L * g;
-}
-
-// Robin and interface terms of boundary slot s: adds them to r, returns the Robin inflow
-template <class R>
-__device__ __forceinline__ double boundary_terms(const Dev &d, int64_t s, R Ti, const R *Tc, R &r) {
-    using V2 = typename VT<R>::V2;
-    double q = 0.0;
-    if (d.robin) {
-        const V2 ab = ((const V2 *)d.robin)[s];
-        const R f = ab.x - ab.y * Ti;
-        r += f;
-        q = (double)f;
-    }
-    const int32_t l0 = d.link_ptr[s], l1 = d.link_ptr[s + 1];
-    const R *w = (const R *)d.link_w;
-    for (int32_t k = l0; k < l1; ++k) r += w[k] * (Tc[d.link_node[k]] - Ti);
-    return q;
-}
-
-// material tables of at most LDS_MATS rows are read from LDS, larger ones from
-// global memory; the kernels are instantiated for each case so that every
-// table access compiles to LDS or global loads (a pointer that may be either
-// would compile to the slower flat loads)
-constexpr int LDS_MATS = 8;
-
-// copy a small table into LDS (visible after the caller's next barrier)
-template <class M>
-__device__ __forceinline__ void stage_table(const M *src, int n, M *dst) {
-    static_assert(sizeof(M) % 4 == 0, "table rows are whole words");
-    const int words = n * (int)(sizeof(M) / 4);
-    for (int w = threadIdx.x; w < words; w += blockDim.x) ((uint32_t *)dst)[w] = ((const uint32_t *)src)[w];
-}
+using step::boundary_terms;
+using step::fx_from;
+using step::fx_to;
+using step::h_of_t;
+using step::LDS_MATS;
+using step::stage_table;
+using step::t_of_h;
+using step::VT;
+using step::xcd_remap;
 
 // the constants one element needs, in the working precision (held in registers)
 template <class R>

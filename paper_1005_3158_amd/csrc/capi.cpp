@@ -47,6 +47,12 @@ void layout_sizes(const fem_ctx *c, const Layout &L, int64_t *sz) {
             sz[B_CAP_PARTIALS] = np * R;
             sz[B_APP_MATS] = (int64_t)c->prob.mats.size() * (int64_t)sizeof(AppMat);
         }
+        if (c->variable()) {
+            sz[B_VAR_TABS_F] = (int64_t)c->vtabs.size() * (int64_t)sizeof(Tab<float>);
+            sz[B_VAR_TABS_D] = (int64_t)c->vtabs.size() * (int64_t)sizeof(Tab<double>);
+            sz[B_T_FIXED] = N * 8;
+            sz[B_TIME] = 16;
+        }
     }
     sz[B_ROBIN] = (int64_t)L.robin_a.size() * 2 * R;
     sz[B_LINK_PTR] = (L.n_bc_slots + 1) * 4;
@@ -87,12 +93,14 @@ void upload_layout_t(fem_ctx *c, const Layout &L) {
         v.z = (R)L.xyz[3 * n + 2];
         // conductivity of the node's material; the apparent-capacity kernel
         // takes the material index instead
-        v.w = c->apparent() ? (R)(f & NODE_MAT_MASK) : (R)c->prob.mats[f & NODE_MAT_MASK].k;
+        v.w = c->mat_in_node_x() ? (R)(f & NODE_MAT_MASK) : (R)c->prob.mats[f & NODE_MAT_MASK].k;
         nx[n] = v;
         im[n] = (R)(1.0 / L.m[n]);
         const fem_material &mat = c->prob.mats[f & NODE_MAT_MASK];
         const MatDev &M = c->mats_host[f & NODE_MAT_MASK];
-        const double h0 = h_of_t(mat, L.T_init[n]);
+        // a fixed node starts at T_D + shift(0)
+        const double T_start = (f & NODE_FIXED) ? L.T_init[n] + c->dir_shift(0.0) : L.T_init[n];
+        const double h0 = h_of_t(mat, T_start);
         double hd;
         if (sizeof(R) == 4) {
             float hi = (float)h0;
@@ -106,7 +114,7 @@ void upload_layout_t(fem_ctx *c, const Layout &L) {
         }
         double T, f_s;
         t_of_h(M, hd, T, f_s);
-        if (f & NODE_FIXED) T = L.T_init[n];
+        if (f & NODE_FIXED) T = T_start;
         T2[n] = T2[N + n] = (R)T;
         fs[n] = (R)f_s;
         const double m = 1.0 / (double)im[n];
@@ -139,7 +147,7 @@ void upload_layout_t(fem_ctx *c, const Layout &L) {
     h2d(c, B_LINK_W, lw.data(), (int64_t)lw.size() * (int64_t)sizeof(R));
     if (c->opt.scatter == FEM_SCATTER_LDS_BLOCKED) {
         h2d(c, B_LCONN, L.lconn.data(), (int64_t)L.lconn.size() * 2);
-        if (c->apparent()) {
+        if (c->mat_in_node_x()) {
             // the apparent-capacity kernels read the material of a block whose
             // nodes all share one once per block (pad0; -1 for mixed blocks)
             blocks_app = L.blocks;
@@ -187,6 +195,26 @@ void upload_layout_t(fem_ctx *c, const Layout &L) {
             am.push_back(a);
         }
         h2d(c, B_APP_MATS, am.data(), (int64_t)(am.size() * sizeof(AppMat)));
+    }
+    std::vector<Tab<float>> tf;
+    std::vector<double> tfix, t0(2, 0.0);
+    if (c->variable()) {
+        for (const Tab<double> &t : c->vtabs) {
+            Tab<float> u{};
+            u.n = t.n;
+            for (int j = 0; j < TAB_POINTS; ++j) {
+                u.x[j] = (float)t.x[j];
+                u.y[j] = (float)t.y[j];
+            }
+            tf.push_back(u);
+        }
+        h2d(c, B_VAR_TABS_F, tf.data(), (int64_t)(tf.size() * sizeof(Tab<float>)));
+        h2d(c, B_VAR_TABS_D, c->vtabs.data(), (int64_t)(c->vtabs.size() * sizeof(Tab<double>)));
+        tfix.assign(N, 0.0);
+        for (int64_t n = 0; n < N; ++n)
+            if (L.nflag[n] & NODE_FIXED) tfix[n] = L.T_init[n];
+        h2d(c, B_T_FIXED, tfix.data(), N * 8);
+        h2d(c, B_TIME, t0.data(), 16);
     }
     int64_t sz[B_COUNT];
     layout_sizes(c, L, sz);
@@ -264,10 +292,21 @@ void fill_dev(fem_ctx *c, const Candidate &cd) {
         a.cx_limit = (float)std::ldexp(1.0, 50 - S);
         c->app = a;
     }
+    if (c->variable()) {
+        VarDev v;
+        v.d = d;
+        v.tabs_f = (const Tab<float> *)c->ptr[B_VAR_TABS_F];
+        v.tabs_d = (const Tab<double> *)c->ptr[B_VAR_TABS_D];
+        v.T_fixed = (const double *)c->ptr[B_T_FIXED];
+        v.time = (double *)c->ptr[B_TIME];
+        c->vdev = v;
+    }
 }
 
 hipError_t enqueue_ctx_step(const fem_ctx *c, int parity, hipStream_t s, hipEvent_t *ev) {
-    return c->apparent() ? enqueue_step_apparent(c->app, parity, s, ev) : enqueue_step(c->dev, parity, s, ev);
+    if (c->apparent()) return enqueue_step_apparent(c->app, parity, s, ev);
+    if (c->variable()) return enqueue_step_var(c->vdev, parity, s, ev);
+    return enqueue_step(c->dev, parity, s, ev);
 }
 
 // Bound on the lumped apparent capacitance of any node: an element's Lemmon
@@ -309,6 +348,16 @@ double apparent_cap_bound(const Problem &p) {
     for (double v : acc) mx = std::max(mx, v);
     return mx;
 }
+
+}  // namespace castfem
+
+double fem_ctx::dir_shift(double t) const {
+    if (!variable()) return 0.0;
+    const Tab<double> &sh = vtabs[prob.mats.size() + TAB_DIR_OF_TIME];
+    return sh.n ? tab_eval_host(sh, t) : 0.0;
+}
+
+namespace castfem {
 
 void reset_graph(fem_ctx *c) {
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
@@ -533,6 +582,41 @@ int fem_get_sisters(const fem_ctx *ctx, int32_t *sister) {
     return FEM_OK;
 }
 
+int fem_set_variable_properties(fem_ctx *ctx, int32_t n_mat, const fem_table *k_of_T, const fem_table *h_of_T,
+                                const fem_table *h_of_t, const fem_table *dir_of_t) {
+    if (!ctx) return set_err(FEM_E_INVALID_ARG, "ctx is null");
+    return guarded([&] {
+        if (ctx->stage != ST_NEW) throw PrepError{FEM_E_STATE, "properties must be given before fem_finalize"};
+        if (n_mat != (int32_t)ctx->prob.mats.size()) throw PrepError{FEM_E_INVALID_ARG, "n_mat must match the material table"};
+        std::vector<Tab<double>> t(n_mat + TAB_GLOBAL);
+        auto take = [&](const fem_table *src, Tab<double> &dst) {
+            dst = Tab<double>{};
+            if (!src || src->n == 0) return;
+            if (src->n < 0 || src->n > TAB_POINTS) throw PrepError{FEM_E_INVALID_ARG, "a table holds 1 to 8 points"};
+            for (int j = 0; j < src->n; ++j) {
+                if (!std::isfinite(src->x[j]) || !std::isfinite(src->y[j]))
+                    throw PrepError{FEM_E_INVALID_ARG, "table values must be finite"};
+                if (j > 0 && !(src->x[j] > src->x[j - 1])) throw PrepError{FEM_E_INVALID_ARG, "table x must increase"};
+                dst.x[j] = src->x[j];
+                dst.y[j] = src->y[j];
+            }
+            dst.n = src->n;
+        };
+        for (int32_t q = 0; q < n_mat; ++q) {
+            take(k_of_T ? &k_of_T[q] : nullptr, t[q]);
+            for (int j = 0; j < t[q].n; ++j)
+                if (!(t[q].y[j] > 0)) throw PrepError{FEM_E_INVALID_ARG, "conductivities must be positive"};
+        }
+        take(h_of_T, t[n_mat + TAB_H_OF_T]);
+        take(h_of_t, t[n_mat + TAB_H_OF_TIME]);
+        take(dir_of_t, t[n_mat + TAB_DIR_OF_TIME]);
+        for (int g : {TAB_H_OF_T, TAB_H_OF_TIME})
+            for (int j = 0; j < t[n_mat + g].n; ++j)
+                if (t[n_mat + g].y[j] < 0) throw PrepError{FEM_E_INVALID_ARG, "interface factors must be >= 0"};
+        ctx->vtabs = std::move(t);
+    });
+}
+
 int fem_set_initial_T(fem_ctx *ctx, const double *T0) {
     if (!ctx) return set_err(FEM_E_INVALID_ARG, "ctx is null");
     return guarded([&] {
@@ -557,8 +641,37 @@ int fem_finalize(fem_ctx *ctx, fem_prep_report *rep) {
                 if (m.L > 0 && !(m.T_liq > m.T_sol))
                     throw PrepError{FEM_E_UNSUPPORTED, "apparent capacity needs T_liq > T_sol where L > 0"};
         }
+        if (ctx->variable()) {
+            if (ctx->prob.n_scen != 1) throw PrepError{FEM_E_UNSUPPORTED, "variable properties: one scenario only"};
+            if (ctx->opt.scatter != FEM_SCATTER_LDS_BLOCKED)
+                throw PrepError{FEM_E_UNSUPPORTED, "variable properties: LDS-blocked scatter only"};
+            if (ctx->apparent()) throw PrepError{FEM_E_UNSUPPORTED, "variable properties: enthalpy form only"};
+            if ((int32_t)ctx->vtabs.size() != (int32_t)ctx->prob.mats.size() + TAB_GLOBAL)
+                throw PrepError{FEM_E_INVALID_ARG, "variable properties: material count changed"};
+        }
         Base base;
         prep_base(ctx->prob, base);
+        if (ctx->variable()) {
+            // stability bound and fixed-point range with every property at its largest value
+            Problem pmax = ctx->prob;
+            double hmax = 1.0;
+            for (int g : {TAB_H_OF_T, TAB_H_OF_TIME}) hmax *= tab_max(ctx->vtabs[pmax.mats.size() + g], 1.0);
+            for (size_t q = 0; q < pmax.mats.size(); ++q) pmax.mats[q].k = tab_max(ctx->vtabs[q], pmax.mats[q].k);
+            for (double &h : pmax.if_h) h *= hmax;
+            for (double &h : pmax.contact_h) h *= hmax;
+            Base bmax;
+            prep_base(pmax, bmax);
+            base.dt_bound = bmax.dt_bound;
+            base.dt_scen = bmax.dt_scen;
+            base.elem_abs_max = bmax.elem_abs_max;
+            const Tab<double> &sh = ctx->vtabs[pmax.mats.size() + TAB_DIR_OF_TIME];
+            double smin = 0.0, smax = 0.0;
+            for (int j = 0; j < sh.n; ++j) {
+                smin = std::min(smin, sh.y[j]);
+                smax = std::max(smax, sh.y[j]);
+            }
+            base.T_span += smax - smin;
+        }
         Ordering ord;
         prep_order(ctx->prob, base, ctx->opt.ordering, ord);
         std::vector<Candidate> cands;
@@ -667,6 +780,7 @@ int fem_bind_buffers(fem_ctx *ctx, void *const *dev_ptrs, int32_t n) {
             const size_t cap = prop.maxSharedMemoryPerMultiProcessor ? prop.maxSharedMemoryPerMultiProcessor : prop.sharedMemPerBlock;
             if (mx + 1024 > cap) throw PrepError{FEM_E_UNSUPPORTED, "block LDS footprint above the device limit"};
             if (ctx->apparent()) HIPCHECK(set_apparent_lds_limit(ctx->opt.precision, mx));
+            else if (ctx->variable()) HIPCHECK(set_var_lds_limit(ctx->opt.precision, ctx->prob.nen, mx));
             else HIPCHECK(set_block_lds_limit(ctx->opt.precision, ctx->prob.nen, mx));
         }
         ctx->dt_s.clear();
@@ -995,6 +1109,7 @@ int fem_write_state(fem_ctx *ctx, const void *buf, int64_t bytes) {
     if (!ctx || !buf) return set_err(FEM_E_INVALID_ARG, "null argument");
     return guarded([&] {
         check_bound(ctx, ST_BOUND);
+        if (ctx->variable()) throw PrepError{FEM_E_UNSUPPORTED, "checkpoints of time-dependent properties"};
         const int64_t N = ctx->L().N, R = (int64_t)ctx->rsize(), Q = ctx->L().n_inflow;
         if (bytes < ckpt_bytes(ctx)) throw PrepError{FEM_E_INVALID_ARG, "checkpoint too small"};
         CkptHeader h;

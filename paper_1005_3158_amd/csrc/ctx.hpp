@@ -13,6 +13,7 @@
 #include "../../include/castfem.h"
 #include "apparent.hpp"
 #include "kernels.hpp"
+#include "varprops.hpp"
 #include "prep.hpp"
 
 namespace castfem {
@@ -32,12 +33,13 @@ enum Stage { ST_NEW = 0, ST_FINAL = 1, ST_BOUND = 2 };
 enum Buf {
     B_NODE_X, B_T, B_H, B_INV_M, B_FS, B_MATS, B_CONN, B_R, B_LCONN, B_BLOCKS, B_SH_LIST, B_PARTIALS,
     B_COMB_PTR, B_SH_POS, B_ROBIN, B_LINK_PTR, B_LINK_NODE, B_LINK_W, B_DIAG, B_QNODE, B_FLAGS, B_SEG,
-    B_CAP_PARTIALS, B_APP_MATS, B_COUNT
+    B_CAP_PARTIALS, B_APP_MATS, B_VAR_TABS_F, B_VAR_TABS_D, B_T_FIXED, B_TIME, B_COUNT
 };
 inline const char *const BUF_NAMES[B_COUNT] = {"node_x", "T", "H", "inv_m", "fs", "mats", "conn", "r", "lconn", "blocks",
                                   "sh_list", "partials", "comb_ptr", "sh_pos", "robin", "link_ptr",
                                   "link_node", "link_w", "diag", "qnode", "flags", "segments",
-                                  "cap_partials", "app_mats"};
+                                  "cap_partials", "app_mats", "var_tables_f32", "var_tables_f64", "T_fixed",
+                                  "time"};
 constexpr int64_t ALIGN = 256;
 constexpr int GRAPH_STEPS = 16;  // steps per captured graph (even: both parities)
 constexpr size_t MAX_BLOCK_LDS = 160 * 1024 - 2048;  // gfx950 LDS per workgroup, less static use
@@ -88,6 +90,23 @@ inline void t_of_h(const MatDev &M, double H, double &T, double &fs) {
     }
 }
 
+// value of a table at x (n >= 1): linear between points, constant beyond the ends
+inline double tab_eval_host(const Tab<double> &t, double x) {
+    const int n = t.n;
+    if (x <= t.x[0]) return t.y[0];
+    if (x >= t.x[n - 1]) return t.y[n - 1];
+    int j = 0;
+    while (j + 2 < n && !(x < t.x[j + 1])) ++j;
+    return t.y[j] + (t.y[j + 1] - t.y[j]) * (x - t.x[j]) / (t.x[j + 1] - t.x[j]);
+}
+// the largest value of a table, or `constant` if it is not given
+inline double tab_max(const Tab<double> &t, double constant) {
+    if (t.n == 0) return constant;
+    double m = t.y[0];
+    for (int j = 1; j < t.n; ++j) m = std::max(m, t.y[j]);
+    return m;
+}
+
 }  // namespace castfem
 
 using namespace castfem;
@@ -106,6 +125,10 @@ struct fem_ctx {
     Dev dev;
     AppDev app;                 // apparent-capacity mode: the step's view of the buffers
     double cap_bound = 0;       // apparent mode: bound on any node's lumped capacitance (J/K)
+    // temperature- and time-dependent properties: n_mat conductivity tables, then
+    // h(T), h(t) and the fixed-temperature shift (empty: constant properties)
+    std::vector<Tab<double>> vtabs;
+    VarDev vdev;
     std::vector<MatDev> mats_host;
     int parity = 0;
     int64_t steps = 0;
@@ -122,6 +145,11 @@ struct fem_ctx {
     const Layout &L() const { return cands[chosen].L; }
     size_t rsize() const { return opt.precision == FEM_PREC_FP64 ? 8 : 4; }
     bool apparent() const { return opt.latent_model == FEM_LATENT_APPARENT; }
+    bool variable() const { return !vtabs.empty(); }
+    // the fixed-temperature shift at time t (0 without variable properties)
+    double dir_shift(double t) const;
+    // node_x.w carries the material index instead of the conductivity
+    bool mat_in_node_x() const { return apparent() || variable(); }
 };
 
 

@@ -495,6 +495,7 @@ int fem_sur_create(fem_sur **out, fem_ctx *ctx, const fem_sur_options *o) {
     return guarded([&] {
         check_bound(ctx, ST_BOUND);
         if (ctx->apparent()) throw PrepError{FEM_E_UNSUPPORTED, "the surrogate runs on the enthalpy form only"};
+        if (ctx->variable()) throw PrepError{FEM_E_UNSUPPORTED, "the surrogate needs constant properties"};
         if (o->width != WIDTH) throw PrepError{FEM_E_UNSUPPORTED, "width must be 64"};
         if (o->layers < 1 || o->layers > MAX_LAYERS) throw PrepError{FEM_E_INVALID_ARG, "layers must be 1..4"};
         if (o->horizon < 3) throw PrepError{FEM_E_INVALID_ARG, "horizon must be >= 3"};

@@ -210,3 +210,36 @@ def test_matched_faces_given_as_contact_find_their_partners():
         cf.fem_finalize(ctx)
     assert e.value.code == -2
     cf.fem_destroy(ctx)
+
+
+def test_variable_properties_bound_and_refusals(orc):
+    """Host side of temperature- and time-dependent properties: the stability bound
+    at the largest properties equals the oracle's; unsupported combinations and
+    malformed tables are refused."""
+    vp = dict(k_of_T=[[(550.0, 180.0), (700.0, 95.0)], None], h_of_T=[(100.0, 3.0), (650.0, 0.5)],
+              h_of_t=[(0.0, 1.0), (1.0, 2.0)], dir_of_t=[(0.0, 0.0), (5.0, 30.0)])
+    p = dict(configs.config2(n=8), varprops=vp)
+    ctx = cf.fem_create(cf.make_options())
+    rep = cf.setup_problem(ctx, p)
+    cf.fem_destroy(ctx)
+    assert rep["dt_bound"] == pytest.approx(orc.stable_dt_var(p, orc.VarProps(2, **vp)), rel=1e-12)
+    for opts in (dict(scatter=cf.FEM_SCATTER_COLORED), dict(latent_model=cf.FEM_LATENT_APPARENT)):
+        ctx = cf.fem_create(cf.make_options(**opts))
+        with pytest.raises(cf.FemError) as e:
+            cf.setup_problem(ctx, p)
+        assert e.value.code == -7
+        cf.fem_destroy(ctx)
+    b = configs.batch(n_scen=2, elems_range=(800, 1600))
+    b["varprops"] = dict(h_of_t=[(0.0, 1.0)])
+    ctx = cf.fem_create(cf.make_options())
+    with pytest.raises(cf.FemError) as e:
+        cf.setup_problem(ctx, b)
+    assert e.value.code == -7
+    cf.fem_destroy(ctx)
+    for bad in (dict(h_of_t=[(1.0, 1.0), (0.5, 2.0)]), dict(k_of_T=[[(0.0, -1.0)], None]),
+                dict(h_of_T=[(0.0, float("nan"))])):
+        ctx = cf.fem_create(cf.make_options())
+        with pytest.raises(cf.FemError) as e:
+            cf.setup_problem(ctx, dict(configs.config2(n=4), varprops=bad))
+        assert e.value.code == -1
+        cf.fem_destroy(ctx)

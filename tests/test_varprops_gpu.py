@@ -1,0 +1,119 @@
+"""GPU parity of temperature- and time-dependent properties (k(T) per element,
+interface factors h(T) and h(t), time-shifted fixed temperatures) against the
+oracle's variable-property mode, through the C interface.
+
+Tolerances as for constant properties: FP64 1e-8 K; FP32 1e-3 K away from the
+freezing range and 0.05 K within 5 K of it.
+"""
+import numpy as np
+import pytest
+
+from castgen import configs
+
+pytestmark = pytest.mark.gpu
+
+K_CAST = [(550.0, 180.0), (620.0, 150.0), (700.0, 95.0)]
+K_SAND = [(0.0, 0.4), (700.0, 1.2)]
+H_T = [(100.0, 3.0), (650.0, 0.5)]
+H_TIME = [(0.0, 1.0), (0.5, 0.3), (1.5, 1.5)]
+SHIFT = [(0.0, 0.0), (15.0, 250.0), (40.0, 120.0)]
+
+
+def _cf():
+    from paper_1005_3158_amd import castfem as cf
+    return cf
+
+
+def _band(T, T_ref, mat=configs.ALLOY):
+    band = (T_ref >= mat[3] - 5.0) & (T_ref <= mat[4] + 5.0)
+    err = np.abs(T - T_ref)
+    return (float(np.max(err[~band])) if np.any(~band) else 0.0,
+            float(np.max(err[band])) if np.any(band) else 0.0, int(band.sum()))
+
+
+def _with(p, **vp):
+    q = dict(p)
+    q["varprops"] = vp
+    return q
+
+
+def _compare(orc, p, steps, precision, **opts):
+    cf = _cf()
+    vp = orc.VarProps(len(p["materials"]), **p["varprops"])
+    dt = 0.9 * orc.stable_dt_var(p, vp)
+    _, T_ref, fs_ref, D = orc.run_var(p, vp, dt, steps, diag=True)
+    s = cf.Solver(p, precision=precision, **opts)
+    try:
+        assert s.stable_dt() == pytest.approx(orc.stable_dt_var(p, vp), rel=1e-12)
+        s.step(dt, steps)
+        T, fs, en = s.T(), s.fs(), s.energy()
+    finally:
+        s.close()
+    return T, fs, en, T_ref, fs_ref, D
+
+
+def test_fp64_tets_with_k_of_T_and_variable_contact(orc):
+    cf = _cf()
+    p = _with(configs.config2(n=10), k_of_T=[K_CAST, K_SAND], h_of_T=H_T, h_of_t=H_TIME)
+    T, fs, en, T_ref, fs_ref, D = _compare(orc, p, 300, cf.FEM_PREC_FP64,
+                                           lds_bytes=cf.lds_for_nodes(300, cf.FEM_PREC_FP64))
+    err = float(np.max(np.abs(T - T_ref)))
+    print("variable properties, tets fp64: max|dT| = %.3e K, energy residual %.2e" % (err, en["residual"]), flush=True)
+    assert err <= 1e-8
+    assert float(np.max(np.abs(fs - fs_ref))) <= 1e-10
+    assert en["E"] == pytest.approx(D[-1, orc.D_E], rel=1e-12)
+    assert en["residual"] <= 1e-11
+
+
+def test_fp64_hex_cube_with_k_of_T_and_a_moving_wall(orc):
+    cf = _cf()
+    p = _with(configs.config1(), k_of_T=[K_CAST], dir_of_t=SHIFT)
+    T, fs, en, T_ref, fs_ref, D = _compare(orc, p, 200, cf.FEM_PREC_FP64, block_elems=512)
+    err = float(np.max(np.abs(T - T_ref)))
+    print("variable properties, hex fp64 with moving wall: max|dT| = %.3e K, Q_cum %.6e (oracle %.6e), "
+          "residual %.2e" % (err, en["Q_cum"], D[-1, orc.D_QCUM], en["residual"]), flush=True)
+    assert err <= 1e-8
+    assert en["Q_cum"] == pytest.approx(D[-1, orc.D_QCUM], rel=1e-9)
+    assert en["residual"] <= 1e-11
+
+
+@pytest.mark.parametrize("mesh", ["matched", "nonmatching"])
+def test_fp32_2000_steps(orc, mesh):
+    cf = _cf()
+    base = configs.config2(n=14) if mesh == "matched" else configs.tet_casting_nonmatching()
+    p = _with(base, k_of_T=[K_CAST, K_SAND], h_of_T=H_T, h_of_t=H_TIME)
+    T, fs, en, T_ref, fs_ref, D = _compare(orc, p, 2000, cf.FEM_PREC_FP32_KAHAN)
+    off, on, nb = _band(T, T_ref)
+    print("variable properties fp32 %s: max|dT| off-front %.3e K, band %.3e K (%d nodes); energy residual %.3e "
+          "(oracle %.3e)" % (mesh, off, on, nb, en["residual"], D[-1, orc.D_RESID]), flush=True)
+    assert off <= 1e-3 and on <= 0.05
+    assert float(np.max(np.abs(fs - fs_ref))) <= 1e-3
+
+
+def test_graph_and_eager_steps_agree_and_time_advances_on_the_device():
+    """The device-held time must advance the same way in captured graphs and in
+    eager launches: the time factor of the contact makes any slip visible."""
+    cf = _cf()
+    p = _with(configs.config2(n=10), h_of_t=H_TIME, k_of_T=[K_CAST, None])
+    opts = dict(precision=cf.FEM_PREC_FP32_KAHAN, lds_bytes=cf.lds_for_nodes(400))
+    a = cf.Solver(p, **opts)
+    dt = 0.9 * a.stable_dt()
+    a.step(dt, 160)
+    b = cf.Solver(p, **opts)
+    cf.fem_time_kernels(b.ctx, dt, 160)
+    assert np.array_equal(a.T(), b.T()) and np.array_equal(a.H(), b.H())
+    a.close()
+    b.close()
+
+
+def test_surrogate_and_checkpoint_restore_are_refused():
+    cf = _cf()
+    s = cf.Solver(_with(configs.config2(n=6), h_of_t=H_TIME))
+    with pytest.raises(cf.FemError) as e:
+        cf.Surrogate(s, layers=3)
+    assert e.value.code == -7
+    ck = cf.fem_read_state(s.ctx)
+    with pytest.raises(cf.FemError) as e:
+        cf.fem_write_state(s.ctx, ck)
+    assert e.value.code == -7
+    s.close()
