@@ -29,7 +29,20 @@ HBM_PEAK_GBS = 8000.0
 
 
 ENTHALPY_SOURCES = ("kernels.hip", "kernels.hpp", "elem.hpp")
-APPARENT_SOURCES = ("apparent.hip", "apparent.hpp", "kernels.hpp", "elem.hpp")
+APPARENT_SOURCES = ("apparent.hip", "apparent.hpp", "step_common.hpp", "kernels.hpp", "elem.hpp")
+VARPROPS_SOURCES = ("varprops.hip", "varprops.hpp", "step_common.hpp", "kernels.hpp", "elem.hpp")
+# properties of the variable-property workload: conductivity tables of the alloy
+# and the sand, interface factors against the pair temperature and against time
+VARPROPS = dict(k_of_T=[[(550.0, 180.0), (620.0, 150.0), (700.0, 95.0)], [(0.0, 0.4), (700.0, 1.2)]],
+                h_of_T=[(100.0, 3.0), (650.0, 0.5)], h_of_t=[(0.0, 1.0), (0.5, 0.3), (1.5, 1.5)])
+
+
+def sources_of(kernel_key):
+    if "k_block_app" in kernel_key:
+        return APPARENT_SOURCES
+    if "k_block_var" in kernel_key:
+        return VARPROPS_SOURCES
+    return ENTHALPY_SOURCES
 
 
 def kernel_hash(sources=ENTHALPY_SOURCES):
@@ -74,7 +87,7 @@ def traffic_from_counters(fetch_dir, write_dir, block_nodes, kernel_key="k_block
     fetch_scale, write_scale = gib_kib / cf_, gib_kib / cw
     out = {
         "kernel": kernel_key, "block_nodes": block_nodes, "dispatches": nk,
-        "kernel_hash": kernel_hash(APPARENT_SOURCES if "app" in kernel_key else ENTHALPY_SOURCES),
+        "kernel_hash": kernel_hash(sources_of(kernel_key)),
         "fetch_kib_raw": kf, "write_kib_raw": kw, "copy_fetch_kib": cf_, "copy_write_kib": cw,
         "fetch_scale": fetch_scale, "write_scale": write_scale,
         "bytes_per_launch": 1024.0 * (kf * fetch_scale + kw * write_scale),
@@ -107,13 +120,14 @@ def main():
                          "picks there, pinned so that the committed traffic counters match the timed kernel; "
                          "autotuned for the batch")
     ap.add_argument("--workload", default="tet128",
-                    choices=["tet128", "tet256", "batch", "surrogate", "apparent", "contact"],
+                    choices=["tet128", "tet256", "batch", "surrogate", "apparent", "contact", "varprops"],
                     help="tet128: the 128^3 cast/mould mesh; tet256: the 256^3 mesh with eight seeded casting "
                          "boxes (beyond the last-level cache); batch: 256 scenarios of 20k-400k tets; "
                          "surrogate: train on chill-cube trajectories, then time-to-solidify plain vs surrogate; "
                          "apparent: the 128^3 mesh stepped in the apparent-heat-capacity form, compared with "
                          "the enthalpy form; contact: a casting cube and its mould meshed separately "
-                         "(non-matching interface, sisters found by the library)")
+                         "(non-matching interface, sisters found by the library); varprops: the 128^3 mesh with "
+                         "k(T) tables and interface factors h(T), h(t)")
     ap.add_argument("--contact-cells", type=int, nargs=2, default=[96, 128], metavar=("CAST", "MOULD"),
                     help="contact: cells per side of the casting cube's grid and of the mould box's grid")
     ap.add_argument("--compare-steps", type=int, default=20000,
@@ -155,6 +169,8 @@ def main():
         return bench_apparent(args, log)
     if args.workload == "contact":
         return bench_contact(args, log)
+    if args.workload == "varprops":
+        return bench_varprops(args, log)
     big = args.workload == "tet256"
     if big:
         args.no_surrogate = True
@@ -469,6 +485,89 @@ def bench_contact(args, log):
         },
         "cpu_baseline": None,
         "energy_residual": {"steps": en["steps"], "residual": en["residual"]},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_varprops(args, log):
+    """The 128^3 cast/mould mesh with temperature- and time-dependent properties:
+    k(T) of both materials at each element's mean T, interface coefficients scaled
+    by h(T) at each node pair's mean and by h(t).  Timed steps, the element kernel
+    against the HBM roofline, full-size parity and the oracle as CPU baseline."""
+    import torch
+    from castgen import configs
+    from paper_1005_3158_amd import castfem as cf
+
+    prob = dict(configs.config2(n=args.n), varprops=VARPROPS)
+    E, N = prob["conn"].shape[0], prob["xyz"].shape[0]
+    block_nodes = 512 if args.block_nodes is None else args.block_nodes
+    opts = dict(precision=cf.FEM_PREC_FP32_KAHAN, lds_bytes=cf.lds_for_nodes(block_nodes))
+    t0 = time.time()
+    s = cf.Solver(prob, **opts)
+    t_setup = time.time() - t0
+    rep = s.report
+    dt = 0.9 * s.stable_dt()
+    log("variable properties: %d tets, %d nodes; setup %.1f s; dt %.4e s" % (E, N, t_setup, dt))
+    s.step(dt, args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(dt, args.steps)
+    torch.cuda.synchronize()
+    t_run = time.perf_counter() - t0
+    value = E * args.steps / t_run
+    kt = cf.fem_time_kernels(s.ctx, dt, args.profile_steps)
+    ach_e = kt["bytes_element"] / (kt["ms_element"] * 1e-3) / 1e9
+    ach_c = kt["bytes_combine"] / (kt["ms_combine"] * 1e-3) / 1e9 if kt["ms_combine"] > 0 else None
+    en = s.energy()
+    nbytes = 1 << 30
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    copy_gbs = 2 * nbytes / (cf.fem_copy_kernel(s.ctx, dst.data_ptr(), src.data_ptr(), nbytes, 20) * 1e-3) / 1e9
+    del src, dst
+    s.close()
+    log("steps %d in %.4f s: %.3f ms/step, %.4g element-steps/s; element kernel %.4f ms (%.1f GB/s alg), node "
+        "kernel %.4f ms; energy residual %.2e" % (args.steps, t_run, 1e3 * t_run / args.steps, value,
+                                                  kt["ms_element"], ach_e, kt["ms_combine"], en["residual"]))
+    cpu = parity = None
+    if args.cpu_steps > 0:
+        from oracle import oracle
+        k = args.cpu_steps
+        g = cf.Solver(prob, **opts)
+        g.step(dt, k)
+        T_gpu = g.T()
+        g.close()
+        P = oracle.Problem(prob)
+        vp = oracle.VarProps(len(prob["materials"]), **VARPROPS)
+        t0 = time.perf_counter()
+        _, T_ref, _ = oracle.run_var(P, vp, dt, k)
+        t_cpu = time.perf_counter() - t0
+        cpu = {"value": E * k / t_cpu, "unit": "element-steps/s", "cores": 1, "kind": "oracle",
+               "sample": "%d steps with variable properties of the full 128^3 mesh from the initial state (FP64, one "
+                         "thread, including its lumping and initial enthalpy), %.1f s" % (k, t_cpu)}
+        parity = {"steps": k, "max_abs_dT_K": float(np.max(np.abs(T_gpu - T_ref)))}
+        log("oracle: %d steps in %.1f s; max|T_gpu - T_oracle| = %.3e K" % (k, t_cpu, parity["max_abs_dT_K"]))
+    out = {
+        "metric": METRIC, "value": value, "unit": "element-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * t_run / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 (compensated enthalpy, f64 T(H) and reductions)", "data": "synthetic",
+        "config": {
+            "workload": "128^3 jittered Kuhn tets (%d tets, %d nodes), alloy cube in sand mould, k(T) tables of both "
+                        "materials, interface factors h(T) and h(t), Hilbert ordering, LDS-blocked scatter, "
+                        "dt=0.9 x bound at the largest properties" % (E, N),
+            "n_elems": E, "n_nodes": N, "dt": dt, "block_nodes": rep["max_local_nodes"], "n_blocks": rep["n_blocks"],
+            "setup_s": t_setup, "properties": VARPROPS,
+        },
+        "copy_kernel_GBps": copy_gbs,
+        "roofline": {
+            "bound": "hbm", "kernel": "k_block_var<float,4> (blocked residual with k(T) per element + private update)",
+            "achieved": ach_e, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach_e / HBM_PEAK_GBS,
+            "traffic": load_traffic("block_varprops_config2", rep["max_local_nodes"], VARPROPS_SOURCES),
+            "ms_per_launch": kt["ms_element"], "alg_bytes_per_launch": kt["bytes_element"],
+            "node_kernel": {"ms_per_launch": kt["ms_combine"], "alg_bytes_per_launch": kt["bytes_combine"],
+                            "achieved": ach_c},
+        },
+        "cpu_baseline": cpu, "parity": parity, "energy_residual": en["residual"],
     }
     print(json.dumps(out), flush=True)
 
