@@ -136,6 +136,8 @@ def main():
     ap.add_argument("--held-out", type=int, default=None,
                     help="surrogate: held-out trajectories (seeds 5500+); default 50, or 20 inside the default run")
     ap.add_argument("--epochs", type=int, default=8, help="surrogate: training epochs per round")
+    ap.add_argument("--horizon", type=int, default=32,
+                    help="surrogate: steps one jump covers (32: the shortest on the plateau of the measured sweep)")
     ap.add_argument("--rounds", type=int, default=1, help="surrogate: training rounds (later ones through jumps)")
     ap.add_argument("--verify-tol", type=float, default=3.0, help="surrogate: one-step verification tolerance (K)")
     ap.add_argument("--fs-tol", type=float, default=1e-6,
@@ -677,7 +679,8 @@ def run_surrogate(args, log):
         b = configs.chill_batch(list(range(5000, 5000 + args.train_traj)))
         gen = cf.Solver(b, precision=cf.FEM_PREC_FP32_KAHAN)
         dt = 0.9 * gen.stable_dt_scenarios()
-        sur = cf.Surrogate(gen, layers=3, max_samples=1, train=True, seed=11, loss=loss, extrapolation=extrap)
+        sur = cf.Surrogate(gen, layers=3, horizon=args.horizon, max_samples=1, train=True, seed=11, loss=loss,
+                           extrapolation=extrap)
         if params is not None:
             sur.set_params(params)
         S = torch.empty((n_chunks, 4, gen.n_nodes), dtype=torch.float32, device=gen.device)
@@ -734,10 +737,10 @@ def run_surrogate(args, log):
             rp = plain.advance(dt1, 10 ** 6, None, until_solid=True)
             # the same gates with the untrained network (w_out = 0): the extrapolation alone
             ex = cf.Solver(p, precision=cf.FEM_PREC_FP32_KAHAN, lds_bytes=lds)
-            se = cf.Surrogate(ex, layers=3, extrapolation=extrap)
+            se = cf.Surrogate(ex, layers=3, horizon=args.horizon, extrapolation=extrap)
             re_ = ex.advance(dt1, 10 ** 6, se, until_solid=True, verify_tol=args.verify_tol, fs_tol=args.fs_tol)
             acc = cf.Solver(p, precision=cf.FEM_PREC_FP32_KAHAN, lds_bytes=lds)
-            sa = cf.Surrogate(acc, layers=3, extrapolation=extrap)
+            sa = cf.Surrogate(acc, layers=3, horizon=args.horizon, extrapolation=extrap)
             sa.set_params(params)
             ra = acc.advance(dt1, 10 ** 6, sa, until_solid=True, verify_tol=args.verify_tol, fs_tol=args.fs_tol)
             for k, r in (("plain", rp), ("extrap", re_), ("net", ra)):
@@ -775,7 +778,7 @@ def run_surrogate(args, log):
         "dtype": "bf16 net (f32 accumulate), f32+compensated explicit state, f64 gates", "data": "synthetic",
         "config": {"workload": "16^3 hex alloy cube with a convective chill on x=0: train on %d trajectories, "
                                "%d held-out trajectories run to full solidification" % (args.train_traj, args.held_out),
-                   "layers": 3, "width": 64, "horizon": 16, "epochs": args.epochs, "rounds": args.rounds,
+                   "layers": 3, "width": 64, "horizon": args.horizon, "epochs": args.epochs, "rounds": args.rounds,
                    "loss": args.loss, "extrapolation": args.extrapolation, "energy_tol": 1e-4, "fs_tol": args.fs_tol,
                    "verify_tol_K": args.verify_tol},
         "plain_seconds": t_plain, "surrogate_seconds": t_sur,
