@@ -3,7 +3,9 @@ times: 128^3 jittered Kuhn tets (12,582,912 tets, 2,181,347 nodes), alloy cube i
 sand with h_i = 1000, FP32 state with compensated enthalpy, LDS-blocked scatter,
 Hilbert ordering, 512-node blocks, steps in captured graphs.
 
-- Three steps against the FP64 oracle at every node (the oracle takes ~5 s per step).
+- Three steps against the FP64 oracle at every node (the oracle takes ~5 s per step), also in
+  the apparent-capacity form and with temperature- and time-dependent properties; the
+  non-matching contact workload (16.3M tets) with all of its sisters and two steps.
 - 400 steps against properties that hold at any size: the energy balance
   (FP64 E - E0 - Q_cum), finite values, and bitwise reproducibility of the
   fixed-point scatter (two runs give the same state).  The discrete maximum
@@ -68,6 +70,49 @@ def test_three_full_size_apparent_steps_match_the_oracle(config2, orc):
           (err.max(), np.sqrt(np.mean(err ** 2)), np.abs(fs - fs_ref).max()), flush=True)
     assert err.max() <= 1e-3
     assert np.abs(fs - fs_ref).max() <= 1e-4
+
+
+def test_three_full_size_steps_with_variable_properties_match_the_oracle(config2, orc):
+    """k(T) of both materials, interface factors h(T) and h(t), in the benchmark's
+    launch shape (512-node blocks), against the oracle's variable-property run."""
+    from paper_1005_3158_amd import castfem as cf
+    vp = dict(k_of_T=[[(550.0, 180.0), (620.0, 150.0), (700.0, 95.0)], [(0.0, 0.4), (700.0, 1.2)]],
+              h_of_T=[(100.0, 3.0), (650.0, 0.5)], h_of_t=[(0.0, 1.0), (0.5, 0.3), (1.5, 1.5)])
+    p = dict(config2, varprops=vp)
+    props = orc.VarProps(2, **vp)
+    dt = 0.9 * orc.stable_dt_var(p, props)
+    s = cf.Solver(p, precision=cf.FEM_PREC_FP32_KAHAN, lds_bytes=cf.lds_for_nodes(BLOCK_NODES))
+    try:
+        s.step(dt, 3)
+        T = s.T()
+    finally:
+        s.close()
+    _, T_ref, _ = orc.run_var(p, props, dt, 3)
+    err = np.abs(T - T_ref)
+    print("variable properties: max|T - oracle| %.3e K" % err.max(), flush=True)
+    assert err.max() <= 1e-3
+
+
+def test_full_size_nonmatching_contact(orc):
+    """The contact workload of the benchmark (16.3M tets, 159,744 contact faces): every
+    sister equal to the oracle's all-pairs search, and two steps against the oracle."""
+    from paper_1005_3158_amd import castfem as cf
+    p = configs.tet_casting_nonmatching(n_cast=96, n_mold=128, jitter=0.15)
+    nf = p["contact_faces"].shape[0]
+    s = cf.Solver(p, precision=cf.FEM_PREC_FP32_KAHAN, lds_bytes=cf.lds_for_nodes(BLOCK_NODES))
+    try:
+        dt = 0.9 * s.stable_dt()
+        sis = cf.fem_get_sisters(s.ctx, nf)
+        s.step(dt, 2)
+        T = s.T()
+    finally:
+        s.close()
+    P = orc.Problem(p)
+    assert np.array_equal(sis, P.sisters)
+    _, T_ref, _ = orc.run(P, dt, 2)
+    err = np.abs(T - T_ref)
+    print("non-matching contact, %d faces: max|T - oracle| %.3e K" % (nf, err.max()), flush=True)
+    assert err.max() <= 1e-3
 
 
 def test_four_hundred_full_size_steps_keep_energy_and_are_reproducible(config2, orc):
