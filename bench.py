@@ -64,7 +64,7 @@ def load_traffic(kind, block_nodes, sources=ENTHALPY_SOURCES):
     return t.get("bytes_per_launch")
 
 
-def traffic_from_counters(fetch_dir, write_dir, block_nodes, kernel_key="k_block<float, 4>",
+def traffic_from_counters(fetch_dir, write_dir, block_nodes, kernel_key="k_block<float, 4, true>",
                           out_name="block_element_config2"):
     """Summarise two rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE,
     KiB per dispatch) into HBM bytes per launch of the blocked element kernel.
@@ -104,7 +104,7 @@ def main():
         # --traffic-from FETCH_DIR WRITE_DIR BLOCK_NODES [RECORD_NAME [KERNEL_NAME]]
         traffic_from_counters(sys.argv[2], sys.argv[3], int(sys.argv[4]),
                               out_name=sys.argv[5] if len(sys.argv) > 5 else "block_element_config2",
-                              kernel_key=sys.argv[6] if len(sys.argv) > 6 else "k_block<float, 4>")
+                              kernel_key=sys.argv[6] if len(sys.argv) > 6 else "k_block<float, 4, true>")
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)

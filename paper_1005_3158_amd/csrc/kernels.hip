@@ -25,27 +25,20 @@
 #include <type_traits>
 
 #include "elem.hpp"
+#include "step_common.hpp"
 
 namespace castfem {
 namespace {
 
-template <class R> struct VT;
-template <> struct VT<float> { using V4 = float4; using V2 = float2; };
-template <> struct VT<double> { using V4 = double4; using V2 = double2; };
-
-__device__ __forceinline__ uint32_t flag_bits(float w) { return __float_as_uint(w); }
-__device__ __forceinline__ uint32_t flag_bits(double w) { return (uint32_t)__double_as_longlong(w); }
-
-__device__ __forceinline__ float mat_k(const MatDev &m, float) { return m.kf; }
-__device__ __forceinline__ double mat_k(const MatDev &m, double) { return m.k; }
-
-// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
-// contiguous range of logical blocks so neighbouring blocks share its L2.
-__device__ __forceinline__ int xcd_remap(int w, int n) {
-    const int x = w & 7, i = w >> 3;
-    const int q = n >> 3, rem = n & 7;
-    return x * q + min(x, rem) + i;
-}
+using step::boundary_terms;
+using step::fx_from;
+using step::fx_to;
+using step::LDS_MATS;
+using step::NodeH;
+using step::stage_table;
+using step::t_of_h;
+using step::VT;
+using step::xcd_remap;
 
 struct DiagAcc {
     double v[NDIAG];
@@ -55,90 +48,6 @@ struct DiagAcc {
         v[DG_TMAX] = -DBL_MAX;
     }
 };
-
-// enthalpy relation (Eq. 11, linear latent release); isothermal: slope = 0
-__device__ __forceinline__ void t_of_h(const MatDev &M, double H, double &T, double &fs) {
-    if (!M.latent || H <= M.Hs) {
-        T = H * M.inv_c;
-        fs = 1.0;
-    } else if (H >= M.Hl) {
-        T = (H - M.L) * M.inv_c;
-        fs = 0.0;
-    } else {
-        T = M.Ts + (H - M.Hs) * M.slope;
-        fs = 1.0 - (H - M.Hs) * M.inv_dH;
-    }
-}
-
-// ------------------------------------------------------------ node update
-// FP32: error-free two-sum of (hi, inc) carried into lo, then renormalised.
-__device__ __forceinline__ float2 kahan_add(float2 h, float inc) {
-#pragma clang fp contract(off)
-    float s = h.x + inc;
-    float bp = s - h.x;
-    float e = (h.x - (s - bp)) + (inc - bp);
-    float lo = h.y + e;
-    float hi = s + lo;
-    lo = lo - (hi - s);
-    return make_float2(hi, lo);
-}
-
-template <class R> struct Node;
-
-// Enthalpy update of a free node g with residual r (fixed nodes are never
-// passed: their H, T and fs keep the values set at bind time).
-template <> struct Node<float> {
-    static __device__ __forceinline__ void update(const Dev &d, const MatDev *mats, int64_t g, float r,
-                                                  uint32_t flag, float *Tn) {
-        const MatDev &M = mats[flag & NODE_MAT_MASK];
-        float2 *H = (float2 *)d.H;
-        const float im = ((const float *)d.inv_m)[g];
-        float inc;
-        {
-#pragma clang fp contract(off)
-            inc = r * (M.dtf * im);
-        }
-        const float2 h = kahan_add(H[g], inc);
-        H[g] = h;
-        double T, fs;
-        t_of_h(M, (double)h.x + (double)h.y, T, fs);
-        Tn[g] = (float)T;
-        ((float *)d.fs)[g] = (float)fs;
-    }
-};
-
-template <> struct Node<double> {
-    static __device__ __forceinline__ void update(const Dev &d, const MatDev *mats, int64_t g, double r,
-                                                  uint32_t flag, double *Tn) {
-        const MatDev &M = mats[flag & NODE_MAT_MASK];
-        double *H = (double *)d.H;
-        const double im = ((const double *)d.inv_m)[g];
-        const double h = H[g] + r * (M.dt * im);
-        H[g] = h;
-        double T, fs;
-        t_of_h(M, h, T, fs);
-        Tn[g] = T;
-        ((double *)d.fs)[g] = fs;
-    }
-};
-
-// Robin and interface terms of boundary slot s for a node at temperature Ti:
-// adds them to r and returns the Robin inflow
-template <class R>
-__device__ __forceinline__ double boundary_terms(const Dev &d, int64_t s, R Ti, const R *Tc, R &r) {
-    using V2 = typename VT<R>::V2;
-    double q = 0.0;
-    if (d.robin) {
-        const V2 ab = ((const V2 *)d.robin)[s];
-        const R f = ab.x - ab.y * Ti;
-        r += f;
-        q = (double)f;
-    }
-    const int32_t l0 = d.link_ptr[s], l1 = d.link_ptr[s + 1];
-    const R *w = (const R *)d.link_w;
-    for (int32_t k = l0; k < l1; ++k) r += w[k] * (Tc[d.link_node[k]] - Ti);
-    return q;
-}
 
 // sum / min / max over the 64 lanes of a wavefront
 __device__ __forceinline__ double wave_sum(double v) {
@@ -230,35 +139,12 @@ __global__ __launch_bounds__(256) void k_elems(Dev d, int parity, int64_t e0, in
 // adds are slow on gfx950 while 64-bit integer adds run at close to full LDS
 // rate, so each element contribution r is rounded to the integer q = r * 2^S
 // (|q| < 2^51, scale chosen on the host from a bound on every node's element
-// sums) and added with an integer atomic.  Integer sums do not depend on the
-// order of the additions, so the blocked path is bitwise reproducible, and
-// the four contributions of an element sum to exactly zero.
-struct Fixed {
-    // round(r * scale) as a two's-complement integer: adding 1.5 * 2^52 puts
-    // the rounded value in the low mantissa bits of the double
-    static __device__ __forceinline__ long long from(float r, double scale) {
-        const double magic = 6755399441055744.0;  // 1.5 * 2^52
-        const double x = __builtin_fma((double)r, scale, magic);
-        return __double_as_longlong(x) - __double_as_longlong(magic);
-    }
-    static __device__ __forceinline__ float to(long long q, double inv_scale) {
-        return (float)((double)q * inv_scale);
-    }
-};
-
-// materials staged in LDS when the table is small
-constexpr int LDS_MATS = 8;
-
-__device__ __forceinline__ const MatDev *stage_mats(const Dev &d, MatDev *s_mats) {
-    if (d.n_mat > LDS_MATS) return d.mats;
-    const int words = d.n_mat * (int)(sizeof(MatDev) / 8);
-    for (int w = threadIdx.x; w < words; w += blockDim.x)
-        ((double *)s_mats)[w] = ((const double *)d.mats)[w];
-    return s_mats;   // visible after the caller's next barrier
-}
+// sums) and added with an integer atomic (step::fx_from).  Integer sums do not
+// depend on the order of the additions, so the blocked path is bitwise
+// reproducible, and the four contributions of an element sum to exactly zero.
 
 // element phase of the blocked layout, one workgroup per element block
-template <class R, int NEN>
+template <class R, int NEN, bool LDS_TABLES>
 __global__ __launch_bounds__(1024) void k_block(Dev d, int parity) {
     using V4 = typename VT<R>::V4;
     using LC = typename std::conditional<NEN == 4, uint2, uint4>::type;
@@ -277,7 +163,8 @@ __global__ __launch_bounds__(1024) void k_block(Dev d, int parity) {
     const R *Tc = (const R *)d.T + parity * d.N;
     R *Tn = (R *)d.T + (1 - parity) * d.N;
     if (threadIdx.x == 0) s_bad = 0;
-    const MatDev *mats = stage_mats(d, s_mats);
+    if constexpr (LDS_TABLES) stage_table(d.mats, d.n_mat, s_mats);   // visible after the next barrier
+    const MatDev *mats = LDS_TABLES ? s_mats : d.mats;
 
     // gather: private nodes are a contiguous range, shared nodes a list;
     // node_x holds x, y, z and the conductivity of the node's material
@@ -323,7 +210,7 @@ __global__ __launch_bounds__(1024) void k_block(Dev d, int parity) {
             long long sum = 0;
             for (int a = 1; a < NEN; ++a) {
                 bad |= !(fabsf(re[a]) < d.fx_limit);   // also catches NaN
-                q[a] = Fixed::from(re[a], d.fx_scale);
+                q[a] = fx_from(re[a], d.fx_scale);
                 sum += q[a];
             }
             q[0] = -sum;
@@ -343,13 +230,13 @@ __global__ __launch_bounds__(1024) void k_block(Dev d, int parity) {
     const bool poison = s_bad != 0;
     auto resid = [&](int l) -> R {
         R r;
-        if constexpr (std::is_same<R, float>::value) r = Fixed::to(s_acc[l], d.fx_inv);
+        if constexpr (std::is_same<R, float>::value) r = fx_to(s_acc[l], d.fx_inv);
         else r = s_acc[l];
         return poison ? R(NAN) : r;
     };
     for (int l = threadIdx.x; l < bi.n_int; l += blockDim.x) {
         const int64_t g = (int64_t)bi.int_base + l;
-        Node<R>::update(d, mats, g, resid(l), d.flags[g], Tn);
+        NodeH<R>::update(d, mats[d.flags[g] & NODE_MAT_MASK], g, resid(l), Tn);
     }
     // one partial per shared node, stored where the combine reads it
     R *P = (R *)d.partials;
@@ -362,13 +249,16 @@ __global__ __launch_bounds__(1024) void k_block(Dev d, int parity) {
 // carry boundary inflow (Robin faces, reactions of fixed temperatures); each
 // of them accumulates its own FP64 sum of dt * inflow, so no reduction runs
 // per step and the total does not depend on the schedule.
-template <class R, bool COMBINE>
+template <class R, bool COMBINE, bool LDS_TABLES>
 __global__ __launch_bounds__(NODE_THREADS) void k_nodes(Dev d, int parity) {
     __shared__ MatDev s_mats[LDS_MATS];
     const int64_t count = COMBINE ? d.N - d.n_private : d.N;
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const MatDev *mats = stage_mats(d, s_mats);
-    __syncthreads();
+    if constexpr (LDS_TABLES) {
+        stage_table(d.mats, d.n_mat, s_mats);
+        __syncthreads();
+    }
+    const MatDev *mats = LDS_TABLES ? s_mats : d.mats;
     if (s >= count) return;
     const int64_t g = d.bc_first + s;
     const R *Tc = (const R *)d.T + parity * d.N;
@@ -394,7 +284,7 @@ __global__ __launch_bounds__(NODE_THREADS) void k_nodes(Dev d, int parity) {
     double q = 0.0;
     if (f & NODE_BC) q = boundary_terms<R>(d, s, Tc[g], Tc, r);
     if (f & NODE_FIXED) q -= (double)r;     // reaction of a fixed temperature
-    else Node<R>::update(d, mats, g, r, f, Tn);
+    else NodeH<R>::update(d, mats[f & NODE_MAT_MASK], g, r, Tn);
     if (s < d.n_inflow) d.qnode[s] += q * mats[f & NODE_MAT_MASK].dt;
 }
 
@@ -468,11 +358,12 @@ __global__ __launch_bounds__(256) void k_stage(int32_t *__restrict__ dst_chk, co
     for (int64_t i = t; i < n_qn; i += stride) dst_qn[i] = qn[i];
 }
 
-template <class R, int NEN>
+template <class R, int NEN, bool LDS_TABLES>
 hipError_t step_t(const Dev &d, int parity, hipStream_t s, hipEvent_t *ev) {
     if (ev) (void)hipEventRecord(ev[0], s);
     if (d.scatter == FEM_SCATTER_LDS_BLOCKED) {
-        hipLaunchKernelGGL((k_block<R, NEN>), dim3((unsigned)d.n_blocks), dim3(d.threads), d.lds_bytes, s, d, parity);
+        hipLaunchKernelGGL((k_block<R, NEN, LDS_TABLES>), dim3((unsigned)d.n_blocks), dim3(d.threads), d.lds_bytes, s,
+                           d, parity);
     } else if (d.scatter == FEM_SCATTER_GLOBAL_ATOMIC) {
         if (d.E > 0)
             hipLaunchKernelGGL((k_elems<R, NEN, true>), dim3((unsigned)((d.E + 255) / 256)), dim3(256), 0, s, d,
@@ -493,19 +384,37 @@ hipError_t step_t(const Dev &d, int parity, hipStream_t s, hipEvent_t *ev) {
     const int64_t count = comb ? d.N - d.n_private : d.N;
     if (count > 0) {
         if (comb)
-            hipLaunchKernelGGL((k_nodes<R, true>), dim3((unsigned)node_grid(count)), dim3(NODE_THREADS), 0, s, d, parity);
+            hipLaunchKernelGGL((k_nodes<R, true, LDS_TABLES>), dim3((unsigned)node_grid(count)), dim3(NODE_THREADS), 0, s,
+                               d, parity);
         else
-            hipLaunchKernelGGL((k_nodes<R, false>), dim3((unsigned)node_grid(count)), dim3(NODE_THREADS), 0, s, d, parity);
+            hipLaunchKernelGGL((k_nodes<R, false, LDS_TABLES>), dim3((unsigned)node_grid(count)), dim3(NODE_THREADS), 0,
+                               s, d, parity);
     }
     if (ev) (void)hipEventRecord(ev[3], s);
     return hipGetLastError();
 }
 
+// material tables of at most LDS_MATS rows are read from LDS, larger ones (a
+// batch) from global memory, each in its own instantiation
+template <class R, int NEN>
+hipError_t step_nen(const Dev &d, int parity, hipStream_t s, hipEvent_t *ev) {
+    return d.n_mat <= LDS_MATS ? step_t<R, NEN, true>(d, parity, s, ev) : step_t<R, NEN, false>(d, parity, s, ev);
+}
+
+template <class R, int NEN>
+hipError_t set_limit(size_t bytes) {
+    for (const void *k : {(const void *)k_block<R, NEN, true>, (const void *)k_block<R, NEN, false>}) {
+        const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 }  // namespace
 
 hipError_t enqueue_step(const Dev &d, int parity, hipStream_t s, hipEvent_t *ev) {
-    if (d.prec == FEM_PREC_FP64) return d.nen == 4 ? step_t<double, 4>(d, parity, s, ev) : step_t<double, 8>(d, parity, s, ev);
-    return d.nen == 4 ? step_t<float, 4>(d, parity, s, ev) : step_t<float, 8>(d, parity, s, ev);
+    if (d.prec == FEM_PREC_FP64) return d.nen == 4 ? step_nen<double, 4>(d, parity, s, ev) : step_nen<double, 8>(d, parity, s, ev);
+    return d.nen == 4 ? step_nen<float, 4>(d, parity, s, ev) : step_nen<float, 8>(d, parity, s, ev);
 }
 
 hipError_t enqueue_state_diag(const Dev &d, int parity, hipStream_t s) {
@@ -516,10 +425,8 @@ hipError_t enqueue_state_diag(const Dev &d, int parity, hipStream_t s) {
 }
 
 hipError_t set_block_lds_limit(int prec, int nen, size_t bytes) {
-    const void *f;
-    if (prec == FEM_PREC_FP64) f = nen == 4 ? (const void *)k_block<double, 4> : (const void *)k_block<double, 8>;
-    else f = nen == 4 ? (const void *)k_block<float, 4> : (const void *)k_block<float, 8>;
-    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (prec == FEM_PREC_FP64) return nen == 4 ? set_limit<double, 4>(bytes) : set_limit<double, 8>(bytes);
+    return nen == 4 ? set_limit<float, 4>(bytes) : set_limit<float, 8>(bytes);
 }
 
 hipError_t enqueue_stage(int32_t *dst_chk, const int32_t *chk, int64_t n_chk, double *dst_dg, const double *dg,
