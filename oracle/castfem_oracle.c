@@ -769,7 +769,7 @@ double orc_table(const double *tab, double x)
     if (x <= xs[0]) return ys[0];
     if (x >= xs[n - 1]) return ys[n - 1];
     int j = 0;
-    while (!(x < xs[j + 1])) ++j;
+    while (j + 2 < n && !(x < xs[j + 1])) ++j;   /* bounded: a NaN x ends in the last segment */
     return ys[j] + (ys[j + 1] - ys[j]) * (x - xs[j]) / (xs[j + 1] - xs[j]);
 }
 
