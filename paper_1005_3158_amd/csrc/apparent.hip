@@ -46,6 +46,18 @@ __device__ __forceinline__ MatR<double> mat_r(const AppMat &m, double) {
     return {m.k, m.rho, m.c, m.L, m.Ts, m.Tl, m.inv_dT};
 }
 
+// clamp to [0, 1] (one v_med3 in FP32)
+__device__ __forceinline__ float clamp01(float x) { return __builtin_amdgcn_fmed3f(x, 0.0f, 1.0f); }
+__device__ __forceinline__ double clamp01(double x) { return fmin(fmax(x, 0.0), 1.0); }
+
+// sqrt(hh / g2) for g2 > 0: FP32 with the hardware square root and reciprocal
+// square root (about 1 ulp each; the FP32 path rounds its inputs far more),
+// FP64 correctly rounded
+__device__ __forceinline__ float lemmon_ratio(float hh, float g2) {
+    return __builtin_amdgcn_sqrtf(hh) * __builtin_amdgcn_rsqf(g2);
+}
+__device__ __forceinline__ double lemmon_ratio(double hh, double g2) { return sqrt(hh / g2); }
+
 // Residual r = -K^e T^e and lumped capacitance share rho C_app V / 4 of a
 // linear tetrahedron.  With edges d_j = x_j - x_0, c_1 = d_2 x d_3 (cyclic),
 // D = d_1 . c_1 = 6 V: G = sum_j (T_j - T_0) c_j = D grad T and, with the liquid
@@ -68,7 +80,7 @@ __device__ __forceinline__ void tet_app(const typename VT<R>::V4 *p, const MatR<
     re[0] = -(re[1] + re[2] + re[3]);
     // liquid fraction; inv_dT = 0 (no latent heat) gives f = 0 everywhere
     const R ts = M.Ts, idt = M.inv_dT;
-    auto frac = [&](R T) { return fmin(fmax((T - ts) * idt, R(0)), R(1)); };
+    auto frac = [&](R T) { return clamp01((T - ts) * idt); };
     const R f0 = frac(p[0].w);
     const R b1 = frac(p[1].w) - f0, b2 = frac(p[2].w) - f0, b3 = frac(p[3].w) - f0;
     const R c = M.c, L = M.L;
@@ -78,7 +90,7 @@ __device__ __forceinline__ void tet_app(const typename VT<R>::V4 *p, const MatR<
     const R g2 = dot3(G, G);
     R capp;
     if (g2 > R(0)) {
-        capp = sqrt(dot3(GH, GH) / g2);
+        capp = lemmon_ratio(dot3(GH, GH), g2);
     } else {
         // uniform element: the slope of H(T) at its temperature
         const R tm = (((p[0].w + p[1].w) + p[2].w) + p[3].w) * R(0.25);
