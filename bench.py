@@ -326,7 +326,7 @@ def bench_apparent(args, log):
     E, N = prob["conn"].shape[0], prob["xyz"].shape[0]
     block_nodes = 512 if args.block_nodes is None else args.block_nodes
     app = dict(precision=cf.FEM_PREC_FP32_KAHAN, latent_model=cf.FEM_LATENT_APPARENT,
-               lds_bytes=36 * block_nodes)
+               lds_bytes=cf.lds_for_nodes(block_nodes, apparent=True))
     t0 = time.time()
     s = cf.Solver(prob, **app)
     t_setup = time.time() - t0

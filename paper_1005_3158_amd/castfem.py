@@ -24,9 +24,13 @@ FEM_LATENT_ENTHALPY, FEM_LATENT_APPARENT = 0, 1
 LDS_PER_NODE = {FEM_PREC_FP64: 48, FEM_PREC_FP32_KAHAN: 28}
 
 
-def lds_for_nodes(nodes, precision=FEM_PREC_FP32_KAHAN):
-    """lds_bytes option that caps an LDS block at `nodes` local nodes."""
-    return LDS_PER_NODE[precision] * int(nodes)
+LDS_PER_NODE_APPARENT = {FEM_PREC_FP64: 52, FEM_PREC_FP32_KAHAN: 32}
+
+
+def lds_for_nodes(nodes, precision=FEM_PREC_FP32_KAHAN, apparent=False):
+    """lds_bytes option that caps an LDS block at `nodes` local nodes (apparent:
+    for the apparent-heat-capacity form, whose kernels hold more per node)."""
+    return (LDS_PER_NODE_APPARENT if apparent else LDS_PER_NODE)[precision] * int(nodes)
 
 EXPORTS = [
     "fem_create", "fem_destroy", "fem_last_error", "fem_set_stream", "fem_upload_mesh", "fem_set_materials",

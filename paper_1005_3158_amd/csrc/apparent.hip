@@ -137,9 +137,9 @@ template <> struct NodeApp<double> {
 // the LDS accumulators of its nodes.  UNIFORM: every element has material M;
 // otherwise each element takes the material of its first node.  Returns true
 // if a contribution fell outside the fixed-point range (or was not finite).
-template <class R, bool UNIFORM, class ACC>
+template <class R, bool UNIFORM, class ACC, class CACC>
 __device__ __forceinline__ bool block_elements(const AppDev &a, const BlockInfo &bi, const typename VT<R>::V4 *s_x,
-                                               ACC *s_acc, ACC *s_cap, const int32_t *s_mat, const AppMat *amats,
+                                               ACC *s_acc, CACC *s_cap, const int32_t *s_mat, const AppMat *amats,
                                                const MatR<R> M) {
     using V4 = typename VT<R>::V4;
     const Dev &d = a.d;
@@ -160,15 +160,16 @@ __device__ __forceinline__ bool block_elements(const AppDev &a, const BlockInfo 
             const long long q1 = fx_from(re[1], d.fx_scale), q2 = fx_from(re[2], d.fx_scale),
                             q3 = fx_from(re[3], d.fx_scale);
             const long long q0 = -(q1 + q2 + q3);
-            const long long qc = fx_from(cap, a.cx_scale);
+            // capacitances are positive and their node sums stay below 2^31: 32-bit sums
+            const uint32_t qc = (uint32_t)fx_from(cap, a.cx_scale);
             atomicAdd((unsigned long long *)&s_acc[l0], (unsigned long long)q0);
             atomicAdd((unsigned long long *)&s_acc[l1], (unsigned long long)q1);
             atomicAdd((unsigned long long *)&s_acc[l2], (unsigned long long)q2);
             atomicAdd((unsigned long long *)&s_acc[l3], (unsigned long long)q3);
-            atomicAdd((unsigned long long *)&s_cap[l0], (unsigned long long)qc);
-            atomicAdd((unsigned long long *)&s_cap[l1], (unsigned long long)qc);
-            atomicAdd((unsigned long long *)&s_cap[l2], (unsigned long long)qc);
-            atomicAdd((unsigned long long *)&s_cap[l3], (unsigned long long)qc);
+            atomicAdd(&s_cap[l0], qc);
+            atomicAdd(&s_cap[l1], qc);
+            atomicAdd(&s_cap[l2], qc);
+            atomicAdd(&s_cap[l3], qc);
         } else {
             atomicAdd(&s_acc[l0], re[0]);
             atomicAdd(&s_acc[l1], re[1]);
@@ -189,6 +190,8 @@ template <class R, bool LDS_TABLES>
 __global__ __launch_bounds__(1024) void k_block_app(AppDev a, int parity) {
     using V4 = typename VT<R>::V4;
     using ACC = typename std::conditional<std::is_same<R, float>::value, long long, double>::type;
+    // FP32: 32-bit fixed-point capacitance sums; FP64: double
+    using CACC = typename std::conditional<std::is_same<R, float>::value, uint32_t, double>::type;
     const Dev &d = a.d;
     extern __shared__ __attribute__((aligned(32))) unsigned char smem[];
     __shared__ MatDev s_mats[LDS_MATS];
@@ -199,7 +202,7 @@ __global__ __launch_bounds__(1024) void k_block_app(AppDev a, int parity) {
     const int nloc = bi.n_int + bi.n_sh;
     V4 *s_x = (V4 *)smem;                        // x, y, z, T per local node
     ACC *s_acc = (ACC *)(s_x + nloc);            // residual
-    ACC *s_cap = s_acc + nloc;                   // lumped capacitance
+    CACC *s_cap = (CACC *)(s_acc + nloc);        // lumped capacitance
     int32_t *s_mat = (int32_t *)(s_cap + nloc);  // material index
     const V4 *X = (const V4 *)d.node_x;
     const R *Tc = (const R *)d.T + parity * d.N;
@@ -219,7 +222,7 @@ __global__ __launch_bounds__(1024) void k_block_app(AppDev a, int parity) {
         x.w = Tc[g];
         s_x[l] = x;
         s_acc[l] = ACC(0);
-        s_cap[l] = ACC(0);
+        s_cap[l] = CACC(0);
     }
     __syncthreads();
 
@@ -239,7 +242,7 @@ __global__ __launch_bounds__(1024) void k_block_app(AppDev a, int parity) {
         return poison ? R(NAN) : r;
     };
     auto capv = [&](int l) -> R {
-        if constexpr (std::is_same<R, float>::value) return fx_to(s_cap[l], a.cx_inv);
+        if constexpr (std::is_same<R, float>::value) return (float)((double)s_cap[l] * a.cx_inv);
         else return s_cap[l];
     };
     for (int l = threadIdx.x; l < bi.n_int; l += blockDim.x) {

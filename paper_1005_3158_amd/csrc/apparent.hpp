@@ -28,11 +28,12 @@ struct AppDev {
     void *cap_partials = nullptr;   // R per (block, shared node): partial capacitance
     const AppMat *amats = nullptr;
     double cx_scale = 1.0, cx_inv = 1.0;   // FP32: fixed-point scale 2^S of capacitance sums and 2^-S
-    float cx_limit = 0.0f;                 // largest element capacitance that fits (C * 2^S < 2^50)
+    float cx_limit = 0.0f;                 // largest element capacitance that fits (C * 2^S < 2^31)
 };
 
-// LDS bytes per local node: x, y, z, T; residual and capacitance accumulators; material
-inline size_t lds_per_node_apparent(int prec) { return prec == FEM_PREC_FP64 ? 52 : 36; }
+// LDS bytes per local node: x, y, z, T; residual and capacitance accumulators (FP32:
+// 64- and 32-bit fixed point); material
+inline size_t lds_per_node_apparent(int prec) { return prec == FEM_PREC_FP64 ? 52 : 32; }
 
 // One step reading T buffer `parity`; ev as for enqueue_step.
 hipError_t enqueue_step_apparent(const AppDev &a, int parity, hipStream_t s, hipEvent_t *ev);

@@ -283,13 +283,16 @@ void fill_dev(fem_ctx *c, const Candidate &cd) {
         a.d.lds_bytes = (size_t)L.max_local * lds_per_node_apparent(d.prec);
         a.cap_partials = c->ptr[B_CAP_PARTIALS];
         a.amats = (const AppMat *)c->ptr[B_APP_MATS];
-        // capacitance sums: every element share is positive and each node's
-        // sum is at most cap_bound; a margin of 4 keeps them below 2^50
-        const double bound = 4.0 * std::max(c->cap_bound, 1e-300);
-        const int S = std::min(80, (int)std::floor(std::log2(std::ldexp(1.0, 50) / bound)));
+        // FP32 capacitance sums in 32-bit fixed point: every element share is
+        // positive and each node's sum is at most cap_bound, so cap_bound * 2^S
+        // <= 2^31 keeps every sum (with its rounding) below 2^32.  For a typical
+        // node the quantisation is ~1e-7 of its capacitance (the bound exceeds a
+        // node's sum by the Lemmon-ratio bound, ~10-100).
+        const double bound = 2.0 * std::max(c->cap_bound, 1e-300);
+        const int S = std::min(80, (int)std::floor(std::log2(std::ldexp(1.0, 32) / bound)));
         a.cx_scale = std::ldexp(1.0, S);
         a.cx_inv = std::ldexp(1.0, -S);
-        a.cx_limit = (float)std::ldexp(1.0, 50 - S);
+        a.cx_limit = (float)std::ldexp(1.0, 31 - S);
         c->app = a;
     }
     if (c->variable()) {

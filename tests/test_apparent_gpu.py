@@ -55,7 +55,7 @@ def tet12(orc):
 def test_fp64_against_oracle(tet12, lds_nodes, orc):
     cf = _cf()
     p, dt, T_ref, fs_ref, D = tet12
-    T, fs, H, en = _run(p, dt, 300, precision=cf.FEM_PREC_FP64, lds_bytes=52 * lds_nodes)
+    T, fs, H, en = _run(p, dt, 300, precision=cf.FEM_PREC_FP64, lds_bytes=cf.lds_for_nodes(lds_nodes, cf.FEM_PREC_FP64, apparent=True))
     err = float(np.max(np.abs(T - T_ref)))
     print("apparent tet12 fp64 (%d-node blocks): max|dT| = %.3e K, energy residual %.3e (oracle %.3e)"
           % (lds_nodes, err, en["residual"], D[-1, orc.D_RESID]), flush=True)
@@ -128,7 +128,7 @@ def test_fp32_front_on_the_neumann_bar(orc):
 def test_fp32_is_bitwise_reproducible_and_graph_equals_eager():
     cf = _cf()
     p = configs.config2(n=14)
-    opts = dict(precision=cf.FEM_PREC_FP32_KAHAN, latent_model=cf.FEM_LATENT_APPARENT, lds_bytes=36 * 400)
+    opts = dict(precision=cf.FEM_PREC_FP32_KAHAN, latent_model=cf.FEM_LATENT_APPARENT, lds_bytes=cf.lds_for_nodes(400, apparent=True))
     a = cf.Solver(p, **opts)
     dt = 0.9 * a.stable_dt()
     a.step(dt, 160)                      # ten captured 16-step graphs

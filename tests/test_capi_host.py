@@ -163,7 +163,7 @@ def test_apparent_mode_options_and_buffers():
     p = configs.config2(n=6)
     sizes = {}
     for model in (cf.FEM_LATENT_ENTHALPY, app):
-        ctx = cf.fem_create(cf.make_options(latent_model=model, lds_bytes=36 * 200))
+        ctx = cf.fem_create(cf.make_options(latent_model=model, lds_bytes=cf.lds_for_nodes(200, apparent=True)))
         rep = cf.setup_problem(ctx, p)
         sizes[model] = ({n: b for n, b, a in cf.fem_query_buffers(ctx)}, rep)
         cf.fem_destroy(ctx)

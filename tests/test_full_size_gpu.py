@@ -54,11 +54,11 @@ def test_three_full_size_steps_match_the_oracle(config2, orc):
 
 def test_three_full_size_apparent_steps_match_the_oracle(config2, orc):
     """The apparent-heat-capacity form in the benchmark's launch shape (512-node
-    blocks at its 36 B of LDS per node) against the oracle's apparent form."""
+    blocks at its 32 B of LDS per node) against the oracle's apparent form."""
     from paper_1005_3158_amd import castfem as cf
     dt = 0.9 * orc.stable_dt(config2)
     s = cf.Solver(config2, precision=cf.FEM_PREC_FP32_KAHAN, latent_model=cf.FEM_LATENT_APPARENT,
-                  lds_bytes=36 * BLOCK_NODES)
+                  lds_bytes=cf.lds_for_nodes(BLOCK_NODES, apparent=True))
     try:
         s.step(dt, 3)
         T, fs = s.T(), s.fs()
