@@ -659,7 +659,7 @@ def bench_surrogate(args, log):
     print(json.dumps(run_surrogate(args, log)), flush=True)
 
 
-TIMING_RUNS = 2     # surrogate comparison: runs per trajectory and mode, the fastest counts
+TIMING_RUNS = 5     # surrogate comparison: runs per trajectory and mode, the fastest counts
 
 
 def run_surrogate(args, log):
