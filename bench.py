@@ -465,6 +465,12 @@ def bench_contact(args, log):
     ach_e = kt["bytes_element"] / (kt["ms_element"] * 1e-3) / 1e9
     s.step(dt, max(0, args.compare_steps - args.warmup - args.steps - args.profile_steps))
     en = s.energy()
+    # plain copy ceiling (also the reference that scales the traffic counters)
+    nbytes = 1 << 30
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    copy_gbs = 2 * nbytes / (cf.fem_copy_kernel(s.ctx, dst.data_ptr(), src.data_ptr(), nbytes, 20) * 1e-3) / 1e9
+    del src, dst
     log("steps %d in %.4f s: %.4g element-steps/s; element kernel %.4f ms (%.1f GB/s alg); after %d steps "
         "energy residual %.3e" % (args.steps, t_run, value, kt["ms_element"], ach_e, en["steps"], en["residual"]))
     s.close()
@@ -504,11 +510,13 @@ def bench_contact(args, log):
             "n_elems": E, "n_nodes": N, "n_contact": nf, "dt": dt, "block_nodes": rep["max_local_nodes"],
             "n_blocks": rep["n_blocks"], "setup_s": t_setup,
         },
+        "copy_kernel_GBps": copy_gbs,
         "sister_search_s": rep["contact_search_seconds"],
         "sisters_checked": {"faces": int(sample.size), "differ": mism, "oracle_s": t_ref},
         "roofline": {
             "bound": "hbm", "kernel": "k_block<float,4> (the enthalpy element kernel; contact terms are node links)",
-            "achieved": ach_e, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach_e / HBM_PEAK_GBS, "traffic": None,
+            "achieved": ach_e, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach_e / HBM_PEAK_GBS,
+            "traffic": load_traffic("block_element_contact", rep["max_local_nodes"]),
             "ms_per_launch": kt["ms_element"], "alg_bytes_per_launch": kt["bytes_element"],
         },
         "cpu_baseline": cpu, "parity": parity,
