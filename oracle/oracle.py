@@ -18,12 +18,19 @@ ORC_NDIAG = 9
 D_E, D_LATENT, D_Q, D_QCUM, D_TMIN, D_TMAX, D_NLIQ, D_NONFINITE, D_RESID = range(9)
 
 
+SRC_OMP = os.path.join(HERE, "castfem_oracle_omp.c")
+LIB_OMP = os.path.join(HERE, "liboracle_omp.so")
+
+
 def build(force=False):
-    """Compile the oracle with gcc (plain -O2, no fast-math)."""
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        tmp = LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", tmp, SRC, "-lm"])
-        os.replace(tmp, LIB)
+    """Compile the oracle with gcc (plain -O2, no fast-math), and the same source
+    once more with its multi-threaded run (bitwise the serial run)."""
+    for src, lib_, extra in ((SRC, LIB, []), (SRC_OMP, LIB_OMP, ["-fopenmp"])):
+        deps = (SRC, src, os.path.join(HERE, "castfem_oracle.h"))
+        if force or not os.path.exists(lib_) or os.path.getmtime(lib_) < max(os.path.getmtime(d) for d in deps):
+            tmp = lib_ + ".tmp%d" % os.getpid()
+            subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared"] + extra + ["-o", tmp, src, "-lm"])
+            os.replace(tmp, lib_)
     return LIB
 
 
@@ -215,6 +222,35 @@ def run(prob, dt, n_steps, H=None, diag=False):
     D = np.zeros((n_steps + 1, ORC_NDIAG)) if diag else None
     _check(lib().orc_run(P.ref, C.c_double(dt), C.c_int64(n_steps), _ptr(H),
                          _ptr(D) if diag else None), "run")
+    T, fs = state_T(P, H)
+    return (H, T, fs, D) if diag else (H, T, fs)
+
+
+_lib_omp = None
+
+
+def _omp():
+    global _lib_omp
+    if _lib_omp is None:
+        build()
+        _lib_omp = C.CDLL(LIB_OMP)
+        _lib_omp.orc_omp_threads.restype = C.c_int32
+    return _lib_omp
+
+
+def omp_threads():
+    """Threads the multi-threaded run uses by default (OpenMP's own count)."""
+    return int(_omp().orc_omp_threads())
+
+
+def run_omp(prob, dt, n_steps, H=None, diag=False, threads=0):
+    """run() over all host cores (threads = 0: OpenMP's default), bitwise equal to run():
+    the same element routines, each node's element sum in the serial order."""
+    P = _as_problem(prob)
+    H = initial_H(P) if H is None else np.array(H, dtype=np.float64)
+    D = np.zeros((n_steps + 1, ORC_NDIAG)) if diag else None
+    _check(_omp().orc_run_omp(P.ref, C.c_double(dt), C.c_int64(n_steps), _ptr(H),
+                              _ptr(D) if diag else None, C.c_int32(threads)), "run_omp")
     T, fs = state_T(P, H)
     return (H, T, fs, D) if diag else (H, T, fs)
 
