@@ -268,9 +268,12 @@ int fem_read_H(fem_ctx *ctx, double *H_host);
 int fem_energy(fem_ctx *ctx, fem_energy_report *rep);
 /* The same per scenario: reps[n_scen]. */
 int fem_energy_scenarios(fem_ctx *ctx, fem_energy_report *reps);
-/* Checkpoint of the evolving state (enthalpy, its compensation, both
- * temperature buffers, step count, time, energy budget).  With buf == NULL
- * *bytes receives the size. */
+/* Checkpoint of the evolving state (enthalpy with its compensation, the
+ * current temperatures, fraction solid, step count, time, energy budget), every
+ * per-node array in input-node order, so that it restores into any layout of
+ * the same problem (another ordering, block size or autotuner choice).  With
+ * buf == NULL *bytes receives the size.  fem_write_state refuses a checkpoint
+ * of another node count, precision or scenario count (FEM_E_INVALID_ARG). */
 int fem_read_state(fem_ctx *ctx, void *buf, int64_t *bytes);
 int fem_write_state(fem_ctx *ctx, const void *buf, int64_t bytes);
 /* New (device) id of every input node (n_nodes int32). */
@@ -285,6 +288,10 @@ int fem_time_kernels(fem_ctx *ctx, double dt, int64_t n_steps, fem_kernel_times 
 /* Device-to-device copy of `bytes` (multiple of 16) by a plain vector kernel on
  * the context stream; the reference for measured bandwidth and counters. */
 int fem_copy_kernel(fem_ctx *ctx, void *dst, const void *src, int64_t bytes, int32_t repeats, double *ms_per_copy);
+/* The same copy with non-temporal loads and stores over up to 32,768
+ * workgroups: the streaming-bandwidth ceiling the element kernel is compared
+ * with.  Same arguments and errors as fem_copy_kernel. */
+int fem_copy_kernel_nt(fem_ctx *ctx, void *dst, const void *src, int64_t bytes, int32_t repeats, double *ms_per_copy);
 
 /* ------------------------------------------------------------ surrogate */
 /* A learned message-passing surrogate that jumps the enthalpy state `horizon`

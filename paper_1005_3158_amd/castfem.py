@@ -37,7 +37,7 @@ EXPORTS = [
     "fem_set_dirichlet", "fem_set_flux_faces", "fem_set_interface", "fem_set_initial_T", "fem_finalize",
     "fem_query_buffers", "fem_bind_buffers", "fem_get_report", "fem_stable_dt", "fem_step", "fem_read_T",
     "fem_read_fs", "fem_read_H", "fem_energy", "fem_read_state", "fem_write_state", "fem_get_node_perm",
-    "fem_time_kernels", "fem_copy_kernel", "fem_set_scenarios", "fem_stable_dt_scenarios", "fem_step_batch",
+    "fem_time_kernels", "fem_copy_kernel", "fem_copy_kernel_nt", "fem_set_scenarios", "fem_stable_dt_scenarios", "fem_step_batch",
     "fem_energy_scenarios", "fem_sur_create", "fem_sur_destroy", "fem_sur_query_buffers", "fem_sur_bind_buffers",
     "fem_sur_n_params", "fem_sur_get_params", "fem_sur_set_params", "fem_sur_features", "fem_sur_loss_grad",
     "fem_sur_train", "fem_sur_predict", "fem_snapshot_H", "fem_advance", "fem_sur_generate", "fem_sur_save",
@@ -141,6 +141,7 @@ def lib():
             "fem_read_T": [vp, vp], "fem_read_fs": [vp, vp], "fem_read_H": [vp, vp], "fem_energy": [vp, vp],
             "fem_read_state": [vp, vp, vp], "fem_write_state": [vp, vp, i64], "fem_get_node_perm": [vp, vp],
             "fem_time_kernels": [vp, dp, i64, vp], "fem_copy_kernel": [vp, vp, vp, i64, i32, vp],
+            "fem_copy_kernel_nt": [vp, vp, vp, i64, i32, vp],
             "fem_set_scenarios": [vp, i32, vp], "fem_stable_dt_scenarios": [vp, vp],
             "fem_step_batch": [vp, vp, i64], "fem_energy_scenarios": [vp, vp],
             "fem_sur_create": [vp, vp, vp], "fem_sur_destroy": [vp], "fem_sur_query_buffers": [vp, vp, vp],
@@ -362,6 +363,13 @@ def fem_time_kernels(ctx, dt, n_steps):
 def fem_copy_kernel(ctx, dst_ptr, src_ptr, nbytes, repeats):
     ms = C.c_double()
     _call("fem_copy_kernel", ctx, C.c_void_p(dst_ptr), C.c_void_p(src_ptr), int(nbytes), int(repeats), C.byref(ms))
+    return ms.value
+
+
+def fem_copy_kernel_nt(ctx, dst_ptr, src_ptr, nbytes, repeats):
+    ms = C.c_double()
+    _call("fem_copy_kernel_nt", ctx, C.c_void_p(dst_ptr), C.c_void_p(src_ptr), int(nbytes), int(repeats),
+          C.byref(ms))
     return ms.value
 
 

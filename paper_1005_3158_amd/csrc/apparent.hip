@@ -151,7 +151,8 @@ __device__ __forceinline__ bool block_elements(const AppDev &a, const BlockInfo 
         uint2 nxt{};
         if (e + (int)blockDim.x < bi.n_e) nxt = lc[e + blockDim.x];
         const int l0 = cur.x & 0xFFFF, l1 = cur.x >> 16, l2 = cur.y & 0xFFFF, l3 = cur.y >> 16;
-        const V4 p[4] = {s_x[l0], s_x[l1], s_x[l2], s_x[l3]};
+        V4 p[4] = {s_x[l0], s_x[l1], s_x[l2], s_x[l3]};
+        step::local_coords<4>(p, d.x_scale);
         R re[4], cap;
         tet_app<R>(p, UNIFORM ? M : mat_r(amats[s_mat[l0]], R(0)), re, cap);
         if constexpr (std::is_same<R, float>::value) {
@@ -277,12 +278,8 @@ __global__ __launch_bounds__(NODE_THREADS) void k_nodes_app(AppDev a, int parity
     const uint32_t f = d.flags[g];
     const R *P = (const R *)d.partials;
     const R *Pc = (const R *)a.cap_partials;
-    const int32_t k0 = d.comb_ptr[s], k1 = d.comb_ptr[s + 1];
-    R r = P[k0], C = Pc[k0];                 // every shared node has a partial
-    for (int32_t k = k0 + 1; k < k1; ++k) {
-        r += P[k];
-        C += Pc[k];
-    }
+    R r = step::combine_partials(d, P, s, f);
+    R C = step::combine_partials(d, Pc, s, f);
     double q = 0.0;
     if (f & NODE_BC) q = boundary_terms<R>(d, s, Tc[g], Tc, r);
     if (f & NODE_FIXED) q -= (double)r;     // reaction of a fixed temperature

@@ -39,12 +39,12 @@ void layout_sizes(const fem_ctx *c, const Layout &L, int64_t *sz) {
         const int64_t np = (int64_t)L.sh_list.size();
         sz[B_LCONN] = E * L.nen * 2;
         sz[B_BLOCKS] = (int64_t)L.blocks.size() * (int64_t)sizeof(BlockInfo);
-        sz[B_SH_LIST] = np * 4;
-        sz[B_PARTIALS] = np * R;
+        sz[B_SH_LIST] = (np + 1) * 4;   // one padding entry: the gather's clamped loads
+        sz[B_PARTIALS] = L.n_partial_slots * R;
         sz[B_COMB_PTR] = (N - L.n_private + 1) * 4;
         sz[B_SH_POS] = np * 4;
         if (c->apparent()) {
-            sz[B_CAP_PARTIALS] = np * R;
+            sz[B_CAP_PARTIALS] = L.n_partial_slots * R;
             sz[B_APP_MATS] = (int64_t)c->prob.mats.size() * (int64_t)sizeof(AppMat);
         }
         if (c->variable()) {
@@ -85,12 +85,42 @@ void upload_layout_t(fem_ctx *c, const Layout &L) {
     c->tmin0 = INFINITY;
     c->tmax0 = -INFINITY;
     c->nliq0 = 0;
+    // FP32: coordinates as fixed-point integers (in the float bits) of a
+    // power-of-two unit that maps the bounding box into [0, 2^30] and keeps
+    // every element's extent below 2^24 units (exact in FP32, and element
+    // formulas evaluated in units stay far from FP32 overflow)
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, ext = 0.0, span = 0.0;
+    for (int64_t n = 0; n < N; ++n)
+        for (int a = 0; a < 3; ++a) lo[a] = std::min(lo[a], L.xyz[3 * n + a]);
+    for (int64_t n = 0; n < N; ++n)
+        for (int a = 0; a < 3; ++a) ext = std::max(ext, L.xyz[3 * n + a] - lo[a]);
+    for (int64_t e = 0; e < L.E; ++e)
+        for (int a = 0; a < 3; ++a) {
+            double mn = INFINITY, mx = -INFINITY;
+            for (int j = 0; j < L.nen; ++j) {
+                const double x = L.xyz[3 * (int64_t)L.conn[e * L.nen + j] + a];
+                mn = std::min(mn, x);
+                mx = std::max(mx, x);
+            }
+            span = std::max(span, mx - mn);
+        }
+    const double unit = std::ldexp(1.0, (int)std::ceil(std::log2(std::max(
+                                            {ext / 1073741824.0, span / 8388608.0, 1e-30}))));
+    c->x_scale = sizeof(R) == 4 ? (float)unit : 1.0f;
     for (int64_t n = 0; n < N; ++n) {
         const uint32_t f = L.nflag[n];
         V4 v;
-        v.x = (R)L.xyz[3 * n];
-        v.y = (R)L.xyz[3 * n + 1];
-        v.z = (R)L.xyz[3 * n + 2];
+        if constexpr (sizeof(R) == 4) {
+            int32_t q[3];
+            for (int a = 0; a < 3; ++a) q[a] = (int32_t)std::llround((L.xyz[3 * n + a] - lo[a]) / unit);
+            std::memcpy(&v.x, &q[0], 4);
+            std::memcpy(&v.y, &q[1], 4);
+            std::memcpy(&v.z, &q[2], 4);
+        } else {
+            v.x = (R)L.xyz[3 * n];
+            v.y = (R)L.xyz[3 * n + 1];
+            v.z = (R)L.xyz[3 * n + 2];
+        }
         // conductivity of the node's material; the apparent-capacity kernel
         // takes the material index instead
         v.w = c->mat_in_node_x() ? (R)(f & NODE_MAT_MASK) : (R)c->prob.mats[f & NODE_MAT_MASK].k;
@@ -167,8 +197,17 @@ void upload_layout_t(fem_ctx *c, const Layout &L) {
         } else {
             h2d(c, B_BLOCKS, L.blocks.data(), (int64_t)L.blocks.size() * (int64_t)sizeof(BlockInfo));
         }
-        h2d(c, B_SH_LIST, L.sh_list.data(), (int64_t)L.sh_list.size() * 4);
+        {
+            std::vector<int32_t> shp(L.sh_list);
+            shp.push_back(0);
+            h2d(c, B_SH_LIST, shp.data(), (int64_t)shp.size() * 4);
+            HIPCHECK(hipStreamSynchronize(c->stream));   // shp is a temporary
+        }
         h2d(c, B_COMB_PTR, L.comb_ptr.data(), (int64_t)L.comb_ptr.size() * 4);
+        // partial slots of a node's missing blocks are never written: zero them once
+        HIPCHECK(hipMemsetAsync(c->ptr[B_PARTIALS], 0, (size_t)(L.n_partial_slots * sizeof(R)), c->stream));
+        if (c->apparent())
+            HIPCHECK(hipMemsetAsync(c->ptr[B_CAP_PARTIALS], 0, (size_t)(L.n_partial_slots * sizeof(R)), c->stream));
         h2d(c, B_SH_POS, L.sh_pos.data(), (int64_t)L.sh_pos.size() * 4);
     } else {
         h2d(c, B_CONN, L.conn.data(), (int64_t)L.conn.size() * 4);
@@ -234,6 +273,7 @@ void fill_dev(fem_ctx *c, const Candidate &cd) {
     d.N = L.N;
     d.E = L.E;
     d.node_x = c->ptr[B_NODE_X];
+    d.x_scale = c->x_scale;
     d.T = c->ptr[B_T];
     d.H = c->ptr[B_H];
     d.inv_m = c->ptr[B_INV_M];
@@ -263,7 +303,7 @@ void fill_dev(fem_ctx *c, const Candidate &cd) {
     d.n_bc_slots = L.n_bc_slots;
     d.bc_first = L.bc_first;
     d.threads = cd.threads;
-    d.lds_bytes = (size_t)L.max_local * lds_per_node(d.prec);
+    d.lds_bytes = block_lds_bytes(d.prec, L.max_local);
     d.n_colors = L.color_ptr.empty() ? 0 : (int)L.color_ptr.size() - 1;
     d.color_ptr_host = L.color_ptr.empty() ? nullptr : L.color_ptr.data();
     // fixed-point scale: a node's element sum is bounded by
@@ -388,7 +428,26 @@ void eager_steps(fem_ctx *c, int64_t n) {
     }
 }
 
+// capture GRAPH_STEPS steps (starting from T buffer 0) into the context's graph
+void build_graph(fem_ctx *c) {
+    HIPCHECK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t err = hipSuccess;
+    for (int s = 0; s < GRAPH_STEPS && err == hipSuccess; ++s) err = enqueue_ctx_step(c, s & 1, c->stream, nullptr);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+    HIPCHECK(err);
+    HIPCHECK(e2);
+    c->graph = g;
+    HIPCHECK(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+    // upload it now, so that its first launch does not pay for it
+    HIPCHECK(hipGraphUpload(c->gexec, c->stream));
+}
+
+// n steps: whole graphs of GRAPH_STEPS steps, the rest eagerly.  The graph is
+// built by the first call on a stream whatever its n (n = 0 included), so a
+// short warm-up leaves it instantiated and later calls only launch it.
 void run_steps(fem_ctx *c, int64_t n) {
+    if (c->stream != nullptr && !c->gexec) build_graph(c);
     if (c->stream == nullptr || n < GRAPH_STEPS) {
         eager_steps(c, n);
         return;
@@ -396,17 +455,6 @@ void run_steps(fem_ctx *c, int64_t n) {
     if (c->parity == 1) {
         eager_steps(c, 1);
         --n;
-    }
-    if (!c->gexec) {
-        HIPCHECK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-        hipError_t err = hipSuccess;
-        for (int s = 0; s < GRAPH_STEPS && err == hipSuccess; ++s) err = enqueue_ctx_step(c, s & 1, c->stream, nullptr);
-        hipGraph_t g = nullptr;
-        hipError_t e2 = hipStreamEndCapture(c->stream, &g);
-        HIPCHECK(err);
-        HIPCHECK(e2);
-        c->graph = g;
-        HIPCHECK(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
     }
     for (int64_t r = 0; r < n / GRAPH_STEPS; ++r) HIPCHECK(hipGraphLaunch(c->gexec, c->stream));
     eager_steps(c, n % GRAPH_STEPS);
@@ -779,7 +827,7 @@ int fem_bind_buffers(fem_ctx *ctx, void *const *dev_ptrs, int32_t n) {
             HIPCHECK(hipGetDeviceProperties(&prop, ctx->opt.device));
             size_t mx = 0;
             const size_t per = ctx->apparent() ? lds_per_node_apparent(ctx->opt.precision) : lds_per_node(ctx->opt.precision);
-            for (const Candidate &c : ctx->cands) mx = std::max(mx, (size_t)c.L.max_local * per);
+            for (const Candidate &c : ctx->cands) mx = std::max(mx, (size_t)(c.L.max_local + 1) * per);
             const size_t cap = prop.maxSharedMemoryPerMultiProcessor ? prop.maxSharedMemoryPerMultiProcessor : prop.sharedMemPerBlock;
             if (mx + 1024 > cap) throw PrepError{FEM_E_UNSUPPORTED, "block LDS footprint above the device limit"};
             if (ctx->apparent()) HIPCHECK(set_apparent_lds_limit(ctx->opt.precision, mx));
@@ -1065,45 +1113,77 @@ int fem_energy_scenarios(fem_ctx *ctx, fem_energy_report *reps) {
 
 // checkpoint layout: header, H, T (both buffers), fs, per-node inflow sums,
 // simulated time of every scenario
+// Checkpoints hold every per-node array in input-node order (the numbering
+// of fem_upload_mesh), so a state restores into any layout of the same
+// problem: another ordering, block size or autotuner choice.  Layout: header,
+// H (8 B per node: FP64, or the FP32 hi/lo pair), T of the current step and
+// f_s (R per node), the inflow sums of the nodes carrying boundary inflow
+// (FP64, in increasing input id), time and estimated jumped inflow per scenario.
 struct CkptHeader {
     uint64_t magic, N, prec, n_inflow, n_scen;
     int64_t parity, steps;
 };
-constexpr uint64_t CKPT_MAGIC = 0x32504B434D454643ull;
+constexpr uint64_t CKPT_MAGIC = 0x33504B434D454643ull;
 
 int64_t ckpt_bytes(const fem_ctx *ctx) {
     const int64_t N = ctx->L().N, R = (int64_t)ctx->rsize();
-    return (int64_t)sizeof(CkptHeader) + N * 8 + 2 * N * R + N * R + ctx->L().n_inflow * 8 + 2 * ctx->prob.n_scen * 8;
+    return (int64_t)sizeof(CkptHeader) + N * 8 + N * R + N * R + ctx->L().n_inflow * 8 + 2 * ctx->prob.n_scen * 8;
+}
+
+// inflow slots of the layout in increasing input id of their nodes
+std::vector<int64_t> inflow_slots_by_input(const Layout &L) {
+    std::vector<int64_t> q(L.n_inflow);
+    for (int64_t k = 0; k < L.n_inflow; ++k) q[k] = k;
+    std::sort(q.begin(), q.end(), [&](int64_t a, int64_t b) { return L.iperm[L.bc_first + a] < L.iperm[L.bc_first + b]; });
+    return q;
+}
+
+// out[input i] = in[device perm[i]] for N items of `w` bytes (or the reverse)
+void permute_items(const Layout &L, const char *in, char *out, int64_t w, bool to_input) {
+    for (int64_t i = 0; i < L.N; ++i) {
+        const int64_t dv = L.perm[i];
+        if (to_input) std::memcpy(out + i * w, in + dv * w, w);
+        else std::memcpy(out + dv * w, in + i * w, w);
+    }
 }
 
 int fem_read_state(fem_ctx *ctx, void *buf, int64_t *bytes) {
     if (!ctx || !bytes) return set_err(FEM_E_INVALID_ARG, "null argument");
     return guarded([&] {
         check_bound(ctx, ST_BOUND);
-        const int64_t N = ctx->L().N, R = (int64_t)ctx->rsize(), Q = ctx->L().n_inflow;
+        const Layout &L = ctx->L();
+        const int64_t N = L.N, R = (int64_t)ctx->rsize(), Q = L.n_inflow;
         const int64_t need = ckpt_bytes(ctx);
         if (!buf) {
             *bytes = need;
             return;
         }
         if (*bytes < need) throw PrepError{FEM_E_INVALID_ARG, "checkpoint buffer too small"};
+        std::vector<char> H(N * 8), T(N * R), fs(N * R);
+        std::vector<double> qn(Q);
+        HIPCHECK(hipMemcpyAsync(H.data(), ctx->ptr[B_H], N * 8, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHECK(hipMemcpyAsync(T.data(), (char *)ctx->ptr[B_T] + ctx->parity * N * R, N * R, hipMemcpyDeviceToHost,
+                                ctx->stream));
+        HIPCHECK(hipMemcpyAsync(fs.data(), ctx->ptr[B_FS], N * R, hipMemcpyDeviceToHost, ctx->stream));
+        if (Q) HIPCHECK(hipMemcpyAsync(qn.data(), ctx->ptr[B_QNODE], Q * 8, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHECK(hipStreamSynchronize(ctx->stream));
         CkptHeader h{CKPT_MAGIC, (uint64_t)N, (uint64_t)ctx->opt.precision, (uint64_t)Q, (uint64_t)ctx->prob.n_scen,
                      ctx->parity, ctx->steps};
         char *p = (char *)buf;
         std::memcpy(p, &h, sizeof h);
         p += sizeof h;
-        HIPCHECK(hipMemcpyAsync(p, ctx->ptr[B_H], N * 8, hipMemcpyDeviceToHost, ctx->stream));
+        permute_items(L, H.data(), p, 8, true);
         p += N * 8;
-        HIPCHECK(hipMemcpyAsync(p, ctx->ptr[B_T], 2 * N * R, hipMemcpyDeviceToHost, ctx->stream));
-        p += 2 * N * R;
-        HIPCHECK(hipMemcpyAsync(p, ctx->ptr[B_FS], N * R, hipMemcpyDeviceToHost, ctx->stream));
+        permute_items(L, T.data(), p, R, true);
         p += N * R;
-        if (Q) HIPCHECK(hipMemcpyAsync(p, ctx->ptr[B_QNODE], Q * 8, hipMemcpyDeviceToHost, ctx->stream));
+        permute_items(L, fs.data(), p, R, true);
+        p += N * R;
+        const std::vector<int64_t> order = inflow_slots_by_input(L);
+        for (int64_t k = 0; k < Q; ++k) std::memcpy(p + 8 * k, &qn[order[k]], 8);
         p += Q * 8;
         std::memcpy(p, ctx->time_s.data(), ctx->prob.n_scen * 8);
         p += ctx->prob.n_scen * 8;
         std::memcpy(p, ctx->Qx_s.data(), ctx->prob.n_scen * 8);
-        HIPCHECK(hipStreamSynchronize(ctx->stream));
         *bytes = need;
     });
 }
@@ -1113,27 +1193,40 @@ int fem_write_state(fem_ctx *ctx, const void *buf, int64_t bytes) {
     return guarded([&] {
         check_bound(ctx, ST_BOUND);
         if (ctx->variable()) throw PrepError{FEM_E_UNSUPPORTED, "checkpoints of time-dependent properties"};
-        const int64_t N = ctx->L().N, R = (int64_t)ctx->rsize(), Q = ctx->L().n_inflow;
+        const Layout &L = ctx->L();
+        const int64_t N = L.N, R = (int64_t)ctx->rsize(), Q = L.n_inflow;
         if (bytes < ckpt_bytes(ctx)) throw PrepError{FEM_E_INVALID_ARG, "checkpoint too small"};
         CkptHeader h;
         std::memcpy(&h, buf, sizeof h);
         if (h.magic != CKPT_MAGIC || h.N != (uint64_t)N || h.prec != (uint64_t)ctx->opt.precision ||
-            h.n_inflow != (uint64_t)Q || h.n_scen != (uint64_t)ctx->prob.n_scen)
+            h.n_inflow != (uint64_t)Q || h.n_scen != (uint64_t)ctx->prob.n_scen || (h.parity != 0 && h.parity != 1))
             throw PrepError{FEM_E_INVALID_ARG, "checkpoint does not match this context"};
         const char *p = (const char *)buf + sizeof h;
-        HIPCHECK(hipMemcpyAsync(ctx->ptr[B_H], p, N * 8, hipMemcpyHostToDevice, ctx->stream));
+        std::vector<char> H(N * 8), T(N * R), fs(N * R);
+        std::vector<double> qn(Q);
+        permute_items(L, p, H.data(), 8, false);
         p += N * 8;
-        HIPCHECK(hipMemcpyAsync(ctx->ptr[B_T], p, 2 * N * R, hipMemcpyHostToDevice, ctx->stream));
-        p += 2 * N * R;
-        HIPCHECK(hipMemcpyAsync(ctx->ptr[B_FS], p, N * R, hipMemcpyHostToDevice, ctx->stream));
+        permute_items(L, p, T.data(), R, false);
         p += N * R;
-        if (Q) HIPCHECK(hipMemcpyAsync(ctx->ptr[B_QNODE], p, Q * 8, hipMemcpyHostToDevice, ctx->stream));
+        permute_items(L, p, fs.data(), R, false);
+        p += N * R;
+        const std::vector<int64_t> order = inflow_slots_by_input(L);
+        for (int64_t k = 0; k < Q; ++k) std::memcpy(&qn[order[k]], p + 8 * k, 8);
         p += Q * 8;
-        std::memcpy(ctx->time_s.data(), p, ctx->prob.n_scen * 8);
+        std::vector<double> time_s(ctx->prob.n_scen), Qx_s(ctx->prob.n_scen);
+        std::memcpy(time_s.data(), p, ctx->prob.n_scen * 8);
         p += ctx->prob.n_scen * 8;
-        std::memcpy(ctx->Qx_s.data(), p, ctx->prob.n_scen * 8);
+        std::memcpy(Qx_s.data(), p, ctx->prob.n_scen * 8);
+        const int par = (int)h.parity;
+        HIPCHECK(hipMemcpyAsync(ctx->ptr[B_H], H.data(), N * 8, hipMemcpyHostToDevice, ctx->stream));
+        HIPCHECK(hipMemcpyAsync((char *)ctx->ptr[B_T] + par * N * R, T.data(), N * R, hipMemcpyHostToDevice,
+                                ctx->stream));
+        HIPCHECK(hipMemcpyAsync(ctx->ptr[B_FS], fs.data(), N * R, hipMemcpyHostToDevice, ctx->stream));
+        if (Q) HIPCHECK(hipMemcpyAsync(ctx->ptr[B_QNODE], qn.data(), Q * 8, hipMemcpyHostToDevice, ctx->stream));
         HIPCHECK(hipStreamSynchronize(ctx->stream));
-        ctx->parity = (int)h.parity;
+        ctx->time_s = time_s;
+        ctx->Qx_s = Qx_s;
+        ctx->parity = par;
         ctx->steps = h.steps;
     });
 }
@@ -1189,16 +1282,18 @@ int fem_time_kernels(fem_ctx *ctx, double dt, int64_t n_steps, fem_kernel_times 
     });
 }
 
-int fem_copy_kernel(fem_ctx *ctx, void *dst, const void *src, int64_t bytes, int32_t repeats, double *ms_per_copy) {
+namespace {
+int timed_copy(fem_ctx *ctx, void *dst, const void *src, int64_t bytes, int32_t repeats, double *ms_per_copy,
+               hipError_t (*copy)(void *, const void *, int64_t, hipStream_t)) {
     if (!ctx || !dst || !src || !ms_per_copy) return set_err(FEM_E_INVALID_ARG, "null argument");
     return guarded([&] {
         if (bytes <= 0 || bytes % 16 || repeats <= 0) throw PrepError{FEM_E_INVALID_ARG, "bytes must be a positive multiple of 16"};
         hipEvent_t e0, e1;
         HIPCHECK(hipEventCreate(&e0));
         HIPCHECK(hipEventCreate(&e1));
-        HIPCHECK(enqueue_copy(dst, src, bytes / 16, ctx->stream));
+        HIPCHECK(copy(dst, src, bytes / 16, ctx->stream));
         HIPCHECK(hipEventRecord(e0, ctx->stream));
-        for (int r = 0; r < repeats; ++r) HIPCHECK(enqueue_copy(dst, src, bytes / 16, ctx->stream));
+        for (int r = 0; r < repeats; ++r) HIPCHECK(copy(dst, src, bytes / 16, ctx->stream));
         HIPCHECK(hipEventRecord(e1, ctx->stream));
         HIPCHECK(hipEventSynchronize(e1));
         float ms = 0;
@@ -1207,6 +1302,15 @@ int fem_copy_kernel(fem_ctx *ctx, void *dst, const void *src, int64_t bytes, int
         (void)hipEventDestroy(e1);
         *ms_per_copy = ms / repeats;
     });
+}
+}  // namespace
+
+int fem_copy_kernel(fem_ctx *ctx, void *dst, const void *src, int64_t bytes, int32_t repeats, double *ms_per_copy) {
+    return timed_copy(ctx, dst, src, bytes, repeats, ms_per_copy, enqueue_copy);
+}
+
+int fem_copy_kernel_nt(fem_ctx *ctx, void *dst, const void *src, int64_t bytes, int32_t repeats, double *ms_per_copy) {
+    return timed_copy(ctx, dst, src, bytes, repeats, ms_per_copy, enqueue_copy_nt);
 }
 
 }  // extern "C"

@@ -130,6 +130,7 @@ struct fem_ctx {
     std::vector<Tab<double>> vtabs;
     VarDev vdev;
     std::vector<MatDev> mats_host;
+    float x_scale = 1.0f;       // FP32 node coordinates: metres per fixed-point unit
     int parity = 0;
     int64_t steps = 0;
     double E0 = 0, Eref = 0, lat0 = 0, tmin0 = 0, tmax0 = 0;

@@ -125,8 +125,9 @@ __global__ __launch_bounds__(256) void k_elems(Dev d, int parity, int64_t e0, in
     V4 p[NEN];
     for (int a = 0; a < NEN; ++a) c[a] = d.conn[e * NEN + a];
     for (int a = 0; a < NEN; ++a) p[a] = X[c[a]];
-    const R k = p[0].w;       // conductivity of the element's material
+    const R k = p[0].w * d.x_scale;     // conductivity of the element's material, per unit length
     for (int a = 0; a < NEN; ++a) p[a].w = Tc[c[a]];
+    step::local_units<NEN>(p);
     R re[NEN];
     Elem<R, NEN>::residual(p, k, re);
     for (int a = 0; a < NEN; ++a) {
@@ -143,6 +144,10 @@ __global__ __launch_bounds__(256) void k_elems(Dev d, int parity, int64_t e0, in
 // depend on the order of the additions, so the blocked path is bitwise
 // reproducible, and the four contributions of an element sum to exactly zero.
 
+// nodes per thread and pass of the gather and of the private-node update
+constexpr int GATHER_U = 4;
+constexpr int UPDATE_U = 2;
+
 // element phase of the blocked layout, one workgroup per element block
 template <class R, int NEN, bool LDS_TABLES>
 __global__ __launch_bounds__(1024) void k_block(Dev d, int parity) {
@@ -156,9 +161,10 @@ __global__ __launch_bounds__(1024) void k_block(Dev d, int parity) {
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const BlockInfo bi = d.blocks[b];
     const int nloc = bi.n_int + bi.n_sh;
+    // nloc + 1 slots each: slot nloc is the gather's spare
     V4 *s_x = (V4 *)smem;                       // x, y, z, T per local node
-    ACC *s_acc = (ACC *)(s_x + nloc);           // residual accumulator
-    R *s_k = (R *)(s_acc + nloc);               // conductivity of the node's material
+    ACC *s_acc = (ACC *)(s_x + nloc + 1);       // residual accumulator
+    R *s_k = (R *)(s_acc + nloc + 1);           // conductivity of the node's material
     const V4 *X = (const V4 *)d.node_x;
     const R *Tc = (const R *)d.T + parity * d.N;
     R *Tn = (R *)d.T + (1 - parity) * d.N;
@@ -167,14 +173,38 @@ __global__ __launch_bounds__(1024) void k_block(Dev d, int parity) {
     const MatDev *mats = LDS_TABLES ? s_mats : d.mats;
 
     // gather: private nodes are a contiguous range, shared nodes a list;
-    // node_x holds x, y, z and the conductivity of the node's material
-    for (int l = threadIdx.x; l < nloc; l += blockDim.x) {
-        const int64_t g = l < bi.n_int ? (int64_t)bi.int_base + l : (int64_t)d.sh_list[bi.sh_begin + (l - bi.n_int)];
-        V4 x = X[g];
-        s_k[l] = x.w;
-        x.w = Tc[g];
-        s_x[l] = x;
-        s_acc[l] = ACC(0);
+    // node_x holds x, y, z and the conductivity of the node's material.
+    // GATHER_U nodes per thread and pass, with no condition inside a pass, so
+    // that their loads are in flight together: first the shared-node indices,
+    // then every coordinate and temperature.  Lanes past the block load valid
+    // entries (the shared list ends with one padding entry) and write the spare
+    // LDS slot nloc, which nothing reads.
+    const int32_t *shl = d.sh_list + bi.sh_begin;
+    for (int l0 = threadIdx.x; l0 < nloc; l0 += GATHER_U * blockDim.x) {
+        int32_t sv[GATHER_U];
+#pragma unroll
+        for (int u = 0; u < GATHER_U; ++u) sv[u] = shl[min(max(l0 + u * (int)blockDim.x - bi.n_int, 0), bi.n_sh)];
+        V4 x[GATHER_U];
+        R t[GATHER_U];
+#pragma unroll
+        for (int u = 0; u < GATHER_U; ++u) {
+            const int l = l0 + u * (int)blockDim.x;
+            const int64_t g = l < bi.n_int ? (int64_t)bi.int_base + l : (int64_t)sv[u];
+            x[u] = X[g];
+            t[u] = Tc[g];
+        }
+#pragma unroll
+        for (int u = 0; u < GATHER_U; ++u) {
+            const int w = min(l0 + u * (int)blockDim.x, nloc);
+            s_k[w] = x[u].w;
+            V4 v;
+            v.x = x[u].x;
+            v.y = x[u].y;
+            v.z = x[u].z;
+            v.w = t[u];
+            s_x[w] = v;
+            s_acc[w] = ACC(0);
+        }
     }
     __syncthreads();
 
@@ -202,7 +232,8 @@ __global__ __launch_bounds__(1024) void k_block(Dev d, int parity) {
         }
         V4 p[NEN];
         for (int a = 0; a < NEN; ++a) p[a] = s_x[l[a]];
-        const R k = s_k[l[0]];
+        const R k = s_k[l[0]] * d.x_scale;   // per unit length of the element coordinates
+        step::local_units<NEN>(p);
         R re[NEN];
         Elem<R, NEN>::residual(p, k, re);
         if constexpr (std::is_same<R, float>::value) {
@@ -234,9 +265,29 @@ __global__ __launch_bounds__(1024) void k_block(Dev d, int parity) {
         else r = s_acc[l];
         return poison ? R(NAN) : r;
     };
-    for (int l = threadIdx.x; l < bi.n_int; l += blockDim.x) {
-        const int64_t g = (int64_t)bi.int_base + l;
-        NodeH<R>::update(d, mats[d.flags[g] & NODE_MAT_MASK], g, resid(l), Tn);
+    // UPDATE_U private nodes per thread and pass, their loads issued together
+    // before the first update; the last nodes of a thread go one by one
+    {
+        int l = threadIdx.x;
+        for (; l + (UPDATE_U - 1) * (int)blockDim.x < bi.n_int; l += UPDATE_U * blockDim.x) {
+            uint32_t f[UPDATE_U];
+            typename NodeH<R>::Pre pre[UPDATE_U];
+#pragma unroll
+            for (int u = 0; u < UPDATE_U; ++u) {
+                const int64_t g = (int64_t)bi.int_base + l + u * (int)blockDim.x;
+                f[u] = d.flags[g];
+                pre[u] = NodeH<R>::load(d, g);
+            }
+#pragma unroll
+            for (int u = 0; u < UPDATE_U; ++u) {
+                const int lu = l + u * (int)blockDim.x;
+                NodeH<R>::store(d, mats[f[u] & NODE_MAT_MASK], (int64_t)bi.int_base + lu, pre[u], resid(lu), Tn);
+            }
+        }
+        for (; l < bi.n_int; l += blockDim.x) {
+            const int64_t g = (int64_t)bi.int_base + l;
+            NodeH<R>::update(d, mats[d.flags[g] & NODE_MAT_MASK], g, resid(l), Tn);
+        }
     }
     // one partial per shared node, stored where the combine reads it
     R *P = (R *)d.partials;
@@ -244,48 +295,49 @@ __global__ __launch_bounds__(1024) void k_block(Dev d, int parity) {
 }
 
 // node phase: all nodes (COMBINE = false: residual from r[N], which is reset)
-// or the shared nodes of the blocked layout (COMBINE = true: sum of the
-// node's contiguous partials, in block order).  The first n_inflow slots may
-// carry boundary inflow (Robin faces, reactions of fixed temperatures); each
-// of them accumulates its own FP64 sum of dt * inflow, so no reduction runs
-// per step and the total does not depend on the schedule.
+// or the shared nodes of the blocked layout (COMBINE = true: sum of the node's
+// partials in block order).  The first n_inflow slots may carry boundary inflow
+// (Robin faces, reactions of fixed temperatures); each of them accumulates its
+// own FP64 sum of dt * inflow, so no reduction runs per step and the total does
+// not depend on the schedule.  A thread first loads its word of the material
+// table and then all of its node's data, so that the table's wait before the
+// barrier leaves the node loads in flight.
 template <class R, bool COMBINE, bool LDS_TABLES>
 __global__ __launch_bounds__(NODE_THREADS) void k_nodes(Dev d, int parity) {
     __shared__ MatDev s_mats[LDS_MATS];
+    static_assert(LDS_MATS * sizeof(MatDev) / 4 <= NODE_THREADS, "one table word per thread");
     const int64_t count = COMBINE ? d.N - d.n_private : d.N;
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = s < count;
+    const int64_t g = d.bc_first + (live ? s : 0);
+    const int words = d.n_mat * (int)(sizeof(MatDev) / 4);
+    uint32_t tw = 0;
+    if (LDS_TABLES && (int)threadIdx.x < words) tw = ((const uint32_t *)d.mats)[threadIdx.x];
+    uint32_t f = 0;
+    R r = R(0);
+    typename NodeH<R>::Pre pre{};
+    if (live) {
+        f = d.flags[g];
+        pre = NodeH<R>::load(d, g);
+        if (COMBINE) r = step::partial_slots(d, (const R *)d.partials, s);
+        else r = ((const R *)d.r)[g];
+    }
     if constexpr (LDS_TABLES) {
-        stage_table(d.mats, d.n_mat, s_mats);
+        if ((int)threadIdx.x < words) ((uint32_t *)s_mats)[threadIdx.x] = tw;
         __syncthreads();
     }
     const MatDev *mats = LDS_TABLES ? s_mats : d.mats;
-    if (s >= count) return;
-    const int64_t g = d.bc_first + s;
+    if (!live) return;
     const R *Tc = (const R *)d.T + parity * d.N;
     R *Tn = (R *)d.T + (1 - parity) * d.N;
-    const uint32_t f = d.flags[g];
-    R r;
-    if (COMBINE) {
-        // most shared nodes sit in two to four blocks: issue the first four
-        // loads together, then sum in block order
-        const R *P = (const R *)d.partials;
-        const int32_t k0 = d.comb_ptr[s], k1 = d.comb_ptr[s + 1];
-        const R p0 = P[k0];                        // every shared node has a partial
-        const R p1 = k0 + 1 < k1 ? P[k0 + 1] : R(0);
-        const R p2 = k0 + 2 < k1 ? P[k0 + 2] : R(0);
-        const R p3 = k0 + 3 < k1 ? P[k0 + 3] : R(0);
-        r = ((p0 + p1) + p2) + p3;
-        for (int32_t k = k0 + 4; k < k1; ++k) r += P[k];
-    } else {
-        R *rr = (R *)d.r;
-        r = rr[g];
-        rr[g] = R(0);
-    }
+    if (COMBINE) r = step::partial_extras(d, (const R *)d.partials, s, f, r);
+    else ((R *)d.r)[g] = R(0);
     double q = 0.0;
     if (f & NODE_BC) q = boundary_terms<R>(d, s, Tc[g], Tc, r);
+    const MatDev &M = mats[f & NODE_MAT_MASK];
     if (f & NODE_FIXED) q -= (double)r;     // reaction of a fixed temperature
-    else NodeH<R>::update(d, mats[f & NODE_MAT_MASK], g, r, Tn);
-    if (s < d.n_inflow) d.qnode[s] += q * mats[f & NODE_MAT_MASK].dt;
+    else NodeH<R>::store(d, M, g, pre, r, Tn);
+    if (s < d.n_inflow) d.qnode[s] += q * M.dt;
 }
 
 // state diagnostics on demand: one workgroup per single-scenario node segment
@@ -341,6 +393,26 @@ __global__ __launch_bounds__(256) void k_copy(float4 *__restrict__ dst, const fl
         dst[i + 3 * stride] = e;
     }
     for (; i < n; i += stride) dst[i] = src[i];
+}
+
+// copy with non-temporal loads and stores (the data is not kept in the caches
+// for a later reader), four 16-byte words in flight per thread: the ceiling of
+// streaming HBM bandwidth on this device
+typedef float v4f __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void k_copy_nt(v4f *__restrict__ dst, const v4f *__restrict__ src, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n; i += 4 * stride) {
+        const v4f a = __builtin_nontemporal_load(src + i);
+        const v4f b = __builtin_nontemporal_load(src + i + stride);
+        const v4f c = __builtin_nontemporal_load(src + i + 2 * stride);
+        const v4f e = __builtin_nontemporal_load(src + i + 3 * stride);
+        __builtin_nontemporal_store(a, dst + i);
+        __builtin_nontemporal_store(b, dst + i + stride);
+        __builtin_nontemporal_store(c, dst + i + 2 * stride);
+        __builtin_nontemporal_store(e, dst + i + 3 * stride);
+    }
+    for (; i < n; i += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
 // the read-back of one check: integer check counts, per-segment diagnostics and
@@ -441,6 +513,13 @@ hipError_t enqueue_copy(void *dst, const void *src, int64_t n16, hipStream_t s) 
     const int64_t want = (n16 + 4 * 256 - 1) / (4 * 256);
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, 256 * 32));
     hipLaunchKernelGGL(k_copy, dim3(grid), dim3(256), 0, s, (float4 *)dst, (const float4 *)src, n16);
+    return hipGetLastError();
+}
+
+hipError_t enqueue_copy_nt(void *dst, const void *src, int64_t n16, hipStream_t s) {
+    const int64_t want = (n16 + 4 * 256 - 1) / (4 * 256);
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, 32768));
+    hipLaunchKernelGGL(k_copy_nt, dim3(grid), dim3(256), 0, s, (v4f *)dst, (const v4f *)src, n16);
     return hipGetLastError();
 }
 

@@ -26,7 +26,8 @@ struct Dev {
     int scatter = FEM_SCATTER_LDS_BLOCKED;
     int64_t N = 0, E = 0;
     // nodes
-    void *node_x = nullptr;   // R4 per node: x, y, z, flag bits
+    void *node_x = nullptr;   // R4 per node: x, y, z (FP32: fixed-point integer bits), and k or the material
+    float x_scale = 1.0f;     // FP32: metres per coordinate unit (a power of two)
     void *T = nullptr;        // R[2N] ping-pong temperatures
     void *H = nullptr;        // float2 (hi, lo) or double per node
     void *inv_m = nullptr;    // R per node
@@ -38,7 +39,7 @@ struct Dev {
     const uint16_t *lconn = nullptr;    // LDS-blocked local connectivity
     const BlockInfo *blocks = nullptr;
     const int32_t *sh_list = nullptr;
-    void *partials = nullptr;           // R per (block, shared node)
+    void *partials = nullptr;           // R per partial slot (see Layout::comb_ptr)
     const int32_t *comb_ptr = nullptr, *sh_pos = nullptr;
     const uint32_t *flags = nullptr;    // material | flag bits per node
     // boundary slots
@@ -69,6 +70,9 @@ inline int64_t node_grid(int64_t n) { return (n + NODE_THREADS - 1) / NODE_THREA
 
 // LDS bytes per local node of the blocked kernel
 inline size_t lds_per_node(int prec) { return prec == FEM_PREC_FP64 ? 48 : 28; }
+// dynamic LDS of the blocked kernel for blocks of at most max_local nodes (one
+// spare node slot that the gather's tail lanes write)
+inline size_t block_lds_bytes(int prec, int64_t max_local) { return (size_t)(max_local + 1) * lds_per_node(prec); }
 
 // Enqueue one explicit step reading T buffer `parity` and writing 1 - parity.
 // If ev is not null, ev[0..1] bracket the element kernel(s) and ev[2..3] the
@@ -80,6 +84,8 @@ hipError_t enqueue_state_diag(const Dev &d, int parity, hipStream_t s);
 hipError_t set_block_lds_limit(int prec, int nen, size_t bytes);
 // Plain vector copy of n16 16-byte words.
 hipError_t enqueue_copy(void *dst, const void *src, int64_t n16, hipStream_t s);
+// The same with non-temporal loads and stores and up to 32,768 workgroups.
+hipError_t enqueue_copy_nt(void *dst, const void *src, int64_t n16, hipStream_t s);
 // Copy check counts, diagnostics and inflow sums into page-locked host memory the device can write.
 hipError_t enqueue_stage(int32_t *dst_chk, const int32_t *chk, int64_t n_chk, double *dst_dg, const double *dg,
                          int64_t n_dg, double *dst_qn, const double *qn, int64_t n_qn, hipStream_t s);

@@ -727,6 +727,8 @@ void prep_layout(const Problem &p, const Base &b, const PrepOptions &o, const Or
     L.N = N;
     L.E = E;
     L.dt_bound = b.dt_bound;
+    L.xtra.clear();
+    L.n_partial_slots = 0;
     // 1. locality ordering of nodes and elements
     std::vector<int32_t> perm = ord.perm;
     std::vector<int64_t> eorder = ord.eorder;
@@ -796,11 +798,12 @@ void prep_layout(const Problem &p, const Base &b, const PrepOptions &o, const Or
         by_owner_rank(shar);
         // shared nodes carrying boundary inflow (Robin faces, fixed temperature)
         // come first: only the node-kernel workgroups covering them reduce it
-        std::stable_partition(shar.begin(), shar.end(), [&](int32_t i) {
-            return b.fixed[i] || b.robin_b[i] != 0.0 || b.robin_a[i] != 0.0;
-        });
-        L.n_inflow = 0;
-        for (int32_t i : shar) L.n_inflow += (b.fixed[i] || b.robin_b[i] != 0.0 || b.robin_a[i] != 0.0) ? 1 : 0;
+        auto inflow = [&](int32_t i) { return b.fixed[i] || b.robin_b[i] != 0.0 || b.robin_a[i] != 0.0; };
+        const auto inflow_end = std::stable_partition(shar.begin(), shar.end(), inflow);
+        // after them the nodes in at most PARTIAL_SLOTS blocks, then the few in
+        // more: only the node-kernel workgroups covering those read extra partials
+        std::stable_partition(inflow_end, shar.end(), [&](int32_t i) { return nblk[i] <= PARTIAL_SLOTS; });
+        L.n_inflow = (int64_t)(inflow_end - shar.begin());
         L.n_private = (int64_t)priv.size();
         std::vector<int32_t> fin(N);
         for (size_t r = 0; r < priv.size(); ++r) fin[priv[r]] = (int32_t)r;
@@ -880,17 +883,28 @@ void prep_layout(const Problem &p, const Base &b, const PrepOptions &o, const Or
                 for (int a = 0; a < nen; ++a) L.lconn[s * nen + a] = (uint16_t)local_id(s, a);
         }
         if (L.max_local > o.max_local_nodes) fail(FEM_E_INVALID_ARG, "internal: block above node cap");
-        // combine lists: the partial slots of every shared node in block order
+        // partial slots: the j-th block (in block order) of shared node s writes
+        // slot j < PARTIAL_SLOTS at j * nsh + s (slot-major, so the combine's
+        // loads are coalesced and need no index; unused slots stay zero), and
+        // the rest at PARTIAL_SLOTS * nsh + comb_ptr[s] + j - PARTIAL_SLOTS
         const int64_t nsh = N - L.n_private;
         L.comb_ptr.assign(nsh + 1, 0);
-        for (int32_t g : L.sh_list) L.comb_ptr[g - L.n_private + 1]++;
+        for (int64_t s = 0; s < nsh; ++s)
+            L.comb_ptr[s + 1] = std::max<int32_t>(nblk[shar[s]] - PARTIAL_SLOTS, 0);
         for (int64_t s = 0; s < nsh; ++s) L.comb_ptr[s + 1] += L.comb_ptr[s];
-        // partials of one node are contiguous, in block order, so the combine
-        // reads them in one run; each block writes its partial to sh_pos
         L.sh_pos.resize(L.sh_list.size());
-        std::vector<int32_t> fill(L.comb_ptr.begin(), L.comb_ptr.end() - 1);
-        for (size_t slot = 0; slot < L.sh_list.size(); ++slot)
-            L.sh_pos[slot] = fill[L.sh_list[slot] - L.n_private]++;
+        std::vector<int32_t> rank(nsh, 0);
+        for (size_t slot = 0; slot < L.sh_list.size(); ++slot) {
+            const int64_t s = L.sh_list[slot] - L.n_private;
+            const int32_t j = rank[s]++;
+            L.sh_pos[slot] = j < PARTIAL_SLOTS ? (int32_t)(j * nsh + s)
+                                               : (int32_t)(PARTIAL_SLOTS * nsh + L.comb_ptr[s] + j - PARTIAL_SLOTS);
+        }
+        for (int64_t s = 0; s < nsh; ++s)
+            if (rank[s] != nblk[shar[s]]) fail(FEM_E_MESH, "internal: partial slots");
+        L.n_partial_slots = PARTIAL_SLOTS * nsh + L.comb_ptr[nsh];
+        L.xtra.assign(N, 0);
+        for (int64_t s = 0; s < nsh; ++s) L.xtra[L.n_private + s] = nblk[shar[s]] > PARTIAL_SLOTS;
         L.bc_first = L.n_private;
         L.n_bc_slots = nsh;
         L.block_elems = o.block_elems;
@@ -942,7 +956,8 @@ void prep_layout(const Problem &p, const Base &b, const PrepOptions &o, const Or
     for (int64_t n = 0; n < N; ++n) {
         int64_t i = L.iperm[n];
         for (int d = 0; d < 3; ++d) L.xyz[3 * n + d] = p.xyz[3 * i + d];
-        L.nflag[n] = (uint32_t)b.nmat[i] | (b.fixed[i] ? NODE_FIXED : 0u) | (has_bc(i) ? NODE_BC : 0u);
+        L.nflag[n] = (uint32_t)b.nmat[i] | (b.fixed[i] ? NODE_FIXED : 0u) | (has_bc(i) ? NODE_BC : 0u) |
+                     (!L.xtra.empty() && L.xtra[n] ? NODE_XTRA : 0u);
         L.m[n] = b.m[i];
         L.T_init[n] = b.T_init[i];
     }

@@ -32,8 +32,12 @@ struct Problem {
     int32_t scen_of_mat(int32_t m) const { return mat_scen.empty() ? 0 : mat_scen[m]; }
 };
 
-// node flag bits stored next to the material id
-enum : uint32_t { NODE_FIXED = 1u << 31, NODE_BC = 1u << 30, NODE_MAT_MASK = 0xFFFFu };
+// node flag bits stored next to the material id; NODE_XTRA: a shared node in
+// more than PARTIAL_SLOTS blocks (it has partials beyond the slot-major ones)
+enum : uint32_t { NODE_FIXED = 1u << 31, NODE_BC = 1u << 30, NODE_XTRA = 1u << 29, NODE_MAT_MASK = 0xFFFFu };
+
+// partial residuals per shared node held slot-major (the rest go to a list)
+constexpr int PARTIAL_SLOTS = 4;
 
 struct BlockInfo {        // one LDS element block (8 ints, 32 bytes)
     int32_t e_begin;      // first element of the block (blocked element order)
@@ -77,8 +81,12 @@ struct Layout {
     std::vector<int32_t> seg_scen;    // n_seg
     std::vector<int32_t> sh_list;     // per block: global ids of its shared nodes
     std::vector<uint16_t> lconn;      // per element: local ids in its block
-    std::vector<int32_t> comb_ptr;    // per shared node: its partials are [comb_ptr[s], comb_ptr[s+1])
+    // partials of shared node s: slot j < PARTIAL_SLOTS at j * nsh + s, the
+    // others at PARTIAL_SLOTS * nsh + [comb_ptr[s], comb_ptr[s+1]), all in block order
+    std::vector<int32_t> comb_ptr;
     std::vector<int32_t> sh_pos;      // per sh_list entry: where that block writes its partial
+    int64_t n_partial_slots = 0;      // size of the partial array (unused slots hold zero)
+    std::vector<uint8_t> xtra;        // per node (final numbering): NODE_XTRA
     int64_t max_local = 0;
     // report
     double dt_bound = 0;

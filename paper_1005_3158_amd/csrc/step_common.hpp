@@ -24,6 +24,45 @@ __device__ __forceinline__ int xcd_remap(int w, int n) {
     return x * q + min(x, rem) + i;
 }
 
+// Node coordinates of the FP32 kernels are fixed-point integers carried in
+// the float bits of x, y and z (Dev::x_scale metres per unit, a power of two
+// chosen so that no element spans 2^24 units or more).  An element takes them
+// relative to its node 0: integer differences are exact, and so is their
+// conversion to float, so every edge carries the fixed-point resolution
+// (about 1e-7 of a typical edge) instead of the FP32 rounding of absolute
+// coordinates (about 1e-5 of an edge on a 128^3 grid of the domain, a
+// systematic error of the conduction operator).  The element formulas depend
+// on coordinate differences only.
+//   local_units: coordinates in units.  The residual -K^e T^e of a linear
+//     element scales with length, so the caller multiplies the conductivity
+//     by x_scale instead of every coordinate.
+//   local_coords: coordinates in metres (for formulas with volumes).
+// FP64 coordinates are plain metres (x_scale = 1) and stay as they are.
+template <int NEN>
+__device__ __forceinline__ void local_units(float4 *p) {
+    const int x0 = __float_as_int(p[0].x), y0 = __float_as_int(p[0].y), z0 = __float_as_int(p[0].z);
+#pragma unroll
+    for (int a = 0; a < NEN; ++a) {
+        p[a].x = (float)(__float_as_int(p[a].x) - x0);
+        p[a].y = (float)(__float_as_int(p[a].y) - y0);
+        p[a].z = (float)(__float_as_int(p[a].z) - z0);
+    }
+}
+template <int NEN>
+__device__ __forceinline__ void local_units(double4 *) {}
+template <int NEN>
+__device__ __forceinline__ void local_coords(float4 *p, float scale) {
+    local_units<NEN>(p);
+#pragma unroll
+    for (int a = 0; a < NEN; ++a) {
+        p[a].x *= scale;
+        p[a].y *= scale;
+        p[a].z *= scale;
+    }
+}
+template <int NEN>
+__device__ __forceinline__ void local_coords(double4 *, float) {}
+
 // round(r * scale) as a two's-complement integer via the 1.5 * 2^52 shift
 __device__ __forceinline__ long long fx_from(float r, double scale) {
     const double magic = 6755399441055744.0;
@@ -64,35 +103,55 @@ __device__ __forceinline__ double h_of_t(const MatDev &M, double T) {
 }
 
 // Enthalpy update of a free node g with residual r: H += dt r / m (FP32: two-sum
-// into the (hi, lo) pair), then T and f_s from H in FP64.
+// into the (hi, lo) pair), then T and f_s from H in FP64.  update() does it in
+// one go; load() and store() split it, so that a thread can issue the loads of
+// several nodes before it waits for the first.
 template <class R> struct NodeH;
 template <> struct NodeH<float> {
-    static __device__ __forceinline__ void update(const Dev &d, const MatDev &M, int64_t g, float r, float *Tn) {
-        float2 *H = (float2 *)d.H;
-        const float im = ((const float *)d.inv_m)[g];
+    struct Pre {
+        float2 h;
+        float im;
+    };
+    static __device__ __forceinline__ Pre load(const Dev &d, int64_t g) {
+        return Pre{((const float2 *)d.H)[g], ((const float *)d.inv_m)[g]};
+    }
+    static __device__ __forceinline__ void store(const Dev &d, const MatDev &M, int64_t g, const Pre &p, float r,
+                                                 float *Tn) {
         float inc;
         {
 #pragma clang fp contract(off)
-            inc = r * (M.dtf * im);
+            inc = r * (M.dtf * p.im);
         }
-        const float2 h = kahan_add(H[g], inc);
-        H[g] = h;
+        const float2 h = kahan_add(p.h, inc);
+        ((float2 *)d.H)[g] = h;
         double T, fs;
         t_of_h(M, (double)h.x + (double)h.y, T, fs);
         Tn[g] = (float)T;
         ((float *)d.fs)[g] = (float)fs;
     }
+    static __device__ __forceinline__ void update(const Dev &d, const MatDev &M, int64_t g, float r, float *Tn) {
+        store(d, M, g, load(d, g), r, Tn);
+    }
 };
 template <> struct NodeH<double> {
-    static __device__ __forceinline__ void update(const Dev &d, const MatDev &M, int64_t g, double r, double *Tn) {
-        double *H = (double *)d.H;
-        const double im = ((const double *)d.inv_m)[g];
-        const double h = H[g] + r * (M.dt * im);
-        H[g] = h;
+    struct Pre {
+        double h;
+        double im;
+    };
+    static __device__ __forceinline__ Pre load(const Dev &d, int64_t g) {
+        return Pre{((const double *)d.H)[g], ((const double *)d.inv_m)[g]};
+    }
+    static __device__ __forceinline__ void store(const Dev &d, const MatDev &M, int64_t g, const Pre &p, double r,
+                                                 double *Tn) {
+        const double h = p.h + r * (M.dt * p.im);
+        ((double *)d.H)[g] = h;
         double T, fs;
         t_of_h(M, h, T, fs);
         Tn[g] = T;
         ((double *)d.fs)[g] = fs;
+    }
+    static __device__ __forceinline__ void update(const Dev &d, const MatDev &M, int64_t g, double r, double *Tn) {
+        store(d, M, g, load(d, g), r, Tn);
     }
 };
 
@@ -112,6 +171,36 @@ __device__ __forceinline__ double boundary_terms(const Dev &d, int64_t s, R Ti, 
     const R *w = (const R *)d.link_w;
     for (int32_t k = l0; k < l1; ++k) r += w[k] * (Tc[d.link_node[k]] - Ti);
     return q;
+}
+
+// Sum of the residual partials of the blocked layout's shared node s (slot s of
+// the node kernels) with flags f: the PARTIAL_SLOTS slot-major partials (zero
+// where the node is in fewer blocks), then, for a node flagged NODE_XTRA, the
+// rest from its list; left to right in block order.  The slot loads depend on
+// s only, so they issue together with the node's other loads.
+template <class R>
+__device__ __forceinline__ R partial_slots(const Dev &d, const R *P, int64_t s) {
+    const int64_t nsh = d.N - d.n_private;
+    R p[PARTIAL_SLOTS];
+#pragma unroll
+    for (int j = 0; j < PARTIAL_SLOTS; ++j) p[j] = P[j * nsh + s];
+    R r = p[0];
+#pragma unroll
+    for (int j = 1; j < PARTIAL_SLOTS; ++j) r += p[j];
+    return r;
+}
+template <class R>
+__device__ __forceinline__ R partial_extras(const Dev &d, const R *P, int64_t s, uint32_t f, R r) {
+    if (f & NODE_XTRA) {
+        const R *X = P + PARTIAL_SLOTS * (d.N - d.n_private);
+        const int32_t k0 = d.comb_ptr[s], k1 = d.comb_ptr[s + 1];
+        for (int32_t k = k0; k < k1; ++k) r += X[k];
+    }
+    return r;
+}
+template <class R>
+__device__ __forceinline__ R combine_partials(const Dev &d, const R *P, int64_t s, uint32_t f) {
+    return partial_extras(d, P, s, f, partial_slots(d, P, s));
 }
 
 // material tables of at most LDS_MATS rows are read from LDS, larger ones from

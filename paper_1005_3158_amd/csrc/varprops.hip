@@ -131,7 +131,8 @@ __global__ __launch_bounds__(1024) void k_block_var(VarDev v, int parity) {
             k = tab_eval(ktab[m], tsum * R(1.0 / NEN));
         }
         R re[NEN];
-        elem_residual<R, NEN>(p, k, re);
+        step::local_units<NEN>(p);
+        elem_residual<R, NEN>(p, k * d.x_scale, re);   // k per unit length of the element coordinates
         if constexpr (std::is_same<R, float>::value) {
             long long q[NEN];
             long long sum = 0;
@@ -191,9 +192,7 @@ __global__ __launch_bounds__(NODE_THREADS) void k_nodes_var(VarDev v, int parity
     const uint32_t f = d.flags[g];
     const MatDev &M = mats[f & NODE_MAT_MASK];
     const R *P = (const R *)d.partials;
-    const int32_t k0 = d.comb_ptr[s], k1 = d.comb_ptr[s + 1];
-    R r = P[k0];                              // every shared node has a partial
-    for (int32_t k = k0 + 1; k < k1; ++k) r += P[k];
+    R r = step::combine_partials(d, P, s, f);
     double q = 0.0;
     if (f & NODE_BC) {
         const R Ti = Tc[g];
