@@ -23,13 +23,13 @@ namespace {
 enum SBuf {
     S_NBR_PTR, S_NBR, S_INV_DEG, S_COEF, S_PARAMS, S_GRADS, S_ADAM_M, S_ADAM_V, S_WBF, S_X, S_ZIN, S_U, S_Z,
     S_HL, S_Y, S_BASE, S_SCALE, S_TARGET, S_DH, S_DZ, S_DU, S_PARTIALS, S_LOSS, S_IDX, S_PARTIALS2, S_DY, S_H0, S_H1, S_H2, S_HN, S_REXT, S_QSAVE, S_CHECK,
-    S_SCEN, S_SCEN_SEG_PTR, S_SCEN_SEG, S_SEG_PART, S_SCEN_SUM, S_COUNT
+    S_SCEN, S_SCEN_SEG_PTR, S_SCEN_SEG, S_SEG_PART, S_SCEN_SUM, S_H2_PAIR, S_COUNT
 };
 const char *const SBUF_NAMES[S_COUNT] = {"nbr_ptr", "nbr", "inv_deg", "coef", "params", "grads", "adam_m",
                                          "adam_v", "weights_bf16", "X", "Z_in", "U", "Z", "H_last", "y",
                                          "base", "scale", "target", "dH", "dZ", "dU", "partials", "loss_part",
                                          "sample_idx", "partials2", "dy", "H0", "H1", "H2", "H_pred", "r_ext", "q_saved", "check", "scenario",
-                                         "scen_seg_ptr", "scen_seg", "seg_part", "scen_sum"};
+                                         "scen_seg_ptr", "scen_seg", "seg_part", "scen_sum", "H2_pair"};
 
 // counter-based generator (SplitMix64 of seed and counter) for the
 // initial parameters and the sample shuffles
@@ -108,6 +108,10 @@ void sur_sizes(fem_sur *s) {
     z[S_HN] = N * 8;
     z[S_REXT] = N * 8;
     z[S_QSAVE] = s->ctx->L().n_inflow * 8;
+    // FP32 state: the raw (hi, lo) enthalpy pairs at H2, so that a rejected jump
+    // returns to exactly that state (hi + lo can need more than the 53 bits of
+    // the FP64 copy in H2)
+    z[S_H2_PAIR] = s->ctx->opt.precision == FEM_PREC_FP64 ? 0 : N * 8;
     z[S_CHECK] = 2 * check_blocks(N) * 4;
     z[S_SCEN] = N * 4;
     z[S_SCEN_SEG_PTR] = (s->n_scen + 1) * 4;
@@ -268,6 +272,7 @@ void fill_surdev(fem_sur *s) {
     d.H0 = (double *)s->ptr[S_H0];
     d.H1 = (double *)s->ptr[S_H1];
     d.H2 = (double *)s->ptr[S_H2];
+    d.H2_pair = (float2 *)s->ptr[S_H2_PAIR];
     d.Hn = (double *)s->ptr[S_HN];
     d.rext = (double *)s->ptr[S_REXT];
     d.check = (int32_t *)s->ptr[S_CHECK];
@@ -341,7 +346,7 @@ void enqueue_jump(fem_sur *s, int p, bool cont, float fs_tol, float verify_tol) 
     HIPCHECK(enqueue_step(c->dev, q, st, nullptr));
     q ^= 1;
     // H2, and the inflow sums at H2 for a fallback to start from
-    HIPCHECK(state_to_f64(c->dev, s->d.H2, c->L().n_inflow ? (double *)s->ptr[S_QSAVE] : nullptr, st));
+    HIPCHECK(state_to_f64(c->dev, s->d.H2, c->L().n_inflow ? (double *)s->ptr[S_QSAVE] : nullptr, st, s->d.H2_pair));
     HIPCHECK(features(s->d, cont ? s->d.Hn : s->d.H0, s->d.H1, s->d.H2, 1, nullptr, s->N, nullptr, 1, st));
     HIPCHECK(forward(s->d, s->N, 0, 0, st));
     HIPCHECK(write_jump(s->d, c->dev, q, fs_tol, st));
@@ -767,7 +772,7 @@ int fem_sur_generate(fem_sur *s, const double *dt_per_scenario, int64_t n_chunks
             HIPCHECK(state_to_f64(ctx->dev, s->d.H1, nullptr, st));
             run_steps(ctx, 1);
             HIPCHECK(state_to_f32(ctx->dev, S + 2 * N, st));
-            HIPCHECK(state_to_f64(ctx->dev, s->d.H2, nullptr, st));
+            HIPCHECK(state_to_f64(ctx->dev, s->d.H2, nullptr, st, s->d.H2_pair));
             run_steps(ctx, H - 2);
             HIPCHECK(state_to_f32(ctx->dev, S + 3 * N, st));
             clock(H);

@@ -611,7 +611,7 @@ __global__ void k_apply(SurDev s, int64_t R, double *H) {
 // the state's enthalpy into out; with keep, also the node inflow sums into keep
 // (the state a rejected jump returns to)
 template <class OUT>
-__global__ __launch_bounds__(256) void k_state_out(Dev d, OUT *out, double *keep) {
+__global__ __launch_bounds__(256) void k_state_out(Dev d, OUT *out, double *keep, float2 *pair_out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (keep && i < d.n_inflow) keep[i] = d.qnode[i];
     if (i >= d.N) return;
@@ -621,6 +621,7 @@ __global__ __launch_bounds__(256) void k_state_out(Dev d, OUT *out, double *keep
     } else {
         const float2 v = ((const float2 *)d.H)[i];
         h = (double)v.x + (double)v.y;
+        if (pair_out) pair_out[i] = v;
     }
     out[i] = (OUT)h;
 }
@@ -677,7 +678,18 @@ __global__ __launch_bounds__(256) void k_restore(SurDev s, Dev d, int parity, co
     if (i >= d.N) return;
     const uint32_t f = d.flags[i];
     if (f & NODE_FIXED) return;
-    set_node<R>(d, i, d.mats[f & NODE_MAT_MASK], s.H2[i], (R *)d.T + parity * d.N);
+    const MatDev &M = d.mats[f & NODE_MAT_MASK];
+    if (sizeof(R) == 4 && s.H2_pair) {
+        // the saved pair itself, with T and f_s evaluated as the step does
+        const float2 v = s.H2_pair[i];
+        ((float2 *)d.H)[i] = v;
+        double T, fs;
+        t_of_h(M, (double)v.x + (double)v.y, T, fs);
+        ((R *)d.T)[parity * d.N + i] = (R)T;
+        ((R *)d.fs)[i] = (R)fs;
+    } else {
+        set_node<R>(d, i, M, s.H2[i], (R *)d.T + parity * d.N);
+    }
 }
 
 template <class R>
@@ -801,14 +813,15 @@ hipError_t apply(const SurDev &s, int64_t R, double *H_out, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t state_to_f64(const Dev &d, double *out, double *keep_qnode, hipStream_t st) {
+hipError_t state_to_f64(const Dev &d, double *out, double *keep_qnode, hipStream_t st, float2 *pair_out) {
     const int64_t n = keep_qnode ? std::max<int64_t>(d.N, d.n_inflow) : d.N;
-    hipLaunchKernelGGL(k_state_out<double>, dim3(grid_for(n, 256)), dim3(256), 0, st, d, out, keep_qnode);
+    hipLaunchKernelGGL(k_state_out<double>, dim3(grid_for(n, 256)), dim3(256), 0, st, d, out, keep_qnode, pair_out);
     return hipGetLastError();
 }
 
 hipError_t state_to_f32(const Dev &d, float *out, hipStream_t st) {
-    hipLaunchKernelGGL(k_state_out<float>, dim3(grid_for(d.N, 256)), dim3(256), 0, st, d, out, (double *)nullptr);
+    hipLaunchKernelGGL(k_state_out<float>, dim3(grid_for(d.N, 256)), dim3(256), 0, st, d, out, (double *)nullptr,
+                       (float2 *)nullptr);
     return hipGetLastError();
 }
 

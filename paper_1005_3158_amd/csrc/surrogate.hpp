@@ -104,6 +104,7 @@ struct SurDev {
     double *loss_part = nullptr;          // per workgroup loss partials
     // jumps of the solver state
     double *H0 = nullptr, *H1 = nullptr, *H2 = nullptr;  // N: the three explicit states a jump starts from
+    float2 *H2_pair = nullptr;            // N (FP32 state): the enthalpy pairs at H2, bit for bit (null in FP64)
     double *Hn = nullptr;                 // N: the predicted state (the next chunk's H0)
     double *rext = nullptr;               // N: increment the extrapolation expects one step past the horizon
     int32_t *check = nullptr;             // 2 x per workgroup: nodes whose f_s fell; nodes failing the verification
@@ -129,7 +130,9 @@ hipError_t apply(const SurDev &s, int64_t rows, double *H_out, hipStream_t st); 
 
 // solver state <-> surrogate (d: the context's device layout, T buffer `parity`)
 // (keep_qnode, if not null: also the per-node inflow sums, d.n_inflow doubles)
-hipError_t state_to_f64(const Dev &d, double *out, double *keep_qnode, hipStream_t st);
+// FP64 copy of the enthalpy state into out (and of the inflow sums into
+// keep_qnode, and of the raw FP32 pairs into pair_out, when not null)
+hipError_t state_to_f64(const Dev &d, double *out, double *keep_qnode, hipStream_t st, float2 *pair_out = nullptr);
 hipError_t state_to_f32(const Dev &d, float *out, hipStream_t st);
 // write H = base + scale * (y - the scenario's weighted mean of y) (one state slot,
 // unprojected y) into the solver state with its T and fraction solid; counts
