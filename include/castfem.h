@@ -250,6 +250,20 @@ int fem_stable_dt(const fem_ctx *ctx, double *dt);
 /* n_steps explicit steps of size dt (Eq. 14 in enthalpy form), enqueued on the
  * stream; repeated calls reuse a captured hipGraph. */
 int fem_step(fem_ctx *ctx, double dt, int64_t n_steps);
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): fem_step without any
+ * allocation.  Every launch is enqueued eagerly (no graph is built), a new dt
+ * is written into the device material table by a kernel, and the partial
+ * residuals of the shared nodes live in the library's static device scratch
+ * of 32 MiB (file-scope, one copy per GPU, kept until the process ends)
+ * instead of the bound `partials` buffer; each call clears the part it uses
+ * with a fill kernel.  Results are those of fem_step bit for bit.  All calls
+ * on one GPU share that scratch: calls that overlap on one GPU (two streams,
+ * two threads) race.  Enthalpy form, one scenario and the LDS-blocked scatter
+ * only (else FEM_E_UNSUPPORTED); a mesh needing more than 32 MiB of partials
+ * (about 4 * shared nodes * 4 bytes in FP32) is refused with FEM_E_UNSUPPORTED.
+ * Other errors as fem_step. */
+int fem_step_no_alloc(fem_ctx *ctx, double dt, int64_t n_steps);
 /* Stability bound of every scenario (n_scen doubles). */
 int fem_stable_dt_scenarios(const fem_ctx *ctx, double *dt_bounds);
 /* n_steps steps of every scenario at once, scenario s with its own dt

@@ -35,7 +35,7 @@ def lds_for_nodes(nodes, precision=FEM_PREC_FP32_KAHAN, apparent=False):
 EXPORTS = [
     "fem_create", "fem_destroy", "fem_last_error", "fem_set_stream", "fem_upload_mesh", "fem_set_materials",
     "fem_set_dirichlet", "fem_set_flux_faces", "fem_set_interface", "fem_set_initial_T", "fem_finalize",
-    "fem_query_buffers", "fem_bind_buffers", "fem_get_report", "fem_stable_dt", "fem_step", "fem_read_T",
+    "fem_query_buffers", "fem_bind_buffers", "fem_get_report", "fem_stable_dt", "fem_step", "fem_step_no_alloc", "fem_read_T",
     "fem_read_fs", "fem_read_H", "fem_energy", "fem_read_state", "fem_write_state", "fem_get_node_perm",
     "fem_time_kernels", "fem_copy_kernel", "fem_copy_kernel_nt", "fem_set_scenarios", "fem_stable_dt_scenarios", "fem_step_batch",
     "fem_energy_scenarios", "fem_sur_create", "fem_sur_destroy", "fem_sur_query_buffers", "fem_sur_bind_buffers",
@@ -138,6 +138,7 @@ def lib():
             "fem_set_interface": [vp, i64, vp, vp, vp], "fem_set_initial_T": [vp, vp],
             "fem_finalize": [vp, vp], "fem_query_buffers": [vp, vp, vp], "fem_bind_buffers": [vp, vp, i32],
             "fem_get_report": [vp, vp], "fem_stable_dt": [vp, vp], "fem_step": [vp, dp, i64],
+            "fem_step_no_alloc": [vp, dp, i64],
             "fem_read_T": [vp, vp], "fem_read_fs": [vp, vp], "fem_read_H": [vp, vp], "fem_energy": [vp, vp],
             "fem_read_state": [vp, vp, vp], "fem_write_state": [vp, vp, i64], "fem_get_node_perm": [vp, vp],
             "fem_time_kernels": [vp, dp, i64, vp], "fem_copy_kernel": [vp, vp, vp, i64, i32, vp],
@@ -309,6 +310,10 @@ def fem_stable_dt(ctx):
 
 def fem_step(ctx, dt, n_steps):
     _call("fem_step", ctx, float(dt), int(n_steps))
+
+
+def fem_step_no_alloc(ctx, dt, n_steps):
+    _call("fem_step_no_alloc", ctx, float(dt), int(n_steps))
 
 
 def _read(name, ctx, n):

@@ -878,6 +878,11 @@ int fem_bind_buffers(fem_ctx *ctx, void *const *dev_ptrs, int32_t n) {
         ctx->cands.push_back(std::move(keep));
         ctx->chosen = 0;
         fill_dev(ctx, ctx->cands[0]);
+        // the whole material table on the device (dt = 0 until a step sets it):
+        // fem_step_no_alloc updates only its time-step fields
+        for (size_t q = 0; q < ctx->prob.mats.size(); ++q) ctx->mats_host[q] = make_mat(ctx->prob.mats[q], 0.0);
+        h2d(ctx, B_MATS, ctx->mats_host.data(), (int64_t)(ctx->mats_host.size() * sizeof(MatDev)));
+        HIPCHECK(hipStreamSynchronize(ctx->stream));
         ctx->stage = ST_BOUND;
     });
 }
@@ -898,6 +903,46 @@ int fem_step(fem_ctx *ctx, double dt, int64_t n_steps) {
             throw PrepError{FEM_E_UNSTABLE, "dt " + std::to_string(dt) + " above the stability bound " + std::to_string(ctx->base.dt_bound)};
         set_dt(ctx, dt);
         run_steps(ctx, n_steps);
+        ctx->steps += n_steps;
+        for (double &t : ctx->time_s) t += dt * (double)n_steps;
+    });
+}
+
+int fem_step_no_alloc(fem_ctx *ctx, double dt, int64_t n_steps) {
+    if (!ctx) return set_err(FEM_E_INVALID_ARG, "ctx is null");
+    return guarded([&] {
+        check_bound(ctx, ST_BOUND);
+        if (!(dt > 0) || !std::isfinite(dt) || n_steps < 0) throw PrepError{FEM_E_INVALID_ARG, "dt must be > 0 and n_steps >= 0"};
+        if (dt > ctx->base.dt_bound && !ctx->opt.allow_unstable)
+            throw PrepError{FEM_E_UNSTABLE, "dt " + std::to_string(dt) + " above the stability bound " + std::to_string(ctx->base.dt_bound)};
+        if (ctx->apparent() || ctx->variable() || ctx->prob.n_scen != 1 || ctx->opt.scatter != FEM_SCATTER_LDS_BLOCKED)
+            throw PrepError{FEM_E_UNSUPPORTED, "fem_step_no_alloc: enthalpy form, one scenario, LDS-blocked scatter"};
+        const Layout &L = ctx->L();
+        const int64_t bytes = L.n_partial_slots * (int64_t)ctx->rsize();
+        if (bytes > SCRATCH_BYTES)
+            throw PrepError{FEM_E_UNSUPPORTED, "fem_step_no_alloc: the mesh needs " + std::to_string(bytes) +
+                                                   " bytes of partial residuals; the static scratch holds " +
+                                                   std::to_string(SCRATCH_BYTES) + " (use fem_step)"};
+        HIPCHECK(hipSetDevice(ctx->opt.device));
+        void *sp = nullptr;
+        HIPCHECK(scratch_address(ctx->opt.device, &sp));
+        for (int b = 0; b < B_COUNT; ++b)
+            if (ctx->ptr[b] && (char *)ctx->ptr[b] < (char *)sp + SCRATCH_BYTES && (char *)sp < (char *)ctx->ptr[b] + ctx->sizes[b])
+                throw PrepError{FEM_E_HIP, std::string("internal: the static scratch overlaps buffer ") + BUF_NAMES[b]};
+        // slots a shared node has no block for must read zero: clear the region
+        // this mesh uses (the last call on this GPU, of any context, left its own)
+        HIPCHECK(enqueue_zero(sp, bytes, ctx->stream));
+        if (ctx->dt_s.size() != 1 || ctx->dt_s[0] != dt) {
+            HIPCHECK(enqueue_set_dt((MatDev *)ctx->ptr[B_MATS], (int)ctx->prob.mats.size(), dt, ctx->stream));
+            for (size_t q = 0; q < ctx->mats_host.size(); ++q) ctx->mats_host[q] = make_mat(ctx->prob.mats[q], dt);
+            ctx->dt_s.assign(1, dt);
+        }
+        Dev d = ctx->dev;
+        d.partials = sp;
+        for (int64_t k = 0; k < n_steps; ++k) {
+            HIPCHECK(enqueue_step(d, ctx->parity, ctx->stream, nullptr));
+            ctx->parity ^= 1;
+        }
         ctx->steps += n_steps;
         for (double &t : ctx->time_s) t += dt * (double)n_steps;
     });

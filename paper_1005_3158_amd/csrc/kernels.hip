@@ -22,6 +22,7 @@
 
 #include <cfloat>
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 
 #include "elem.hpp"
@@ -520,6 +521,60 @@ hipError_t enqueue_copy_nt(void *dst, const void *src, int64_t n16, hipStream_t 
     const int64_t want = (n16 + 4 * 256 - 1) / (4 * 256);
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, 32768));
     hipLaunchKernelGGL(k_copy_nt, dim3(grid), dim3(256), 0, s, (v4f *)dst, (const v4f *)src, n16);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ allocation-free stepping
+// The partial residuals of fem_step_no_alloc live in this file-scope device
+// array: every GPU the library runs on holds its own copy until the process
+// ends, and every call on that GPU shares it.  Host code never uses the
+// array's name as an address; scratch_address() resolves it once per device.
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+
+namespace {
+
+__global__ __launch_bounds__(256) void k_zero(uint4 *__restrict__ p, int64_t n16) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride) p[i] = make_uint4(0, 0, 0, 0);
+}
+
+__global__ void k_set_dt(MatDev *m, int n, double dt) {
+    for (int q = threadIdx.x; q < n; q += blockDim.x) {
+        m[q].dt = dt;
+        m[q].dtf = (float)dt;
+    }
+}
+
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mutex;
+void *scratch_ptrs[MAX_DEVICES] = {};
+
+}  // namespace
+
+hipError_t scratch_address(int device, void **out) {
+    if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(scratch_mutex);
+    if (!scratch_ptrs[device]) {
+        // the device must be current: each GPU has its own copy of the array
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        scratch_ptrs[device] = p;
+    }
+    *out = scratch_ptrs[device];
+    return hipSuccess;
+}
+
+hipError_t enqueue_zero(void *p, int64_t bytes, hipStream_t s) {
+    const int64_t n16 = (bytes + 15) / 16;
+    if (n16 == 0) return hipSuccess;
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n16 + 255) / 256, 4096));
+    hipLaunchKernelGGL(k_zero, dim3(grid), dim3(256), 0, s, (uint4 *)p, n16);
+    return hipGetLastError();
+}
+
+hipError_t enqueue_set_dt(MatDev *mats, int n, double dt, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_dt, dim3(1), dim3(64), 0, s, mats, n, dt);
     return hipGetLastError();
 }
 

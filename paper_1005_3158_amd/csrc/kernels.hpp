@@ -86,6 +86,15 @@ hipError_t set_block_lds_limit(int prec, int nen, size_t bytes);
 hipError_t enqueue_copy(void *dst, const void *src, int64_t n16, hipStream_t s);
 // The same with non-temporal loads and stores and up to 32,768 workgroups.
 hipError_t enqueue_copy_nt(void *dst, const void *src, int64_t n16, hipStream_t s);
+
+// Allocation-free stepping: bytes of the library's static device scratch (the
+// partial residuals of fem_step_no_alloc), its address on `device` (which must
+// be current; resolved once per device), a zero fill and a dt update of the
+// material table by kernels (no copy, no allocation).
+constexpr int64_t SCRATCH_BYTES = 32ll << 20;
+hipError_t scratch_address(int device, void **out);
+hipError_t enqueue_zero(void *p, int64_t bytes, hipStream_t s);
+hipError_t enqueue_set_dt(MatDev *mats, int n, double dt, hipStream_t s);
 // Copy check counts, diagnostics and inflow sums into page-locked host memory the device can write.
 hipError_t enqueue_stage(int32_t *dst_chk, const int32_t *chk, int64_t n_chk, double *dst_dg, const double *dg,
                          int64_t n_dg, double *dst_qn, const double *qn, int64_t n_qn, hipStream_t s);
