@@ -194,9 +194,9 @@ def main():
     golden = json.load(open(os.path.join(ROOT, "tests", "golden", "oracle_constants.json")))
     dt_ref = golden["config2"]["dt_bound"] if (args.n == 128 and not big) else None
     m = measure_step(prob, args, log, args.steps, args.warmup, "block_element_config5" if big else "block_element_config2",
-                     dt_ref)
+                     dt_ref, with_copy=True)
     s = m.pop("solver")
-    copy = copy_ceiling(s.ctx, log)
+    copy = m.pop("copy")
 
     # parity spot check and CPU baseline: the FP64 oracle over the first steps, on one
     # core (the oracle as it is) and over all host cores (its multi-threaded run)
@@ -247,6 +247,7 @@ def main():
                                                            time.time() - t0))
         m5 = measure_step(p5, args, log, args.config5_steps, 16, "block_element_config5", None)
         m5.pop("solver").close()
+        m5.pop("copy")
         del p5
         m5["effective_frac_copy_ceiling"] = m5["effective_GBps"] / copy["ceiling_GBps"]
         m5["workload"] = ("256^3 jittered Kuhn tets (%d tets, %d nodes), eight seeded alloy boxes in sand mould, "
@@ -266,7 +267,7 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def measure_step(prob, args, log, steps, warmup, traffic_kind, dt_ref):
+def measure_step(prob, args, log, steps, warmup, traffic_kind, dt_ref, with_copy=False):
     """Set up one mesh, time `steps` explicit steps after `warmup` (inputs resident
     in HBM, the step graph built before the timed region), and time the kernels of
     one step with HIP events on the solver stream.  Returns the figures and the
@@ -295,6 +296,13 @@ def measure_step(prob, args, log, steps, warmup, traffic_kind, dt_ref):
             raise SystemExit("stability bound %.17g differs from the oracle's %.17g" % (dt_bound, dt_ref))
         dt_bound = dt_ref
     dt = 0.9 * dt_bound
+    # untimed work first: the kernel durations (HIP events on the solver stream over
+    # eager steps) and the copy ceiling, which also bring the GPU to its steady clocks
+    kt = cf.fem_time_kernels(s.ctx, dt, args.profile_steps)
+    ach_e = kt["bytes_element"] / (kt["ms_element"] * 1e-3) / 1e9
+    ach_c = kt["bytes_combine"] / (kt["ms_combine"] * 1e-3) / 1e9 if kt["ms_combine"] > 0 else None
+    log("element kernel %.4f ms (%.1f GB/s alg), node kernel %.4f ms" % (kt["ms_element"], ach_e, kt["ms_combine"]))
+    copy = copy_ceiling(s.ctx, log) if with_copy else None
     s.step(dt, warmup)          # the first call also builds the step graph
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -306,12 +314,11 @@ def measure_step(prob, args, log, steps, warmup, traffic_kind, dt_ref):
     eff = b_alg * steps / t_run / 1e9
     log("steps %d in %.4f s: %.4f ms/step, %.4g element-steps/s, effective %.1f GB/s; energy residual %.2e"
         % (steps, t_run, 1e3 * t_run / steps, E * steps / t_run, eff, en["residual"]))
-    kt = cf.fem_time_kernels(s.ctx, dt, args.profile_steps)
-    ach_e = kt["bytes_element"] / (kt["ms_element"] * 1e-3) / 1e9
-    ach_c = kt["bytes_combine"] / (kt["ms_combine"] * 1e-3) / 1e9 if kt["ms_combine"] > 0 else None
-    log("element kernel %.4f ms (%.1f GB/s alg), node kernel %.4f ms" % (kt["ms_element"], ach_e, kt["ms_combine"]))
     traffic = load_traffic(traffic_kind, rep["max_local_nodes"])
+    node_kind = traffic_kind.replace("block_element", "node_combine")
+    traffic_nodes = load_traffic(node_kind, rep["max_local_nodes"])
     return {
+        "copy": copy,
         "solver": s, "n_elems": E, "n_nodes": N, "dt": dt, "block_nodes": rep["max_local_nodes"],
         "n_blocks": rep["n_blocks"], "shared_fraction": rep["shared_fraction"], "setup_s": t_setup,
         "value": E * steps / t_run, "ms_per_step": 1e3 * t_run / steps,
@@ -326,7 +333,8 @@ def measure_step(prob, args, log, steps, warmup, traffic_kind, dt_ref):
             "ms_per_launch": kt["ms_element"],
             "alg_bytes_per_launch": kt["bytes_element"],
             "node_kernel": {"ms_per_launch": kt["ms_combine"], "alg_bytes_per_launch": kt["bytes_combine"],
-                            "achieved": ach_c},
+                            "achieved": ach_c, "traffic": traffic_nodes,
+                            "traffic_GBps": traffic_nodes / (kt["ms_combine"] * 1e-3) / 1e9 if traffic_nodes else None},
         },
     }
 

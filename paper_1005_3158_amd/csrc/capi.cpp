@@ -422,6 +422,7 @@ void set_dt_scen(fem_ctx *c, const std::vector<double> &dt) {
 void set_dt(fem_ctx *c, double dt) { set_dt_scen(c, std::vector<double>(c->prob.n_scen, dt)); }
 
 void eager_steps(fem_ctx *c, int64_t n) {
+    if (n > 0) c->diag_fresh = false;
     for (int64_t s = 0; s < n; ++s) {
         HIPCHECK(enqueue_ctx_step(c, c->parity, c->stream, nullptr));
         c->parity ^= 1;
@@ -433,6 +434,9 @@ void build_graph(fem_ctx *c) {
     HIPCHECK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     hipError_t err = hipSuccess;
     for (int s = 0; s < GRAPH_STEPS && err == hipSuccess; ++s) err = enqueue_ctx_step(c, s & 1, c->stream, nullptr);
+    // every GRAPH_STEPS steps the FP64 state reductions of the energy balance
+    // (E, latent heat left, T range, liquid and non-finite counts per segment)
+    if (err == hipSuccess) err = enqueue_state_diag(c->dev, 0, c->stream);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(c->stream, &g);
     HIPCHECK(err);
@@ -457,6 +461,7 @@ void run_steps(fem_ctx *c, int64_t n) {
         --n;
     }
     for (int64_t r = 0; r < n / GRAPH_STEPS; ++r) HIPCHECK(hipGraphLaunch(c->gexec, c->stream));
+    if (n >= GRAPH_STEPS) c->diag_fresh = true;
     eager_steps(c, n % GRAPH_STEPS);
 }
 
@@ -822,6 +827,7 @@ int fem_bind_buffers(fem_ctx *ctx, void *const *dev_ptrs, int32_t n) {
         HIPCHECK(hipSetDevice(ctx->opt.device));
         for (int b = 0; b < B_COUNT; ++b) ctx->ptr[b] = ctx->sizes[b] ? dev_ptrs[b] : nullptr;
         reset_graph(ctx);
+        ctx->diag_fresh = false;
         if (ctx->opt.scatter == FEM_SCATTER_LDS_BLOCKED) {
             hipDeviceProp_t prop;
             HIPCHECK(hipGetDeviceProperties(&prop, ctx->opt.device));
@@ -937,6 +943,7 @@ int fem_step_no_alloc(fem_ctx *ctx, double dt, int64_t n_steps) {
             for (size_t q = 0; q < ctx->mats_host.size(); ++q) ctx->mats_host[q] = make_mat(ctx->prob.mats[q], dt);
             ctx->dt_s.assign(1, dt);
         }
+        ctx->diag_fresh = false;
         Dev d = ctx->dev;
         d.partials = sp;
         for (int64_t k = 0; k < n_steps; ++k) {
@@ -1069,7 +1076,7 @@ void energy_copies(fem_ctx *ctx, std::vector<double> &dg, std::vector<double> &q
 
 void energy_scenarios(fem_ctx *ctx, fem_energy_report *reps) {
     std::vector<double> dg, qn;
-    HIPCHECK(enqueue_state_diag(ctx->dev, ctx->parity, ctx->stream));
+    if (!ctx->diag_fresh) HIPCHECK(enqueue_state_diag(ctx->dev, ctx->parity, ctx->stream));
     energy_copies(ctx, dg, qn);
     HIPCHECK(hipStreamSynchronize(ctx->stream));
     HIPCHECK(hipGetLastError());
@@ -1263,6 +1270,7 @@ int fem_write_state(fem_ctx *ctx, const void *buf, int64_t bytes) {
         p += ctx->prob.n_scen * 8;
         std::memcpy(Qx_s.data(), p, ctx->prob.n_scen * 8);
         const int par = (int)h.parity;
+        ctx->diag_fresh = false;
         HIPCHECK(hipMemcpyAsync(ctx->ptr[B_H], H.data(), N * 8, hipMemcpyHostToDevice, ctx->stream));
         HIPCHECK(hipMemcpyAsync((char *)ctx->ptr[B_T] + par * N * R, T.data(), N * R, hipMemcpyHostToDevice,
                                 ctx->stream));
@@ -1291,6 +1299,7 @@ int fem_time_kernels(fem_ctx *ctx, double dt, int64_t n_steps, fem_kernel_times 
         if (n_steps <= 0 || n_steps > 100000) throw PrepError{FEM_E_INVALID_ARG, "n_steps must be in 1..100000"};
         if (!(dt > 0) || (dt > ctx->base.dt_bound && !ctx->opt.allow_unstable)) throw PrepError{FEM_E_UNSTABLE, "bad dt"};
         set_dt(ctx, dt);
+        ctx->diag_fresh = false;
         std::vector<hipEvent_t> ev(4 * n_steps);
         for (auto &e : ev) HIPCHECK(hipEventCreate(&e));
         for (int64_t s = 0; s < n_steps; ++s) {

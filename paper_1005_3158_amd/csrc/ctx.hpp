@@ -140,6 +140,10 @@ struct fem_ctx {
     std::vector<double> Qx_s;   // boundary inflow estimated over steps the surrogate jumped
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
+    // the device state diagnostics (`diag`) belong to the current state: the
+    // last state change was a graph of GRAPH_STEPS steps, whose last node
+    // reduces them (every other state change clears this)
+    bool diag_fresh = false;
     double setup_seconds = 0;
 
     Layout &L() { return cands[chosen].L; }

@@ -373,6 +373,7 @@ void drop_graph(fem_sur *s, int what, int p) {
 // run a chunk of kind `what` from parity p through a graph captured on first use
 void run_chunk(fem_sur *s, int what, int p, float fs_tol, float verify_tol) {
     fem_ctx *c = s->ctx;
+    c->diag_fresh = false;
     auto enqueue = [&] {
         if (what == CHUNK_FALLBACK) enqueue_fallback(s, p);
         else enqueue_jump(s, p, what == CHUNK_CONT, fs_tol, verify_tol);
@@ -779,6 +780,7 @@ int fem_sur_generate(fem_sur *s, const double *dt_per_scenario, int64_t n_chunks
             if (jump_every > 0 && k % jump_every == jump_every - 1) {
                 // continue from the network's jump instead of the explicit state
                 const int p = ctx->parity ^ (int)((H - 2) & 1);   // T parity at H2
+                ctx->diag_fresh = false;
                 HIPCHECK(restore_h2(s->d, ctx->dev, p, nullptr, st));
                 ctx->parity = p;
                 HIPCHECK(features(s->d, s->d.H0, s->d.H1, s->d.H2, 1, nullptr, N, nullptr, 1, st));
