@@ -125,6 +125,13 @@ def lib():
     """Load libcastfem.so; raise if it has not been built (there is no fallback path)."""
     global _lib
     if _lib is None:
+        # torch first: the process then holds torch's HIP runtime, which the
+        # library resolves to as well (loading the library first would bring in
+        # a second runtime, and torch's GPU calls then find no device)
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise ImportError("libcastfem.so is not built: run __graft_entry__.build() "
                               "(or python paper_1005_3158_amd/build.py)")

@@ -43,6 +43,8 @@ void layout_sizes(const fem_ctx *c, const Layout &L, int64_t *sz) {
         sz[B_PARTIALS] = L.n_partial_slots * R;
         sz[B_COMB_PTR] = (N - L.n_private + 1) * 4;
         sz[B_SH_POS] = np * 4;
+        // windows of the material table for the node kernel's workgroups (large tables only)
+        if ((int64_t)c->prob.mats.size() > MAT_WINDOW) sz[B_NODE_WIN] = node_grid(N - L.n_private) * 4;
         if (c->apparent()) {
             sz[B_CAP_PARTIALS] = L.n_partial_slots * R;
             sz[B_APP_MATS] = (int64_t)c->prob.mats.size() * (int64_t)sizeof(AppMat);
@@ -166,6 +168,7 @@ void upload_layout_t(fem_ctx *c, const Layout &L) {
     h2d(c, B_FLAGS, L.nflag.data(), N * 4);
     std::vector<R> rob(L.robin_a.size() * 2), lw(L.link_w.size());
     std::vector<BlockInfo> blocks_app;
+    std::vector<int32_t> node_win;
     for (size_t s = 0; s < L.robin_a.size(); ++s) {
         rob[2 * s] = (R)L.robin_a[s];
         rob[2 * s + 1] = (R)L.robin_b[s];
@@ -177,25 +180,37 @@ void upload_layout_t(fem_ctx *c, const Layout &L) {
     h2d(c, B_LINK_W, lw.data(), (int64_t)lw.size() * (int64_t)sizeof(R));
     if (c->opt.scatter == FEM_SCATTER_LDS_BLOCKED) {
         h2d(c, B_LCONN, L.lconn.data(), (int64_t)L.lconn.size() * 2);
-        if (c->mat_in_node_x()) {
-            // the apparent-capacity kernels read the material of a block whose
-            // nodes all share one once per block (pad0; -1 for mixed blocks)
-            blocks_app = L.blocks;
-            for (BlockInfo &b : blocks_app) {
-                int32_t m = -1;
-                bool mixed = false;
-                auto see = [&](int64_t g) {
-                    const int32_t q = (int32_t)(L.nflag[g] & NODE_MAT_MASK);
-                    if (m < 0) m = q;
-                    else if (q != m) mixed = true;
-                };
-                for (int32_t i = 0; i < b.n_int; ++i) see((int64_t)b.int_base + i);
-                for (int32_t i = 0; i < b.n_sh; ++i) see(L.sh_list[b.sh_begin + i]);
-                b.pad0 = mixed ? -1 : m;
+        // per block: its one material or -1 (pad0; the apparent-capacity kernels
+        // read the constants of a single-material block once), and the first row
+        // of its window of MAT_WINDOW material rows or -1 if its materials span
+        // more (pad1; the step kernels stage the window in LDS)
+        blocks_app = L.blocks;
+        for (BlockInfo &b : blocks_app) {
+            int32_t lo = INT32_MAX, hi = -1;
+            auto see = [&](int64_t g) {
+                const int32_t q = (int32_t)(L.nflag[g] & NODE_MAT_MASK);
+                lo = std::min(lo, q);
+                hi = std::max(hi, q);
+            };
+            for (int32_t i = 0; i < b.n_int; ++i) see((int64_t)b.int_base + i);
+            for (int32_t i = 0; i < b.n_sh; ++i) see(L.sh_list[b.sh_begin + i]);
+            b.pad0 = (c->mat_in_node_x() && hi == lo) ? lo : -1;
+            b.pad1 = (hi >= lo && hi - lo < MAT_WINDOW) ? lo : -1;
+        }
+        h2d(c, B_BLOCKS, blocks_app.data(), (int64_t)blocks_app.size() * (int64_t)sizeof(BlockInfo));
+        if (c->sizes[B_NODE_WIN]) {
+            const int64_t cnt = N - L.n_private, nw = node_grid(cnt);
+            node_win.resize(nw);
+            for (int64_t w = 0; w < nw; ++w) {
+                int32_t lo = INT32_MAX, hi = -1;
+                for (int64_t k = w * NODE_THREADS; k < std::min(cnt, (w + 1) * NODE_THREADS); ++k) {
+                    const int32_t q = (int32_t)(L.nflag[L.bc_first + k] & NODE_MAT_MASK);
+                    lo = std::min(lo, q);
+                    hi = std::max(hi, q);
+                }
+                node_win[w] = (hi >= lo && hi - lo < MAT_WINDOW) ? lo : -1;
             }
-            h2d(c, B_BLOCKS, blocks_app.data(), (int64_t)blocks_app.size() * (int64_t)sizeof(BlockInfo));
-        } else {
-            h2d(c, B_BLOCKS, L.blocks.data(), (int64_t)L.blocks.size() * (int64_t)sizeof(BlockInfo));
+            h2d(c, B_NODE_WIN, node_win.data(), nw * 4);
         }
         {
             std::vector<int32_t> shp(L.sh_list);
@@ -285,6 +300,7 @@ void fill_dev(fem_ctx *c, const Candidate &cd) {
     d.blocks = (const BlockInfo *)c->ptr[B_BLOCKS];
     d.sh_list = (const int32_t *)c->ptr[B_SH_LIST];
     d.partials = c->ptr[B_PARTIALS];
+    d.node_win = (const int32_t *)c->ptr[B_NODE_WIN];
     d.comb_ptr = (const int32_t *)c->ptr[B_COMB_PTR];
     d.sh_pos = (const int32_t *)c->ptr[B_SH_POS];
     d.flags = (const uint32_t *)c->ptr[B_FLAGS];

@@ -170,8 +170,11 @@ __global__ __launch_bounds__(1024) void k_block(Dev d, int parity) {
     const R *Tc = (const R *)d.T + parity * d.N;
     R *Tn = (R *)d.T + (1 - parity) * d.N;
     if (threadIdx.x == 0) s_bad = 0;
-    if constexpr (LDS_TABLES) stage_table(d.mats, d.n_mat, s_mats);   // visible after the next barrier
-    const MatDev *mats = LDS_TABLES ? s_mats : d.mats;
+    // material rows in LDS (visible after the next barrier): the whole table when
+    // it has at most LDS_MATS rows, else the block's window of rows (a block of a
+    // batch holds the few materials of one scenario; bi.pad1 < 0: no window)
+    if constexpr (LDS_TABLES) stage_table(d.mats, d.n_mat, s_mats);
+    else if (bi.pad1 >= 0) stage_table(d.mats + bi.pad1, min(LDS_MATS, d.n_mat - bi.pad1), s_mats);
 
     // gather: private nodes are a contiguous range, shared nodes a list;
     // node_x holds x, y, z and the conductivity of the node's material.
@@ -267,8 +270,9 @@ __global__ __launch_bounds__(1024) void k_block(Dev d, int parity) {
         return poison ? R(NAN) : r;
     };
     // UPDATE_U private nodes per thread and pass, their loads issued together
-    // before the first update; the last nodes of a thread go one by one
-    {
+    // before the first update; the last nodes of a thread go one by one.  Material
+    // m is row m - m0 of `mats` (LDS rows, or the global table with m0 = 0).
+    auto update_private = [&](const MatDev *mats, int m0) {
         int l = threadIdx.x;
         for (; l + (UPDATE_U - 1) * (int)blockDim.x < bi.n_int; l += UPDATE_U * blockDim.x) {
             uint32_t f[UPDATE_U];
@@ -282,14 +286,18 @@ __global__ __launch_bounds__(1024) void k_block(Dev d, int parity) {
 #pragma unroll
             for (int u = 0; u < UPDATE_U; ++u) {
                 const int lu = l + u * (int)blockDim.x;
-                NodeH<R>::store(d, mats[f[u] & NODE_MAT_MASK], (int64_t)bi.int_base + lu, pre[u], resid(lu), Tn);
+                NodeH<R>::store(d, mats[(int)(f[u] & NODE_MAT_MASK) - m0], (int64_t)bi.int_base + lu, pre[u],
+                                resid(lu), Tn);
             }
         }
         for (; l < bi.n_int; l += blockDim.x) {
             const int64_t g = (int64_t)bi.int_base + l;
-            NodeH<R>::update(d, mats[d.flags[g] & NODE_MAT_MASK], g, resid(l), Tn);
+            NodeH<R>::update(d, mats[(int)(d.flags[g] & NODE_MAT_MASK) - m0], g, resid(l), Tn);
         }
-    }
+    };
+    if (LDS_TABLES) update_private(s_mats, 0);
+    else if (bi.pad1 >= 0) update_private(s_mats, bi.pad1);
+    else update_private(d.mats, 0);
     // one partial per shared node, stored where the combine reads it
     R *P = (R *)d.partials;
     for (int l = threadIdx.x; l < bi.n_sh; l += blockDim.x) P[d.sh_pos[bi.sh_begin + l]] = resid(bi.n_int + l);
@@ -311,9 +319,13 @@ __global__ __launch_bounds__(NODE_THREADS) void k_nodes(Dev d, int parity) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = s < count;
     const int64_t g = d.bc_first + (live ? s : 0);
-    const int words = d.n_mat * (int)(sizeof(MatDev) / 4);
+    // material rows in LDS: the whole table, or this workgroup's window of
+    // LDS_MATS rows from m0 (m0 < 0: no window, rows read from global memory)
+    const int m0 = LDS_TABLES ? 0 : (d.node_win ? d.node_win[blockIdx.x] : -1);
+    const bool staged = LDS_TABLES || m0 >= 0;
+    const int words = staged ? min(LDS_MATS, d.n_mat - m0) * (int)(sizeof(MatDev) / 4) : 0;
     uint32_t tw = 0;
-    if (LDS_TABLES && (int)threadIdx.x < words) tw = ((const uint32_t *)d.mats)[threadIdx.x];
+    if ((int)threadIdx.x < words) tw = ((const uint32_t *)(d.mats + m0))[threadIdx.x];
     uint32_t f = 0;
     R r = R(0);
     typename NodeH<R>::Pre pre{};
@@ -323,11 +335,10 @@ __global__ __launch_bounds__(NODE_THREADS) void k_nodes(Dev d, int parity) {
         if (COMBINE) r = step::partial_slots(d, (const R *)d.partials, s);
         else r = ((const R *)d.r)[g];
     }
-    if constexpr (LDS_TABLES) {
+    if (staged) {           // uniform over the workgroup
         if ((int)threadIdx.x < words) ((uint32_t *)s_mats)[threadIdx.x] = tw;
         __syncthreads();
     }
-    const MatDev *mats = LDS_TABLES ? s_mats : d.mats;
     if (!live) return;
     const R *Tc = (const R *)d.T + parity * d.N;
     R *Tn = (R *)d.T + (1 - parity) * d.N;
@@ -335,10 +346,14 @@ __global__ __launch_bounds__(NODE_THREADS) void k_nodes(Dev d, int parity) {
     else ((R *)d.r)[g] = R(0);
     double q = 0.0;
     if (f & NODE_BC) q = boundary_terms<R>(d, s, Tc[g], Tc, r);
-    const MatDev &M = mats[f & NODE_MAT_MASK];
-    if (f & NODE_FIXED) q -= (double)r;     // reaction of a fixed temperature
-    else NodeH<R>::store(d, M, g, pre, r, Tn);
-    if (s < d.n_inflow) d.qnode[s] += q * M.dt;
+    auto finish = [&](const MatDev &M) {
+        if (f & NODE_FIXED) q -= (double)r;     // reaction of a fixed temperature
+        else NodeH<R>::store(d, M, g, pre, r, Tn);
+        if (s < d.n_inflow) d.qnode[s] += q * M.dt;
+    };
+    const int m = (int)(f & NODE_MAT_MASK);
+    if (staged) finish(s_mats[m - m0]);
+    else finish(d.mats[m]);
 }
 
 // state diagnostics on demand: one workgroup per single-scenario node segment

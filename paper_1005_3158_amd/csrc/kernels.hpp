@@ -40,6 +40,7 @@ struct Dev {
     const BlockInfo *blocks = nullptr;
     const int32_t *sh_list = nullptr;
     void *partials = nullptr;           // R per partial slot (see Layout::comb_ptr)
+    const int32_t *node_win = nullptr;  // per node-kernel workgroup: first row of its material window, or -1
     const int32_t *comb_ptr = nullptr, *sh_pos = nullptr;
     const uint32_t *flags = nullptr;    // material | flag bits per node
     // boundary slots
@@ -65,6 +66,8 @@ struct Dev {
 };
 
 constexpr int NODE_THREADS = 256;
+// rows of a material-table window staged in LDS by the step kernels
+constexpr int MAT_WINDOW = 8;
 
 inline int64_t node_grid(int64_t n) { return (n + NODE_THREADS - 1) / NODE_THREADS; }
 

@@ -207,7 +207,7 @@ __device__ __forceinline__ R combine_partials(const Dev &d, const R *P, int64_t 
 // global memory; kernels are instantiated for each case so that every table
 // access compiles to LDS or global loads (a pointer that may be either would
 // compile to the slower flat loads)
-constexpr int LDS_MATS = 8;
+constexpr int LDS_MATS = MAT_WINDOW;
 
 // copy a small table into LDS (visible after the caller's next barrier)
 template <class M>
