@@ -920,15 +920,30 @@ def bench_batch(args, log):
     reps = s.energy_scenarios()
     worst = max(r["residual"] for r in reps)
     b_alg = 16.0 * E + 48.0 * N
+    # kernel durations (HIP events, eager steps at the smallest scenario step, after the timed run)
+    kt = cf.fem_time_kernels(s.ctx, float(dt.min()), args.profile_steps)
+    ach_e = kt["bytes_element"] / (kt["ms_element"] * 1e-3) / 1e9
+    ach_c = kt["bytes_combine"] / (kt["ms_combine"] * 1e-3) / 1e9 if kt["ms_combine"] > 0 else None
+    traffic = load_traffic("block_element_batch", rep["max_local_nodes"])
+    log("steps %d: %.4f ms/step; element kernel %.4f ms (%.1f GB/s alg), node kernel %.4f ms; %d threads per block"
+        % (steps, 1e3 * t_run / steps, kt["ms_element"], ach_e, kt["ms_combine"], rep["block_threads"]))
     out = {
         "metric": METRIC, "value": E * steps / t_run, "unit": "element-steps/s", "n_gpus": 1, "steps": steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * t_run / steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32 (compensated enthalpy, f64 T(H) and reductions)", "data": "synthetic",
         "config": {"workload": "batch of %d casting scenarios (%d tets, %d nodes), per-scenario dt" % (n_scen, E, N),
                    "n_elems": E, "n_nodes": N, "n_scen": n_scen, "block_nodes": rep["max_local_nodes"],
-                   "n_blocks": rep["n_blocks"], "setup_s": t_setup},
+                   "block_threads": rep["block_threads"], "n_blocks": rep["n_blocks"],
+                   "shared_fraction": rep["shared_fraction"], "setup_s": t_setup},
         "effective_GBps": b_alg * steps / t_run / 1e9,
         "effective_frac_hbm": b_alg * steps / t_run / 1e9 / HBM_PEAK_GBS,
+        "roofline": {
+            "bound": "hbm", "kernel": "k_block<float,4> with material windows (blocked residual + private update)",
+            "achieved": ach_e, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach_e / HBM_PEAK_GBS,
+            "traffic": traffic, "ms_per_launch": kt["ms_element"], "alg_bytes_per_launch": kt["bytes_element"],
+            "node_kernel": {"ms_per_launch": kt["ms_combine"], "alg_bytes_per_launch": kt["bytes_combine"],
+                            "achieved": ach_c},
+        },
         "worst_scenario_energy_residual": worst,
     }
     s.close()

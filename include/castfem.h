@@ -115,7 +115,8 @@ typedef struct {
     double setup_seconds;        /* host time of fem_finalize */
     double contact_search_seconds;   /* host time of the sister search (fem_set_contact) */
     int64_t n_contact;           /* contact faces */
-    int64_t reserved[2];
+    int64_t block_threads;       /* LDS-blocked: threads per element block in use */
+    int64_t reserved[1];
 } fem_prep_report;
 
 typedef struct {

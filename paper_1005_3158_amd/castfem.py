@@ -83,7 +83,7 @@ class fem_prep_report(C.Structure):
                 ("n_colors", C.c_int64), ("bandwidth_before", C.c_int64), ("bandwidth_after", C.c_int64),
                 ("block_elems", C.c_int64), ("shared_fraction", C.c_double), ("dt_bound", C.c_double),
                 ("setup_seconds", C.c_double), ("contact_search_seconds", C.c_double), ("n_contact", C.c_int64),
-                ("reserved", C.c_int64 * 2)]
+                ("block_threads", C.c_int64), ("reserved", C.c_int64 * 1)]
 
 
 class fem_buffer_desc(C.Structure):

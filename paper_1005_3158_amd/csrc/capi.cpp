@@ -494,6 +494,7 @@ void fill_report(const fem_ctx *c, fem_prep_report *rep) {
     rep->n_shared = c->opt.scatter == FEM_SCATTER_LDS_BLOCKED ? L.N - L.n_private : 0;
     rep->n_partials = (int64_t)L.sh_list.size();
     rep->max_local_nodes = L.max_local;
+    rep->block_threads = c->cands.empty() ? 0 : c->cands[c->chosen].threads;
     rep->n_colors = L.color_ptr.empty() ? 0 : (int64_t)L.color_ptr.size() - 1;
     rep->bandwidth_before = L.bw_before;
     rep->bandwidth_after = L.bw_after;
@@ -752,15 +753,23 @@ int fem_finalize(fem_ctx *ctx, fem_prep_report *rep) {
         if (ctx->opt.scatter == FEM_SCATTER_LDS_BLOCKED && ctx->opt.block_elems == 0 && ctx->opt.lds_bytes == 0) {
             // autotune over block node sets (the paper's timed search over the block count);
             // small meshes also try small blocks, so that more compute units take part
-            for (int64_t nodes : {128, 256, 512, 640, 768, 1024, 1536}) {
-                if ((size_t)nodes * per > MAX_BLOCK_LDS) continue;
+            // (node cap, threads): larger blocks also with more threads, so that a
+            // compute unit keeps its waves when fewer blocks fit its LDS
+            std::vector<std::pair<int64_t, int>> tries;
+            for (int64_t nodes : {128, 256, 512, 640, 768, 1024, 1536}) tries.push_back({nodes, thr});
+            if (!ctx->opt.threads)
+                for (const auto &t : {std::pair<int64_t, int>{1024, 512}, {2048, 1024}, {3072, 1024}})
+                    tries.push_back(t);
+            for (const auto &t : tries) {
+                const int64_t nodes = t.first;
+                if ((size_t)(nodes + 1) * per > MAX_BLOCK_LDS) continue;
                 if (nodes < 512 && ctx->prob.N > 512 * 512) continue;
                 Candidate c;
                 c.o.ordering = ctx->opt.ordering;
                 c.o.scatter = ctx->opt.scatter;
                 c.o.max_local_nodes = nodes;
                 c.o.block_elems = 1 << 20;
-                c.threads = thr;
+                c.threads = t.second;
                 cands.push_back(std::move(c));
             }
         } else {

@@ -329,9 +329,12 @@ __global__ __launch_bounds__(NODE_THREADS) void k_nodes(Dev d, int parity) {
     uint32_t f = 0;
     R r = R(0);
     typename NodeH<R>::Pre pre{};
+    int32_t l0 = 0, l1 = 0;         // this slot's interface links (loaded with the rest)
     if (live) {
         f = d.flags[g];
         pre = NodeH<R>::load(d, g);
+        l0 = d.link_ptr[s];
+        l1 = d.link_ptr[s + 1];
         if (COMBINE) r = step::partial_slots(d, (const R *)d.partials, s);
         else r = ((const R *)d.r)[g];
     }
@@ -345,7 +348,7 @@ __global__ __launch_bounds__(NODE_THREADS) void k_nodes(Dev d, int parity) {
     if (COMBINE) r = step::partial_extras(d, (const R *)d.partials, s, f, r);
     else ((R *)d.r)[g] = R(0);
     double q = 0.0;
-    if (f & NODE_BC) q = boundary_terms<R>(d, s, Tc[g], Tc, r);
+    if (f & NODE_BC) q = boundary_terms<R>(d, s, Tc[g], Tc, r, l0, l1);
     auto finish = [&](const MatDev &M) {
         if (f & NODE_FIXED) q -= (double)r;     // reaction of a fixed temperature
         else NodeH<R>::store(d, M, g, pre, r, Tn);

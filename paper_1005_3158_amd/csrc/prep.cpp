@@ -800,9 +800,12 @@ void prep_layout(const Problem &p, const Base &b, const PrepOptions &o, const Or
         // come first: only the node-kernel workgroups covering them reduce it
         auto inflow = [&](int32_t i) { return b.fixed[i] || b.robin_b[i] != 0.0 || b.robin_a[i] != 0.0; };
         const auto inflow_end = std::stable_partition(shar.begin(), shar.end(), inflow);
-        // after them the nodes in at most PARTIAL_SLOTS blocks, then the few in
-        // more: only the node-kernel workgroups covering those read extra partials
-        std::stable_partition(inflow_end, shar.end(), [&](int32_t i) { return nblk[i] <= PARTIAL_SLOTS; });
+        // then the other nodes with boundary terms (interface links), so that the
+        // node-kernel workgroups that follow have none; then the nodes in at most
+        // PARTIAL_SLOTS blocks, then the few in more: only the workgroups covering
+        // those read extra partials
+        const auto bc_end = std::stable_partition(inflow_end, shar.end(), [&](int32_t i) { return has_bc(i); });
+        std::stable_partition(bc_end, shar.end(), [&](int32_t i) { return nblk[i] <= PARTIAL_SLOTS; });
         L.n_inflow = (int64_t)(inflow_end - shar.begin());
         L.n_private = (int64_t)priv.size();
         std::vector<int32_t> fin(N);

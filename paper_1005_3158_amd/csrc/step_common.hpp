@@ -158,7 +158,8 @@ template <> struct NodeH<double> {
 // Robin and interface terms of boundary slot s for a node at temperature Ti:
 // adds them to r and returns the Robin inflow
 template <class R>
-__device__ __forceinline__ double boundary_terms(const Dev &d, int64_t s, R Ti, const R *Tc, R &r) {
+__device__ __forceinline__ double boundary_terms(const Dev &d, int64_t s, R Ti, const R *Tc, R &r, int32_t l0,
+                                                 int32_t l1) {
     using V2 = typename VT<R>::V2;
     double q = 0.0;
     if (d.robin) {
@@ -167,10 +168,14 @@ __device__ __forceinline__ double boundary_terms(const Dev &d, int64_t s, R Ti, 
         r += f;
         q = (double)f;
     }
-    const int32_t l0 = d.link_ptr[s], l1 = d.link_ptr[s + 1];
     const R *w = (const R *)d.link_w;
     for (int32_t k = l0; k < l1; ++k) r += w[k] * (Tc[d.link_node[k]] - Ti);
     return q;
+}
+// the same, with the slot's link range [link_ptr[s], link_ptr[s + 1]) read here
+template <class R>
+__device__ __forceinline__ double boundary_terms(const Dev &d, int64_t s, R Ti, const R *Tc, R &r) {
+    return boundary_terms<R>(d, s, Ti, Tc, r, d.link_ptr[s], d.link_ptr[s + 1]);
 }
 
 // Sum of the residual partials of the blocked layout's shared node s (slot s of
