@@ -152,6 +152,8 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true", help="default run: skip the surrogate comparison")
     ap.add_argument("--no-config5", action="store_true", help="default run: skip the 256^3 mesh")
     ap.add_argument("--config5-steps", type=int, default=200, help="default run: timed steps on the 256^3 mesh")
+    ap.add_argument("--no-projection", action="store_true",
+                    help="surrogate: no energy-neutral projection of the network's correction")
     ap.add_argument("--lr", type=float, default=1e-3, help="surrogate: initial learning rate")
     ap.add_argument("--loss", default="huber", choices=["H", "T", "huber"], help="surrogate: training loss")
     ap.add_argument("--extrapolation", default="quadratic", choices=["linear", "quadratic"],
@@ -925,6 +927,7 @@ def bench_batch(args, log):
     ach_e = kt["bytes_element"] / (kt["ms_element"] * 1e-3) / 1e9
     ach_c = kt["bytes_combine"] / (kt["ms_combine"] * 1e-3) / 1e9 if kt["ms_combine"] > 0 else None
     traffic = load_traffic("block_element_batch", rep["max_local_nodes"])
+    copy = copy_ceiling(s.ctx, log)
     log("steps %d: %.4f ms/step; element kernel %.4f ms (%.1f GB/s alg), node kernel %.4f ms; %d threads per block"
         % (steps, 1e3 * t_run / steps, kt["ms_element"], ach_e, kt["ms_combine"], rep["block_threads"]))
     out = {
@@ -937,6 +940,7 @@ def bench_batch(args, log):
                    "shared_fraction": rep["shared_fraction"], "setup_s": t_setup},
         "effective_GBps": b_alg * steps / t_run / 1e9,
         "effective_frac_hbm": b_alg * steps / t_run / 1e9 / HBM_PEAK_GBS,
+        "copy_ceiling": copy,
         "roofline": {
             "bound": "hbm", "kernel": "k_block<float,4> with material windows (blocked residual + private update)",
             "achieved": ach_e, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach_e / HBM_PEAK_GBS,
@@ -978,7 +982,7 @@ def run_surrogate(args, log):
         gen = cf.Solver(b, precision=cf.FEM_PREC_FP32_KAHAN)
         dt = 0.9 * gen.stable_dt_scenarios()
         sur = cf.Surrogate(gen, layers=3, horizon=args.horizon, max_samples=1, train=True, seed=11, loss=loss,
-                           extrapolation=extrap)
+                           extrapolation=extrap, projection=not args.no_projection)
         if params is not None:
             sur.set_params(params)
         S = torch.empty((n_chunks, 4, gen.n_nodes), dtype=torch.float32, device=gen.device)
@@ -1035,10 +1039,10 @@ def run_surrogate(args, log):
             rp = plain.advance(dt1, 10 ** 6, None, until_solid=True)
             # the same gates with the untrained network (w_out = 0): the extrapolation alone
             ex = cf.Solver(p, precision=cf.FEM_PREC_FP32_KAHAN, lds_bytes=lds)
-            se = cf.Surrogate(ex, layers=3, horizon=args.horizon, extrapolation=extrap)
+            se = cf.Surrogate(ex, layers=3, horizon=args.horizon, extrapolation=extrap, projection=not args.no_projection)
             re_ = ex.advance(dt1, 10 ** 6, se, until_solid=True, verify_tol=args.verify_tol, fs_tol=args.fs_tol)
             acc = cf.Solver(p, precision=cf.FEM_PREC_FP32_KAHAN, lds_bytes=lds)
-            sa = cf.Surrogate(acc, layers=3, horizon=args.horizon, extrapolation=extrap)
+            sa = cf.Surrogate(acc, layers=3, horizon=args.horizon, extrapolation=extrap, projection=not args.no_projection)
             sa.set_params(params)
             ra = acc.advance(dt1, 10 ** 6, sa, until_solid=True, verify_tol=args.verify_tol, fs_tol=args.fs_tol)
             for k, r in (("plain", rp), ("extrap", re_), ("net", ra)):
@@ -1057,7 +1061,9 @@ def run_surrogate(args, log):
                         sur_steps=ra["steps"], computed=ra["plain_steps"], kept=ra["jumps_accepted"],
                         rejected=ra["jumps_rejected"], err_K=float(dT.max()), rms_K=float(np.sqrt(np.mean(dT ** 2))),
                         residual=acc.energy()["residual"], extrap_s=re_["wall_seconds"], extrap_kept=re_["jumps_accepted"],
-                        extrap_rejected=re_["jumps_rejected"], extrap_err_K=float(dTe.max())))
+                        extrap_rejected=re_["jumps_rejected"], extrap_err_K=float(dTe.max()),
+                        rejected_by={k: int(ra["rejected_" + k]) for k in ("fs", "energy", "verify")},
+                        extrap_rejected_by={k: int(re_["rejected_" + k]) for k in ("fs", "energy", "verify")}))
         log("seed %d: plain %d steps %.4f s; surrogate %d steps (%d computed, %d/%d jumps kept) %.4f s; "
             "max|dT| %.3f K rms %.3f K; extrapolation only %.4f s, max|dT| %.3f K"
             % (seed, rp["steps"], rp["wall_seconds"], ra["steps"], ra["plain_steps"], ra["jumps_accepted"],
@@ -1078,7 +1084,7 @@ def run_surrogate(args, log):
                                "%d held-out trajectories run to full solidification" % (args.train_traj, args.held_out),
                    "layers": 3, "width": 64, "horizon": args.horizon, "epochs": args.epochs, "rounds": args.rounds,
                    "loss": args.loss, "extrapolation": args.extrapolation, "energy_tol": 1e-4, "fs_tol": args.fs_tol,
-                   "verify_tol_K": args.verify_tol},
+                   "verify_tol_K": args.verify_tol, "projection": not args.no_projection},
         "plain_seconds": t_plain, "surrogate_seconds": t_sur,
         "max_err_K": float(errs.max()), "median_err_K": float(np.median(errs)),
         "within_0p5K": int(np.sum(errs <= 0.5)), "n_held_out": len(res),
@@ -1094,7 +1100,9 @@ def run_surrogate(args, log):
             "max_err_K": float(max(r["extrap_err_K"] for r in res)),
             "within_0p5K": int(sum(r["extrap_err_K"] <= 0.5 for r in res)),
             "jumps_kept": int(sum(r["extrap_kept"] for r in res)),
-            "jumps_rejected": int(sum(r["extrap_rejected"] for r in res))},
+            "jumps_rejected": int(sum(r["extrap_rejected"] for r in res)),
+            "rejected_by": {k: int(sum(r["extrap_rejected_by"][k] for r in res)) for k in ("fs", "energy", "verify")}},
+        "rejected_by": {k: int(sum(r["rejected_by"][k] for r in res)) for k in ("fs", "energy", "verify")},
         "per_trajectory": res,
     }
     return out

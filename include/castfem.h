@@ -361,7 +361,9 @@ typedef struct {
     int32_t train;         /* nonzero: size the training buffers too */
     int32_t loss;          /* FEM_SUR_LOSS_*: what the training loss measures */
     int32_t extrapolation; /* FEM_SUR_EXTRAP_*: the base the network corrects */
-    int32_t reserved[5];   /* must be zero */
+    int32_t no_projection; /* nonzero: y is used as it is (ybar = 0), the correction is not energy-neutral
+                              (for studying the projection and checking gradients without its cancellation) */
+    int32_t reserved[4];   /* must be zero */
     uint64_t seed;         /* initial parameters (He-normal, counter-based generator) */
 } fem_sur_options;
 

@@ -363,3 +363,53 @@ def loss_and_grad(p, X, t, ptr, col, layers, bf16=False, proj_w=None):
     g["W_in"] = c["X"].T @ dz
     g["b_in"] = dz.sum(axis=0)
     return loss, g, y
+
+
+# BF16 unit roundoff: 8 significant bits, round to nearest
+BF16_U = 2.0 ** -8
+
+
+def bf16_rounding_points(layers):
+    """Roundings on the longest chain from an input to a gradient entry: features,
+    W_in, z_in and h_0; per layer W_l, the aggregated and the hidden states, z_l and
+    the backward dz_l; and the backward dz_in."""
+    return 4 + 5 * layers + 1
+
+
+def gradient_error_bound(p, X, t, ptr, col, layers, proj_w=None):
+    """First-order forward error bound of the gradient computed with BF16 operands
+    (rounded at the kernels' points) against the exact one.  Every rounded operand
+    carries a relative error below u = 2^-8, and through k roundings a product of
+    them is off by at most gamma_k = k u / (1 - k u) of itself (Higham, Accuracy and
+    Stability of Numerical Algorithms, Sec. 3.1), so each entry of a block is off
+    by at most gamma_k times the same sum taken over absolute values: the backward
+    pass below with |W|, |activations|, |dy| and the masks of the exact pass.
+    Returns (per-block bound arrays, loss bound)."""
+    y, c = forward(p, X, ptr, col, layers, False, proj_w)
+    k = bf16_rounding_points(layers)
+    gam = k * BF16_U / (1.0 - k * BF16_U)
+    W = c["W"]
+    # |y| as built from absolute values, and |dL/dy| from the loss derivative
+    ha = [np.abs(h) for h in c["hs"]]
+    ya = ha[-1] @ np.abs(p["w_out"]) + abs(p["b_out"][0])
+    if proj_w is not None:
+        ya = ya + np.dot(proj_w, ya)
+    loss, dy = (t if callable(t) else h_loss(t))(y)
+    dya = np.abs(dy)
+    if proj_w is not None:
+        dya = dya + proj_w * dya.sum()
+    # the loss: |d loss| <= sum |dL/dy| |dy| with |dy| <= gamma |y|
+    loss_bound = gam * float(np.dot(dya, ya))
+    g = {"w_out": ha[-1].T @ dya, "b_out": np.array([dya.sum()])}
+    dh = np.outer(dya, np.abs(p["w_out"]))
+    width = p["b_in"].size
+    for l in reversed(range(layers)):
+        dz = dh * (c["z%d" % l] > 0)
+        g["W%d" % l] = np.abs(c["u%d" % l]).T @ dz
+        g["b%d" % l] = dz.sum(axis=0)
+        du = dz @ np.abs(W["W%d" % l]).T
+        dh = dh + du[:, :width] + apply_mean_T(ptr, col, du[:, width:])
+    dz = dh * (c["z_in"] > 0)
+    g["W_in"] = np.abs(c["X"]).T @ dz
+    g["b_in"] = dz.sum(axis=0)
+    return {key: gam * v for key, v in g.items()}, loss_bound

@@ -103,7 +103,8 @@ class fem_kernel_times(C.Structure):
 
 class fem_sur_options(C.Structure):
     _fields_ = [("width", C.c_int32), ("layers", C.c_int32), ("horizon", C.c_int32), ("max_samples", C.c_int32),
-                ("train", C.c_int32), ("loss", C.c_int32), ("extrapolation", C.c_int32), ("reserved", C.c_int32 * 5),
+                ("train", C.c_int32), ("loss", C.c_int32), ("extrapolation", C.c_int32), ("no_projection", C.c_int32),
+                ("reserved", C.c_int32 * 4),
                 ("seed", C.c_uint64)]
 
 
@@ -391,10 +392,10 @@ FEM_SUR_EXTRAP_LINEAR, FEM_SUR_EXTRAP_QUADRATIC = 0, 1
 
 
 def fem_sur_create(ctx, width=64, layers=3, horizon=16, max_samples=1, train=False, seed=0, loss=FEM_SUR_LOSS_H,
-                   extrapolation=FEM_SUR_EXTRAP_LINEAR):
+                   extrapolation=FEM_SUR_EXTRAP_LINEAR, projection=True):
     o = fem_sur_options()
     o.width, o.layers, o.horizon, o.max_samples, o.train, o.seed = width, layers, horizon, max_samples, int(train), seed
-    o.loss, o.extrapolation = loss, extrapolation
+    o.loss, o.extrapolation, o.no_projection = loss, extrapolation, int(not projection)
     s = C.c_void_p()
     _call("fem_sur_create", C.byref(s), ctx, C.byref(o))
     return s
@@ -618,11 +619,12 @@ class Surrogate:
     """The learned surrogate of a Solver; torch allocates its device buffers."""
 
     def __init__(self, solver, layers=3, horizon=16, max_samples=1, train=False, seed=0, loss=FEM_SUR_LOSS_H,
-                 extrapolation=FEM_SUR_EXTRAP_LINEAR):
+                 extrapolation=FEM_SUR_EXTRAP_LINEAR, projection=True):
         self.solver = solver
         self.torch = solver.torch
         self.n_nodes = solver.n_nodes
-        self.sur = fem_sur_create(solver.ctx, 64, layers, horizon, max_samples, train, seed, loss, extrapolation)
+        self.sur = fem_sur_create(solver.ctx, 64, layers, horizon, max_samples, train, seed, loss, extrapolation,
+                                  projection)
         self.buffers, ptrs = _allocate(self.torch, solver.device, fem_sur_query_buffers(self.sur))
         fem_sur_bind_buffers(self.sur, ptrs)
 

@@ -228,6 +228,7 @@ void fill_surdev(fem_sur *s) {
     d.layers = s->opt.layers;
     d.horizon = s->opt.horizon;
     d.loss_mode = s->opt.loss;
+    d.project = s->opt.no_projection ? 0 : 1;
     d.quadratic = s->opt.extrapolation == FEM_SUR_EXTRAP_QUADRATIC ? 1 : 0;
     d.pl = s->pl;
     d.nbr_ptr = (const int32_t *)s->ptr[S_NBR_PTR];

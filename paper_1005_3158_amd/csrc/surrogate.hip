@@ -504,9 +504,12 @@ __global__ __launch_bounds__(256) void k_proj_bwd(SurDev s, int64_t R) {
     const int c4 = (int)(t & 15) * 4;
     if (r >= R) return;
     const int64_t q = r / s.N, i = r - q * s.N;
-    const double *ss = s.scen_sum + 2 * (q * s.n_scen + s.scen[i]);
-    const double w = ss[1] > 0.0 ? (double)((const float4 *)s.coef)[i].w * (double)s.scale[r] / ss[1] : 0.0;
-    const float dy = (float)((double)s.y[r] - w * ss[0]);
+    float dy = s.y[r];
+    if (s.project) {
+        const double *ss = s.scen_sum + 2 * (q * s.n_scen + s.scen[i]);
+        const double w = ss[1] > 0.0 ? (double)((const float4 *)s.coef)[i].w * (double)s.scale[r] / ss[1] : 0.0;
+        dy = (float)((double)s.y[r] - w * ss[0]);
+    }
     if (c4 == 0) s.dy[r] = dy;
     const float4 wo = *(const float4 *)(s.params + s.pl.w_out + c4);
     *(float4 *)(s.dH + r * WIDTH + c4) = make_float4(dy * wo.x, dy * wo.y, dy * wo.z, dy * wo.w);
@@ -652,7 +655,8 @@ __global__ __launch_bounds__(256) void k_write_jump(SurDev s, Dev d, int parity,
             s.Hn[i] = s.H2[i];
         } else {
             const MatDev &M = d.mats[f & NODE_MAT_MASK];
-            const double Hn = s.base[i] + (double)s.scale[i] * ((double)s.y[i] - s.scen_sum[2 * s.scen[i]]);
+            const double ybar = s.project ? s.scen_sum[2 * s.scen[i]] : 0.0;
+            const double Hn = s.base[i] + (double)s.scale[i] * ((double)s.y[i] - ybar);
             s.Hn[i] = Hn;
             set_node<R>(d, i, M, Hn, (R *)d.T + parity * d.N);
             if (M.latent) {
@@ -744,6 +748,7 @@ hipError_t forward(const SurDev &s, int64_t R, int store, int project, hipStream
                        2 * WIDTH, (float *)nullptr, 0);
     const unsigned gl = grid_for(R, LAYER_ROWS);
     for (int l = 0; l < s.layers; ++l) hipLaunchKernelGGL(k_layer, dim3(gl), dim3(256), 0, st, s, l, R, store);
+    if (!s.project) return hipGetLastError();
     const int64_t slots = R / s.N;
     hipLaunchKernelGGL(k_seg_sum, dim3((unsigned)s.n_seg, (unsigned)slots), dim3(256), 0, st, s, (const float *)s.y, 1);
     hipLaunchKernelGGL(k_scen_sum, dim3(grid_for(slots * s.n_scen, 256)), dim3(256), 0, st, s, slots, 1);
@@ -754,8 +759,10 @@ hipError_t forward(const SurDev &s, int64_t R, int store, int project, hipStream
 hipError_t loss_and_dy(const SurDev &s, int64_t R, hipStream_t st) {
     hipLaunchKernelGGL(k_loss, dim3(grid_for(R, 256)), dim3(256), 0, st, s, R);
     const int64_t slots = R / s.N;
-    hipLaunchKernelGGL(k_seg_sum, dim3((unsigned)s.n_seg, (unsigned)slots), dim3(256), 0, st, s, (const float *)s.y, 0);
-    hipLaunchKernelGGL(k_scen_sum, dim3(grid_for(slots * s.n_scen, 256)), dim3(256), 0, st, s, slots, 0);
+    if (s.project) {
+        hipLaunchKernelGGL(k_seg_sum, dim3((unsigned)s.n_seg, (unsigned)slots), dim3(256), 0, st, s, (const float *)s.y, 0);
+        hipLaunchKernelGGL(k_scen_sum, dim3(grid_for(slots * s.n_scen, 256)), dim3(256), 0, st, s, slots, 0);
+    }
     hipLaunchKernelGGL(k_proj_bwd, dim3(grid_for(R * 16, 256)), dim3(256), 0, st, s, R);
     return hipGetLastError();
 }

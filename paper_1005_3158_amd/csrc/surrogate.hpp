@@ -58,6 +58,7 @@ struct SurDev {
     int layers = 3;
     int horizon = 16;         // explicit steps per jump
     int loss_mode = LOSS_H;   // LOSS_H, LOSS_HUBER: target (Ht - base) / s; LOSS_T: target T(Ht)
+    int project = 1;          // 0: the output is used as it is (no energy-neutral projection)
     int quadratic = 0;        // base: 0 linear through H1, H2; 1 quadratic through H0, H1, H2
     ParamLayout pl;
     // graph: mean over mesh neighbours

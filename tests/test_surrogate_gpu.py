@@ -49,6 +49,9 @@ def gpu(chill):
     sur = cf.Surrogate(solver, layers=LAYERS, max_samples=2, train=True, seed=1)
     sur_t = cf.Surrogate(solver, layers=LAYERS, max_samples=2, train=True, seed=1, loss=cf.FEM_SUR_LOSS_T)
     sur_u = cf.Surrogate(solver, layers=LAYERS, max_samples=2, train=True, seed=1, loss=cf.FEM_SUR_LOSS_HUBER)
+    # without the energy-neutral projection (no cancellation in dL/dy)
+    sur_np = {k: cf.Surrogate(solver, layers=LAYERS, max_samples=2, train=True, seed=1, loss=v, projection=False)
+              for k, v in (("H", cf.FEM_SUR_LOSS_H), ("T", cf.FEM_SUR_LOSS_T), ("U", cf.FEM_SUR_LOSS_HUBER))}
     perm = solver.node_perm()
 
     def dev(*states):
@@ -57,8 +60,8 @@ def gpu(chill):
             a[q, perm] = h
         return torch.from_numpy(a).to(solver.device)
 
-    yield dict(cf=cf, solver=solver, sur=sur, sur_t=sur_t, sur_u=sur_u, perm=perm, dev=dev, torch=torch)
-    for x in (sur, sur_t, sur_u):
+    yield dict(cf=cf, solver=solver, sur=sur, sur_t=sur_t, sur_u=sur_u, sur_np=sur_np, perm=perm, dev=dev, torch=torch)
+    for x in [sur, sur_t, sur_u] + list(sur_np.values()):
         x.close()
     solver.close()
 
@@ -88,9 +91,10 @@ def test_features_match_the_oracle(chill, gpu):
     assert 0 < np.count_nonzero(scale) < scale.size
 
 
-def _ref_loss_grad(chill, vparams, triples, loss_kind="H", bf16=False):
+def _ref_loss_grad(chill, vparams, triples, loss_kind="H", bf16=False, projection=True, bound=False):
     """Mean over the states of the reference loss and gradient (FP64, or with the
-    kernels' BF16 rounding points)."""
+    kernels' BF16 rounding points); bound=True: the first-order bound of the BF16
+    rounding error of that mean instead (loss bound, flat gradient bound)."""
     p = chill["p"]
     ptr, col = S.graph_mean_operator(p["conn"], p["xyz"].shape[0])
     loss, grad = 0.0, None
@@ -101,8 +105,11 @@ def _ref_loss_grad(chill, vparams, triples, loss_kind="H", bf16=False):
         mask = scale > 0
         assert mask.any()
         f = {"H": S.h_loss(t, mask), "U": S.huber_loss(t, mask), "T": S.t_loss(p, base, ht, scale)}[loss_kind]
-        l, g, _ = S.loss_and_grad(vparams, X, f, ptr, col, LAYERS, bf16=bf16,
-                                  proj_w=S.projection_weights(p, scale, chill["st"]))
+        pw = S.projection_weights(p, scale, chill["st"]) if projection else None
+        if bound:
+            g, l = S.gradient_error_bound(vparams, X, f, ptr, col, LAYERS, proj_w=pw)
+        else:
+            l, g, _ = S.loss_and_grad(vparams, X, f, ptr, col, LAYERS, bf16=bf16, proj_w=pw)
         gv = S.flatten_params(g, LAYERS)
         loss += l / len(triples)
         grad = gv / len(triples) if grad is None else grad + gv / len(triples)
@@ -119,46 +126,51 @@ def _blocks():
     return out
 
 
+@pytest.mark.parametrize("projection", [True, False])
 @pytest.mark.parametrize("slots,loss_kind", [(1, "H"), (2, "H"), (2, "T"), (2, "U")])
-def test_loss_and_gradients_match_the_fp64_reference(chill, gpu, slots, loss_kind):
+def test_loss_and_gradients_match_the_fp64_reference(chill, gpu, slots, loss_kind, projection):
+    """Two bars.  Against the reference rounded at the kernels' own BF16 points only
+    the FP32 summation order differs (mechanical check).  Against the exact FP64
+    reference the bar is the first-order bound of the BF16 rounding: through k
+    roundings of relative size u = 2^-8 every gradient entry is off by at most
+    gamma_k = k u / (1 - k u) times the same sum over absolute values (computed by
+    the reference, S.gradient_error_bound).  ReLU masks flip where a pre-activation
+    lies within rounding of zero, which a first-order bound does not cover entry by
+    entry, so the bound is taken per parameter block in the Frobenius norm."""
     H = chill["H"]
     triples = [(H[32], H[33], H[34], H[48]), (H[160], H[161], H[162], H[176])][:slots]
     v32, vp = ref_params()
-    sur = {"H": gpu["sur"], "T": gpu["sur_t"], "U": gpu["sur_u"]}[loss_kind]
+    if projection:
+        sur = {"H": gpu["sur"], "T": gpu["sur_t"], "U": gpu["sur_u"]}[loss_kind]
+    else:
+        sur = gpu["sur_np"][loss_kind]
     sur.set_params(v32)
     H0 = gpu["dev"](*[t[0] for t in triples])
     H1 = gpu["dev"](*[t[1] for t in triples])
     H2 = gpu["dev"](*[t[2] for t in triples])
     Ht = gpu["dev"](*[t[3] for t in triples])
     loss, g = sur.loss_grad(H0, H1, H2, Ht, stride=gpu["solver"].n_nodes, slots=slots)
-    loss_r, g_r = _ref_loss_grad(chill, vp, triples, loss_kind)
-    loss_b, g_b = _ref_loss_grad(chill, vp, triples, loss_kind, bf16=True)
-    print("loss gpu %.6e ref %.6e ref(bf16) %.6e" % (loss, loss_r, loss_b))
-    # against the reference with the same BF16 rounding points only the FP32
-    # summation order differs: that is the parity bar.  Against exact FP64 the
-    # BF16 rounding itself shows, amplified by cancellation in the gradient sums
-    # (the projection makes dL/dy sum to zero per scenario): the reference's own
-    # BF16-vs-FP64 deviation on these states is up to 6 % in the loss, 46 % in a
-    # block and cosine 0.965, and the bounds below carry a margin over that.
+    loss_r, g_r = _ref_loss_grad(chill, vp, triples, loss_kind, projection=projection)
+    loss_b, g_b = _ref_loss_grad(chill, vp, triples, loss_kind, bf16=True, projection=projection)
+    loss_bound, g_bound = _ref_loss_grad(chill, vp, triples, loss_kind, projection=projection, bound=True)
+    print("loss gpu %.6e ref %.6e ref(bf16) %.6e, bound %.2e" % (loss, loss_r, loss_b, loss_bound))
     assert loss == pytest.approx(loss_b, rel=1e-5)
-    assert loss == pytest.approx(loss_r, rel=0.15)
+    assert abs(loss - loss_r) <= loss_bound
     gnorm = np.linalg.norm(g_r)
     for name, sl in _blocks():
-        if name == "b_out":
+        if name == "b_out" and projection:
             # the energy-neutral projection removes any constant output: zero gradient
             assert np.all(np.abs(g[sl]) <= 1e-6 * gnorm) and np.all(np.abs(g_r[sl]) <= 1e-12 * gnorm)
             continue
         nr = np.linalg.norm(g_r[sl])
         rel_b = np.linalg.norm(g[sl] - g_b[sl]) / nr
-        rel = np.linalg.norm(g[sl] - g_r[sl]) / nr
-        print("%-6s |g| %.3e  vs bf16 ref %.2e  vs fp64 ref %.2e" % (name, nr, rel_b, rel))
+        err, bnd = np.linalg.norm(g[sl] - g_r[sl]), np.linalg.norm(g_bound[sl])
+        print("%-6s |g| %.3e  vs bf16 ref %.2e  vs fp64 ref %.2e of its bound" % (name, nr, rel_b, err / bnd))
         # the hidden states agree bit for bit; what remains is the FP32 summation order
         # of the products (~1e-5), which the Huber loss's clip raises to ~7e-4 of its
         # small gradients (an FP32-product emulation of the reference shows the same)
         assert rel_b <= 2e-3, name
-        assert rel <= 0.6, name
-    cos = float(np.dot(g, g_r) / (np.linalg.norm(g) * gnorm))
-    assert cos >= 0.95
+        assert err <= bnd, name
 
 
 @pytest.mark.parametrize("quadratic", [False, True])
