@@ -788,6 +788,9 @@ static int has(const double *tab) { return tab && tab[0] > 0; }
 static int check_var(const orc_problem *p, const orc_varprops *v)
 {
     if (!table_ok(v->h_of_T) || !table_ok(v->h_of_t) || !table_ok(v->dir_of_t)) return ORC_ERR_ARG;
+    if (v->dir_sched)
+        for (int64_t d = 0; d < p->n_dir; ++d)
+            if (!table_ok(v->dir_sched + ORC_TABLE * d) || !has(v->dir_sched + ORC_TABLE * d)) return ORC_ERR_ARG;
     if (v->k_of_T)
         for (int32_t q = 0; q < p->n_mat; ++q)
             if (!table_ok(v->k_of_T + ORC_TABLE * q)) return ORC_ERR_ARG;
@@ -922,8 +925,8 @@ int orc_run_var(const orc_problem *p, const orc_varprops *v, double t0, double d
             if (n == 0) E0 = diag[ORC_D_E];
         }
         if (n == n_steps) break;
-        /* free nodes: H += dt r / m; fixed nodes: H(T_D + shift(t + dt)), whose
-         * change the boundary supplies */
+        /* free nodes: H += dt r / m; fixed nodes: H(f(t + dt) + shift(t + dt)) with
+         * f the node's schedule or its constant T_D; the boundary supplies the change */
         unsigned char *fixed = dirichlet_mask(p);
         if (!fixed) { rc = ORC_ERR_ARG; goto done; }
         for (int64_t i = 0; i < N; ++i)
@@ -933,7 +936,8 @@ int orc_run_var(const orc_problem *p, const orc_varprops *v, double t0, double d
         for (int64_t d = 0; d < p->n_dir; ++d) {
             int32_t i = p->dir_nodes[d];
             if (nmat[i] < 0) continue;
-            double Hn = orc_H_of_T(p->materials + 6 * nmat[i], p->dir_T[d] + shift);
+            double TD = v->dir_sched ? orc_table(v->dir_sched + ORC_TABLE * d, t + dt) : p->dir_T[d];
+            double Hn = orc_H_of_T(p->materials + 6 * nmat[i], TD + shift);
             Qcum += m[i] * (Hn - H[i]);
             H[i] = Hn;
         }

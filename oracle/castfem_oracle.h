@@ -146,7 +146,10 @@ int orc_run_apparent(const orc_problem *p, double dt, int64_t n_steps, double *H
  *             factor at (T_i + T_j) / 2;
  *   h_of_t:   factor on every interface coefficient against time;
  *   dir_of_t: shift added to every fixed temperature against time:
- *             T_i(t) = T_D,i + shift(t).
+ *             T_i(t) = T_D,i + shift(t);
+ *   dir_sched: the prescribed temperature f(x_i, t) of every fixed node as its
+ *             own table against time (n_dir tables in the order of dir_nodes),
+ *             taking the place of T_D,i: T_i(t) = f_i(t) + shift(t).
  * orc_residual_var: r = F - K T at time t with these properties.
  * orc_run_var: n explicit steps from time t0 (the state H must hold the fixed
  *   temperatures of t0); the prescribed change of a fixed node's enthalpy counts
@@ -157,6 +160,7 @@ typedef struct {
     const double *h_of_T;     /* ORC_TABLE, or NULL */
     const double *h_of_t;     /* ORC_TABLE, or NULL */
     const double *dir_of_t;   /* ORC_TABLE, or NULL */
+    const double *dir_sched;  /* n_dir x ORC_TABLE, or NULL */
 } orc_varprops;
 
 double orc_table(const double *tab, double x);

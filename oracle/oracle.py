@@ -321,7 +321,8 @@ ORC_TABLE = 17
 
 
 class _VarProps(C.Structure):
-    _fields_ = [("k_of_T", C.c_void_p), ("h_of_T", C.c_void_p), ("h_of_t", C.c_void_p), ("dir_of_t", C.c_void_p)]
+    _fields_ = [("k_of_T", C.c_void_p), ("h_of_T", C.c_void_p), ("h_of_t", C.c_void_p), ("dir_of_t", C.c_void_p),
+                ("dir_sched", C.c_void_p)]
 
 
 def table(points):
@@ -336,12 +337,15 @@ def table(points):
 
 
 class VarProps:
-    """k_of_T: per material a point list or None; h_of_T, h_of_t, dir_of_t: point lists or None."""
+    """k_of_T: per material a point list or None; h_of_T, h_of_t, dir_of_t: point lists or None;
+    dir_sched: per fixed node (in the order of dirichlet_nodes) a point list (t, T) or None."""
 
-    def __init__(self, n_mat, k_of_T=None, h_of_T=None, h_of_t=None, dir_of_t=None):
+    def __init__(self, n_mat, k_of_T=None, h_of_T=None, h_of_t=None, dir_of_t=None, dir_sched=None):
         self.k = np.concatenate([table(k_of_T[q] if k_of_T else None) for q in range(n_mat)])
         self.hT, self.ht, self.dt = table(h_of_T), table(h_of_t), table(dir_of_t)
-        self.s = _VarProps(_ptr(self.k), _ptr(self.hT), _ptr(self.ht), _ptr(self.dt))
+        self.sched = None if dir_sched is None else np.concatenate([table(s) for s in dir_sched] or [np.zeros(0)])
+        self.s = _VarProps(_ptr(self.k), _ptr(self.hT), _ptr(self.ht), _ptr(self.dt),
+                           _ptr(self.sched) if self.sched is not None and self.sched.size else None)
 
     @property
     def ref(self):
@@ -370,15 +374,17 @@ def stable_dt_var(prob, props):
 
 
 def initial_H_var(prob, props, t0=0.0):
-    """Initial enthalpy with every fixed node at T_D + shift(t0)."""
+    """Initial enthalpy with every fixed node at f(t0) + shift(t0) (f: its schedule, else T_D)."""
     P = _as_problem(prob)
     H = initial_H(P)
-    if P.keep["dir_nodes"].size and props.dt[0] > 0:
+    if P.keep["dir_nodes"].size and (props.dt[0] > 0 or props.sched is not None):
         lib().orc_table.restype = C.c_double
-        shift = lib().orc_table(_ptr(props.dt), C.c_double(t0))
+        shift = lib().orc_table(_ptr(props.dt), C.c_double(t0)) if props.dt[0] > 0 else 0.0
         nm = node_material(P)
         mats = P.keep["materials"]
-        for i, TD in zip(P.keep["dir_nodes"], P.keep["dir_T"]):
+        for d, (i, TD) in enumerate(zip(P.keep["dir_nodes"], P.keep["dir_T"])):
+            if props.sched is not None:
+                TD = lib().orc_table(_ptr(props.sched[ORC_TABLE * d:ORC_TABLE * (d + 1)]), C.c_double(t0))
             H[i] = H_of_T(mats[nm[i]], TD + shift)[0]
     return H
 

@@ -1,13 +1,19 @@
 """Pins of the oracle's temperature- and time-dependent properties: conductivity
 k(T) per element (Sec. 2 after Eq. 1), interface coefficients that vary with
 temperature and time (Eq. 8 and the remark that follows it), and a fixed
-temperature that varies in time (Eq. 3 with f(x, t)).
+temperature that varies in time, uniformly (a shift) or node by node (Eq. 3 with
+f(x, t), each fixed node with its own table against time).
 
 Checked against: the constant-property run, an independent 1-D explicit scheme
 with element-mean conductivity and a moving wall temperature (the noise-free hex
 cube reduces to it), energy conservation where the couplings stay symmetric,
 the energy identity with the prescribed change of fixed nodes counted as
-inflow, and the lumped two-body recurrence with a time-varying contact.
+inflow, and the lumped two-body recurrence with a time-varying contact.  The
+per-node form: a constant schedule is the plain fixed temperature (bit for
+bit), one schedule for every node is the shift, a bar whose two ends follow
+their own histories is an independent two-wall 1-D scheme, and a linearly
+rising wall on a semi-infinite solid converges at second order to the closed
+form 4 beta t i^2erfc(x / 2 sqrt(alpha t)).
 """
 import numpy as np
 import pytest
@@ -137,3 +143,135 @@ def test_malformed_tables_are_refused(orc):
     p = configs.tet_casting(n=4)
     with pytest.raises(ValueError):
         orc.stable_dt_var(p, orc.VarProps(2, h_of_t=[(1.0, 1.0), (0.5, 2.0)]))
+
+
+# ---------------------------------------------------------------- f(x, t) per node
+def _faces(p, lx):
+    x = p["xyz"][:, 0]
+    return np.nonzero(x == 0.0)[0], np.nonzero(np.isclose(x, lx))[0]
+
+
+def _with_walls(p, left, right):
+    q = dict(p)
+    q["dirichlet_nodes"] = np.concatenate([left, right]).astype(np.int32)
+    q["dirichlet_T"] = np.zeros(left.size + right.size)
+    return q
+
+
+def test_a_constant_schedule_is_the_fixed_temperature(orc):
+    p = configs.config1(noise_amp=2.0)
+    nd = p["dirichlet_nodes"].size
+    dt = 0.9 * orc.stable_dt(p)
+    _, T, _ = orc.run_var(p, orc.VarProps(1), dt, 150)
+    _, Ts, _ = orc.run_var(p, orc.VarProps(1, dir_sched=[[(0.0, 25.0)]] * nd), dt, 150)
+    assert np.array_equal(T, Ts)
+
+
+def test_one_schedule_for_every_node_is_the_shift(orc):
+    p = configs.config1(noise_amp=2.0)
+    nd = p["dirichlet_nodes"].size
+    dt = 0.9 * orc.stable_dt(p)
+    _, T, _ = orc.run_var(p, orc.VarProps(1, dir_of_t=SHIFT), dt, 300)
+    sched = [(t, 25.0 + s) for t, s in SHIFT]
+    _, Ts, _ = orc.run_var(p, orc.VarProps(1, dir_sched=[sched] * nd), dt, 300)
+    assert np.max(np.abs(T - Ts)) <= 1e-10
+    # both together: the schedule takes the place of T_D and the shift still adds
+    _, Tb, _ = orc.run_var(p, orc.VarProps(1, dir_of_t=SHIFT, dir_sched=[[(0.0, 25.0)]] * nd), dt, 300)
+    assert np.max(np.abs(T - Tb)) <= 1e-10
+
+
+def _ftcs_1d_two_walls(T0, n, h, dt, steps, mat, left_of, right_of):
+    """1-D explicit scheme on n+1 nodes, constant k, both ends prescribed (written
+    independently of the oracle)."""
+    k, rho, c, Ts, Tl, L = mat
+
+    def H_of(T):
+        return c * T + L * np.clip((T - Ts) / (Tl - Ts), 0.0, 1.0)
+
+    def T_of(H):
+        Hs, Hl = c * Ts, c * Tl + L
+        return np.where(H <= Hs, H / c, np.where(H >= Hl, (H - L) / c,
+                                                 Ts + (H - Hs) * (Tl - Ts) / (c * (Tl - Ts) + L)))
+
+    T = np.full(n + 1, float(T0))
+    T[0], T[-1] = left_of(0.0), right_of(0.0)
+    H = H_of(T)
+    for s in range(steps):
+        T = T_of(H)
+        flux = k * (T[1:] - T[:-1]) / h
+        H[1:-1] = H[1:-1] + dt * (flux[1:] - flux[:-1]) / (rho * h)
+        t = (s + 1) * dt
+        H[0], H[-1] = H_of(np.array([left_of(t), right_of(t)]))
+    return T_of(H)
+
+
+def test_two_walls_with_their_own_schedules_is_the_1d_scheme(orc):
+    """Each end of a bar follows its own piecewise-linear history (a ramp with a
+    hold on one, an oscillation on the other): the nodes of the two faces read
+    different tables at the same time."""
+    lx, nx = 0.1, 16
+    h = lx / nx
+    p = configs.hex_bar(nx=nx, ny=1, nz=1, lx=lx, ly=h, lz=h, T_init=700.0)
+    left, right = _faces(p, lx)
+    q = _with_walls(p, left, right)
+    L_s = [(0.0, 700.0), (8.0, 400.0), (20.0, 400.0), (30.0, 200.0)]
+    R_s = [(0.0, 700.0), (5.0, 650.0), (10.0, 720.0), (15.0, 600.0), (25.0, 690.0)]
+    v = orc.VarProps(1, dir_sched=[L_s] * left.size + [R_s] * right.size)
+    dt = 0.9 * orc.stable_dt_var(q, v)
+    steps = int(32.0 / dt)
+    _, T, fs = orc.run_var(q, v, dt, steps)
+    interp = lambda pts: (lambda t: np.interp(t, [a for a, b in pts], [b for a, b in pts]))
+    ref = _ftcs_1d_two_walls(700.0, nx, h, dt, steps, ALLOY, interp(L_s), interp(R_s))
+    i = np.rint(p["xyz"][:, 0] / h).astype(int)
+    assert np.max(np.abs(T - ref[i])) <= 1e-9
+    assert T[left].max() == pytest.approx(200.0, abs=1e-9) and T[right].max() == pytest.approx(690.0, abs=1e-9)
+    assert np.min(fs) < 1.0 and np.max(fs) > 0.0        # the walls drive the bar through the mushy range
+
+
+def _ramp_error(orc, nx, beta=5.0, t_end=40.0):
+    lx = 0.4
+    h = lx / nx
+    k, rho, c = K_AL, RHO_AL, C_AL
+    alpha = k / (rho * c)
+    p = configs.hex_bar(nx=nx, ny=1, nz=1, lx=lx, ly=h, lz=h, T_init=25.0, material=(k, rho, c, 0.0, 0.0, 0.0))
+    nd = p["dirichlet_nodes"].size
+    v = orc.VarProps(1, dir_sched=[[(0.0, 25.0), (t_end, 25.0 + beta * t_end)]] * nd)
+    steps = int(np.ceil(t_end / (0.45 * h * h / alpha)))
+    _, T, _ = orc.run_var(p, v, t_end / steps, steps)
+    from scipy import special
+    z = p["xyz"][:, 0] / (2.0 * np.sqrt(alpha * t_end))
+    i2 = (1.0 + 2.0 * z * z) * special.erfc(z) - 2.0 / np.sqrt(np.pi) * z * np.exp(-z * z)   # 4 i^2erfc(z)
+    return np.max(np.abs(T - (25.0 + beta * t_end * i2)))
+
+
+def test_linearly_rising_wall_is_the_closed_form(orc):
+    """Semi-infinite solid whose surface temperature rises as T0 + beta t:
+    T - T0 = 4 beta t i^2erfc(x / (2 sqrt(alpha t))) (the repeated integral of the
+    complementary error function), approached at second order in h."""
+    e1, e2, e3 = _ramp_error(orc, 64), _ramp_error(orc, 128), _ramp_error(orc, 256)
+    assert e3 < 0.05          # of a 200 K rise
+    assert 3.2 < e1 / e2 < 5.0 and 3.2 < e2 / e3 < 5.0
+
+
+def test_energy_identity_with_a_schedule_that_varies_over_the_face(orc):
+    p = configs.config1(noise_amp=2.0)
+    d = p["dirichlet_nodes"]
+    y = p["xyz"][d, 1] / 0.1
+    dt = 0.9 * orc.stable_dt_var(p, orc.VarProps(1, k_of_T=[K_TAB]))
+    sched = [[(0.0, 25.0 + 30.0 * yy), (150 * dt, 500.0 - 100.0 * yy), (600 * dt, 60.0)] for yy in y]
+    v = orc.VarProps(1, k_of_T=[K_TAB], dir_sched=sched)
+    assert orc.stable_dt_var(p, v) == pytest.approx(dt / 0.9, rel=1e-15)
+    H, T, _, D = orc.run_var(p, v, dt, 400, diag=True)
+    assert D[-1, orc.D_RESID] <= 1e-12
+    t = 400 * dt
+    assert np.max(np.abs(T[d] - np.array([np.interp(t, [a for a, b in s], [b for a, b in s]) for s in sched]))) <= 1e-9
+    # the face is not uniform: the field is not that of the one-schedule run
+    _, T1, _ = orc.run_var(p, orc.VarProps(1, k_of_T=[K_TAB], dir_sched=[sched[0]] * d.size), dt, 400)
+    assert np.max(np.abs(T - T1)) > 1.0
+
+
+def test_malformed_schedules_are_refused(orc):
+    p = configs.config1()
+    nd = p["dirichlet_nodes"].size
+    with pytest.raises(ValueError):
+        orc.stable_dt_var(p, orc.VarProps(1, dir_sched=[[(1.0, 25.0), (0.5, 30.0)]] * nd))
