@@ -218,6 +218,21 @@ int fem_get_sisters(const fem_ctx *ctx, int32_t *sister);
  * Call before fem_finalize. */
 int fem_set_variable_properties(fem_ctx *ctx, int32_t n_mat, const fem_table *k_of_T, const fem_table *h_of_T,
                                 const fem_table *h_of_t, const fem_table *dir_of_t);
+/* Prescribed temperature as a function of place and time, T = f(x, t) on the
+ * fixed-temperature boundary (Eq. 3), node by node: n_times common times
+ * times[0] < ... < times[n_times - 1] (s, 1 <= n_times <= 8) and, for the k-th
+ * node of fem_set_dirichlet (in its order), its temperatures at those times in
+ * values[k * n_times .. k * n_times + n_times - 1] (C), linear in between and
+ * constant beyond the ends.  The schedule takes the place of the constant
+ * values of fem_set_dirichlet (a node starts at f(x, 0)); a dir_of_t shift of
+ * fem_set_variable_properties still adds.  The prescribed change of a fixed
+ * node's enthalpy counts as boundary inflow.  Both arrays are host memory,
+ * copied.  Makes the context one with variable properties (the same limits:
+ * one scenario, enthalpy form, LDS-blocked scatter, no surrogate or state
+ * restore).  Call after fem_set_dirichlet and before fem_finalize; errors:
+ * FEM_E_STATE (no fixed nodes, or after fem_finalize), FEM_E_INVALID_ARG (count
+ * out of range, times not increasing, a value not finite). */
+int fem_set_dirichlet_schedule(fem_ctx *ctx, int32_t n_times, const double *times, const double *values);
 /* Initial temperature of every node (Eq. 2); fixed nodes take their value. */
 int fem_set_initial_T(fem_ctx *ctx, const double *T0);
 /* Batch of independent casting scenarios in one mesh: material_scenario[m]

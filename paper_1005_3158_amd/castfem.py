@@ -42,6 +42,7 @@ EXPORTS = [
     "fem_sur_n_params", "fem_sur_get_params", "fem_sur_set_params", "fem_sur_features", "fem_sur_loss_grad",
     "fem_sur_train", "fem_sur_predict", "fem_snapshot_H", "fem_advance", "fem_sur_generate", "fem_sur_save",
     "fem_sur_load", "fem_set_contact", "fem_get_sisters", "fem_set_variable_properties",
+    "fem_set_dirichlet_schedule",
 ]
 
 
@@ -164,6 +165,7 @@ def lib():
             "fem_sur_save": [vp, C.c_char_p], "fem_sur_load": [vp, C.c_char_p],
             "fem_set_contact": [vp, i64, vp, vp, vp], "fem_get_sisters": [vp, vp],
             "fem_set_variable_properties": [vp, i32, vp, vp, vp, vp],
+            "fem_set_dirichlet_schedule": [vp, i32, vp, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -250,6 +252,13 @@ def fem_set_variable_properties(ctx, n_mat, k_of_T=None, h_of_T=None, h_of_t=Non
     tabs = [make_table(t) for t in (h_of_T, h_of_t, dir_of_t)]
     _call("fem_set_variable_properties", ctx, int(n_mat), C.cast(ks, C.c_void_p),
           *[C.cast(C.byref(t), C.c_void_p) for t in tabs])
+
+
+def fem_set_dirichlet_schedule(ctx, times, values):
+    """times: n common times; values: (fixed nodes x n) temperatures, in the order of fem_set_dirichlet."""
+    t = np.ascontiguousarray(times, dtype=np.float64)
+    v = np.ascontiguousarray(values, dtype=np.float64)
+    _call("fem_set_dirichlet_schedule", ctx, int(t.size), _p(t), _p(v))
 
 
 def fem_get_sisters(ctx, n):
@@ -515,6 +524,8 @@ def setup_problem(ctx, prob):
         fem_set_contact(ctx, prob["contact_faces"], prob["contact_side"], prob["contact_h"])
     if prob.get("varprops"):
         fem_set_variable_properties(ctx, len(prob["materials"]), **prob["varprops"])
+    if prob.get("dirichlet_schedule") is not None:
+        fem_set_dirichlet_schedule(ctx, *prob["dirichlet_schedule"])
     fem_set_initial_T(ctx, prob["T0"])
     if "mat_scenario" in prob:
         fem_set_scenarios(ctx, prob["mat_scenario"])

@@ -54,6 +54,7 @@ void layout_sizes(const fem_ctx *c, const Layout &L, int64_t *sz) {
             sz[B_VAR_TABS_D] = (int64_t)c->vtabs.size() * (int64_t)sizeof(Tab<double>);
             sz[B_T_FIXED] = N * 8;
             sz[B_TIME] = 16;
+            sz[B_SCHED] = L.n_inflow * (int64_t)c->sched_t.size() * 8;
         }
     }
     sz[B_ROBIN] = (int64_t)L.robin_a.size() * 2 * R;
@@ -251,7 +252,7 @@ void upload_layout_t(fem_ctx *c, const Layout &L) {
         h2d(c, B_APP_MATS, am.data(), (int64_t)(am.size() * sizeof(AppMat)));
     }
     std::vector<Tab<float>> tf;
-    std::vector<double> tfix, t0(2, 0.0);
+    std::vector<double> tfix, sched, t0(2, 0.0);
     if (c->variable()) {
         for (const Tab<double> &t : c->vtabs) {
             Tab<float> u{};
@@ -269,6 +270,16 @@ void upload_layout_t(fem_ctx *c, const Layout &L) {
             if (L.nflag[n] & NODE_FIXED) tfix[n] = L.T_init[n];
         h2d(c, B_T_FIXED, tfix.data(), N * 8);
         h2d(c, B_TIME, t0.data(), 16);
+        if (const int64_t K = (int64_t)c->sched_t.size()) {
+            // the rows of the fixed nodes' schedules at their shared slots
+            sched.assign(L.n_inflow * K, 0.0);
+            for (size_t q = 0; q < c->prob.dir_nodes.size(); ++q) {
+                const int64_t slot = (int64_t)L.perm[c->prob.dir_nodes[q]] - L.bc_first;
+                if (slot < 0 || slot >= L.n_inflow) throw PrepError{FEM_E_INVALID_ARG, "fixed node outside the inflow slots"};
+                std::copy(c->sched_T.begin() + q * K, c->sched_T.begin() + (q + 1) * K, sched.begin() + slot * K);
+            }
+            h2d(c, B_SCHED, sched.data(), L.n_inflow * K * 8);
+        }
     }
     int64_t sz[B_COUNT];
     layout_sizes(c, L, sz);
@@ -358,6 +369,11 @@ void fill_dev(fem_ctx *c, const Candidate &cd) {
         v.tabs_d = (const Tab<double> *)c->ptr[B_VAR_TABS_D];
         v.T_fixed = (const double *)c->ptr[B_T_FIXED];
         v.time = (double *)c->ptr[B_TIME];
+        v.n_sched = (int32_t)c->sched_t.size();
+        if (v.n_sched) {
+            v.sched = (const double *)c->ptr[B_SCHED];
+            for (int k = 0; k < v.n_sched; ++k) v.sched_t[k] = c->sched_t[k];
+        }
         c->vdev = v;
     }
 }
@@ -690,6 +706,25 @@ int fem_set_variable_properties(fem_ctx *ctx, int32_t n_mat, const fem_table *k_
     });
 }
 
+int fem_set_dirichlet_schedule(fem_ctx *ctx, int32_t n_times, const double *times, const double *values) {
+    if (!ctx) return set_err(FEM_E_INVALID_ARG, "ctx is null");
+    return guarded([&] {
+        if (ctx->stage != ST_NEW) throw PrepError{FEM_E_STATE, "the schedule must be given before fem_finalize"};
+        const int64_t nd = (int64_t)ctx->prob.dir_nodes.size();
+        if (nd == 0) throw PrepError{FEM_E_STATE, "no fixed-temperature nodes (fem_set_dirichlet first)"};
+        if (n_times < 1 || n_times > TAB_POINTS) throw PrepError{FEM_E_INVALID_ARG, "a schedule holds 1 to 8 times"};
+        if (!times || !values) throw PrepError{FEM_E_INVALID_ARG, "null schedule array"};
+        for (int k = 0; k < n_times; ++k) {
+            if (!std::isfinite(times[k])) throw PrepError{FEM_E_INVALID_ARG, "schedule times must be finite"};
+            if (k > 0 && !(times[k] > times[k - 1])) throw PrepError{FEM_E_INVALID_ARG, "schedule times must increase"};
+        }
+        for (int64_t i = 0; i < nd * n_times; ++i)
+            if (!std::isfinite(values[i])) throw PrepError{FEM_E_INVALID_ARG, "scheduled temperatures must be finite"};
+        ctx->sched_t.assign(times, times + n_times);
+        ctx->sched_T.assign(values, values + nd * n_times);
+    });
+}
+
 int fem_set_initial_T(fem_ctx *ctx, const double *T0) {
     if (!ctx) return set_err(FEM_E_INVALID_ARG, "ctx is null");
     return guarded([&] {
@@ -706,6 +741,26 @@ int fem_finalize(fem_ctx *ctx, fem_prep_report *rep) {
         if (ctx->stage != ST_NEW) throw PrepError{FEM_E_STATE, "already finalized"};
         if (!ctx->have_mesh) throw PrepError{FEM_E_STATE, "no mesh uploaded"};
         auto t0 = std::chrono::steady_clock::now();
+        double sched_lo = INFINITY, sched_hi = -INFINITY;
+        if (const size_t K = ctx->sched_t.size()) {
+            // a node-by-node prescribed temperature: the context takes the
+            // variable-property step, and every fixed node starts at f(x, 0)
+            Problem &p = ctx->prob;
+            if (ctx->sched_T.size() != p.dir_nodes.size() * K)
+                throw PrepError{FEM_E_INVALID_ARG, "the schedule does not match the fixed-temperature set"};
+            if (ctx->vtabs.empty()) ctx->vtabs.assign(p.mats.size() + TAB_GLOBAL, Tab<double>{});
+            Tab<double> row{};
+            row.n = (int32_t)K;
+            for (size_t k = 0; k < K; ++k) row.x[k] = ctx->sched_t[k];
+            for (size_t q = 0; q < p.dir_nodes.size(); ++q) {
+                for (size_t k = 0; k < K; ++k) {
+                    row.y[k] = ctx->sched_T[q * K + k];
+                    sched_lo = std::min(sched_lo, row.y[k]);
+                    sched_hi = std::max(sched_hi, row.y[k]);
+                }
+                p.dir_T[q] = tab_eval_host(row, 0.0);
+            }
+        }
         if (ctx->apparent()) {
             if (ctx->prob.nen != FEM_TET4) throw PrepError{FEM_E_UNSUPPORTED, "apparent capacity: linear tetrahedra only"};
             if (ctx->opt.scatter != FEM_SCATTER_LDS_BLOCKED)
@@ -742,6 +797,19 @@ int fem_finalize(fem_ctx *ctx, fem_prep_report *rep) {
             for (int j = 0; j < sh.n; ++j) {
                 smin = std::min(smin, sh.y[j]);
                 smax = std::max(smax, sh.y[j]);
+            }
+            if (sched_hi >= sched_lo) {
+                // the scheduled values join the span of the data (initial field, fixed and ambient temperatures)
+                double lo = sched_lo, hi = sched_hi;
+                for (double T : base.T_init) {
+                    lo = std::min(lo, T);
+                    hi = std::max(hi, T);
+                }
+                for (double T : ctx->prob.flux_Tinf) {
+                    lo = std::min(lo, T);
+                    hi = std::max(hi, T);
+                }
+                base.T_span = std::max(base.T_span, hi - lo);
             }
             base.T_span += smax - smin;
         }

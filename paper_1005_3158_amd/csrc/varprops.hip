@@ -47,6 +47,18 @@ __device__ __forceinline__ R tab_eval(const Tab<R> &t, R x) {
     return t.y[j] + (t.y[j + 1] - t.y[j]) * (x - t.x[j]) / (t.x[j + 1] - t.x[j]);
 }
 
+// the scheduled temperature of shared slot s at time x: its row of values over
+// the common times, linear in between, constant beyond the ends (as tab_eval)
+__device__ __forceinline__ double sched_value(const VarDev &v, int64_t s, double x) {
+    const int n = v.n_sched;
+    const double *y = v.sched + s * n;
+    if (x <= v.sched_t[0]) return y[0];
+    if (x >= v.sched_t[n - 1]) return y[n - 1];
+    int j = 0;
+    while (j + 2 < n && !(x < v.sched_t[j + 1])) ++j;
+    return y[j] + (y[j + 1] - y[j]) * (x - v.sched_t[j]) / (v.sched_t[j + 1] - v.sched_t[j]);
+}
+
 template <class R, int NEN>
 __device__ __forceinline__ void elem_residual(const typename VT<R>::V4 *p, R k, R *r) {
     if constexpr (NEN == 4) {
@@ -216,9 +228,12 @@ __global__ __launch_bounds__(NODE_THREADS) void k_nodes_var(VarDev v, int parity
     double qfix = 0.0;
     if (f & NODE_FIXED) {
         q -= (double)r;   // reaction of a fixed temperature
-        if (tab_given(gd[TAB_DIR_OF_TIME].n)) {
+        const bool shifted = tab_given(gd[TAB_DIR_OF_TIME].n);
+        if (shifted || v.n_sched) {
             // the prescribed temperature of the next state; its enthalpy change is inflow
-            const double Tnew = v.T_fixed[g] + tab_eval(gd[TAB_DIR_OF_TIME], t + dt);
+            const double tn = t + dt;
+            const double Tnew = (v.n_sched ? sched_value(v, s, tn) : v.T_fixed[g]) +
+                                (shifted ? tab_eval(gd[TAB_DIR_OF_TIME], tn) : 0.0);
             const double Hn = h_of_t(M, Tnew);
             double Hold, Tchk, fs;
             if constexpr (std::is_same<R, float>::value) {

@@ -2,7 +2,7 @@
 // element conductivity k(T) at the element's mean temperature (Sec. 2 after
 // Eq. 1: K re-weighted per element and step), interface coefficients scaled by
 // factors of temperature and time (Eq. 8 and the remark after it), and fixed
-// temperatures shifted in time (Eq. 3 with f(x, t)).
+// temperatures that vary in time, uniformly or node by node (Eq. 3 with f(x, t)).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -29,6 +29,12 @@ struct VarDev {
     const Tab<double> *tabs_d = nullptr;
     const double *T_fixed = nullptr;    // per node: the fixed temperature before its time shift
     double *time = nullptr;             // [2]: time of the state held in T buffer 0 and 1
+    // prescribed temperature f(x, t) node by node: n_sched common times and, per
+    // shared slot s < n_inflow (every fixed node has one), its n_sched values
+    // (rows of other slots unused); n_sched = 0: the constant T_fixed
+    const double *sched = nullptr;
+    int32_t n_sched = 0, pad_ = 0;
+    double sched_t[TAB_POINTS] = {};
 };
 
 __host__ __device__ inline bool tab_given(int32_t n) { return n > 0; }

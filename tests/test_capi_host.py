@@ -243,3 +243,44 @@ def test_variable_properties_bound_and_refusals(orc):
             cf.setup_problem(ctx, dict(configs.config2(n=4), varprops=bad))
         assert e.value.code == -1
         cf.fem_destroy(ctx)
+
+
+def test_dirichlet_schedule_checks_and_layout():
+    """Host side of the node-by-node prescribed temperature: call order, malformed
+    schedules, a schedule that no longer matches the fixed set, the colored scatter
+    refused; a valid one makes the context one with variable properties (its
+    buffers appear) and sets the fixed nodes' starting values to f(x, 0)."""
+    p = configs.config1()
+    nd = p["dirichlet_nodes"].size
+    good = (np.array([0.0, 1.0, 3.0]), np.tile([40.0, 80.0, 20.0], (nd, 1)))
+    ctx = cf.fem_create(cf.make_options())
+    cf.fem_upload_mesh(ctx, p["elem_type"], p["xyz"], p["conn"], p["elem_mat"])
+    cf.fem_set_materials(ctx, p["materials"])
+    with pytest.raises(cf.FemError) as e:          # no fixed nodes yet
+        cf.fem_set_dirichlet_schedule(ctx, *good)
+    assert e.value.code == -3
+    cf.fem_set_dirichlet(ctx, p["dirichlet_nodes"], p["dirichlet_T"])
+    for times, values in ((np.array([0.0, 0.0]), np.zeros((nd, 2))), (np.arange(9.0), np.zeros((nd, 9))),
+                          (np.array([0.0, 1.0]), np.full((nd, 2), np.nan))):
+        with pytest.raises(cf.FemError) as e:
+            cf.fem_set_dirichlet_schedule(ctx, times, values)
+        assert e.value.code == -1
+    cf.fem_set_dirichlet_schedule(ctx, *good)
+    cf.fem_set_dirichlet(ctx, p["dirichlet_nodes"][:-1], p["dirichlet_T"][:-1])   # the set changed
+    cf.fem_set_initial_T(ctx, p["T0"])
+    with pytest.raises(cf.FemError) as e:
+        cf.fem_finalize(ctx)
+    assert e.value.code == -1
+    cf.fem_destroy(ctx)
+    q = dict(p, dirichlet_schedule=good)
+    ctx = cf.fem_create(cf.make_options(scatter=cf.FEM_SCATTER_COLORED))
+    with pytest.raises(cf.FemError) as e:
+        cf.setup_problem(ctx, q)
+    assert e.value.code == -7
+    cf.fem_destroy(ctx)
+    ctx = cf.fem_create(cf.make_options(lds_bytes=cf.lds_for_nodes(512)))
+    cf.setup_problem(ctx, q)
+    names = {n: b for n, b, _ in cf.fem_query_buffers(ctx)}
+    cf.fem_destroy(ctx)
+    assert names["dirichlet_schedule"] >= nd * 3 * 8
+    assert names["var_tables_f64"] > 0

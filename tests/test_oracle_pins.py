@@ -515,3 +515,46 @@ def test_p16_constant_flux_energy(orc):
     dE = D[1:, orc.D_E] - D[:-1, orc.D_E]
     assert np.allclose(dE, 2.0e4 * A * dt, rtol=1e-10)
     assert np.allclose(D[:, orc.D_Q], 2.0e4 * A, rtol=1e-12)
+
+
+# ------------------------------------------------------------------ diagnostics
+def test_diagnostics_of_the_state(orc):
+    """The latent heat still to release, the T range and the liquid count of the
+    diagnostics against the returned state (numpy) and the closed form of the
+    start: the cube is liquid but for its chilled face, which starts solid and
+    whose nodes carry the half-cell layer of lumped mass (A h / 2), so
+    rho L (V - A h / 2) of latent heat is left."""
+    p = configs.config1()
+    dt = 0.9 * orc.stable_dt(p)
+    H, T, fs, D = orc.run(p, dt, 300, diag=True)
+    m = orc.lumped_mass(p)
+    L = ALLOY[5]
+    h = 0.1 / 16
+    assert D[0, orc.D_LATENT] == pytest.approx(RHO_AL * L * (0.1 ** 3 - 0.1 ** 2 * h / 2), rel=1e-12)
+    assert D[0, orc.D_NLIQ] == p["xyz"].shape[0] - p["dirichlet_nodes"].size   # the chilled face starts solid
+    assert D[-1, orc.D_LATENT] == pytest.approx(float(np.sum(m * L * (1.0 - fs))), rel=1e-12)
+    assert D[-1, orc.D_TMIN] == T.min() and D[-1, orc.D_TMAX] == T.max()
+    assert D[-1, orc.D_NLIQ] == np.count_nonzero(fs < 1.0)
+    assert 0 < D[-1, orc.D_NLIQ] < D[0, orc.D_NLIQ]
+
+
+def test_latent_heat_left_follows_the_neumann_front(orc):
+    """Isothermal solidification of a bar from a chilled end: the latent heat still
+    to release is rho L A (l - X(t)) with the Neumann front X = 2 lambda sqrt(alpha t)."""
+    St = C_AL * (660.0 - 25.0) / 3.9e5
+    lam = neumann_lambda(St)
+    nx, lx = 32, 0.1
+    h = lx / nx
+    mat = (K_AL, RHO_AL, C_AL, 660.0, 660.0, 3.9e5)
+    p = configs.hex_bar(nx=nx, ny=1, nz=1, lx=lx, ly=h, lz=h, T_init=660.0, material=mat)
+    dt = 0.45 * h * h / ALPHA
+    x = p["xyz"][:, 0]
+    H = orc.initial_H(p)
+    H[x > 0] = C_AL * 660.0 + 3.9e5
+    steps = int(round(75.0 / dt))
+    _, _, _, D = orc.run(p, dt, steps, H=H, diag=True)
+    for n in (steps // 2, steps):
+        t = n * dt
+        front = 2 * lam * math.sqrt(ALPHA * t)
+        exact = RHO_AL * 3.9e5 * h * h * (lx - front)
+        assert abs(D[n, orc.D_LATENT] - exact) <= 0.02 * RHO_AL * 3.9e5 * h * h * front

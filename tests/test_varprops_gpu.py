@@ -1,6 +1,7 @@
 """GPU parity of temperature- and time-dependent properties (k(T) per element,
-interface factors h(T) and h(t), time-shifted fixed temperatures) against the
-oracle's variable-property mode, through the C interface.
+interface factors h(T) and h(t), fixed temperatures shifted in time or
+scheduled node by node, f(x, t)) against the oracle's variable-property mode,
+through the C interface.
 
 Tolerances as for constant properties: FP64 1e-8 K; FP32 1e-3 K away from the
 freezing range and 0.05 K within 5 K of it.
@@ -37,9 +38,17 @@ def _with(p, **vp):
     return q
 
 
+def _oracle_props(orc, p):
+    kw = dict(p.get("varprops") or {})
+    if p.get("dirichlet_schedule") is not None:
+        times, values = p["dirichlet_schedule"]
+        kw["dir_sched"] = [list(zip(times, row)) for row in np.asarray(values).reshape(-1, len(times))]
+    return orc.VarProps(len(p["materials"]), **kw)
+
+
 def _compare(orc, p, steps, precision, **opts):
     cf = _cf()
-    vp = orc.VarProps(len(p["materials"]), **p["varprops"])
+    vp = _oracle_props(orc, p)
     dt = 0.9 * orc.stable_dt_var(p, vp)
     _, T_ref, fs_ref, D = orc.run_var(p, vp, dt, steps, diag=True)
     s = cf.Solver(p, precision=precision, **opts)
@@ -117,3 +126,48 @@ def test_surrogate_and_checkpoint_restore_are_refused():
         cf.fem_write_state(s.ctx, ck)
     assert e.value.code == -7
     s.close()
+
+
+def _scheduled(p, nodes, times, fn):
+    """p with `nodes` held at fn(x, t) at the given times (a node-by-node schedule)."""
+    q = dict(p)
+    q["dirichlet_nodes"] = np.asarray(nodes, np.int32)
+    q["dirichlet_T"] = np.zeros(len(nodes))
+    x = p["xyz"][nodes]
+    q["dirichlet_schedule"] = (np.asarray(times, float), np.stack([fn(x, t) for t in times], axis=1))
+    return q
+
+
+def test_fp64_hex_cube_with_a_schedule_over_the_face(orc):
+    cf = _cf()
+    base = configs.config1()
+    dt = 0.9 * orc.stable_dt(base)
+    d = base["dirichlet_nodes"]
+    p = _with(_scheduled(base, d, [0.0, 120 * dt, 260 * dt, 400 * dt],
+                         lambda x, t: 25.0 + 4000.0 * x[:, 1] * (1.0 + np.sin(3.0e3 * t * x[:, 2])) + t / dt),
+              k_of_T=[K_CAST], dir_of_t=SHIFT)
+    T, fs, en, T_ref, fs_ref, D = _compare(orc, p, 300, cf.FEM_PREC_FP64, block_elems=512)
+    err = float(np.max(np.abs(T - T_ref)))
+    print("node-by-node schedule, hex fp64: max|dT| = %.3e K, Q_cum %.6e (oracle %.6e), residual %.2e"
+          % (err, en["Q_cum"], D[-1, orc.D_QCUM], en["residual"]), flush=True)
+    assert err <= 1e-8
+    assert en["Q_cum"] == pytest.approx(D[-1, orc.D_QCUM], rel=1e-9)
+    assert en["residual"] <= 1e-11
+    assert np.ptp(T[d]) > 50.0       # the face is not uniform
+
+
+def test_fp32_tets_with_a_scheduled_mould_face(orc):
+    cf = _cf()
+    base = configs.config2(n=14)
+    x = base["xyz"]
+    face = np.nonzero(x[:, 0] <= 1e-12)[0]
+    dt = 0.9 * orc.stable_dt(base)
+    p = _with(_scheduled(base, face, [0.0, 500 * dt, 1500 * dt],
+                         lambda xx, t: 25.0 + (t / (1500 * dt)) * (300.0 + 2000.0 * xx[:, 1])),
+              k_of_T=[K_CAST, K_SAND])
+    T, fs, en, T_ref, fs_ref, D = _compare(orc, p, 2000, cf.FEM_PREC_FP32_KAHAN)
+    off, on, nb = _band(T, T_ref)
+    print("node-by-node schedule, tets fp32: max|dT| off-front %.3e K, band %.3e K (%d nodes); energy residual %.3e "
+          "(oracle %.3e)" % (off, on, nb, en["residual"], D[-1, orc.D_RESID]), flush=True)
+    assert off <= 1e-3 and on <= 0.05
+    assert float(np.max(np.abs(fs - fs_ref))) <= 1e-3
