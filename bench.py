@@ -139,14 +139,12 @@ def main():
                     help="apparent: steps of both forms compared for energy drift and front position")
     ap.add_argument("--train-traj", type=int, default=500, help="surrogate: training trajectories (seeds 5000+)")
     ap.add_argument("--held-out", type=int, default=None,
-                    help="surrogate: held-out trajectories (seeds 5500+); default 50, or 20 inside the default run")
+                    help="surrogate: held-out trajectories (seeds 5500+); default 50")
     ap.add_argument("--epochs", type=int, default=8, help="surrogate: training epochs per round")
-    ap.add_argument("--horizon", type=int, default=32,
-                    help="surrogate: steps one jump covers (32: the shortest on the plateau of the measured sweep)")
+    ap.add_argument("--horizon", type=int, default=16, help="surrogate: steps one jump covers")
     ap.add_argument("--rounds", type=int, default=1, help="surrogate: training rounds (later ones through jumps)")
-    ap.add_argument("--verify-tol", type=float, default=2.0,
-                    help="surrogate: one-step verification tolerance (K); 2 K keeps every held-out run within 0.5 K "
-                         "at the 32-step horizon")
+    ap.add_argument("--verify-tol", type=float, default=3.0,
+                    help="surrogate: one-step verification tolerance (K)")
     ap.add_argument("--fs-tol", type=float, default=1e-6,
                     help="surrogate: largest fall of a node's fraction solid a kept jump may cause")
     ap.add_argument("--no-surrogate", action="store_true", help="default run: skip the surrogate comparison")
@@ -260,7 +258,7 @@ def main():
     if not args.no_surrogate:
         # the metric's second part: time to solidify, plain vs surrogate, measured against the plain run
         if args.held_out is None:
-            args.held_out = 20
+            args.held_out = 50
         sur = run_surrogate(args, log)
         keep = ("metric", "value", "unit", "plain_seconds", "surrogate_seconds", "max_err_K", "median_err_K",
                 "within_0p5K", "n_held_out", "jumps_kept", "jumps_rejected", "explicit_steps_computed_frac",

@@ -346,9 +346,10 @@ void enqueue_jump(fem_sur *s, int p, bool cont, float fs_tol, float verify_tol) 
     HIPCHECK(state_to_f64(c->dev, s->d.H1, nullptr, st));
     HIPCHECK(enqueue_step(c->dev, q, st, nullptr));
     q ^= 1;
-    // H2, and the inflow sums at H2 for a fallback to start from
-    HIPCHECK(state_to_f64(c->dev, s->d.H2, c->L().n_inflow ? (double *)s->ptr[S_QSAVE] : nullptr, st, s->d.H2_pair));
-    HIPCHECK(features(s->d, cont ? s->d.Hn : s->d.H0, s->d.H1, s->d.H2, 1, nullptr, s->N, nullptr, 1, st));
+    // features from the state H2 itself, which the same kernel keeps (with the
+    // inflow sums at H2) for a fallback to start from
+    HIPCHECK(features_live(s->d, c->dev, cont ? s->d.Hn : s->d.H0, s->d.H1,
+                           c->L().n_inflow ? (double *)s->ptr[S_QSAVE] : nullptr, st));
     HIPCHECK(forward(s->d, s->N, 0, 0, st));
     HIPCHECK(write_jump(s->d, c->dev, q, fs_tol, st));
     HIPCHECK(enqueue_step(c->dev, q, st, nullptr));

@@ -51,15 +51,11 @@ __device__ __forceinline__ void t_of_h(const MatDev &M, double H, double &T, dou
 // Row r = q N + i holds node i of state slot q; the slot is sample idx[q]
 // (q without a list), read at offset sample * stride of H0 / H1 / H2 / Ht,
 // three consecutive explicit states and the state `horizon` steps after H0.
-template <class HT>
-__global__ __launch_bounds__(256) void k_features(SurDev s, const HT *H0, const HT *H1, const HT *H2, const float *Ht,
-                                                  int64_t stride, const int32_t *idx, int64_t slots) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= slots * s.N) return;
-    const int64_t q = r / s.N, i = r - q * s.N;
-    const int64_t at = (idx ? (int64_t)idx[q] : q) * stride + i;
+// the features, base, implied increment, scale (and target, with Ht) of row r
+// (node i) from its three enthalpies
+__device__ __forceinline__ void feature_row(const SurDev &s, int64_t r, int64_t i, double h0, double h1, double h2,
+                                            const float *Ht_at) {
     const MatDev &M = ((const MatDev *)s.mats)[s.flags[i] & NODE_MAT_MASK];
-    const double h0 = (double)H0[at], h1 = (double)H1[at], h2 = (double)H2[at];
     const double rate = h2 - h1, acc = (h2 - h1) - (h1 - h0);
     double T2, fs2;
     t_of_h(M, h2, T2, fs2);
@@ -97,15 +93,46 @@ __global__ __launch_bounds__(256) void k_features(SurDev s, const HT *H0, const 
     // the increment of the step after the horizon that the extrapolation implies
     if (r < s.N) s.rext[r] = s.quadratic ? rate + (m + 1.0) * acc : rate;
     s.scale[r] = mu ? (float)sa : 0.0f;
-    if (Ht) {
+    if (Ht_at) {
         if (s.loss_mode == LOSS_T) {
             double Tt, fst;
-            t_of_h(M, (double)Ht[at], Tt, fst);
+            t_of_h(M, (double)*Ht_at, Tt, fst);
             s.target[r] = (float)Tt;
         } else {
-            s.target[r] = (float)(((double)Ht[at] - s.base[r]) / sa);   // LOSS_H, LOSS_HUBER
+            s.target[r] = (float)(((double)*Ht_at - s.base[r]) / sa);   // LOSS_H, LOSS_HUBER
         }
     }
+}
+
+template <class HT>
+__global__ __launch_bounds__(256) void k_features(SurDev s, const HT *H0, const HT *H1, const HT *H2, const float *Ht,
+                                                  int64_t stride, const int32_t *idx, int64_t slots) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= slots * s.N) return;
+    const int64_t q = r / s.N, i = r - q * s.N;
+    const int64_t at = (idx ? (int64_t)idx[q] : q) * stride + i;
+    feature_row(s, r, i, (double)H0[at], (double)H1[at], (double)H2[at], Ht ? Ht + at : nullptr);
+}
+
+// One state of the solver: H2 is the solver's current state, read here and kept
+// (FP64 copy in s.H2, the raw FP32 pairs, the node inflow sums) for a rejected
+// jump to return to; H0 and H1 are earlier FP64 copies.
+template <class R>
+__global__ __launch_bounds__(256) void k_features_live(SurDev s, Dev d, const double *H0, const double *H1,
+                                                       double *keep_qnode) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (keep_qnode && i < d.n_inflow) keep_qnode[i] = d.qnode[i];
+    if (i >= s.N) return;
+    double h2;
+    if constexpr (sizeof(R) == 8) {
+        h2 = ((const double *)d.H)[i];
+    } else {
+        const float2 v = ((const float2 *)d.H)[i];
+        h2 = (double)v.x + (double)v.y;
+        if (s.H2_pair) s.H2_pair[i] = v;
+    }
+    s.H2[i] = h2;
+    feature_row(s, i, i, H0[i], H1[i], h2, nullptr);
 }
 
 // ---------------------------------------------------------------- products
@@ -256,16 +283,27 @@ __global__ void k_reduce_final(const float *__restrict__ P2, int64_t ngroups, in
 // h_l = h_{l-1} + relu(z) into U[l+1] (or H_last); the last layer also forms
 // y = h_L . w_out + b_out.  With store the mean is also written into the
 // second half of U[l] (the weight gradient reads it).
+// Rows per workgroup: 32 for large row counts (training batches: the weights
+// are staged once per 32 rows), 16 for a single small mesh (inference on a few
+// thousand rows: twice the workgroups, so that every compute unit gathers)
 constexpr int LAYER_ROWS = 32;
+constexpr int LAYER_ROWS_SMALL = 16;
+constexpr int64_t LAYER_SMALL_MAX = 16384;   // row counts up to this take the 16-row form
 
+template <int ROWS>
 __global__ __launch_bounds__(256) void k_layer(SurDev s, int l, int64_t R, int store) {
+    static_assert(ROWS == 16 || ROWS == 32, "16 or 32 rows per workgroup");
     constexpr int LDU = 2 * WIDTH + 8;
-    __shared__ __align__(16) bf16 Ut[LAYER_ROWS][LDU];
+    constexpr int TPR = 256 / ROWS;          // threads per row in the gather
+    constexpr int CH = WIDTH / TPR;          // channels per thread: 8 (one 16-byte word) or 4
+    constexpr int NW = CH / 2;               // 32-bit words per thread
+    constexpr int NT = ROWS / 16 == 2 ? 2 : 1;   // 16-column output tiles per wave
+    __shared__ __align__(16) bf16 Ut[ROWS][LDU];
     __shared__ __align__(16) bf16 Wt[WIDTH][LDU];      // W_l^T, row n holds W_l[:, n]
-    __shared__ float ypart[2][LAYER_ROWS];
+    __shared__ float ypart[4][ROWS];
     const bf16 *__restrict__ U = s.U[l];
     const int t = threadIdx.x;
-    const int64_t row0 = (int64_t)blockIdx.x * LAYER_ROWS;
+    const int64_t row0 = (int64_t)blockIdx.x * ROWS;
     // W_l^T: all four 16-byte pieces of this thread in flight at once, stored to
     // LDS only after the neighbour loads below have been issued
     constexpr int WPIECES = WIDTH * (2 * WIDTH / 8) / 256;
@@ -274,35 +312,46 @@ __global__ __launch_bounds__(256) void k_layer(SurDev s, int l, int64_t R, int s
         const int v = t + 256 * j;
         wv[j] = *(const uint4 *)(s.wt[l] + (v / (2 * WIDTH / 8)) * 2 * WIDTH + (v % (2 * WIDTH / 8)) * 8);
     }
+    auto load_w = [&](const bf16 *p, uint32_t *w) {
+        if constexpr (NW == 4) {
+            const uint4 v = *(const uint4 *)p;
+            w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
+        } else {
+            const uint2 v = *(const uint2 *)p;
+            w[0] = v.x; w[1] = v.y;
+        }
+    };
+    auto store_w = [&](bf16 *p, const uint32_t *w) {
+        if constexpr (NW == 4) *(uint4 *)p = make_uint4(w[0], w[1], w[2], w[3]);
+        else *(uint2 *)p = make_uint2(w[0], w[1]);
+    };
     {
-        const int rr = t >> 3, c8 = (t & 7) * 8;
+        const int rr = t / TPR, cc = (t % TPR) * CH;
         const int64_t r = row0 + rr;
-        uint4 own = make_uint4(0, 0, 0, 0), mean = make_uint4(0, 0, 0, 0);
+        uint32_t own[NW] = {}, mean[NW] = {};
         if (r < R) {
-            own = *(const uint4 *)(U + r * 2 * WIDTH + c8);
+            load_w(U + r * 2 * WIDTH + cc, own);
             const int64_t i = r % s.N, base = r - i;
-            float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            float acc[CH] = {};
             const int32_t q0 = s.nbr_ptr[i], q1 = s.nbr_ptr[i + 1];
             // eight neighbour rows in flight (more in flight measured no faster on
             // small graphs and, with the registers they take, slower on large ones)
             int32_t q = q0;
             for (; q + 8 <= q1; q += 8) {
-                uint4 w[8];
-                for (int u = 0; u < 8; ++u) w[u] = *(const uint4 *)(U + (base + s.nbr[q + u]) * 2 * WIDTH + c8);
-                for (int u = 0; u < 8; ++u) {
-                    const uint32_t x[4] = {w[u].x, w[u].y, w[u].z, w[u].w};
-                    for (int k = 0; k < 4; ++k) {
-                        acc[2 * k] += bf2f((bf16)(x[k] & 0xffffu));
-                        acc[2 * k + 1] += bf2f((bf16)(x[k] >> 16));
+                uint32_t w[8][NW];
+                for (int u = 0; u < 8; ++u) load_w(U + (base + s.nbr[q + u]) * 2 * WIDTH + cc, w[u]);
+                for (int u = 0; u < 8; ++u)
+                    for (int k = 0; k < NW; ++k) {
+                        acc[2 * k] += bf2f((bf16)(w[u][k] & 0xffffu));
+                        acc[2 * k + 1] += bf2f((bf16)(w[u][k] >> 16));
                     }
-                }
             }
             for (; q < q1; ++q) {
-                const uint4 w = *(const uint4 *)(U + (base + s.nbr[q]) * 2 * WIDTH + c8);
-                const uint32_t x[4] = {w.x, w.y, w.z, w.w};
-                for (int k = 0; k < 4; ++k) {
-                    acc[2 * k] += bf2f((bf16)(x[k] & 0xffffu));
-                    acc[2 * k + 1] += bf2f((bf16)(x[k] >> 16));
+                uint32_t w[NW];
+                load_w(U + (base + s.nbr[q]) * 2 * WIDTH + cc, w);
+                for (int k = 0; k < NW; ++k) {
+                    acc[2 * k] += bf2f((bf16)(w[k] & 0xffffu));
+                    acc[2 * k + 1] += bf2f((bf16)(w[k] >> 16));
                 }
             }
             // the mean as a correctly rounded division of the exact FP32 sum (the BF16
@@ -310,16 +359,14 @@ __global__ __launch_bounds__(256) void k_layer(SurDev s, int l, int64_t R, int s
             // the exact mean; a product with a rounded 1/deg lands on the other side of
             // a rounding tie, which the repeated values of a mesh make frequent
             const float dg = (float)(q1 - q0);
-            uint32_t o[4];
-            for (int k = 0; k < 4; ++k) {
+            for (int k = 0; k < NW; ++k) {
                 const float m0 = q1 > q0 ? acc[2 * k] / dg : 0.f, m1 = q1 > q0 ? acc[2 * k + 1] / dg : 0.f;
-                o[k] = (uint32_t)f2bf(m0) | ((uint32_t)f2bf(m1) << 16);
+                mean[k] = (uint32_t)f2bf(m0) | ((uint32_t)f2bf(m1) << 16);
             }
-            mean = make_uint4(o[0], o[1], o[2], o[3]);
-            if (store) *(uint4 *)(s.U[l] + r * 2 * WIDTH + WIDTH + c8) = mean;
+            if (store) store_w(s.U[l] + r * 2 * WIDTH + WIDTH + cc, mean);
         }
-        *(uint4 *)&Ut[rr][c8] = own;
-        *(uint4 *)&Ut[rr][WIDTH + c8] = mean;
+        store_w(&Ut[rr][cc], own);
+        store_w(&Ut[rr][WIDTH + cc], mean);
     }
     for (int j = 0; j < WPIECES; ++j) {
         const int v = t + 256 * j;
@@ -329,11 +376,14 @@ __global__ __launch_bounds__(256) void k_layer(SurDev s, int l, int64_t R, int s
     constexpr int K = 2 * WIDTH;
     const int wave = t >> 6, lane = t & 63;
     const int ar = lane & 15, kq = (lane >> 4) * 4;
-    const int rt = wave & 1, nt0 = (wave >> 1) * 2;
-    f4 acc[2] = {f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}};
+    // 32 rows: wave w takes row tile w & 1 and column tiles 2 (w >> 1), +1;
+    // 16 rows: one row tile, wave w takes column tile w
+    const int rt = NT == 2 ? (wave & 1) : 0, nt0 = NT == 2 ? (wave >> 1) * 2 : wave;
+    f4 acc[NT];
+    for (int n = 0; n < NT; ++n) acc[n] = f4{0.f, 0.f, 0.f, 0.f};
     for (int k0 = 0; k0 < K; k0 += 16) {
         const s4 a = *(const s4 *)&Ut[rt * 16 + ar][k0 + kq];
-        for (int n = 0; n < 2; ++n) {
+        for (int n = 0; n < NT; ++n) {
             const s4 b = *(const s4 *)&Wt[(nt0 + n) * 16 + ar][k0 + kq];
             acc[n] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[n], 0, 0, 0);
         }
@@ -344,7 +394,7 @@ __global__ __launch_bounds__(256) void k_layer(SurDev s, int l, int64_t R, int s
     const int ldh = last ? WIDTH : 2 * WIDTH;
     const float *wo = s.params + s.pl.w_out;
     float yp[4] = {0.f, 0.f, 0.f, 0.f};   // last layer: this lane's part of y for rows kq + j
-    for (int n = 0; n < 2; ++n) {
+    for (int n = 0; n < NT; ++n) {
         const int col = (nt0 + n) * 16 + ar;
         for (int j = 0; j < 4; ++j) {
             const int rr = rt * 16 + kq + j;
@@ -358,15 +408,19 @@ __global__ __launch_bounds__(256) void k_layer(SurDev s, int l, int64_t R, int s
         }
     }
     if (last) {
-        // y = h_L . w_out + b_out: the 16 lanes holding a row, then the two waves holding its columns
+        // y = h_L . w_out + b_out: the 16 lanes holding a row, then the waves holding its columns
         for (int j = 0; j < 4; ++j)
             for (int off = 8; off > 0; off >>= 1) yp[j] += __shfl_xor(yp[j], off, 16);
+        constexpr int PARTS = NT == 2 ? 2 : 4;   // waves sharing a row tile
+        const int part = NT == 2 ? (wave >> 1) : wave;
         if (ar == 0)
-            for (int j = 0; j < 4; ++j) ypart[wave >> 1][rt * 16 + kq + j] = yp[j];
+            for (int j = 0; j < 4; ++j) ypart[part][rt * 16 + kq + j] = yp[j];
         __syncthreads();
-        if (t < LAYER_ROWS) {
+        if (t < ROWS) {
             const int64_t row = row0 + t;
-            if (row < R) s.y[row] = (ypart[0][t] + ypart[1][t]) + s.params[s.pl.b_out];
+            float y = 0.f;
+            for (int q = 0; q < PARTS; ++q) y += ypart[q][t];
+            if (row < R) s.y[row] = y + s.params[s.pl.b_out];
         }
     }
 }
@@ -740,14 +794,31 @@ hipError_t features(const SurDev &s, const void *H0, const void *H1, const void 
     return hipGetLastError();
 }
 
+hipError_t features_live(const SurDev &s, const Dev &d, const double *H0, const double *H1, double *keep_qnode,
+                         hipStream_t st) {
+    const int64_t n = keep_qnode ? std::max<int64_t>(s.N, d.n_inflow) : s.N;
+    if (d.prec == FEM_PREC_FP64)
+        hipLaunchKernelGGL(k_features_live<double>, dim3(grid_for(n, 256)), dim3(256), 0, st, s, d, H0, H1, keep_qnode);
+    else
+        hipLaunchKernelGGL(k_features_live<float>, dim3(grid_for(n, 256)), dim3(256), 0, st, s, d, H0, H1, keep_qnode);
+    return hipGetLastError();
+}
+
 hipError_t forward(const SurDev &s, int64_t R, int store, int project, hipStream_t st) {
     const unsigned g = grid_for(R, 64);
     // encoder into the first half of U_0
     hipLaunchKernelGGL((k_gemm<WIDTH, 0>), dim3(g), dim3(256), 0, st, s.X, KIN, KIN, s.wt_in,
                        s.params + s.pl.b_in, R, store ? s.Zin : (bf16 *)nullptr, (const bf16 *)nullptr, 0, s.U[0],
                        2 * WIDTH, (float *)nullptr, 0);
-    const unsigned gl = grid_for(R, LAYER_ROWS);
-    for (int l = 0; l < s.layers; ++l) hipLaunchKernelGGL(k_layer, dim3(gl), dim3(256), 0, st, s, l, R, store);
+    if (R <= LAYER_SMALL_MAX) {
+        const unsigned gl = grid_for(R, LAYER_ROWS_SMALL);
+        for (int l = 0; l < s.layers; ++l)
+            hipLaunchKernelGGL(k_layer<LAYER_ROWS_SMALL>, dim3(gl), dim3(256), 0, st, s, l, R, store);
+    } else {
+        const unsigned gl = grid_for(R, LAYER_ROWS);
+        for (int l = 0; l < s.layers; ++l)
+            hipLaunchKernelGGL(k_layer<LAYER_ROWS>, dim3(gl), dim3(256), 0, st, s, l, R, store);
+    }
     if (!s.project) return hipGetLastError();
     const int64_t slots = R / s.N;
     hipLaunchKernelGGL(k_seg_sum, dim3((unsigned)s.n_seg, (unsigned)slots), dim3(256), 0, st, s, (const float *)s.y, 1);

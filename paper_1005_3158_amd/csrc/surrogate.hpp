@@ -134,6 +134,10 @@ hipError_t apply(const SurDev &s, int64_t rows, double *H_out, hipStream_t st); 
 // FP64 copy of the enthalpy state into out (and of the inflow sums into
 // keep_qnode, and of the raw FP32 pairs into pair_out, when not null)
 hipError_t state_to_f64(const Dev &d, double *out, double *keep_qnode, hipStream_t st, float2 *pair_out = nullptr);
+// features of one state whose H2 is the solver's current state (kept in s.H2, the
+// FP32 pairs and keep_qnode as state_to_f64 keeps them), from FP64 copies H0, H1
+hipError_t features_live(const SurDev &s, const Dev &d, const double *H0, const double *H1, double *keep_qnode,
+                         hipStream_t st);
 hipError_t state_to_f32(const Dev &d, float *out, hipStream_t st);
 // write H = base + scale * (y - the scenario's weighted mean of y) (one state slot,
 // unprojected y) into the solver state with its T and fraction solid; counts

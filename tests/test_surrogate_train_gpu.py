@@ -89,29 +89,54 @@ def test_trained_network_beats_the_extrapolation_on_held_out_trajectories(traine
     assert rms["trained"] < 0.8 * rms["extrapolation"]
 
 
-def test_accelerated_run_against_the_plain_run(trained, orc):
-    cf = _cf()
-    p = configs.config4_trajectory(HELD_OUT[0])
-    dt = 0.9 * orc.stable_dt(p)
-    plain = cf.Solver(p, **_fixed_layout(cf))
-    rp = plain.advance(dt, 200000, None, until_solid=True)
-    acc = cf.Solver(p, **_fixed_layout(cf))
-    sur = cf.Surrogate(acc, layers=3, extrapolation=cf.FEM_SUR_EXTRAP_QUADRATIC)
-    sur.set_params(trained["params"])
-    ra = acc.advance(dt, 200000, sur, until_solid=True)
-    ref = cf.Solver(p, **_fixed_layout(cf))
-    ref.step(dt, ra["steps"])
-    err = float(np.max(np.abs(acc.T() - ref.T())))
-    en = acc.energy()
-    print("plain: %d steps %.4f s; surrogate: %d steps (%d computed, %d/%d jumps kept) %.4f s; "
-          "max |T_sur - T_plain| = %.3f K; energy residual %.2e"
-          % (rp["steps"], rp["wall_seconds"], ra["steps"], ra["plain_steps"], ra["jumps_accepted"],
-             ra["jumps_accepted"] + ra["jumps_rejected"], ra["wall_seconds"], err, en["residual"]))
-    assert rp["solid"] == 1 and ra["solid"] == 1
-    assert ra["jumps_accepted"] > 0 and ra["plain_steps"] < rp["steps"]
-    # every kept jump passed the energy gate: the drift it leaves is bounded by the gate
-    assert en["residual"] <= (ra["jumps_accepted"] + 1) * 1e-4
-    assert np.isfinite(err)
-    sur.close()
-    for s in (plain, acc, ref):
+VERIFY_TOL = 3.0    # K, the one-step verification of a jump (as the benchmark runs it)
+RUNS = 3            # wall-clock: the fastest of RUNS runs of each mode (identical results)
+
+
+def _advance(cf, p, dt, params):
+    """Run p to full solidification plainly (params None) or with the surrogate;
+    returns (report with the fastest wall-clock, final T)."""
+    best, T = None, None
+    for _ in range(RUNS):
+        s = cf.Solver(p, **_fixed_layout(cf))
+        sur = None
+        if params is not None:
+            sur = cf.Surrogate(s, layers=3, horizon=16, extrapolation=cf.FEM_SUR_EXTRAP_QUADRATIC)
+            sur.set_params(params)
+        r = s.advance(dt, 200000, sur, until_solid=True, verify_tol=VERIFY_TOL)
+        r["residual"] = s.energy()["residual"]
+        if best is None or r["wall_seconds"] < best["wall_seconds"]:
+            best, T = r, s.T()
+        if sur is not None:
+            sur.close()
         s.close()
+    return best, T
+
+
+@pytest.mark.parametrize("seed", HELD_OUT)
+def test_accelerated_run_against_the_plain_run(trained, orc, seed):
+    """Time to full solidification at the 16-step horizon: with the trained network
+    and with the extrapolation alone (zero network), each faster than the plain run
+    and within 0.5 K of it at the end (the plain run continued to the same step)."""
+    cf = _cf()
+    p = configs.config4_trajectory(seed)
+    dt = 0.9 * orc.stable_dt(p)
+    rp, _ = _advance(cf, p, dt, None)
+    assert rp["solid"] == 1
+    for name, params in (("trained", trained["params"]), ("extrapolation", np.zeros_like(trained["params"]))):
+        ra, T = _advance(cf, p, dt, params)
+        ref = cf.Solver(p, **_fixed_layout(cf))
+        ref.step(dt, ra["steps"])
+        err = float(np.max(np.abs(T - ref.T())))
+        ref.close()
+        print("seed %d %s: plain %d steps %.4f s; surrogate %d steps (%d computed, %d/%d jumps kept) %.4f s "
+              "(%.2fx); max |T_sur - T_plain| = %.3f K; energy residual %.2e"
+              % (seed, name, rp["steps"], rp["wall_seconds"], ra["steps"], ra["plain_steps"], ra["jumps_accepted"],
+                 ra["jumps_accepted"] + ra["jumps_rejected"], ra["wall_seconds"],
+                 rp["wall_seconds"] / ra["wall_seconds"], err, ra["residual"]), flush=True)
+        assert ra["solid"] == 1
+        assert ra["jumps_accepted"] > 0 and ra["plain_steps"] < rp["steps"]
+        # every kept jump passed the energy gate: the drift it leaves is bounded by the gate
+        assert ra["residual"] <= (ra["jumps_accepted"] + 1) * 1e-4
+        assert err <= 0.5
+        assert ra["wall_seconds"] < rp["wall_seconds"]
