@@ -211,10 +211,11 @@ int fem_get_sisters(const fem_ctx *ctx, int32_t *sister);
  *   h_of_t: factor on every interface coefficient against time t (s);
  *   dir_of_t: shift added to every fixed temperature: T_i(t) = T_D,i + shift(t);
  *     the prescribed change of a fixed node's enthalpy counts as boundary inflow.
- * Time starts at 0 at fem_bind_buffers and advances by dt per step on the
- * device.  The stability bound takes every property at its largest value.
- * Supported with one scenario, the enthalpy form and the LDS-blocked scatter;
- * the surrogate and fem_write_state refuse such a context (FEM_E_UNSUPPORTED).
+ * Time starts at 0 at fem_bind_buffers and advances on the device, in a batch
+ * (fem_set_scenarios) per scenario by that scenario's dt.  The stability bound
+ * takes every property at its largest value.  Supported with the enthalpy form
+ * and the LDS-blocked scatter; the surrogate and fem_write_state refuse such a
+ * context (FEM_E_UNSUPPORTED).
  * Call before fem_finalize. */
 int fem_set_variable_properties(fem_ctx *ctx, int32_t n_mat, const fem_table *k_of_T, const fem_table *h_of_T,
                                 const fem_table *h_of_t, const fem_table *dir_of_t);
@@ -228,8 +229,8 @@ int fem_set_variable_properties(fem_ctx *ctx, int32_t n_mat, const fem_table *k_
  * fem_set_variable_properties still adds.  The prescribed change of a fixed
  * node's enthalpy counts as boundary inflow.  Both arrays are host memory,
  * copied.  Makes the context one with variable properties (the same limits:
- * one scenario, enthalpy form, LDS-blocked scatter, no surrogate or state
- * restore).  Call after fem_set_dirichlet and before fem_finalize; errors:
+ * enthalpy form, LDS-blocked scatter, no surrogate or state restore; in a
+ * batch each fixed node follows its schedule on its scenario's clock).  Call after fem_set_dirichlet and before fem_finalize; errors:
  * FEM_E_STATE (no fixed nodes, or after fem_finalize), FEM_E_INVALID_ARG (count
  * out of range, times not increasing, a value not finite). */
 int fem_set_dirichlet_schedule(fem_ctx *ctx, int32_t n_times, const double *times, const double *values);

@@ -53,7 +53,8 @@ void layout_sizes(const fem_ctx *c, const Layout &L, int64_t *sz) {
             sz[B_VAR_TABS_F] = (int64_t)c->vtabs.size() * (int64_t)sizeof(Tab<float>);
             sz[B_VAR_TABS_D] = (int64_t)c->vtabs.size() * (int64_t)sizeof(Tab<double>);
             sz[B_T_FIXED] = N * 8;
-            sz[B_TIME] = 16;
+            sz[B_TIME] = 16 * (int64_t)c->prob.n_scen;
+            sz[B_VAR_SCEN] = ((int64_t)c->prob.mats.size() + c->prob.n_scen) * 4;
             sz[B_SCHED] = L.n_inflow * (int64_t)c->sched_t.size() * 8;
         }
     }
@@ -252,7 +253,8 @@ void upload_layout_t(fem_ctx *c, const Layout &L) {
         h2d(c, B_APP_MATS, am.data(), (int64_t)(am.size() * sizeof(AppMat)));
     }
     std::vector<Tab<float>> tf;
-    std::vector<double> tfix, sched, t0(2, 0.0);
+    std::vector<double> tfix, sched, t0;
+    std::vector<int32_t> vscen;
     if (c->variable()) {
         for (const Tab<double> &t : c->vtabs) {
             Tab<float> u{};
@@ -269,7 +271,16 @@ void upload_layout_t(fem_ctx *c, const Layout &L) {
         for (int64_t n = 0; n < N; ++n)
             if (L.nflag[n] & NODE_FIXED) tfix[n] = L.T_init[n];
         h2d(c, B_T_FIXED, tfix.data(), N * 8);
-        h2d(c, B_TIME, t0.data(), 16);
+        t0.assign(2 * (size_t)c->prob.n_scen, 0.0);
+        h2d(c, B_TIME, t0.data(), (int64_t)t0.size() * 8);
+        // the scenario of every material, then a material of every scenario (its dt)
+        vscen.assign(c->prob.mats.size() + (size_t)c->prob.n_scen, -1);
+        for (size_t m = 0; m < c->prob.mats.size(); ++m) {
+            const int32_t sc = c->prob.scen_of_mat((int32_t)m);
+            vscen[m] = sc;
+            if (vscen[c->prob.mats.size() + sc] < 0) vscen[c->prob.mats.size() + sc] = (int32_t)m;
+        }
+        h2d(c, B_VAR_SCEN, vscen.data(), (int64_t)vscen.size() * 4);
         if (const int64_t K = (int64_t)c->sched_t.size()) {
             // the rows of the fixed nodes' schedules at their shared slots
             sched.assign(L.n_inflow * K, 0.0);
@@ -369,6 +380,9 @@ void fill_dev(fem_ctx *c, const Candidate &cd) {
         v.tabs_d = (const Tab<double> *)c->ptr[B_VAR_TABS_D];
         v.T_fixed = (const double *)c->ptr[B_T_FIXED];
         v.time = (double *)c->ptr[B_TIME];
+        v.n_scen = c->prob.n_scen;
+        v.mat_scen = (const int32_t *)c->ptr[B_VAR_SCEN];
+        v.scen_mat = v.mat_scen + c->prob.mats.size();
         v.n_sched = (int32_t)c->sched_t.size();
         if (v.n_sched) {
             v.sched = (const double *)c->ptr[B_SCHED];
@@ -770,7 +784,6 @@ int fem_finalize(fem_ctx *ctx, fem_prep_report *rep) {
                     throw PrepError{FEM_E_UNSUPPORTED, "apparent capacity needs T_liq > T_sol where L > 0"};
         }
         if (ctx->variable()) {
-            if (ctx->prob.n_scen != 1) throw PrepError{FEM_E_UNSUPPORTED, "variable properties: one scenario only"};
             if (ctx->opt.scatter != FEM_SCATTER_LDS_BLOCKED)
                 throw PrepError{FEM_E_UNSUPPORTED, "variable properties: LDS-blocked scatter only"};
             if (ctx->apparent()) throw PrepError{FEM_E_UNSUPPORTED, "variable properties: enthalpy form only"};

@@ -8,8 +8,9 @@
 //     interface links whose coefficient is scaled by h_T((T_i + T_j) / 2) and
 //     h_t(t), the update; a fixed node takes T_D + shift(t + dt), and the change of
 //     its enthalpy counts as boundary inflow.  The time of each T buffer lives in
-//     device memory (two slots, one per parity), so captured graphs of steps
-//     advance it without host involvement.
+//     device memory (two slots, one per parity, per scenario of a batch, each
+//     advancing by its scenario's dt), so captured graphs of steps advance it
+//     without host involvement.
 #include "varprops.hpp"
 
 #include <type_traits>
@@ -192,9 +193,10 @@ __global__ __launch_bounds__(NODE_THREADS) void k_nodes_var(VarDev v, int parity
         __syncthreads();
     }
     const MatDev *mats = LDS_TABLES ? s_mats : d.mats;
-    const double t = v.time[parity];
-    const double dt = mats[0].dt;   // one scenario
-    if (s == 0) v.time[1 - parity] = t + dt;
+    const int ns = v.n_scen;
+    // thread s < n_scen advances the time of scenario s (by its own dt) in the
+    // slot of the state this step writes
+    if (s < ns) v.time[(1 - parity) * ns + s] = v.time[parity * ns + s] + d.mats[v.scen_mat[s]].dt;
     if (s >= count) return;
     const Tab<R> *gt = tabs(v, R(0)) + d.n_mat;
     const Tab<double> *gd = v.tabs_d + d.n_mat;
@@ -203,6 +205,8 @@ __global__ __launch_bounds__(NODE_THREADS) void k_nodes_var(VarDev v, int parity
     R *Tn = (R *)d.T + (1 - parity) * d.N;
     const uint32_t f = d.flags[g];
     const MatDev &M = mats[f & NODE_MAT_MASK];
+    const double t = v.time[parity * ns + (ns > 1 ? v.mat_scen[f & NODE_MAT_MASK] : 0)];
+    const double dt = M.dt;         // the node's scenario's step
     const R *P = (const R *)d.partials;
     R r = step::combine_partials(d, P, s, f);
     double q = 0.0;
@@ -266,9 +270,9 @@ hipError_t step_t(const VarDev &v, int parity, hipStream_t s, hipEvent_t *ev) {
         (void)hipEventRecord(ev[1], s);
         (void)hipEventRecord(ev[2], s);
     }
-    // launched even without shared nodes: its first thread advances the time
+    // launched even without shared nodes: its first n_scen threads advance the time
     const int64_t count = d.N - d.n_private;
-    hipLaunchKernelGGL((k_nodes_var<R, LDS_TABLES>), dim3((unsigned)std::max<int64_t>(1, node_grid(count))),
+    hipLaunchKernelGGL((k_nodes_var<R, LDS_TABLES>), dim3((unsigned)node_grid(std::max<int64_t>(count, v.n_scen))),
                        dim3(NODE_THREADS), 0, s, v, parity);
     if (ev) (void)hipEventRecord(ev[3], s);
     return hipGetLastError();

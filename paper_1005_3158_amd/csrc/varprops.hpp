@@ -28,12 +28,16 @@ struct VarDev {
     const Tab<float> *tabs_f = nullptr; // n_mat conductivity tables, then the TAB_GLOBAL tables
     const Tab<double> *tabs_d = nullptr;
     const double *T_fixed = nullptr;    // per node: the fixed temperature before its time shift
-    double *time = nullptr;             // [2]: time of the state held in T buffer 0 and 1
+    // time of the state held in T buffer 0 and 1, per scenario: time[parity * n_scen + scenario]
+    double *time = nullptr;
+    const int32_t *mat_scen = nullptr;  // [n_mat]: scenario of each material
+    const int32_t *scen_mat = nullptr;  // [n_scen]: a material of each scenario (its dt)
+    int32_t n_scen = 1;
     // prescribed temperature f(x, t) node by node: n_sched common times and, per
     // shared slot s < n_inflow (every fixed node has one), its n_sched values
     // (rows of other slots unused); n_sched = 0: the constant T_fixed
     const double *sched = nullptr;
-    int32_t n_sched = 0, pad_ = 0;
+    int32_t n_sched = 0;
     double sched_t[TAB_POINTS] = {};
 };
 

@@ -229,13 +229,20 @@ def test_variable_properties_bound_and_refusals(orc):
             cf.setup_problem(ctx, p)
         assert e.value.code == -7
         cf.fem_destroy(ctx)
+    # a batch takes them too: every scenario's bound at its own largest properties
     b = configs.batch(n_scen=2, elems_range=(800, 1600))
-    b["varprops"] = dict(h_of_t=[(0.0, 1.0)])
+    b["varprops"] = dict(h_of_t=[(0.0, 1.0), (1.0, 2.5)])
     ctx = cf.fem_create(cf.make_options())
-    with pytest.raises(cf.FemError) as e:
-        cf.setup_problem(ctx, b)
-    assert e.value.code == -7
+    cf.setup_problem(ctx, b)
+    bounds = cf.fem_stable_dt_scenarios(ctx, 2)
     cf.fem_destroy(ctx)
+    for s, sp in enumerate(b["meta"]["scenarios"]):
+        q = {k: v for k, v in b.items() if k != "varprops"}
+        q["if_h"] = np.asarray(b["if_h"]) * 2.5
+        ctx = cf.fem_create(cf.make_options())
+        cf.setup_problem(ctx, q)
+        assert bounds[s] == pytest.approx(cf.fem_stable_dt_scenarios(ctx, 2)[s], rel=1e-14)
+        cf.fem_destroy(ctx)
     for bad in (dict(h_of_t=[(1.0, 1.0), (0.5, 2.0)]), dict(k_of_T=[[(0.0, -1.0)], None]),
                 dict(h_of_T=[(0.0, float("nan"))])):
         ctx = cf.fem_create(cf.make_options())
