@@ -311,8 +311,9 @@ int fem_write_state(fem_ctx *ctx, const void *buf, int64_t bytes);
 int fem_get_node_perm(const fem_ctx *ctx, int32_t *perm);
 
 /* ------------------------------------------------------------ measurement */
-/* Run n_steps without a graph, bracketing every kernel with HIP events on the
- * context stream, and return the mean launch durations and the algorithmic
+/* Run n_steps without a graph, each step kernel timed by start and stop events
+ * of its own launch on the context stream (the dispatch gap between launches
+ * is not counted), and return the mean launch durations and the algorithmic
  * bytes per launch (16 B per element, 48 B per node split between kernels;
  * 44 B per node in the apparent-capacity form, which reads no 1/m_i). */
 int fem_time_kernels(fem_ctx *ctx, double dt, int64_t n_steps, fem_kernel_times *out);

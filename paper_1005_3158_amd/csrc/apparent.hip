@@ -15,6 +15,8 @@
 //
 #include "apparent.hpp"
 
+#include <hip/hip_ext.h>
+
 #include <cfloat>
 #include <type_traits>
 
@@ -144,13 +146,14 @@ __device__ __forceinline__ bool block_elements(const AppDev &a, const BlockInfo 
     using V4 = typename VT<R>::V4;
     const Dev &d = a.d;
     bool bad = false;
-    const uint2 *lc = (const uint2 *)(d.lconn + (int64_t)bi.e_begin * 4);
-    uint2 cur{};
-    if ((int)threadIdx.x < bi.n_e) cur = lc[threadIdx.x];
+    step::ConnRaw<4> cur{};
+    if ((int)threadIdx.x < bi.n_e) cur = step::conn_load<4>(d, (int64_t)bi.e_begin + threadIdx.x);
     for (int e = threadIdx.x; e < bi.n_e; e += blockDim.x) {
-        uint2 nxt{};
-        if (e + (int)blockDim.x < bi.n_e) nxt = lc[e + blockDim.x];
-        const int l0 = cur.x & 0xFFFF, l1 = cur.x >> 16, l2 = cur.y & 0xFFFF, l3 = cur.y >> 16;
+        step::ConnRaw<4> nxt{};
+        if (e + (int)blockDim.x < bi.n_e) nxt = step::conn_load<4>(d, (int64_t)bi.e_begin + e + blockDim.x);
+        int l[4];
+        step::conn_ids<4>(cur, l);
+        const int l0 = l[0], l1 = l[1], l2 = l[2], l3 = l[3];
         V4 p[4] = {s_x[l0], s_x[l1], s_x[l2], s_x[l3]};
         step::local_coords<4>(p, d.x_scale);
         R re[4], cap;
@@ -290,18 +293,19 @@ __global__ __launch_bounds__(NODE_THREADS) void k_nodes_app(AppDev a, int parity
 template <class R, bool LDS_TABLES>
 hipError_t step_t(const AppDev &a, int parity, hipStream_t s, hipEvent_t *ev) {
     const Dev &d = a.d;
-    if (ev) (void)hipEventRecord(ev[0], s);
-    hipLaunchKernelGGL((k_block_app<R, LDS_TABLES>), dim3((unsigned)d.n_blocks), dim3(d.threads), d.lds_bytes, s, a,
-                       parity);
-    if (ev) {
-        (void)hipEventRecord(ev[1], s);
-        (void)hipEventRecord(ev[2], s);
-    }
+    // timed launches (eager) carry their own start and stop events
+    const dim3 gb((unsigned)d.n_blocks), bb(d.threads);
+    if (ev) hipExtLaunchKernelGGL((k_block_app<R, LDS_TABLES>), gb, bb, (uint32_t)d.lds_bytes, s, ev[0], ev[1], 0u, a, parity);
+    else hipLaunchKernelGGL((k_block_app<R, LDS_TABLES>), gb, bb, d.lds_bytes, s, a, parity);
     const int64_t count = d.N - d.n_private;
-    if (count > 0)
-        hipLaunchKernelGGL((k_nodes_app<R, LDS_TABLES>), dim3((unsigned)node_grid(count)), dim3(NODE_THREADS), 0, s, a,
-                           parity);
-    if (ev) (void)hipEventRecord(ev[3], s);
+    if (count > 0) {
+        const dim3 g((unsigned)node_grid(count)), b(NODE_THREADS);
+        if (ev) hipExtLaunchKernelGGL((k_nodes_app<R, LDS_TABLES>), g, b, 0u, s, ev[2], ev[3], 0u, a, parity);
+        else hipLaunchKernelGGL((k_nodes_app<R, LDS_TABLES>), g, b, 0, s, a, parity);
+    } else if (ev) {
+        (void)hipEventRecord(ev[2], s);
+        (void)hipEventRecord(ev[3], s);
+    }
     return hipGetLastError();
 }
 

@@ -37,7 +37,7 @@ void layout_sizes(const fem_ctx *c, const Layout &L, int64_t *sz) {
         sz[B_R] = N * R;
     } else {
         const int64_t np = (int64_t)L.sh_list.size();
-        sz[B_LCONN] = E * L.nen * 2;
+        sz[B_LCONN] = L.lconn12.empty() ? E * L.nen * 2 : (int64_t)L.lconn12.size() * 4;
         sz[B_BLOCKS] = (int64_t)L.blocks.size() * (int64_t)sizeof(BlockInfo);
         sz[B_SH_LIST] = (np + 1) * 4;   // one padding entry: the gather's clamped loads
         sz[B_PARTIALS] = L.n_partial_slots * R;
@@ -181,7 +181,8 @@ void upload_layout_t(fem_ctx *c, const Layout &L) {
     h2d(c, B_LINK_NODE, L.link_node.data(), (int64_t)L.link_node.size() * 4);
     h2d(c, B_LINK_W, lw.data(), (int64_t)lw.size() * (int64_t)sizeof(R));
     if (c->opt.scatter == FEM_SCATTER_LDS_BLOCKED) {
-        h2d(c, B_LCONN, L.lconn.data(), (int64_t)L.lconn.size() * 2);
+        if (L.lconn12.empty()) h2d(c, B_LCONN, L.lconn.data(), (int64_t)L.lconn.size() * 2);
+        else h2d(c, B_LCONN, L.lconn12.data(), (int64_t)L.lconn12.size() * 4);
         // per block: its one material or -1 (pad0; the apparent-capacity kernels
         // read the constants of a single-material block once), and the first row
         // of its window of MAT_WINDOW material rows or -1 if its materials span
@@ -319,6 +320,7 @@ void fill_dev(fem_ctx *c, const Candidate &cd) {
     d.conn = (const int32_t *)c->ptr[B_CONN];
     d.r = c->ptr[B_R];
     d.lconn = (const uint16_t *)c->ptr[B_LCONN];
+    d.conn12 = L.lconn12.empty() ? 0 : 1;
     d.blocks = (const BlockInfo *)c->ptr[B_BLOCKS];
     d.sh_list = (const int32_t *)c->ptr[B_SH_LIST];
     d.partials = c->ptr[B_PARTIALS];

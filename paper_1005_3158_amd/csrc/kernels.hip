@@ -20,6 +20,8 @@
 // error-free two-sum; T(H) is evaluated in FP64 from hi + lo.
 #include "kernels.hpp"
 
+#include <hip/hip_ext.h>
+
 #include <cfloat>
 #include <algorithm>
 #include <mutex>
@@ -153,7 +155,6 @@ constexpr int UPDATE_U = 2;
 template <class R, int NEN, bool LDS_TABLES>
 __global__ __launch_bounds__(1024) void k_block(Dev d, int parity) {
     using V4 = typename VT<R>::V4;
-    using LC = typename std::conditional<NEN == 4, uint2, uint4>::type;
     // FP32: 64-bit fixed-point accumulators; FP64: double accumulators
     using ACC = typename std::conditional<std::is_same<R, float>::value, long long, double>::type;
     extern __shared__ __attribute__((aligned(32))) unsigned char smem[];
@@ -214,26 +215,14 @@ __global__ __launch_bounds__(1024) void k_block(Dev d, int parity) {
 
     // element residuals accumulated in LDS; the next element's connectivity
     // is loaded one iteration ahead
-    const LC *lc = (const LC *)(d.lconn + (int64_t)bi.e_begin * NEN);
-    LC cur{};
-    if ((int)threadIdx.x < bi.n_e) cur = lc[threadIdx.x];
+    step::ConnRaw<NEN> cur{};
+    if ((int)threadIdx.x < bi.n_e) cur = step::conn_load<NEN>(d, (int64_t)bi.e_begin + threadIdx.x);
     bool bad = false;
     for (int e = threadIdx.x; e < bi.n_e; e += blockDim.x) {
-        LC nxt{};
-        if (e + (int)blockDim.x < bi.n_e) nxt = lc[e + blockDim.x];
+        step::ConnRaw<NEN> nxt{};
+        if (e + (int)blockDim.x < bi.n_e) nxt = step::conn_load<NEN>(d, (int64_t)bi.e_begin + e + blockDim.x);
         int l[NEN];
-        if constexpr (NEN == 4) {
-            l[0] = cur.x & 0xFFFF;
-            l[1] = cur.x >> 16;
-            l[2] = cur.y & 0xFFFF;
-            l[3] = cur.y >> 16;
-        } else {
-            const uint32_t w[4] = {cur.x, cur.y, cur.z, cur.w};
-            for (int a = 0; a < 4; ++a) {
-                l[2 * a] = w[a] & 0xFFFF;
-                l[2 * a + 1] = w[a] >> 16;
-            }
-        }
+        step::conn_ids<NEN>(cur, l);
         V4 p[NEN];
         for (int a = 0; a < NEN; ++a) p[a] = s_x[l[a]];
         const R k = s_k[l[0]] * d.x_scale;   // per unit length of the element coordinates
@@ -451,10 +440,16 @@ __global__ __launch_bounds__(256) void k_stage(int32_t *__restrict__ dst_chk, co
 
 template <class R, int NEN, bool LDS_TABLES>
 hipError_t step_t(const Dev &d, int parity, hipStream_t s, hipEvent_t *ev) {
-    if (ev) (void)hipEventRecord(ev[0], s);
-    if (d.scatter == FEM_SCATTER_LDS_BLOCKED) {
-        hipLaunchKernelGGL((k_block<R, NEN, LDS_TABLES>), dim3((unsigned)d.n_blocks), dim3(d.threads), d.lds_bytes, s,
-                           d, parity);
+    const bool blocked = d.scatter == FEM_SCATTER_LDS_BLOCKED;
+    if (ev && !blocked) (void)hipEventRecord(ev[0], s);
+    if (blocked) {
+        // timed launches (eager) carry their own start and stop events
+        if (ev)
+            hipExtLaunchKernelGGL((k_block<R, NEN, LDS_TABLES>), dim3((unsigned)d.n_blocks), dim3(d.threads),
+                                  (uint32_t)d.lds_bytes, s, ev[0], ev[1], 0u, d, parity);
+        else
+            hipLaunchKernelGGL((k_block<R, NEN, LDS_TABLES>), dim3((unsigned)d.n_blocks), dim3(d.threads),
+                               d.lds_bytes, s, d, parity);
     } else if (d.scatter == FEM_SCATTER_GLOBAL_ATOMIC) {
         if (d.E > 0)
             hipLaunchKernelGGL((k_elems<R, NEN, true>), dim3((unsigned)((d.E + 255) / 256)), dim3(256), 0, s, d,
@@ -467,21 +462,21 @@ hipError_t step_t(const Dev &d, int parity, hipStream_t s, hipEvent_t *ev) {
                                    d, parity, e0, e1);
         }
     }
-    if (ev) {
-        (void)hipEventRecord(ev[1], s);
-        (void)hipEventRecord(ev[2], s);
-    }
-    const bool comb = d.scatter == FEM_SCATTER_LDS_BLOCKED;
-    const int64_t count = comb ? d.N - d.n_private : d.N;
+    if (ev && !blocked) (void)hipEventRecord(ev[1], s);
+    const int64_t count = blocked ? d.N - d.n_private : d.N;
     if (count > 0) {
-        if (comb)
-            hipLaunchKernelGGL((k_nodes<R, true, LDS_TABLES>), dim3((unsigned)node_grid(count)), dim3(NODE_THREADS), 0, s,
-                               d, parity);
-        else
-            hipLaunchKernelGGL((k_nodes<R, false, LDS_TABLES>), dim3((unsigned)node_grid(count)), dim3(NODE_THREADS), 0,
-                               s, d, parity);
+        const dim3 g((unsigned)node_grid(count)), b(NODE_THREADS);
+        if (ev) {
+            if (blocked) hipExtLaunchKernelGGL((k_nodes<R, true, LDS_TABLES>), g, b, 0u, s, ev[2], ev[3], 0u, d, parity);
+            else hipExtLaunchKernelGGL((k_nodes<R, false, LDS_TABLES>), g, b, 0u, s, ev[2], ev[3], 0u, d, parity);
+        } else {
+            if (blocked) hipLaunchKernelGGL((k_nodes<R, true, LDS_TABLES>), g, b, 0, s, d, parity);
+            else hipLaunchKernelGGL((k_nodes<R, false, LDS_TABLES>), g, b, 0, s, d, parity);
+        }
+    } else if (ev) {
+        (void)hipEventRecord(ev[2], s);
+        (void)hipEventRecord(ev[3], s);
     }
-    if (ev) (void)hipEventRecord(ev[3], s);
     return hipGetLastError();
 }
 

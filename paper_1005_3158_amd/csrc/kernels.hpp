@@ -36,7 +36,11 @@ struct Dev {
     // elements
     const int32_t *conn = nullptr;      // global-atomic / coloured
     void *r = nullptr;                  // R[N] residual (global-atomic / coloured)
-    const uint16_t *lconn = nullptr;    // LDS-blocked local connectivity
+    // LDS-blocked local connectivity: 16-bit ids, NEN per element; or, with
+    // conn12 (tets in blocks of at most 4096 nodes), two tets per three words
+    // with 12-bit ids (see step::conn_load)
+    const uint16_t *lconn = nullptr;
+    int32_t conn12 = 0;
     const BlockInfo *blocks = nullptr;
     const int32_t *sh_list = nullptr;
     void *partials = nullptr;           // R per partial slot (see Layout::comb_ptr)

@@ -886,6 +886,21 @@ void prep_layout(const Problem &p, const Base &b, const PrepOptions &o, const Or
                 for (int a = 0; a < nen; ++a) L.lconn[s * nen + a] = (uint16_t)local_id(s, a);
         }
         if (L.max_local > o.max_local_nodes) fail(FEM_E_INVALID_ARG, "internal: block above node cap");
+        // tets with 12-bit local ids: 6 bytes of connectivity per element instead of 8
+        L.lconn12.clear();
+        if (nen == 4 && L.max_local <= 4096) {
+            L.lconn12.assign(3 * ((E + 1) / 2), 0u);
+            for (int64_t e = 0; e < E; e += 2) {
+                uint64_t v[2] = {0, 0};
+                for (int h = 0; h < 2 && e + h < E; ++h)
+                    for (int a = 0; a < 4; ++a) v[h] |= (uint64_t)L.lconn[(e + h) * 4 + a] << (12 * a);
+                const uint64_t lo = v[0] | (v[1] << 48);
+                uint32_t *w = &L.lconn12[3 * (e / 2)];
+                w[0] = (uint32_t)lo;
+                w[1] = (uint32_t)(lo >> 32);
+                w[2] = (uint32_t)(v[1] >> 16);
+            }
+        }
         // partial slots: the j-th block (in block order) of shared node s writes
         // slot j < PARTIAL_SLOTS at j * nsh + s (slot-major, so the combine's
         // loads are coalesced and need no index; unused slots stay zero), and

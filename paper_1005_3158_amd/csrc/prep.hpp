@@ -81,6 +81,10 @@ struct Layout {
     std::vector<int32_t> seg_scen;    // n_seg
     std::vector<int32_t> sh_list;     // per block: global ids of its shared nodes
     std::vector<uint16_t> lconn;      // per element: local ids in its block
+    // tets in blocks of at most 4096 nodes: the same ids packed 12 bits each, two
+    // tets per three 32-bit words (tet 2p in bits 0-47 of words 3p..3p+2, tet
+    // 2p+1 in bits 48-95); empty otherwise
+    std::vector<uint32_t> lconn12;
     // partials of shared node s: slot j < PARTIAL_SLOTS at j * nsh + s, the
     // others at PARTIAL_SLOTS * nsh + [comb_ptr[s], comb_ptr[s+1]), all in block order
     std::vector<int32_t> comb_ptr;

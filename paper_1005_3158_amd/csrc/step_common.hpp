@@ -12,6 +12,48 @@
 namespace castfem {
 namespace step {
 
+// Local ids of element e (global element index) of the blocked layout: raw
+// words loaded ahead of their use (x, y, z; w = which tet of a packed pair, or
+// 2 for 16-bit ids), then decoded.
+template <int NEN>
+struct ConnRaw {
+    uint32_t x, y, z, w;
+};
+template <int NEN>
+__device__ __forceinline__ ConnRaw<NEN> conn_load(const Dev &d, int64_t e) {
+    if constexpr (NEN == 4) {
+        if (d.conn12) {
+            const uint3 v = ((const uint3 *)d.lconn)[e >> 1];
+            return {v.x, v.y, v.z, (uint32_t)(e & 1)};
+        }
+        const uint2 v = ((const uint2 *)d.lconn)[e];
+        return {v.x, v.y, 0u, 2u};
+    } else {
+        const uint4 v = ((const uint4 *)d.lconn)[e];
+        return {v.x, v.y, v.z, v.w};
+    }
+}
+template <int NEN>
+__device__ __forceinline__ void conn_ids(const ConnRaw<NEN> &c, int *l) {
+    if constexpr (NEN == 4) {
+        if (c.w == 2u) {
+            l[0] = c.x & 0xFFFF;
+            l[1] = c.x >> 16;
+            l[2] = c.y & 0xFFFF;
+            l[3] = c.y >> 16;
+        } else {
+            const uint64_t v = c.w ? (((uint64_t)c.z << 16) | (c.y >> 16)) : (((uint64_t)c.y << 32) | c.x);
+            for (int a = 0; a < 4; ++a) l[a] = (int)((v >> (12 * a)) & 0xFFFu);
+        }
+    } else {
+        const uint32_t w[4] = {c.x, c.y, c.z, c.w};
+        for (int a = 0; a < 4; ++a) {
+            l[2 * a] = w[a] & 0xFFFF;
+            l[2 * a + 1] = w[a] >> 16;
+        }
+    }
+}
+
 template <class R> struct VT;
 template <> struct VT<float> { using V4 = float4; using V2 = float2; };
 template <> struct VT<double> { using V4 = double4; using V2 = double2; };

@@ -13,6 +13,8 @@
 //     without host involvement.
 #include "varprops.hpp"
 
+#include <hip/hip_ext.h>
+
 #include <type_traits>
 
 #include "elem.hpp"
@@ -80,7 +82,6 @@ __device__ __forceinline__ void elem_residual(const typename VT<R>::V4 *p, R k, 
 template <class R, int NEN, bool LDS_TABLES>
 __global__ __launch_bounds__(1024) void k_block_var(VarDev v, int parity) {
     using V4 = typename VT<R>::V4;
-    using LC = typename std::conditional<NEN == 4, uint2, uint4>::type;
     using ACC = typename std::conditional<std::is_same<R, float>::value, long long, double>::type;
     const Dev &d = v.d;
     extern __shared__ __attribute__((aligned(32))) unsigned char smem[];
@@ -113,26 +114,14 @@ __global__ __launch_bounds__(1024) void k_block_var(VarDev v, int parity) {
     }
     __syncthreads();
 
-    const LC *lc = (const LC *)(d.lconn + (int64_t)bi.e_begin * NEN);
-    LC cur{};
-    if ((int)threadIdx.x < bi.n_e) cur = lc[threadIdx.x];
+    step::ConnRaw<NEN> cur{};
+    if ((int)threadIdx.x < bi.n_e) cur = step::conn_load<NEN>(d, (int64_t)bi.e_begin + threadIdx.x);
     bool bad = false;
     for (int e = threadIdx.x; e < bi.n_e; e += blockDim.x) {
-        LC nxt{};
-        if (e + (int)blockDim.x < bi.n_e) nxt = lc[e + blockDim.x];
+        step::ConnRaw<NEN> nxt{};
+        if (e + (int)blockDim.x < bi.n_e) nxt = step::conn_load<NEN>(d, (int64_t)bi.e_begin + e + blockDim.x);
         int l[NEN];
-        if constexpr (NEN == 4) {
-            l[0] = cur.x & 0xFFFF;
-            l[1] = cur.x >> 16;
-            l[2] = cur.y & 0xFFFF;
-            l[3] = cur.y >> 16;
-        } else {
-            const uint32_t w[4] = {cur.x, cur.y, cur.z, cur.w};
-            for (int a = 0; a < 4; ++a) {
-                l[2 * a] = w[a] & 0xFFFF;
-                l[2 * a + 1] = w[a] >> 16;
-            }
-        }
+        step::conn_ids<NEN>(cur, l);
         V4 p[NEN];
         for (int a = 0; a < NEN; ++a) p[a] = s_x[l[a]];
         // conductivity at the element's mean temperature
@@ -263,18 +252,15 @@ __global__ __launch_bounds__(NODE_THREADS) void k_nodes_var(VarDev v, int parity
 template <class R, int NEN, bool LDS_TABLES>
 hipError_t step_t(const VarDev &v, int parity, hipStream_t s, hipEvent_t *ev) {
     const Dev &d = v.d;
-    if (ev) (void)hipEventRecord(ev[0], s);
-    hipLaunchKernelGGL((k_block_var<R, NEN, LDS_TABLES>), dim3((unsigned)d.n_blocks), dim3(d.threads), d.lds_bytes, s,
-                       v, parity);
-    if (ev) {
-        (void)hipEventRecord(ev[1], s);
-        (void)hipEventRecord(ev[2], s);
-    }
+    // timed launches (eager) carry their own start and stop events
+    const dim3 gb((unsigned)d.n_blocks), bb(d.threads);
+    if (ev) hipExtLaunchKernelGGL((k_block_var<R, NEN, LDS_TABLES>), gb, bb, (uint32_t)d.lds_bytes, s, ev[0], ev[1], 0u, v, parity);
+    else hipLaunchKernelGGL((k_block_var<R, NEN, LDS_TABLES>), gb, bb, d.lds_bytes, s, v, parity);
     // launched even without shared nodes: its first n_scen threads advance the time
     const int64_t count = d.N - d.n_private;
-    hipLaunchKernelGGL((k_nodes_var<R, LDS_TABLES>), dim3((unsigned)node_grid(std::max<int64_t>(count, v.n_scen))),
-                       dim3(NODE_THREADS), 0, s, v, parity);
-    if (ev) (void)hipEventRecord(ev[3], s);
+    const dim3 g((unsigned)node_grid(std::max<int64_t>(count, v.n_scen))), b(NODE_THREADS);
+    if (ev) hipExtLaunchKernelGGL((k_nodes_var<R, LDS_TABLES>), g, b, 0u, s, ev[2], ev[3], 0u, v, parity);
+    else hipLaunchKernelGGL((k_nodes_var<R, LDS_TABLES>), g, b, 0, s, v, parity);
     return hipGetLastError();
 }
 
