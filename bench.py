@@ -71,7 +71,8 @@ def load_traffic(kind, block_nodes, sources=ENTHALPY_SOURCES):
 def traffic_from_counters(fetch_dir, write_dir, block_nodes, kernel_key="k_block<float, 4, true>",
                           out_name="block_element_config2"):
     """Summarise two rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE,
-    KiB per dispatch) into HBM bytes per launch of the blocked element kernel.
+    KiB per dispatch) into HBM bytes per launch of a kernel, over its dispatches in
+    the launch shape of its last one.
     Each counter is scaled by what it reads for the plain 1 GiB copy kernel the
     benchmark launches in the same run (1 GiB read and 1 GiB written)."""
     import csv
@@ -81,8 +82,13 @@ def traffic_from_counters(fetch_dir, write_dir, block_nodes, kernel_key="k_block
         rows = []
         for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
             rows += list(csv.DictReader(open(f)))
-        kern = [float(r["Counter_Value"]) for r in rows if kernel_key in r["Kernel_Name"]]
-        copy = [float(r["Counter_Value"]) for r in rows if "k_copy" in r["Kernel_Name"]]
+        rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+        kr = [r for r in rows if kernel_key in r["Kernel_Name"]]
+        # the launch shape of the timed runs (the last dispatch): an autotuner's trial
+        # launches of other block shapes share the kernel's name
+        shape = (kr[-1]["Grid_Size"], kr[-1]["Workgroup_Size"])
+        kern = [float(r["Counter_Value"]) for r in kr if (r["Grid_Size"], r["Workgroup_Size"]) == shape]
+        copy = [float(r["Counter_Value"]) for r in rows if "::k_copy(" in r["Kernel_Name"]]   # the plain copy
         return sum(kern) / len(kern), sum(copy) / len(copy), len(kern)
 
     kf, cf_, nk = per_kernel(fetch_dir)
