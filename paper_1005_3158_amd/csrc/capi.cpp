@@ -38,6 +38,8 @@ void layout_sizes(const fem_ctx *c, const Layout &L, int64_t *sz) {
     } else {
         const int64_t np = (int64_t)L.sh_list.size();
         sz[B_LCONN] = L.lconn12.empty() ? E * L.nen * 2 : (int64_t)L.lconn12.size() * 4;
+        sz[B_VCONN] = (int64_t)L.vconn.size() * 2;
+        sz[B_VW] = (int64_t)L.vw.size() * R;
         sz[B_BLOCKS] = (int64_t)L.blocks.size() * (int64_t)sizeof(BlockInfo);
         sz[B_SH_LIST] = (np + 1) * 4;   // one padding entry: the gather's clamped loads
         sz[B_PARTIALS] = L.n_partial_slots * R;
@@ -168,7 +170,7 @@ void upload_layout_t(fem_ctx *c, const Layout &L) {
     h2d(c, B_T, T2.data(), 2 * N * (int64_t)sizeof(R));
     h2d(c, B_FS, fs.data(), N * (int64_t)sizeof(R));
     h2d(c, B_FLAGS, L.nflag.data(), N * 4);
-    std::vector<R> rob(L.robin_a.size() * 2), lw(L.link_w.size());
+    std::vector<R> rob(L.robin_a.size() * 2), lw(L.link_w.size()), vw;
     std::vector<BlockInfo> blocks_app;
     std::vector<int32_t> node_win;
     for (size_t s = 0; s < L.robin_a.size(); ++s) {
@@ -183,6 +185,12 @@ void upload_layout_t(fem_ctx *c, const Layout &L) {
     if (c->opt.scatter == FEM_SCATTER_LDS_BLOCKED) {
         if (L.lconn12.empty()) h2d(c, B_LCONN, L.lconn.data(), (int64_t)L.lconn.size() * 2);
         else h2d(c, B_LCONN, L.lconn12.data(), (int64_t)L.lconn12.size() * 4);
+        if (!L.vw.empty()) {
+            h2d(c, B_VCONN, L.vconn.data(), (int64_t)L.vconn.size() * 2);
+            vw.resize(L.vw.size());
+            for (size_t v = 0; v < L.vw.size(); ++v) vw[v] = (R)L.vw[v];
+            h2d(c, B_VW, vw.data(), (int64_t)vw.size() * (int64_t)sizeof(R));
+        }
         // per block: its one material or -1 (pad0; the apparent-capacity kernels
         // read the constants of a single-material block once), and the first row
         // of its window of MAT_WINDOW material rows or -1 if its materials span
@@ -321,6 +329,8 @@ void fill_dev(fem_ctx *c, const Candidate &cd) {
     d.r = c->ptr[B_R];
     d.lconn = (const uint16_t *)c->ptr[B_LCONN];
     d.conn12 = L.lconn12.empty() ? 0 : 1;
+    d.vconn = (const uint16_t *)c->ptr[B_VCONN];
+    d.vw = c->ptr[B_VW];
     d.blocks = (const BlockInfo *)c->ptr[B_BLOCKS];
     d.sh_list = (const int32_t *)c->ptr[B_SH_LIST];
     d.partials = c->ptr[B_PARTIALS];
@@ -866,6 +876,9 @@ int fem_finalize(fem_ctx *ctx, fem_prep_report *rep) {
             c.threads = thr;
             cands.push_back(std::move(c));
         }
+        // matched interface pairs become elements of the blocks in the enthalpy
+        // step with constant properties (the other forms keep them as node links)
+        for (Candidate &cd : cands) cd.o.interface_in_blocks = !ctx->apparent() && !ctx->variable();
         // candidate layouts are independent: build them concurrently
         std::vector<PrepError> errs(cands.size(), PrepError{FEM_OK, ""});
 #pragma omp parallel for schedule(dynamic, 1)

@@ -33,13 +33,13 @@ enum Stage { ST_NEW = 0, ST_FINAL = 1, ST_BOUND = 2 };
 enum Buf {
     B_NODE_X, B_T, B_H, B_INV_M, B_FS, B_MATS, B_CONN, B_R, B_LCONN, B_BLOCKS, B_SH_LIST, B_PARTIALS,
     B_COMB_PTR, B_SH_POS, B_ROBIN, B_LINK_PTR, B_LINK_NODE, B_LINK_W, B_DIAG, B_QNODE, B_FLAGS, B_SEG,
-    B_CAP_PARTIALS, B_APP_MATS, B_VAR_TABS_F, B_VAR_TABS_D, B_T_FIXED, B_TIME, B_NODE_WIN, B_SCHED, B_VAR_SCEN, B_COUNT
+    B_CAP_PARTIALS, B_APP_MATS, B_VAR_TABS_F, B_VAR_TABS_D, B_T_FIXED, B_TIME, B_NODE_WIN, B_SCHED, B_VAR_SCEN, B_VCONN, B_VW, B_COUNT
 };
 inline const char *const BUF_NAMES[B_COUNT] = {"node_x", "T", "H", "inv_m", "fs", "mats", "conn", "r", "lconn", "blocks",
                                   "sh_list", "partials", "comb_ptr", "sh_pos", "robin", "link_ptr",
                                   "link_node", "link_w", "diag", "qnode", "flags", "segments",
                                   "cap_partials", "app_mats", "var_tables_f32", "var_tables_f64", "T_fixed",
-                                  "time", "node_windows", "dirichlet_schedule", "var_scenarios"};
+                                  "time", "node_windows", "dirichlet_schedule", "var_scenarios", "pair_conn", "pair_w"};
 constexpr int64_t ALIGN = 256;
 constexpr int GRAPH_STEPS = 16;  // steps per captured graph (even: both parities)
 constexpr size_t MAX_BLOCK_LDS = 160 * 1024 - 2048;  // gfx950 LDS per workgroup, less static use

@@ -245,6 +245,39 @@ __global__ __launch_bounds__(1024) void k_block(Dev d, int parity) {
         }
         cur = nxt;
     }
+    // matched interface pairs of the block (Eq. 8 with the sister face's mean as
+    // ambient): node p of face a receives w (sum of face b's T - 3 T_p) and node
+    // q of face b the converse; the six sum to zero, exactly in fixed point
+    for (int v = threadIdx.x; v < bi.n_v; v += blockDim.x) {
+        const int64_t gv = (int64_t)bi.v_begin + v;
+        const uint32_t *vc = (const uint32_t *)(d.vconn + 6 * gv);
+        const uint32_t c0 = vc[0], c1 = vc[1], c2 = vc[2];
+        const int l[6] = {(int)(c0 & 0xFFFF), (int)(c0 >> 16), (int)(c1 & 0xFFFF),
+                          (int)(c1 >> 16), (int)(c2 & 0xFFFF), (int)(c2 >> 16)};
+        const R w = ((const R *)d.vw)[gv];
+        R T[6];
+        for (int a = 0; a < 6; ++a) T[a] = s_x[l[a]].w;
+        const R sa = (T[0] + T[1]) + T[2], sb = (T[3] + T[4]) + T[5];
+        R re[6];
+        for (int a = 0; a < 3; ++a) {
+            re[a] = w * (sb - R(3) * T[a]);
+            re[3 + a] = w * (sa - R(3) * T[3 + a]);
+        }
+        if constexpr (std::is_same<R, float>::value) {
+            long long q[6];
+            long long sum = 0;
+            for (int a = 1; a < 6; ++a) {
+                bad |= !(fabsf(re[a]) < d.fx_limit);
+                q[a] = fx_from(re[a], d.fx_scale);
+                sum += q[a];
+            }
+            q[0] = -sum;
+            for (int a = 0; a < 6; ++a)
+                atomicAdd((unsigned long long *)&s_acc[l[a]], (unsigned long long)q[a]);
+        } else {
+            for (int a = 0; a < 6; ++a) atomicAdd(&s_acc[l[a]], re[a]);
+        }
+    }
     if (bad) s_bad = 1;
     __syncthreads();
 

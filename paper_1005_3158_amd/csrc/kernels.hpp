@@ -41,6 +41,10 @@ struct Dev {
     // with 12-bit ids (see step::conn_load)
     const uint16_t *lconn = nullptr;
     int32_t conn12 = 0;
+    // matched interface pairs as block elements: six local ids per pair (face a,
+    // face b; BlockInfo::v_begin / n_v) and the coupling w (R) of each
+    const uint16_t *vconn = nullptr;
+    const void *vw = nullptr;
     const BlockInfo *blocks = nullptr;
     const int32_t *sh_list = nullptr;
     void *partials = nullptr;           // R per partial slot (see Layout::comb_ptr)

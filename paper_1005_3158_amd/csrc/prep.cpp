@@ -197,6 +197,7 @@ void prep_base(const Problem &p, Base &b) {
     std::vector<Trip> t;
     const int64_t npair = (int64_t)p.if_h.size();
     t.reserve(npair * 18);
+    b.pair_w.assign(npair, 0.0);
     for (int64_t f = 0; f < npair; ++f) {
         const int32_t *fa = &p.if_a[3 * f], *fb = &p.if_b[3 * f];
         for (int a = 0; a < 3; ++a)
@@ -205,6 +206,7 @@ void prep_base(const Problem &p, Base &b) {
             fail(FEM_E_MESH, "interface pair " + std::to_string(f) + " joins two scenarios");
         double A = face_area(p.xyz, fa, 3);
         double w = p.if_h[f] * A / 9.0;
+        b.pair_w[f] = w;
         for (int a = 0; a < 3; ++a)
             for (int c = 0; c < 3; ++c) {
                 t.push_back({fa[a], fb[c], w});
@@ -232,20 +234,28 @@ void prep_base(const Problem &p, Base &b) {
     } else {
         b.sisters.clear();
     }
-    std::sort(t.begin(), t.end(), [](const Trip &x, const Trip &y) { return x.i != y.i ? x.i < y.i : x.j < y.j; });
-    b.lptr.assign(N + 1, 0);
-    b.lnode.clear();
-    b.lw.clear();
-    for (size_t s = 0; s < t.size();) {
-        size_t u = s;
-        double w = 0;
-        while (u < t.size() && t[u].i == t[s].i && t[u].j == t[s].j) w += t[u++].w;
-        b.lnode.push_back(t[s].j);
-        b.lw.push_back(w);
-        b.lptr[t[s].i + 1]++;
-        s = u;
-    }
-    for (int64_t i = 0; i < N; ++i) b.lptr[i + 1] += b.lptr[i];
+    // CSR by node of trips [t0, t1) of t, equal (i, j) merged
+    auto to_csr = [&](size_t t0, size_t t1, std::vector<int32_t> &ptr, std::vector<int32_t> &node,
+                      std::vector<double> &wt) {
+        std::sort(t.begin() + t0, t.begin() + t1,
+                  [](const Trip &x, const Trip &y) { return x.i != y.i ? x.i < y.i : x.j < y.j; });
+        ptr.assign(N + 1, 0);
+        node.clear();
+        wt.clear();
+        for (size_t s = t0; s < t1;) {
+            size_t u = s;
+            double w = 0;
+            while (u < t1 && t[u].i == t[s].i && t[u].j == t[s].j) w += t[u++].w;
+            node.push_back(t[s].j);
+            wt.push_back(w);
+            ptr[t[s].i + 1]++;
+            s = u;
+        }
+        for (int64_t i = 0; i < N; ++i) ptr[i + 1] += ptr[i];
+    };
+    // the contact links alone (before the trips are sorted together)
+    to_csr((size_t)npair * 18, t.size(), b.clptr, b.clnode, b.clw);
+    to_csr(0, t.size(), b.lptr, b.lnode, b.lw);
     tm.mark("boundary terms");
     // stability bound: Gershgorin rows of the assembled operator over m_i c_i
     std::vector<int64_t> ptr, inc;
@@ -282,6 +292,8 @@ void prep_base(const Problem &p, Base &b) {
                     eabs += std::fabs(Ke[a][c]);
                 }
             }
+            // interface couplings may be summed in the element blocks too
+            for (int32_t s = b.lptr[i]; s < b.lptr[i + 1]; ++s) eabs += 2.0 * b.lw[s];
             if (eabs > eabs_t) eabs_t = eabs;
             double kabs = 0.0;
             for (double v : vals) kabs += std::fabs(v);
@@ -652,17 +664,16 @@ std::vector<int32_t> order_sfc(const Problem &p, bool hilbert) {
 namespace {
 
 // element order for a node ordering: SFC key of the centroid for curve
-// orderings, the smallest renumbered node otherwise
-std::vector<int64_t> element_order(const Problem &p, const std::vector<int32_t> &perm, int ordering) {
+// orderings, the smallest and largest renumbered node otherwise; the keys of
+// the ordered elements in `keys`
+std::vector<int64_t> element_order(const Problem &p, const std::vector<int32_t> &perm, int ordering,
+                                   std::vector<uint64_t> &keys) {
     const int64_t E = p.E;
     const int nen = p.nen;
-    if (ordering == FEM_ORDER_NONE) {
-        std::vector<int64_t> idx(E);
-        std::iota(idx.begin(), idx.end(), 0);
-        return idx;
-    }
     std::vector<uint64_t> key(E);
-    if (ordering == FEM_ORDER_MORTON || ordering == FEM_ORDER_HILBERT) {
+    if (ordering == FEM_ORDER_NONE) {
+        for (int64_t e = 0; e < E; ++e) key[e] = (uint64_t)e;
+    } else if (ordering == FEM_ORDER_MORTON || ordering == FEM_ORDER_HILBERT) {
         Quant qz(p.xyz, p.N, E);
 #pragma omp parallel for
         for (int64_t e = 0; e < E; ++e) {
@@ -683,7 +694,48 @@ std::vector<int64_t> element_order(const Problem &p, const std::vector<int32_t> 
             key[e] = (lo << 32) | hi;
         }
     }
-    return sort_by_key<int64_t>(key);
+    std::vector<int64_t> order = ordering == FEM_ORDER_NONE ? std::vector<int64_t>() : sort_by_key<int64_t>(key);
+    if (ordering == FEM_ORDER_NONE) {
+        order.resize(E);
+        std::iota(order.begin(), order.end(), 0);
+    }
+    keys.resize(E);
+    for (int64_t r = 0; r < E; ++r) keys[r] = key[order[r]];
+    return order;
+}
+
+// matched interface pairs in the same kind of order: the centroid of face a (which
+// face b shares) for curve orderings, the smallest and largest renumbered node of
+// the six otherwise, after every element without an ordering
+std::vector<int64_t> pair_order(const Problem &p, const std::vector<int32_t> &perm, int ordering,
+                                std::vector<uint64_t> &keys) {
+    const int64_t P = (int64_t)p.if_h.size();
+    std::vector<uint64_t> key(P);
+    if (ordering == FEM_ORDER_NONE) {
+        for (int64_t f = 0; f < P; ++f) key[f] = (uint64_t)(p.E + f);
+    } else if (ordering == FEM_ORDER_MORTON || ordering == FEM_ORDER_HILBERT) {
+        Quant qz(p.xyz, p.N, p.E);
+        for (int64_t f = 0; f < P; ++f) {
+            double c[3] = {0, 0, 0};
+            for (int a = 0; a < 3; ++a)
+                for (int d = 0; d < 3; ++d) c[d] += p.xyz[3 * (int64_t)p.if_a[3 * f + a] + d];
+            key[f] = qz.key(c[0] / 3, c[1] / 3, c[2] / 3, ordering == FEM_ORDER_HILBERT);
+        }
+    } else {
+        for (int64_t f = 0; f < P; ++f) {
+            uint64_t lo = UINT64_MAX, hi = 0;
+            for (int a = 0; a < 6; ++a) {
+                const uint64_t v = (uint64_t)perm[a < 3 ? p.if_a[3 * f + a] : p.if_b[3 * f + a - 3]];
+                lo = std::min(lo, v);
+                hi = std::max(hi, v);
+            }
+            key[f] = (lo << 32) | hi;
+        }
+    }
+    std::vector<int64_t> order = sort_by_key<int64_t>(key);
+    keys.resize(P);
+    for (int64_t r = 0; r < P; ++r) keys[r] = key[order[r]];
+    return order;
 }
 
 }  // namespace
@@ -698,7 +750,10 @@ void prep_order(const Problem &p, const Base &b, int ordering, Ordering &ord) {
         std::iota(ord.perm.begin(), ord.perm.end(), 0);
     } else fail(FEM_E_INVALID_ARG, "unknown ordering");
     tm.mark("node ordering");
-    ord.eorder = element_order(p, ord.perm, ordering);
+    ord.eorder = element_order(p, ord.perm, ordering, ord.ekey);
+    ord.porder = pair_order(p, ord.perm, ordering, ord.pkey);
+    ord.escen.assign(p.E, 0);
+    ord.pscen.assign(ord.porder.size(), 0);
     tm.mark("element ordering");
     if (p.n_scen > 1) {
         // a batch is numbered scenario by scenario (the ordering applies
@@ -714,8 +769,28 @@ void prep_order(const Problem &p, const Base &b, int ordering, Ordering &ord) {
         for (int64_t r = 0; r < p.E; ++r) ekey[r] = ((uint64_t)p.scen_of_mat(p.emat[ord.eorder[r]]) << 40) | (uint64_t)r;
         std::vector<int64_t> eidx = sort_by_key<int64_t>(ekey);
         std::vector<int64_t> e2(p.E);
-        for (int64_t r = 0; r < p.E; ++r) e2[r] = ord.eorder[eidx[r]];
+        std::vector<uint64_t> k2(p.E);
+        for (int64_t r = 0; r < p.E; ++r) {
+            e2[r] = ord.eorder[eidx[r]];
+            k2[r] = ord.ekey[eidx[r]];
+            ord.escen[r] = (uint64_t)p.scen_of_mat(p.emat[e2[r]]);
+        }
         ord.eorder.swap(e2);
+        ord.ekey.swap(k2);
+        // interface pairs likewise (a pair never joins two scenarios)
+        const int64_t P = (int64_t)ord.porder.size();
+        std::vector<uint64_t> pk(P);
+        for (int64_t r = 0; r < P; ++r) pk[r] = ((uint64_t)p.scen_of_mat(nm[p.if_a[3 * ord.porder[r]]]) << 40) | (uint64_t)r;
+        std::vector<int64_t> pidx = sort_by_key<int64_t>(pk);
+        std::vector<int64_t> p2(P);
+        std::vector<uint64_t> q2(P);
+        for (int64_t r = 0; r < P; ++r) {
+            p2[r] = ord.porder[pidx[r]];
+            q2[r] = ord.pkey[pidx[r]];
+            ord.pscen[r] = (uint64_t)p.scen_of_mat(nm[p.if_a[3 * p2[r]]]);
+        }
+        ord.porder.swap(p2);
+        ord.pkey.swap(q2);
         tm.mark("scenario-major order");
     }
 }
@@ -733,52 +808,91 @@ void prep_layout(const Problem &p, const Base &b, const PrepOptions &o, const Or
     std::vector<int32_t> perm = ord.perm;
     std::vector<int64_t> eorder = ord.eorder;
 
+    // matched interface pairs as block elements (blocked enthalpy step): their
+    // couplings leave the node links, which keep the contact faces alone
+    const bool pairs_in_blocks = o.interface_in_blocks && o.scatter == FEM_SCATTER_LDS_BLOCKED && !ord.porder.empty();
+    const std::vector<int32_t> &lptr = pairs_in_blocks ? b.clptr : b.lptr;
+    const std::vector<int32_t> &lnode = pairs_in_blocks ? b.clnode : b.lnode;
+    const std::vector<double> &lw = pairs_in_blocks ? b.clw : b.lw;
     auto has_bc = [&](int64_t i) {
-        return b.robin_b[i] != 0.0 || b.robin_a[i] != 0.0 || b.lptr[i + 1] > b.lptr[i];
+        return b.robin_b[i] != 0.0 || b.robin_a[i] != 0.0 || lptr[i + 1] > lptr[i];
     };
+    L.vconn.clear();
+    L.vw.clear();
 
     // 2. element blocks (LDS-blocked scatter) and the final node numbering
     if (o.scatter == FEM_SCATTER_LDS_BLOCKED) {
         if (o.max_local_nodes > 65535) fail(FEM_E_INVALID_ARG, "block node cap above 65535");
         std::vector<int64_t> stamp(N, -1);
-        std::vector<std::pair<int64_t, int64_t>> blk;  // (first slot in eorder, count)
-        int64_t cur = 0, nloc = 0, start = 0;
-        int32_t cur_scen = E ? p.scen_of_mat(p.emat[eorder[0]]) : 0;
-        for (int64_t s = 0; s < E; ++s) {
-            const int32_t *c = &p.conn[eorder[s] * nen];
+        // the elements (in eorder) and the interface pairs (in ord.porder) of
+        // every block: both streams are sorted by (scenario, key), and a block
+        // takes the next item of their merge until a cap or a scenario change
+        struct Blk {
+            int64_t e0, ne, v0, nv;
+        };
+        std::vector<Blk> blk;
+        const int64_t P = pairs_in_blocks ? (int64_t)ord.porder.size() : 0;
+        auto item_nodes = [&](bool pair, int64_t k, int32_t *nd) {
+            if (!pair) {
+                for (int a = 0; a < nen; ++a) nd[a] = p.conn[eorder[k] * nen + a];
+                return nen;
+            }
+            const int64_t f = ord.porder[k];
+            for (int a = 0; a < 3; ++a) {
+                nd[a] = p.if_a[3 * f + a];
+                nd[3 + a] = p.if_b[3 * f + a];
+            }
+            return 6;
+        };
+        int64_t cur = 0, nloc = 0, e0 = 0, v0 = 0, ie = 0, iv = 0;
+        int32_t cur_scen = -1;
+        while (ie < E || iv < P) {
+            const bool pair = iv < P && (ie >= E || ord.pscen[iv] < ord.escen[ie] ||
+                                         (ord.pscen[iv] == ord.escen[ie] && ord.pkey[iv] < ord.ekey[ie]));
+            int32_t nd[8];
+            const int k = item_nodes(pair, pair ? iv : ie, nd);
             int nnew = 0;
-            for (int a = 0; a < nen; ++a) nnew += stamp[c[a]] != cur;
-            int64_t cnt = s - start;
-            const int32_t sc = p.scen_of_mat(p.emat[eorder[s]]);
+            for (int a = 0; a < k; ++a) nnew += stamp[nd[a]] != cur;
+            const int64_t cnt = (ie - e0) + (iv - v0);
+            const int32_t sc = pair ? (int32_t)ord.pscen[iv] : p.scen_of_mat(p.emat[eorder[ie]]);
+            if (cur_scen < 0) cur_scen = sc;
             if (cnt > 0 && (cnt + 1 > o.block_elems || nloc + nnew > o.max_local_nodes || sc != cur_scen)) {
                 cur_scen = sc;
-                blk.push_back({start, cnt});
+                blk.push_back({e0, ie - e0, v0, iv - v0});
                 ++cur;
-                start = s;
+                e0 = ie;
+                v0 = iv;
                 nloc = 0;
-                nnew = nen;
-                for (int a = 0; a < nen; ++a)
+                nnew = k;
+                for (int a = 0; a < k; ++a)
                     for (int q = 0; q < a; ++q)
-                        if (c[q] == c[a]) --nnew;
+                        if (nd[q] == nd[a]) --nnew;
             }
-            for (int a = 0; a < nen; ++a) stamp[c[a]] = cur;
+            for (int a = 0; a < k; ++a) stamp[nd[a]] = cur;
             nloc += nnew;
+            if (pair) ++iv;
+            else ++ie;
         }
-        if (E - start > 0) blk.push_back({start, E - start});
+        if ((ie - e0) + (iv - v0) > 0) blk.push_back({e0, ie - e0, v0, iv - v0});
         const int64_t nb = (int64_t)blk.size();
         // blocks touching each node; owner block of private nodes
         std::vector<int32_t> nblk(N, 0), owner(N, -1);
         std::fill(stamp.begin(), stamp.end(), -1);
+        auto block_nodes = [&](int64_t q, auto &&visit) {
+            int32_t nd[8];
+            for (int64_t s = blk[q].e0; s < blk[q].e0 + blk[q].ne; ++s)
+                for (int a = 0, k = item_nodes(false, s, nd); a < k; ++a) visit(nd[a]);
+            for (int64_t v = blk[q].v0; v < blk[q].v0 + blk[q].nv; ++v)
+                for (int a = 0, k = item_nodes(true, v, nd); a < k; ++a) visit(nd[a]);
+        };
         for (int64_t q = 0; q < nb; ++q)
-            for (int64_t s = blk[q].first; s < blk[q].first + blk[q].second; ++s)
-                for (int a = 0; a < nen; ++a) {
-                    int32_t n = p.conn[eorder[s] * nen + a];
-                    if (stamp[n] != q) {
-                        stamp[n] = q;
-                        nblk[n]++;
-                        if (owner[n] < 0) owner[n] = (int32_t)q;
-                    }
+            block_nodes(q, [&](int32_t n) {
+                if (stamp[n] != q) {
+                    stamp[n] = q;
+                    nblk[n]++;
+                    if (owner[n] < 0) owner[n] = (int32_t)q;
                 }
+            });
         // private nodes grouped by owner block, in ordering rank within a block;
         // shared nodes after them ordered by first block then rank
         std::vector<int32_t> priv, shar;
@@ -819,6 +933,8 @@ void prep_layout(const Problem &p, const Base &b, const PrepOptions &o, const Or
         L.blocks.resize(nb);
         L.sh_list.clear();
         L.lconn.resize(E * nen);
+        L.vconn.assign(6 * P, 0);
+        L.vw.assign(P, 0.0);
         L.max_local = 0;
         std::vector<int32_t> local(N, -1);
         std::vector<int32_t> shl;
@@ -827,16 +943,16 @@ void prep_layout(const Problem &p, const Base &b, const PrepOptions &o, const Or
         std::vector<int64_t> bord;
         for (int64_t q = 0; q < nb; ++q) {
             BlockInfo &bi = L.blocks[q];
-            bi.e_begin = (int32_t)blk[q].first;
-            bi.n_e = (int32_t)blk[q].second;
+            bi.e_begin = (int32_t)blk[q].e0;
+            bi.n_e = (int32_t)blk[q].ne;
+            bi.v_begin = (int32_t)blk[q].v0;
+            bi.n_v = (int32_t)blk[q].nv;
             bi.int_base = (int32_t)priv_begin[q];
             bi.n_int = (int32_t)(priv_begin[q + 1] - priv_begin[q]);
             shl.clear();
-            for (int64_t s = blk[q].first; s < blk[q].first + blk[q].second; ++s)
-                for (int a = 0; a < nen; ++a) {
-                    int32_t n = p.conn[eorder[s] * nen + a];
-                    if (perm[n] >= L.n_private) shl.push_back(perm[n]);
-                }
+            block_nodes(q, [&](int32_t n) {
+                if (perm[n] >= L.n_private) shl.push_back(perm[n]);
+            });
             std::sort(shl.begin(), shl.end());
             shl.erase(std::unique(shl.begin(), shl.end()), shl.end());
             bi.sh_begin = (int32_t)L.sh_list.size();
@@ -846,7 +962,7 @@ void prep_layout(const Problem &p, const Base &b, const PrepOptions &o, const Or
             for (size_t r = 0; r < shl.size(); ++r) local[shl[r]] = bi.n_int + (int32_t)r;
             const int64_t nl = bi.n_int + bi.n_sh;
             L.max_local = std::max<int64_t>(L.max_local, nl);
-            const int64_t b0 = blk[q].first, b1 = blk[q].first + blk[q].second;
+            const int64_t b0 = blk[q].e0, b1 = blk[q].e0 + blk[q].ne;
             auto local_id = [&](int64_t s, int a) {
                 int32_t g = perm[p.conn[eorder[s] * nen + a]];
                 int32_t l = g < L.n_private ? g - bi.int_base : local[g];
@@ -884,6 +1000,18 @@ void prep_layout(const Problem &p, const Base &b, const PrepOptions &o, const Or
             }
             for (int64_t s = b0; s < b1; ++s)
                 for (int a = 0; a < nen; ++a) L.lconn[s * nen + a] = (uint16_t)local_id(s, a);
+            // interface pairs: face a then face b, in local ids, with their coupling
+            for (int64_t v = blk[q].v0; v < blk[q].v0 + blk[q].nv; ++v) {
+                int32_t nd[8];
+                item_nodes(true, v, nd);
+                for (int a = 0; a < 6; ++a) {
+                    const int32_t g = perm[nd[a]];
+                    const int32_t l = g < L.n_private ? g - bi.int_base : local[g];
+                    if (l < 0 || l >= nl) fail(FEM_E_MESH, "internal: block numbering of an interface pair");
+                    L.vconn[v * 6 + a] = (uint16_t)l;
+                }
+                L.vw[v] = b.pair_w[ord.porder[v]];
+            }
         }
         if (L.max_local > o.max_local_nodes) fail(FEM_E_INVALID_ARG, "internal: block above node cap");
         // tets with 12-bit local ids: 6 bytes of connectivity per element instead of 8
@@ -998,9 +1126,9 @@ void prep_layout(const Problem &p, const Base &b, const PrepOptions &o, const Or
             L.robin_a[s] = b.robin_a[i];
             L.robin_b[s] = b.robin_b[i];
         }
-        for (int32_t q = b.lptr[i]; q < b.lptr[i + 1]; ++q) {
-            L.link_node.push_back(perm[b.lnode[q]]);
-            L.link_w.push_back(b.lw[q]);
+        for (int32_t q = lptr[i]; q < lptr[i + 1]; ++q) {
+            L.link_node.push_back(perm[lnode[q]]);
+            L.link_w.push_back(lw[q]);
         }
         L.link_ptr[s + 1] = (int32_t)L.link_node.size();
     }

@@ -39,7 +39,7 @@ enum : uint32_t { NODE_FIXED = 1u << 31, NODE_BC = 1u << 30, NODE_XTRA = 1u << 2
 // partial residuals per shared node held slot-major (the rest go to a list)
 constexpr int PARTIAL_SLOTS = 4;
 
-struct BlockInfo {        // one LDS element block (8 ints, 32 bytes)
+struct BlockInfo {        // one LDS element block (10 ints, 40 bytes)
     int32_t e_begin;      // first element of the block (blocked element order)
     int32_t n_e;          // elements in the block
     int32_t int_base;     // first global id of its private nodes (contiguous)
@@ -47,6 +47,8 @@ struct BlockInfo {        // one LDS element block (8 ints, 32 bytes)
     int32_t sh_begin;     // offset of its shared-node list (and partial slots)
     int32_t n_sh;         // shared nodes: local ids n_int..n_int+n_sh-1
     int32_t pad0, pad1;   // pad0: in the apparent-capacity form, the block's one material or -1
+    int32_t v_begin;      // first interface pair of the block (Layout::vconn), with
+    int32_t n_v;          // ... the number of them (interface pairs as block elements)
 };
 
 struct Layout {
@@ -85,6 +87,10 @@ struct Layout {
     // tets per three 32-bit words (tet 2p in bits 0-47 of words 3p..3p+2, tet
     // 2p+1 in bits 48-95); empty otherwise
     std::vector<uint32_t> lconn12;
+    // interface pairs as block elements: six local ids (face a, then face b) and
+    // the coupling w per pair, in block order
+    std::vector<uint16_t> vconn;
+    std::vector<double> vw;
     // partials of shared node s: slot j < PARTIAL_SLOTS at j * nsh + s, the
     // others at PARTIAL_SLOTS * nsh + [comb_ptr[s], comb_ptr[s+1]), all in block order
     std::vector<int32_t> comb_ptr;
@@ -107,6 +113,9 @@ struct PrepOptions {
     int64_t block_elems = 8192;
     int64_t max_local_nodes = 2600;
     bool color_in_block = true;       // order each block's elements by a local colouring
+    // matched interface pairs (fem_set_interface) as six-node elements of the LDS
+    // blocks instead of node links of the node kernel (enthalpy step)
+    bool interface_in_blocks = false;
 };
 
 // Throws std::runtime_error with a message; the C interface maps it to a code.
@@ -126,6 +135,11 @@ struct Base {
     // aggregated interface links in input numbering, CSR by node
     std::vector<int32_t> lptr, lnode;
     std::vector<double> lw;
+    // the links of the non-matching contact faces alone (the same form)
+    std::vector<int32_t> clptr, clnode;
+    std::vector<double> clw;
+    // per matched interface pair: its coupling w = h A / 9 of every node pair
+    std::vector<double> pair_w;
     double dt_bound = 0;
     bool any_robin = false;
     std::vector<double> dt_scen;      // stability bound of every scenario
@@ -140,6 +154,11 @@ struct Base {
 struct Ordering {
     std::vector<int32_t> perm;
     std::vector<int64_t> eorder;
+    // the sort key of every element in eorder (scenario, locality key), and the
+    // matched interface pairs in the same order of keys
+    std::vector<uint64_t> escen, ekey;
+    std::vector<int64_t> porder;
+    std::vector<uint64_t> pscen, pkey;
 };
 
 void prep_base(const Problem &p, Base &b);                                     // throws PrepError
