@@ -59,13 +59,14 @@ def kernel_hash(sources=ENTHALPY_SOURCES):
 def load_traffic(kind, block_nodes, sources=ENTHALPY_SOURCES):
     """HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs, if they
     were taken on the current kernel source with the same block size."""
-    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % kind)
-    if not os.path.exists(path):
-        return None
-    t = json.load(open(path))
-    if t.get("kernel_hash") != kernel_hash(sources) or t.get("block_nodes") != block_nodes:
-        return None
-    return t.get("bytes_per_launch")
+    for name in ("traffic_%s.json" % kind, "traffic_%s_%d.json" % (kind, block_nodes)):
+        path = os.path.join(ROOT, "profiles", name)
+        if not os.path.exists(path):
+            continue
+        t = json.load(open(path))
+        if t.get("kernel_hash") == kernel_hash(sources) and t.get("block_nodes") == block_nodes:
+            return t.get("bytes_per_launch")
+    return None
 
 
 def traffic_from_counters(fetch_dir, write_dir, block_nodes, kernel_key="k_block<float, 4, true>",
@@ -129,6 +130,8 @@ def main():
                     help="LDS block node cap (0 = autotune).  Default: 512 on the benchmark mesh, what the autotuner "
                          "picks there, pinned so that the committed traffic counters match the timed kernel; "
                          "autotuned for the batch")
+    ap.add_argument("--block-threads", type=int, default=0,
+                    help="threads per element block with --block-nodes (0 = 256)")
     ap.add_argument("--workload", default="tet128",
                     choices=["tet128", "tet256", "batch", "surrogate", "apparent", "contact", "varprops", "orderings"],
                     help="tet128: the 128^3 cast/mould mesh; tet256: the 256^3 mesh with eight seeded casting "
@@ -923,6 +926,7 @@ def run_batch(args, log, block_nodes, steps):
     opts = dict(precision=cf.FEM_PREC_FP32_KAHAN, scatter=cf.FEM_SCATTER_LDS_BLOCKED)
     if block_nodes:
         opts["lds_bytes"] = cf.lds_for_nodes(block_nodes)
+        opts["threads"] = args.block_threads
     t0 = time.time()
     s = cf.Solver(prob, **opts)
     t_setup = time.time() - t0
@@ -944,6 +948,7 @@ def run_batch(args, log, block_nodes, steps):
     ach_e = kt["bytes_element"] / (kt["ms_element"] * 1e-3) / 1e9
     ach_c = kt["bytes_combine"] / (kt["ms_combine"] * 1e-3) / 1e9 if kt["ms_combine"] > 0 else None
     traffic = load_traffic("block_element_batch", rep["max_local_nodes"])
+    traffic_nodes = load_traffic("node_combine_batch", rep["max_local_nodes"])
     copy = copy_ceiling(s.ctx, log)
     log("steps %d: %.4f ms/step; element kernel %.4f ms (%.1f GB/s alg), node kernel %.4f ms; %d threads per block"
         % (steps, 1e3 * t_run / steps, kt["ms_element"], ach_e, kt["ms_combine"], rep["block_threads"]))
@@ -963,7 +968,7 @@ def run_batch(args, log, block_nodes, steps):
             "achieved": ach_e, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach_e / HBM_PEAK_GBS,
             "traffic": traffic, "ms_per_launch": kt["ms_element"], "alg_bytes_per_launch": kt["bytes_element"],
             "node_kernel": {"ms_per_launch": kt["ms_combine"], "alg_bytes_per_launch": kt["bytes_combine"],
-                            "achieved": ach_c},
+                            "achieved": ach_c, "traffic": traffic_nodes},
         },
         "worst_scenario_energy_residual": worst,
     }

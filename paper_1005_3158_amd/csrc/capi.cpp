@@ -1294,8 +1294,10 @@ int fem_energy_scenarios(fem_ctx *ctx, fem_energy_report *reps) {
     });
 }
 
-// checkpoint layout: header, H, T (both buffers), fs, per-node inflow sums,
-// simulated time of every scenario
+}  // extern "C"
+
+namespace {
+
 // Checkpoints hold every per-node array in input-node order (the numbering
 // of fem_upload_mesh), so a state restores into any layout of the same
 // problem: another ordering, block size or autotuner choice.  Layout: header,
@@ -1329,6 +1331,10 @@ void permute_items(const Layout &L, const char *in, char *out, int64_t w, bool t
         else std::memcpy(out + dv * w, in + i * w, w);
     }
 }
+
+}  // namespace
+
+extern "C" {
 
 int fem_read_state(fem_ctx *ctx, void *buf, int64_t *bytes) {
     if (!ctx || !bytes) return set_err(FEM_E_INVALID_ARG, "null argument");
