@@ -970,30 +970,53 @@ int fem_bind_buffers(fem_ctx *ctx, void *const *dev_ptrs, int32_t n) {
             hipEvent_t e0, e1;
             HIPCHECK(hipEventCreate(&e0));
             HIPCHECK(hipEventCreate(&e1));
-            auto trial = [&](size_t q, int steps) {
+            // steps of one candidate from the initial state: eager, or (graphs) in
+            // whole captured graphs of GRAPH_STEPS steps with their state
+            // reductions, as fem_step runs them
+            auto trial = [&](size_t q, int steps, bool graphs) {
                 ctx->chosen = (int)q;
                 if (ctx->opt.precision == FEM_PREC_FP64) upload_layout_t<double>(ctx, ctx->cands[q].L);
                 else upload_layout_t<float>(ctx, ctx->cands[q].L);
                 fill_dev(ctx, ctx->cands[q]);
                 set_dt(ctx, dt);
                 ctx->parity = 0;
-                eager_steps(ctx, 4);
+                graphs = graphs && ctx->stream != nullptr;
+                if (graphs) {
+                    reset_graph(ctx);
+                    build_graph(ctx);
+                    steps = std::max(1, steps / GRAPH_STEPS) * GRAPH_STEPS;
+                    HIPCHECK(hipGraphLaunch(ctx->gexec, ctx->stream));
+                } else {
+                    eager_steps(ctx, 4);
+                }
                 HIPCHECK(hipEventRecord(e0, ctx->stream));
-                eager_steps(ctx, steps);
+                if (graphs)
+                    for (int r = 0; r < steps / GRAPH_STEPS; ++r) HIPCHECK(hipGraphLaunch(ctx->gexec, ctx->stream));
+                else
+                    eager_steps(ctx, steps);
                 HIPCHECK(hipEventRecord(e1, ctx->stream));
                 HIPCHECK(hipEventSynchronize(e1));
+                if (graphs) reset_graph(ctx);
                 float ms = 0;
                 HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
                 return ms / (double)steps;
             };
-            for (size_t q = 0; q < ctx->cands.size(); ++q) ctx->cands[q].ms = trial(q, 20);
-            // the three fastest again, longer: candidates within a few per cent of
-            // each other are told apart by the second trial, not by the noise of the first
+            for (size_t q = 0; q < ctx->cands.size(); ++q) ctx->cands[q].ms = trial(q, 20, false);
+            // the three fastest again as the timed path runs, in captured graphs, over
+            // at least 50 ms of steps: candidates within a few per cent of each other
+            // are told apart by the second trial, not by the noise of the first
             std::vector<size_t> rank(ctx->cands.size());
             std::iota(rank.begin(), rank.end(), (size_t)0);
             std::sort(rank.begin(), rank.end(), [&](size_t a, size_t b) { return ctx->cands[a].ms < ctx->cands[b].ms; });
-            for (size_t r = 0; r < std::min<size_t>(3, rank.size()); ++r)
-                ctx->cands[rank[r]].ms = std::min(ctx->cands[rank[r]].ms, trial(rank[r], 60));
+            const size_t finalists = std::min<size_t>(3, rank.size());
+            for (size_t r = 0; r < finalists; ++r) {
+                const double ms1 = ctx->cands[rank[r]].ms;
+                const int n2 = (int)std::min(4000.0, std::max(64.0, 50.0 / std::max(ms1, 1e-3)));
+                ctx->cands[rank[r]].ms = trial(rank[r], n2, true);
+            }
+            // a candidate outside the finalists keeps its eager time, which counts its
+            // launch gaps: it cannot be picked over a finalist timed in graphs
+            for (size_t r = finalists; r < rank.size(); ++r) ctx->cands[rank[r]].ms = 1e30;
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);
             int best = 0;
