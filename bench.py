@@ -26,7 +26,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "element-steps/s + HBM GB/s %peak; surrogate vs plain time-to-solidify at ≤0.5 K"
 HBM_PEAK_GBS = 8000.0
-BLOCK_NODES = 512       # LDS block node cap of the timed launch configuration
+BLOCK_NODES = 0         # benchmark meshes: block shape autotuned (nodes and threads)
+ORDERINGS_BLOCK_NODES = 512   # one fixed block size for the ordering x scatter comparison
 
 
 # every file the traffic-recorded kernels compile (their translation unit and
@@ -127,9 +128,9 @@ def main():
     ap.add_argument("--scatter", default="lds", choices=["lds", "atomic", "colored"])
     ap.add_argument("--ordering", default="hilbert", choices=["none", "rcm", "morton", "hilbert"])
     ap.add_argument("--block-nodes", type=int, default=None,
-                    help="LDS block node cap (0 = autotune).  Default: 512 on the benchmark mesh, what the autotuner "
-                         "picks there, pinned so that the committed traffic counters match the timed kernel; "
-                         "autotuned for the batch")
+                    help="LDS block node cap (0 = autotune).  Default: autotuned (nodes and threads) on the "
+                         "benchmark meshes and the batch; 512 for the apparent, contact and variable-property "
+                         "legs.  Traffic counter records are kept per block size")
     ap.add_argument("--block-threads", type=int, default=0,
                     help="threads per element block with --block-nodes (0 = 256)")
     ap.add_argument("--workload", default="tet128",
@@ -235,7 +236,8 @@ def main():
                          if big else "128^3 jittered Kuhn tets (%d tets, %d nodes), alloy cube in sand mould") % (E, N) +
                         ", h_i=1000, random input numbering, %s ordering, %s scatter, dt=0.9 x bound"
                         % (args.ordering, args.scatter),
-            "n_elems": E, "n_nodes": N, "dt": m["dt"], "block_nodes": m["block_nodes"], "n_blocks": m["n_blocks"],
+            "n_elems": E, "n_nodes": N, "dt": m["dt"], "block_nodes": m["block_nodes"],
+            "block_threads": m["block_threads"], "n_blocks": m["n_blocks"],
             "shared_fraction": m["shared_fraction"], "setup_s": m["setup_s"],
         },
         "effective_GBps": m["effective_GBps"],
@@ -302,6 +304,7 @@ def measure_step(prob, args, log, steps, warmup, traffic_kind, dt_ref, with_copy
     block_nodes = BLOCK_NODES if args.block_nodes is None else args.block_nodes
     if block_nodes and scatter == cf.FEM_SCATTER_LDS_BLOCKED:
         opts["lds_bytes"] = cf.lds_for_nodes(block_nodes)
+        opts["threads"] = args.block_threads
     t0 = time.time()
     s = cf.Solver(prob, **opts)
     t_setup = time.time() - t0
@@ -338,7 +341,7 @@ def measure_step(prob, args, log, steps, warmup, traffic_kind, dt_ref, with_copy
     return {
         "copy": copy,
         "solver": s, "n_elems": E, "n_nodes": N, "dt": dt, "block_nodes": rep["max_local_nodes"],
-        "n_blocks": rep["n_blocks"], "shared_fraction": rep["shared_fraction"], "setup_s": t_setup,
+        "block_threads": rep["block_threads"], "n_blocks": rep["n_blocks"], "shared_fraction": rep["shared_fraction"], "setup_s": t_setup,
         "value": E * steps / t_run, "ms_per_step": 1e3 * t_run / steps,
         "effective_GBps": eff, "effective_frac_hbm": eff / HBM_PEAK_GBS, "energy_residual": en["residual"],
         "roofline": {
@@ -834,7 +837,7 @@ def bench_orderings(args, log):
         for sname, sc in scatters.items():
             opts = dict(precision=cf.FEM_PREC_FP32_KAHAN, ordering=o, scatter=sc)
             if sc == cf.FEM_SCATTER_LDS_BLOCKED:
-                opts["lds_bytes"] = cf.lds_for_nodes(BLOCK_NODES)
+                opts["lds_bytes"] = cf.lds_for_nodes(ORDERINGS_BLOCK_NODES)
             t0 = time.time()
             s = cf.Solver(prob, **opts)
             t_setup = time.time() - t0

@@ -1,6 +1,7 @@
 """The full-size workloads against stored FP64 oracle samples, in the launch
 configuration the benchmark times (FP32 state with compensated enthalpy,
-LDS-blocked scatter, Hilbert ordering, 512-node blocks, steps in captured graphs).
+LDS-blocked scatter, Hilbert ordering, block shape autotuned, steps in captured
+graphs).
 
 - The 128^3 cast/mould mesh (12,582,912 tets) over its 2000 steps: every node
   the oracle has in the liquidus-front band [T_sol - 5, T_liq + 5] at steps 1000
@@ -25,7 +26,6 @@ from castgen import configs
 pytestmark = pytest.mark.gpu
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-BLOCK_NODES = 512
 BAND = (configs.ALLOY[3] - 5.0, configs.ALLOY[4] + 5.0)
 
 
@@ -42,7 +42,7 @@ def _golden(name):
 def _solver(prob):
     from paper_1005_3158_amd import castfem as cf
     return cf.Solver(prob, precision=cf.FEM_PREC_FP32_KAHAN, scatter=cf.FEM_SCATTER_LDS_BLOCKED,
-                     ordering=cf.FEM_ORDER_HILBERT, lds_bytes=cf.lds_for_nodes(BLOCK_NODES))
+                     ordering=cf.FEM_ORDER_HILBERT)
 
 
 def _compare(tag, g, T, fs):
@@ -72,6 +72,8 @@ def test_config2_2000_steps_against_the_oracle_at_the_front():
     dt = float(g["dt"])
     s = _solver(p)
     try:
+        print("config 2: %d blocks of %d nodes and %d threads" % (
+            s.report["n_blocks"], s.report["max_local_nodes"], s.report["block_threads"]), flush=True)
         assert abs(s.stable_dt() - dt / 0.9) <= 1e-9 * dt
         done = 0
         nb = []
@@ -99,8 +101,9 @@ def test_config5_first_100_steps_against_the_oracle():
     dt = float(g["dt"])
     s = _solver(p)
     try:
-        print("config 5: %d tets, %d nodes, %d blocks, shared fraction %.3f" % (
-            s.n_elems, s.n_nodes, s.report["n_blocks"], s.report["shared_fraction"]), flush=True)
+        print("config 5: %d tets, %d nodes, %d blocks of %d nodes and %d threads, shared fraction %.3f" % (
+            s.n_elems, s.n_nodes, s.report["n_blocks"], s.report["max_local_nodes"], s.report["block_threads"],
+            s.report["shared_fraction"]), flush=True)
         assert abs(s.stable_dt() - dt / 0.9) <= 1e-9 * dt
         s.step(dt, int(g["s100_step"]))
         T, fs = s.T(), s.fs()
